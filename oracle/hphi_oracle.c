@@ -1,0 +1,373 @@
+/*
+ * Oracle for the H*v hot path -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, obviously correct CPU code. Only tests/, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it. It shares nothing with
+ * the HIP library (no headers, no tables, no helpers).
+ *
+ * What it computes (HPhi update paper, arXiv:2307.13222):
+ *   - the sector basis: every N-bit configuration with a fixed number of set
+ *     bits (fixed total S^z for spins, fixed N_up / N_dn for electrons), the
+ *     sector keywords 2Sz / nelec of the Standard-mode tables (Sec. 4.1,
+ *     Table "Keywords"; the cTPQ basics of Sec. 3.5.1 describe x as the set of
+ *     spin or particle positions);
+ *   - the spin-1/2 XXZ Hamiltonian applied to a vector, row by row
+ *     (Heisenberg model of Sec. 3.2, S^z = (n_up - n_dn)/2);
+ *   - the Hubbard Hamiltonian -t sum c^+c + U n_up n_dn applied to a vector
+ *     (Sec. 3.4, Eq. Hquench; Sec. 5 transfer integrals), with the fermion
+ *     sign written out from the anticommutation relations.
+ *
+ * Readings where the paper is silent (bit 1 = up spin / occupied orbital,
+ * ascending integer order, all up orbitals ordered before all down orbitals)
+ * are fixed here in the simplest form and are stated again where used.
+ *
+ * Ranking is done two independent ways: binary search in the sorted list,
+ * and the combinatorial number system (rank = sum_k C(c_k, k) over the set
+ * bit positions c_1 < ... < c_n), which equals the ascending position.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+
+static int pc64(uint64_t x) { return __builtin_popcountll(x); }
+
+/* Binomial coefficient C(n, k) by the multiplicative formula (exact while it
+ * fits in 64 bits; every use here is far below that). */
+uint64_t or_binom(int n, int k)
+{
+    if (k < 0 || n < 0 || k > n) return 0;
+    if (k > n - k) k = n - k;
+    uint64_t r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (uint64_t)(n - k + i) / (uint64_t)i;
+    return r;
+}
+
+/* All nbits-bit integers with popcount npop, ascending. Brute force over
+ * [0, 2^nbits). Returns the count written (at most cap). */
+int64_t or_basis_fill(int nbits, int npop, uint64_t *out, int64_t cap)
+{
+    int64_t n = 0;
+    uint64_t end = (nbits >= 64) ? 0 : ((uint64_t)1 << nbits);
+    for (uint64_t x = 0; x < end; ++x) {
+        if (pc64(x) == npop) {
+            if (n < cap) out[n] = x;
+            ++n;
+        }
+    }
+    return n;
+}
+
+/* Combinatorial-number-system rank: sum over the set bits, taken from the
+ * lowest (k = 1) to the highest (k = n), of C(position, k). */
+int64_t or_rank_combinadic(uint64_t x)
+{
+    int64_t r = 0;
+    int k = 0;
+    for (int pos = 0; pos < 64; ++pos) {
+        if ((x >> pos) & 1) {
+            ++k;
+            r += (int64_t)or_binom(pos, k);
+        }
+    }
+    return r;
+}
+
+/* Inverse of the above: the configuration with npop set bits whose rank is r.
+ * Greedy from the highest set bit down. */
+uint64_t or_unrank_combinadic(int64_t r, int npop)
+{
+    uint64_t x = 0;
+    for (int k = npop; k >= 1; --k) {
+        int pos = k - 1;
+        while ((int64_t)or_binom(pos + 1, k) <= r) ++pos;
+        r -= (int64_t)or_binom(pos, k);
+        x |= (uint64_t)1 << pos;
+    }
+    return x;
+}
+
+/* Position of x in the ascending list, or -1. */
+int64_t or_rank_search(const uint64_t *list, int64_t dim, uint64_t x)
+{
+    int64_t lo = 0, hi = dim - 1;
+    while (lo <= hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (list[mid] == x) return mid;
+        if (list[mid] < x) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+void or_rank_search_many(const uint64_t *list, int64_t dim, const uint64_t *xs,
+                         int64_t n, int64_t *out)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) out[i] = or_rank_search(list, dim, xs[i]);
+}
+
+void or_rank_combinadic_many(const uint64_t *xs, int64_t n, int64_t *out)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) out[i] = or_rank_combinadic(xs[i]);
+}
+
+/* ---------------------------------------------------------------- spins -- */
+
+/* One matrix row of the spin-1/2 XXZ Hamiltonian
+ *   H = sum_b [ Jz_b S^z_i S^z_j + Jxy_b (S^x_i S^x_j + S^y_i S^y_j) ]
+ *       - sum_i h_i S^z_i,
+ * bit 1 = up spin (S^z = +1/2). S^x S^x + S^y S^y = (S^+S^- + S^-S^+)/2, so a
+ * bond whose two spins are antiparallel connects x to x with both spins
+ * flipped, with amplitude Jxy/2. The diagonal is Jz/4 for a parallel pair
+ * and -Jz/4 for an antiparallel one. Emits (column configuration, value)
+ * pairs: the diagonal first, then one entry per antiparallel bond. */
+static int spin_row(uint64_t x, int nsites, int nb, const int32_t *bi,
+                    const int32_t *bj, const double *jz, const double *jxy,
+                    const double *hz, uint64_t *cols, double *vals)
+{
+    double d = 0.0;
+    int m = 1;
+    for (int b = 0; b < nb; ++b) {
+        int si = (int)((x >> bi[b]) & 1), sj = (int)((x >> bj[b]) & 1);
+        if (si == sj) {
+            d += 0.25 * jz[b];
+        } else {
+            d -= 0.25 * jz[b];
+            cols[m] = x ^ (((uint64_t)1 << bi[b]) | ((uint64_t)1 << bj[b]));
+            vals[m] = 0.5 * jxy[b];
+            ++m;
+        }
+    }
+    if (hz) {
+        for (int i = 0; i < nsites; ++i) {
+            double sz = ((x >> i) & 1) ? 0.5 : -0.5;
+            d -= hz[i] * sz;
+        }
+    }
+    cols[0] = x;
+    vals[0] = d;
+    return m;
+}
+
+/* w = H v over a materialized ascending basis; ranks by binary search. */
+void or_spin_hv(int nsites, const uint64_t *states, int64_t dim, int nb,
+                const int32_t *bi, const int32_t *bj, const double *jz,
+                const double *jxy, const double *hz, const double *v,
+                double *w)
+{
+    #pragma omp parallel
+    {
+        uint64_t *cols = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nb + 1));
+        double *vals = (double *)malloc(sizeof(double) * (size_t)(nb + 1));
+        #pragma omp for schedule(static)
+        for (int64_t r = 0; r < dim; ++r) {
+            int m = spin_row(states[r], nsites, nb, bi, bj, jz, jxy, hz, cols, vals);
+            double acc = vals[0] * v[r];
+            for (int k = 1; k < m; ++k) {
+                int64_t c = or_rank_search(states, dim, cols[k]);
+                acc += vals[k] * v[c];
+            }
+            w[r] = acc;
+        }
+        free(cols);
+        free(vals);
+    }
+}
+
+/* One sparse row by index, without a materialized basis (combinadic rank).
+ * For sampled-row checks at sizes whose basis list does not fit in memory.
+ * Returns the number of entries (diagonal first). */
+int or_spin_row_by_index(int nsites, int npop, int64_t row, int nb,
+                         const int32_t *bi, const int32_t *bj, const double *jz,
+                         const double *jxy, const double *hz, int64_t *cols,
+                         double *vals)
+{
+    uint64_t x = or_unrank_combinadic(row, npop);
+    uint64_t *cfg = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nb + 1));
+    int m = spin_row(x, nsites, nb, bi, bj, jz, jxy, hz, cfg, vals);
+    for (int k = 0; k < m; ++k) cols[k] = or_rank_combinadic(cfg[k]);
+    free(cfg);
+    return m;
+}
+
+/* Diagonal S^z_l for each site of each configuration, used by the S^z(q)
+ * excitation: sz[r * nsites + l] = +1/2 or -1/2. */
+void or_spin_sz_table(int nsites, const uint64_t *states, int64_t dim, double *sz)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < dim; ++r)
+        for (int l = 0; l < nsites; ++l)
+            sz[r * nsites + l] = ((states[r] >> l) & 1) ? 0.5 : -0.5;
+}
+
+/* -------------------------------------------------------------- Hubbard -- */
+
+/* Fermion sign of c^+_a c_b (a != b, same species) acting on a configuration
+ * occ in which b is occupied and a is empty, for the ordering
+ * |occ> = prod_{k in occ, ascending} c^+_k |0>.
+ * c_b anticommutes past the occupied orbitals below b; c^+_a then moves to
+ * its sorted place past the occupied orbitals (b removed) below a. The sign
+ * is (-1)^(number of those crossings), computed here literally. */
+static double hop_sign(uint64_t occ, int a, int b)
+{
+    int below_b = 0, below_a = 0;
+    for (int k = 0; k < b; ++k) below_b += (int)((occ >> k) & 1);
+    uint64_t rest = occ & ~((uint64_t)1 << b);
+    for (int k = 0; k < a; ++k) below_a += (int)((rest >> k) & 1);
+    return ((below_a + below_b) & 1) ? -1.0 : 1.0;
+}
+
+/* w = H v for
+ *   H = - sum_h t_h sum_sigma (c^+_{i sigma} c_{j sigma} + c^+_{j sigma} c_{i sigma})
+ *       + sum_i U_i n_{i up} n_{i dn}.
+ * Basis index = r_up * dim_dn + r_dn (up-major). All up orbitals precede all
+ * down orbitals in the operator ordering; a same-species hop then moves past
+ * the other species an even number of times in total, so only the
+ * same-species crossings give a sign. */
+void or_hubbard_hv(int nsites, const uint64_t *ups, int64_t dup,
+                   const uint64_t *dns, int64_t ddn, int nh, const int32_t *hi,
+                   const int32_t *hj, const double *ht, const double *u_site,
+                   const double *v, double *w)
+{
+    (void)nsites;
+    #pragma omp parallel for schedule(static)
+    for (int64_t ru = 0; ru < dup; ++ru) {
+        uint64_t u = ups[ru];
+        for (int64_t rd = 0; rd < ddn; ++rd) {
+            uint64_t d = dns[rd];
+            int64_t me = ru * ddn + rd;
+            double diag = 0.0;
+            for (int i = 0; i < nsites; ++i)
+                if (((u >> i) & 1) && ((d >> i) & 1)) diag += u_site[i];
+            double acc = diag * v[me];
+            for (int h = 0; h < nh; ++h) {
+                int i = hi[h], j = hj[h];
+                /* up species */
+                int ui = (int)((u >> i) & 1), uj = (int)((u >> j) & 1);
+                if (ui != uj) {
+                    int a = ui ? j : i, b = ui ? i : j;   /* move b -> a */
+                    uint64_t u2 = u ^ (((uint64_t)1 << i) | ((uint64_t)1 << j));
+                    int64_t c = or_rank_search(ups, dup, u2);
+                    /* <u2| c^+_a c_b |u> = sign; element of H is -t * sign */
+                    acc += -ht[h] * hop_sign(u, a, b) * v[c * ddn + rd];
+                }
+                int di = (int)((d >> i) & 1), dj = (int)((d >> j) & 1);
+                if (di != dj) {
+                    int a = di ? j : i, b = di ? i : j;
+                    uint64_t d2 = d ^ (((uint64_t)1 << i) | ((uint64_t)1 << j));
+                    int64_t c = or_rank_search(dns, ddn, d2);
+                    acc += -ht[h] * hop_sign(d, a, b) * v[ru * ddn + c];
+                }
+            }
+            w[me] = acc;
+        }
+    }
+}
+
+/* One sparse row of the Hubbard Hamiltonian by (r_up, r_dn); entries are
+ * flat indices. Returns the count (diagonal first). */
+int or_hubbard_row(int nsites, const uint64_t *ups, int64_t dup,
+                   const uint64_t *dns, int64_t ddn, int nh, const int32_t *hi,
+                   const int32_t *hj, const double *ht, const double *u_site,
+                   int64_t ru, int64_t rd, int64_t *cols, double *vals)
+{
+    (void)nsites;
+    uint64_t u = ups[ru], d = dns[rd];
+    double diag = 0.0;
+    for (int i = 0; i < nsites; ++i)
+        if (((u >> i) & 1) && ((d >> i) & 1)) diag += u_site[i];
+    int m = 0;
+    cols[m] = ru * ddn + rd; vals[m] = diag; ++m;
+    for (int h = 0; h < nh; ++h) {
+        int i = hi[h], j = hj[h];
+        int ui = (int)((u >> i) & 1), uj = (int)((u >> j) & 1);
+        if (ui != uj) {
+            int a = ui ? j : i, b = ui ? i : j;
+            uint64_t u2 = u ^ (((uint64_t)1 << i) | ((uint64_t)1 << j));
+            cols[m] = or_rank_search(ups, dup, u2) * ddn + rd;
+            vals[m] = -ht[h] * hop_sign(u, a, b);
+            ++m;
+        }
+        int di = (int)((d >> i) & 1), dj = (int)((d >> j) & 1);
+        if (di != dj) {
+            int a = di ? j : i, b = di ? i : j;
+            uint64_t d2 = d ^ (((uint64_t)1 << i) | ((uint64_t)1 << j));
+            cols[m] = ru * ddn + or_rank_search(dns, ddn, d2);
+            vals[m] = -ht[h] * hop_sign(d, a, b);
+            ++m;
+        }
+    }
+    return m;
+}
+
+/* --------------------------------------------------------------- random -- */
+
+/* SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): the state advances by the
+ * golden-ratio increment 0x9E3779B97F4A7C15 and each output is the state
+ * passed through the published finalizer. Element i of the stream for a seed
+ * is the output after i+1 advances, so any element can be made directly. */
+static uint64_t splitmix_out(uint64_t state)
+{
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+void or_splitmix_u64(uint64_t seed, int64_t first, int64_t n, uint64_t *out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = splitmix_out(seed + (uint64_t)(first + i + 1) * 0x9E3779B97F4A7C15ULL);
+}
+
+/* Uniform on [-1/2, 1/2): the top 53 bits scaled by 2^-53, minus 1/2. */
+void or_splitmix_uniform(uint64_t seed, int64_t first, int64_t n, double *out)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t z = splitmix_out(seed + (uint64_t)(first + i + 1) * 0x9E3779B97F4A7C15ULL);
+        out[i] = (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+    }
+}
+
+/* ------------------------------------------------------ sparse export -- */
+
+/* Every row of the spin Hamiltonian in a fixed-stride layout (stride nb+1):
+ * cols[r*(nb+1)+k], vals[...], count[r]. Used to form a sparse matrix for
+ * direct solves and dense checks at small sizes. */
+void or_spin_ell(int nsites, const uint64_t *states, int64_t dim, int nb,
+                 const int32_t *bi, const int32_t *bj, const double *jz,
+                 const double *jxy, const double *hz, int64_t *cols,
+                 double *vals, int32_t *count)
+{
+    #pragma omp parallel
+    {
+        uint64_t *cfg = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nb + 1));
+        #pragma omp for schedule(static)
+        for (int64_t r = 0; r < dim; ++r) {
+            int64_t base = r * (int64_t)(nb + 1);
+            int m = spin_row(states[r], nsites, nb, bi, bj, jz, jxy, hz, cfg, vals + base);
+            for (int k = 0; k < m; ++k) cols[base + k] = or_rank_search(states, dim, cfg[k]);
+            count[r] = m;
+        }
+        free(cfg);
+    }
+}
+
+/* Same for the Hubbard Hamiltonian (stride 2*nh+1). */
+void or_hubbard_ell(int nsites, const uint64_t *ups, int64_t dup,
+                    const uint64_t *dns, int64_t ddn, int nh, const int32_t *hi,
+                    const int32_t *hj, const double *ht, const double *u_site,
+                    int64_t *cols, double *vals, int32_t *count)
+{
+    int64_t stride = 2 * (int64_t)nh + 1;
+    #pragma omp parallel for schedule(static)
+    for (int64_t ru = 0; ru < dup; ++ru)
+        for (int64_t rd = 0; rd < ddn; ++rd) {
+            int64_t r = ru * ddn + rd;
+            count[r] = or_hubbard_row(nsites, ups, dup, dns, ddn, nh, hi, hj, ht,
+                                      u_site, ru, rd, cols + r * stride,
+                                      vals + r * stride);
+        }
+}

@@ -1,0 +1,185 @@
+"""Seeded synthetic inputs shared by the library's callers and by the tests.
+
+This module holds lattice geometry, coupling draws and seeded random test
+vectors only; it contains none of the Hamiltonian, basis or solver
+arithmetic. Both the HIP path (through its Python binding) and the oracle are
+fed from here, so the two sides see identical inputs.
+
+Lattices follow the Standard-mode lattice keywords of the HPhi update paper
+(Sec. 4.1, Table "Keywords": Chain, Ladder, Square), with periodic boundaries.
+Site numbering: chain s = x; 2-leg ladder s = x + L*leg (rung coordinate
+x = s mod L); square s = x + Lx*y.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+
+@dataclass
+class SpinModel:
+    """Spin-1/2 XXZ couplings: H = sum_b Jz_b Sz_i Sz_j + Jxy_b (Sx Sx + Sy Sy)
+    - sum_i hz_i Sz_i. Bond lists are literal (a repeated pair adds)."""
+    n_sites: int
+    bi: np.ndarray
+    bj: np.ndarray
+    jz: np.ndarray
+    jxy: np.ndarray
+    hz: Optional[np.ndarray] = None
+    site_x: Optional[np.ndarray] = None   # coordinate used for S^z(q) phases
+    name: str = ""
+
+    @property
+    def n_bonds(self) -> int:
+        return int(self.bi.shape[0])
+
+
+@dataclass
+class HubbardModel:
+    """H = -sum_h t_h sum_sigma (c+_i c_j + h.c.) + sum_i U_i n_up n_dn."""
+    n_sites: int
+    hi: np.ndarray
+    hj: np.ndarray
+    t: np.ndarray
+    u_site: np.ndarray
+    name: str = ""
+
+    @property
+    def n_hops(self) -> int:
+        return int(self.hi.shape[0])
+
+
+def _spin(n, pairs, couplings, name, site_x=None, hz=None) -> SpinModel:
+    pairs = np.asarray(pairs, dtype=np.int32).reshape(-1, 2)
+    c = np.asarray(couplings, dtype=np.float64).reshape(-1, 2)
+    if site_x is None:
+        site_x = np.arange(n, dtype=np.int64)
+    return SpinModel(n, pairs[:, 0].copy(), pairs[:, 1].copy(), c[:, 0].copy(),
+                     c[:, 1].copy(), None if hz is None else np.asarray(hz, np.float64),
+                     np.asarray(site_x, dtype=np.int64), name)
+
+
+def chain_pairs(n: int, dist: int = 1) -> List[Tuple[int, int]]:
+    return [(s, (s + dist) % n) for s in range(n)]
+
+
+def ladder_pairs(n: int) -> List[Tuple[int, int]]:
+    """2-leg ladder with n sites (n even): legs periodic along x, rungs."""
+    if n % 2:
+        raise ValueError("a 2-leg ladder needs an even site count")
+    L = n // 2
+    pairs = []
+    for leg in range(2):
+        for x in range(L):
+            pairs.append((x + L * leg, (x + 1) % L + L * leg))
+    for x in range(L):
+        pairs.append((x, x + L))
+    return pairs
+
+
+def square_pairs(lx: int, ly: int, diagonal: bool = False) -> List[Tuple[int, int]]:
+    """Nearest-neighbour bonds (s, s+x), (s, s+y); with diagonal=True the
+    next-nearest (s, s+x+y), (s, s+x-y). Periodic in both directions."""
+    pairs = []
+    for y in range(ly):
+        for x in range(lx):
+            s = x + lx * y
+            if not diagonal:
+                pairs.append((s, (x + 1) % lx + lx * y))
+                pairs.append((s, x + lx * ((y + 1) % ly)))
+            else:
+                pairs.append((s, (x + 1) % lx + lx * ((y + 1) % ly)))
+                pairs.append((s, (x + 1) % lx + lx * ((y - 1) % ly)))
+    return pairs
+
+
+def heisenberg_chain(n: int, j: float = 1.0) -> SpinModel:
+    p = chain_pairs(n)
+    return _spin(n, p, [(j, j)] * len(p), f"heisenberg_chain_{n}")
+
+
+def xxz_chain_j2(n: int, j1=(1.0, 0.8), j2=(0.5, 0.4)) -> SpinModel:
+    """XXZ chain with nearest (Jz, Jxy) = j1 and next-nearest j2 bonds."""
+    p1, p2 = chain_pairs(n, 1), chain_pairs(n, 2)
+    return _spin(n, p1 + p2, [j1] * len(p1) + [j2] * len(p2), f"xxz_j2_chain_{n}")
+
+
+def j1j2_square(lx: int, ly: int, j1: float = 1.0, j2: float = 0.5) -> SpinModel:
+    p1 = square_pairs(lx, ly, False)
+    p2 = square_pairs(lx, ly, True)
+    n = lx * ly
+    return _spin(n, p1 + p2, [(j1, j1)] * len(p1) + [(j2, j2)] * len(p2),
+                 f"j1j2_square_{lx}x{ly}", site_x=np.arange(n) % lx)
+
+
+def random_heisenberg(n: int, lattice: str, seed: int, lo: float = 0.5,
+                      hi: float = 1.5) -> SpinModel:
+    """Heisenberg chain or 2-leg ladder, J_b ~ U[lo, hi] per bond (seeded)."""
+    if lattice == "chain":
+        p, site_x = chain_pairs(n), np.arange(n)
+    elif lattice == "ladder":
+        p, site_x = ladder_pairs(n), np.arange(n) % (n // 2)
+    else:
+        raise ValueError(lattice)
+    rng = np.random.default_rng(seed)
+    j = rng.uniform(lo, hi, size=len(p))
+    return _spin(n, p, np.stack([j, j], axis=1), f"rand_{lattice}_{n}_s{seed}",
+                 site_x=site_x)
+
+
+def hubbard_square(lx: int, ly: int, t: float = 1.0, u: float = 4.0) -> HubbardModel:
+    p = np.asarray(square_pairs(lx, ly, False), dtype=np.int32)
+    n = lx * ly
+    return HubbardModel(n, p[:, 0].copy(), p[:, 1].copy(), np.full(len(p), t),
+                        np.full(n, u, dtype=np.float64), f"hubbard_square_{lx}x{ly}")
+
+
+def hubbard_chain(n: int, t: float = 1.0, u: float = 4.0) -> HubbardModel:
+    p = np.asarray(chain_pairs(n), dtype=np.int32)
+    return HubbardModel(n, p[:, 0].copy(), p[:, 1].copy(), np.full(len(p), t),
+                        np.full(n, u, dtype=np.float64), f"hubbard_chain_{n}")
+
+
+def random_vector(dim: int, seed: int, dtype=np.float64, nvec: int = 1) -> np.ndarray:
+    """Seeded test vector (numpy PCG64), uniform in [-1/2, 1/2); complex
+    dtypes get independent real and imaginary parts. Shape (dim,) or
+    (dim, nvec)."""
+    rng = np.random.default_rng(seed)
+    shape = (dim,) if nvec == 1 else (dim, nvec)
+    if np.issubdtype(np.dtype(dtype), np.complexfloating):
+        v = rng.random(shape) - 0.5 + 1j * (rng.random(shape) - 0.5)
+    else:
+        v = rng.random(shape) - 0.5
+    return v.astype(dtype)
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds from the start of the replay
+    kind: str               # "lanczos" or "sqw"
+    lattice: str            # "chain" or "ladder"
+    n_sites: int
+    two_sz: int
+
+
+def serving_requests(n_req: int, rate: float, seed: int = 7,
+                     n_range=(12, 26), sqw_frac: float = 0.5) -> List[Request]:
+    """Poisson arrivals (exponential gaps at `rate` per second); half the
+    requests ask for a ground state, half for S(q, w); half chains, half
+    2-leg ladders (odd sizes redrawn for ladders); 2Sz = N mod 2."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for r in range(n_req):
+        t += rng.exponential(1.0 / rate)
+        kind = "sqw" if rng.random() < sqw_frac else "lanczos"
+        lattice = "ladder" if rng.random() < 0.5 else "chain"
+        while True:
+            n = int(rng.integers(n_range[0], n_range[1] + 1))
+            if lattice == "chain" or n % 2 == 0:
+                break
+        out.append(Request(r, t, kind, lattice, n, n % 2))
+    return out

@@ -1,0 +1,196 @@
+"""Pins of the oracle's Hubbard H*v: an independent Jordan-Wigner matrix
+construction on the full Fock space (signs included), free-fermion and
+atomic-limit energies, the two-site closed form, the ring sign pins, the
+closed-form trace, hermiticity and the Kronecker-sum structure."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import core as O
+from paper_2307_13222_amd import workloads as W
+
+
+def jw_dense_hubbard(m) -> np.ndarray:
+    """H on the 4^N Fock space: orbital o = i (up, site i) or N + i (down);
+    bit o of the integer is the occupation of orbital o. Annihilators by
+    Jordan-Wigner, c_o = (prod_{o' < o} Z_{o'}) sigma^-_o with Z = diag(1, -1),
+    so the basis vector with bits {o} is prod_{o ascending} c^+_o |0>."""
+    n = m.n_sites
+    n_orb = 2 * n
+    Z = sp.csr_matrix(np.diag([1.0, -1.0]))
+    lower = sp.csr_matrix(np.array([[0.0, 1.0], [0.0, 0.0]]))   # |1> -> |0>
+    I2 = sp.identity(2, format="csr")
+
+    def annihilate(o):
+        mats = []
+        for k in range(n_orb - 1, -1, -1):     # kron order: highest orbital first
+            mats.append(Z if k < o else (lower if k == o else I2))
+        out = mats[0]
+        for mm in mats[1:]:
+            out = sp.kron(out, mm, format="csr")
+        return out
+
+    c = [annihilate(o) for o in range(n_orb)]
+    cd = [x.T.tocsr() for x in c]
+    dim = 1 << n_orb
+    H = sp.csr_matrix((dim, dim))
+    for h in range(m.n_hops):
+        i, j, t = int(m.hi[h]), int(m.hj[h]), float(m.t[h])
+        for s in (0, n):
+            H = H - t * (cd[i + s] @ c[j + s] + cd[j + s] @ c[i + s])
+    for i in range(n):
+        H = H + m.u_site[i] * (cd[i] @ c[i]) @ (cd[i + n] @ c[i + n])
+    return H
+
+
+def sector_indices(n, ups, dns):
+    return (ups.astype(np.int64)[:, None] | (dns.astype(np.int64)[None, :] << n)).ravel()
+
+
+def random_hubbard(n, seed, p=0.6):
+    rng = np.random.default_rng(seed)
+    pairs = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < p]
+    a = np.array(pairs, dtype=np.int32)
+    return W.HubbardModel(n, a[:, 0].copy(), a[:, 1].copy(), rng.normal(size=len(pairs)),
+                          rng.normal(size=n) * 2, "rand")
+
+
+@pytest.mark.parametrize("n,seed", [(3, 0), (4, 1), (5, 2)])
+def test_hubbard_matches_jordan_wigner(n, seed):
+    m = random_hubbard(n, seed)
+    Hfull = jw_dense_hubbard(m)
+    for nu in range(n + 1):
+        for nd in range(n + 1):
+            ups, dns = O.hubbard_basis(n, nu, nd)
+            idx = sector_indices(n, ups, dns)
+            ref = Hfull[idx][:, idx].toarray()
+            Hs = O.hubbard_sparse(m, ups, dns).toarray()
+            assert np.allclose(Hs, ref, atol=1e-13, rtol=0), (nu, nd)
+            v = W.random_vector(len(idx), nu * 7 + nd)
+            assert np.allclose(O.hubbard_hv(m, ups, dns, v), ref @ v, atol=1e-12)
+
+
+def test_jordan_wigner_reference_is_fermionic():
+    # sanity of the independent construction itself: {c_a, c^+_b} = delta_ab
+    m = W.hubbard_chain(2, 1.0, 0.0)
+    n_orb = 4
+    Z = sp.csr_matrix(np.diag([1.0, -1.0]))
+    lower = sp.csr_matrix(np.array([[0.0, 1.0], [0.0, 0.0]]))
+
+    def ann(o):
+        out = None
+        for k in range(n_orb - 1, -1, -1):
+            mm = Z if k < o else (lower if k == o else sp.identity(2, format="csr"))
+            out = mm if out is None else sp.kron(out, mm, format="csr")
+        return out
+    cs = [ann(o) for o in range(n_orb)]
+    for a in range(n_orb):
+        for b in range(n_orb):
+            ac = (cs[a] @ cs[b].T + cs[b].T @ cs[a]).toarray()
+            assert np.allclose(ac, np.eye(16) * (a == b))
+            assert np.allclose((cs[a] @ cs[b] + cs[b] @ cs[a]).toarray(), 0)
+    assert m.n_hops == 2
+
+
+def e0_hub(m, nu, nd):
+    ups, dns = O.hubbard_basis(m.n_sites, nu, nd)
+    return np.linalg.eigvalsh(O.hubbard_sparse(m, ups, dns).toarray())[0]
+
+
+def hopping_levels(m):
+    n = m.n_sites
+    h = np.zeros((n, n))
+    for k in range(m.n_hops):
+        i, j = int(m.hi[k]), int(m.hj[k])
+        h[i, j] -= m.t[k]
+        h[j, i] -= m.t[k]
+    return np.linalg.eigvalsh(h)
+
+
+@pytest.mark.parametrize("lx,ly,nu,nd", [(2, 3, 3, 3), (3, 2, 2, 4), (2, 2, 2, 2), (6, 1, 3, 2)])
+def test_free_fermions_u0(lx, ly, nu, nd):
+    m = W.hubbard_square(lx, ly, t=1.0, u=0.0) if ly > 1 else W.hubbard_chain(lx, 1.0, 0.0)
+    eps = hopping_levels(m)
+    assert abs(e0_hub(m, nu, nd) - (eps[:nu].sum() + eps[:nd].sum())) < 1e-11
+
+
+def test_free_fermions_4x4_half_filling_levels():
+    # -12 per species for the 4x4 periodic lattice at 8 particles
+    eps = hopping_levels(W.hubbard_square(4, 4, 1.0, 0.0))
+    assert abs(eps[:8].sum() + 12.0) < 1e-12
+
+
+def test_free_fermions_3x3_lanczos():
+    m = W.hubbard_square(3, 3, 1.0, 0.0)
+    ups, dns = O.hubbard_basis(9, 4, 4)
+    r = O.lanczos(lambda v: O.hubbard_hv(m, ups, dns, v), W.random_vector(126 * 126, 2), 250)
+    eps = hopping_levels(m)
+    assert abs(O.tridiag_lowest(r["alpha"], r["beta"])[0] - 2 * eps[:4].sum()) < 1e-9
+
+
+@pytest.mark.parametrize("nu,nd", [(2, 2), (3, 2), (3, 3), (1, 4)])
+def test_atomic_limit(nu, nd):
+    m = W.hubbard_chain(5, t=0.0, u=3.5)
+    assert abs(e0_hub(m, nu, nd) - 3.5 * max(0, nu + nd - 5)) < 1e-12
+
+
+@pytest.mark.parametrize("u", [0.0, 1.0, 4.0, 8.0])
+def test_two_site_closed_form(u):
+    m = W.HubbardModel(2, np.array([0], np.int32), np.array([1], np.int32), np.array([1.0]),
+                       np.array([u, u]), "dimer")
+    assert abs(e0_hub(m, 1, 1) - (u - math.sqrt(u * u + 16)) / 2) < 1e-13
+
+
+def test_ring_sign_pins():
+    # spinless fermions on periodic rings: wrong boundary signs give -2 sqrt 2
+    assert abs(e0_hub(W.hubbard_chain(4, 1.0, 0.0), 2, 0) + 2.0) < 1e-13
+    assert abs(e0_hub(W.hubbard_chain(6, 1.0, 0.0), 3, 0) + 4.0) < 1e-13
+
+
+def test_t_sign_symmetry_bipartite():
+    # 2x4 periodic: every ring even, so the lattice is bipartite
+    a = W.hubbard_square(2, 4, 1.0, 4.0)
+    b = W.hubbard_square(2, 4, -1.0, 4.0)
+    ups, dns = O.hubbard_basis(8, 3, 2)
+    ea = np.linalg.eigvalsh(O.hubbard_sparse(a, ups, dns).toarray())
+    eb = np.linalg.eigvalsh(O.hubbard_sparse(b, ups, dns).toarray())
+    assert np.allclose(ea, eb, atol=1e-11)
+
+
+@pytest.mark.parametrize("n,nu,nd", [(6, 3, 3), (8, 4, 3), (16, 8, 8)])
+def test_trace_closed_form(n, nu, nd):
+    u = 4.0
+    dim = math.comb(n, nu) * math.comb(n, nd)
+    ref = u * nu * nd / n * dim
+    if n == 16:
+        assert abs(ref - 2650190400.0) < 1e-3
+        return
+    m = W.hubbard_chain(n, 1.0, u)
+    ups, dns = O.hubbard_basis(n, nu, nd)
+    assert abs(O.hubbard_sparse(m, ups, dns).diagonal().sum() - ref) < 1e-9 * ref
+
+
+def test_hermitian_and_kronecker_structure():
+    m = W.hubbard_square(2, 4, 1.0, 4.0)
+    ups, dns = O.hubbard_basis(8, 4, 3)
+    Hs = O.hubbard_sparse(m, ups, dns)
+    assert abs(Hs - Hs.T).max() < 1e-15
+    # H = T_up (x) I + I (x) T_dn + U D with T from the one-species sectors
+    tu = O.hubbard_sparse(W.HubbardModel(8, m.hi, m.hj, m.t, np.zeros(8)), ups, np.array([0], np.uint64))
+    td = O.hubbard_sparse(W.HubbardModel(8, m.hi, m.hj, m.t, np.zeros(8)), np.array([0], np.uint64), dns)
+    D = np.array([[bin(int(a) & int(b)).count("1") for b in dns] for a in ups], float).ravel()
+    K = sp.kron(tu, sp.identity(len(dns))) + sp.kron(sp.identity(len(ups)), td) + sp.diags(4.0 * D)
+    assert abs(Hs - K).max() < 1e-14
+
+
+def test_row_matches_sparse():
+    m = W.hubbard_square(2, 4, 1.0, 4.0)
+    ups, dns = O.hubbard_basis(8, 4, 4)
+    Hs = O.hubbard_sparse(m, ups, dns)
+    for ru, rd in [(0, 0), (5, 60), (69, 69), (33, 2)]:
+        cols, vals = O.hubbard_row(m, ups, dns, ru, rd)
+        dense = np.zeros(Hs.shape[0])
+        np.add.at(dense, cols, vals)
+        assert np.allclose(dense, Hs.getrow(ru * len(dns) + rd).toarray()[0], atol=1e-15)

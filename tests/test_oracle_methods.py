@@ -1,0 +1,208 @@
+"""Pins of the oracle's iterative methods: Lanczos against dense
+diagonalization and its breakdown rule; the cTPQ propagator against the
+exact exponential within the Taylor truncation bound, its beta = 0 and large
+beta limits and the canonical energy at small size; D(z) by direct solves
+against the spectral sum, the Lanczos continued fraction and its analytic
+properties; SplitMix64 against its published outputs."""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import core as O
+from paper_2307_13222_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def spin_setup(m, two_sz=0):
+    s = O.basis_list(m.n_sites, O.sector_popcount_spin(m.n_sites, two_sz))
+    return s, (lambda v: O.spin_hv(m, s, v))
+
+
+# ---------------------------------------------------------------- Lanczos --
+
+@pytest.mark.parametrize("model", ["chain12", "ladder12", "xxz10"])
+def test_lanczos_matches_dense(model):
+    m = {"chain12": W.random_heisenberg(12, "chain", 1),
+         "ladder12": W.random_heisenberg(12, "ladder", 2),
+         "xxz10": W.xxz_chain_j2(10)}[model]
+    s, hv = spin_setup(m)
+    Ed = np.linalg.eigvalsh(O.spin_sparse(m, s).toarray())
+    r = O.lanczos(hv, O.splitmix_uniform(1, 0, len(s)), 200)
+    assert abs(O.tridiag_lowest(r["alpha"], r["beta"])[0] - Ed[0]) < 1e-10
+
+
+def test_lanczos_hubbard_matches_dense():
+    m = W.hubbard_square(2, 3, 1.0, 4.0)
+    ups, dns = O.hubbard_basis(6, 3, 3)
+    Ed = np.linalg.eigvalsh(O.hubbard_sparse(m, ups, dns).toarray())
+    r = O.lanczos(lambda v: O.hubbard_hv(m, ups, dns, v), W.random_vector(400, 3), 150)
+    assert abs(O.tridiag_lowest(r["alpha"], r["beta"])[0] - Ed[0]) < 1e-10
+
+
+def test_lanczos_breakdown_on_eigenvector():
+    # Ising chain: every basis state is an eigenvector -> breakdown at k = 1
+    m = W._spin(8, W.chain_pairs(8), [(1.0, 0.0)] * 8, "ising")
+    s, hv = spin_setup(m)
+    v0 = np.zeros(len(s)); v0[5] = 1.0
+    r = O.lanczos(hv, v0, 50)
+    assert r["steps"] == 1
+    assert abs(r["alpha"][0] - O.spin_sparse(m, s).diagonal()[5]) < 1e-14
+
+
+def test_lanczos_ground_vector_is_eigenvector():
+    m = W.heisenberg_chain(12)
+    s, hv = spin_setup(m)
+    v0 = O.splitmix_uniform(2, 0, len(s))
+    r = O.lanczos(hv, v0, 120)
+    e = O.tridiag_lowest(r["alpha"], r["beta"])[0]
+    psi = O.lanczos_ground_vector(hv, v0, r["alpha"], r["beta"])
+    assert np.linalg.norm(hv(psi) - e * psi) < 1e-7
+
+
+def test_tridiag_against_dense():
+    rng = np.random.default_rng(0)
+    a, b = rng.normal(size=50), np.concatenate([[0.0], rng.normal(size=49)])
+    T = np.diag(a) + np.diag(b[1:], 1) + np.diag(b[1:], -1)
+    assert np.allclose(O.tridiag_lowest(a, b, 5), np.linalg.eigvalsh(T)[:5], atol=1e-13)
+
+
+# ------------------------------------------------------------------- cTPQ --
+
+def test_ctpq_step_truncation_bound():
+    m = W.heisenberg_chain(10)
+    s, hv = spin_setup(m)
+    Hd = O.spin_sparse(m, s).toarray()
+    rng = np.random.default_rng(5)
+    phi = rng.normal(size=len(s)) + 1j * rng.normal(size=len(s))
+    phi /= np.linalg.norm(phi)
+    nrm = np.abs(np.linalg.eigvalsh(Hd)).max()
+    for n_max, dtau in [(6, 0.02), (2, 0.1), (10, 0.01)]:
+        out = O.ctpq(hv, phi, n_max, dtau, 1)
+        exact = scipy.linalg.expm(-dtau / 2 * Hd) @ phi
+        got = out["phi"] * math.sqrt(out["D"][1, 0])   # undo the renormalization
+        x = dtau * nrm / 2
+        bound = x ** (n_max + 1) / math.factorial(n_max + 1) * math.exp(x)
+        assert np.linalg.norm(got - exact) <= bound * 1.0001 + 1e-15
+        if n_max == 2:
+            assert np.linalg.norm(got - exact) > 1e-8        # the bound is not vacuous
+
+
+def test_ctpq_beta0_mean_and_low_temperature():
+    m = W.heisenberg_chain(12)
+    s, hv = spin_setup(m)
+    Hd = O.spin_sparse(m, s).toarray()
+    ev = np.linalg.eigvalsh(Hd)
+    B = 8
+    phi0 = np.stack([O.splitmix_complex_gaussian(100 + k, len(s)) for k in range(B)], axis=1)
+    out = O.ctpq(hv, phi0, 6, 0.02, 400)
+    # beta = 0: <H> averages to Tr H / d within O(|H| / sqrt(d B))
+    trd = np.trace(Hd) / len(s)
+    assert abs(out["E"][0].mean() - trd) < 4 * np.std(ev) / math.sqrt(len(s) * B)
+    # canonical energy E(beta) from the spectrum; TPQ matches within sampling
+    for k in (50, 200, 400):
+        beta = out["beta"][k]
+        wts = np.exp(-beta * (ev - ev[0]))
+        e_can = np.sum(ev * wts) / np.sum(wts)
+        # TPQ estimate weighted by the per-vector squared norms
+        logN = np.cumsum(np.log(out["D"][1:k + 1]), axis=0)[-1]
+        wv = np.exp(logN - logN.max())
+        e_tpq = np.sum(wv * out["E"][k]) / np.sum(wv)
+        assert abs(e_tpq - e_can) < 0.05 * abs(e_can) + 0.05
+    # beta = 8 is deep in the low-temperature regime of L = 12
+    assert out["E"][400].mean() - ev[0] < 0.2
+
+
+def test_ctpq_norm_bookkeeping():
+    m = W.heisenberg_chain(8)
+    s, hv = spin_setup(m)
+    Hd = O.spin_sparse(m, s).toarray()
+    phi = O.splitmix_complex_gaussian(3, len(s))
+    out = O.ctpq(hv, phi, 12, 0.05, 10)
+    # prod_l D_l = N_k = |U_c^k phi|^2 (D_0 = N_0)
+    acc = np.zeros_like(Hd); term = np.eye(len(s))
+    for n in range(13):
+        acc = acc + term
+        term = term @ (-0.05 / 2 * Hd) / (n + 1)
+    x = phi.copy()
+    for _ in range(10):
+        x = acc @ x
+    assert abs(np.prod(out["D"][:11]) / np.vdot(x, x).real - 1) < 1e-10
+
+
+# ---------------------------------------------------------------- D(z) ----
+
+def sqw_setup(n=10, q=math.pi, lattice="chain", seed=3):
+    m = W.random_heisenberg(n, lattice, seed)
+    s, hv = spin_setup(m, n % 2)
+    Hs = O.spin_sparse(m, s)
+    ev, U = np.linalg.eigh(Hs.toarray())
+    psi = U[:, 0]
+    b = O.szq_excitation(m, s, q, psi)
+    return m, s, hv, Hs, ev, b
+
+
+def test_dyn_corr_direct_equals_spectral():
+    m, s, hv, Hs, ev, b = sqw_setup()
+    zs = ev[0] + np.linspace(0, 4, 9) + 0.05j
+    d1 = O.dyn_corr_direct(Hs, b, zs)
+    d2 = O.dyn_corr_spectral(Hs.toarray(), b, zs)
+    assert np.allclose(d1, d2, rtol=1e-10, atol=1e-12)
+
+
+def test_dyn_corr_properties():
+    m, s, hv, Hs, ev, b = sqw_setup(10, math.pi / 5 * 2)
+    zs = ev[0] + np.linspace(0, 4, 7) + 0.05j
+    d = O.dyn_corr_direct(Hs, b, zs)
+    assert np.all(-d.imag > 0)
+    dc = O.dyn_corr_direct(Hs, b, np.conj(zs))
+    assert np.allclose(dc, np.conj(d), rtol=1e-12)
+    zbig = np.array([1e6 + 1j])
+    assert abs(O.dyn_corr_direct(Hs, b, zbig)[0] * zbig[0] / np.vdot(b, b) - 1) < 1e-4
+
+
+def test_szq_q0_vanishes_in_sz0():
+    m, s, hv, Hs, ev, b = sqw_setup(10, 0.0)
+    assert np.linalg.norm(b) < 1e-12
+
+
+def test_szq_parseval():
+    n = 12
+    m = W.random_heisenberg(n, "chain", 4)
+    s, hv = spin_setup(m)
+    r = O.lanczos(hv, O.splitmix_uniform(1, 0, len(s)), 150)
+    psi = O.lanczos_ground_vector(hv, O.splitmix_uniform(1, 0, len(s)), r["alpha"], r["beta"])
+    tot = sum(np.vdot(bq, bq).real for bq in
+              (O.szq_excitation(m, s, 2 * math.pi * k / n, psi) for k in range(n)))
+    assert abs(tot - n * n / 4) < 1e-9
+
+
+def test_continued_fraction_matches_direct():
+    m, s, hv, Hs, ev, b = sqw_setup()
+    zs = ev[0] + np.linspace(0, 4, 5) + 0.1j
+    a, bb = O.lanczos_complex(hv, b, 250)
+    d_cf = O.continued_fraction(a, bb, np.vdot(b, b).real, zs)
+    d_dir = O.dyn_corr_direct(Hs, b, zs)
+    assert np.allclose(d_cf, d_dir, rtol=1e-8)
+
+
+# ----------------------------------------------------------------- random --
+
+def test_splitmix_published_outputs():
+    vals = [int(x) for x in open(os.path.join(GOLDEN, "splitmix64_seed1234567.txt"))
+            if x.strip() and not x.startswith("#")]
+    assert [int(x) for x in O.splitmix_u64(1234567, 0, 5)] == vals
+    # counter-based: element i alone equals element i of the stream
+    assert int(O.splitmix_u64(1234567, 3, 1)[0]) == vals[3]
+
+
+def test_uniform_and_gaussian_statistics():
+    u = O.splitmix_uniform(9, 0, 200000)
+    assert u.min() >= -0.5 and u.max() < 0.5
+    assert abs(u.mean()) < 0.003 and abs(u.var() - 1 / 12) < 0.002
+    g = O.splitmix_complex_gaussian(9, 100000)
+    assert abs(np.mean(np.abs(g) ** 2) - 2.0) < 0.03
+    assert abs(np.mean(g.real)) < 0.01 and abs(np.mean(g.imag)) < 0.01
