@@ -1,0 +1,275 @@
+/*
+ * hphi_mi355.h -- C ABI of the MI355X (gfx950) matrix-free H*v / Lanczos /
+ * cTPQ / shifted-Krylov library.
+ *
+ * The operations follow the problem statement of the HPhi update paper
+ * (arXiv:2307.13222): a spin-1/2 or Hubbard lattice model given by its site
+ * count, conserved sector (the 2Sz and nelec keywords of the Standard-mode
+ * table in Sec. 4.1) and bond / transfer lists (Sec. 3.4, Eq. Hquench;
+ * Sec. 5); the matrix-vector product that every iterative method reduces to
+ * (Sec. 1); the Lanczos ground state (Sec. 1); the canonical TPQ propagator
+ * (Sec. 3.5.1); the dynamical correlation function by the shifted Krylov
+ * method (Sec. 3.2).
+ *
+ * Conventions that hold for every entry point:
+ *  - Return value: 0 on success, a negative HPHI_ERR_* code on failure; the
+ *    message of the last failure on the calling thread is hphi_last_error().
+ *  - Pointers named *_dev are device pointers on the context's device; the
+ *    caller owns them (they are typically torch tensors' data pointers).
+ *    Every other pointer is host memory owned by the caller.
+ *  - The library owns basis tables, Hamiltonian tables and its own scratch
+ *    memory; they are released by the matching *_free call.
+ *  - `stream` is a hipStream_t (NULL = the default stream). Calls that only
+ *    launch kernels are asynchronous on that stream; calls that return host
+ *    scalars synchronize it before returning.
+ *  - Configuration bit convention: site i is bit i; bit = 1 means spin up
+ *    (spins) or an occupied orbital (electrons). Basis states are ordered by
+ *    ascending integer value. A Hubbard state (u, d) has flat index
+ *    rank_up(u) * dim_dn + rank_dn(d).
+ *  - Vector layout: element (state r, vector j) of a block of nvec vectors
+ *    sits at r * nvec + j ("interleaved"); complex numbers are (re, im)
+ *    pairs. Input and output blocks must not alias.
+ */
+#ifndef HPHI_MI355_H
+#define HPHI_MI355_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------- errors -- */
+#define HPHI_OK                 0
+#define HPHI_ERR_INVALID_ARG   -1   /* bad size, site index, sector, option */
+#define HPHI_ERR_EMPTY_SECTOR  -2   /* the requested sector has no states   */
+#define HPHI_ERR_DIM_OVERFLOW  -3   /* dimension beyond 2^62 or a table     */
+#define HPHI_ERR_OUT_OF_MEMORY -4   /* device or host allocation failed     */
+#define HPHI_ERR_DEVICE        -5   /* a HIP runtime call failed            */
+#define HPHI_ERR_UNSUPPORTED   -6   /* valid request this build cannot do   */
+
+typedef enum {
+    HPHI_F64 = 0,    /* real double                         */
+    HPHI_F32 = 1,    /* real float (storage), FP64 dots     */
+    HPHI_C128 = 2,   /* complex double, (re, im) pairs      */
+    HPHI_C64 = 3     /* complex float (storage), FP64 dots  */
+} hphi_dtype;
+
+typedef struct hphi_ctx hphi_ctx;
+typedef struct hphi_basis hphi_basis;
+typedef struct hphi_ham hphi_ham;
+
+/* Message of the last failure on this thread ("" if none). The string is
+ * owned by the library and valid until the next failing call. */
+const char *hphi_last_error(void);
+
+/* Library version string (static storage). */
+const char *hphi_version(void);
+
+/* Open a context on HIP device `device` (0-based). *ctx receives the handle.
+ * Errors: INVALID_ARG (no such device), DEVICE. */
+int hphi_init(int device, hphi_ctx **ctx);
+
+/* Release a context. Bases and Hamiltonians made from it must be freed
+ * first. NULL is accepted. */
+void hphi_fini(hphi_ctx *ctx);
+
+/* ------------------------------------------------------------- basis -- */
+
+/* Sector basis of a spin-1/2 system: all n_sites-bit configurations with
+ * (n_up - n_dn) = two_sz, i.e. a fixed total S^z (keyword 2Sz, Sec. 4.1).
+ * Builds the split two-level rank table on host and device:
+ *   idx(x) = hi_off[x >> n_lo] + lo_rank[x & (2^n_lo - 1)],
+ * with lo_rank[l] the rank of l among n_lo-bit patterns of equal popcount
+ * and hi_off[h] the number of sector states whose high part is below h.
+ * Errors: INVALID_ARG (n_sites < 1 or > 64, |two_sz| > n_sites, parity of
+ * n_sites + two_sz odd), DIM_OVERFLOW, OUT_OF_MEMORY, DEVICE. */
+int hphi_basis_spin(hphi_ctx *ctx, int n_sites, int two_sz, hphi_basis **out);
+
+/* Sector basis of the Hubbard model with fixed N_up and N_dn (keyword nelec
+ * with fixed 2Sz, Sec. 4.1): the product of the two one-species bases.
+ * Errors: INVALID_ARG (n_sites < 1 or > 32, n_up or n_dn outside
+ * [0, n_sites]), DIM_OVERFLOW, OUT_OF_MEMORY, DEVICE. */
+int hphi_basis_hubbard(hphi_ctx *ctx, int n_sites, int n_up, int n_dn, hphi_basis **out);
+
+void hphi_basis_free(hphi_basis *b);
+
+/* Dimension of the sector (number of basis states). */
+int64_t hphi_basis_dim(const hphi_basis *b);
+
+/* Host copy of basis states [first, first + count): spins give the
+ * configuration, Hubbard states are packed as (u << 32) | d.
+ * Errors: INVALID_ARG (range outside [0, dim)). */
+int hphi_basis_states(const hphi_basis *b, int64_t first, int64_t count, uint64_t *host_out);
+
+/* Host ranks of n configurations (packed as above); -1 for a configuration
+ * outside the sector. */
+int hphi_basis_rank(const hphi_basis *b, const uint64_t *states, int64_t n, int64_t *idx_out);
+
+/* Device versions of the two calls above: the same tables the H*v kernels
+ * use, evaluated by GPU kernels. Asynchronous on `stream`. */
+int hphi_basis_states_device(const hphi_basis *b, int64_t first, int64_t count,
+                             uint64_t *out_dev, void *stream);
+int hphi_basis_rank_device(const hphi_basis *b, const uint64_t *states_dev, int64_t n,
+                           int64_t *idx_dev, void *stream);
+
+/* Read-only host view of the rank tables of one species (spin: species 0;
+ * Hubbard: 0 = up, 1 = down). Pointers stay valid until hphi_basis_free.
+ * lo_rank has 2^n_lo entries, hi_off 2^n_hi + 1 (the last is the total). */
+int hphi_basis_tables(const hphi_basis *b, int species, const uint32_t **lo_rank,
+                      const uint64_t **hi_off, int *n_lo, int *n_hi);
+
+/* ------------------------------------------------------- Hamiltonians -- */
+
+/* One spin bond: H += jz S^z_i S^z_j + jxy (S^x_i S^x_j + S^y_i S^y_j). */
+typedef struct { int32_t i, j; double jz, jxy; } hphi_spin_bond;
+
+/* One transfer: H += -t sum_sigma (c+_{i sigma} c_{j sigma} + h.c.). */
+typedef struct { int32_t i, j; double t; } hphi_hop;
+
+/* Spin-1/2 XXZ Hamiltonian on a spin basis (Heisenberg model of Sec. 3.2):
+ *   H = sum_b [jz_b S^z_i S^z_j + jxy_b (S^x_i S^x_j + S^y_i S^y_j)]
+ *       - sum_i hz[i] S^z_i          (hz may be NULL).
+ * Bond lists are literal: a repeated pair adds. The basis must outlive the
+ * Hamiltonian. Errors: INVALID_ARG (site >= n_sites, i == j, n_bonds < 0 or
+ * > 4096, basis of the wrong kind), OUT_OF_MEMORY, DEVICE. */
+int hphi_ham_spin(hphi_basis *b, const hphi_spin_bond *bonds, int n_bonds,
+                  const double *hz, hphi_ham **out);
+
+/* Hubbard Hamiltonian (Sec. 3.4, Eq. Hquench with a static U; Sec. 5):
+ *   H = -sum_h t_h sum_sigma (c+_i c_j + h.c.) + sum_i u_site[i] n_i,up n_i,dn.
+ * Fermion order: all up orbitals (ascending site) before all down orbitals,
+ * so a hop's sign is (-1)^(occupied same-species sites strictly between
+ * i and j). Errors: INVALID_ARG (site >= n_sites, i == j, u_site NULL,
+ * more than 128 distinct t values), OUT_OF_MEMORY, DEVICE. */
+int hphi_ham_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops,
+                     const double *u_site, hphi_ham **out);
+
+void hphi_ham_free(hphi_ham *h);
+
+/* Exact trace of H over the sector, summed on the device in FP64. */
+int hphi_ham_trace(hphi_ham *h, double *trace_out, void *stream);
+
+/* ------------------------------------------------------------- H * v -- */
+
+/* w = H v for a block of nvec vectors of type dt (interleaved layout),
+ * the product at the core of every Krylov and power method (Sec. 1).
+ * Real types hold nvec real vectors, complex types nvec complex vectors.
+ * F32 / C64 store in float and accumulate each row in float.
+ * Asynchronous on `stream`. v_dev and w_dev must not alias.
+ * Errors: INVALID_ARG (nvec < 1 or > 32, null pointers), UNSUPPORTED,
+ * DEVICE. */
+int hphi_mult(hphi_ham *h, hphi_dtype dt, const void *v_dev, void *w_dev,
+              int64_t nvec, void *stream);
+
+/* ------------------------------------------------------------ Lanczos -- */
+
+typedef struct {
+    int max_iter;          /* Krylov steps (>= 1)                            */
+    int check_every;       /* 0: run max_iter steps; m > 0: every m steps the
+                              host solves T_k and stops when the lowest
+                              n_energies Ritz values move by < tol           */
+    double tol;            /* convergence threshold for check_every > 0      */
+    uint64_t seed;         /* start vector: SplitMix64 uniform [-1/2, 1/2)   */
+    const void *v0_dev;    /* or a caller start vector (storage dtype); NULL
+                              = use the seed                                 */
+    hphi_dtype storage;    /* HPHI_F64 or HPHI_F32 (FP64 dots and scalars)   */
+    void *stream;          /* hipStream_t                                    */
+    double *alpha_out;     /* optional host arrays of max_iter entries:      */
+    double *beta_out;      /*   T_k diagonal and beta[k] (beta[0] = 0)       */
+    void *psi_dev;         /* optional: ground-state Ritz vector (storage
+                              dtype, normalized), from a second pass         */
+    int use_graph;         /* capture the iteration in a hipGraph            */
+    int time_kernels;      /* bracket every H*v with HIP events on `stream`
+                              (not with use_graph); totals go to info        */
+} hphi_lanczos_opts;
+
+typedef struct {
+    int iterations;        /* Krylov steps done                              */
+    int converged;         /* 1 if the check_every test passed               */
+    int breakdown;         /* 1 if beta_k fell below 1e-13 max(1, |alpha|)   */
+    double seconds;        /* wall time of the solve                         */
+    double hv_seconds;     /* with time_kernels: summed H*v launch durations */
+    int hv_calls;          /* number of H*v launches timed                   */
+} hphi_lanczos_info;
+
+/* Lanczos ground state (Sec. 1): v_0 = r/|r|; w = H v_k - beta_k v_{k-1};
+ * alpha_k = <v_k, w>; w -= alpha_k v_k; beta_{k+1} = |w|; v_{k+1} = w /
+ * beta_{k+1}; no reorthogonalization. The lowest n_energies eigenvalues of
+ * the tridiagonal T_k come from host FP64 Sturm bisection. Synchronous.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *opts, double *energies,
+                 int n_energies, hphi_lanczos_info *info);
+
+/* Lowest k eigenvalues (ascending) of the symmetric tridiagonal matrix with
+ * diagonal alpha[0..n) and off-diagonal beta[1..n) (beta[0] ignored), by
+ * Sturm-sequence bisection in FP64; the host routine hphi_lanczos uses.
+ * If vec is non-NULL it receives the normalized eigenvector of the lowest
+ * eigenvalue (n entries, inverse iteration). */
+int hphi_tridiag_lowest(const double *alpha, const double *beta, int n, int k,
+                        double *eig_out, double *vec);
+
+/* ----------------------------------------------------------------- cTPQ -- */
+
+typedef struct {
+    int n_vec;             /* independent random vectors (1..32)             */
+    int n_max;             /* Taylor order of U_c                            */
+    double dtau;           /* imaginary-time slice                           */
+    int k_steps;           /* steps: beta_k = k dtau, k = 1..k_steps         */
+    hphi_dtype storage;    /* HPHI_C128 or HPHI_C64                          */
+    uint64_t seed;         /* vector j uses seed + j: complex Gaussian
+                              entries (Box-Muller on SplitMix64 outputs)     */
+    const void *phi0_dev;  /* or a caller start block [dim][n_vec] complex   */
+    void *stream;
+} hphi_ctpq_opts;
+
+/* Canonical TPQ (Sec. 3.5.1): Phi_k = U_c(dtau)^k Phi_rand with
+ * U_c = sum_{n<=n_max} (-dtau H / 2)^n / n!, applied to n_vec vectors at
+ * once by block H*V. After each step the squared norm N (FP64) gives
+ * D_k = N_k / N_{k-1} (D_0 = N_0 = |Phi_rand|^2), the state is renormalized
+ * and <H> = <Phi|H|Phi>, <H^2> = |H Phi|^2 are recorded.
+ * Outputs (host, (k_steps + 1) * n_vec, row k = beta_k): D_out, E_out,
+ * E2_out (any may be NULL). phi_dev (device, [dim][n_vec] complex of the
+ * storage type) receives the final normalized states. Synchronous.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+int hphi_ctpq(hphi_ham *h, const hphi_ctpq_opts *opts, void *phi_dev,
+              double *D_out, double *E_out, double *E2_out);
+
+/* --------------------------------------------------- S^zz(q, w) / D(z) -- */
+
+/* Excitation b = sum_l e^{i q x_l} S^z_l psi for a spin basis (Sec. 3.2):
+ * phase[2*l], phase[2*l+1] = (cos, sin)(q x_l) per site, host array.
+ * psi_dev: F64 vector; b_dev: C128 vector. Asynchronous on `stream`. */
+int hphi_szq(hphi_ham *h, const double *phase, const void *psi_dev, void *b_dev,
+             void *stream);
+
+typedef struct {
+    int max_iter;          /* COCG steps cap                                 */
+    double tol;            /* stop when max_j |r_j| / |b| < tol              */
+    int seed_shift;        /* index of the seed system (-1: middle shift)    */
+    void *stream;
+} hphi_sqw_opts;
+
+typedef struct {
+    int iterations;
+    int converged;
+    double max_residual;   /* max_j |r_j| / |b| at exit                      */
+    double seconds;
+} hphi_sqw_info;
+
+/* Dynamical correlation D(z_j) = <b| (z_j - H)^-1 |b> for n_shift complex
+ * shifts z_j = (z_re[j], z_im[j]) from one Krylov sequence (shifted COCG on
+ * the complex-symmetric z - H; Sec. 3.2, method "CG"). Only the projections
+ * <b|x_j> are kept (host scalar recurrences per shift). D_out receives
+ * 2 * n_shift doubles (re, im); resid_out (nullable) the per-shift relative
+ * residual norms. b_dev: C128 vector. Synchronous.
+ * Errors: INVALID_ARG (n_shift < 1 or > 4096), OUT_OF_MEMORY, DEVICE. */
+int hphi_sqw(hphi_ham *h, const hphi_sqw_opts *opts, const void *b_dev,
+             const double *z_re, const double *z_im, int n_shift, double *D_out,
+             double *resid_out, hphi_sqw_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPHI_MI355_H */

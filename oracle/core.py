@@ -65,6 +65,8 @@ def lib():
         L.or_spin_sz_table.restype = None; L.or_spin_sz_table.argtypes = [i32, p, i64, p]
         L.or_hubbard_hv.restype = None
         L.or_hubbard_hv.argtypes = [i32, p, i64, p, i64, i32, p, p, p, p, p, p]
+        L.or_hubbard_hv_rows.restype = None
+        L.or_hubbard_hv_rows.argtypes = [i32, p, i64, p, i64, i32, p, p, p, p, p, i64, i64, p]
         L.or_hubbard_row.restype = i32
         L.or_hubbard_row.argtypes = [i32, p, i64, p, i64, i32, p, p, p, p, i64, i64, p, p]
         L.or_splitmix_u64.restype = None; L.or_splitmix_u64.argtypes = [u64, i64, i64, p]
@@ -199,6 +201,16 @@ def hubbard_hv(m, ups: np.ndarray, dns: np.ndarray, v: np.ndarray) -> np.ndarray
     w = np.empty_like(vv)
     lib().or_hubbard_hv(m.n_sites, _p(ups), ups.shape[0], _p(dns), dns.shape[0], hi.shape[0],
                         _p(hi), _p(hj), _p(t), _p(us), _p(vv), _p(w))
+    return w
+
+
+def hubbard_hv_rows(m, ups, dns, v: np.ndarray, ru_first: int, ru_count: int) -> np.ndarray:
+    """Up-rows [ru_first, ru_first + ru_count) of H v (all down states)."""
+    hi, hj, t, us = _hub_arrays(m)
+    vv = np.ascontiguousarray(v, dtype=np.float64)
+    w = np.empty(ru_count * dns.shape[0])
+    lib().or_hubbard_hv_rows(m.n_sites, _p(ups), ups.shape[0], _p(dns), dns.shape[0], hi.shape[0],
+                             _p(hi), _p(hj), _p(t), _p(us), _p(vv), int(ru_first), int(ru_count), _p(w))
     return w
 
 

@@ -265,6 +265,41 @@ void or_hubbard_hv(int nsites, const uint64_t *ups, int64_t dup,
     }
 }
 
+/* Rows [ru_first, ru_first + ru_count) x all r_dn of w = H v (the same
+ * arithmetic as or_hubbard_hv, on a bounded set of output rows; v is the
+ * whole vector). w holds ru_count * ddn entries. */
+void or_hubbard_hv_rows(int nsites, const uint64_t *ups, int64_t dup,
+                        const uint64_t *dns, int64_t ddn, int nh, const int32_t *hi,
+                        const int32_t *hj, const double *ht, const double *u_site,
+                        const double *v, int64_t ru_first, int64_t ru_count, double *w)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < ru_count * ddn; ++k) {
+        int64_t ru = ru_first + k / ddn, rd = k % ddn;
+        uint64_t u = ups[ru], d = dns[rd];
+        double diag = 0.0;
+        for (int i = 0; i < nsites; ++i)
+            if (((u >> i) & 1) && ((d >> i) & 1)) diag += u_site[i];
+        double acc = diag * v[ru * ddn + rd];
+        for (int h = 0; h < nh; ++h) {
+            int i = hi[h], j = hj[h];
+            int ui = (int)((u >> i) & 1), uj = (int)((u >> j) & 1);
+            if (ui != uj) {
+                int a = ui ? j : i, b = ui ? i : j;
+                uint64_t u2 = u ^ (((uint64_t)1 << i) | ((uint64_t)1 << j));
+                acc += -ht[h] * hop_sign(u, a, b) * v[or_rank_search(ups, dup, u2) * ddn + rd];
+            }
+            int di = (int)((d >> i) & 1), dj = (int)((d >> j) & 1);
+            if (di != dj) {
+                int a = di ? j : i, b = di ? i : j;
+                uint64_t d2 = d ^ (((uint64_t)1 << i) | ((uint64_t)1 << j));
+                acc += -ht[h] * hop_sign(d, a, b) * v[ru * ddn + or_rank_search(dns, ddn, d2)];
+            }
+        }
+        w[k] = acc;
+    }
+}
+
 /* One sparse row of the Hubbard Hamiltonian by (r_up, r_dn); entries are
  * flat indices. Returns the count (diagonal first). */
 int or_hubbard_row(int nsites, const uint64_t *ups, int64_t dup,

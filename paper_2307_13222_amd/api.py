@@ -1,0 +1,290 @@
+"""Thin Python binding over the C ABI (argument marshalling only).
+
+Device memory and streams come from PyTorch-ROCm; every step of the hot path
+runs in the HIP library. Names mirror include/hphi_mi355.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+from .workloads import HubbardModel, SpinModel
+
+
+class HphiError(RuntimeError):
+    pass
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = L.lib().hphi_last_error()
+        raise HphiError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def dtype_code(t) -> int:
+    torch = _torch()
+    m = {torch.float64: L.F64, torch.float32: L.F32, torch.complex128: L.C128, torch.complex64: L.C64}
+    if t.dtype not in m:
+        raise HphiError(f"unsupported tensor dtype {t.dtype}")
+    return m[t.dtype]
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        torch = _torch()
+        return torch.cuda.current_stream().cuda_stream or None
+    return getattr(stream, "cuda_stream", stream) or None
+
+
+def _dev_check(t, name):
+    if not t.is_cuda:
+        raise HphiError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise HphiError(f"{name} must be contiguous")
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = C.c_void_p()
+        _check(L.lib().hphi_init(device, C.byref(h)), "hphi_init")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            L.lib().hphi_fini(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Basis:
+    def __init__(self, ctx: Context, handle, kind: str):
+        self.ctx, self.h, self.kind = ctx, handle, kind
+
+    @classmethod
+    def spin(cls, ctx: Context, n_sites: int, two_sz: int) -> "Basis":
+        h = C.c_void_p()
+        _check(L.lib().hphi_basis_spin(ctx.h, n_sites, two_sz, C.byref(h)), "hphi_basis_spin")
+        b = cls(ctx, h, "spin")
+        b.n_sites = n_sites
+        return b
+
+    @classmethod
+    def hubbard(cls, ctx: Context, n_sites: int, n_up: int, n_dn: int) -> "Basis":
+        h = C.c_void_p()
+        _check(L.lib().hphi_basis_hubbard(ctx.h, n_sites, n_up, n_dn, C.byref(h)), "hphi_basis_hubbard")
+        b = cls(ctx, h, "hubbard")
+        b.n_sites = n_sites
+        return b
+
+    @property
+    def dim(self) -> int:
+        return int(L.lib().hphi_basis_dim(self.h))
+
+    def states(self, first: int, count: int) -> np.ndarray:
+        out = np.empty(count, dtype=np.uint64)
+        _check(L.lib().hphi_basis_states(self.h, first, count, out.ctypes.data), "hphi_basis_states")
+        return out
+
+    def rank(self, states: np.ndarray) -> np.ndarray:
+        s = np.ascontiguousarray(states, dtype=np.uint64)
+        out = np.empty(s.shape[0], dtype=np.int64)
+        _check(L.lib().hphi_basis_rank(self.h, s.ctypes.data, s.shape[0], out.ctypes.data), "hphi_basis_rank")
+        return out
+
+    def states_device(self, first: int, count: int, stream=None):
+        torch = _torch()
+        out = torch.empty(count, dtype=torch.int64, device=f"cuda:{self.ctx.device}")
+        _check(L.lib().hphi_basis_states_device(self.h, first, count, out.data_ptr(),
+                                                 _stream_ptr(stream)), "hphi_basis_states_device")
+        return out
+
+    def rank_device(self, states, stream=None):
+        torch = _torch()
+        _dev_check(states, "states")
+        out = torch.empty(states.shape[0], dtype=torch.int64, device=states.device)
+        _check(L.lib().hphi_basis_rank_device(self.h, states.data_ptr(), states.shape[0],
+                                               out.data_ptr(), _stream_ptr(stream)),
+               "hphi_basis_rank_device")
+        return out
+
+    def tables(self, species: int = 0):
+        lo = C.POINTER(C.c_uint32)()
+        hi = C.POINTER(C.c_uint64)()
+        nlo, nhi = C.c_int(), C.c_int()
+        _check(L.lib().hphi_basis_tables(self.h, species, C.byref(lo), C.byref(hi), C.byref(nlo),
+                                         C.byref(nhi)), "hphi_basis_tables")
+        lo_a = np.ctypeslib.as_array(lo, shape=(1 << nlo.value,)).copy()
+        hi_a = np.ctypeslib.as_array(hi, shape=((1 << nhi.value) + 1,)).copy()
+        return lo_a, hi_a, nlo.value, nhi.value
+
+    def close(self):
+        if self.h:
+            L.lib().hphi_basis_free(self.h)
+            self.h = None
+
+
+class Hamiltonian:
+    def __init__(self, basis: Basis, handle, model):
+        self.basis, self.h, self.model = basis, handle, model
+
+    @classmethod
+    def spin(cls, basis: Basis, m: SpinModel) -> "Hamiltonian":
+        arr = (L.SpinBond * max(1, m.n_bonds))()
+        for k in range(m.n_bonds):
+            arr[k] = L.SpinBond(int(m.bi[k]), int(m.bj[k]), float(m.jz[k]), float(m.jxy[k]))
+        hz = None
+        if m.hz is not None:
+            hz_a = np.ascontiguousarray(m.hz, dtype=np.float64)
+            hz = hz_a.ctypes.data_as(L.PD)
+        h = C.c_void_p()
+        _check(L.lib().hphi_ham_spin(basis.h, arr, m.n_bonds, hz, C.byref(h)), "hphi_ham_spin")
+        return cls(basis, h, m)
+
+    @classmethod
+    def hubbard(cls, basis: Basis, m: HubbardModel) -> "Hamiltonian":
+        arr = (L.Hop * max(1, m.n_hops))()
+        for k in range(m.n_hops):
+            arr[k] = L.Hop(int(m.hi[k]), int(m.hj[k]), float(m.t[k]))
+        us = np.ascontiguousarray(m.u_site, dtype=np.float64)
+        h = C.c_void_p()
+        _check(L.lib().hphi_ham_hubbard(basis.h, arr, m.n_hops, us.ctypes.data_as(L.PD), C.byref(h)),
+               "hphi_ham_hubbard")
+        return cls(basis, h, m)
+
+    def trace(self, stream=None) -> float:
+        out = C.c_double()
+        _check(L.lib().hphi_ham_trace(self.h, C.byref(out), _stream_ptr(stream)), "hphi_ham_trace")
+        return out.value
+
+    def mult(self, v, w=None, stream=None):
+        """w = H v. v: (dim,) or (dim, nvec) device tensor (f64, f32, c128, c64)."""
+        torch = _torch()
+        _dev_check(v, "v")
+        nvec = 1 if v.dim() == 1 else v.shape[1]
+        if w is None:
+            w = torch.empty_like(v)
+        _dev_check(w, "w")
+        _check(L.lib().hphi_mult(self.h, dtype_code(v), v.data_ptr(), w.data_ptr(), nvec,
+                                 _stream_ptr(stream)), "hphi_mult")
+        return w
+
+    def close(self):
+        if self.h:
+            L.lib().hphi_ham_free(self.h)
+            self.h = None
+
+
+def lanczos(ham: Hamiltonian, max_iter: int, seed: int = 1, v0=None, storage: str = "f64",
+            n_energies: int = 1, want_vector: bool = False, use_graph: bool = False,
+            check_every: int = 0, tol: float = 1e-12, time_kernels: bool = False,
+            stream=None) -> Dict:
+    torch = _torch()
+    o = L.LanczosOpts()
+    o.max_iter, o.check_every, o.tol, o.seed = max_iter, check_every, tol, seed
+    o.storage = L.F64 if storage == "f64" else L.F32
+    tdt = torch.float64 if storage == "f64" else torch.float32
+    if v0 is not None:
+        _dev_check(v0, "v0")
+        if v0.dtype != tdt:
+            raise HphiError("v0 must have the storage dtype")
+        o.v0_dev = v0.data_ptr()
+    o.stream = _stream_ptr(stream)
+    alpha = np.zeros(max_iter)
+    beta = np.zeros(max_iter)
+    o.alpha_out = alpha.ctypes.data_as(L.PD)
+    o.beta_out = beta.ctypes.data_as(L.PD)
+    psi = None
+    if want_vector:
+        psi = torch.empty(ham.basis.dim, dtype=tdt, device=f"cuda:{ham.basis.ctx.device}")
+        o.psi_dev = psi.data_ptr()
+    o.use_graph = 1 if use_graph else 0
+    o.time_kernels = 1 if time_kernels else 0
+    e = np.zeros(n_energies)
+    info = L.LanczosInfo()
+    _check(L.lib().hphi_lanczos(ham.h, C.byref(o), e.ctypes.data_as(L.PD), n_energies, C.byref(info)),
+           "hphi_lanczos")
+    n = info.iterations
+    return {"energies": e, "alpha": alpha[:n], "beta": beta[:n], "iterations": n,
+            "converged": bool(info.converged), "breakdown": bool(info.breakdown),
+            "seconds": info.seconds, "hv_seconds": info.hv_seconds, "hv_calls": info.hv_calls,
+            "psi": psi}
+
+
+def tridiag_lowest(alpha: np.ndarray, beta: np.ndarray, k: int = 1, want_vector: bool = False):
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    ev = np.zeros(k)
+    vec = np.zeros(len(a)) if want_vector else None
+    _check(L.lib().hphi_tridiag_lowest(a.ctypes.data_as(L.PD), b.ctypes.data_as(L.PD), len(a), k,
+                                       ev.ctypes.data_as(L.PD),
+                                       vec.ctypes.data_as(L.PD) if vec is not None else None),
+           "hphi_tridiag_lowest")
+    return (ev, vec) if want_vector else ev
+
+
+def ctpq(ham: Hamiltonian, n_vec: int, n_max: int, dtau: float, k_steps: int,
+         storage: str = "c128", seed: int = 1, phi0=None, stream=None) -> Dict:
+    torch = _torch()
+    o = L.CtpqOpts()
+    o.n_vec, o.n_max, o.dtau, o.k_steps, o.seed = n_vec, n_max, dtau, k_steps, seed
+    o.storage = L.C128 if storage == "c128" else L.C64
+    tdt = torch.complex128 if storage == "c128" else torch.complex64
+    if phi0 is not None:
+        _dev_check(phi0, "phi0")
+        if phi0.dtype != tdt:
+            raise HphiError("phi0 must have the storage dtype")
+        o.phi0_dev = phi0.data_ptr()
+    o.stream = _stream_ptr(stream)
+    phi = torch.empty((ham.basis.dim, n_vec), dtype=tdt, device=f"cuda:{ham.basis.ctx.device}")
+    D = np.zeros((k_steps + 1, n_vec))
+    E = np.zeros((k_steps + 1, n_vec))
+    E2 = np.zeros((k_steps + 1, n_vec))
+    _check(L.lib().hphi_ctpq(ham.h, C.byref(o), phi.data_ptr(), D.ctypes.data_as(L.PD),
+                             E.ctypes.data_as(L.PD), E2.ctypes.data_as(L.PD)), "hphi_ctpq")
+    return {"beta": dtau * np.arange(k_steps + 1), "D": D, "E": E, "E2": E2, "phi": phi}
+
+
+def szq(ham: Hamiltonian, q: float, psi, stream=None):
+    """b = sum_l e^{i q x_l} S^z_l psi, x_l from the model's site_x."""
+    torch = _torch()
+    _dev_check(psi, "psi")
+    x = np.asarray(ham.model.site_x, dtype=np.float64)
+    phase = np.empty(2 * len(x))
+    phase[0::2] = np.cos(q * x)
+    phase[1::2] = np.sin(q * x)
+    b = torch.empty(ham.basis.dim, dtype=torch.complex128, device=psi.device)
+    _check(L.lib().hphi_szq(ham.h, phase.ctypes.data_as(L.PD), psi.data_ptr(), b.data_ptr(),
+                            _stream_ptr(stream)), "hphi_szq")
+    return b
+
+
+def sqw(ham: Hamiltonian, b, z: Sequence[complex], max_iter: int = 2000, tol: float = 1e-8,
+        seed_shift: int = -1, stream=None) -> Dict:
+    _dev_check(b, "b")
+    z = np.asarray(z, dtype=np.complex128)
+    zr, zi = np.ascontiguousarray(z.real), np.ascontiguousarray(z.imag)
+    D = np.zeros(2 * len(z))
+    res = np.zeros(len(z))
+    o = L.SqwOpts()
+    o.max_iter, o.tol, o.seed_shift, o.stream = max_iter, tol, seed_shift, _stream_ptr(stream)
+    info = L.SqwInfo()
+    _check(L.lib().hphi_sqw(ham.h, C.byref(o), b.data_ptr(), zr.ctypes.data_as(L.PD),
+                            zi.ctypes.data_as(L.PD), len(z), D.ctypes.data_as(L.PD),
+                            res.ctypes.data_as(L.PD), C.byref(info)), "hphi_sqw")
+    return {"D": D[0::2] + 1j * D[1::2], "residual": res, "iterations": info.iterations,
+            "converged": bool(info.converged), "max_residual": info.max_residual,
+            "seconds": info.seconds}

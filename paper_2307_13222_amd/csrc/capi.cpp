@@ -1,0 +1,596 @@
+// C ABI entry points: contexts, bases, Hamiltonians, H*v, trace, Lanczos.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+
+#include "internal.h"
+
+using namespace hphi;
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+int ensure_reduce(hphi_ham *h)
+{
+    if (!h->red_partial.p) {
+        HPHI_TRY(h->red_partial.alloc(sizeof(double) * (size_t)kMaxGrid * 64));
+        HPHI_TRY(h->red_counter.alloc(sizeof(unsigned) * 16));
+        HPHI_HIP(hipMemset(h->red_counter.p, 0, sizeof(unsigned) * 16));
+        HPHI_TRY(h->red_result.alloc(sizeof(double) * 128));
+    }
+    return HPHI_OK;
+}
+
+Reduce reduce_of(hphi_ham *h, double *result = nullptr)
+{
+    Reduce r;
+    r.partial = h->red_partial.as<double>();
+    r.counter = h->red_counter.as<unsigned>();
+    r.result = result ? result : h->red_result.as<double>();
+    return r;
+}
+
+} // namespace
+
+namespace hphi {
+
+int launch_mult(hphi_ham *h, const MultArgs &a)
+{
+    if (h->kind == 0) return launch_spin_mult(h, a);
+    return launch_hub_mult(h, a);
+}
+
+} // namespace hphi
+
+extern "C" {
+
+const char *hphi_version(void) { return "hphi_mi355 0.1 (gfx950)"; }
+
+const char *hphi_last_error(void) { return hphi::last_error(); }
+
+int hphi_init(int device, hphi_ctx **ctx)
+{
+    if (!ctx) return fail(HPHI_ERR_INVALID_ARG, "ctx is NULL");
+    int n = 0;
+    HPHI_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(HPHI_ERR_INVALID_ARG, "device %d of %d", device, n);
+    HPHI_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HPHI_HIP(hipGetDeviceProperties(&prop, device));
+    auto *c = new hphi_ctx;
+    c->device = device;
+    c->n_cu = prop.multiProcessorCount;
+    c->lds_per_block = prop.sharedMemPerBlock;
+    *ctx = c;
+    return HPHI_OK;
+}
+
+void hphi_fini(hphi_ctx *ctx) { delete ctx; }
+
+int hphi_basis_spin(hphi_ctx *ctx, int n_sites, int two_sz, hphi_basis **out)
+{
+    if (!ctx || !out) return fail(HPHI_ERR_INVALID_ARG, "null argument");
+    if (n_sites < 1 || n_sites > 64) return fail(HPHI_ERR_INVALID_ARG, "n_sites %d outside [1, 64]", n_sites);
+    if (std::abs(two_sz) > n_sites || ((n_sites + two_sz) & 1))
+        return fail(HPHI_ERR_INVALID_ARG, "2Sz = %d impossible for %d sites", two_sz, n_sites);
+    DeviceGuard g(ctx->device);
+    std::unique_ptr<hphi_basis> b(new hphi_basis);
+    b->ctx = ctx;
+    b->kind = 0;
+    b->n_sites = n_sites;
+    const int n_up = (n_sites + two_sz) / 2;
+    // materialize the state list when it is addressable by 32-bit indices
+    // and configurations fit 32 bits; larger sectors stay implicit
+    const bool mat = n_sites <= 32;
+    HPHI_TRY(build_species(b->sp[0], n_sites, n_up, 0, false));
+    if (mat && b->sp[0].dim < (int64_t(1) << 32)) {
+        HPHI_TRY(b->sp[0].d_states.alloc((size_t)b->sp[0].dim * b->sp[0].state_bytes));
+        HPHI_TRY(launch_materialize(b->sp[0], nullptr));
+        HPHI_HIP(hipDeviceSynchronize());
+    }
+    b->dim = b->sp[0].dim;
+    *out = b.release();
+    return HPHI_OK;
+}
+
+int hphi_basis_hubbard(hphi_ctx *ctx, int n_sites, int n_up, int n_dn, hphi_basis **out)
+{
+    if (!ctx || !out) return fail(HPHI_ERR_INVALID_ARG, "null argument");
+    if (n_sites < 1 || n_sites > 32) return fail(HPHI_ERR_INVALID_ARG, "n_sites %d outside [1, 32]", n_sites);
+    if (n_up < 0 || n_up > n_sites || n_dn < 0 || n_dn > n_sites)
+        return fail(HPHI_ERR_INVALID_ARG, "n_up/n_dn outside [0, %d]", n_sites);
+    DeviceGuard g(ctx->device);
+    std::unique_ptr<hphi_basis> b(new hphi_basis);
+    b->ctx = ctx;
+    b->kind = 1;
+    b->n_sites = n_sites;
+    HPHI_TRY(build_species(b->sp[0], n_sites, n_up, 0, true));
+    HPHI_TRY(build_species(b->sp[1], n_sites, n_dn, 0, true));
+    if (b->sp[0].dim > (int64_t)kNbrColMask || b->sp[1].dim > (int64_t)kNbrColMask)
+        return fail(HPHI_ERR_DIM_OVERFLOW, "one-species dimension above 2^24");
+    unsigned __int128 d = (unsigned __int128)b->sp[0].dim * (unsigned __int128)b->sp[1].dim;
+    if (d > ((unsigned __int128)1 << 62)) return fail(HPHI_ERR_DIM_OVERFLOW, "dimension beyond 2^62");
+    b->dim = (int64_t)d;
+    *out = b.release();
+    return HPHI_OK;
+}
+
+void hphi_basis_free(hphi_basis *b) { delete b; }
+
+int64_t hphi_basis_dim(const hphi_basis *b) { return b ? b->dim : 0; }
+
+int hphi_basis_states(const hphi_basis *b, int64_t first, int64_t count, uint64_t *host_out)
+{
+    if (!b || (!host_out && count > 0)) return fail(HPHI_ERR_INVALID_ARG, "null argument");
+    if (first < 0 || count < 0 || first + count > b->dim) return fail(HPHI_ERR_INVALID_ARG, "range outside the basis");
+    for (int64_t t = 0; t < count; ++t) {
+        const int64_t r = first + t;
+        if (b->kind == 0) {
+            host_out[t] = b->sp[0].state_at(r);
+        } else {
+            const int64_t ru = r / b->sp[1].dim, rd = r % b->sp[1].dim;
+            host_out[t] = (b->sp[0].state_at(ru) << 32) | b->sp[1].state_at(rd);
+        }
+    }
+    return HPHI_OK;
+}
+
+int hphi_basis_rank(const hphi_basis *b, const uint64_t *states, int64_t n, int64_t *idx_out)
+{
+    if (!b || ((!states || !idx_out) && n > 0)) return fail(HPHI_ERR_INVALID_ARG, "null argument");
+    for (int64_t t = 0; t < n; ++t) {
+        if (b->kind == 0) {
+            idx_out[t] = b->sp[0].rank_of(states[t]);
+        } else {
+            const int64_t ru = b->sp[0].rank_of(states[t] >> 32);
+            const int64_t rd = b->sp[1].rank_of(states[t] & 0xFFFFFFFFull);
+            idx_out[t] = (ru < 0 || rd < 0) ? -1 : ru * b->sp[1].dim + rd;
+        }
+    }
+    return HPHI_OK;
+}
+
+int hphi_basis_states_device(const hphi_basis *b, int64_t first, int64_t count, uint64_t *out_dev, void *stream)
+{
+    if (!b || (!out_dev && count > 0)) return fail(HPHI_ERR_INVALID_ARG, "null argument");
+    if (first < 0 || count < 0 || first + count > b->dim) return fail(HPHI_ERR_INVALID_ARG, "range outside the basis");
+    DeviceGuard g(b->ctx->device);
+    return launch_states_device(b, first, count, out_dev, (hipStream_t)stream);
+}
+
+int hphi_basis_rank_device(const hphi_basis *b, const uint64_t *states_dev, int64_t n, int64_t *idx_dev, void *stream)
+{
+    if (!b || ((!states_dev || !idx_dev) && n > 0) || n < 0) return fail(HPHI_ERR_INVALID_ARG, "bad argument");
+    DeviceGuard g(b->ctx->device);
+    return launch_rank_device(b, states_dev, n, idx_dev, (hipStream_t)stream);
+}
+
+int hphi_basis_tables(const hphi_basis *b, int species, const uint32_t **lo_rank, const uint64_t **hi_off,
+                      int *n_lo, int *n_hi)
+{
+    if (!b || species < 0 || species > b->kind) return fail(HPHI_ERR_INVALID_ARG, "bad species");
+    const Species &s = b->sp[species];
+    if (lo_rank) *lo_rank = s.lo_rank.data();
+    if (hi_off) *hi_off = s.hi_off.data();
+    if (n_lo) *n_lo = s.n_lo;
+    if (n_hi) *n_hi = s.n_hi;
+    return HPHI_OK;
+}
+
+int hphi_ham_spin(hphi_basis *b, const hphi_spin_bond *bonds, int n_bonds, const double *hz, hphi_ham **out)
+{
+    if (!b || !out || (n_bonds > 0 && !bonds)) return fail(HPHI_ERR_INVALID_ARG, "null argument");
+    if (b->kind != 0) return fail(HPHI_ERR_INVALID_ARG, "spin Hamiltonian needs a spin basis");
+    if (n_bonds < 0 || n_bonds > 4096) return fail(HPHI_ERR_INVALID_ARG, "n_bonds %d outside [0, 4096]", n_bonds);
+    DeviceGuard g(b->ctx->device);
+    std::unique_ptr<hphi_ham> h(new hphi_ham);
+    h->basis = b;
+    h->kind = 0;
+    h->n_bonds = n_bonds;
+    for (int k = 0; k < n_bonds; ++k) {
+        const int i = bonds[k].i, j = bonds[k].j;
+        if (i < 0 || j < 0 || i >= b->n_sites || j >= b->n_sites || i == j)
+            return fail(HPHI_ERR_INVALID_ARG, "bond %d (%d, %d) invalid for %d sites", k, i, j, b->n_sites);
+        SpinBondDev d{};
+        d.mask = (uint64_t(1) << i) | (uint64_t(1) << j);
+        d.jz4 = 0.25 * bonds[k].jz;
+        d.jxy2 = 0.5 * bonds[k].jxy;
+        d.i = i;
+        d.j = j;
+        h->bonds.push_back(d);
+    }
+    if (n_bonds > 0) HPHI_TRY(upload(h->d_bonds, h->bonds.data(), sizeof(SpinBondDev) * n_bonds));
+    else HPHI_TRY(h->d_bonds.alloc(sizeof(SpinBondDev)));
+    if (hz) {
+        h->has_field = true;
+        HPHI_TRY(upload(h->d_hz, hz, sizeof(double) * b->n_sites));
+    }
+    HPHI_TRY(ensure_reduce(h.get()));
+    *out = h.release();
+    return HPHI_OK;
+}
+
+// Per-species neighbour lists of the hopping matrix T_sigma: for state s
+// and transfer (i, j) with exactly one of i, j occupied, the target
+// s ^ (1<<i | 1<<j), value -t and sign (-1)^(occupied sites strictly
+// between i and j).
+static int build_hub_species(const Species &sp, const std::vector<hphi_hop> &hops,
+                             std::map<double, int> &classes, DevMem &off_d, DevMem &nbr_d, int64_t &max_deg,
+                             DevMem &sell_base_d, DevMem &sell_width_d, DevMem &sell_d)
+{
+    std::vector<uint32_t> off((size_t)sp.dim + 1, 0);
+    std::vector<uint32_t> ent;
+    ent.reserve((size_t)sp.dim * hops.size() / 2 + 1);
+    max_deg = 0;
+    for (int64_t r = 0; r < sp.dim; ++r) {
+        const uint64_t s = sp.state_at(r);
+        off[r] = (uint32_t)ent.size();
+        for (const hphi_hop &hp : hops) {
+            const int bi = (int)((s >> hp.i) & 1), bj = (int)((s >> hp.j) & 1);
+            if (bi == bj) continue;
+            const uint64_t t = s ^ ((uint64_t(1) << hp.i) | (uint64_t(1) << hp.j));
+            const int lo = std::min(hp.i, hp.j), hi = std::max(hp.i, hp.j);
+            const uint64_t between = (hi - lo > 1) ? (((uint64_t(1) << hi) - 1) & ~((uint64_t(1) << (lo + 1)) - 1)) : 0;
+            const uint32_t sign = (uint32_t)(__builtin_popcountll(s & between) & 1);
+            const int64_t tr = sp.rank_of(t);
+            const int cls = classes.at(-hp.t);
+            ent.push_back((uint32_t)tr | ((uint32_t)cls << 24) | (sign << 31));
+        }
+        max_deg = std::max<int64_t>(max_deg, (int64_t)ent.size() - off[r]);
+        if (ent.size() > 0xFFFFFFF0ull) return fail(HPHI_ERR_DIM_OVERFLOW, "neighbour list above 2^32 entries");
+    }
+    off[sp.dim] = (uint32_t)ent.size();
+    // sliced ELL, padded with zero-valued self entries
+    const int64_t nchunk = (sp.dim + kSellChunk - 1) / kSellChunk;
+    std::vector<uint32_t> base(nchunk + 1, 0), width(nchunk, 0), sell;
+    for (int64_t j = 0; j < nchunk; ++j) {
+        uint32_t wmax = 0;
+        for (int64_t c = j * kSellChunk; c < std::min(sp.dim, (j + 1) * kSellChunk); ++c)
+            wmax = std::max(wmax, off[c + 1] - off[c]);
+        width[j] = wmax;
+        base[j + 1] = base[j] + wmax * kSellChunk;
+    }
+    sell.assign(base[nchunk] > 0 ? base[nchunk] : 1, 0u);
+    for (int64_t j = 0; j < nchunk; ++j)
+        for (int l = 0; l < kSellChunk; ++l) {
+            const int64_t c = j * kSellChunk + l;
+            for (uint32_t k = 0; k < width[j]; ++k) {
+                uint32_t e = (uint32_t)(c < sp.dim ? c : 0) | (kZeroClass << 24);
+                if (c < sp.dim && k < off[c + 1] - off[c]) e = ent[off[c] + k];
+                sell[base[j] + (size_t)k * kSellChunk + l] = e;
+            }
+        }
+    HPHI_TRY(upload(off_d, off.data(), sizeof(uint32_t) * off.size()));
+    if (ent.empty()) ent.push_back(0);
+    HPHI_TRY(upload(nbr_d, ent.data(), sizeof(uint32_t) * ent.size()));
+    HPHI_TRY(upload(sell_base_d, base.data(), sizeof(uint32_t) * base.size()));
+    HPHI_TRY(upload(sell_width_d, width.data(), sizeof(uint32_t) * width.size()));
+    HPHI_TRY(upload(sell_d, sell.data(), sizeof(uint32_t) * sell.size()));
+    return HPHI_OK;
+}
+
+int hphi_ham_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops, const double *u_site, hphi_ham **out)
+{
+    if (!b || !out || (n_hops > 0 && !hops) || !u_site) return fail(HPHI_ERR_INVALID_ARG, "null argument");
+    if (b->kind != 1) return fail(HPHI_ERR_INVALID_ARG, "Hubbard Hamiltonian needs a Hubbard basis");
+    if (n_hops < 0 || n_hops > 4096) return fail(HPHI_ERR_INVALID_ARG, "n_hops %d outside [0, 4096]", n_hops);
+    DeviceGuard g(b->ctx->device);
+    std::unique_ptr<hphi_ham> h(new hphi_ham);
+    h->basis = b;
+    h->kind = 1;
+    std::map<double, int> classes;
+    for (int k = 0; k < n_hops; ++k) {
+        const int i = hops[k].i, j = hops[k].j;
+        if (i < 0 || j < 0 || i >= b->n_sites || j >= b->n_sites || i == j)
+            return fail(HPHI_ERR_INVALID_ARG, "hop %d (%d, %d) invalid for %d sites", k, i, j, b->n_sites);
+        h->hops.push_back(hops[k]);
+        if (!classes.count(-hops[k].t)) {
+            const int c = (int)classes.size();
+            if (c >= (int)kZeroClass) return fail(HPHI_ERR_INVALID_ARG, "more than 127 distinct transfer values");
+            classes[-hops[k].t] = c;
+        }
+    }
+    std::vector<double> coef(128, 0.0);
+    for (auto &kv : classes) coef[kv.second] = kv.first;
+    h->hub.n_coef = (int)classes.size();
+    HPHI_TRY(upload(h->hub.coef, coef.data(), sizeof(double) * 128));
+    h->u_site.assign(u_site, u_site + b->n_sites);
+    HPHI_TRY(upload(h->hub.u_site, u_site, sizeof(double) * b->n_sites));
+    h->hub.uniform_u = true;
+    h->hub.u0 = u_site[0];
+    for (int i = 1; i < b->n_sites; ++i)
+        if (u_site[i] != u_site[0]) h->hub.uniform_u = false;
+    for (int sgm = 0; sgm < 2; ++sgm)
+        HPHI_TRY(build_hub_species(b->sp[sgm], h->hops, classes, h->hub.off[sgm], h->hub.nbr[sgm],
+                                   h->hub.max_deg[sgm], h->hub.sell_base[sgm], h->hub.sell_width[sgm],
+                                   h->hub.sell[sgm]));
+    HPHI_TRY(ensure_reduce(h.get()));
+    *out = h.release();
+    return HPHI_OK;
+}
+
+void hphi_ham_free(hphi_ham *h) { delete h; }
+
+int hphi_ham_trace(hphi_ham *h, double *trace_out, void *stream)
+{
+    if (!h || !trace_out) return fail(HPHI_ERR_INVALID_ARG, "null argument");
+    DeviceGuard g(h->basis->ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    HPHI_TRY(launch_trace(h, reduce_of(h), st));
+    HPHI_HIP(hipMemcpyAsync(trace_out, h->red_result.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    HPHI_HIP(hipStreamSynchronize(st));
+    return HPHI_OK;
+}
+
+int hphi_mult(hphi_ham *h, hphi_dtype dt, const void *v_dev, void *w_dev, int64_t nvec, void *stream)
+{
+    if (!h || !v_dev || !w_dev) return fail(HPHI_ERR_INVALID_ARG, "null argument");
+    if (nvec < 1 || nvec > 32) return fail(HPHI_ERR_INVALID_ARG, "nvec %lld outside [1, 32]", (long long)nvec);
+    if (dt != HPHI_F64 && dt != HPHI_F32 && dt != HPHI_C128 && dt != HPHI_C64)
+        return fail(HPHI_ERR_INVALID_ARG, "unknown dtype %d", (int)dt);
+    if (nvec * dtype_lanes(dt) > 32) return fail(HPHI_ERR_INVALID_ARG, "more than 32 real lanes per state");
+    if (v_dev == w_dev) return fail(HPHI_ERR_INVALID_ARG, "v and w alias");
+    DeviceGuard g(h->basis->ctx->device);
+    MultArgs a{};
+    a.dtype = dt;
+    a.nvec = (int)nvec;
+    a.v = v_dev;
+    a.w = w_dev;
+    a.stream = (hipStream_t)stream;
+    a.red = reduce_of(h);
+    return launch_mult(h, a);
+}
+
+int hphi_tridiag_lowest(const double *alpha, const double *beta, int n, int k, double *eig_out, double *vec)
+{
+    return tridiag_lowest(alpha, beta, n, k, eig_out, vec);
+}
+
+// ---------------------------------------------------------------- Lanczos --
+
+namespace {
+
+struct LanczosRun {
+    hphi_ham *h;
+    int dt;
+    int64_t dim;
+    hipStream_t st;
+    DevMem q[3];
+    DevMem lz_mem, ab;   // LzDev; alpha[max_iter + 1] then beta[max_iter + 2]
+    LzDev *lz = nullptr;
+    double *alpha = nullptr, *beta = nullptr;
+    int cur = 0, prev = 2, wbuf = 1;
+    bool timing = false;
+    std::vector<hipEvent_t> ev;   // pairs around each H*v
+
+    ~LanczosRun()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+
+    int mark()
+    {
+        hipEvent_t e;
+        HPHI_HIP(hipEventCreate(&e));
+        ev.push_back(e);
+        HPHI_HIP(hipEventRecord(e, st));
+        return HPHI_OK;
+    }
+
+    int timed(double *seconds, int *calls)
+    {
+        double tot = 0.0;
+        for (size_t i = 0; i + 1 < ev.size(); i += 2) {
+            float ms = 0.f;
+            HPHI_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+            tot += ms;
+        }
+        *seconds = tot * 1e-3;
+        *calls = (int)(ev.size() / 2);
+        return HPHI_OK;
+    }
+
+    int setup(int max_iter)
+    {
+        const size_t bytes = (size_t)dim * dtype_size(dt);
+        for (auto &m : q) HPHI_TRY(m.alloc(bytes));
+        HPHI_TRY(lz_mem.alloc(sizeof(LzDev)));
+        HPHI_HIP(hipMemsetAsync(lz_mem.p, 0, sizeof(LzDev), st));
+        lz = lz_mem.as<LzDev>();
+        HPHI_TRY(ab.alloc(sizeof(double) * (2 * (size_t)max_iter + 4)));
+        HPHI_HIP(hipMemsetAsync(ab.p, 0, ab.bytes, st));
+        alpha = ab.as<double>();
+        beta = alpha + max_iter + 1;
+        return HPHI_OK;
+    }
+
+    int start(const hphi_lanczos_opts *o)
+    {
+        cur = 0; wbuf = 1; prev = 2;
+        if (o->v0_dev) {
+            HPHI_HIP(hipMemcpyAsync(q[0].p, o->v0_dev, (size_t)dim * dtype_size(dt), hipMemcpyDeviceToDevice, st));
+        } else {
+            HPHI_TRY(launch_rng_uniform(dt, q[0].p, dim, o->seed, st));
+        }
+        Reduce r = reduce_of(h, lz->nrm);
+        HPHI_TRY(launch_dots(dt, 1, dim, q[0].p, q[0].p, r, 1, st));
+        return launch_lz_init(dt, lz, dim, r, st);
+    }
+
+    // one Krylov step on the current buffers; first = no v_{k-1} term
+    int step(bool first, const double *svec, void *psi)
+    {
+        if (psi) HPHI_TRY(launch_lz_psi_accum(dt, lz, svec, dim, psi, q[cur].p, st));
+        MultArgs a{};
+        a.dtype = dt;
+        a.nvec = 1;
+        a.v = q[cur].p;
+        a.w = q[wbuf].p;
+        a.u = first ? nullptr : q[prev].p;
+        a.coef = lz->coef;
+        a.dots = 1;
+        a.dot_raw = 0;
+        a.red = reduce_of(h, lz->dot);
+        a.stream = st;
+        if (timing) HPHI_TRY(mark());
+        HPHI_TRY(launch_mult(h, a));
+        if (timing) HPHI_TRY(mark());
+        HPHI_TRY(launch_lz_update(dt, lz, alpha, beta, dim, q[wbuf].p, q[cur].p, reduce_of(h, lz->nrm), st));
+        const int old_prev = prev;
+        prev = cur;
+        cur = wbuf;
+        wbuf = old_prev;
+        return HPHI_OK;
+    }
+
+    int run(int n_iter, bool graph, const double *svec, void *psi, int check_every, double tol,
+            int n_energies, int *converged, std::vector<double> &last_ev)
+    {
+        int k = 0;
+        HPHI_TRY(step(true, svec, psi));
+        ++k;
+        if (graph && n_iter - k >= 6 && check_every == 0 && !psi) {
+            hipGraph_t gph;
+            hipGraphExec_t exec;
+            HPHI_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            int rc = HPHI_OK;
+            for (int t = 0; t < 3 && rc == HPHI_OK; ++t) rc = step(false, nullptr, nullptr);
+            hipError_t e = hipStreamEndCapture(st, &gph);
+            if (rc != HPHI_OK) return rc;
+            if (e != hipSuccess) return fail(HPHI_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+            HPHI_HIP(hipGraphInstantiate(&exec, gph, nullptr, nullptr, 0));
+            while (n_iter - k >= 3) {
+                HPHI_HIP(hipGraphLaunch(exec, st));
+                k += 3;
+            }
+            (void)hipGraphExecDestroy(exec);
+            (void)hipGraphDestroy(gph);
+        }
+        std::vector<double> ha, hb;
+        for (; k < n_iter; ++k) {
+            HPHI_TRY(step(false, svec, psi));
+            if (check_every > 0 && (k + 1) % check_every == 0) {
+                LzDev hl;
+                HPHI_HIP(hipMemcpyAsync(&hl, lz, sizeof(LzDev), hipMemcpyDeviceToHost, st));
+                HPHI_HIP(hipStreamSynchronize(st));
+                const int n = hl.iter;
+                if (hl.done || n < n_energies) {
+                    if (hl.done) break;
+                    continue;
+                }
+                ha.resize(n);
+                hb.resize(n + 1);
+                HPHI_HIP(hipMemcpy(ha.data(), alpha, sizeof(double) * n, hipMemcpyDeviceToHost));
+                HPHI_HIP(hipMemcpy(hb.data(), beta, sizeof(double) * (n + 1), hipMemcpyDeviceToHost));
+                std::vector<double> ev(n_energies);
+                HPHI_TRY(tridiag_lowest(ha.data(), hb.data(), n, n_energies, ev.data(), nullptr));
+                bool ok = last_ev.size() == ev.size();
+                for (size_t i = 0; ok && i < ev.size(); ++i)
+                    ok = std::fabs(ev[i] - last_ev[i]) < tol * std::max(1.0, std::fabs(ev[i]));
+                last_ev = ev;
+                if (ok) {
+                    *converged = 1;
+                    break;
+                }
+            }
+        }
+        return HPHI_OK;
+    }
+};
+
+} // namespace
+
+int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *o, double *energies, int n_energies,
+                 hphi_lanczos_info *info)
+{
+    if (!h || !o || (n_energies > 0 && !energies)) return fail(HPHI_ERR_INVALID_ARG, "null argument");
+    if (o->max_iter < 1 || o->max_iter > 100000) return fail(HPHI_ERR_INVALID_ARG, "max_iter %d", o->max_iter);
+    if (o->storage != HPHI_F64 && o->storage != HPHI_F32)
+        return fail(HPHI_ERR_INVALID_ARG, "Lanczos storage must be F64 or F32");
+    if (n_energies < 0 || n_energies > o->max_iter) return fail(HPHI_ERR_INVALID_ARG, "n_energies %d", n_energies);
+    if (o->check_every < 0) return fail(HPHI_ERR_INVALID_ARG, "check_every < 0");
+    DeviceGuard g(h->basis->ctx->device);
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = (hipStream_t)o->stream;
+    hipStream_t own = nullptr;
+    if (o->use_graph && !st) {
+        HPHI_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+        st = own;
+    }
+    struct StreamDrop {
+        hipStream_t s;
+        ~StreamDrop() { if (s) (void)hipStreamDestroy(s); }
+    } drop{own};
+    LanczosRun L;
+    L.h = h;
+    L.dt = o->storage;
+    L.dim = h->basis->dim;
+    L.st = st;
+    L.timing = o->time_kernels != 0 && !o->use_graph;
+    HPHI_TRY(L.setup(o->max_iter));
+    HPHI_TRY(L.start(o));
+    int converged = 0;
+    std::vector<double> last_ev;
+    HPHI_TRY(L.run(o->max_iter, o->use_graph != 0, nullptr, nullptr, o->check_every, o->tol,
+                   std::max(1, n_energies), &converged, last_ev));
+    LzDev hl;
+    HPHI_HIP(hipMemcpyAsync(&hl, L.lz, sizeof(LzDev), hipMemcpyDeviceToHost, st));
+    HPHI_HIP(hipStreamSynchronize(st));
+    const int n = hl.iter;
+    std::vector<double> ha(n), hb(n + 1);
+    HPHI_HIP(hipMemcpy(ha.data(), L.alpha, sizeof(double) * n, hipMemcpyDeviceToHost));
+    HPHI_HIP(hipMemcpy(hb.data(), L.beta, sizeof(double) * (n + 1), hipMemcpyDeviceToHost));
+    hb[0] = 0.0;
+    if (o->alpha_out) std::memcpy(o->alpha_out, ha.data(), sizeof(double) * n);
+    if (o->beta_out) std::memcpy(o->beta_out, hb.data(), sizeof(double) * n);
+    const int ne = std::min(n_energies, n);
+    if (ne > 0) HPHI_TRY(tridiag_lowest(ha.data(), hb.data(), n, ne, energies, nullptr));
+    for (int i = ne; i < n_energies; ++i) energies[i] = NAN;
+    double hv_s = 0.0;
+    int hv_n = 0;
+    if (L.timing) HPHI_TRY(L.timed(&hv_s, &hv_n));
+    L.timing = false;
+    if (o->psi_dev && n > 0) {
+        // second pass: same start vector and kernels, psi = sum_k s_k v_k
+        std::vector<double> s(n);
+        double e0;
+        HPHI_TRY(tridiag_lowest(ha.data(), hb.data(), n, 1, &e0, s.data()));
+        DevMem sv;
+        HPHI_TRY(upload(sv, s.data(), sizeof(double) * n));
+        HPHI_HIP(hipMemsetAsync(o->psi_dev, 0, (size_t)L.dim * dtype_size(L.dt), st));
+        HPHI_TRY(L.start(o));
+        std::vector<double> dummy;
+        int cv = 0;
+        HPHI_TRY(L.run(n, false, sv.as<double>(), o->psi_dev, 0, 0.0, 1, &cv, dummy));
+        Reduce r = reduce_of(h);
+        HPHI_TRY(launch_dots(L.dt, 1, L.dim, o->psi_dev, o->psi_dev, r, 1, st));
+        HPHI_TRY(launch_scale_lanes(L.dt, 1, L.dim, o->psi_dev, h->red_result.as<double>(), 1, st));
+        HPHI_HIP(hipStreamSynchronize(st));
+    }
+    if (info) {
+        info->iterations = n;
+        info->converged = converged;
+        info->breakdown = hl.breakdown;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        info->hv_seconds = hv_s;
+        info->hv_calls = hv_n;
+    }
+    return HPHI_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,237 @@
+// C ABI of the methods built on H*v: cTPQ (block Taylor propagator) and the
+// dynamical correlation function by shifted COCG.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+using namespace hphi;
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+Reduce reduce_at(hphi_ham *h, double *result)
+{
+    Reduce r;
+    r.partial = h->red_partial.as<double>();
+    r.counter = h->red_counter.as<unsigned>();
+    r.result = result;
+    return r;
+}
+
+} // namespace
+
+extern "C" {
+
+// cTPQ. The propagator U_c = sum_{n<=n_max} x^n / n!, x = -dtau H / 2, is
+// evaluated by Horner's rule y <- phi + (x / n) y for n = n_max .. 1 (the
+// same polynomial as the term-by-term sum), one block H*V per order with the
+// epilogue w = c1 H y + c2 phi fused into the kernel. The first order of each
+// step applies H to the normalized state itself, so its raw FP64 dots give
+// <phi|H|phi> and |H phi|^2 at beta_{k-1}; the last order's output dots give
+// the squared norm N_k = D_k of U_c phi.
+int hphi_ctpq(hphi_ham *h, const hphi_ctpq_opts *o, void *phi_dev, double *D_out, double *E_out,
+              double *E2_out)
+{
+    if (!h || !o || !phi_dev) return fail(HPHI_ERR_INVALID_ARG, "null argument");
+    if (o->n_vec < 1 || o->n_vec > 16) return fail(HPHI_ERR_INVALID_ARG, "n_vec %d outside [1, 16]", o->n_vec);
+    if (o->n_max < 1 || o->n_max > 64) return fail(HPHI_ERR_INVALID_ARG, "n_max %d outside [1, 64]", o->n_max);
+    if (o->k_steps < 0 || !(o->dtau > 0.0)) return fail(HPHI_ERR_INVALID_ARG, "k_steps / dtau");
+    if (o->storage != HPHI_C128 && o->storage != HPHI_C64)
+        return fail(HPHI_ERR_INVALID_ARG, "cTPQ storage must be C128 or C64");
+    if (h->kind == 1 && o->n_vec != 1)
+        return fail(HPHI_ERR_UNSUPPORTED, "Hubbard cTPQ runs one vector per call");
+    DeviceGuard g(h->basis->ctx->device);
+    hipStream_t st = (hipStream_t)o->stream;
+    const int dt = o->storage, nv = o->n_vec, nl = 2 * nv;
+    const int64_t dim = h->basis->dim;
+    const size_t bytes = (size_t)dim * nl * dtype_size(dt);
+    DevMem y1, y2, scal, res_first, res_last;
+    HPHI_TRY(y1.alloc(bytes));
+    HPHI_TRY(y2.alloc(bytes));
+    HPHI_TRY(scal.alloc(sizeof(double) * (2 * (size_t)o->n_max + 2 + 64)));
+    HPHI_TRY(res_first.alloc(sizeof(double) * 2 * 64));
+    HPHI_TRY(res_last.alloc(sizeof(double) * 2 * 64));
+    // epilogue coefficients: order n uses (c1, c2) = (-dtau / (2 n), 1)
+    std::vector<double> cf(2 * (size_t)o->n_max + 2, 0.0);
+    for (int n = 1; n <= o->n_max; ++n) {
+        cf[2 * n] = -o->dtau / (2.0 * n);
+        cf[2 * n + 1] = 1.0;
+    }
+    HPHI_HIP(hipMemcpy(scal.p, cf.data(), sizeof(double) * cf.size(), hipMemcpyHostToDevice));
+    double *d_coef = scal.as<double>();
+    double *d_lane_scale = d_coef + 2 * o->n_max + 2;
+
+    void *A = phi_dev;
+    if (o->phi0_dev) HPHI_HIP(hipMemcpyAsync(A, o->phi0_dev, bytes, hipMemcpyDeviceToDevice, st));
+    else HPHI_TRY(launch_rng_cgauss(dt, A, dim, nv, o->seed, st));
+
+    std::vector<double> hf(2 * nl), hl(2 * nl);
+    // N_0 and normalization
+    HPHI_TRY(launch_dots(dt, nl, dim, A, A, reduce_at(h, res_last.as<double>()), 1, st));
+    HPHI_HIP(hipMemcpyAsync(hl.data(), res_last.p, sizeof(double) * nl, hipMemcpyDeviceToHost, st));
+    HPHI_TRY(launch_pair_rsqrt(res_last.as<double>(), d_lane_scale, nl, st));
+    HPHI_TRY(launch_scale_lanes(dt, nl, dim, A, d_lane_scale, 0, st));
+    HPHI_HIP(hipStreamSynchronize(st));
+    for (int j = 0; j < nv; ++j)
+        if (D_out) D_out[j] = hl[2 * j] + hl[2 * j + 1];
+
+    void *Y[2] = {y1.p, y2.p};
+    const int K = o->k_steps;
+    for (int k = 0; k <= K; ++k) {
+        // k < K: one propagator step from beta_k to beta_{k+1};
+        // k == K: only the first-order product for <H>, <H^2> at beta_K.
+        const int n_top = o->n_max;
+        const void *src = A;
+        int yb = 0;
+        for (int n = n_top; n >= 1; --n) {
+            const bool first = (n == n_top), last = (n == 1);
+            MultArgs a{};
+            a.dtype = dt;
+            a.nvec = nv;
+            a.v = src;
+            a.w = Y[yb];
+            a.u = A;
+            a.coef = d_coef + 2 * n;
+            a.stream = st;
+            if (first) {
+                a.dots = 1;
+                a.dot_raw = 1;
+                a.red = reduce_at(h, res_first.as<double>());
+            } else if (last) {
+                a.dots = 1;
+                a.dot_raw = 0;
+                a.red = reduce_at(h, res_last.as<double>());
+            } else {
+                a.red = reduce_at(h, h->red_result.as<double>());
+            }
+            HPHI_TRY(launch_mult(h, a));
+            if (k == K) break;
+            src = Y[yb];
+            yb ^= 1;
+        }
+        if (k == K || n_top == 1) {
+            // norms of a first-order-only step need their own pass
+            if (k < K) HPHI_TRY(launch_dots(dt, nl, dim, Y[0], Y[0], reduce_at(h, res_last.as<double>()), 1, st));
+        }
+        HPHI_HIP(hipMemcpyAsync(hf.data(), res_first.p, sizeof(double) * 2 * nl, hipMemcpyDeviceToHost, st));
+        if (k < K) {
+            // the last order wrote Y[yb ^ 1]; its lanes' |.|^2 sit at res_last[nl + l]
+            void *out = Y[yb ^ 1];
+            double *nrm = res_last.as<double>() + (n_top == 1 ? 0 : nl);
+            HPHI_HIP(hipMemcpyAsync(hl.data(), nrm, sizeof(double) * nl, hipMemcpyDeviceToHost, st));
+            HPHI_TRY(launch_pair_rsqrt(nrm, d_lane_scale, nl, st));
+            HPHI_TRY(launch_scale_lanes(dt, nl, dim, out, d_lane_scale, 0, st));
+            // new state: copy back into the caller's buffer
+            HPHI_HIP(hipMemcpyAsync(A, out, bytes, hipMemcpyDeviceToDevice, st));
+        }
+        HPHI_HIP(hipStreamSynchronize(st));
+        for (int j = 0; j < nv; ++j) {
+            if (E_out) E_out[(size_t)k * nv + j] = hf[2 * j] + hf[2 * j + 1];
+            if (E2_out) E2_out[(size_t)k * nv + j] = hf[nl + 2 * j] + hf[nl + 2 * j + 1];
+            if (k < K && D_out) D_out[(size_t)(k + 1) * nv + j] = hl[2 * j] + hl[2 * j + 1];
+        }
+    }
+    return HPHI_OK;
+}
+
+int hphi_szq(hphi_ham *h, const double *phase, const void *psi_dev, void *b_dev, void *stream)
+{
+    if (!h || !phase || !psi_dev || !b_dev) return fail(HPHI_ERR_INVALID_ARG, "null argument");
+    if (h->kind != 0) return fail(HPHI_ERR_INVALID_ARG, "S^z(q) needs a spin Hamiltonian");
+    if (h->basis->n_sites > 64) return fail(HPHI_ERR_INVALID_ARG, "too many sites");
+    DeviceGuard g(h->basis->ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    DevMem ph;
+    HPHI_TRY(upload(ph, phase, sizeof(double) * 2 * h->basis->n_sites));
+    HPHI_TRY(launch_szq(h, ph.as<double>(), psi_dev, b_dev, st));
+    HPHI_HIP(hipStreamSynchronize(st));
+    return HPHI_OK;
+}
+
+int hphi_sqw(hphi_ham *h, const hphi_sqw_opts *o, const void *b_dev, const double *z_re, const double *z_im,
+             int n_shift, double *D_out, double *resid_out, hphi_sqw_info *info)
+{
+    if (!h || !o || !b_dev || !z_re || !z_im || !D_out) return fail(HPHI_ERR_INVALID_ARG, "null argument");
+    if (n_shift < 1 || n_shift > 4096) return fail(HPHI_ERR_INVALID_ARG, "n_shift %d outside [1, 4096]", n_shift);
+    if (o->max_iter < 1) return fail(HPHI_ERR_INVALID_ARG, "max_iter < 1");
+    if (o->seed_shift >= n_shift) return fail(HPHI_ERR_INVALID_ARG, "seed_shift out of range");
+    DeviceGuard g(h->basis->ctx->device);
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = (hipStream_t)o->stream;
+    const int64_t dim = h->basis->dim;
+    const int seed = o->seed_shift >= 0 ? o->seed_shift : n_shift / 2;
+    DevMem r, p, hp, cgm, shm;
+    HPHI_TRY(r.alloc(sizeof(double) * 2 * (size_t)dim));
+    HPHI_TRY(p.alloc(sizeof(double) * 2 * (size_t)dim));
+    HPHI_TRY(hp.alloc(sizeof(double) * 2 * (size_t)dim));
+    CgDev c0{};
+    c0.zs = {z_re[seed], z_im[seed]};
+    HPHI_TRY(upload(cgm, &c0, sizeof(CgDev)));
+    std::vector<ShiftDev> s0(n_shift);
+    for (int j = 0; j < n_shift; ++j) {
+        s0[j] = ShiftDev{};
+        s0[j].sigma = {z_re[j] - z_re[seed], z_im[j] - z_im[seed]};
+    }
+    HPHI_TRY(upload(shm, s0.data(), sizeof(ShiftDev) * n_shift));
+    Reduce red = reduce_at(h, h->red_result.as<double>());
+    HPHI_TRY(launch_cocg_init(b_dev, r.p, p.p, dim, cgm.p, shm.p, n_shift, o->tol, red, st));
+    int it = 0, converged = 0;
+    CgDev hc{};
+    const int check = 8;
+    while (it < o->max_iter) {
+        MultArgs a{};
+        a.dtype = HPHI_C128;
+        a.nvec = 1;
+        a.v = p.p;
+        a.w = hp.p;
+        a.red = red;
+        a.stream = st;
+        HPHI_TRY(launch_mult(h, a));
+        HPHI_TRY(launch_cocg_iter(r.p, p.p, hp.p, b_dev, dim, cgm.p, shm.p, n_shift, o->tol, red, st));
+        ++it;
+        if (it % check == 0 || it == o->max_iter) {
+            HPHI_HIP(hipMemcpyAsync(&hc, cgm.p, sizeof(CgDev), hipMemcpyDeviceToHost, st));
+            HPHI_HIP(hipStreamSynchronize(st));
+            if (hc.max_res < o->tol) {
+                converged = 1;
+                break;
+            }
+            if (hc.breakdown) break;
+        }
+    }
+    HPHI_HIP(hipMemcpyAsync(&hc, cgm.p, sizeof(CgDev), hipMemcpyDeviceToHost, st));
+    std::vector<ShiftDev> s1(n_shift);
+    HPHI_HIP(hipMemcpyAsync(s1.data(), shm.p, sizeof(ShiftDev) * n_shift, hipMemcpyDeviceToHost, st));
+    HPHI_HIP(hipStreamSynchronize(st));
+    double mx = 0.0;
+    for (int j = 0; j < n_shift; ++j) {
+        D_out[2 * j] = s1[j].X.re;
+        D_out[2 * j + 1] = s1[j].X.im;
+        if (resid_out) resid_out[j] = s1[j].res;
+        mx = std::max(mx, s1[j].res);
+    }
+    if (info) {
+        info->iterations = it;
+        info->converged = converged;
+        info->max_residual = mx;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return HPHI_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,253 @@
+// Internal declarations of the HIP library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hphi_mi355.h"
+
+namespace hphi {
+
+// Record a failure (thread-local message) and return `code`.
+int fail(int code, const char *fmt, ...);
+const char *last_error();
+
+#define HPHI_HIP(expr)                                                              \
+    do {                                                                            \
+        hipError_t e_ = (expr);                                                     \
+        if (e_ != hipSuccess)                                                       \
+            return ::hphi::fail(HPHI_ERR_DEVICE, "%s failed: %s (%s:%d)", #expr,   \
+                                hipGetErrorString(e_), __FILE__, __LINE__);         \
+    } while (0)
+
+#define HPHI_TRY(expr)                \
+    do {                              \
+        int rc_ = (expr);             \
+        if (rc_ != HPHI_OK) return rc_; \
+    } while (0)
+
+// Owning device allocation.
+struct DevMem {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem &) = delete;
+    DevMem &operator=(const DevMem &) = delete;
+    ~DevMem() { reset(); }
+    int alloc(size_t n);
+    void reset();
+    template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+int upload(DevMem &m, const void *host, size_t bytes);
+
+// One species' sector: n_bits-bit patterns with n_pop set bits, ascending,
+// ranked by the split two-level table idx = hi_off[x >> n_lo] + lo_rank[x & mask].
+struct Species {
+    int n_bits = 0, n_pop = 0, n_lo = 0, n_hi = 0;
+    int64_t dim = 0;
+    std::vector<uint32_t> lo_rank;      // 2^n_lo
+    std::vector<uint64_t> hi_off;       // 2^n_hi + 1
+    std::vector<uint32_t> lo_list;      // lo patterns grouped by popcount
+    std::vector<uint32_t> lo_list_off;  // n_lo + 2 group offsets
+    DevMem d_lo_rank, d_hi_off, d_hi_off32, d_lo_list, d_lo_list_off;
+    DevMem d_states;                    // materialized states (uint32 or uint64) or empty
+    int state_bytes = 0;
+    bool materialized() const { return d_states.p != nullptr; }
+    uint64_t state_at(int64_t r) const;  // host unrank via the tables
+    int64_t rank_of(uint64_t x) const;   // host rank, -1 if outside
+};
+
+int build_species(Species &s, int n_bits, int n_pop, int n_lo_override, bool materialize);
+
+} // namespace hphi
+
+struct hphi_ctx {
+    int device = 0;
+    int n_cu = 0;
+    size_t lds_per_block = 0;
+};
+
+struct hphi_basis {
+    hphi_ctx *ctx = nullptr;
+    int kind = 0;  // 0 = spin, 1 = Hubbard
+    int n_sites = 0;
+    int64_t dim = 0;
+    hphi::Species sp[2];
+};
+
+namespace hphi {
+
+// Spin bond as the kernels read it.
+struct SpinBondDev {
+    uint64_t mask;   // (1 << i) | (1 << j)
+    double jz4;      // jz / 4
+    double jxy2;     // jxy / 2
+    int32_t i, j;
+    int32_t pad0, pad1;
+};
+
+// Packed Hubbard neighbour entry: bits 0..23 target rank, 24..30 value
+// class, bit 31 fermion sign.
+constexpr uint32_t kNbrColMask = 0x00FFFFFFu;
+
+// Value class 127 is reserved for 0.0: sliced-ELL padding entries point at
+// their own column with that class, so padded slots need no branch.
+constexpr uint32_t kZeroClass = 127u;
+constexpr int kSellChunk = 64;
+
+struct HubTables {
+    DevMem off[2];   // uint32 [dim_sigma + 1]
+    DevMem nbr[2];   // uint32 packed entries
+    // sliced ELL of the same lists: chunks of 64 consecutive states, entry
+    // k of state c at sell[base[c / 64] + k * 64 + c % 64], width[c / 64]
+    // entries per state in the chunk (padded)
+    DevMem sell_base[2], sell_width[2], sell[2];
+    DevMem coef;     // double [128]: -t per value class
+    DevMem u_site;   // double [n_sites]
+    int n_coef = 0;
+    bool uniform_u = true;
+    double u0 = 0.0;
+    int64_t max_deg[2] = {0, 0};
+};
+
+} // namespace hphi
+
+struct hphi_ham {
+    hphi_basis *basis = nullptr;
+    int kind = 0;
+    // spin
+    int n_bonds = 0;
+    std::vector<hphi::SpinBondDev> bonds;
+    hphi::DevMem d_bonds;
+    hphi::DevMem d_hz;   // double [n_sites] or empty
+    bool has_field = false;
+    // Hubbard
+    hphi::HubTables hub;
+    std::vector<hphi_hop> hops;
+    std::vector<double> u_site;
+    // scratch for reductions
+    hphi::DevMem red_partial;   // double [kMaxGrid * 64]
+    hphi::DevMem red_counter;   // unsigned [16]
+    hphi::DevMem red_result;    // double [64]
+};
+
+namespace hphi {
+
+constexpr int kMaxGrid = 4096;
+
+// Reduction target: per-block partial sums, a completion counter, and the
+// reduced result (first `n` doubles) written by the last block to finish.
+struct Reduce {
+    double *partial = nullptr;
+    unsigned *counter = nullptr;
+    double *result = nullptr;
+};
+
+// ---- kernel launchers (kernels.hip) ----
+// w = c1 * (H v) + c2 * u; coef = device [c1, c2] or nullptr (c1 = 1, c2 = 0);
+// u may be nullptr. dots: 0 = none, 1 = sum v.w per lane, 2 = v.w and w.w
+// per lane (result[lane], result[nlanes + lane]).
+struct MultArgs {
+    int dtype;          // hphi_dtype
+    int nvec;           // vectors in the block
+    const void *v;
+    void *w;
+    const void *u;
+    void *acc;          // optional: acc += w (same layout)
+    const double *coef;
+    int dots;           // 0: none; 1: per-lane <v, x> and <x, x>
+    int dot_raw;        // x = H v (1) or x = the epilogue output w (0)
+    Reduce red;
+    hipStream_t stream;
+};
+int launch_spin_mult(hphi_ham *h, const MultArgs &a);
+int launch_hub_mult(hphi_ham *h, const MultArgs &a);
+int launch_mult(hphi_ham *h, const MultArgs &a);
+
+int launch_rank_device(const hphi_basis *b, const uint64_t *states, int64_t n, int64_t *idx,
+                       hipStream_t st);
+int launch_states_device(const hphi_basis *b, int64_t first, int64_t count, uint64_t *out,
+                         hipStream_t st);
+int launch_materialize(Species &s, hipStream_t st);
+
+// vector kernels
+int launch_rng_uniform(int dtype, void *out, int64_t n, uint64_t seed, hipStream_t st);
+int launch_rng_cgauss(int dtype, void *out, int64_t dim, int nvec, uint64_t seed, hipStream_t st);
+int launch_dots(int dtype, int nlanes, int64_t rows, const void *x, const void *y, Reduce red,
+                int mode, hipStream_t st);   // mode 0: x.y per lane; 1: x.x per lane
+int launch_scale_lanes(int dtype, int nlanes, int64_t rows, void *x, const double *scale_dev,
+                       int mode, hipStream_t st);   // mode 0: x *= s[lane]; 1: x *= 1/sqrt(s[lane])
+int launch_axpy_lanes(int dtype, int nlanes, int64_t rows, void *y, const void *x,
+                      const double *a_dev, double a_host, hipStream_t st);
+int launch_copy_cast(int dst_dtype, void *dst, int src_dtype, const void *src, int64_t n,
+                     hipStream_t st);
+int launch_trace(hphi_ham *h, Reduce red, hipStream_t st);
+int launch_szq(hphi_ham *h, const double *phase_dev, const void *psi, void *b, hipStream_t st);
+
+// Lanczos device scalars and kernels
+struct LzDev {
+    double coef[2];      // H*v epilogue: c1 = s_k, c2 = -beta_k s_{k-1}
+    double dot[4];       // result slot of the H*v kernel's <q_k, w>
+    double nrm[4];       // result slot of the update kernel / initial norm
+    double s_cur, s_prev;
+    double psi_coef;     // second pass: coefficient of q_k in psi
+    int iter;
+    int done;
+    int breakdown;
+    int pad;
+};
+int launch_lz_init(int dtype, LzDev *lz, int64_t dim, Reduce red, hipStream_t st);
+int launch_lz_update(int dtype, LzDev *lz, double *alpha, double *beta, int64_t dim, void *w,
+                     const void *qk, Reduce red, hipStream_t st);
+int launch_lz_psi_accum(int dtype, LzDev *lz, const double *svec, int64_t dim, void *psi,
+                        const void *qk, hipStream_t st);
+
+// host tridiagonal solver
+int tridiag_lowest(const double *alpha, const double *beta, int n, int k, double *eig,
+                   double *vec);
+
+int dtype_size(int dtype);     // bytes per scalar element (complex counts 2 lanes)
+int dtype_lanes(int dtype);    // 1 real, 2 complex
+bool dtype_is_f32(int dtype);
+
+} // namespace hphi
+
+namespace hphi {
+
+// ---- shifted COCG state (kern_methods.hip) ----
+struct cd {
+    double re, im;
+};
+
+struct CgDev {
+    cd zs;
+    cd rho;                 // r_k^T r_k
+    cd alpha, beta;         // current alpha_k, beta_k
+    cd alpha_prev, beta_prev;
+    double rnorm2;          // |r_{k+1}|^2
+    double bnorm2;          // |b|^2
+    cd bhr;                 // b^H r_{k+1}
+    double max_res;         // max over unconverged shifts of |r_j| / |b|
+    int iter;
+    int breakdown;
+};
+
+struct ShiftDev {
+    cd sigma, pi, pi_prev, X, P;
+    double res;
+    int conv;
+    int pad;
+};
+
+int launch_cocg_init(const void *b, void *r, void *p, int64_t dim, void *cg, void *sh, int nsh, double tol,
+                     Reduce red, hipStream_t st);
+int launch_cocg_iter(void *r, void *p, const void *h, const void *b, int64_t dim, void *cg, void *sh,
+                     int nsh, double tol, Reduce red, hipStream_t st);
+int launch_pair_rsqrt(const double *n, double *s, int nl, hipStream_t st);
+
+} // namespace hphi

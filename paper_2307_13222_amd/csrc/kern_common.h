@@ -1,0 +1,94 @@
+// Device helpers shared by the kernel files: wavefront/block reductions with a
+// deterministic last-block finish, packed-table lookups, SplitMix64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace hphi {
+
+constexpr int kBlock = 256;      // threads per workgroup for streaming kernels
+constexpr int kWave = 64;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Reduce NR per-thread values over the block; on return thread 0 holds the
+// sums in vals[]. `sh` needs NR * (blockDim / 64) doubles.
+template <int NR>
+__device__ __forceinline__ void block_sum(double (&vals)[NR], double *sh)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) vals[i] = wave_sum(vals[i]);
+    __syncthreads();
+    if (lane == 0)
+        for (int i = 0; i < NR; ++i) sh[i * nw + wid] = vals[i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NR; ++i) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += sh[i * nw + w];
+            vals[i] = s;
+        }
+    __syncthreads();
+}
+
+// Block partials -> red.partial[block * nres + i]; the last block to finish
+// sums the partials of all blocks in block order (fixed order, hence
+// run-to-run identical) into red.result[i] and re-arms the counter.
+// Returns true in the last block (all threads) so callers can finish scalar
+// work after the reduction; red.result is then valid for thread 0 only after
+// the final __syncthreads inside.
+__device__ __forceinline__ bool grid_finish(const double *blockvals, int nres, const Reduce &red,
+                                            double *sh)
+{
+    __shared__ unsigned s_last;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < nres; ++i) red.partial[(size_t)blockIdx.x * nres + i] = blockvals[i];
+        __threadfence();
+        unsigned prev = atomicAdd(red.counter, 1u);
+        s_last = (prev == gridDim.x - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    __threadfence();
+    const int nb = gridDim.x;
+    for (int i = 0; i < nres; ++i) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x)
+            v += __builtin_nontemporal_load(&red.partial[(size_t)b * nres + i]);
+        double vv[1] = {v};
+        block_sum<1>(vv, sh);
+        if (threadIdx.x == 0) red.result[i] = vv[0];
+    }
+    if (threadIdx.x == 0) *red.counter = 0u;
+    __threadfence();
+    __syncthreads();
+    return true;
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): state advances by the golden-ratio
+// constant; output is the published finalizer of the state.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double u53(uint64_t z) { return (double)(z >> 11) * (1.0 / 9007199254740992.0); }
+
+template <typename T> struct VecOf;
+template <> struct VecOf<double> { using t2 = double2; };
+template <> struct VecOf<float> { using t2 = float2; };
+
+} // namespace hphi

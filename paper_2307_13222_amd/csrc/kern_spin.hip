@@ -1,0 +1,263 @@
+// Spin-1/2 XXZ H*v on the S^z-conserved basis (Heisenberg/XXZ model of the
+// HPhi update paper, Sec. 3.2 and the Spin model keyword of Sec. 4.1).
+//
+// Gather formulation, one thread per output state x (row owner, no atomics):
+//   w[x] = diag(x) v[x] + sum_{bonds b antiparallel in x} (Jxy_b / 2) v[rank(x ^ m_b)]
+//   diag(x) = sum_b (Jz_b / 4) (+1 parallel, -1 antiparallel) - sum_i h_i S^z_i
+// rank() is the split two-level table hi_off[y >> n_lo] + lo_rank[y & mask],
+// staged in LDS when it fits. A block of NV real lanes per state (NV = 1 for
+// a real vector, 2 for one complex vector, 32 for 16 complex vectors) is
+// stored interleaved, so one gather moves NV * sizeof(S) contiguous bytes and
+// the index work is paid once for all lanes.
+#include "kern_common.h"
+
+namespace hphi {
+
+struct SpinKArgs {
+    const uint32_t *states;
+    int64_t dim;
+    const SpinBondDev *bonds;
+    int nb;
+    const double *hz;
+    int n_sites;
+    const uint32_t *lo_rank;
+    const uint32_t *hi_off;
+    int n_lo, n_hi;
+    const void *v;
+    void *w;
+    const void *u;
+    void *acc_out;
+    const double *coef;
+    int nd;
+    int dot_raw;   // dots of H v itself (1) or of the epilogue output (0)
+    Reduce red;
+};
+
+// Load NV contiguous scalars at p (p aligned to min(16, NV * sizeof(S))).
+template <typename S, int NV>
+__device__ __forceinline__ void load_lanes(const S *__restrict__ p, S (&o)[NV])
+{
+    constexpr int B = NV * (int)sizeof(S);
+    if constexpr (B >= 16) {
+        const float4 *q = reinterpret_cast<const float4 *>(p);
+#pragma unroll
+        for (int k = 0; k < B / 16; ++k) {
+            float4 t = q[k];
+            S *d = o + k * (16 / (int)sizeof(S));
+            __builtin_memcpy(d, &t, 16);
+        }
+    } else if constexpr (B == 8) {
+        float2 t = *reinterpret_cast<const float2 *>(p);
+        __builtin_memcpy(o, &t, 8);
+    } else {
+        o[0] = p[0];
+    }
+}
+
+template <typename S, int NV>
+__device__ __forceinline__ void store_lanes(S *__restrict__ p, const S (&o)[NV])
+{
+    constexpr int B = NV * (int)sizeof(S);
+    if constexpr (B >= 16) {
+        float4 *q = reinterpret_cast<float4 *>(p);
+#pragma unroll
+        for (int k = 0; k < B / 16; ++k) {
+            float4 t;
+            __builtin_memcpy(&t, o + k * (16 / (int)sizeof(S)), 16);
+            q[k] = t;
+        }
+    } else if constexpr (B == 8) {
+        float2 t;
+        __builtin_memcpy(&t, o, 8);
+        *reinterpret_cast<float2 *>(p) = t;
+    } else {
+        p[0] = o[0];
+    }
+}
+
+template <typename S, int NV, bool LDS_TAB, bool DOTS>
+__global__ __launch_bounds__(kBlock) void k_spin_hv(SpinKArgs a)
+{
+    extern __shared__ uint32_t smem_tab[];
+    __shared__ double sh_red[kBlock / kWave * 2 * 32];
+    __shared__ double sh_blk[64];
+
+    const uint32_t *lo = a.lo_rank;
+    const uint32_t *hi = a.hi_off;
+    if constexpr (LDS_TAB) {
+        const int nl = 1 << a.n_lo, nh = 1 << a.n_hi;
+        for (int i = threadIdx.x; i < nl; i += blockDim.x) smem_tab[i] = a.lo_rank[i];
+        for (int i = threadIdx.x; i < nh; i += blockDim.x) smem_tab[nl + i] = a.hi_off[i];
+        __syncthreads();
+        lo = smem_tab;
+        hi = smem_tab + nl;
+    }
+    const uint32_t lomask = (1u << a.n_lo) - 1u;
+    const int n_lo = a.n_lo;
+    const S *__restrict__ v = static_cast<const S *>(a.v);
+    S *__restrict__ w = static_cast<S *>(a.w);
+    const S *__restrict__ u = static_cast<const S *>(a.u);
+    S *__restrict__ accp = static_cast<S *>(a.acc_out);
+    double c1 = 1.0, c2 = 0.0;
+    if (a.coef) {
+        c1 = a.coef[0];
+        c2 = a.coef[1];
+    }
+    const S c1s = (S)c1, c2s = (S)c2;
+
+    constexpr int ND = DOTS ? NV : 1;
+    double d0[ND], d1[ND];
+#pragma unroll
+    for (int j = 0; j < ND; ++j) d0[j] = d1[j] = 0.0;
+
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < a.dim;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t x = a.states[r];
+        S acc[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) acc[j] = (S)0;
+        S diag = (S)0;
+        for (int b = 0; b < a.nb; ++b) {
+            const uint32_t m = (uint32_t)a.bonds[b].mask;
+            const uint32_t t = x & m;
+            const S jz4 = (S)a.bonds[b].jz4;
+            if (t == 0u || t == m) {
+                diag += jz4;
+            } else {
+                diag -= jz4;
+                const uint32_t y = x ^ m;
+                const uint32_t idx = hi[y >> n_lo] + lo[y & lomask];
+                const S cf = (S)a.bonds[b].jxy2;
+                S nv[NV];
+                load_lanes<S, NV>(v + (size_t)idx * NV, nv);
+#pragma unroll
+                for (int j = 0; j < NV; ++j) acc[j] += cf * nv[j];
+            }
+        }
+        if (a.hz) {
+            for (int i = 0; i < a.n_sites; ++i)
+                diag -= (S)a.hz[i] * (((x >> i) & 1u) ? (S)0.5 : (S)-0.5);
+        }
+        S me[NV];
+        load_lanes<S, NV>(v + (size_t)r * NV, me);
+        S hv[NV], out[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            hv[j] = acc[j] + diag * me[j];
+            out[j] = c1s * hv[j];
+        }
+        if (u) {
+            S uu[NV];
+            load_lanes<S, NV>(u + (size_t)r * NV, uu);
+#pragma unroll
+            for (int j = 0; j < NV; ++j) out[j] += c2s * uu[j];
+        }
+        store_lanes<S, NV>(w + (size_t)r * NV, out);
+        if (accp) {
+            S aa[NV];
+            load_lanes<S, NV>(accp + (size_t)r * NV, aa);
+#pragma unroll
+            for (int j = 0; j < NV; ++j) aa[j] += out[j];
+            store_lanes<S, NV>(accp + (size_t)r * NV, aa);
+        }
+        if constexpr (DOTS) {
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                const double o = a.dot_raw ? (double)hv[j] : (double)out[j];
+                d0[j] += (double)me[j] * o;
+                d1[j] += o * o;
+            }
+        }
+    }
+    if constexpr (DOTS) {
+        // per-lane block sums, one lane at a time to bound LDS use
+        for (int j = 0; j < NV; ++j) {
+            double vals[2] = {d0[j], d1[j]};
+            block_sum<2>(vals, sh_red);
+            if (threadIdx.x == 0) {
+                sh_blk[j] = vals[0];
+                sh_blk[NV + j] = vals[1];
+            }
+        }
+        __syncthreads();
+        grid_finish(sh_blk, 2 * NV, a.red, sh_red);
+    }
+}
+
+template <typename S, int NV, bool LDS>
+static void launch_spin_d(const SpinKArgs &a, int grid, size_t lds_bytes, hipStream_t st)
+{
+    if (a.nd) {
+        if (LDS) hipFuncSetAttribute((const void *)k_spin_hv<S, NV, LDS, true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        hipLaunchKernelGGL((k_spin_hv<S, NV, LDS, true>), dim3(grid), dim3(kBlock), lds_bytes, st, a);
+    } else {
+        if (LDS) hipFuncSetAttribute((const void *)k_spin_hv<S, NV, LDS, false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        hipLaunchKernelGGL((k_spin_hv<S, NV, LDS, false>), dim3(grid), dim3(kBlock), lds_bytes, st, a);
+    }
+}
+
+template <typename S, int NV>
+static int launch_spin_t(const SpinKArgs &a, bool lds, int grid, size_t lds_bytes, hipStream_t st)
+{
+    if (lds) launch_spin_d<S, NV, true>(a, grid, lds_bytes, st);
+    else launch_spin_d<S, NV, false>(a, grid, 0, st);
+    HPHI_HIP(hipGetLastError());
+    return HPHI_OK;
+}
+
+template <typename S>
+static int launch_spin_nv(int nv, const SpinKArgs &a, bool lds, int grid, size_t lds_bytes,
+                          hipStream_t st)
+{
+    switch (nv) {
+    case 1: return launch_spin_t<S, 1>(a, lds, grid, lds_bytes, st);
+    case 2: return launch_spin_t<S, 2>(a, lds, grid, lds_bytes, st);
+    case 4: return launch_spin_t<S, 4>(a, lds, grid, lds_bytes, st);
+    case 8: return launch_spin_t<S, 8>(a, lds, grid, lds_bytes, st);
+    case 16: return launch_spin_t<S, 16>(a, lds, grid, lds_bytes, st);
+    case 32: return launch_spin_t<S, 32>(a, lds, grid, lds_bytes, st);
+    }
+    return fail(HPHI_ERR_UNSUPPORTED, "spin H*v: %d real lanes per state (supported 1,2,4,8,16,32)", nv);
+}
+
+int launch_spin_mult(hphi_ham *h, const MultArgs &m)
+{
+    const hphi_basis *b = h->basis;
+    const Species &s = b->sp[0];
+    if (!s.materialized() || s.state_bytes != 4 || !s.d_hi_off32.p)
+        return fail(HPHI_ERR_UNSUPPORTED, "spin H*v with a materialized list needs N <= 32");
+    SpinKArgs a{};
+    a.states = s.d_states.as<uint32_t>();
+    a.dim = s.dim;
+    a.bonds = h->d_bonds.as<SpinBondDev>();
+    a.nb = h->n_bonds;
+    a.hz = h->has_field ? h->d_hz.as<double>() : nullptr;
+    a.n_sites = b->n_sites;
+    a.lo_rank = s.d_lo_rank.as<uint32_t>();
+    a.hi_off = s.d_hi_off32.as<uint32_t>();
+    a.n_lo = s.n_lo;
+    a.n_hi = s.n_hi;
+    a.v = m.v;
+    a.w = m.w;
+    a.u = m.u;
+    a.acc_out = m.acc;
+    a.coef = m.coef;
+    a.nd = m.dots;
+    a.dot_raw = m.dot_raw;
+    a.red = m.red;
+    const int nv = m.nvec * dtype_lanes(m.dtype);
+    size_t tab = sizeof(uint32_t) * ((size_t(1) << s.n_lo) + (size_t(1) << s.n_hi));
+    bool lds = tab <= 96 * 1024;
+    int64_t need = (s.dim + kBlock - 1) / kBlock;
+    int per_cu = lds ? (tab <= 16 * 1024 ? 8 : (tab <= 48 * 1024 ? 2 : 1)) : 8;
+    int64_t cap = (int64_t)(h->basis->ctx->n_cu > 0 ? h->basis->ctx->n_cu : 256) * per_cu;
+    if (cap > kMaxGrid) cap = kMaxGrid;
+    int grid = (int)(need < cap ? need : cap);
+    if (grid < 1) grid = 1;
+    if (dtype_is_f32(m.dtype)) return launch_spin_nv<float>(nv, a, lds, grid, tab, m.stream);
+    return launch_spin_nv<double>(nv, a, lds, grid, tab, m.stream);
+}
+
+} // namespace hphi

@@ -1,0 +1,381 @@
+"""GPU parity of the HIP path against the oracle, through the C ABI.
+
+Bars: bit-exact for basis states and indices; FP64 H*v within 1e-12 of the
+oracle relative to max|Hv|; Lanczos ground energies within 1e-10. Sizes span
+several workgroups with ragged tails; the full 4x4 Hubbard sector (dim
+165,636,900) and the 28-site sector are checked on sampled rows / exhaustive
+tables."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import core as O
+from paper_2307_13222_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2307_13222_amd import api as A
+    return A
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    return api.Context(0)
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def relmax(a, b):
+    return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+
+
+# ------------------------------------------------------------------ basis --
+
+@pytest.mark.parametrize("n,two_sz", [(1, 1), (2, 0), (12, 0), (13, 1), (16, 0), (17, -3), (20, 2)])
+def test_spin_basis_bit_exact(api, ctx, n, two_sz):
+    say("basis", n, two_sz)
+    b = api.Basis.spin(ctx, n, two_sz)
+    k = O.sector_popcount_spin(n, two_sz)
+    ref = O.basis_list(n, k)
+    assert b.dim == len(ref)
+    lo, hi, nlo, nhi = b.tables(0)
+    # table identity against the combinadic rank, exhaustively
+    idx = hi[ref >> np.uint64(nlo)].astype(np.int64) + lo[ref & np.uint64((1 << nlo) - 1)].astype(np.int64)
+    assert np.array_equal(idx, np.arange(len(ref)))
+    assert np.array_equal(lo.astype(np.int64), O.rank_combinadic(np.arange(1 << nlo, dtype=np.uint64)))
+    # device unrank and rank
+    st = host(b.states_device(0, b.dim)).astype(np.uint64)
+    assert np.array_equal(st, ref)
+    r = host(b.rank_device(dev(ref.astype(np.int64))))
+    assert np.array_equal(r, np.arange(len(ref)))
+    # configurations outside the sector rank to -1
+    bad = np.array([(1 << min(n, 62)) - 1 if k != n else 0, 0 if k else 1], dtype=np.int64)
+    assert np.all(host(b.rank_device(dev(bad))) == -1)
+    # host routines agree
+    assert np.array_equal(b.states(0, min(b.dim, 1000)), ref[:1000])
+    assert np.array_equal(b.rank(ref[:1000]), np.arange(min(b.dim, 1000)))
+
+
+def test_spin_basis_28_exhaustive(api, ctx):
+    say("basis 28")
+    b = api.Basis.spin(ctx, 28, 0)
+    ref = O.basis_list(28, 14)
+    st = host(b.states_device(0, b.dim)).astype(np.uint64)
+    assert np.array_equal(st, ref)
+    r = host(b.rank_device(dev(ref.astype(np.int64))))
+    assert np.array_equal(r, np.arange(len(ref)))
+
+
+def test_spin_basis_36_tables_and_samples(api, ctx):
+    say("basis 36")
+    b = api.Basis.spin(ctx, 36, 0)
+    assert b.dim == math.comb(36, 18) == 9075135300
+    lo, hi, nlo, nhi = b.tables(0)
+    assert np.array_equal(lo.astype(np.int64), O.rank_combinadic(np.arange(1 << nlo, dtype=np.uint64)))
+    # hi_off[h] = sum_{h' < h} C(n_lo, 18 - popcount(h')), exhaustively
+    pc = np.array([bin(h).count("1") for h in range(1 << nhi)])
+    cnt = np.array([math.comb(nlo, 18 - p) if 0 <= 18 - p <= nlo else 0 for p in pc], dtype=np.uint64)
+    assert np.array_equal(hi[:-1], np.concatenate([[0], np.cumsum(cnt)[:-1]]).astype(np.uint64))
+    rng = np.random.default_rng(36)
+    rows = np.concatenate([[0, 1, b.dim - 1], rng.integers(0, b.dim, 3000)]).astype(np.int64)
+    ref = np.array([O.unrank_combinadic(int(r), 18) for r in rows], dtype=np.uint64)
+    st = host(b.states_device(0, 1)).astype(np.uint64)
+    assert st[0] == (1 << 18) - 1
+    got = np.array([int(host(b.states_device(int(r), 1))[0]) for r in rows[:50]], dtype=np.uint64)
+    assert np.array_equal(got, ref[:50])
+    assert np.array_equal(host(b.rank_device(dev(ref.astype(np.int64)))), rows)
+
+
+@pytest.mark.parametrize("n,nu,nd", [(4, 2, 2), (6, 3, 2), (9, 4, 5), (16, 8, 8)])
+def test_hubbard_basis_bit_exact(api, ctx, n, nu, nd):
+    say("hub basis", n, nu, nd)
+    b = api.Basis.hubbard(ctx, n, nu, nd)
+    ups, dns = O.hubbard_basis(n, nu, nd)
+    assert b.dim == len(ups) * len(dns)
+    rng = np.random.default_rng(n)
+    rows = np.unique(np.concatenate([[0, b.dim - 1], rng.integers(0, b.dim, 5000)])).astype(np.int64)
+    ref = (ups[rows // len(dns)].astype(np.uint64) << np.uint64(32)) | dns[rows % len(dns)]
+    got = np.concatenate([host(b.states_device(int(r), 1)) for r in rows[:40]]).astype(np.uint64)
+    assert np.array_equal(got, ref[:40])
+    if b.dim <= 20000:
+        assert np.array_equal(host(b.states_device(0, b.dim)).astype(np.uint64),
+                              ((ups.astype(np.uint64)[:, None] << np.uint64(32)) | dns[None, :]).ravel())
+    assert np.array_equal(host(b.rank_device(dev(ref.astype(np.int64)))), rows)
+
+
+# ------------------------------------------------------------- spin H*v --
+
+SPIN_CASES = {
+    "chain16": (lambda: W.heisenberg_chain(16), 0),
+    "xxz_j2_18_sz2": (lambda: W.xxz_chain_j2(18), 2),
+    "ladder14": (lambda: W.random_heisenberg(14, "ladder", 3), 0),
+    "j1j2_4x4_field": (lambda: W._spin(16, W.square_pairs(4, 4) + W.square_pairs(4, 4, True),
+                                       [(1.0, 0.7)] * 32 + [(0.5, 0.45)] * 32, "j1j2f",
+                                       hz=np.linspace(-0.3, 0.4, 16)), 0),
+    "chain13_odd": (lambda: W.random_heisenberg(13, "chain", 9), 1),
+    "tiny3": (lambda: W._spin(3, [(0, 1), (1, 2)], [(1.0, 1.0), (0.5, 2.0)], "t3"), 1),
+}
+
+
+@pytest.mark.parametrize("case", list(SPIN_CASES))
+def test_spin_mult_f64(api, ctx, case):
+    say("spin mult", case)
+    mk, two_sz = SPIN_CASES[case]
+    m = mk()
+    b = api.Basis.spin(ctx, m.n_sites, two_sz)
+    h = api.Hamiltonian.spin(b, m)
+    s = O.basis_list(m.n_sites, O.sector_popcount_spin(m.n_sites, two_sz))
+    v = W.random_vector(len(s), 11)
+    w = host(h.mult(dev(v)))
+    ref = O.spin_hv(m, s, v)
+    assert relmax(w, ref) < 1e-12
+
+
+@pytest.mark.parametrize("nvec,dt", [(1, "c128"), (16, "c128"), (16, "c64"), (4, "f64"), (32, "f32"), (1, "f32")])
+def test_spin_mult_blocks(api, ctx, nvec, dt):
+    import torch
+    say("spin block", nvec, dt)
+    m = W.xxz_chain_j2(16)
+    b = api.Basis.spin(ctx, 16, 0)
+    h = api.Hamiltonian.spin(b, m)
+    s = O.basis_list(16, 8)
+    cplx = dt.startswith("c")
+    v = W.random_vector(len(s), 5, np.complex128 if cplx else np.float64, nvec=nvec)
+    if v.ndim == 1:
+        v = v[:, None]
+    tdt = {"c128": torch.complex128, "c64": torch.complex64, "f64": torch.float64, "f32": torch.float32}[dt]
+    vt = dev(v).to(tdt)
+    if nvec == 1:
+        vt = vt[:, 0].contiguous()
+    w = host(h.mult(vt)).reshape(len(s), nvec)
+    ref = O.spin_hv(m, s, host(vt).reshape(len(s), nvec).astype(np.complex128 if cplx else np.float64))
+    tol = 1e-12 if dt in ("c128", "f64") else 3e-6
+    assert relmax(w, ref) < tol
+    if dt in ("c128", "f64") and nvec > 1:
+        # a block column equals the single-vector product bit for bit
+        col = vt[:, 1].contiguous()
+        w1 = host(h.mult(col))
+        assert np.array_equal(w1, w[:, 1])
+
+
+def test_spin_mult_deterministic(api, ctx):
+    m = W.xxz_chain_j2(20)
+    b = api.Basis.spin(ctx, 20, 0)
+    h = api.Hamiltonian.spin(b, m)
+    v = dev(W.random_vector(b.dim, 2))
+    w1, w2 = host(h.mult(v)), host(h.mult(v))
+    assert np.array_equal(w1, w2)
+
+
+# ---------------------------------------------------------- Hubbard H*v --
+
+HUB_CASES = {
+    "sq2x3_33": (lambda: W.hubbard_square(2, 3, 1.0, 4.0), 3, 3),
+    "sq3x3_45": (lambda: W.hubbard_square(3, 3, 1.0, 4.0), 4, 5),
+    "chain10_random_u": (lambda: W.HubbardModel(10, *[np.asarray(a, np.int32) for a in zip(*W.chain_pairs(10))],
+                                                np.linspace(0.7, 1.3, 10), np.linspace(2.0, 5.0, 10), "c10"), 5, 4),
+    "sq2x4_empty_dn": (lambda: W.hubbard_square(2, 4, 1.0, 8.0), 3, 0),
+    "sq4x4_small_filling": (lambda: W.hubbard_square(4, 4, 1.0, 4.0), 2, 3),
+}
+
+
+@pytest.mark.parametrize("case", list(HUB_CASES))
+def test_hubbard_mult_f64(api, ctx, case):
+    say("hub mult", case)
+    mk, nu, nd = HUB_CASES[case]
+    m = mk()
+    b = api.Basis.hubbard(ctx, m.n_sites, nu, nd)
+    h = api.Hamiltonian.hubbard(b, m)
+    ups, dns = O.hubbard_basis(m.n_sites, nu, nd)
+    v = W.random_vector(b.dim, 21)
+    w = host(h.mult(dev(v)))
+    assert relmax(w, O.hubbard_hv(m, ups, dns, v)) < 1e-12
+    vc = W.random_vector(b.dim, 22, np.complex128)
+    wc = host(h.mult(dev(vc)))
+    assert relmax(wc, O.hubbard_hv(m, ups, dns, vc)) < 1e-12
+
+
+def test_hubbard_4x4_full_size_sampled_rows(api, ctx):
+    import torch
+    say("hub 4x4 full size")
+    m = W.hubbard_square(4, 4, 1.0, 4.0)
+    b = api.Basis.hubbard(ctx, 16, 8, 8)
+    h = api.Hamiltonian.hubbard(b, m)
+    ups, dns = O.hubbard_basis(16, 8, 8)
+    g = torch.Generator(device="cuda").manual_seed(3)
+    v = torch.rand(b.dim, dtype=torch.float64, device="cuda", generator=g) - 0.5
+    w = h.mult(v)
+    w2 = h.mult(v)
+    assert torch.equal(w, w2)
+    rng = np.random.default_rng(7)
+    rows = np.concatenate([[0, b.dim - 1], rng.integers(0, b.dim, 3000)])
+    wmax = float(w.abs().max())
+    errs = []
+    for r in rows:
+        cols, vals = O.hubbard_row(m, ups, dns, int(r) // 12870, int(r) % 12870)
+        vv = host(v[torch.from_numpy(cols).cuda()])
+        errs.append(abs(float(w[int(r)]) - float(np.dot(vals, vv))))
+    assert max(errs) / wmax < 1e-12
+    # trace over the full sector against the closed form U N_up N_dn / N dim
+    assert abs(h.trace() - 2650190400.0) < 1e-6 * 2650190400.0
+
+
+# ----------------------------------------------------------------- trace --
+
+def test_spin_trace_closed_form(api, ctx):
+    b = api.Basis.spin(ctx, 16, 0)
+    h = api.Hamiltonian.spin(b, W.heisenberg_chain(16))
+    assert abs(h.trace() + 3432.0) < 1e-9
+
+
+# --------------------------------------------------------------- Lanczos --
+
+def test_lanczos_heisenberg16(api, ctx):
+    import torch
+    say("lanczos c1")
+    m = W.heisenberg_chain(16)
+    b = api.Basis.spin(ctx, 16, 0)
+    h = api.Hamiltonian.spin(b, m)
+    r = api.lanczos(h, 200, seed=1)
+    bethe = -7.142296360616785
+    assert abs(r["energies"][0] - bethe) < 1e-10
+    # the oracle from the same start vector (its own SplitMix64 stream)
+    s = O.basis_list(16, 8)
+    v0 = O.splitmix_uniform(1, 0, len(s))
+    ro = O.lanczos(lambda x: O.spin_hv(m, s, x), v0, 200)
+    assert abs(r["energies"][0] - O.tridiag_lowest(ro["alpha"], ro["beta"])[0]) < 1e-10
+    assert np.allclose(r["alpha"][:20], ro["alpha"][:20], atol=1e-12)
+    assert np.allclose(r["beta"][1:20], ro["beta"][1:20], atol=1e-12)
+    # the device start vector is the same stream: pass the oracle's vector in
+    r2 = api.lanczos(h, 200, v0=dev(v0))
+    assert np.array_equal(r2["alpha"], r["alpha"]) and np.array_equal(r2["beta"], r["beta"])
+    # graph-captured iteration: identical numbers
+    r3 = api.lanczos(h, 200, seed=1, use_graph=True)
+    assert np.array_equal(r3["alpha"], r["alpha"])
+    # FP32 storage, FP64 scalars
+    r4 = api.lanczos(h, 200, seed=1, storage="f32")
+    assert abs(r4["energies"][0] - bethe) < 1e-5
+    assert torch.cuda.is_available()
+
+
+def test_lanczos_breakdown_and_vector(api, ctx):
+    import torch
+    say("lanczos breakdown / psi")
+    m = W._spin(8, W.chain_pairs(8), [(1.0, 0.0)] * 8, "ising")
+    b = api.Basis.spin(ctx, 8, 0)
+    h = api.Hamiltonian.spin(b, m)
+    v0 = np.zeros(b.dim); v0[5] = 1.0
+    r = api.lanczos(h, 50, v0=dev(v0))
+    assert r["breakdown"] and r["iterations"] == 1
+    m2 = W.random_heisenberg(12, "ladder", 2)
+    b2 = api.Basis.spin(ctx, 12, 0)
+    h2 = api.Hamiltonian.spin(b2, m2)
+    r2 = api.lanczos(h2, 150, seed=4, want_vector=True)
+    psi = r2["psi"]
+    res = h2.mult(psi) - r2["energies"][0] * psi
+    assert float(torch.linalg.norm(res)) < 1e-6
+    assert abs(float(torch.linalg.norm(psi)) - 1) < 1e-12
+    s = O.basis_list(12, 6)
+    assert abs(r2["energies"][0] - np.linalg.eigvalsh(O.spin_sparse(m2, s).toarray())[0]) < 1e-10
+
+
+def test_lanczos_check_every_converges(api, ctx):
+    m = W.random_heisenberg(14, "chain", 8)
+    b = api.Basis.spin(ctx, 14, 0)
+    h = api.Hamiltonian.spin(b, m)
+    r = api.lanczos(h, 500, seed=2, check_every=10, tol=1e-12)
+    assert r["converged"] and r["iterations"] < 500
+    s = O.basis_list(14, 7)
+    ro = O.lanczos(lambda x: O.spin_hv(m, s, x), O.splitmix_uniform(2, 0, len(s)), 300)
+    assert abs(r["energies"][0] - O.tridiag_lowest(ro["alpha"], ro["beta"])[0]) < 1e-10
+
+
+def test_lanczos_hubbard_small(api, ctx):
+    say("lanczos hubbard")
+    m = W.hubbard_square(2, 4, 1.0, 4.0)
+    b = api.Basis.hubbard(ctx, 8, 4, 4)
+    h = api.Hamiltonian.hubbard(b, m)
+    r = api.lanczos(h, 200, seed=3)
+    ups, dns = O.hubbard_basis(8, 4, 4)
+    e = np.linalg.eigvalsh(O.hubbard_sparse(m, ups, dns).toarray())[0]
+    assert abs(r["energies"][0] - e) < 1e-10
+    hu0 = api.Hamiltonian.hubbard(api.Basis.hubbard(ctx, 9, 4, 4), W.hubbard_square(3, 3, 1.0, 0.0))
+    r0 = api.lanczos(hu0, 250, seed=5)
+    levels = np.linalg.eigvalsh(-(np.roll(np.eye(3), 1, 0) + np.roll(np.eye(3), -1, 0)))
+    eps = np.sort((levels[:, None] + levels[None, :]).ravel())
+    assert abs(r0["energies"][0] - 2 * eps[:4].sum()) < 1e-9
+
+
+# ------------------------------------------------------------------ cTPQ --
+
+@pytest.mark.parametrize("dt,tol", [("c128", 1e-11), ("c64", 2e-5)])
+def test_ctpq_matches_oracle(api, ctx, dt, tol):
+    import torch
+    say("ctpq", dt)
+    m = W.heisenberg_chain(12)
+    b = api.Basis.spin(ctx, 12, 0)
+    h = api.Hamiltonian.spin(b, m)
+    s = O.basis_list(12, 6)
+    B = 4
+    phi0 = np.stack([O.splitmix_complex_gaussian(100 + j, len(s)) for j in range(B)], axis=1)
+    tdt = torch.complex128 if dt == "c128" else torch.complex64
+    g = api.ctpq(h, B, 6, 0.02, 25, storage=dt, phi0=dev(phi0).to(tdt))
+    phi_in = host(dev(phi0).to(tdt)).astype(np.complex128)
+    o = O.ctpq(lambda x: O.spin_hv(m, s, x), phi_in, 6, 0.02, 25)
+    assert relmax(g["D"], o["D"]) < tol
+    assert relmax(g["E"], o["E"]) < tol
+    assert relmax(g["E2"], o["E2"]) < tol
+
+
+def test_ctpq_device_rng_matches_oracle_stream(api, ctx):
+    say("ctpq rng")
+    m = W.heisenberg_chain(10)
+    b = api.Basis.spin(ctx, 10, 0)
+    h = api.Hamiltonian.spin(b, m)
+    g = api.ctpq(h, 2, 4, 0.05, 0, storage="c128", seed=40)
+    s = O.basis_list(10, 5)
+    for j in range(2):
+        z = O.splitmix_complex_gaussian(40 + j, len(s))
+        assert abs(g["D"][0, j] - np.vdot(z, z).real) < 1e-9 * np.vdot(z, z).real
+
+
+# ------------------------------------------------------------ S(q, w) ---
+
+@pytest.mark.parametrize("lattice,n", [("chain", 12), ("ladder", 12), ("chain", 13)])
+def test_sqw_matches_direct_solve(api, ctx, lattice, n):
+    say("sqw", lattice, n)
+    m = W.random_heisenberg(n, lattice, 17)
+    two_sz = n % 2
+    b = api.Basis.spin(ctx, n, two_sz)
+    h = api.Hamiltonian.spin(b, m)
+    s = O.basis_list(n, O.sector_popcount_spin(n, two_sz))
+    Hs = O.spin_sparse(m, s)
+    ev, U = np.linalg.eigh(Hs.toarray())
+    psi = U[:, 0]
+    q = math.pi
+    bo = O.szq_excitation(m, s, q, psi)
+    bg = api.szq(h, q, dev(psi))
+    assert relmax(host(bg), bo) < 1e-14
+    z = ev[0] + np.linspace(0, 4 * 1.5, 64) + 0.05j
+    g = api.sqw(h, bg, z, max_iter=3000, tol=1e-10)
+    assert g["converged"], g["max_residual"]
+    d_ref = O.dyn_corr_direct(Hs, bo, z)
+    assert relmax(g["D"], d_ref) < 1e-8
+    assert np.all(-g["D"].imag > 0)

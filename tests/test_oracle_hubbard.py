@@ -185,6 +185,15 @@ def test_hermitian_and_kronecker_structure():
     assert abs(Hs - K).max() < 1e-14
 
 
+def test_row_range_matches_full_product():
+    m = W.hubbard_square(2, 4, 1.0, 4.0)
+    ups, dns = O.hubbard_basis(8, 4, 3)
+    v = W.random_vector(len(ups) * len(dns), 8)
+    full = O.hubbard_hv(m, ups, dns, v).reshape(len(ups), len(dns))
+    part = O.hubbard_hv_rows(m, ups, dns, v, 13, 20).reshape(20, len(dns))
+    assert np.array_equal(part, full[13:33])
+
+
 def test_row_matches_sparse():
     m = W.hubbard_square(2, 4, 1.0, 4.0)
     ups, dns = O.hubbard_basis(8, 4, 4)
