@@ -33,6 +33,8 @@ def parse():
     p.add_argument("--iters", type=int, default=300)
     p.add_argument("--workload", default="hubbard4x4", choices=["hubbard4x4", "heisenberg16"])
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-tune", action="store_true", help="keep the default launch schedule")
+    p.add_argument("--retune", action="store_true", help="sweep schedules even if one is recorded")
     p.add_argument("--cpu-sample-rows", type=int, default=0,
                    help="oracle sample size in up-rows (0 = all rows, one full H*v)")
     return p.parse_args()
@@ -99,6 +101,14 @@ def main():
               "storage": "f64"}
     dim = basis.dim
     stream = torch.cuda.current_stream()
+    tuned = None
+    if not a.no_tune:
+        # schedule sweep (or cached lookup) outside the timed region
+        from paper_2307_13222_amd import autotune
+        tuned = autotune.tune(ham, "f64", 1, force=a.retune)
+        wl["schedule"] = tuned["schedule"]
+        if tuned.get("swept"):
+            print(json.dumps({"autotune": tuned}), file=sys.stderr, flush=True)
     for _ in range(a.warmup):
         api.lanczos(ham, a.iters, seed=1, stream=stream)
     torch.cuda.synchronize()

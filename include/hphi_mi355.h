@@ -148,6 +148,28 @@ int hphi_ham_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops,
 
 void hphi_ham_free(hphi_ham *h);
 
+/* Launch schedule of the H*v kernels of one Hamiltonian (set by the
+ * autotuner; zero fields keep the current value). Results do not depend on
+ * the schedule beyond floating-point summation order.
+ *   hub_slab_cols   columns per L2-resident slab of the Hubbard T_up kernel
+ *                   (8, 16, 32 or 64)
+ *   hub_groups      workgroups per XCD of that kernel (1..1024)
+ *   hub_item_rows   rows per work item of that kernel (8..128)
+ *   hub_row_cols    T_dn kernel variant: 1 = batched table loads, 2 = all
+ *                   loads of two columns issued at once, 3 = of one column
+ *   spin_per_cu     spin H*v workgroups per compute unit (1..16)
+ * Errors: INVALID_ARG (value outside its range). */
+typedef struct {
+    int hub_slab_cols;
+    int hub_groups;
+    int hub_item_rows;
+    int hub_row_cols;
+    int spin_per_cu;
+} hphi_schedule;
+
+int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s);
+int hphi_ham_get_schedule(const hphi_ham *h, hphi_schedule *s);
+
 /* Exact trace of H over the sector, summed on the device in FP64. */
 int hphi_ham_trace(hphi_ham *h, double *trace_out, void *stream);
 

@@ -40,6 +40,11 @@ class CtpqOpts(C.Structure):
                 ("phi0_dev", C.c_void_p), ("stream", C.c_void_p)]
 
 
+class Schedule(C.Structure):
+    _fields_ = [("hub_slab_cols", C.c_int), ("hub_groups", C.c_int), ("hub_item_rows", C.c_int),
+                ("hub_row_cols", C.c_int), ("spin_per_cu", C.c_int)]
+
+
 class SqwOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("tol", C.c_double), ("seed_shift", C.c_int),
                 ("stream", C.c_void_p)]
@@ -71,6 +76,8 @@ SIGNATURES = {
     "hphi_ham_spin": (I, [P, C.POINTER(SpinBond), I, PD, C.POINTER(P)]),
     "hphi_ham_hubbard": (I, [P, C.POINTER(Hop), I, PD, C.POINTER(P)]),
     "hphi_ham_free": (None, [P]),
+    "hphi_ham_set_schedule": (I, [P, C.POINTER(Schedule)]),
+    "hphi_ham_get_schedule": (I, [P, C.POINTER(Schedule)]),
     "hphi_ham_trace": (I, [P, PD, P]),
     "hphi_mult": (I, [P, I, P, P, I64, P]),
     "hphi_lanczos": (I, [P, C.POINTER(LanczosOpts), PD, I, C.POINTER(LanczosInfo)]),

@@ -182,6 +182,17 @@ class Hamiltonian:
                                  _stream_ptr(stream)), "hphi_mult")
         return w
 
+    SCHEDULE_FIELDS = ("hub_slab_cols", "hub_groups", "hub_item_rows", "hub_row_cols", "spin_per_cu")
+
+    def set_schedule(self, **kw):
+        s = L.Schedule(*[int(kw.get(f, 0)) for f in self.SCHEDULE_FIELDS])
+        _check(L.lib().hphi_ham_set_schedule(self.h, C.byref(s)), "hphi_ham_set_schedule")
+
+    def get_schedule(self) -> Dict[str, int]:
+        s = L.Schedule()
+        _check(L.lib().hphi_ham_get_schedule(self.h, C.byref(s)), "hphi_ham_get_schedule")
+        return {f: getattr(s, f) for f in self.SCHEDULE_FIELDS}
+
     def close(self):
         if self.h:
             L.lib().hphi_ham_free(self.h)

@@ -1,0 +1,94 @@
+"""Autotuner for the H*v launch schedules.
+
+Sweeps the schedule knobs of a Hamiltonian (Hubbard T_up slab width,
+workgroups per XCD, rows per work item, T_dn kernel variant; spin
+workgroups per CU), times w = H v for each candidate with HIP events on the
+launch stream, keeps the fastest and records it in a JSON table keyed by
+(model kind, dimensions, dtype, block width). Later runs look the key up and
+apply the stored schedule without sweeping. Only launch geometry changes:
+results agree up to floating-point summation order.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+from typing import Dict, List, Optional
+
+DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_build", "schedules.json")
+
+
+def schedule_key(ham, dtype: str, nvec: int) -> str:
+    b = ham.basis
+    m = ham.model
+    kind = b.kind
+    return f"{kind}:n{b.n_sites}:dim{b.dim}:{getattr(m, 'name', '')}:{dtype}:v{nvec}"
+
+
+def candidates(ham) -> List[Dict[str, int]]:
+    if ham.basis.kind == "hubbard":
+        out = []
+        for cw, g, rows, rc in itertools.product((8, 16, 32), (64, 128, 256), (32, 64, 128), (1, 2, 3)):
+            out.append({"hub_slab_cols": cw, "hub_groups": g, "hub_item_rows": rows, "hub_row_cols": rc})
+        return out
+    return [{"spin_per_cu": p} for p in (1, 2, 4, 8, 16)]
+
+
+def time_mult(ham, v, w, reps: int = 5) -> float:
+    """Median milliseconds of one H*v (HIP events on the current stream)."""
+    import torch
+    ham.mult(v, w)
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ham.mult(v, w)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    times.sort()
+    return times[len(times) // 2]
+
+
+def _load(path: str) -> Dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def tune(ham, dtype: str = "f64", nvec: int = 1, reps: int = 5, cands: Optional[List[Dict]] = None,
+         table: str = DEFAULT_TABLE, force: bool = False) -> Dict:
+    """Apply the best schedule for this Hamiltonian; sweep if unknown."""
+    import torch
+    key = schedule_key(ham, dtype, nvec)
+    tab = _load(table)
+    if key in tab and not force:
+        ham.set_schedule(**tab[key]["schedule"])
+        return {"key": key, "schedule": tab[key]["schedule"], "ms": tab[key]["ms"], "swept": False}
+    tdt = {"f64": torch.float64, "f32": torch.float32, "c128": torch.complex128, "c64": torch.complex64}[dtype]
+    dim = ham.basis.dim
+    shape = (dim,) if nvec == 1 else (dim, nvec)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    v = torch.rand(shape, dtype=torch.float64 if not tdt.is_complex else torch.complex128,
+                   device="cuda", generator=g).to(tdt) - 0.5
+    w = torch.empty_like(v)
+    results = []
+    for c in (cands or candidates(ham)):
+        ham.set_schedule(**c)
+        results.append((time_mult(ham, v, w, reps), c))
+    results.sort(key=lambda t: t[0])
+    best_ms, best = results[0]
+    ham.set_schedule(**best)
+    tab[key] = {"schedule": best, "ms": best_ms, "n_candidates": len(results),
+                "worst_ms": results[-1][0]}
+    os.makedirs(os.path.dirname(table), exist_ok=True)
+    tmp = table + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(tab, f, indent=1, sort_keys=True)
+    os.replace(tmp, table)
+    del v, w
+    return {"key": key, "schedule": best, "ms": best_ms, "swept": True,
+            "table": [(round(t, 4), c) for t, c in results[:8]], "worst_ms": results[-1][0]}

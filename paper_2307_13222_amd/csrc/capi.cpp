@@ -28,9 +28,11 @@ struct DeviceGuard {
 int ensure_reduce(hphi_ham *h)
 {
     if (!h->red_partial.p) {
-        HPHI_TRY(h->red_partial.alloc(sizeof(double) * (size_t)kMaxGrid * 64));
+        HPHI_TRY(h->red_partial.alloc(sizeof(double) * (size_t)kReduceSlots));
         HPHI_TRY(h->red_counter.alloc(sizeof(unsigned) * 16));
         HPHI_HIP(hipMemset(h->red_counter.p, 0, sizeof(unsigned) * 16));
+        HPHI_TRY(h->sched.alloc(sizeof(unsigned) * 16));
+        HPHI_HIP(hipMemset(h->sched.p, 0, sizeof(unsigned) * 16));
         HPHI_TRY(h->red_result.alloc(sizeof(double) * 128));
     }
     return HPHI_OK;
@@ -284,6 +286,76 @@ static int build_hub_species(const Species &sp, const std::vector<hphi_hop> &hop
     return HPHI_OK;
 }
 
+// Neighbour lists of one species split by the sign of the matrix element
+// -t_h * (-1)^(occupied sites between): with all |t_h| = t0 the element is
+// -t0 * s, s = sign(t_h) * fermion sign; `plus` holds s = +1, `minus` s = -1.
+static void split_lists(const Species &sp, const std::vector<hphi_hop> &hops,
+                        std::vector<std::vector<uint32_t>> &plus, std::vector<std::vector<uint32_t>> &minus)
+{
+    plus.assign((size_t)sp.dim, {});
+    minus.assign((size_t)sp.dim, {});
+    for (int64_t r = 0; r < sp.dim; ++r) {
+        const uint64_t s = sp.state_at(r);
+        for (const hphi_hop &hp : hops) {
+            if (((s >> hp.i) & 1) == ((s >> hp.j) & 1)) continue;
+            const uint64_t t = s ^ ((uint64_t(1) << hp.i) | (uint64_t(1) << hp.j));
+            const int lo = std::min(hp.i, hp.j), hi = std::max(hp.i, hp.j);
+            const uint64_t between = (hi - lo > 1) ? (((uint64_t(1) << hi) - 1) & ~((uint64_t(1) << (lo + 1)) - 1)) : 0;
+            const int fs = (__builtin_popcountll(s & between) & 1) ? -1 : 1;
+            const int se = fs * (hp.t < 0 ? -1 : 1);
+            (se > 0 ? plus : minus)[r].push_back((uint32_t)sp.rank_of(t));
+        }
+    }
+}
+
+static int build_hub_fast(hphi_ham *h)
+{
+    const hphi_basis *b = h->basis;
+    const Species &up = b->sp[0], &dn = b->sp[1];
+    std::vector<std::vector<uint32_t>> pl, mi;
+    // down species: sliced ELL of uint16 columns, plus part then minus part
+    split_lists(dn, h->hops, pl, mi);
+    const int64_t nchunk = (dn.dim + kSellChunk - 1) / kSellChunk;
+    std::vector<uint32_t> base(nchunk + 1, 0), wp(nchunk, 0), wm(nchunk, 0);
+    for (int64_t j = 0; j < nchunk; ++j) {
+        for (int64_t c = j * kSellChunk; c < std::min(dn.dim, (j + 1) * kSellChunk); ++c) {
+            wp[j] = std::max<uint32_t>(wp[j], (uint32_t)pl[c].size());
+            wm[j] = std::max<uint32_t>(wm[j], (uint32_t)mi[c].size());
+        }
+        base[j + 1] = base[j] + (wp[j] + wm[j]) * kSellChunk;
+        h->hub.fs_maxw = std::max(h->hub.fs_maxw, wp[j] + wm[j]);
+    }
+    std::vector<uint16_t> ent(std::max<uint32_t>(1, base[nchunk]), (uint16_t)dn.dim);
+    for (int64_t j = 0; j < nchunk; ++j)
+        for (int l = 0; l < kSellChunk; ++l) {
+            const int64_t c = j * kSellChunk + l;
+            if (c >= dn.dim) continue;
+            for (size_t k = 0; k < pl[c].size(); ++k) ent[base[j] + k * kSellChunk + l] = (uint16_t)pl[c][k];
+            for (size_t k = 0; k < mi[c].size(); ++k)
+                ent[base[j] + (wp[j] + k) * kSellChunk + l] = (uint16_t)mi[c][k];
+        }
+    HPHI_TRY(upload(h->hub.fs_base, base.data(), sizeof(uint32_t) * base.size()));
+    HPHI_TRY(upload(h->hub.fs_wp, wp.data(), sizeof(uint32_t) * wp.size()));
+    HPHI_TRY(upload(h->hub.fs_wm, wm.data(), sizeof(uint32_t) * wm.size()));
+    HPHI_TRY(upload(h->hub.fs_ent, ent.data(), sizeof(uint16_t) * ent.size()));
+    // up species: CSR, plus entries then minus entries, targets as row
+    // element offsets r' * dim_dn
+    split_lists(up, h->hops, pl, mi);
+    std::vector<uint32_t> off(up.dim + 1, 0), mid(up.dim, 0), tgt;
+    for (int64_t r = 0; r < up.dim; ++r) {
+        off[r] = (uint32_t)tgt.size();
+        for (uint32_t x : pl[r]) tgt.push_back((uint32_t)((uint64_t)x * (uint64_t)dn.dim));
+        mid[r] = (uint32_t)tgt.size();
+        for (uint32_t x : mi[r]) tgt.push_back((uint32_t)((uint64_t)x * (uint64_t)dn.dim));
+    }
+    off[up.dim] = (uint32_t)tgt.size();
+    if (tgt.empty()) tgt.push_back(0);
+    HPHI_TRY(upload(h->hub.fu_off, off.data(), sizeof(uint32_t) * off.size()));
+    HPHI_TRY(upload(h->hub.fu_mid, mid.data(), sizeof(uint32_t) * mid.size()));
+    HPHI_TRY(upload(h->hub.fu_ent, tgt.data(), sizeof(uint32_t) * tgt.size()));
+    return HPHI_OK;
+}
+
 int hphi_ham_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops, const double *u_site, hphi_ham **out)
 {
     if (!b || !out || (n_hops > 0 && !hops) || !u_site) return fail(HPHI_ERR_INVALID_ARG, "null argument");
@@ -319,12 +391,59 @@ int hphi_ham_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops, const doub
         HPHI_TRY(build_hub_species(b->sp[sgm], h->hops, classes, h->hub.off[sgm], h->hub.nbr[sgm],
                                    h->hub.max_deg[sgm], h->hub.sell_base[sgm], h->hub.sell_width[sgm],
                                    h->hub.sell[sgm]));
+    // uniform-magnitude transfers: the sign-split fast path
+    h->hub.uniform_t = n_hops > 0 && b->sp[1].dim < 65535 &&
+                       (unsigned __int128)b->sp[0].dim * (unsigned __int128)b->sp[1].dim * 2 < ((unsigned __int128)1 << 32);
+    for (int k = 0; k < n_hops && h->hub.uniform_t; ++k)
+        if (std::fabs(hops[k].t) != std::fabs(hops[0].t) || hops[k].t == 0.0) h->hub.uniform_t = false;
+    if (h->hub.uniform_t) {
+        h->hub.t0 = std::fabs(hops[0].t);
+        HPHI_TRY(build_hub_fast(h.get()));
+    }
     HPHI_TRY(ensure_reduce(h.get()));
     *out = h.release();
     return HPHI_OK;
 }
 
 void hphi_ham_free(hphi_ham *h) { delete h; }
+
+int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s)
+{
+    if (!h || !s) return fail(HPHI_ERR_INVALID_ARG, "null argument");
+    hphi_schedule n = h->sched_cfg;
+    if (s->hub_slab_cols) {
+        if (s->hub_slab_cols != 8 && s->hub_slab_cols != 16 && s->hub_slab_cols != 32 && s->hub_slab_cols != 64)
+            return fail(HPHI_ERR_INVALID_ARG, "hub_slab_cols %d", s->hub_slab_cols);
+        n.hub_slab_cols = s->hub_slab_cols;
+    }
+    if (s->hub_groups) {
+        if (s->hub_groups < 1 || s->hub_groups > 1024) return fail(HPHI_ERR_INVALID_ARG, "hub_groups %d", s->hub_groups);
+        n.hub_groups = s->hub_groups;
+    }
+    if (s->hub_item_rows) {
+        if (s->hub_item_rows < 8 || s->hub_item_rows > 128)
+            return fail(HPHI_ERR_INVALID_ARG, "hub_item_rows %d", s->hub_item_rows);
+        n.hub_item_rows = s->hub_item_rows;
+    }
+    if (s->hub_row_cols) {
+        if (s->hub_row_cols < 1 || s->hub_row_cols > 3)
+            return fail(HPHI_ERR_INVALID_ARG, "hub_row_cols %d", s->hub_row_cols);
+        n.hub_row_cols = s->hub_row_cols;
+    }
+    if (s->spin_per_cu) {
+        if (s->spin_per_cu < 1 || s->spin_per_cu > 16) return fail(HPHI_ERR_INVALID_ARG, "spin_per_cu %d", s->spin_per_cu);
+        n.spin_per_cu = s->spin_per_cu;
+    }
+    h->sched_cfg = n;
+    return HPHI_OK;
+}
+
+int hphi_ham_get_schedule(const hphi_ham *h, hphi_schedule *s)
+{
+    if (!h || !s) return fail(HPHI_ERR_INVALID_ARG, "null argument");
+    *s = h->sched_cfg;
+    return HPHI_OK;
+}
 
 int hphi_ham_trace(hphi_ham *h, double *trace_out, void *stream)
 {

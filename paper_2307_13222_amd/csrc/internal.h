@@ -107,6 +107,15 @@ struct HubTables {
     // k of state c at sell[base[c / 64] + k * 64 + c % 64], width[c / 64]
     // entries per state in the chunk (padded)
     DevMem sell_base[2], sell_width[2], sell[2];
+    // Uniform |t| fast path (every transfer has the same magnitude t0):
+    // lists split by fermion sign. Down species: sliced ELL of uint16
+    // column indices, per chunk `plus` then `minus` widths, padded with the
+    // index dim_dn (a zero slot). Up species: CSR with the sign split point.
+    bool uniform_t = false;
+    double t0 = 0.0;
+    uint32_t fs_maxw = 0;                    // widest down chunk (plus + minus)
+    DevMem fs_base, fs_wp, fs_wm, fs_ent;    // down: chunk base, widths, uint16 entries
+    DevMem fu_off, fu_mid, fu_ent;           // up: row offsets, split points, targets
     DevMem coef;     // double [128]: -t per value class
     DevMem u_site;   // double [n_sites]
     int n_coef = 0;
@@ -130,8 +139,10 @@ struct hphi_ham {
     hphi::HubTables hub;
     std::vector<hphi_hop> hops;
     std::vector<double> u_site;
-    // scratch for reductions
-    hphi::DevMem red_partial;   // double [kMaxGrid * 64]
+    hphi_schedule sched_cfg{16, 128, 64, 1, 8};
+    // scratch for reductions and work queues
+    hphi::DevMem sched;         // unsigned [16]: per-XCD item queues + counter
+    hphi::DevMem red_partial;   // double [kReduceSlots]
     hphi::DevMem red_counter;   // unsigned [16]
     hphi::DevMem red_result;    // double [64]
 };
@@ -139,6 +150,7 @@ struct hphi_ham {
 namespace hphi {
 
 constexpr int kMaxGrid = 4096;
+constexpr int64_t kReduceSlots = int64_t(1) << 20;   // doubles of reduction scratch
 
 // Reduction target: per-block partial sums, a completion counter, and the
 // reduced result (first `n` doubles) written by the last block to finish.

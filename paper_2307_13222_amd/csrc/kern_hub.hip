@@ -23,6 +23,9 @@
 
 namespace hphi {
 
+constexpr int kColsRows = 128;          // most rows per work item of the column kernel
+constexpr int kColsLdsEntries = 4096;   // staged neighbour entries per item (>= rows * max degree)
+
 struct HubKArgs {
     const uint32_t *ups, *dns;
     int64_t dup, ddn;
@@ -42,6 +45,14 @@ struct HubKArgs {
     int dot_raw;
     Reduce red;
     int nslab, groups;     // column kernel geometry
+    int item_rows;         // rows per work item (<= kColsRows)
+    int row_cols;          // columns per thread pass of the rows kernel (1, 2)
+    unsigned *sched;       // 8 per-XCD item queues + completion counter
+    // uniform |t| fast path
+    const uint32_t *fs_base, *fs_wp, *fs_wm;
+    const uint16_t *fs_ent;
+    const uint32_t *fu_off, *fu_mid, *fu_ent;
+    double t0;
 };
 
 template <typename S>
@@ -97,7 +108,21 @@ __global__ __launch_bounds__(1024) void k_hub_rows(HubKArgs a)
             const int64_t ch = c >> 6;
             const uint32_t *ent = a.sell_dn + a.sell_base_dn[ch] + (c & 63);
             const uint32_t width = a.sell_width_dn[ch];
-            for (uint32_t k = 0; k < width; ++k) {
+            uint32_t k = 0;
+            // sixteen table loads in flight per lane, then the LDS gathers
+            for (; k + 16 <= width; k += 16) {
+                uint32_t e[16];
+#pragma unroll
+                for (int t = 0; t < 16; ++t) e[t] = ent[(size_t)(k + t) * 64];
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    const S val = entry_val<S>(e[t], s_coef);
+                    const uint32_t col = e[t] & kNbrColMask;
+#pragma unroll
+                    for (int j = 0; j < NV; ++j) acc[j] += val * row[(size_t)col * NV + j];
+                }
+            }
+            for (; k < width; ++k) {
                 const uint32_t e = ent[(size_t)k * 64];
                 const S val = entry_val<S>(e, s_coef);
                 const uint32_t col = e & kNbrColMask;
@@ -105,26 +130,37 @@ __global__ __launch_bounds__(1024) void k_hub_rows(HubKArgs a)
                 for (int j = 0; j < NV; ++j) acc[j] += val * row[(size_t)col * NV + j];
             }
 #pragma unroll
-            for (int j = 0; j < NV; ++j) w[((size_t)ru * ddn + c) * NV + j] = acc[j];
+            for (int j = 0; j < NV; ++j) __builtin_nontemporal_store(acc[j], &w[((size_t)ru * ddn + c) * NV + j]);
         }
     }
 }
 
 // ---------------------------------------------------------------- cols --
-// Persistent grid of 8 * groups workgroups. Workgroups are dispatched to
-// the XCDs round-robin, so workgroup b runs on XCD b % 8; XCD x walks the
-// slabs x, x + 8, x + 16, ... and its `groups` workgroups split each slab's
-// rows, moving through the slabs together: the XCD's L2 holds V[:, slab].
+// Persistent grid. A work item is (slab, chunk of kColsRows rows); XCD x
+// owns the slabs x, x + 8, x + 16, ... and hands out its items in slab
+// order from its own atomic queue, so the workgroups resident on one XCD
+// work on one or two slabs at a time and that XCD's L2 holds V[:, slab].
+// A workgroup learns its XCD from the XCC_ID hardware register; when its
+// queue is empty it takes items from the other XCDs' queues, so every item
+// runs whatever the placement of workgroups on XCDs. w and u are streamed
+// non-temporally so they do not displace the slab in L2.
+// Dot partials are kept per item (item = slab * nchunk + chunk), so the
+// final sum, taken in item order by the last workgroup to finish, does not
+// depend on which workgroup ran which item: results are run-to-run
+// identical. That workgroup also re-arms the queues.
+__device__ __forceinline__ int xcc_id() { return (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7u); }
+
 template <typename S, int NV, int CW, bool DOTS>
 __global__ __launch_bounds__(256) void k_hub_cols(HubKArgs a)
 {
     __shared__ S s_coef[128];
-    __shared__ double sh_red[16];
-    __shared__ double sh_blk[4];
+    __shared__ double sh_red[4 * 2 * NV + 8];
+    __shared__ uint32_t s_ent[kColsLdsEntries];
+    __shared__ uint32_t s_off[kColsRows + 1];
+    __shared__ int s_item;
+    __shared__ unsigned s_last;
     for (int i = threadIdx.x; i < 128; i += blockDim.x) s_coef[i] = (S)a.coef[i];
-    __syncthreads();
-    const int bid = blockIdx.x;
-    const int xcd = bid & 7, g = bid >> 3;
+    const int home = xcc_id();
     const S *__restrict__ v = static_cast<const S *>(a.v);
     S *__restrict__ w = static_cast<S *>(a.w);
     const S *__restrict__ u = static_cast<const S *>(a.u);
@@ -135,17 +171,48 @@ __global__ __launch_bounds__(256) void k_hub_cols(HubKArgs a)
         c2 = a.ecoef[1];
     }
     const S c1s = (S)c1, c2s = (S)c2;
-    double d0[NV], d1[NV];
-#pragma unroll
-    for (int j = 0; j < NV; ++j) d0[j] = d1[j] = 0.0;
 
     const int64_t ddn = a.ddn, dup = a.dup;
-    const int64_t rows_per_g = (dup + a.groups - 1) / a.groups;
-    const int64_t r0 = (int64_t)g * rows_per_g;
-    const int64_t r1 = r0 + rows_per_g < dup ? r0 + rows_per_g : dup;
+    const int nchunk = (int)((dup + a.item_rows - 1) / a.item_rows);
     constexpr int RPW = 64 / CW;              // rows per wave pass
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int slab = xcd; slab < a.nslab; slab += 8) {
+    int q = home, tries = 0;
+    for (;;) {
+        // next item: own XCD first, then the others in turn
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int it = -1;
+            while (tries < 8) {
+                const int nsl_q = q < a.nslab ? (a.nslab - q + 7) / 8 : 0;
+                const int cand = (int)atomicAdd(&a.sched[q], 1u);
+                if (cand < nsl_q * nchunk) {
+                    it = q + 8 * cand;   // (queue, index within the queue)
+                    break;
+                }
+                q = (q + 1) & 7;
+                ++tries;
+            }
+            s_item = it;
+        }
+        __syncthreads();
+        const int item = s_item;
+        if (item < 0) break;
+        const int iq = item & 7, idx = item >> 3;
+        const int slab = iq + 8 * (idx / nchunk);
+        const int chunk = idx % nchunk;
+        const int64_t r0 = (int64_t)chunk * a.item_rows;
+        const int64_t r1 = r0 + a.item_rows < dup ? r0 + a.item_rows : dup;
+        // stage the chunk's neighbour lists
+        {
+            const uint32_t base = a.off_up[r0];
+            for (int64_t i = threadIdx.x; i <= r1 - r0; i += blockDim.x) s_off[i] = a.off_up[r0 + i] - base;
+            const uint32_t n = a.off_up[r1] - base;
+            for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) s_ent[i] = a.nbr_up[base + i];
+        }
+        __syncthreads();
+        double d0[NV], d1[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) d0[j] = d1[j] = 0.0;
         const int64_t col = (int64_t)slab * CW + (lane % CW);
         const bool colok = col < ddn;
         for (int64_t r = r0 + wid * RPW + lane / CW; r < r1; r += 4 * RPW) {
@@ -153,10 +220,30 @@ __global__ __launch_bounds__(256) void k_hub_cols(HubKArgs a)
             const size_t me = (size_t)r * ddn + col;
             S acc[NV];
 #pragma unroll
-            for (int j = 0; j < NV; ++j) acc[j] = w[me * NV + j];
-            const uint32_t e0 = a.off_up[r], e1 = a.off_up[r + 1];
-            for (uint32_t e = e0; e < e1; ++e) {
-                const uint32_t ent = a.nbr_up[e];
+            for (int j = 0; j < NV; ++j) acc[j] = __builtin_nontemporal_load(&w[me * NV + j]);
+            const uint32_t e1 = s_off[r - r0 + 1];
+            uint32_t e = s_off[r - r0];
+            // up to GB neighbour rows in flight at once, then the FMAs
+            constexpr int GB = NV == 1 ? 32 : 16;
+            for (; e < e1; e += GB) {
+                S nv[GB][NV];
+                S val[GB];
+#pragma unroll
+                for (int t = 0; t < GB; ++t) {
+                    const bool ok = e + t < e1;
+                    const uint32_t ent = s_ent[ok ? e + t : e];
+                    val[t] = ok ? entry_val<S>(ent, s_coef) : (S)0;
+                    const size_t src = (size_t)(ent & kNbrColMask) * ddn + col;
+#pragma unroll
+                    for (int j = 0; j < NV; ++j) nv[t][j] = ok ? v[src * NV + j] : (S)0;
+                }
+#pragma unroll
+                for (int t = 0; t < GB; ++t)
+#pragma unroll
+                    for (int j = 0; j < NV; ++j) acc[j] += val[t] * nv[t][j];
+            }
+            for (; e < e1; ++e) {
+                const uint32_t ent = s_ent[e];
                 const S val = entry_val<S>(ent, s_coef);
                 const size_t src = (size_t)(ent & kNbrColMask) * ddn + col;
 #pragma unroll
@@ -170,13 +257,15 @@ __global__ __launch_bounds__(256) void k_hub_cols(HubKArgs a)
             }
             if (u) {
 #pragma unroll
-                for (int j = 0; j < NV; ++j) out[j] += c2s * u[me * NV + j];
+                for (int j = 0; j < NV; ++j) out[j] += c2s * __builtin_nontemporal_load(&u[me * NV + j]);
             }
 #pragma unroll
-            for (int j = 0; j < NV; ++j) w[me * NV + j] = out[j];
+            for (int j = 0; j < NV; ++j) __builtin_nontemporal_store(out[j], &w[me * NV + j]);
             if (accp) {
 #pragma unroll
-                for (int j = 0; j < NV; ++j) accp[me * NV + j] += out[j];
+                for (int j = 0; j < NV; ++j)
+                    __builtin_nontemporal_store(__builtin_nontemporal_load(&accp[me * NV + j]) + out[j],
+                                                &accp[me * NV + j]);
             }
             if constexpr (DOTS) {
 #pragma unroll
@@ -187,37 +276,423 @@ __global__ __launch_bounds__(256) void k_hub_cols(HubKArgs a)
                 }
             }
         }
-    }
-    if constexpr (DOTS) {
-        double vals[2 * NV];
+        if constexpr (DOTS) {
+            double vals[2 * NV];
 #pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            vals[j] = d0[j];
-            vals[NV + j] = d1[j];
+            for (int j = 0; j < NV; ++j) {
+                vals[j] = d0[j];
+                vals[NV + j] = d1[j];
+            }
+            block_sum<2 * NV>(vals, sh_red);
+            if (threadIdx.x == 0) {
+                const size_t slot = (size_t)slab * nchunk + chunk;
+                for (int j = 0; j < 2 * NV; ++j) a.red.partial[slot * 2 * NV + j] = vals[j];
+            }
         }
-        block_sum<2 * NV>(vals, sh_red);
-        if (threadIdx.x == 0)
-            for (int j = 0; j < 2 * NV; ++j) sh_blk[j] = vals[j];
-        __syncthreads();
-        grid_finish(sh_blk, 2 * NV, a.red, sh_red);
+    }
+    // last workgroup out: final dot sums in item order, re-arm the queues
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        s_last = (atomicAdd(&a.sched[8], 1u) == gridDim.x - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    if constexpr (DOTS) {
+        const size_t nitems = (size_t)a.nslab * nchunk;
+        for (int j = 0; j < 2 * NV; ++j) {
+            double s = 0.0;
+            for (size_t it = threadIdx.x; it < nitems; it += blockDim.x)
+                s += __builtin_nontemporal_load(&a.red.partial[it * 2 * NV + j]);
+            double vv[1] = {s};
+            block_sum<1>(vv, sh_red);
+            if (threadIdx.x == 0) a.red.result[j] = vv[0];
+        }
+    }
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 8; ++i) a.sched[i] = 0u;
+        a.sched[8] = 0u;
+        __threadfence();
     }
 }
 
-// Column-slab geometry: CW columns per slab, G workgroups per slab. The
-// defaults keep one 16-column slab (dim_up * 128 B for FP64) per XCD L2 with
-// about one slab's worth of workgroups resident per XCD.
-struct HubGeom {
-    int cw = 16;
-    int groups = 256;
-};
-static HubGeom g_hub_geom;
-
-extern "C" int hphi_internal_set_hub_geom(int cw, int groups)
+// ------------------------------------------------- uniform |t| fast path --
+// Every transfer has magnitude t0, so each list splits into the entries
+// whose element is -t0 (plus) and +t0 (minus):
+//   (T v)[x] = -t0 (sum_plus v - sum_minus v),
+// one address operation, one load and one add per neighbour, no value or
+// sign decoding. Rows kernel: uint16 column entries, padding points at a
+// zero slot behind the staged row.
+template <typename S, int NV>
+__global__ __launch_bounds__(1024) void k_hub_rows_f(HubKArgs a)
 {
-    if (!(cw == 16 || cw == 32 || cw == 64) || groups < 1 || groups > 4096) return HPHI_ERR_INVALID_ARG;
-    g_hub_geom.cw = cw;
-    g_hub_geom.groups = groups;
-    return HPHI_OK;
+    extern __shared__ unsigned char smem_raw[];
+    S *s_row = reinterpret_cast<S *>(smem_raw);
+    const S *__restrict__ v = static_cast<const S *>(a.v);
+    S *__restrict__ w = static_cast<S *>(a.w);
+    const int64_t ddn = a.ddn;
+    const S nt0 = (S)(-a.t0);
+    for (int64_t ru = blockIdx.x; ru < a.dup; ru += gridDim.x) {
+        const S *vrow = v + (size_t)ru * ddn * NV;
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < ddn * NV; i += blockDim.x) s_row[i] = vrow[i];
+        if (threadIdx.x < NV) s_row[ddn * NV + threadIdx.x] = (S)0;
+        __syncthreads();
+        const uint32_t uu = a.ups[ru];
+        for (int64_t c = threadIdx.x; c < ddn; c += blockDim.x) {
+            const S dg = hub_diag<S>(a, uu, a.dns[c]);
+            const int64_t ch = c >> 6;
+            const uint16_t *ent = a.fs_ent + a.fs_base[ch] + (c & 63);
+            const uint32_t wp = a.fs_wp[ch], wt = wp + a.fs_wm[ch];
+            S ap[NV], am[NV];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) ap[j] = am[j] = (S)0;
+            uint32_t k = 0;
+            for (; k + 8 <= wp; k += 8) {
+                uint32_t e[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) e[t] = ent[(k + t) * 64];
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+#pragma unroll
+                    for (int j = 0; j < NV; ++j) ap[j] += s_row[e[t] * NV + j];
+            }
+            for (; k < wp; ++k) {
+                const uint32_t e = ent[k * 64];
+#pragma unroll
+                for (int j = 0; j < NV; ++j) ap[j] += s_row[e * NV + j];
+            }
+            for (; k + 8 <= wt; k += 8) {
+                uint32_t e[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) e[t] = ent[(k + t) * 64];
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+#pragma unroll
+                    for (int j = 0; j < NV; ++j) am[j] += s_row[e[t] * NV + j];
+            }
+            for (; k < wt; ++k) {
+                const uint32_t e = ent[k * 64];
+#pragma unroll
+                for (int j = 0; j < NV; ++j) am[j] += s_row[e * NV + j];
+            }
+#pragma unroll
+            for (int j = 0; j < NV; ++j)
+                __builtin_nontemporal_store(dg * s_row[c * NV + j] + nt0 * (ap[j] - am[j]),
+                                            &w[((size_t)ru * ddn + c) * NV + j]);
+        }
+    }
+}
+
+// LDS-resident column metadata: next to the staged row, the workgroup keeps
+// every chunk's table offset and list widths and every column's down state
+// (16 bits) for its whole persistent sweep over rows, so a column's table
+// loads issue after one LDS read instead of a chain of L2 round trips.
+// Each column's entries (up to 32, predicated) are requested at once.
+template <typename S, int NV>
+__global__ __launch_bounds__(1024) void k_hub_rows_fm(HubKArgs a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int64_t ddn = a.ddn;
+    const int64_t nch = (ddn + 63) >> 6;
+    S *s_row = reinterpret_cast<S *>(smem_raw);
+    uint32_t *s_base = reinterpret_cast<uint32_t *>(s_row + (ddn + 1) * NV);
+    uint32_t *s_w = s_base + nch;
+    uint16_t *s_d = reinterpret_cast<uint16_t *>(s_w + nch);
+    const S *__restrict__ v = static_cast<const S *>(a.v);
+    S *__restrict__ w = static_cast<S *>(a.w);
+    const S nt0 = (S)(-a.t0);
+    const uint32_t pad = (uint32_t)ddn;
+    for (int64_t j = threadIdx.x; j < nch; j += blockDim.x) {
+        s_base[j] = a.fs_base[j];
+        s_w[j] = a.fs_wp[j] | ((a.fs_wp[j] + a.fs_wm[j]) << 16);
+    }
+    for (int64_t c = threadIdx.x; c < ddn; c += blockDim.x) s_d[c] = (uint16_t)a.dns[c];
+    for (int64_t ru = blockIdx.x; ru < a.dup; ru += gridDim.x) {
+        const S *vrow = v + (size_t)ru * ddn * NV;
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < ddn * NV; i += blockDim.x) s_row[i] = vrow[i];
+        if (threadIdx.x < NV) s_row[ddn * NV + threadIdx.x] = (S)0;
+        __syncthreads();
+        const uint32_t uu = a.ups[ru];
+        for (int64_t c = threadIdx.x; c < ddn; c += blockDim.x) {
+            const uint32_t mw = s_w[c >> 6];
+            const uint32_t wp = mw & 0xFFFFu, wt = mw >> 16;
+            const uint16_t *ent = a.fs_ent + s_base[c >> 6] + (uint32_t)(c & 63);
+            uint32_t e[32];
+#pragma unroll
+            for (int t = 0; t < 32; ++t) e[t] = (uint32_t)t < wt ? (uint32_t)ent[t * 64] : pad;
+            S ap[NV], am[NV];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) ap[j] = am[j] = (S)0;
+#pragma unroll
+            for (int t = 0; t < 32; ++t) {
+                const bool plus = (uint32_t)t < wp;
+#pragma unroll
+                for (int j = 0; j < NV; ++j) {
+                    const S x = s_row[e[t] * NV + j];
+                    ap[j] += plus ? x : (S)0;
+                    am[j] += plus ? (S)0 : x;
+                }
+            }
+            for (uint32_t t = 32; t < wt; ++t) {
+                const uint32_t et = ent[t * 64];
+#pragma unroll
+                for (int j = 0; j < NV; ++j) {
+                    if (t < wp) ap[j] += s_row[et * NV + j];
+                    else am[j] += s_row[et * NV + j];
+                }
+            }
+            const S dg = hub_diag<S>(a, uu, (uint32_t)s_d[c]);
+#pragma unroll
+            for (int j = 0; j < NV; ++j)
+                __builtin_nontemporal_store(dg * s_row[c * NV + j] + nt0 * (ap[j] - am[j]),
+                                            &w[((size_t)ru * ddn + c) * NV + j]);
+        }
+    }
+}
+
+// Deep variant: each lane issues every table load of CPT columns (up to 32
+// entries each) before the first gather, then splits the sums at the sign
+// boundary. Used when the widest chunk has at most 32 entries.
+template <typename S, int NV, int CPT>
+__global__ __launch_bounds__(1024) void k_hub_rows_fd(HubKArgs a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    S *s_row = reinterpret_cast<S *>(smem_raw);
+    const S *__restrict__ v = static_cast<const S *>(a.v);
+    S *__restrict__ w = static_cast<S *>(a.w);
+    const int64_t ddn = a.ddn;
+    const S nt0 = (S)(-a.t0);
+    const uint16_t pad = (uint16_t)ddn;
+    for (int64_t ru = blockIdx.x; ru < a.dup; ru += gridDim.x) {
+        const S *vrow = v + (size_t)ru * ddn * NV;
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < ddn * NV; i += blockDim.x) s_row[i] = vrow[i];
+        if (threadIdx.x < NV) s_row[ddn * NV + threadIdx.x] = (S)0;
+        __syncthreads();
+        const uint32_t uu = a.ups[ru];
+        for (int64_t c0 = threadIdx.x; c0 < ddn; c0 += (int64_t)CPT * blockDim.x) {
+            uint32_t e[CPT][32];
+            uint32_t wp[CPT];
+            int64_t cc[CPT];
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) {
+                cc[q] = c0 + (int64_t)q * blockDim.x;
+                const bool ok = cc[q] < ddn;
+                const int64_t c = ok ? cc[q] : c0;
+                const int64_t ch = c >> 6;
+                const uint16_t *ent = a.fs_ent + a.fs_base[ch] + (c & 63);
+                wp[q] = ok ? a.fs_wp[ch] : 0u;
+                const uint32_t wt = ok ? wp[q] + a.fs_wm[ch] : 0u;
+#pragma unroll
+                for (int t = 0; t < 32; ++t) e[q][t] = (uint32_t)t < wt ? ent[t * 64] : pad;
+            }
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) {
+                if (cc[q] >= ddn) continue;
+                S ap[NV], am[NV];
+#pragma unroll
+                for (int j = 0; j < NV; ++j) ap[j] = am[j] = (S)0;
+#pragma unroll
+                for (int t = 0; t < 32; ++t) {
+                    const bool plus = (uint32_t)t < wp[q];
+#pragma unroll
+                    for (int j = 0; j < NV; ++j) {
+                        const S x = s_row[e[q][t] * NV + j];
+                        ap[j] += plus ? x : (S)0;
+                        am[j] += plus ? (S)0 : x;
+                    }
+                }
+                const int64_t c = cc[q];
+                const S dg = hub_diag<S>(a, uu, a.dns[c]);
+#pragma unroll
+                for (int j = 0; j < NV; ++j)
+                    __builtin_nontemporal_store(dg * s_row[c * NV + j] + nt0 * (ap[j] - am[j]),
+                                                &w[((size_t)ru * ddn + c) * NV + j]);
+            }
+        }
+    }
+}
+
+// Columns kernel of the fast path: the same XCD-queued slab sweep as
+// k_hub_cols; staged entries are byte offsets of the neighbour rows.
+template <typename S, int NV, int CW, bool DOTS>
+__global__ __launch_bounds__(256) void k_hub_cols_f(HubKArgs a)
+{
+    __shared__ double sh_red[4 * 2 * NV + 8];
+    __shared__ uint32_t s_ent[kColsLdsEntries];
+    __shared__ uint32_t s_off[kColsRows + 1];
+    __shared__ uint32_t s_mid[kColsRows];
+    __shared__ int s_item;
+    __shared__ unsigned s_last;
+    const int home = xcc_id();
+    const char *__restrict__ vb = static_cast<const char *>(a.v);
+    const S *__restrict__ v = static_cast<const S *>(a.v);
+    S *__restrict__ w = static_cast<S *>(a.w);
+    const S *__restrict__ u = static_cast<const S *>(a.u);
+    S *__restrict__ accp = static_cast<S *>(a.acc_out);
+    double c1 = 1.0, c2 = 0.0;
+    if (a.ecoef) {
+        c1 = a.ecoef[0];
+        c2 = a.ecoef[1];
+    }
+    const S c1s = (S)c1, c2s = (S)c2, nt0 = (S)(-a.t0);
+    constexpr uint32_t ESZ = NV * sizeof(S);
+
+    const int64_t ddn = a.ddn, dup = a.dup;
+    const int nchunk = (int)((dup + a.item_rows - 1) / a.item_rows);
+    constexpr int RPW = 64 / CW;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int q = home, tries = 0;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int it = -1;
+            while (tries < 8) {
+                const int nsl_q = q < a.nslab ? (a.nslab - q + 7) / 8 : 0;
+                const int cand = (int)atomicAdd(&a.sched[q], 1u);
+                if (cand < nsl_q * nchunk) {
+                    it = q + 8 * cand;
+                    break;
+                }
+                q = (q + 1) & 7;
+                ++tries;
+            }
+            s_item = it;
+        }
+        __syncthreads();
+        const int item = s_item;
+        if (item < 0) break;
+        const int iq = item & 7, idx = item >> 3;
+        const int slab = iq + 8 * (idx / nchunk);
+        const int chunk = idx % nchunk;
+        const int64_t r0 = (int64_t)chunk * a.item_rows;
+        const int64_t r1 = r0 + a.item_rows < dup ? r0 + a.item_rows : dup;
+        {
+            const uint32_t base = a.fu_off[r0];
+            for (int64_t i = threadIdx.x; i <= r1 - r0; i += blockDim.x) s_off[i] = a.fu_off[r0 + i] - base;
+            for (int64_t i = threadIdx.x; i < r1 - r0; i += blockDim.x) s_mid[i] = a.fu_mid[r0 + i] - base;
+            const uint32_t n = a.fu_off[r1] - base;
+            for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) s_ent[i] = a.fu_ent[base + i] * ESZ;
+        }
+        __syncthreads();
+        double d0[NV], d1[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) d0[j] = d1[j] = 0.0;
+        const int64_t col = (int64_t)slab * CW + (lane % CW);
+        const bool colok = col < ddn;
+        const uint32_t colb = (uint32_t)col * ESZ;
+        for (int64_t r = r0 + wid * RPW + lane / CW; r < r1; r += 4 * RPW) {
+            if (!colok) continue;
+            const size_t me = (size_t)r * ddn + col;
+            S ap[NV], am[NV];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) ap[j] = am[j] = (S)0;
+            const uint32_t eb = s_off[r - r0], em = s_mid[r - r0], ee = s_off[r - r0 + 1];
+            uint32_t e = eb;
+            for (; e + 8 <= em; e += 8) {
+                S nv[8][NV];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const S *p = reinterpret_cast<const S *>(vb + (s_ent[e + t] + colb));
+#pragma unroll
+                    for (int j = 0; j < NV; ++j) nv[t][j] = p[j];
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+#pragma unroll
+                    for (int j = 0; j < NV; ++j) ap[j] += nv[t][j];
+            }
+            for (; e < em; ++e) {
+                const S *p = reinterpret_cast<const S *>(vb + (s_ent[e] + colb));
+#pragma unroll
+                for (int j = 0; j < NV; ++j) ap[j] += p[j];
+            }
+            for (; e + 8 <= ee; e += 8) {
+                S nv[8][NV];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const S *p = reinterpret_cast<const S *>(vb + (s_ent[e + t] + colb));
+#pragma unroll
+                    for (int j = 0; j < NV; ++j) nv[t][j] = p[j];
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+#pragma unroll
+                    for (int j = 0; j < NV; ++j) am[j] += nv[t][j];
+            }
+            for (; e < ee; ++e) {
+                const S *p = reinterpret_cast<const S *>(vb + (s_ent[e] + colb));
+#pragma unroll
+                for (int j = 0; j < NV; ++j) am[j] += p[j];
+            }
+            S out[NV], raw[NV];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                raw[j] = __builtin_nontemporal_load(&w[me * NV + j]) + nt0 * (ap[j] - am[j]);
+                out[j] = c1s * raw[j];
+            }
+            if (u) {
+#pragma unroll
+                for (int j = 0; j < NV; ++j) out[j] += c2s * __builtin_nontemporal_load(&u[me * NV + j]);
+            }
+#pragma unroll
+            for (int j = 0; j < NV; ++j) __builtin_nontemporal_store(out[j], &w[me * NV + j]);
+            if (accp) {
+#pragma unroll
+                for (int j = 0; j < NV; ++j)
+                    __builtin_nontemporal_store(__builtin_nontemporal_load(&accp[me * NV + j]) + out[j],
+                                                &accp[me * NV + j]);
+            }
+            if constexpr (DOTS) {
+#pragma unroll
+                for (int j = 0; j < NV; ++j) {
+                    const double o = a.dot_raw ? (double)raw[j] : (double)out[j];
+                    d0[j] += (double)v[me * NV + j] * o;
+                    d1[j] += o * o;
+                }
+            }
+        }
+        if constexpr (DOTS) {
+            double vals[2 * NV];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                vals[j] = d0[j];
+                vals[NV + j] = d1[j];
+            }
+            block_sum<2 * NV>(vals, sh_red);
+            if (threadIdx.x == 0) {
+                const size_t slot = (size_t)slab * nchunk + chunk;
+                for (int j = 0; j < 2 * NV; ++j) a.red.partial[slot * 2 * NV + j] = vals[j];
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        s_last = (atomicAdd(&a.sched[8], 1u) == gridDim.x - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    if constexpr (DOTS) {
+        const size_t nitems = (size_t)a.nslab * nchunk;
+        for (int j = 0; j < 2 * NV; ++j) {
+            double s = 0.0;
+            for (size_t it = threadIdx.x; it < nitems; it += blockDim.x)
+                s += __builtin_nontemporal_load(&a.red.partial[it * 2 * NV + j]);
+            double vv[1] = {s};
+            block_sum<1>(vv, sh_red);
+            if (threadIdx.x == 0) a.red.result[j] = vv[0];
+        }
+    }
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 8; ++i) a.sched[i] = 0u;
+        a.sched[8] = 0u;
+        __threadfence();
+    }
 }
 
 template <typename S, int NV, int CW>
@@ -225,6 +700,13 @@ static void launch_cols_t(const HubKArgs &a, int grid, hipStream_t st)
 {
     if (a.nd) hipLaunchKernelGGL((k_hub_cols<S, NV, CW, true>), dim3(grid), dim3(256), 0, st, a);
     else hipLaunchKernelGGL((k_hub_cols<S, NV, CW, false>), dim3(grid), dim3(256), 0, st, a);
+}
+
+template <typename S, int NV, int CW>
+static void launch_cols_f(const HubKArgs &a, int grid, hipStream_t st)
+{
+    if (a.nd) hipLaunchKernelGGL((k_hub_cols_f<S, NV, CW, true>), dim3(grid), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_hub_cols_f<S, NV, CW, false>), dim3(grid), dim3(256), 0, st, a);
 }
 
 template <typename S, int NV>
@@ -240,7 +722,28 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
     int64_t grid_r = (int64_t)ncu * per_cu;
     if (grid_r > a.dup) grid_r = a.dup;
     int threads = 1024;
-    if (lds_row) {
+    const size_t fast_row_bytes = (size_t)(a.ddn + 1) * NV * sizeof(S);
+    const bool fast = h->hub.uniform_t && fast_row_bytes <= 160 * 1024 &&
+                      (unsigned __int128)a.dup * a.ddn * NV * sizeof(S) < ((unsigned __int128)1 << 32);
+    const int rmode = h->sched_cfg.hub_row_cols;
+    const size_t fm_bytes = fast_row_bytes + 8 * (size_t)((a.ddn + 63) / 64) + 2 * (size_t)a.ddn + 16;
+    if (fast && rmode == 3 && fm_bytes <= 160 * 1024 && h->basis->n_sites <= 16) {
+        hipFuncSetAttribute((const void *)k_hub_rows_fm<S, NV>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fm_bytes);
+        hipLaunchKernelGGL((k_hub_rows_fm<S, NV>), dim3((unsigned)grid_r), dim3(threads), fm_bytes, st, a);
+    } else if (fast && h->hub.fs_maxw <= 32 && rmode == 2) {
+        hipFuncSetAttribute((const void *)k_hub_rows_fd<S, NV, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fast_row_bytes);
+        hipLaunchKernelGGL((k_hub_rows_fd<S, NV, 2>), dim3((unsigned)grid_r), dim3(threads), fast_row_bytes, st, a);
+    } else if (fast && h->hub.fs_maxw <= 32 && rmode == 3) {
+        hipFuncSetAttribute((const void *)k_hub_rows_fd<S, NV, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fast_row_bytes);
+        hipLaunchKernelGGL((k_hub_rows_fd<S, NV, 1>), dim3((unsigned)grid_r), dim3(threads), fast_row_bytes, st, a);
+    } else if (fast) {
+        hipFuncSetAttribute((const void *)k_hub_rows_f<S, NV>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fast_row_bytes);
+        hipLaunchKernelGGL((k_hub_rows_f<S, NV>), dim3((unsigned)grid_r), dim3(threads), fast_row_bytes, st, a);
+    } else if (lds_row) {
         hipFuncSetAttribute((const void *)k_hub_rows<S, NV, true>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)row_bytes);
         hipLaunchKernelGGL((k_hub_rows<S, NV, true>), dim3((unsigned)grid_r), dim3(threads),
@@ -250,18 +753,35 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
                            128 * sizeof(S), st, a);
     }
     HPHI_HIP(hipGetLastError());
-    // column kernel
-    const int cw = g_hub_geom.cw;
-    int groups = g_hub_geom.groups;
-    const int64_t min_rows_per_group = 4 * (64 / cw);
-    if ((int64_t)groups * min_rows_per_group > a.dup)
-        groups = (int)std::max<int64_t>(1, a.dup / min_rows_per_group);
+    // column kernel, geometry from the Hamiltonian's schedule
+    const int cw = h->sched_cfg.hub_slab_cols;
+    const int groups = h->sched_cfg.hub_groups;
+    int item_rows = h->sched_cfg.hub_item_rows;
+    // the item's neighbour lists must fit the staging array
+    while (item_rows > 8 && (int64_t)item_rows * h->hub.max_deg[0] > kColsLdsEntries) item_rows /= 2;
+    if ((int64_t)item_rows * h->hub.max_deg[0] > kColsLdsEntries)
+        return fail(HPHI_ERR_UNSUPPORTED, "Hubbard up-species degree %lld too large for staging",
+                    (long long)h->hub.max_deg[0]);
+    a.item_rows = item_rows;
     a.groups = groups;
     a.nslab = (int)((a.ddn + cw - 1) / cw);
     const int64_t grid_c = 8 * (int64_t)groups;
-    if (grid_c * 2 * NV > (int64_t)kMaxGrid * 64)
-        return fail(HPHI_ERR_UNSUPPORTED, "Hubbard column grid beyond the reduction scratch");
+    const int64_t nitems = (int64_t)a.nslab * ((a.dup + item_rows - 1) / item_rows);
+    if (a.nd && nitems * 2 * NV > (int64_t)kReduceSlots)
+        return fail(HPHI_ERR_UNSUPPORTED, "Hubbard column items beyond the reduction scratch");
+    a.sched = h->sched.as<unsigned>();
+    if (fast) {
+        switch (cw) {
+        case 8: launch_cols_f<S, NV, 8>(a, (int)grid_c, st); break;
+        case 16: launch_cols_f<S, NV, 16>(a, (int)grid_c, st); break;
+        case 32: launch_cols_f<S, NV, 32>(a, (int)grid_c, st); break;
+        default: launch_cols_f<S, NV, 64>(a, (int)grid_c, st); break;
+        }
+        HPHI_HIP(hipGetLastError());
+        return HPHI_OK;
+    }
     switch (cw) {
+    case 8: launch_cols_t<S, NV, 8>(a, (int)grid_c, st); break;
     case 16: launch_cols_t<S, NV, 16>(a, (int)grid_c, st); break;
     case 32: launch_cols_t<S, NV, 32>(a, (int)grid_c, st); break;
     default: launch_cols_t<S, NV, 64>(a, (int)grid_c, st); break;
@@ -296,6 +816,14 @@ int launch_hub_mult(hphi_ham *h, const MultArgs &m)
     a.nd = m.dots;
     a.dot_raw = m.dot_raw;
     a.red = m.red;
+    a.fs_base = h->hub.fs_base.as<uint32_t>();
+    a.fs_wp = h->hub.fs_wp.as<uint32_t>();
+    a.fs_wm = h->hub.fs_wm.as<uint32_t>();
+    a.fs_ent = h->hub.fs_ent.as<uint16_t>();
+    a.fu_off = h->hub.fu_off.as<uint32_t>();
+    a.fu_mid = h->hub.fu_mid.as<uint32_t>();
+    a.fu_ent = h->hub.fu_ent.as<uint32_t>();
+    a.t0 = h->hub.t0;
     const int nv = m.nvec * dtype_lanes(m.dtype);
     const bool f32 = dtype_is_f32(m.dtype);
     if (nv == 1) return f32 ? launch_hub_t<float, 1>(h, a, m.stream) : launch_hub_t<double, 1>(h, a, m.stream);

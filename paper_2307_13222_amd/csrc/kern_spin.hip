@@ -251,7 +251,9 @@ int launch_spin_mult(hphi_ham *h, const MultArgs &m)
     size_t tab = sizeof(uint32_t) * ((size_t(1) << s.n_lo) + (size_t(1) << s.n_hi));
     bool lds = tab <= 96 * 1024;
     int64_t need = (s.dim + kBlock - 1) / kBlock;
-    int per_cu = lds ? (tab <= 16 * 1024 ? 8 : (tab <= 48 * 1024 ? 2 : 1)) : 8;
+    // workgroups per CU from the schedule, capped by the LDS the tables use
+    int per_cu = h->sched_cfg.spin_per_cu;
+    if (lds) per_cu = std::min(per_cu, std::max(1, (int)((160 * 1024) / (tab + 4096))));
     int64_t cap = (int64_t)(h->basis->ctx->n_cu > 0 ? h->basis->ctx->n_cu : 256) * per_cu;
     if (cap > kMaxGrid) cap = kMaxGrid;
     int grid = (int)(need < cap ? need : cap);

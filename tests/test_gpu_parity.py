@@ -192,6 +192,9 @@ HUB_CASES = {
     "chain10_random_u": (lambda: W.HubbardModel(10, *[np.asarray(a, np.int32) for a in zip(*W.chain_pairs(10))],
                                                 np.linspace(0.7, 1.3, 10), np.linspace(2.0, 5.0, 10), "c10"), 5, 4),
     "sq2x4_empty_dn": (lambda: W.hubbard_square(2, 4, 1.0, 8.0), 3, 0),
+    "chain9_mixed_sign_t": (lambda: W.HubbardModel(9, *[np.asarray(a, np.int32) for a in zip(*W.chain_pairs(9))],
+                                                   np.array([1.0, -1.0, -1.0, 1.0, 1.0, -1.0, 1.0, -1.0, 1.0]) * 0.8,
+                                                   np.full(9, 3.0), "c9pm"), 4, 5),
     "sq4x4_small_filling": (lambda: W.hubbard_square(4, 4, 1.0, 4.0), 2, 3),
 }
 
@@ -210,6 +213,30 @@ def test_hubbard_mult_f64(api, ctx, case):
     vc = W.random_vector(b.dim, 22, np.complex128)
     wc = host(h.mult(dev(vc)))
     assert relmax(wc, O.hubbard_hv(m, ups, dns, vc)) < 1e-12
+
+
+def test_hubbard_schedules_bit_identical(api, ctx):
+    # launch geometry does not change any element's summation order
+    say("hub schedules")
+    m = W.hubbard_square(3, 4, 1.0, 4.0)
+    b = api.Basis.hubbard(ctx, 12, 6, 5)
+    h = api.Hamiltonian.hubbard(b, m)
+    v = dev(W.random_vector(b.dim, 4))
+    ref = None
+    for sch in [dict(hub_slab_cols=16, hub_groups=128, hub_item_rows=64, hub_row_cols=1),
+                dict(hub_slab_cols=8, hub_groups=64, hub_item_rows=32, hub_row_cols=2),
+                dict(hub_slab_cols=32, hub_groups=256, hub_item_rows=128, hub_row_cols=3),
+                dict(hub_slab_cols=64, hub_groups=1, hub_item_rows=8, hub_row_cols=1)]:
+        h.set_schedule(**sch)
+        assert h.get_schedule()["hub_slab_cols"] == sch["hub_slab_cols"]
+        w = host(h.mult(v))
+        if ref is None:
+            ref = w
+            ups, dns = O.hubbard_basis(12, 6, 5)
+            assert relmax(w, O.hubbard_hv(m, ups, dns, host(v))) < 1e-12
+        assert np.array_equal(w, ref), sch
+    with pytest.raises(api.HphiError):
+        h.set_schedule(hub_slab_cols=12)
 
 
 def test_hubbard_4x4_full_size_sampled_rows(api, ctx):
@@ -316,6 +343,9 @@ def test_lanczos_hubbard_small(api, ctx):
     ups, dns = O.hubbard_basis(8, 4, 4)
     e = np.linalg.eigvalsh(O.hubbard_sparse(m, ups, dns).toarray())[0]
     assert abs(r["energies"][0] - e) < 1e-10
+    # dynamic work queues, fixed-order reductions: run-to-run identical
+    r2 = api.lanczos(h, 200, seed=3)
+    assert np.array_equal(r["alpha"], r2["alpha"]) and np.array_equal(r["beta"], r2["beta"])
     hu0 = api.Hamiltonian.hubbard(api.Basis.hubbard(ctx, 9, 4, 4), W.hubbard_square(3, 3, 1.0, 0.0))
     r0 = api.lanczos(hu0, 250, seed=5)
     levels = np.linalg.eigvalsh(-(np.roll(np.eye(3), 1, 0) + np.roll(np.eye(3), -1, 0)))
