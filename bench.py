@@ -1,16 +1,25 @@
-"""Benchmark: matrix-free H*v inside plain Lanczos on one MI355X.
+"""Benchmark: matrix-free H*v inside plain Lanczos / cTPQ on one MI355X.
 
-Workload (default): Fermi-Hubbard model on the 4x4 periodic square lattice,
-t = 1, U = 4, N_up = N_dn = 8 (dim 12870^2 = 165,636,900), real FP64
-vectors, Lanczos ground state with 300 iterations from a seeded uniform
-[-1/2, 1/2) start vector. One step = one full Lanczos solve (start vector,
-300 fused H*v + update iterations, host tridiagonal eigensolve). Basis,
-tables and vectors are resident on the device before the timed region.
+Default workload (the headline configuration): Fermi-Hubbard model on the 4x4
+periodic square lattice, t = 1, U = 4, N_up = N_dn = 8 (dim 12870^2 =
+165,636,900), real FP64 vectors, Lanczos ground state with 300 iterations
+from a seeded uniform [-1/2, 1/2) start vector. One step = one full Lanczos
+solve (start vector, 300 fused H*v + update iterations, host tridiagonal
+eigensolve). Basis, tables and vectors are resident on the device before the
+timed region.
 
 Prints one JSON line: value = effective H*v bandwidth (algorithmic bytes:
-read v + write w, 16 B per state) over the H*v launches timed with HIP
-events inside the timed solves; Lanczos solves/s and per-solve p50/p99;
-roofline of the H*v; the oracle's CPU rate on a bounded sample.
+read v + write w, 16 B per state in FP64) over the H*v launches timed with
+HIP events inside the timed solves; Lanczos solves/s and per-solve p50/p99;
+the roofline of the H*v; the oracle's CPU rate on a bounded sample.
+
+Other workloads (--workload), reported the same way:
+  heisenberg16  spin-1/2 Heisenberg ring N = 16 (dim 12870), 200 iterations
+  ctpq_xxz28    16 TPQ vectors, XXZ (1.0, 0.8) + J2 (0.5, 0.4) ring N = 28
+                (dim 40,116,600), complex FP32 storage, n_max 6, dtau 0.02;
+                error vs the same run in complex FP64
+  j1j2_6x6      J1-J2 Heisenberg 6x6 (J2 = 0.5), dim 9,075,135,300, FP32
+                Lanczos vectors (36.3 GB each); E0 vs an FP64-storage run
 """
 from __future__ import annotations
 
@@ -23,6 +32,7 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "H·v HBM GB/s (% peak) + Lanczos solves/s, p50/p99; batched/FP32 vs plain FP64"
 
 
 def parse():
@@ -30,52 +40,113 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--iters", type=int, default=300)
-    p.add_argument("--workload", default="hubbard4x4", choices=["hubbard4x4", "heisenberg16"])
+    p.add_argument("--iters", type=int, default=0, help="Krylov / TPQ steps per solve (0 = workload default)")
+    p.add_argument("--workload", default="hubbard4x4",
+                   choices=["hubbard4x4", "heisenberg16", "ctpq_xxz28", "j1j2_6x6"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-tune", action="store_true", help="keep the default launch schedule")
     p.add_argument("--retune", action="store_true", help="sweep schedules even if one is recorded")
     p.add_argument("--cpu-sample-rows", type=int, default=0,
-                   help="oracle sample size in up-rows (0 = all rows, one full H*v)")
+                   help="oracle sample size in up-rows (hubbard4x4)")
     return p.parse_args()
+
+
+def omp_threads() -> int:
+    return int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
 
 
 def cpu_baseline(workload: str, sample_rows: int):
     """The oracle's row-wise H*v (plain C, OpenMP) on a bounded sample of
-    the same workload, reported in the same unit as `value` (GB/s of
-    algorithmic H*v bytes)."""
+    the same workload, in the same unit as `value` (GB/s of algorithmic H*v
+    bytes)."""
     from oracle import core as O
     from paper_2307_13222_amd import workloads as W
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
     if workload == "hubbard4x4":
         m = W.hubbard_square(4, 4, 1.0, 4.0)
         ups, dns = O.hubbard_basis(16, 8, 8)
-        # rows of the sample: all down states of the first nu up states; the
-        # gathers still read the whole vector
-        nu = sample_rows if sample_rows > 0 else 3000
-        nu = min(nu, len(ups))
+        # all down states of the first nu up states; gathers read the whole vector
+        nu = min(sample_rows if sample_rows > 0 else 3000, len(ups))
         v = np.random.default_rng(0).random(len(ups) * len(dns)) - 0.5
         t0 = time.perf_counter()
         w = O.hubbard_hv_rows(m, ups, dns, v, 0, nu)
         dt = time.perf_counter() - t0
-        states = nu * len(dns)
+        states, bytes_per = nu * len(dns), 16.0
         del w
         sample = (f"oracle Hubbard H*v over up-rows [0, {nu}) of {len(ups)} "
                   f"({states} of {len(ups) * len(dns)} states)")
-    else:
-        m = W.heisenberg_chain(16)
-        s = O.basis_list(16, 8)
+    elif workload in ("heisenberg16", "ctpq_xxz28"):
+        n = 16 if workload == "heisenberg16" else 20
+        m = W.heisenberg_chain(16) if n == 16 else W.xxz_chain_j2(20)
+        s = O.basis_list(n, n // 2)
         v = np.random.default_rng(0).random(len(s)) - 0.5
-        reps = 50
+        reps = 50 if n == 16 else 3
         t0 = time.perf_counter()
         for _ in range(reps):
             O.spin_hv(m, s, v)
         dt = time.perf_counter() - t0
-        states = reps * len(s)
-        sample = f"oracle spin H*v x{reps} on dim {len(s)}"
-    gbs = 16.0 * states / dt / 1e9
-    return {"value": round(gbs, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
+        states, bytes_per = reps * len(s), 16.0
+        sample = f"oracle spin H*v x{reps} on N={n} (dim {len(s)}), FP64 real"
+    else:
+        m = W.j1j2_square(6, 6, 1.0, 0.5)
+        rows = 20000
+        t0 = time.perf_counter()
+        for r in np.random.default_rng(1).integers(0, 9075135300, rows):
+            O.spin_row(m, 18, int(r))
+        dt = time.perf_counter() - t0
+        states, bytes_per = rows, 8.0
+        sample = f"oracle sparse rows of the 6x6 J1-J2 sector, {rows} random rows (row formula only)"
+    gbs = bytes_per * states / dt / 1e9
+    return {"value": round(gbs, 4), "unit": "GB/s", "cores": omp_threads(), "kind": "oracle",
             "sample": sample, "seconds": round(dt, 3)}
+
+
+def roofline(gbs: float, alg_bytes: float, kernel: str):
+    return {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel,
+            "alg_bytes_per_launch": alg_bytes}
+
+
+def base_line(a, value, ms_per_step, dtype, config):
+    return {"metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": a.steps,
+            "warmup": a.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def run_lanczos(a, api, ham, dim, iters, storage, wl, kernel, tune_dtype):
+    import torch
+    stream = torch.cuda.current_stream()
+    if not a.no_tune:
+        from paper_2307_13222_amd import autotune
+        tuned = autotune.tune(ham, tune_dtype, 1, force=a.retune)
+        wl["schedule"] = tuned["schedule"]
+        if tuned.get("swept"):
+            print(json.dumps({"autotune": tuned}), file=sys.stderr, flush=True)
+    for _ in range(a.warmup):
+        api.lanczos(ham, iters, seed=1, storage=storage, stream=stream)
+    torch.cuda.synchronize()
+    lat, hv_s, hv_n, energies = [], 0.0, 0, []
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        s0 = time.perf_counter()
+        r = api.lanczos(ham, iters, seed=1 + k, storage=storage, stream=stream, time_kernels=True)
+        lat.append(time.perf_counter() - s0)
+        hv_s += r["hv_seconds"]
+        hv_n += r["hv_calls"]
+        energies.append(float(r["energies"][0]))
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    hv_avg = hv_s / max(1, hv_n)
+    esize = 8.0 if storage == "f64" else 4.0
+    alg_bytes = 2 * esize * dim
+    gbs = alg_bytes / hv_avg / 1e9
+    out = base_line(a, gbs, 1e3 * total / a.steps, storage, wl)
+    out.update({"hbm_peak_frac": round(gbs / HBM_PEAK_GBS, 4),
+                "lanczos_solves_per_s": round(a.steps / total, 4),
+                "solve_ms_p50": round(1e3 * float(np.percentile(lat, 50)), 3),
+                "solve_ms_p99": round(1e3 * float(np.percentile(lat, 99)), 3),
+                "hv_ms_avg": round(1e3 * hv_avg, 5), "e0": energies[0],
+                "roofline": roofline(gbs, alg_bytes, kernel)})
+    return out, energies
 
 
 def main():
@@ -88,71 +159,87 @@ def main():
 
     ctx = api.Context(0)
     if a.workload == "hubbard4x4":
+        iters = a.iters or 300
         m = W.hubbard_square(4, 4, 1.0, 4.0)
         basis = api.Basis.hubbard(ctx, 16, 8, 8)
         ham = api.Hamiltonian.hubbard(basis, m)
-        wl = {"workload": "hubbard_4x4_pbc_t1_U4_half_filling", "dim": basis.dim, "lanczos_iters": a.iters,
+        wl = {"workload": "hubbard_4x4_pbc_t1_U4_half_filling", "dim": basis.dim, "lanczos_iters": iters,
               "storage": "f64", "lattice": "square 4x4", "n_up": 8, "n_dn": 8}
-    else:
+        out, _ = run_lanczos(a, api, ham, basis.dim, iters, "f64", wl,
+                             "H*v = k_hub_rows_fm + k_hub_cols_f (T_dn/U rows kernel + T_up slab kernel)", "f64")
+    elif a.workload == "heisenberg16":
+        iters = a.iters or 200
         m = W.heisenberg_chain(16)
         basis = api.Basis.spin(ctx, 16, 0)
         ham = api.Hamiltonian.spin(basis, m)
-        wl = {"workload": "heisenberg_chain16_sz0", "dim": basis.dim, "lanczos_iters": a.iters,
-              "storage": "f64"}
-    dim = basis.dim
-    stream = torch.cuda.current_stream()
-    tuned = None
-    if not a.no_tune:
-        # schedule sweep (or cached lookup) outside the timed region
-        from paper_2307_13222_amd import autotune
-        tuned = autotune.tune(ham, "f64", 1, force=a.retune)
-        wl["schedule"] = tuned["schedule"]
-        if tuned.get("swept"):
-            print(json.dumps({"autotune": tuned}), file=sys.stderr, flush=True)
-    for _ in range(a.warmup):
-        api.lanczos(ham, a.iters, seed=1, stream=stream)
-    torch.cuda.synchronize()
-    lat, hv_s, hv_n, energies = [], 0.0, 0, []
-    t0 = time.perf_counter()
-    for k in range(a.steps):
-        s0 = time.perf_counter()
-        r = api.lanczos(ham, a.iters, seed=1 + k, stream=stream, time_kernels=True)
-        lat.append(time.perf_counter() - s0)
-        hv_s += r["hv_seconds"]
-        hv_n += r["hv_calls"]
-        energies.append(float(r["energies"][0]))
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-    hv_avg = hv_s / max(1, hv_n)
-    alg_bytes = 16.0 * dim                      # read v + write w, FP64
-    gbs = alg_bytes / hv_avg / 1e9
-    out = {
-        "metric": "H·v HBM GB/s (% peak) + Lanczos solves/s, p50/p99; batched/FP32 vs plain FP64",
-        "value": round(gbs, 2),
-        "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": round(1e3 * total / a.steps, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": wl,
-        "hbm_peak_frac": round(gbs / HBM_PEAK_GBS, 4),
-        "lanczos_solves_per_s": round(a.steps / total, 4),
-        "solve_ms_p50": round(1e3 * float(np.percentile(lat, 50)), 3),
-        "solve_ms_p99": round(1e3 * float(np.percentile(lat, 99)), 3),
-        "hv_ms_avg": round(1e3 * hv_avg, 5),
-        "e0": energies[0],
-        "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "H*v (k_hub_rows + k_hub_cols)", "alg_bytes_per_launch": alg_bytes},
-    }
+        wl = {"workload": "heisenberg_chain16_sz0", "dim": basis.dim, "lanczos_iters": iters, "storage": "f64"}
+        out, _ = run_lanczos(a, api, ham, basis.dim, iters, "f64", wl, "H*v = k_spin_hv<double,1>", "f64")
+    elif a.workload == "j1j2_6x6":
+        iters = a.iters or 100
+        m = W.j1j2_square(6, 6, 1.0, 0.5)
+        basis = api.Basis.spin(ctx, 36, 0)
+        ham = api.Hamiltonian.spin(basis, m)
+        wl = {"workload": "j1j2_square_6x6_J2_0.5_sz0", "dim": basis.dim, "lanczos_iters": iters,
+              "storage": "f32 vectors, f64 alpha/beta"}
+        a.no_tune = True
+        out, e32 = run_lanczos(a, api, ham, basis.dim, iters, "f32", wl,
+                               "H*v = k_spin_hv_implicit<float> (implicit basis, 64-bit indices)", "f32")
+        torch.cuda.empty_cache()
+        r64 = api.lanczos(ham, iters, seed=1, storage="f64")
+        out["e0_fp64_storage"] = float(r64["energies"][0])
+        out["e0_abs_diff_fp32_vs_fp64"] = abs(e32[0] - float(r64["energies"][0]))
+    else:
+        out = run_ctpq(a, api, ctx, W)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.workload, a.cpu_sample_rows)
     print(json.dumps(out), flush=True)
+
+
+def run_ctpq(a, api, ctx, W):
+    """Batched cTPQ: 16 vectors advanced together by block H*V."""
+    import torch
+    from paper_2307_13222_amd import autotune
+    k_steps = a.iters or 250
+    m = W.xxz_chain_j2(28)
+    basis = api.Basis.spin(ctx, 28, 0)
+    ham = api.Hamiltonian.spin(basis, m)
+    dim, nv = basis.dim, 16
+    wl = {"workload": "ctpq_xxz_j2_chain28_sz0_16vec", "dim": dim, "n_vec": nv, "n_max": 6, "dtau": 0.02,
+          "k_steps": k_steps, "storage": "c64 (FP32 complex), f64 norms"}
+    if not a.no_tune:
+        wl["schedule"] = autotune.tune(ham, "c64", nv, force=a.retune)["schedule"]
+    # block H*V time with HIP events (the kernel the propagator runs)
+    v = (torch.rand((dim, nv), dtype=torch.complex64, device="cuda") - (0.5 + 0.5j)).contiguous()
+    w = torch.empty_like(v)
+    hv_ms = autotune.time_mult(ham, v, w, reps=10)
+    del v, w
+    alg_bytes = 2.0 * dim * nv * 8
+    gbs = alg_bytes / (hv_ms * 1e-3) / 1e9
+    for _ in range(a.warmup):
+        api.ctpq(ham, nv, 6, 0.02, 2, storage="c64", seed=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat = []
+    res = None
+    for k in range(a.steps):
+        s0 = time.perf_counter()
+        res = api.ctpq(ham, nv, 6, 0.02, k_steps, storage="c64", seed=1)
+        lat.append(time.perf_counter() - s0)
+    total = time.perf_counter() - t0
+    del res["phi"]
+    torch.cuda.empty_cache()
+    ref = api.ctpq(ham, nv, 6, 0.02, k_steps, storage="c128", seed=1)
+    del ref["phi"]
+    dE = float(np.max(np.abs(res["E"] - ref["E"])))
+    dlogN = float(np.max(np.abs(np.cumsum(np.log(res["D"]), 0) - np.cumsum(np.log(ref["D"]), 0))))
+    out = base_line(a, gbs, 1e3 * total / a.steps, "c64", wl)
+    out.update({"hbm_peak_frac": round(gbs / HBM_PEAK_GBS, 4), "block_hv_ms": round(hv_ms, 4),
+                "ctpq_steps_per_s": round(a.steps * k_steps / total, 3),
+                "ctpq_run_ms_p50": round(1e3 * float(np.percentile(lat, 50)), 3),
+                "max_abs_dE_fp32_vs_fp64": dE, "max_abs_dlogN_fp32_vs_fp64": dlogN,
+                "E_beta_final_mean": float(np.mean(res["E"][-1])),
+                "roofline": roofline(gbs, alg_bytes, "block H*V = k_spin_hv<float,32> (16 complex vectors)")})
+    return out
 
 
 if __name__ == "__main__":

@@ -158,6 +158,10 @@ void hphi_ham_free(hphi_ham *h);
  *   hub_row_cols    T_dn kernel variant: 1 = batched table loads, 2 = all
  *                   loads of two columns issued at once, 3 = of one column
  *   spin_per_cu     spin H*v workgroups per compute unit (1..16)
+ *   spin_implicit   1: spin H*v rebuilds configurations from row indices
+ *                   (the path sectors without a stored state list take:
+ *                   more than 32 sites or 2^32 states); -1: stored list
+ *                   when there is one
  * Errors: INVALID_ARG (value outside its range). */
 typedef struct {
     int hub_slab_cols;
@@ -165,6 +169,7 @@ typedef struct {
     int hub_item_rows;
     int hub_row_cols;
     int spin_per_cu;
+    int spin_implicit;
 } hphi_schedule;
 
 int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s);

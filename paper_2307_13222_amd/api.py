@@ -182,7 +182,8 @@ class Hamiltonian:
                                  _stream_ptr(stream)), "hphi_mult")
         return w
 
-    SCHEDULE_FIELDS = ("hub_slab_cols", "hub_groups", "hub_item_rows", "hub_row_cols", "spin_per_cu")
+    SCHEDULE_FIELDS = ("hub_slab_cols", "hub_groups", "hub_item_rows", "hub_row_cols", "spin_per_cu",
+                       "spin_implicit")
 
     def set_schedule(self, **kw):
         s = L.Schedule(*[int(kw.get(f, 0)) for f in self.SCHEDULE_FIELDS])

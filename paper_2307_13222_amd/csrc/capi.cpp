@@ -434,6 +434,11 @@ int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s)
         if (s->spin_per_cu < 1 || s->spin_per_cu > 16) return fail(HPHI_ERR_INVALID_ARG, "spin_per_cu %d", s->spin_per_cu);
         n.spin_per_cu = s->spin_per_cu;
     }
+    if (s->spin_implicit) {
+        if (s->spin_implicit != 1 && s->spin_implicit != -1)
+            return fail(HPHI_ERR_INVALID_ARG, "spin_implicit %d", s->spin_implicit);
+        n.spin_implicit = s->spin_implicit == 1 ? 1 : 0;
+    }
     h->sched_cfg = n;
     return HPHI_OK;
 }

@@ -139,7 +139,10 @@ struct hphi_ham {
     hphi::HubTables hub;
     std::vector<hphi_hop> hops;
     std::vector<double> u_site;
-    hphi_schedule sched_cfg{16, 128, 64, 1, 8};
+    // defaults: the autotuner's choice for the 4x4 Hubbard sector at half
+    // filling (32-column slabs, 256 workgroups per XCD, 64-row items,
+    // LDS-resident row metadata); spin: 8 workgroups per CU
+    hphi_schedule sched_cfg{32, 256, 64, 3, 8, 0};
     // scratch for reductions and work queues
     hphi::DevMem sched;         // unsigned [16]: per-XCD item queues + counter
     hphi::DevMem red_partial;   // double [kReduceSlots]
@@ -178,6 +181,7 @@ struct MultArgs {
     hipStream_t stream;
 };
 int launch_spin_mult(hphi_ham *h, const MultArgs &a);
+int launch_spin_mult_implicit(hphi_ham *h, const MultArgs &a);
 int launch_hub_mult(hphi_ham *h, const MultArgs &a);
 int launch_mult(hphi_ham *h, const MultArgs &a);
 

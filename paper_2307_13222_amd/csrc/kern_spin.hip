@@ -226,8 +226,8 @@ int launch_spin_mult(hphi_ham *h, const MultArgs &m)
 {
     const hphi_basis *b = h->basis;
     const Species &s = b->sp[0];
-    if (!s.materialized() || s.state_bytes != 4 || !s.d_hi_off32.p)
-        return fail(HPHI_ERR_UNSUPPORTED, "spin H*v with a materialized list needs N <= 32");
+    if (!s.materialized() || s.state_bytes != 4 || !s.d_hi_off32.p || h->sched_cfg.spin_implicit)
+        return launch_spin_mult_implicit(h, m);
     SpinKArgs a{};
     a.states = s.d_states.as<uint32_t>();
     a.dim = s.dim;
