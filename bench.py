@@ -174,6 +174,22 @@ def main():
         ham = api.Hamiltonian.spin(basis, m)
         wl = {"workload": "heisenberg_chain16_sz0", "dim": basis.dim, "lanczos_iters": iters, "storage": "f64"}
         out, _ = run_lanczos(a, api, ham, basis.dim, iters, "f64", wl, "H*v = k_spin_hv<double,1>", "f64")
+        # many independent solves per launch (one workgroup per solve)
+        hams = [ham] * 256
+        rates, lat_b = {}, {}
+        for B in (1, 16, 64, 256):
+            api.lanczos_batch(hams[:B], iters, list(range(1, B + 1)))
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                res = api.lanczos_batch(hams[:B], iters, list(range(1, B + 1)))
+                ts.append(time.perf_counter() - t0)
+            rates[str(B)] = round(B / float(np.median(ts)), 2)
+            lat_b[str(B)] = round(1e3 * float(np.median(ts)), 3)
+            assert abs(res[0]["energy"] - out["e0"]) < 1e-9
+        out["batched_solves_per_s"] = rates
+        out["batched_launch_ms"] = lat_b
     elif a.workload == "j1j2_6x6":
         iters = a.iters or 100
         m = W.j1j2_square(6, 6, 1.0, 0.5)

@@ -229,6 +229,29 @@ typedef struct {
 int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *opts, double *energies,
                  int n_energies, hphi_lanczos_info *info);
 
+/* One request of a batched Lanczos launch. */
+typedef struct {
+    hphi_ham *ham;         /* spin Hamiltonian on a stored basis (<= 32 sites) */
+    int max_iter;          /* Krylov steps                                    */
+    uint64_t seed;         /* SplitMix64 start vector (as hphi_lanczos)       */
+    double *alpha_out;     /* optional host arrays, max_iter entries          */
+    double *beta_out;
+    double energy;         /* out: lowest Ritz value of T_k                   */
+    int iterations;        /* out: steps done                                 */
+    int breakdown;         /* out: 1 if beta_k fell below the threshold       */
+} hphi_batch_item;
+
+/* Many independent Lanczos ground-state solves in one launch, one
+ * workgroup per request (the recurrence of hphi_lanczos, FP64 vectors,
+ * fixed-order block reductions: a request's numbers do not depend on the
+ * other requests in the launch). Meant for sectors small enough that a
+ * single solve is bound by kernel-launch latency. The library allocates
+ * 3 * dim doubles of workspace per request for the call. Synchronous on
+ * `stream`. Errors: INVALID_ARG (n < 1, max_iter < 1), UNSUPPORTED (a
+ * Hamiltonian that is not a spin model on a stored basis), OUT_OF_MEMORY,
+ * DEVICE. */
+int hphi_lanczos_batch(hphi_batch_item *items, int n, void *stream);
+
 /* Lowest k eigenvalues (ascending) of the symmetric tridiagonal matrix with
  * diagonal alpha[0..n) and off-diagonal beta[1..n) (beta[0] ignored), by
  * Sturm-sequence bisection in FP64; the host routine hphi_lanczos uses.

@@ -34,6 +34,12 @@ class LanczosInfo(C.Structure):
                 ("seconds", C.c_double), ("hv_seconds", C.c_double), ("hv_calls", C.c_int)]
 
 
+class BatchItem(C.Structure):
+    _fields_ = [("ham", C.c_void_p), ("max_iter", C.c_int), ("seed", C.c_uint64),
+                ("alpha_out", C.POINTER(C.c_double)), ("beta_out", C.POINTER(C.c_double)),
+                ("energy", C.c_double), ("iterations", C.c_int), ("breakdown", C.c_int)]
+
+
 class CtpqOpts(C.Structure):
     _fields_ = [("n_vec", C.c_int), ("n_max", C.c_int), ("dtau", C.c_double),
                 ("k_steps", C.c_int), ("storage", C.c_int), ("seed", C.c_uint64),
@@ -82,6 +88,7 @@ SIGNATURES = {
     "hphi_mult": (I, [P, I, P, P, I64, P]),
     "hphi_lanczos": (I, [P, C.POINTER(LanczosOpts), PD, I, C.POINTER(LanczosInfo)]),
     "hphi_tridiag_lowest": (I, [PD, PD, I, I, PD, PD]),
+    "hphi_lanczos_batch": (I, [C.POINTER(BatchItem), I, P]),
     "hphi_ctpq": (I, [P, C.POINTER(CtpqOpts), P, PD, PD, PD]),
     "hphi_szq": (I, [P, PD, P, P, P]),
     "hphi_sqw": (I, [P, C.POINTER(SqwOpts), P, PD, PD, I, PD, PD, C.POINTER(SqwInfo)]),

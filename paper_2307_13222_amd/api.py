@@ -236,6 +236,36 @@ def lanczos(ham: Hamiltonian, max_iter: int, seed: int = 1, v0=None, storage: st
             "psi": psi}
 
 
+def lanczos_batch(hams: Sequence[Hamiltonian], max_iter, seeds, keep_coefficients: bool = False,
+                  stream=None):
+    """Independent Lanczos ground-state solves in one launch (one workgroup
+    per request). max_iter and seeds are scalars or per-request sequences."""
+    n = len(hams)
+    its = [max_iter] * n if np.isscalar(max_iter) else list(max_iter)
+    sds = [seeds] * n if np.isscalar(seeds) else list(seeds)
+    arr = (L.BatchItem * n)()
+    keep = []
+    for i, h in enumerate(hams):
+        arr[i].ham = h.h
+        arr[i].max_iter = int(its[i])
+        arr[i].seed = int(sds[i])
+        if keep_coefficients:
+            a = np.zeros(its[i])
+            b = np.zeros(its[i])
+            keep.append((a, b))
+            arr[i].alpha_out = a.ctypes.data_as(L.PD)
+            arr[i].beta_out = b.ctypes.data_as(L.PD)
+    _check(L.lib().hphi_lanczos_batch(arr, n, _stream_ptr(stream)), "hphi_lanczos_batch")
+    out = []
+    for i in range(n):
+        d = {"energy": arr[i].energy, "iterations": arr[i].iterations, "breakdown": bool(arr[i].breakdown)}
+        if keep_coefficients:
+            k = arr[i].iterations
+            d["alpha"], d["beta"] = keep[i][0][:k], keep[i][1][:k]
+        out.append(d)
+    return out
+
+
 def tridiag_lowest(alpha: np.ndarray, beta: np.ndarray, k: int = 1, want_vector: bool = False):
     a = np.ascontiguousarray(alpha, dtype=np.float64)
     b = np.ascontiguousarray(beta, dtype=np.float64)

@@ -149,6 +149,87 @@ int hphi_ctpq(hphi_ham *h, const hphi_ctpq_opts *o, void *phi_dev, double *D_out
     return HPHI_OK;
 }
 
+int hphi_lanczos_batch(hphi_batch_item *items, int n, void *stream)
+{
+    if (!items || n < 1) return fail(HPHI_ERR_INVALID_ARG, "empty batch");
+    for (int i = 0; i < n; ++i) {
+        if (!items[i].ham) return fail(HPHI_ERR_INVALID_ARG, "item %d has no Hamiltonian", i);
+        if (items[i].max_iter < 1 || items[i].max_iter > 100000)
+            return fail(HPHI_ERR_INVALID_ARG, "item %d max_iter %d", i, items[i].max_iter);
+        if (items[i].ham->basis->ctx != items[0].ham->basis->ctx)
+            return fail(HPHI_ERR_INVALID_ARG, "batch items on different contexts");
+    }
+    DeviceGuard g(items[0].ham->basis->ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    // one allocation: vectors, then alpha/beta, then flags
+    size_t nq = 0, nab = 0;
+    for (int i = 0; i < n; ++i) {
+        nq += 3 * (size_t)items[i].ham->basis->dim;
+        nab += 2 * (size_t)items[i].max_iter + 1;
+    }
+    DevMem work, desc;
+    HPHI_TRY(work.alloc(sizeof(double) * (nq + nab) + sizeof(int) * 2 * (size_t)n));
+    double *qbase = work.as<double>();
+    double *abbase = qbase + nq;
+    int *flags = reinterpret_cast<int *>(abbase + nab);
+    // descriptors: requests whose vector fits in LDS first (LDS kernel),
+    // the rest after (L2 kernel)
+    const size_t kLdsCap = 150 * 1024;
+    std::vector<int> order;
+    size_t lds_max = 0;
+    for (int i = 0; i < n; ++i) {
+        const Species &s = items[i].ham->basis->sp[0];
+        const size_t need = batch_lds_bytes(s.dim, s.n_lo, s.n_hi);
+        if (need <= kLdsCap) {
+            order.push_back(i);
+            lds_max = std::max(lds_max, need);
+        }
+    }
+    const int n_lds = (int)order.size();
+    for (int i = 0; i < n; ++i) {
+        const Species &s = items[i].ham->basis->sp[0];
+        if (batch_lds_bytes(s.dim, s.n_lo, s.n_hi) > kLdsCap) order.push_back(i);
+    }
+    std::vector<unsigned char> hd(batch_item_size() * (size_t)n);
+    size_t oq = 0, oab = 0;
+    std::vector<size_t> ab_off(n);
+    for (int i = 0; i < n; ++i) {
+        ab_off[i] = oab;
+        oab += 2 * (size_t)items[i].max_iter + 1;
+    }
+    for (int p = 0; p < n; ++p) {
+        const int i = order[p];
+        HPHI_TRY(fill_batch_item(items[i].ham, items[i].max_iter, items[i].seed, qbase + oq, abbase + ab_off[i],
+                                 abbase + ab_off[i] + items[i].max_iter, flags + 2 * i,
+                                 hd.data() + batch_item_size() * p));
+        oq += 3 * (size_t)items[i].ham->basis->dim;
+    }
+    HPHI_TRY(desc.alloc(hd.size()));
+    HPHI_HIP(hipMemcpyAsync(desc.p, hd.data(), hd.size(), hipMemcpyHostToDevice, st));
+    if (n_lds > 0) HPHI_TRY(launch_lanczos_batch(desc.p, n_lds, st, lds_max));
+    if (n_lds < n)
+        HPHI_TRY(launch_lanczos_batch(static_cast<unsigned char *>(desc.p) + batch_item_size() * n_lds, n - n_lds,
+                                      st, 0));
+    std::vector<double> hab(nab);
+    std::vector<int> hf(2 * (size_t)n);
+    HPHI_HIP(hipMemcpyAsync(hab.data(), abbase, sizeof(double) * nab, hipMemcpyDeviceToHost, st));
+    HPHI_HIP(hipMemcpyAsync(hf.data(), flags, sizeof(int) * 2 * n, hipMemcpyDeviceToHost, st));
+    HPHI_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i) {
+        const double *al = hab.data() + ab_off[i];
+        const double *be = al + items[i].max_iter;
+        const int k = hf[2 * i];
+        items[i].iterations = k;
+        items[i].breakdown = hf[2 * i + 1];
+        if (items[i].alpha_out) std::memcpy(items[i].alpha_out, al, sizeof(double) * k);
+        if (items[i].beta_out) std::memcpy(items[i].beta_out, be, sizeof(double) * k);
+        double e = NAN;
+        if (k > 0) HPHI_TRY(tridiag_lowest(al, be, k, 1, &e, nullptr));
+        items[i].energy = e;
+    }
+    return HPHI_OK;
+}
+
 int hphi_szq(hphi_ham *h, const double *phase, const void *psi_dev, void *b_dev, void *stream)
 {
     if (!h || !phase || !psi_dev || !b_dev) return fail(HPHI_ERR_INVALID_ARG, "null argument");

@@ -266,4 +266,11 @@ int launch_cocg_iter(void *r, void *p, const void *h, const void *b, int64_t dim
                      int nsh, double tol, Reduce red, hipStream_t st);
 int launch_pair_rsqrt(const double *n, double *s, int nl, hipStream_t st);
 
+// batched small-sector Lanczos (kern_batch.hip)
+size_t batch_item_size();
+int fill_batch_item(hphi_ham *h, int iters, uint64_t seed, double *q, double *alpha, double *beta, int *done,
+                    void *out);
+int launch_lanczos_batch(const void *items_dev, int n, hipStream_t st, size_t lds_bytes);
+size_t batch_lds_bytes(int64_t dim, int n_lo, int n_hi);
+
 } // namespace hphi

@@ -1,0 +1,99 @@
+"""GPU: batched small-sector Lanczos against single solves and the oracle,
+and the serving mix: every request's result is the same alone and in the mix
+(bit for bit; the kernels' reductions are fixed-order per request)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import core as O
+from paper_2307_13222_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2307_13222_amd import api as A
+    return A
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    return api.Context(0)
+
+
+def test_lanczos_batch_matches_single_and_oracle(api, ctx):
+    say("lanczos batch")
+    specs = [(12, "chain", 1), (12, "ladder", 2), (13, "chain", 3), (14, "ladder", 4), (16, "chain", 5),
+             (15, "chain", 6), (16, "ladder", 7), (12, "chain", 8)]
+    hams, models = [], []
+    for n, lat, seed in specs:
+        m = W.random_heisenberg(n, lat, seed)
+        b = api.Basis.spin(ctx, n, n % 2)
+        hams.append(api.Hamiltonian.spin(b, m))
+        models.append(m)
+    out = api.lanczos_batch(hams, 200, [s for _, _, s in specs], keep_coefficients=True)
+    for (n, lat, seed), h, m, o in zip(specs, hams, models, out):
+        single = api.lanczos(h, 200, seed=seed)
+        assert abs(o["energy"] - single["energies"][0]) < 1e-10
+        assert np.allclose(o["alpha"][:15], single["alpha"][:15], atol=1e-12)
+        if n <= 13:
+            s = O.basis_list(n, O.sector_popcount_spin(n, n % 2))
+            assert abs(o["energy"] - np.linalg.eigvalsh(O.spin_sparse(m, s).toarray())[0]) < 1e-10
+    # a request's numbers do not depend on the rest of the launch
+    alone = api.lanczos_batch([hams[4]], 200, [specs[4][2]], keep_coefficients=True)[0]
+    assert np.array_equal(alone["alpha"], out[4]["alpha"]) and alone["energy"] == out[4]["energy"]
+    mixed = api.lanczos_batch([hams[4], hams[0], hams[6]], [200, 50, 120], [specs[4][2], 9, 10],
+                              keep_coefficients=True)
+    assert np.array_equal(mixed[0]["alpha"], out[4]["alpha"])
+    assert mixed[1]["iterations"] == 50
+
+
+def test_lanczos_batch_breakdown(api, ctx):
+    m = W._spin(8, W.chain_pairs(8), [(1.0, 0.0)] * 8, "ising")
+    h = api.Hamiltonian.spin(api.Basis.spin(ctx, 8, 0), m)
+    o = api.lanczos_batch([h], 50, [3])[0]
+    # random start, Ising chain: Krylov space of the diagonal is small
+    assert o["iterations"] <= 50
+    assert o["energy"] >= -8 * 0.25 - 1e-12
+
+
+def test_serving_mix_same_alone_and_in_mix(api, ctx):
+    from paper_2307_13222_amd import serve as S
+    say("serving mix")
+    reqs = W.serving_requests(24, 400.0, seed=7, n_range=(12, 16))
+    ex = S.GpuExecutor(0, n_workers=4, batch_max_dim=20000, lanczos_iters=200)
+    out = S.Server(ex, hbm_budget=8 * 10 ** 9, max_active=32).run(reqs)
+    say("  mix done", out["completed"], out["p50_latency_s"], out["p99_latency_s"], out["peak_active"])
+    assert out["completed"] == 24, [r.error for r in out["results"] if not r.ok]
+    assert out["peak_active"] > 1
+    for r, res in zip(reqs, out["results"]):
+        assert res.rid == r.rid
+        if r.kind == "lanczos" and S.sector_dim(r.n_sites, r.two_sz) <= ex.batch_max_dim:
+            alone = ex.run_batch([r])[0]
+        else:
+            alone = ex.run_one(r)
+        assert alone["energy"] == res.energy, (r, alone["energy"], res.energy)
+        if r.kind == "sqw":
+            assert np.array_equal(alone["D"], res.D)
+            assert np.all(-res.D.imag > 0)
+    # spot check against the oracle: the first S(q, w) request
+    r = next(q for q in reqs if q.kind == "sqw")
+    res = out["results"][r.rid]
+    m = W.random_heisenberg(r.n_sites, r.lattice, seed=r.rid)
+    s = O.basis_list(r.n_sites, O.sector_popcount_spin(r.n_sites, r.two_sz))
+    Hs = O.spin_sparse(m, s)
+    ev, U = np.linalg.eigh(Hs.toarray()) if len(s) <= 4000 else (None, None)
+    if ev is not None:
+        assert abs(res.energy - ev[0]) < 1e-9
+        b = O.szq_excitation(m, s, math.pi, U[:, 0])
+        z = res.energy + res.omega + 0.05j
+        ref = O.dyn_corr_direct(Hs, b, z)
+        assert np.max(np.abs(res.D - ref)) / np.max(np.abs(ref)) < 1e-5
