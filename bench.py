@@ -20,6 +20,11 @@ Other workloads (--workload), reported the same way:
                 error vs the same run in complex FP64
   j1j2_6x6      J1-J2 Heisenberg 6x6 (J2 = 0.5), dim 9,075,135,300, FP32
                 Lanczos vectors (36.3 GB each); E0 vs an FP64-storage run
+  serving_mix   continuous batching of a request stream: half ground states,
+                half S(q, w) (64 shifts, eta 0.05); Heisenberg chains and
+                2-leg ladders, N in 12..26, random bonds J ~ U[0.5, 1.5];
+                capacity (all requests queued at t = 0), then Poisson
+                arrivals at 0.5 / 0.8 / 0.95 of it: p50/p99 latency
 """
 from __future__ import annotations
 
@@ -42,7 +47,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--iters", type=int, default=0, help="Krylov / TPQ steps per solve (0 = workload default)")
     p.add_argument("--workload", default="hubbard4x4",
-                   choices=["hubbard4x4", "heisenberg16", "ctpq_xxz28", "j1j2_6x6"])
+                   choices=["hubbard4x4", "heisenberg16", "ctpq_xxz28", "j1j2_6x6", "serving_mix", "copy_probe"])
+    p.add_argument("--requests", type=int, default=192, help="requests per serving run (serving_mix)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-tune", action="store_true", help="keep the default launch schedule")
     p.add_argument("--retune", action="store_true", help="sweep schedules even if one is recorded")
@@ -157,6 +163,15 @@ def main():
     import torch
     from paper_2307_13222_amd import api, workloads as W
 
+    if a.workload == "copy_probe":
+        copy_probe(a)
+        return
+    if a.workload == "serving_mix":
+        out = run_serving(a, W)
+        if not a.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline_serving(a.requests)
+        print(json.dumps(out), flush=True)
+        return
     ctx = api.Context(0)
     if a.workload == "hubbard4x4":
         iters = a.iters or 300
@@ -209,6 +224,106 @@ def main():
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.workload, a.cpu_sample_rows)
     print(json.dumps(out), flush=True)
+
+
+def run_serving(a, W):
+    """Continuous batching (serve.Server over serve.GpuExecutor): one step =
+    one open-loop pass over the request list."""
+    import torch
+    from paper_2307_13222_amd import serve as S
+    n_req = a.requests
+    ex = S.GpuExecutor(0, n_workers=4, batch_max_dim=20000, lanczos_iters=200)
+    budget = 200 * 10 ** 9
+    for _ in range(a.warmup):
+        S.Server(ex, budget, max_active=64).run(W.serving_requests(24, 1e9, seed=11))
+    torch.cuda.synchronize()
+    # capacity: the whole list queued at t = 0
+    cap_run = S.Server(ex, budget, max_active=64).run(W.serving_requests(n_req, 1e9, seed=7))
+    cap = cap_run["throughput_per_s"]
+    loads = {}
+    t_total, steps = 0.0, 0
+    for frac in (0.5, 0.8, 0.95):
+        for _ in range(max(1, a.steps // 3)):
+            reqs = W.serving_requests(n_req, frac * cap, seed=7)
+            t0 = time.perf_counter()
+            r = S.Server(ex, budget, max_active=64).run(reqs)
+            t_total += time.perf_counter() - t0
+            steps += 1
+        loads[str(frac)] = {"rate_per_s": round(frac * cap, 3), "completed": r["completed"], "failed": r["failed"],
+                            "p50_latency_ms": round(1e3 * r["p50_latency_s"], 2),
+                            "p99_latency_ms": round(1e3 * r["p99_latency_s"], 2),
+                            "throughput_per_s": round(r["throughput_per_s"], 3),
+                            "busy_fraction": round(r["busy_fraction"], 3), "peak_active": r["peak_active"],
+                            "peak_gb": round(r["peak_bytes"] / 1e9, 3)}
+    kinds = {}
+    for res in cap_run["results"]:
+        kinds.setdefault(res.kind, []).append(res)
+    out = {"metric": METRIC, "value": round(cap, 3), "unit": "requests/s", "n_gpus": 1, "steps": steps,
+           "warmup": a.warmup, "ms_per_step": round(1e3 * t_total / max(1, steps), 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "serving_mix_heisenberg_chains_ladders_N12-26", "requests": n_req,
+                      "kinds": {k: len(v) for k, v in kinds.items()}, "lanczos_small_batch_max_dim": 20000,
+                      "sqw_shifts": 64, "eta": 0.05, "workers": 4},
+           "capacity": {"throughput_per_s": round(cap, 3), "span_s": round(cap_run["span_s"], 3),
+                        "completed": cap_run["completed"], "failed": cap_run["failed"],
+                        "p50_latency_ms": round(1e3 * cap_run["p50_latency_s"], 2),
+                        "p99_latency_ms": round(1e3 * cap_run["p99_latency_s"], 2),
+                        "busy_fraction": round(cap_run["busy_fraction"], 3)},
+           "open_loop": loads,
+           "roofline": None}
+    return out
+
+
+def cpu_baseline_serving(n_req: int):
+    """The oracle on a bounded sample of the same request list: the requests
+    with N <= 18 among the first ones, run one after another (ground state
+    by plain Lanczos with the oracle's C H*v; S(q, w) by the Lanczos continued
+    fraction from the excitation, 200 steps)."""
+    import math as _m
+    from oracle import core as O
+    from paper_2307_13222_amd import workloads as W
+    from paper_2307_13222_amd import serve as S
+    reqs = [r for r in W.serving_requests(n_req, 1e9, seed=7) if r.n_sites <= 18]
+    done, t0 = 0, time.perf_counter()
+    for r in reqs:
+        m = W.random_heisenberg(r.n_sites, r.lattice, seed=r.rid)
+        st = O.basis_list(r.n_sites, O.sector_popcount_spin(r.n_sites, r.two_sz))
+        hv = lambda x, m=m, st=st: O.spin_hv(m, st, x)
+        v0 = np.random.default_rng(r.rid).random(len(st)) - 0.5
+        lz = O.lanczos(hv, v0, 200)
+        if r.kind == "sqw":
+            psi = O.lanczos_ground_vector(hv, v0, lz["alpha"], lz["beta"])
+            e0 = float(O.tridiag_lowest(lz["alpha"], lz["beta"])[0])
+            b = O.szq_excitation(m, st, _m.pi, psi)
+            al, be = O.lanczos_complex(lambda x: hv(x.real) + 1j * hv(x.imag), b, 200)
+            O.continued_fraction(al, be, float(np.vdot(b, b).real),
+                                 e0 + S.sqw_grid(float(np.max(m.jz)), 64) + 0.05j)
+        done += 1
+        if time.perf_counter() - t0 > 20.0:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(done / dt, 4), "unit": "requests/s", "cores": omp_threads(), "kind": "oracle",
+            "sample": f"first {done} requests with N <= 18 of the same list, sequential", "seconds": round(dt, 3)}
+
+
+def copy_probe(a):
+    """A plain device copy of known size (2 GiB read + 2 GiB written per
+    launch): run under the FETCH_SIZE / WRITE_SIZE counters, it gives the
+    factor between those counters and bytes moved."""
+    import torch
+    n = 1 << 28
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(a.warmup):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    print(json.dumps({"workload": "copy_probe", "bytes_read_per_launch": 8 * n, "bytes_written_per_launch": 8 * n,
+                      "ms_per_launch": round(1e3 * dt, 4), "GB_per_s": round(16 * n / dt / 1e9, 1)}), flush=True)
 
 
 def run_ctpq(a, api, ctx, W):

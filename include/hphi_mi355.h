@@ -162,6 +162,12 @@ void hphi_ham_free(hphi_ham *h);
  *                   (the path sectors without a stored state list take:
  *                   more than 32 sites or 2^32 states); -1: stored list
  *                   when there is one
+ *   hub_sweep       Hubbard T_up kernel (uniform |t| tables): 1 = per-XCD
+ *                   queues of (slab, hub_item_rows rows) work items;
+ *                   2 = row-range sweep: hub_groups row ranges per XCD,
+ *                   each walking that XCD's slabs in order; 3 = as 1 with
+ *                   two adjacent columns per lane (one real vector with an
+ *                   even number of down states; otherwise as 1)
  * Errors: INVALID_ARG (value outside its range). */
 typedef struct {
     int hub_slab_cols;
@@ -170,6 +176,7 @@ typedef struct {
     int hub_row_cols;
     int spin_per_cu;
     int spin_implicit;
+    int hub_sweep;
 } hphi_schedule;
 
 int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s);

@@ -439,6 +439,10 @@ int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s)
             return fail(HPHI_ERR_INVALID_ARG, "spin_implicit %d", s->spin_implicit);
         n.spin_implicit = s->spin_implicit == 1 ? 1 : 0;
     }
+    if (s->hub_sweep) {
+        if (s->hub_sweep < 1 || s->hub_sweep > 3) return fail(HPHI_ERR_INVALID_ARG, "hub_sweep %d", s->hub_sweep);
+        n.hub_sweep = s->hub_sweep;
+    }
     h->sched_cfg = n;
     return HPHI_OK;
 }

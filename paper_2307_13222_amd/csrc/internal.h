@@ -139,10 +139,10 @@ struct hphi_ham {
     hphi::HubTables hub;
     std::vector<hphi_hop> hops;
     std::vector<double> u_site;
-    // defaults: the autotuner's choice for the 4x4 Hubbard sector at half
-    // filling (32-column slabs, 256 workgroups per XCD, 64-row items,
-    // LDS-resident row metadata); spin: 8 workgroups per CU
-    hphi_schedule sched_cfg{32, 256, 64, 3, 8, 0};
+    // defaults: 64-column slabs, 128 workgroups per XCD, 64-row items,
+    // LDS-resident row metadata, work-item queues with two columns per lane;
+    // spin: 8 workgroups per CU
+    hphi_schedule sched_cfg{64, 128, 64, 3, 8, 0, 3};
     // scratch for reductions and work queues
     hphi::DevMem sched;         // unsigned [16]: per-XCD item queues + counter
     hphi::DevMem red_partial;   // double [kReduceSlots]

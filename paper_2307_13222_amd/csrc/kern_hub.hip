@@ -46,7 +46,7 @@ struct HubKArgs {
     Reduce red;
     int nslab, groups;     // column kernel geometry
     int item_rows;         // rows per work item (<= kColsRows)
-    int row_cols;          // columns per thread pass of the rows kernel (1, 2)
+    int row_cols;          // columns per lane of the T_up queue kernel (1, 2)
     unsigned *sched;       // 8 per-XCD item queues + completion counter
     // uniform |t| fast path
     const uint32_t *fs_base, *fs_wp, *fs_wm;
@@ -403,7 +403,6 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fm(HubKArgs a)
     const S *__restrict__ v = static_cast<const S *>(a.v);
     S *__restrict__ w = static_cast<S *>(a.w);
     const S nt0 = (S)(-a.t0);
-    const uint32_t pad = (uint32_t)ddn;
     for (int64_t j = threadIdx.x; j < nch; j += blockDim.x) {
         s_base[j] = a.fs_base[j];
         s_w[j] = a.fs_wp[j] | ((a.fs_wp[j] + a.fs_wm[j]) << 16);
@@ -417,32 +416,42 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fm(HubKArgs a)
         __syncthreads();
         const uint32_t uu = a.ups[ru];
         for (int64_t c = threadIdx.x; c < ddn; c += blockDim.x) {
-            const uint32_t mw = s_w[c >> 6];
+            // a wave's 64 columns are one chunk: its widths are wave-uniform
+            const uint32_t mw = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_w[c >> 6]);
             const uint32_t wp = mw & 0xFFFFu, wt = mw >> 16;
             const uint16_t *ent = a.fs_ent + s_base[c >> 6] + (uint32_t)(c & 63);
-            uint32_t e[32];
-#pragma unroll
-            for (int t = 0; t < 32; ++t) e[t] = (uint32_t)t < wt ? (uint32_t)ent[t * 64] : pad;
             S ap[NV], am[NV];
 #pragma unroll
             for (int j = 0; j < NV; ++j) ap[j] = am[j] = (S)0;
+            // plus slots [0, wp), then minus slots [wp, wt), in slot order
+            uint32_t t = 0;
+            for (; t + 8 <= wp; t += 8) {
+                uint32_t e[8];
 #pragma unroll
-            for (int t = 0; t < 32; ++t) {
-                const bool plus = (uint32_t)t < wp;
+                for (int k = 0; k < 8; ++k) e[k] = ent[(t + k) * 64];
 #pragma unroll
-                for (int j = 0; j < NV; ++j) {
-                    const S x = s_row[e[t] * NV + j];
-                    ap[j] += plus ? x : (S)0;
-                    am[j] += plus ? (S)0 : x;
-                }
+                for (int k = 0; k < 8; ++k)
+#pragma unroll
+                    for (int j = 0; j < NV; ++j) ap[j] += s_row[e[k] * NV + j];
             }
-            for (uint32_t t = 32; t < wt; ++t) {
+            for (; t < wp; ++t) {
                 const uint32_t et = ent[t * 64];
 #pragma unroll
-                for (int j = 0; j < NV; ++j) {
-                    if (t < wp) ap[j] += s_row[et * NV + j];
-                    else am[j] += s_row[et * NV + j];
-                }
+                for (int j = 0; j < NV; ++j) ap[j] += s_row[et * NV + j];
+            }
+            for (; t + 8 <= wt; t += 8) {
+                uint32_t e[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) e[k] = ent[(t + k) * 64];
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+#pragma unroll
+                    for (int j = 0; j < NV; ++j) am[j] += s_row[e[k] * NV + j];
+            }
+            for (; t < wt; ++t) {
+                const uint32_t et = ent[t * 64];
+#pragma unroll
+                for (int j = 0; j < NV; ++j) am[j] += s_row[et * NV + j];
             }
             const S dg = hub_diag<S>(a, uu, (uint32_t)s_d[c]);
 #pragma unroll
@@ -517,8 +526,26 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fd(HubKArgs a)
 }
 
 // Columns kernel of the fast path: the same XCD-queued slab sweep as
-// k_hub_cols; staged entries are byte offsets of the neighbour rows.
-template <typename S, int NV, int CW, bool DOTS>
+// k_hub_cols; staged entries are byte offsets of the neighbour rows. Each
+// lane owns CPL adjacent columns (CPL = 2 with one real FP64 vector: one
+// 16-byte load per neighbour row, half the requests of CPL = 1; needs an
+// even row length). A scalar's summation order does not depend on CPL.
+template <typename S, int K>
+__device__ __forceinline__ void load_k(const S *p, S (&o)[K])
+{
+    if constexpr (K * sizeof(S) == 16) {
+        const uint4 x = *reinterpret_cast<const uint4 *>(p);
+        __builtin_memcpy(o, &x, 16);
+    } else if constexpr (K * sizeof(S) == 8) {
+        const uint2 x = *reinterpret_cast<const uint2 *>(p);
+        __builtin_memcpy(o, &x, 8);
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) o[j] = p[j];
+    }
+}
+
+template <typename S, int NV, int CW, bool DOTS, int CPL = 1>
 __global__ __launch_bounds__(256) void k_hub_cols_f(HubKArgs a)
 {
     __shared__ double sh_red[4 * 2 * NV + 8];
@@ -543,7 +570,9 @@ __global__ __launch_bounds__(256) void k_hub_cols_f(HubKArgs a)
 
     const int64_t ddn = a.ddn, dup = a.dup;
     const int nchunk = (int)((dup + a.item_rows - 1) / a.item_rows);
-    constexpr int RPW = 64 / CW;
+    constexpr int LPR = CW / CPL;   // lanes per row
+    constexpr int RPW = 64 / LPR;
+    constexpr int K = NV * CPL;     // scalars per lane
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     int q = home, tries = 0;
     for (;;) {
@@ -581,11 +610,189 @@ __global__ __launch_bounds__(256) void k_hub_cols_f(HubKArgs a)
         double d0[NV], d1[NV];
 #pragma unroll
         for (int j = 0; j < NV; ++j) d0[j] = d1[j] = 0.0;
-        const int64_t col = (int64_t)slab * CW + (lane % CW);
+        const int64_t col = (int64_t)slab * CW + CPL * (lane % LPR);
         const bool colok = col < ddn;
         const uint32_t colb = (uint32_t)col * ESZ;
-        for (int64_t r = r0 + wid * RPW + lane / CW; r < r1; r += 4 * RPW) {
+        for (int64_t r = r0 + wid * RPW + lane / LPR; r < r1; r += 4 * RPW) {
             if (!colok) continue;
+            const size_t me = (size_t)r * ddn + col;
+            S ap[K], am[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) ap[j] = am[j] = (S)0;
+            const uint32_t eb = s_off[r - r0], em = s_mid[r - r0], ee = s_off[r - r0 + 1];
+            uint32_t e = eb;
+            for (; e + 8 <= em; e += 8) {
+                S nv[8][K];
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    load_k<S, K>(reinterpret_cast<const S *>(vb + (s_ent[e + t] + colb)), nv[t]);
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+#pragma unroll
+                    for (int j = 0; j < K; ++j) ap[j] += nv[t][j];
+            }
+            for (; e < em; ++e) {
+                S nv[K];
+                load_k<S, K>(reinterpret_cast<const S *>(vb + (s_ent[e] + colb)), nv);
+#pragma unroll
+                for (int j = 0; j < K; ++j) ap[j] += nv[j];
+            }
+            for (; e + 8 <= ee; e += 8) {
+                S nv[8][K];
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    load_k<S, K>(reinterpret_cast<const S *>(vb + (s_ent[e + t] + colb)), nv[t]);
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+#pragma unroll
+                    for (int j = 0; j < K; ++j) am[j] += nv[t][j];
+            }
+            for (; e < ee; ++e) {
+                S nv[K];
+                load_k<S, K>(reinterpret_cast<const S *>(vb + (s_ent[e] + colb)), nv);
+#pragma unroll
+                for (int j = 0; j < K; ++j) am[j] += nv[j];
+            }
+            S out[K], raw[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                raw[j] = __builtin_nontemporal_load(&w[me * NV + j]) + nt0 * (ap[j] - am[j]);
+                out[j] = c1s * raw[j];
+            }
+            if (u) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) out[j] += c2s * __builtin_nontemporal_load(&u[me * NV + j]);
+            }
+#pragma unroll
+            for (int j = 0; j < K; ++j) __builtin_nontemporal_store(out[j], &w[me * NV + j]);
+            if (accp) {
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+                    __builtin_nontemporal_store(__builtin_nontemporal_load(&accp[me * NV + j]) + out[j],
+                                                &accp[me * NV + j]);
+            }
+            if constexpr (DOTS) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const double o = a.dot_raw ? (double)raw[j] : (double)out[j];
+                    d0[j % NV] += (double)v[me * NV + j] * o;
+                    d1[j % NV] += o * o;
+                }
+            }
+        }
+        if constexpr (DOTS) {
+            double vals[2 * NV];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                vals[j] = d0[j];
+                vals[NV + j] = d1[j];
+            }
+            block_sum<2 * NV>(vals, sh_red);
+            if (threadIdx.x == 0) {
+                const size_t slot = (size_t)slab * nchunk + chunk;
+                for (int j = 0; j < 2 * NV; ++j) a.red.partial[slot * 2 * NV + j] = vals[j];
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        s_last = (atomicAdd(&a.sched[8], 1u) == gridDim.x - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    if constexpr (DOTS) {
+        const size_t nitems = (size_t)a.nslab * nchunk;
+        for (int j = 0; j < 2 * NV; ++j) {
+            double s = 0.0;
+            for (size_t it = threadIdx.x; it < nitems; it += blockDim.x)
+                s += __builtin_nontemporal_load(&a.red.partial[it * 2 * NV + j]);
+            double vv[1] = {s};
+            block_sum<1>(vv, sh_red);
+            if (threadIdx.x == 0) a.red.result[j] = vv[0];
+        }
+    }
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 8; ++i) a.sched[i] = 0u;
+        a.sched[8] = 0u;
+        __threadfence();
+    }
+}
+
+// Columns kernel of the fast path, row-range variant. A work item is
+// (x, g): up rows [g * item_rows, (g + 1) * item_rows) over all slabs
+// x, x + 8, x + 16, ..., swept in order. Items of class x sit in the queue of
+// XCD x (the XCD a workgroup runs on is read from the hardware register);
+// a workgroup stages its item's neighbour lists in LDS once and walks the
+// slab sequence, so all workgroups of an XCD move through the same slabs at
+// about the same pace and its L2 holds about one slab at a time. Queues
+// drained, workgroups steal from the other XCDs. Per-element summation order
+// is that of k_hub_cols_f; the FP64 dot partials are one per item, reduced in
+// item order by the last workgroup to finish.
+template <typename S, int NV, int CW, bool DOTS>
+__global__ __launch_bounds__(256) void k_hub_cols_p(HubKArgs a)
+{
+    __shared__ double sh_red[4 * 2 * NV + 8];
+    __shared__ uint32_t s_ent[kColsLdsEntries];
+    __shared__ uint32_t s_off[kColsRows + 1];
+    __shared__ uint32_t s_mid[kColsRows];
+    __shared__ int s_item;
+    __shared__ unsigned s_last;
+    const char *__restrict__ vb = static_cast<const char *>(a.v);
+    const S *__restrict__ v = static_cast<const S *>(a.v);
+    S *__restrict__ w = static_cast<S *>(a.w);
+    const S *__restrict__ u = static_cast<const S *>(a.u);
+    S *__restrict__ accp = static_cast<S *>(a.acc_out);
+    double c1 = 1.0, c2 = 0.0;
+    if (a.ecoef) {
+        c1 = a.ecoef[0];
+        c2 = a.ecoef[1];
+    }
+    const S c1s = (S)c1, c2s = (S)c2, nt0 = (S)(-a.t0);
+    constexpr uint32_t ESZ = NV * sizeof(S);
+    constexpr int RPW = 64 / CW;
+    const int64_t ddn = a.ddn, dup = a.dup;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nrange = a.groups;   // row ranges per slab class
+    int q = xcc_id(), tries = 0;
+    for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int it = -1;
+        while (tries < 8) {
+            const int cand = (int)atomicAdd(&a.sched[q], 1u);
+            if (cand < nrange) {
+                it = q * nrange + cand;
+                break;
+            }
+            q = (q + 1) & 7;
+            ++tries;
+        }
+        s_item = it;
+    }
+    __syncthreads();
+    const int item = s_item;
+    if (item < 0) break;
+    const int x = item / nrange;
+    const int64_t r0 = (int64_t)(item % nrange) * a.item_rows;
+    const int64_t r1 = r0 + a.item_rows < dup ? r0 + a.item_rows : dup;
+    if (r0 < r1) {
+        const uint32_t base = a.fu_off[r0];
+        for (int64_t i = threadIdx.x; i <= r1 - r0; i += blockDim.x) s_off[i] = a.fu_off[r0 + i] - base;
+        for (int64_t i = threadIdx.x; i < r1 - r0; i += blockDim.x) s_mid[i] = a.fu_mid[r0 + i] - base;
+        const uint32_t n = a.fu_off[r1] - base;
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) s_ent[i] = a.fu_ent[base + i] * ESZ;
+    }
+    __syncthreads();
+    double d0[NV], d1[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) d0[j] = d1[j] = 0.0;
+    for (int slab = x; slab < a.nslab; slab += 8) {
+        const int64_t col = (int64_t)slab * CW + (lane % CW);
+        if (col >= ddn) continue;
+        const uint32_t colb = (uint32_t)col * ESZ;
+        for (int64_t r = r0 + wid * RPW + lane / CW; r < r1; r += 4 * RPW) {
             const size_t me = (size_t)r * ddn + col;
             S ap[NV], am[NV];
 #pragma unroll
@@ -655,19 +862,18 @@ __global__ __launch_bounds__(256) void k_hub_cols_f(HubKArgs a)
                 }
             }
         }
-        if constexpr (DOTS) {
-            double vals[2 * NV];
+    }
+    if constexpr (DOTS) {
+        double vals[2 * NV];
 #pragma unroll
-            for (int j = 0; j < NV; ++j) {
-                vals[j] = d0[j];
-                vals[NV + j] = d1[j];
-            }
-            block_sum<2 * NV>(vals, sh_red);
-            if (threadIdx.x == 0) {
-                const size_t slot = (size_t)slab * nchunk + chunk;
-                for (int j = 0; j < 2 * NV; ++j) a.red.partial[slot * 2 * NV + j] = vals[j];
-            }
+        for (int j = 0; j < NV; ++j) {
+            vals[j] = d0[j];
+            vals[NV + j] = d1[j];
         }
+        block_sum<2 * NV>(vals, sh_red);
+        if (threadIdx.x == 0)
+            for (int j = 0; j < 2 * NV; ++j) a.red.partial[(size_t)item * 2 * NV + j] = vals[j];
+    }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -678,7 +884,7 @@ __global__ __launch_bounds__(256) void k_hub_cols_f(HubKArgs a)
     if (!s_last) return;
     __threadfence();
     if constexpr (DOTS) {
-        const size_t nitems = (size_t)a.nslab * nchunk;
+        const size_t nitems = 8 * (size_t)nrange;
         for (int j = 0; j < 2 * NV; ++j) {
             double s = 0.0;
             for (size_t it = threadIdx.x; it < nitems; it += blockDim.x)
@@ -696,6 +902,13 @@ __global__ __launch_bounds__(256) void k_hub_cols_f(HubKArgs a)
 }
 
 template <typename S, int NV, int CW>
+static void launch_cols_p(const HubKArgs &a, int grid, hipStream_t st)
+{
+    if (a.nd) hipLaunchKernelGGL((k_hub_cols_p<S, NV, CW, true>), dim3(grid), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_hub_cols_p<S, NV, CW, false>), dim3(grid), dim3(256), 0, st, a);
+}
+
+template <typename S, int NV, int CW>
 static void launch_cols_t(const HubKArgs &a, int grid, hipStream_t st)
 {
     if (a.nd) hipLaunchKernelGGL((k_hub_cols<S, NV, CW, true>), dim3(grid), dim3(256), 0, st, a);
@@ -705,6 +918,11 @@ static void launch_cols_t(const HubKArgs &a, int grid, hipStream_t st)
 template <typename S, int NV, int CW>
 static void launch_cols_f(const HubKArgs &a, int grid, hipStream_t st)
 {
+    if (a.row_cols == 2 && NV == 1) {
+        if (a.nd) hipLaunchKernelGGL((k_hub_cols_f<S, NV, CW, true, 2>), dim3(grid), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_hub_cols_f<S, NV, CW, false, 2>), dim3(grid), dim3(256), 0, st, a);
+        return;
+    }
     if (a.nd) hipLaunchKernelGGL((k_hub_cols_f<S, NV, CW, true>), dim3(grid), dim3(256), 0, st, a);
     else hipLaunchKernelGGL((k_hub_cols_f<S, NV, CW, false>), dim3(grid), dim3(256), 0, st, a);
 }
@@ -756,6 +974,32 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
     // column kernel, geometry from the Hamiltonian's schedule
     const int cw = h->sched_cfg.hub_slab_cols;
     const int groups = h->sched_cfg.hub_groups;
+    if (fast && h->sched_cfg.hub_sweep == 2) {
+        // persistent sweep: hub_groups row ranges, each within the staging arrays
+        int64_t rows = (a.dup + groups - 1) / groups;
+        if (rows > kColsRows) rows = kColsRows;
+        const int64_t deg = h->hub.max_deg[0] > 0 ? h->hub.max_deg[0] : 1;
+        if (rows * deg > kColsLdsEntries) rows = kColsLdsEntries / deg;
+        if (rows < 1)
+            return fail(HPHI_ERR_UNSUPPORTED, "Hubbard up-species degree %lld too large for staging",
+                        (long long)h->hub.max_deg[0]);
+        const int64_t g_eff = (a.dup + rows - 1) / rows;
+        a.item_rows = (int)rows;
+        a.groups = (int)g_eff;
+        a.nslab = (int)((a.ddn + cw - 1) / cw);
+        const int64_t grid_p = 8 * g_eff;
+        if (grid_p > (int64_t)INT32_MAX || (a.nd && grid_p * 2 * NV > (int64_t)kReduceSlots))
+            return fail(HPHI_ERR_UNSUPPORTED, "Hubbard column sweep grid too large");
+        a.sched = h->sched.as<unsigned>();
+        switch (cw) {
+        case 8: launch_cols_p<S, NV, 8>(a, (int)grid_p, st); break;
+        case 16: launch_cols_p<S, NV, 16>(a, (int)grid_p, st); break;
+        case 32: launch_cols_p<S, NV, 32>(a, (int)grid_p, st); break;
+        default: launch_cols_p<S, NV, 64>(a, (int)grid_p, st); break;
+        }
+        HPHI_HIP(hipGetLastError());
+        return HPHI_OK;
+    }
     int item_rows = h->sched_cfg.hub_item_rows;
     // the item's neighbour lists must fit the staging array
     while (item_rows > 8 && (int64_t)item_rows * h->hub.max_deg[0] > kColsLdsEntries) item_rows /= 2;
@@ -770,6 +1014,8 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
     if (a.nd && nitems * 2 * NV > (int64_t)kReduceSlots)
         return fail(HPHI_ERR_UNSUPPORTED, "Hubbard column items beyond the reduction scratch");
     a.sched = h->sched.as<unsigned>();
+    // hub_sweep 3: two adjacent columns per lane (even row length only)
+    a.row_cols = (h->sched_cfg.hub_sweep == 3 && NV == 1 && a.ddn % 2 == 0) ? 2 : 1;
     if (fast) {
         switch (cw) {
         case 8: launch_cols_f<S, NV, 8>(a, (int)grid_c, st); break;

@@ -276,7 +276,12 @@ def test_hubbard_schedules_bit_identical(api, ctx):
     for sch in [dict(hub_slab_cols=16, hub_groups=128, hub_item_rows=64, hub_row_cols=1),
                 dict(hub_slab_cols=8, hub_groups=64, hub_item_rows=32, hub_row_cols=2),
                 dict(hub_slab_cols=32, hub_groups=256, hub_item_rows=128, hub_row_cols=3),
-                dict(hub_slab_cols=64, hub_groups=1, hub_item_rows=8, hub_row_cols=1)]:
+                dict(hub_slab_cols=64, hub_groups=1, hub_item_rows=8, hub_row_cols=1),
+                dict(hub_slab_cols=16, hub_groups=256, hub_item_rows=64, hub_row_cols=3, hub_sweep=2),
+                dict(hub_slab_cols=8, hub_groups=3, hub_item_rows=64, hub_row_cols=1, hub_sweep=2),
+                dict(hub_slab_cols=64, hub_groups=1024, hub_item_rows=64, hub_row_cols=3, hub_sweep=2),
+                dict(hub_slab_cols=8, hub_groups=128, hub_item_rows=32, hub_row_cols=3, hub_sweep=3),
+                dict(hub_slab_cols=64, hub_groups=256, hub_item_rows=64, hub_row_cols=1, hub_sweep=3)]:
         h.set_schedule(**sch)
         assert h.get_schedule()["hub_slab_cols"] == sch["hub_slab_cols"]
         w = host(h.mult(v))
@@ -287,6 +292,8 @@ def test_hubbard_schedules_bit_identical(api, ctx):
         assert np.array_equal(w, ref), sch
     with pytest.raises(api.HphiError):
         h.set_schedule(hub_slab_cols=12)
+    with pytest.raises(api.HphiError):
+        h.set_schedule(hub_sweep=4)
 
 
 def test_hubbard_4x4_full_size_sampled_rows(api, ctx):
