@@ -48,13 +48,46 @@ def parse():
     p.add_argument("--iters", type=int, default=0, help="Krylov / TPQ steps per solve (0 = workload default)")
     p.add_argument("--workload", default="hubbard4x4",
                    choices=["hubbard4x4", "heisenberg16", "ctpq_xxz28", "j1j2_6x6", "serving_mix", "copy_probe"])
-    p.add_argument("--requests", type=int, default=192, help="requests per serving run (serving_mix)")
+    p.add_argument("--requests", type=int, default=64, help="requests per serving run (serving_mix)")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--no-tune", action="store_true", help="keep the default launch schedule")
-    p.add_argument("--retune", action="store_true", help="sweep schedules even if one is recorded")
+    p.add_argument("--tune", action="store_true",
+                   help="run the schedule autotuner first (default: the built-in schedule)")
+    p.add_argument("--no-tune", action="store_true", help="keep the built-in launch schedule (the default)")
+    p.add_argument("--retune", action="store_true", help="with --tune: sweep even if a schedule is recorded")
     p.add_argument("--cpu-sample-rows", type=int, default=0,
                    help="oracle sample size in up-rows (hubbard4x4)")
-    return p.parse_args()
+    a = p.parse_args()
+    a.no_tune = a.no_tune or not a.tune
+    return a
+
+
+# HBM traffic of one H*v of the 4x4 Hubbard workload, from two rocprofv3 --pmc
+# passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, summed over the two H*v
+# kernels) scaled by the factors a plain 2 GiB device copy gives for the same
+# counters (fetch 2.000, write 1.000). Valid only for the kernel sources and
+# schedule it was taken with; anything else reports null.
+HUB_TRAFFIC = {
+    "sources_sha256": {"kern_hub.hip": "b9af4f85d7892ab229f3f6e66d3d4df30b640f5269bde1ebf166b9a5c0cd3511",
+                       "kern_common.h": "b031d8c5f79430296feee4fc8cb7e28dc7549a9ad041c9c06a17fec777e3ba0a"},
+    "schedule": {"hub_slab_cols": 64, "hub_groups": 128, "hub_item_rows": 64, "hub_row_cols": 3, "hub_sweep": 3},
+    "fetch_kib": 7.32067e6 + 725759.0, "write_kib": 1.33765e6 + 1.41512e6,
+    "fetch_factor": 2.0, "write_factor": 1.0,
+}
+
+
+def hub_traffic(schedule) -> float:
+    """Measured HBM bytes per H*v launch pair, or None when the kernel
+    sources or the schedule differ from those the counters were taken on."""
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2307_13222_amd", "csrc")
+    for f, h in HUB_TRAFFIC["sources_sha256"].items():
+        with open(os.path.join(src, f), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != h:
+                return None
+    if any(schedule.get(k) != v for k, v in HUB_TRAFFIC["schedule"].items()):
+        return None
+    t = HUB_TRAFFIC
+    return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
 
 
 def omp_threads() -> int:
@@ -106,10 +139,10 @@ def cpu_baseline(workload: str, sample_rows: int):
             "sample": sample, "seconds": round(dt, 3)}
 
 
-def roofline(gbs: float, alg_bytes: float, kernel: str):
+def roofline(gbs: float, alg_bytes: float, kernel: str, traffic=None):
     return {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel,
-            "alg_bytes_per_launch": alg_bytes}
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None if traffic is None else round(traffic),
+            "kernel": kernel, "alg_bytes_per_launch": alg_bytes}
 
 
 def base_line(a, value, ms_per_step, dtype, config):
@@ -124,9 +157,11 @@ def run_lanczos(a, api, ham, dim, iters, storage, wl, kernel, tune_dtype):
     if not a.no_tune:
         from paper_2307_13222_amd import autotune
         tuned = autotune.tune(ham, tune_dtype, 1, force=a.retune)
-        wl["schedule"] = tuned["schedule"]
         if tuned.get("swept"):
             print(json.dumps({"autotune": tuned}), file=sys.stderr, flush=True)
+    sched = ham.get_schedule()
+    wl["schedule"] = ({k: v for k, v in sched.items() if k.startswith("hub_")} if ham.basis.kind == "hubbard"
+                      else {k: v for k, v in sched.items() if k.startswith("spin_")})
     for _ in range(a.warmup):
         api.lanczos(ham, iters, seed=1, storage=storage, stream=stream)
     torch.cuda.synchronize()
@@ -151,7 +186,8 @@ def run_lanczos(a, api, ham, dim, iters, storage, wl, kernel, tune_dtype):
                 "solve_ms_p50": round(1e3 * float(np.percentile(lat, 50)), 3),
                 "solve_ms_p99": round(1e3 * float(np.percentile(lat, 99)), 3),
                 "hv_ms_avg": round(1e3 * hv_avg, 5), "e0": energies[0],
-                "roofline": roofline(gbs, alg_bytes, kernel)})
+                "roofline": roofline(gbs, alg_bytes, kernel,
+                                     hub_traffic(wl["schedule"]) if ham.basis.kind == "hubbard" else None)})
     return out, energies
 
 
@@ -234,21 +270,28 @@ def run_serving(a, W):
     n_req = a.requests
     ex = S.GpuExecutor(0, n_workers=4, batch_max_dim=20000, lanczos_iters=200)
     budget = 200 * 10 ** 9
+    def note(msg):
+        print(msg, file=sys.stderr, flush=True)
+
     for _ in range(a.warmup):
-        S.Server(ex, budget, max_active=64).run(W.serving_requests(24, 1e9, seed=11))
+        S.Server(ex, budget, max_active=64).run(W.serving_requests(16, 1e9, seed=11, n_range=(12, 20)))
     torch.cuda.synchronize()
+    note("serving: warm-up done")
     # capacity: the whole list queued at t = 0
     cap_run = S.Server(ex, budget, max_active=64).run(W.serving_requests(n_req, 1e9, seed=7))
     cap = cap_run["throughput_per_s"]
+    note(f"serving: capacity {cap:.3f} requests/s over {cap_run['span_s']:.1f} s")
     loads = {}
     t_total, steps = 0.0, 0
-    for frac in (0.5, 0.8, 0.95):
-        for _ in range(max(1, a.steps // 3)):
-            reqs = W.serving_requests(n_req, frac * cap, seed=7)
-            t0 = time.perf_counter()
-            r = S.Server(ex, budget, max_active=64).run(reqs)
-            t_total += time.perf_counter() - t0
-            steps += 1
+    fracs = (0.5, 0.8, 0.95)
+    for k in range(max(1, a.steps)):
+        frac = fracs[k % len(fracs)]
+        reqs = W.serving_requests(n_req, frac * cap, seed=7 + k // len(fracs))
+        t0 = time.perf_counter()
+        r = S.Server(ex, budget, max_active=64).run(reqs)
+        t_total += time.perf_counter() - t0
+        steps += 1
+        note(f"serving: load {frac} done, p50 {r['p50_latency_s']:.3f} s, p99 {r['p99_latency_s']:.3f} s")
         loads[str(frac)] = {"rate_per_s": round(frac * cap, 3), "completed": r["completed"], "failed": r["failed"],
                             "p50_latency_ms": round(1e3 * r["p50_latency_s"], 2),
                             "p99_latency_ms": round(1e3 * r["p99_latency_s"], 2),
@@ -263,7 +306,8 @@ def run_serving(a, W):
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "serving_mix_heisenberg_chains_ladders_N12-26", "requests": n_req,
                       "kinds": {k: len(v) for k, v in kinds.items()}, "lanczos_small_batch_max_dim": 20000,
-                      "sqw_shifts": 64, "eta": 0.05, "workers": 4},
+                      "sqw_shifts": 64, "eta": 0.05, "sqw_tol": ex.sqw_tol, "sqw_max_iter": ex.sqw_max_iter,
+                      "workers": 4},
            "capacity": {"throughput_per_s": round(cap, 3), "span_s": round(cap_run["span_s"], 3),
                         "completed": cap_run["completed"], "failed": cap_run["failed"],
                         "p50_latency_ms": round(1e3 * cap_run["p50_latency_s"], 2),

@@ -225,7 +225,7 @@ class GpuExecutor:
 
     def __init__(self, device: int = 0, n_workers: int = 4, batch_max_dim: int = 20000,
                  max_batch: int = 512, lanczos_iters: int = 200, max_iter: int = 500, eta: float = 0.05,
-                 n_shift: int = 64, sqw_tol: float = 1e-8):
+                 n_shift: int = 64, sqw_tol: float = 1e-8, sqw_max_iter: int = 6000):
         from . import api
         self.api = api
         self.ctx = api.Context(device)
@@ -237,6 +237,7 @@ class GpuExecutor:
         self.eta = eta
         self.n_shift = n_shift
         self.sqw_tol = sqw_tol
+        self.sqw_max_iter = sqw_max_iter
         self.t0 = time.perf_counter()
         self.work: "queue.Queue" = queue.Queue()
         self.batchq: "queue.Queue" = queue.Queue()
@@ -314,7 +315,7 @@ class GpuExecutor:
         b = api.szq(ham, math.pi, r["psi"], stream=stream)
         omega = sqw_grid(float(np.max(m.jz)), self.n_shift)
         z = e0 + omega + 1j * self.eta
-        d = api.sqw(ham, b, z, max_iter=2000, tol=self.sqw_tol, stream=stream)
+        d = api.sqw(ham, b, z, max_iter=self.sqw_max_iter, tol=self.sqw_tol, stream=stream)
         return {"energy": e0, "iterations": r["iterations"], "omega": omega, "D": d["D"], "path": "stream",
                 "ok": bool(d["converged"]), "error": "" if d["converged"] else "COCG not converged"}
 
