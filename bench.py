@@ -217,7 +217,7 @@ def main():
         wl = {"workload": "hubbard_4x4_pbc_t1_U4_half_filling", "dim": basis.dim, "lanczos_iters": iters,
               "storage": "f64", "lattice": "square 4x4", "n_up": 8, "n_dn": 8}
         out, _ = run_lanczos(a, api, ham, basis.dim, iters, "f64", wl,
-                             "H*v = k_hub_rows_fm + k_hub_cols_f (T_dn/U rows kernel + T_up slab kernel)", "f64")
+                             "H*v = k_hub_rows_fb + k_hub_cols_f (T_dn/U rows kernel + T_up slab kernel)", "f64")
     elif a.workload == "heisenberg16":
         iters = a.iters or 200
         m = W.heisenberg_chain(16)

@@ -152,11 +152,14 @@ void hphi_ham_free(hphi_ham *h);
  * autotuner; zero fields keep the current value). Results do not depend on
  * the schedule beyond floating-point summation order.
  *   hub_slab_cols   columns per L2-resident slab of the Hubbard T_up kernel
- *                   (8, 16, 32 or 64)
+ *                   (8, 16, 32, 64 or 128; 128 only with hub_sweep 3 on
+ *                   one real vector, otherwise 64)
  *   hub_groups      workgroups per XCD of that kernel (1..1024)
  *   hub_item_rows   rows per work item of that kernel (8..128)
  *   hub_row_cols    T_dn kernel variant: 1 = batched table loads, 2 = all
- *                   loads of two columns issued at once, 3 = of one column
+ *                   loads of two columns issued at once, 3 = row metadata
+ *                   in LDS, 4 = as 3 with hop-ordered slots (up to 32767
+ *                   down states; otherwise as 3)
  *   spin_per_cu     spin H*v workgroups per compute unit (1..16)
  *   spin_implicit   1: spin H*v rebuilds configurations from row indices
  *                   (the path sectors without a stored state list take:

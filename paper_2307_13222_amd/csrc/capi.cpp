@@ -338,6 +338,51 @@ static int build_hub_fast(hphi_ham *h)
     HPHI_TRY(upload(h->hub.fs_wp, wp.data(), sizeof(uint32_t) * wp.size()));
     HPHI_TRY(upload(h->hub.fs_wm, wm.data(), sizeof(uint32_t) * wm.size()));
     HPHI_TRY(upload(h->hub.fs_ent, ent.data(), sizeof(uint16_t) * ent.size()));
+    // down species, hop-ordered slots: slot k of a 64-state chunk is one
+    // hop for all its states (the 64 targets of a slot mostly lie in one
+    // group of consecutive states). Lane-major: the slots of one state are
+    // consecutive, padded to a multiple of 8, so a lane reads 8 per 16-byte
+    // load. Entry = column | sign << 15; unconnected slots hold dim_dn.
+    if (dn.dim < 32768) {
+        std::vector<uint32_t> fbase(nchunk + 1, 0), fw(nchunk, 0);
+        std::vector<uint16_t> fent;
+        std::vector<std::vector<uint16_t>> slots;
+        uint32_t wmax = 0;
+        for (int64_t j = 0; j < nchunk; ++j) {
+            const int64_t c0 = j * kSellChunk, c1 = std::min(dn.dim, c0 + kSellChunk);
+            slots.clear();
+            for (const hphi_hop &hp : h->hops) {
+                bool any = false;
+                std::vector<uint16_t> col(kSellChunk, (uint16_t)dn.dim);
+                for (int64_t c = c0; c < c1; ++c) {
+                    const uint64_t st = dn.state_at(c);
+                    if (((st >> hp.i) & 1) == ((st >> hp.j) & 1)) continue;
+                    const uint64_t t = st ^ ((uint64_t(1) << hp.i) | (uint64_t(1) << hp.j));
+                    const int lo = std::min(hp.i, hp.j), hi = std::max(hp.i, hp.j);
+                    const uint64_t between =
+                        (hi - lo > 1) ? (((uint64_t(1) << hi) - 1) & ~((uint64_t(1) << (lo + 1)) - 1)) : 0;
+                    const int fs = (__builtin_popcountll(st & between) & 1) ? -1 : 1;
+                    const int se = fs * (hp.t < 0 ? -1 : 1);
+                    col[c - c0] = (uint16_t)((uint32_t)dn.rank_of(t) | (se < 0 ? 0x8000u : 0u));
+                    any = true;
+                }
+                if (any) slots.push_back(col);
+            }
+            const uint32_t w8 = (uint32_t)((slots.size() + 7) / 8 * 8);
+            fw[j] = w8;
+            wmax = std::max(wmax, w8);
+            const size_t at = fent.size();
+            fent.resize(at + (size_t)w8 * kSellChunk, (uint16_t)dn.dim);
+            for (int l = 0; l < kSellChunk; ++l)
+                for (size_t k = 0; k < slots.size(); ++k) fent[at + (size_t)l * w8 + k] = slots[k][l];
+            fbase[j + 1] = (uint32_t)fent.size();
+        }
+        if (fent.empty()) fent.assign(8, (uint16_t)dn.dim);
+        HPHI_TRY(upload(h->hub.fb_base, fbase.data(), sizeof(uint32_t) * fbase.size()));
+        HPHI_TRY(upload(h->hub.fb_w, fw.data(), sizeof(uint32_t) * fw.size()));
+        HPHI_TRY(upload(h->hub.fb_ent, fent.data(), sizeof(uint16_t) * fent.size()));
+        h->hub.fb_ok = wmax <= 32;   // the kernel holds up to 32 slots per state
+    }
     // up species: CSR, plus entries then minus entries, targets as row
     // element offsets r' * dim_dn
     split_lists(up, h->hops, pl, mi);
@@ -412,7 +457,8 @@ int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s)
     if (!h || !s) return fail(HPHI_ERR_INVALID_ARG, "null argument");
     hphi_schedule n = h->sched_cfg;
     if (s->hub_slab_cols) {
-        if (s->hub_slab_cols != 8 && s->hub_slab_cols != 16 && s->hub_slab_cols != 32 && s->hub_slab_cols != 64)
+        if (s->hub_slab_cols != 8 && s->hub_slab_cols != 16 && s->hub_slab_cols != 32 && s->hub_slab_cols != 64 &&
+            s->hub_slab_cols != 128)
             return fail(HPHI_ERR_INVALID_ARG, "hub_slab_cols %d", s->hub_slab_cols);
         n.hub_slab_cols = s->hub_slab_cols;
     }
@@ -426,7 +472,7 @@ int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s)
         n.hub_item_rows = s->hub_item_rows;
     }
     if (s->hub_row_cols) {
-        if (s->hub_row_cols < 1 || s->hub_row_cols > 3)
+        if (s->hub_row_cols < 1 || s->hub_row_cols > 4)
             return fail(HPHI_ERR_INVALID_ARG, "hub_row_cols %d", s->hub_row_cols);
         n.hub_row_cols = s->hub_row_cols;
     }

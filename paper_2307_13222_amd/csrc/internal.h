@@ -116,6 +116,11 @@ struct HubTables {
     uint32_t fs_maxw = 0;                    // widest down chunk (plus + minus)
     DevMem fs_base, fs_wp, fs_wm, fs_ent;    // down: chunk base, widths, uint16 entries
     DevMem fu_off, fu_mid, fu_ent;           // up: row offsets, split points, targets
+    // down species, bond-ordered slots (dim_dn < 32768): per chunk of 64
+    // states one slot per hop active in any of them, in hop order; entry =
+    // column | sign << 15, inactive lanes point at the zero slot dim_dn
+    bool fb_ok = false;
+    DevMem fb_base, fb_w, fb_ent;
     DevMem coef;     // double [128]: -t per value class
     DevMem u_site;   // double [n_sites]
     int n_coef = 0;
@@ -139,10 +144,10 @@ struct hphi_ham {
     hphi::HubTables hub;
     std::vector<hphi_hop> hops;
     std::vector<double> u_site;
-    // defaults: 64-column slabs, 128 workgroups per XCD, 64-row items,
-    // LDS-resident row metadata, work-item queues with two columns per lane;
+    // defaults: 128-column slabs, 128 workgroups per XCD, 32-row items,
+    // hop-ordered down slots, work-item queues with two columns per lane;
     // spin: 8 workgroups per CU
-    hphi_schedule sched_cfg{64, 128, 64, 3, 8, 0, 3};
+    hphi_schedule sched_cfg{128, 128, 32, 4, 8, 0, 3};
     // scratch for reductions and work queues
     hphi::DevMem sched;         // unsigned [16]: per-XCD item queues + counter
     hphi::DevMem red_partial;   // double [kReduceSlots]

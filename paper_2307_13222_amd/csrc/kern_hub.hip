@@ -52,6 +52,8 @@ struct HubKArgs {
     const uint32_t *fs_base, *fs_wp, *fs_wm;
     const uint16_t *fs_ent;
     const uint32_t *fu_off, *fu_mid, *fu_ent;
+    const uint32_t *fb_base, *fb_w;
+    const uint16_t *fb_ent;
     double t0;
 };
 
@@ -458,6 +460,93 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fm(HubKArgs a)
             for (int j = 0; j < NV; ++j)
                 __builtin_nontemporal_store(dg * s_row[c * NV + j] + nt0 * (ap[j] - am[j]),
                                             &w[((size_t)ru * ddn + c) * NV + j]);
+        }
+    }
+}
+
+// Rows kernel with hop-ordered down slots: slot k of a 64-state chunk is one
+// hop for all 64 lanes (a lane that the hop does not connect reads the zero
+// slot). The lanes of a wave share their high-half pattern, so one slot's
+// targets lie in one group of consecutive states of the row in LDS and the
+// gathers rarely share a bank; the sign rides in bit 15 of the entry. A
+// lane's slots are consecutive in memory: up to 32 of them arrive in four
+// 16-byte loads, issued for the next column while the current one gathers.
+// Row metadata (chunk bases, widths, down states) is staged in LDS as in
+// k_hub_rows_fm. Sum order: hops in input order.
+template <typename S, int NV>
+__device__ __forceinline__ void fb_gather(const uint4 (&q)[4], uint32_t nq, const S *s_row, S (&acc)[NV])
+{
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        if ((uint32_t)g >= nq) break;
+        const uint32_t wd[4] = {q[g].x, q[g].y, q[g].z, q[g].w};
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            const uint32_t e = (wd[h >> 1] >> ((h & 1) * 16)) & 0xFFFFu;
+            const uint32_t col = e & 0x7FFFu;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                const S x = s_row[col * NV + j];
+                acc[j] += (e & 0x8000u) ? -x : x;
+            }
+        }
+    }
+}
+
+template <typename S, int NV>
+__global__ __launch_bounds__(1024) void k_hub_rows_fb(HubKArgs a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int64_t ddn = a.ddn;
+    const int64_t nch = (ddn + 63) >> 6;
+    S *s_row = reinterpret_cast<S *>(smem_raw);
+    uint32_t *s_base = reinterpret_cast<uint32_t *>(s_row + (ddn + 1) * NV);
+    uint32_t *s_w = s_base + nch;
+    uint16_t *s_d = reinterpret_cast<uint16_t *>(s_w + nch);
+    const S *__restrict__ v = static_cast<const S *>(a.v);
+    S *__restrict__ w = static_cast<S *>(a.w);
+    const S nt0 = (S)(-a.t0);
+    for (int64_t j = threadIdx.x; j < nch; j += blockDim.x) {
+        s_base[j] = a.fb_base[j];
+        s_w[j] = a.fb_w[j];
+    }
+    for (int64_t c = threadIdx.x; c < ddn; c += blockDim.x) s_d[c] = (uint16_t)a.dns[c];
+    __syncthreads();
+    // entries of column c: 16-byte words at fb_ent + base(c) + lane * width
+    auto load_col = [&](int64_t c, uint4 (&q)[4], uint32_t &nq) {
+        nq = 0;
+        if (c >= ddn) return;
+        const uint32_t wc = s_w[c >> 6];
+        nq = wc >> 3;
+        const uint4 *p = reinterpret_cast<const uint4 *>(a.fb_ent + s_base[c >> 6] + (uint32_t)(c & 63) * wc);
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+            if ((uint32_t)g < nq) q[g] = p[g];
+    };
+    for (int64_t ru = blockIdx.x; ru < a.dup; ru += gridDim.x) {
+        const S *vrow = v + (size_t)ru * ddn * NV;
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < ddn * NV; i += blockDim.x) s_row[i] = vrow[i];
+        if (threadIdx.x < NV) s_row[ddn * NV + threadIdx.x] = (S)0;
+        uint4 cur[4], nxt[4];
+        uint32_t ncur, nnxt;
+        load_col(threadIdx.x, cur, ncur);
+        __syncthreads();
+        const uint32_t uu = a.ups[ru];
+        for (int64_t c = threadIdx.x; c < ddn; c += blockDim.x) {
+            load_col(c + blockDim.x, nxt, nnxt);
+            S acc[NV];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) acc[j] = (S)0;
+            fb_gather<S, NV>(cur, ncur, s_row, acc);
+            const S dg = hub_diag<S>(a, uu, (uint32_t)s_d[c]);
+#pragma unroll
+            for (int j = 0; j < NV; ++j)
+                __builtin_nontemporal_store(dg * s_row[c * NV + j] + nt0 * acc[j],
+                                            &w[((size_t)ru * ddn + c) * NV + j]);
+#pragma unroll
+            for (int g = 0; g < 4; ++g) cur[g] = nxt[g];
+            ncur = nnxt;
         }
     }
 }
@@ -928,6 +1017,15 @@ static void launch_cols_f(const HubKArgs &a, int grid, hipStream_t st)
 }
 
 template <typename S, int NV>
+static void launch_cols_f128(const HubKArgs &a, int grid, hipStream_t st)
+{
+    if constexpr (NV == 1) {
+        if (a.nd) hipLaunchKernelGGL((k_hub_cols_f<S, 1, 128, true, 2>), dim3(grid), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_hub_cols_f<S, 1, 128, false, 2>), dim3(grid), dim3(256), 0, st, a);
+    }
+}
+
+template <typename S, int NV>
 static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
 {
     const int ncu = h->basis->ctx->n_cu > 0 ? h->basis->ctx->n_cu : 256;
@@ -945,7 +1043,11 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
                       (unsigned __int128)a.dup * a.ddn * NV * sizeof(S) < ((unsigned __int128)1 << 32);
     const int rmode = h->sched_cfg.hub_row_cols;
     const size_t fm_bytes = fast_row_bytes + 8 * (size_t)((a.ddn + 63) / 64) + 2 * (size_t)a.ddn + 16;
-    if (fast && rmode == 3 && fm_bytes <= 160 * 1024 && h->basis->n_sites <= 16) {
+    if (fast && rmode == 4 && h->hub.fb_ok && fm_bytes <= 160 * 1024 && h->basis->n_sites <= 16) {
+        hipFuncSetAttribute((const void *)k_hub_rows_fb<S, NV>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fm_bytes);
+        hipLaunchKernelGGL((k_hub_rows_fb<S, NV>), dim3((unsigned)grid_r), dim3(threads), fm_bytes, st, a);
+    } else if (fast && (rmode == 3 || rmode == 4) && fm_bytes <= 160 * 1024 && h->basis->n_sites <= 16) {
         hipFuncSetAttribute((const void *)k_hub_rows_fm<S, NV>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)fm_bytes);
         hipLaunchKernelGGL((k_hub_rows_fm<S, NV>), dim3((unsigned)grid_r), dim3(threads), fm_bytes, st, a);
@@ -986,12 +1088,13 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
         const int64_t g_eff = (a.dup + rows - 1) / rows;
         a.item_rows = (int)rows;
         a.groups = (int)g_eff;
-        a.nslab = (int)((a.ddn + cw - 1) / cw);
+        const int cwp = cw > 64 ? 64 : cw;   // this kernel takes up to 64 columns per slab
+        a.nslab = (int)((a.ddn + cwp - 1) / cwp);
         const int64_t grid_p = 8 * g_eff;
         if (grid_p > (int64_t)INT32_MAX || (a.nd && grid_p * 2 * NV > (int64_t)kReduceSlots))
             return fail(HPHI_ERR_UNSUPPORTED, "Hubbard column sweep grid too large");
         a.sched = h->sched.as<unsigned>();
-        switch (cw) {
+        switch (cwp) {
         case 8: launch_cols_p<S, NV, 8>(a, (int)grid_p, st); break;
         case 16: launch_cols_p<S, NV, 16>(a, (int)grid_p, st); break;
         case 32: launch_cols_p<S, NV, 32>(a, (int)grid_p, st); break;
@@ -1008,17 +1111,20 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
                     (long long)h->hub.max_deg[0]);
     a.item_rows = item_rows;
     a.groups = groups;
-    a.nslab = (int)((a.ddn + cw - 1) / cw);
+    // hub_sweep 3: two adjacent columns per lane (even row length only)
+    a.row_cols = (h->sched_cfg.hub_sweep == 3 && NV == 1 && a.ddn % 2 == 0) ? 2 : 1;
+    // 128-column slabs only with two columns per lane (one wave per row)
+    const int cw_eff = (cw == 128 && !(fast && a.row_cols == 2)) ? 64 : cw;
+    a.nslab = (int)((a.ddn + cw_eff - 1) / cw_eff);
     const int64_t grid_c = 8 * (int64_t)groups;
     const int64_t nitems = (int64_t)a.nslab * ((a.dup + item_rows - 1) / item_rows);
     if (a.nd && nitems * 2 * NV > (int64_t)kReduceSlots)
         return fail(HPHI_ERR_UNSUPPORTED, "Hubbard column items beyond the reduction scratch");
     a.sched = h->sched.as<unsigned>();
-    // hub_sweep 3: two adjacent columns per lane (even row length only)
-    a.row_cols = (h->sched_cfg.hub_sweep == 3 && NV == 1 && a.ddn % 2 == 0) ? 2 : 1;
     if (fast) {
-        switch (cw) {
+        switch (cw_eff) {
         case 8: launch_cols_f<S, NV, 8>(a, (int)grid_c, st); break;
+        case 128: launch_cols_f128<S, NV>(a, (int)grid_c, st); break;
         case 16: launch_cols_f<S, NV, 16>(a, (int)grid_c, st); break;
         case 32: launch_cols_f<S, NV, 32>(a, (int)grid_c, st); break;
         default: launch_cols_f<S, NV, 64>(a, (int)grid_c, st); break;
@@ -1026,7 +1132,7 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
         HPHI_HIP(hipGetLastError());
         return HPHI_OK;
     }
-    switch (cw) {
+    switch (cw_eff) {
     case 8: launch_cols_t<S, NV, 8>(a, (int)grid_c, st); break;
     case 16: launch_cols_t<S, NV, 16>(a, (int)grid_c, st); break;
     case 32: launch_cols_t<S, NV, 32>(a, (int)grid_c, st); break;
@@ -1069,6 +1175,9 @@ int launch_hub_mult(hphi_ham *h, const MultArgs &m)
     a.fu_off = h->hub.fu_off.as<uint32_t>();
     a.fu_mid = h->hub.fu_mid.as<uint32_t>();
     a.fu_ent = h->hub.fu_ent.as<uint32_t>();
+    a.fb_base = h->hub.fb_base.as<uint32_t>();
+    a.fb_w = h->hub.fb_w.as<uint32_t>();
+    a.fb_ent = h->hub.fb_ent.as<uint16_t>();
     a.t0 = h->hub.t0;
     const int nv = m.nvec * dtype_lanes(m.dtype);
     const bool f32 = dtype_is_f32(m.dtype);
