@@ -67,10 +67,10 @@ def parse():
 # counters (fetch 2.000, write 1.000). Valid only for the kernel sources and
 # schedule it was taken with; anything else reports null.
 HUB_TRAFFIC = {
-    "sources_sha256": {"kern_hub.hip": "b9af4f85d7892ab229f3f6e66d3d4df30b640f5269bde1ebf166b9a5c0cd3511",
+    "sources_sha256": {"kern_hub.hip": "aa56a6f0a59ccb6e34bb1cd0338de379a7f486ea29c8f84ccf87a13083cbd88b",
                        "kern_common.h": "b031d8c5f79430296feee4fc8cb7e28dc7549a9ad041c9c06a17fec777e3ba0a"},
-    "schedule": {"hub_slab_cols": 64, "hub_groups": 128, "hub_item_rows": 64, "hub_row_cols": 3, "hub_sweep": 3},
-    "fetch_kib": 7.32067e6 + 725759.0, "write_kib": 1.33765e6 + 1.41512e6,
+    "schedule": {"hub_slab_cols": 128, "hub_groups": 128, "hub_item_rows": 32, "hub_row_cols": 4, "hub_sweep": 3},
+    "fetch_kib": 7.93603e+06 + 744872, "write_kib": 1.31738e+06 + 1.42102e+06,
     "fetch_factor": 2.0, "write_factor": 1.0,
 }
 
