@@ -67,10 +67,10 @@ def parse():
 # counters (fetch 2.000, write 1.000). Valid only for the kernel sources and
 # schedule it was taken with; anything else reports null.
 HUB_TRAFFIC = {
-    "sources_sha256": {"kern_hub.hip": "aa56a6f0a59ccb6e34bb1cd0338de379a7f486ea29c8f84ccf87a13083cbd88b",
+    "sources_sha256": {"kern_hub.hip": "d6cb97b3dcad67f61416224b679bb0e47aac72f38d3edb18f6529eb1951bbc5a",
                        "kern_common.h": "b031d8c5f79430296feee4fc8cb7e28dc7549a9ad041c9c06a17fec777e3ba0a"},
     "schedule": {"hub_slab_cols": 128, "hub_groups": 128, "hub_item_rows": 32, "hub_row_cols": 4, "hub_sweep": 3},
-    "fetch_kib": 7.93603e+06 + 744872, "write_kib": 1.31738e+06 + 1.42102e+06,
+    "fetch_kib": 7.93528e+06 + 744846, "write_kib": 1.31738e+06 + 1.42139e+06,
     "fetch_factor": 2.0, "write_factor": 1.0,
 }
 
@@ -388,6 +388,7 @@ def run_ctpq(a, api, ctx, W):
     w = torch.empty_like(v)
     hv_ms = autotune.time_mult(ham, v, w, reps=10)
     del v, w
+    print(f"ctpq: block H*V {hv_ms:.3f} ms", file=sys.stderr, flush=True)
     alg_bytes = 2.0 * dim * nv * 8
     gbs = alg_bytes / (hv_ms * 1e-3) / 1e9
     for _ in range(a.warmup):
@@ -400,11 +401,13 @@ def run_ctpq(a, api, ctx, W):
         s0 = time.perf_counter()
         res = api.ctpq(ham, nv, 6, 0.02, k_steps, storage="c64", seed=1)
         lat.append(time.perf_counter() - s0)
+        print(f"ctpq: run {k} {lat[-1]:.2f} s", file=sys.stderr, flush=True)
     total = time.perf_counter() - t0
     del res["phi"]
     torch.cuda.empty_cache()
     ref = api.ctpq(ham, nv, 6, 0.02, k_steps, storage="c128", seed=1)
     del ref["phi"]
+    print("ctpq: FP64 reference done", file=sys.stderr, flush=True)
     dE = float(np.max(np.abs(res["E"] - ref["E"])))
     dlogN = float(np.max(np.abs(np.cumsum(np.log(res["D"]), 0) - np.cumsum(np.log(ref["D"]), 0))))
     out = base_line(a, gbs, 1e3 * total / a.steps, "c64", wl)

@@ -342,18 +342,19 @@ static int build_hub_fast(hphi_ham *h)
     // hop for all its states (the 64 targets of a slot mostly lie in one
     // group of consecutive states). Lane-major: the slots of one state are
     // consecutive, padded to a multiple of 8, so a lane reads 8 per 16-byte
-    // load. Entry = column | sign << 15; unconnected slots hold dim_dn.
+    // load. Two slots per 32-bit word: columns in bits 0..14 and 15..29,
+    // their fermion signs in bits 31 and 30; unconnected slots hold dim_dn.
     if (dn.dim < 32768) {
         std::vector<uint32_t> fbase(nchunk + 1, 0), fw(nchunk, 0);
-        std::vector<uint16_t> fent;
-        std::vector<std::vector<uint16_t>> slots;
+        std::vector<uint32_t> fent;
+        std::vector<std::vector<uint32_t>> slots;   // column | negative << 16
         uint32_t wmax = 0;
         for (int64_t j = 0; j < nchunk; ++j) {
             const int64_t c0 = j * kSellChunk, c1 = std::min(dn.dim, c0 + kSellChunk);
             slots.clear();
             for (const hphi_hop &hp : h->hops) {
                 bool any = false;
-                std::vector<uint16_t> col(kSellChunk, (uint16_t)dn.dim);
+                std::vector<uint32_t> col(kSellChunk, (uint32_t)dn.dim);
                 for (int64_t c = c0; c < c1; ++c) {
                     const uint64_t st = dn.state_at(c);
                     if (((st >> hp.i) & 1) == ((st >> hp.j) & 1)) continue;
@@ -363,7 +364,7 @@ static int build_hub_fast(hphi_ham *h)
                         (hi - lo > 1) ? (((uint64_t(1) << hi) - 1) & ~((uint64_t(1) << (lo + 1)) - 1)) : 0;
                     const int fs = (__builtin_popcountll(st & between) & 1) ? -1 : 1;
                     const int se = fs * (hp.t < 0 ? -1 : 1);
-                    col[c - c0] = (uint16_t)((uint32_t)dn.rank_of(t) | (se < 0 ? 0x8000u : 0u));
+                    col[c - c0] = (uint32_t)dn.rank_of(t) | (se < 0 ? 0x10000u : 0u);
                     any = true;
                 }
                 if (any) slots.push_back(col);
@@ -372,15 +373,20 @@ static int build_hub_fast(hphi_ham *h)
             fw[j] = w8;
             wmax = std::max(wmax, w8);
             const size_t at = fent.size();
-            fent.resize(at + (size_t)w8 * kSellChunk, (uint16_t)dn.dim);
+            fent.resize(at + (size_t)w8 / 2 * kSellChunk, 0);
             for (int l = 0; l < kSellChunk; ++l)
-                for (size_t k = 0; k < slots.size(); ++k) fent[at + (size_t)l * w8 + k] = slots[k][l];
+                for (uint32_t k = 0; k < w8; k += 2) {
+                    const uint32_t e0 = k < slots.size() ? slots[k][l] : (uint32_t)dn.dim;
+                    const uint32_t e1 = k + 1 < slots.size() ? slots[k + 1][l] : (uint32_t)dn.dim;
+                    fent[at + (size_t)l * (w8 / 2) + k / 2] = (e0 & 0x7FFFu) | ((e1 & 0x7FFFu) << 15) |
+                                                              ((e1 >> 16) << 30) | ((e0 >> 16) << 31);
+                }
             fbase[j + 1] = (uint32_t)fent.size();
         }
-        if (fent.empty()) fent.assign(8, (uint16_t)dn.dim);
+        if (fent.empty()) fent.assign(4, (uint32_t)dn.dim | ((uint32_t)dn.dim << 15));
         HPHI_TRY(upload(h->hub.fb_base, fbase.data(), sizeof(uint32_t) * fbase.size()));
         HPHI_TRY(upload(h->hub.fb_w, fw.data(), sizeof(uint32_t) * fw.size()));
-        HPHI_TRY(upload(h->hub.fb_ent, fent.data(), sizeof(uint16_t) * fent.size()));
+        HPHI_TRY(upload(h->hub.fb_ent, fent.data(), sizeof(uint32_t) * fent.size()));
         h->hub.fb_ok = wmax <= 32;   // the kernel holds up to 32 slots per state
     }
     // up species: CSR, plus entries then minus entries, targets as row

@@ -116,9 +116,10 @@ struct HubTables {
     uint32_t fs_maxw = 0;                    // widest down chunk (plus + minus)
     DevMem fs_base, fs_wp, fs_wm, fs_ent;    // down: chunk base, widths, uint16 entries
     DevMem fu_off, fu_mid, fu_ent;           // up: row offsets, split points, targets
-    // down species, bond-ordered slots (dim_dn < 32768): per chunk of 64
-    // states one slot per hop active in any of them, in hop order; entry =
-    // column | sign << 15, inactive lanes point at the zero slot dim_dn
+    // down species, hop-ordered slots (dim_dn < 32768): per chunk of 64
+    // states one slot per hop active in any of them, in hop order, two slots
+    // per uint32 (15-bit columns, signs in bits 31 and 30); inactive lanes
+    // point at the zero slot dim_dn
     bool fb_ok = false;
     DevMem fb_base, fb_w, fb_ent;
     DevMem coef;     // double [128]: -t per value class

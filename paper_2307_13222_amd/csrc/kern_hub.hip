@@ -53,7 +53,7 @@ struct HubKArgs {
     const uint16_t *fs_ent;
     const uint32_t *fu_off, *fu_mid, *fu_ent;
     const uint32_t *fb_base, *fb_w;
-    const uint16_t *fb_ent;
+    const uint32_t *fb_ent;
     double t0;
 };
 
@@ -468,11 +468,23 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fm(HubKArgs a)
 // hop for all 64 lanes (a lane that the hop does not connect reads the zero
 // slot). The lanes of a wave share their high-half pattern, so one slot's
 // targets lie in one group of consecutive states of the row in LDS and the
-// gathers rarely share a bank; the sign rides in bit 15 of the entry. A
+// gathers rarely share a bank; two slots share a 32-bit word (15-bit
+// columns, signs in bits 31 and 30, applied by flipping the sign bit). A
 // lane's slots are consecutive in memory: up to 32 of them arrive in four
 // 16-byte loads, issued for the next column while the current one gathers.
 // Row metadata (chunk bases, widths, down states) is staged in LDS as in
 // k_hub_rows_fm. Sum order: hops in input order.
+// x with its sign flipped when bit 31 of s31 is set (the other bits of s31
+// are zero).
+__device__ __forceinline__ double flip_sign(double x, uint32_t s31)
+{
+    return __longlong_as_double(__double_as_longlong(x) ^ ((long long)s31 << 32));
+}
+__device__ __forceinline__ float flip_sign(float x, uint32_t s31)
+{
+    return __int_as_float(__float_as_int(x) ^ (int)s31);
+}
+
 template <typename S, int NV>
 __device__ __forceinline__ void fb_gather(const uint4 (&q)[4], uint32_t nq, const S *s_row, S (&acc)[NV])
 {
@@ -481,14 +493,14 @@ __device__ __forceinline__ void fb_gather(const uint4 (&q)[4], uint32_t nq, cons
         if ((uint32_t)g >= nq) break;
         const uint32_t wd[4] = {q[g].x, q[g].y, q[g].z, q[g].w};
 #pragma unroll
-        for (int h = 0; h < 8; ++h) {
-            const uint32_t e = (wd[h >> 1] >> ((h & 1) * 16)) & 0xFFFFu;
-            const uint32_t col = e & 0x7FFFu;
+        for (int p = 0; p < 4; ++p) {
+            const uint32_t wv = wd[p];
+            const uint32_t c0 = wv & 0x7FFFu, c1 = (wv >> 15) & 0x7FFFu;
+            const uint32_t s0 = wv & 0x80000000u, s1 = (wv << 1) & 0x80000000u;
 #pragma unroll
-            for (int j = 0; j < NV; ++j) {
-                const S x = s_row[col * NV + j];
-                acc[j] += (e & 0x8000u) ? -x : x;
-            }
+            for (int j = 0; j < NV; ++j) acc[j] += flip_sign(s_row[c0 * NV + j], s0);
+#pragma unroll
+            for (int j = 0; j < NV; ++j) acc[j] += flip_sign(s_row[c1 * NV + j], s1);
         }
     }
 }
@@ -512,13 +524,13 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fb(HubKArgs a)
     }
     for (int64_t c = threadIdx.x; c < ddn; c += blockDim.x) s_d[c] = (uint16_t)a.dns[c];
     __syncthreads();
-    // entries of column c: 16-byte words at fb_ent + base(c) + lane * width
+    // entries of column c: 16-byte words at fb_ent + base(c) + lane * width / 2
     auto load_col = [&](int64_t c, uint4 (&q)[4], uint32_t &nq) {
         nq = 0;
         if (c >= ddn) return;
         const uint32_t wc = s_w[c >> 6];
         nq = wc >> 3;
-        const uint4 *p = reinterpret_cast<const uint4 *>(a.fb_ent + s_base[c >> 6] + (uint32_t)(c & 63) * wc);
+        const uint4 *p = reinterpret_cast<const uint4 *>(a.fb_ent + s_base[c >> 6] + (uint32_t)(c & 63) * (wc >> 1));
 #pragma unroll
         for (int g = 0; g < 4; ++g)
             if ((uint32_t)g < nq) q[g] = p[g];
@@ -1177,7 +1189,7 @@ int launch_hub_mult(hphi_ham *h, const MultArgs &m)
     a.fu_ent = h->hub.fu_ent.as<uint32_t>();
     a.fb_base = h->hub.fb_base.as<uint32_t>();
     a.fb_w = h->hub.fb_w.as<uint32_t>();
-    a.fb_ent = h->hub.fb_ent.as<uint16_t>();
+    a.fb_ent = h->hub.fb_ent.as<uint32_t>();
     a.t0 = h->hub.t0;
     const int nv = m.nvec * dtype_lanes(m.dtype);
     const bool f32 = dtype_is_f32(m.dtype);
