@@ -180,12 +180,15 @@ def run_lanczos(a, api, ham, dim, iters, storage, wl, kernel, tune_dtype):
     esize = 8.0 if storage == "f64" else 4.0
     alg_bytes = 2 * esize * dim
     gbs = alg_bytes / hv_avg / 1e9
+    # the fused recurrence also reads q_{k-1} in every step but the first
+    alg_epi = esize * dim * (3.0 - a.steps / max(1, hv_n))
     out = base_line(a, gbs, 1e3 * total / a.steps, storage, wl)
     out.update({"hbm_peak_frac": round(gbs / HBM_PEAK_GBS, 4),
                 "lanczos_solves_per_s": round(a.steps / total, 4),
                 "solve_ms_p50": round(1e3 * float(np.percentile(lat, 50)), 3),
                 "solve_ms_p99": round(1e3 * float(np.percentile(lat, 99)), 3),
                 "hv_ms_avg": round(1e3 * hv_avg, 5), "e0": energies[0],
+                "hv_gbs_incl_recurrence_read": round(alg_epi / hv_avg / 1e9, 2),
                 "roofline": roofline(gbs, alg_bytes, kernel,
                                      hub_traffic(wl["schedule"]) if ham.basis.kind == "hubbard" else None)})
     return out, energies

@@ -170,7 +170,11 @@ void hphi_ham_free(hphi_ham *h);
  *                   2 = row-range sweep: hub_groups row ranges per XCD,
  *                   each walking that XCD's slabs in order; 3 = as 1 with
  *                   two adjacent columns per lane (one real vector with an
- *                   even number of down states; otherwise as 1)
+ *                   even number of down states; otherwise as 1); 4 = items
+ *                   (64-column slab, group of up rows sharing their high
+ *                   half) with the group's tile in LDS (one real vector,
+ *                   even number of down states, groups of at most 72 rows;
+ *                   otherwise as 1)
  * Errors: INVALID_ARG (value outside its range). */
 typedef struct {
     int hub_slab_cols;

@@ -404,6 +404,52 @@ static int build_hub_fast(hphi_ham *h)
     HPHI_TRY(upload(h->hub.fu_off, off.data(), sizeof(uint32_t) * off.size()));
     HPHI_TRY(upload(h->hub.fu_mid, mid.data(), sizeof(uint32_t) * mid.size()));
     HPHI_TRY(upload(h->hub.fu_ent, tgt.data(), sizeof(uint32_t) * tgt.size()));
+    // up species by high-half groups: in-group hops (both sites in the low
+    // half) point at a row of the same group, which a group tile in LDS holds
+    {
+        std::vector<uint32_t> grows, goff(up.dim + 1, 0), gcnt(up.dim, 0), gent;
+        const uint64_t nh = uint64_t(1) << up.n_hi;
+        for (uint64_t hh = 0; hh < nh; ++hh)
+            if (up.hi_off[hh + 1] > up.hi_off[hh]) grows.push_back((uint32_t)up.hi_off[hh]);
+        grows.push_back((uint32_t)up.dim);
+        bool ok = true;
+        int max_rows = 0;
+        uint32_t max_ent = 0;
+        for (size_t g = 0; g + 1 < grows.size(); ++g) {
+            const uint32_t g0 = grows[g], g1 = grows[g + 1];
+            max_rows = std::max(max_rows, (int)(g1 - g0));
+            const uint32_t e0 = (uint32_t)gent.size();
+            for (uint32_t r = g0; r < g1; ++r) {
+                goff[r] = (uint32_t)gent.size();
+                uint32_t n[4] = {0, 0, 0, 0};
+                for (int part = 0; part < 4; ++part) {
+                    const std::vector<uint32_t> &lst = (part & 1) ? mi[r] : pl[r];
+                    const bool local = part < 2;
+                    for (uint32_t x : lst) {
+                        const bool in = x >= g0 && x < g1;
+                        if (in != local) continue;
+                        gent.push_back(local ? x - g0 : (uint32_t)((uint64_t)x * (uint64_t)dn.dim));
+                        ++n[part];
+                    }
+                }
+                if (n[0] > 255 || n[1] > 255 || n[2] > 255 || n[3] > 255) ok = false;
+                gcnt[r] = n[0] | (n[1] << 8) | (n[2] << 16) | (n[3] << 24);
+            }
+            max_ent = std::max(max_ent, (uint32_t)gent.size() - e0);
+        }
+        goff[up.dim] = (uint32_t)gent.size();
+        if (gent.empty()) gent.push_back(0);
+        if (ok) {
+            HPHI_TRY(upload(h->hub.fg_rows, grows.data(), sizeof(uint32_t) * grows.size()));
+            HPHI_TRY(upload(h->hub.fg_off, goff.data(), sizeof(uint32_t) * goff.size()));
+            HPHI_TRY(upload(h->hub.fg_cnt, gcnt.data(), sizeof(uint32_t) * gcnt.size()));
+            HPHI_TRY(upload(h->hub.fg_ent, gent.data(), sizeof(uint32_t) * gent.size()));
+            h->hub.fg_ngroups = (int)grows.size() - 1;
+            h->hub.fg_max_rows = max_rows;
+            h->hub.fg_max_ent = max_ent;
+            h->hub.fg_ok = true;
+        }
+    }
     return HPHI_OK;
 }
 
@@ -492,7 +538,7 @@ int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s)
         n.spin_implicit = s->spin_implicit == 1 ? 1 : 0;
     }
     if (s->hub_sweep) {
-        if (s->hub_sweep < 1 || s->hub_sweep > 3) return fail(HPHI_ERR_INVALID_ARG, "hub_sweep %d", s->hub_sweep);
+        if (s->hub_sweep < 1 || s->hub_sweep > 4) return fail(HPHI_ERR_INVALID_ARG, "hub_sweep %d", s->hub_sweep);
         n.hub_sweep = s->hub_sweep;
     }
     h->sched_cfg = n;

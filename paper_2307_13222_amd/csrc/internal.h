@@ -116,6 +116,16 @@ struct HubTables {
     uint32_t fs_maxw = 0;                    // widest down chunk (plus + minus)
     DevMem fs_base, fs_wp, fs_wm, fs_ent;    // down: chunk base, widths, uint16 entries
     DevMem fu_off, fu_mid, fu_ent;           // up: row offsets, split points, targets
+    // up species by groups of rows sharing the high half (rows
+    // fg_rows[g] .. fg_rows[g + 1]): per row four consecutive lists,
+    // in-group plus / in-group minus (local row) and far plus / far minus
+    // (target row * dim_dn); fg_off[r] is the row's first entry, fg_cnt[r]
+    // packs the four lengths (8 bits each)
+    bool fg_ok = false;
+    int fg_ngroups = 0;
+    int fg_max_rows = 0;
+    uint32_t fg_max_ent = 0;                 // most entries of one group
+    DevMem fg_rows, fg_off, fg_cnt, fg_ent;
     // down species, hop-ordered slots (dim_dn < 32768): per chunk of 64
     // states one slot per hop active in any of them, in hop order, two slots
     // per uint32 (15-bit columns, signs in bits 31 and 30); inactive lanes

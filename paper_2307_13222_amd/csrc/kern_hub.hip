@@ -54,6 +54,8 @@ struct HubKArgs {
     const uint32_t *fu_off, *fu_mid, *fu_ent;
     const uint32_t *fb_base, *fb_w;
     const uint32_t *fb_ent;
+    const uint32_t *fg_rows, *fg_off, *fg_cnt, *fg_ent;
+    int fg_ngroups;
     double t0;
 };
 
@@ -821,6 +823,208 @@ __global__ __launch_bounds__(256) void k_hub_cols_f(HubKArgs a)
     }
 }
 
+
+// Columns kernel, group tiles (one real vector, two columns per lane). A work
+// item is (slab of 64 columns, group of up rows sharing their high half, at
+// most kGTileRows rows). The group's tile V[group rows][slab] is staged in
+// LDS: hops with both sites in the low half stay inside the group and read
+// the tile, the others gather neighbour rows from global memory as in
+// k_hub_cols_f. Items come from the per-XCD queues in slab order; the
+// epilogue and the per-item FP64 dot partials are those of k_hub_cols_f.
+// Sum order per state: in-group hops, then the others (plus, then minus).
+constexpr int kGTileRows = 72;
+constexpr int kGEnt = 2560;
+
+template <typename S, bool DOTS>
+__global__ __launch_bounds__(256) void k_hub_cols_g(HubKArgs a)
+{
+    constexpr int CW = 64;
+    __shared__ S s_tile[kGTileRows * CW];
+    __shared__ uint32_t s_ent[kGEnt];
+    __shared__ uint32_t s_off[kGTileRows + 1];
+    __shared__ uint32_t s_cnt[kGTileRows];
+    __shared__ double sh_red[4 * 2 + 8];
+    __shared__ int s_item;
+    __shared__ unsigned s_last;
+    const int home = xcc_id();
+    const char *__restrict__ vb = static_cast<const char *>(a.v);
+    const S *__restrict__ v = static_cast<const S *>(a.v);
+    S *__restrict__ w = static_cast<S *>(a.w);
+    const S *__restrict__ u = static_cast<const S *>(a.u);
+    S *__restrict__ accp = static_cast<S *>(a.acc_out);
+    double c1 = 1.0, c2 = 0.0;
+    if (a.ecoef) {
+        c1 = a.ecoef[0];
+        c2 = a.ecoef[1];
+    }
+    const S c1s = (S)c1, c2s = (S)c2, nt0 = (S)(-a.t0);
+    const int64_t ddn = a.ddn;
+    const int ng = a.fg_ngroups;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lc = 2 * (lane & 31);   // this lane's first column within the slab
+    int q = home, tries = 0;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int it = -1;
+            while (tries < 8) {
+                const int nsl_q = q < a.nslab ? (a.nslab - q + 7) / 8 : 0;
+                const int cand = (int)atomicAdd(&a.sched[q], 1u);
+                if (cand < nsl_q * ng) {
+                    it = q + 8 * cand;
+                    break;
+                }
+                q = (q + 1) & 7;
+                ++tries;
+            }
+            s_item = it;
+        }
+        __syncthreads();
+        const int item = s_item;
+        if (item < 0) break;
+        const int iq = item & 7, idx = item >> 3;
+        const int slab = iq + 8 * (idx / ng);
+        const int grp = idx % ng;
+        const uint32_t g0 = a.fg_rows[grp], g1 = a.fg_rows[grp + 1];
+        const int n = (int)(g1 - g0);
+        const int64_t col0 = (int64_t)slab * CW;
+        for (int i = threadIdx.x; i < n * (CW / 2); i += blockDim.x) {
+            const int row = i >> 5, c = 2 * (i & 31);
+            S x0 = (S)0, x1 = (S)0;
+            if (col0 + c < ddn) {
+                const S *p = v + (size_t)(g0 + row) * ddn + col0 + c;
+                x0 = p[0];
+                x1 = p[1];
+            }
+            s_tile[row * CW + c] = x0;
+            s_tile[row * CW + c + 1] = x1;
+        }
+        {
+            const uint32_t base = a.fg_off[g0];
+            for (int i = threadIdx.x; i <= n; i += blockDim.x) s_off[i] = a.fg_off[g0 + i] - base;
+            for (int i = threadIdx.x; i < n; i += blockDim.x) s_cnt[i] = a.fg_cnt[g0 + i];
+            const uint32_t ne = a.fg_off[g1] - base;
+            for (uint32_t i = threadIdx.x; i < ne; i += blockDim.x) s_ent[i] = a.fg_ent[base + i];
+        }
+        __syncthreads();
+        double d0 = 0.0, d1 = 0.0;
+        const int64_t col = col0 + lc;
+        const uint32_t colb = (uint32_t)col * (uint32_t)sizeof(S);
+        for (int r = wid * 2 + (lane >> 5); r < n; r += 8) {
+            if (col >= ddn) continue;
+            const uint32_t cnt = s_cnt[r];
+            const uint32_t n0 = cnt & 255u, n1 = (cnt >> 8) & 255u, n2 = (cnt >> 16) & 255u, n3 = cnt >> 24;
+            uint32_t e = s_off[r];
+            S ap0 = (S)0, ap1 = (S)0, am0 = (S)0, am1 = (S)0;
+            for (uint32_t k = 0; k < n0; ++k) {
+                const S *t = s_tile + s_ent[e + k] * CW + lc;
+                ap0 += t[0];
+                ap1 += t[1];
+            }
+            e += n0;
+            for (uint32_t k = 0; k < n1; ++k) {
+                const S *t = s_tile + s_ent[e + k] * CW + lc;
+                am0 += t[0];
+                am1 += t[1];
+            }
+            e += n1;
+            uint32_t k = 0;
+            for (; k + 8 <= n2; k += 8) {
+                S x[8][2];
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    load_k<S, 2>(reinterpret_cast<const S *>(vb + ((size_t)s_ent[e + k + t] * sizeof(S) + colb)), x[t]);
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    ap0 += x[t][0];
+                    ap1 += x[t][1];
+                }
+            }
+            for (; k < n2; ++k) {
+                S x[2];
+                load_k<S, 2>(reinterpret_cast<const S *>(vb + ((size_t)s_ent[e + k] * sizeof(S) + colb)), x);
+                ap0 += x[0];
+                ap1 += x[1];
+            }
+            e += n2;
+            k = 0;
+            for (; k + 8 <= n3; k += 8) {
+                S x[8][2];
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    load_k<S, 2>(reinterpret_cast<const S *>(vb + ((size_t)s_ent[e + k + t] * sizeof(S) + colb)), x[t]);
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    am0 += x[t][0];
+                    am1 += x[t][1];
+                }
+            }
+            for (; k < n3; ++k) {
+                S x[2];
+                load_k<S, 2>(reinterpret_cast<const S *>(vb + ((size_t)s_ent[e + k] * sizeof(S) + colb)), x);
+                am0 += x[0];
+                am1 += x[1];
+            }
+            const size_t me = (size_t)(g0 + r) * ddn + col;
+            const S raw[2] = {__builtin_nontemporal_load(&w[me]) + nt0 * (ap0 - am0),
+                              __builtin_nontemporal_load(&w[me + 1]) + nt0 * (ap1 - am1)};
+            S out[2] = {c1s * raw[0], c1s * raw[1]};
+            if (u) {
+                out[0] += c2s * __builtin_nontemporal_load(&u[me]);
+                out[1] += c2s * __builtin_nontemporal_load(&u[me + 1]);
+            }
+            __builtin_nontemporal_store(out[0], &w[me]);
+            __builtin_nontemporal_store(out[1], &w[me + 1]);
+            if (accp) {
+                __builtin_nontemporal_store(__builtin_nontemporal_load(&accp[me]) + out[0], &accp[me]);
+                __builtin_nontemporal_store(__builtin_nontemporal_load(&accp[me + 1]) + out[1], &accp[me + 1]);
+            }
+            if constexpr (DOTS) {
+                const S *mv = s_tile + r * CW + lc;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const double o = a.dot_raw ? (double)raw[j] : (double)out[j];
+                    d0 += (double)mv[j] * o;
+                    d1 += o * o;
+                }
+            }
+        }
+        if constexpr (DOTS) {
+            double vals[2] = {d0, d1};
+            block_sum<2>(vals, sh_red);
+            if (threadIdx.x == 0) {
+                const size_t slot = (size_t)slab * ng + grp;
+                a.red.partial[slot * 2] = vals[0];
+                a.red.partial[slot * 2 + 1] = vals[1];
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        s_last = (atomicAdd(&a.sched[8], 1u) == gridDim.x - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    if constexpr (DOTS) {
+        const size_t nitems = (size_t)a.nslab * ng;
+        for (int j = 0; j < 2; ++j) {
+            double sm = 0.0;
+            for (size_t it = threadIdx.x; it < nitems; it += blockDim.x)
+                sm += __builtin_nontemporal_load(&a.red.partial[it * 2 + j]);
+            double vv[1] = {sm};
+            block_sum<1>(vv, sh_red);
+            if (threadIdx.x == 0) a.red.result[j] = vv[0];
+        }
+    }
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 8; ++i) a.sched[i] = 0u;
+        a.sched[8] = 0u;
+        __threadfence();
+    }
+}
+
 // Columns kernel of the fast path, row-range variant. A work item is
 // (x, g): up rows [g * item_rows, (g + 1) * item_rows) over all slabs
 // x, x + 8, x + 16, ..., swept in order. Items of class x sit in the queue of
@@ -1112,6 +1316,25 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
         case 32: launch_cols_p<S, NV, 32>(a, (int)grid_p, st); break;
         default: launch_cols_p<S, NV, 64>(a, (int)grid_p, st); break;
         }
+        HPHI_HIP(hipGetLastError());
+        return HPHI_OK;
+    }
+    if (fast && h->sched_cfg.hub_sweep == 4 && NV == 1 && h->hub.fg_ok && a.ddn % 2 == 0 &&
+        h->hub.fg_max_rows <= kGTileRows && h->hub.fg_max_ent <= (uint32_t)kGEnt) {
+        // group tiles: items (64-column slab, up group)
+        a.fg_rows = h->hub.fg_rows.as<uint32_t>();
+        a.fg_off = h->hub.fg_off.as<uint32_t>();
+        a.fg_cnt = h->hub.fg_cnt.as<uint32_t>();
+        a.fg_ent = h->hub.fg_ent.as<uint32_t>();
+        a.fg_ngroups = h->hub.fg_ngroups;
+        a.nslab = (int)((a.ddn + 63) / 64);
+        const int64_t nitems = (int64_t)a.nslab * a.fg_ngroups;
+        if (a.nd && nitems * 2 > (int64_t)kReduceSlots)
+            return fail(HPHI_ERR_UNSUPPORTED, "Hubbard group items beyond the reduction scratch");
+        a.sched = h->sched.as<unsigned>();
+        const int grid_g = 8 * groups;
+        if (a.nd) hipLaunchKernelGGL((k_hub_cols_g<S, true>), dim3(grid_g), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_hub_cols_g<S, false>), dim3(grid_g), dim3(256), 0, st, a);
         HPHI_HIP(hipGetLastError());
         return HPHI_OK;
     }
