@@ -273,6 +273,22 @@ int hphi_sqw(hphi_ham *h, const hphi_sqw_opts *o, const void *b_dev, const doubl
     HPHI_TRY(launch_cocg_init(b_dev, r.p, p.p, dim, cgm.p, shm.p, n_shift, o->tol, red, st));
     int it = 0, converged = 0;
     CgDev hc{};
+    HPHI_HIP(hipMemcpyAsync(&hc, cgm.p, sizeof(CgDev), hipMemcpyDeviceToHost, st));
+    HPHI_HIP(hipStreamSynchronize(st));
+    if (hc.bnorm2 == 0.0) {
+        // b = 0: D(z) = 0 for every shift, nothing to iterate
+        for (int j = 0; j < n_shift; ++j) {
+            D_out[2 * j] = D_out[2 * j + 1] = 0.0;
+            if (resid_out) resid_out[j] = 0.0;
+        }
+        if (info) {
+            info->iterations = 0;
+            info->converged = 1;
+            info->max_residual = 0.0;
+            info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        return HPHI_OK;
+    }
     const int check = 8;
     while (it < o->max_iter) {
         MultArgs a{};
