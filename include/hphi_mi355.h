@@ -277,7 +277,7 @@ int hphi_tridiag_lowest(const double *alpha, const double *beta, int n, int k,
 /* ----------------------------------------------------------------- cTPQ -- */
 
 typedef struct {
-    int n_vec;             /* independent random vectors (1..32)             */
+    int n_vec;             /* independent random vectors (1..16)             */
     int n_max;             /* Taylor order of U_c                            */
     double dtau;           /* imaginary-time slice                           */
     int k_steps;           /* steps: beta_k = k dtau, k = 1..k_steps         */
@@ -299,6 +299,34 @@ typedef struct {
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
 int hphi_ctpq(hphi_ham *h, const hphi_ctpq_opts *opts, void *phi_dev,
               double *D_out, double *E_out, double *E2_out);
+
+/* ------------------------------------------------ real-time evolution -- */
+
+typedef struct {
+    int n_vec;             /* complex vectors evolved together (1..16;
+                              Hubbard models: 1)                             */
+    int n_max;             /* Taylor order (1..64; the paper's default 10)    */
+    double dt;             /* time step (finite, nonzero; default 0.01)       */
+    int n_steps;           /* steps: t_k = k dt, k = 0..n_steps               */
+    hphi_dtype storage;    /* HPHI_C128 or HPHI_C64                          */
+    void *stream;
+} hphi_tevol_opts;
+
+/* Real-time evolution by the truncated Taylor series of Sec. 3.4:
+ * psi(t + dt) = sum_{n=0}^{n_max} (-i H dt)^n / n! psi(t), evaluated in
+ * Horner form y <- psi + (-i dt / n) H y (n = n_max .. 1), each order one
+ * block H*V with the complex combination fused into its epilogue.
+ * psi_dev: [dim][n_vec] complex of the storage type, in and out (the state
+ * at t_{n_steps} on return); the caller owns it. Per recorded time t_k
+ * (k = 0..n_steps): norm_out[k * n_vec + j] = <psi_j|psi_j>,
+ * energy_out[k * n_vec + j] = <psi_j|H|psi_j> / <psi_j|psi_j>, and for
+ * Hubbard models docc_out[k] = sum_i <n_i,up n_i,dn> / (N_s <psi|psi>)
+ * (the double occupancy of the paper's quench example). Output arrays are
+ * host memory and nullable. Synchronous.
+ * Errors: INVALID_ARG (ranges above, docc_out for a spin model),
+ * UNSUPPORTED (several vectors with a Hubbard model), OUT_OF_MEMORY, DEVICE. */
+int hphi_time_evolve(hphi_ham *h, const hphi_tevol_opts *opts, void *psi_dev,
+                     double *norm_out, double *energy_out, double *docc_out);
 
 /* --------------------------------------------------- S^zz(q, w) / D(z) -- */
 

@@ -10,6 +10,8 @@ References are to the HPhi update paper (arXiv:2307.13222):
   Sec. 1      Krylov/power methods reduce to repeated H*v; Lanczos.
   Sec. 3.2    dynamical correlation D(z) = <Phi_ex|(z - H)^-1|Phi_ex>,
               S^zz(q, w) with S^z_l and phases e^{iql}, q = 2 pi m / L.
+  Sec. 3.4    real-time evolution psi(t + dt) = sum_{n<=n_max} (-i H dt)^n / n!
+              psi(t); norm, energy and double occupancy as its checks.
   Sec. 3.5.1  TPQ state, random vector uniform on the d_H sphere, cTPQ
               propagator U_c = sum_{n<=n_max} (-dtau H / 2)^n / n!,
               beta_k = k dtau, relative squared norms D_k = N_k / N_{k-1}.
@@ -428,3 +430,41 @@ def lanczos_complex(hv, b: np.ndarray, n_iter: int):
         beta.append(bb)
         v_prev, v = v, w / bb
     return np.array(alpha), np.array(beta[:len(alpha)])
+
+
+def taylor_evolve(hv: Callable[[np.ndarray], np.ndarray], psi0: np.ndarray, n_max: int, dt: float,
+                  n_steps: int, weight: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
+    """Real-time evolution (Sec. 3.4): psi(t + dt) = sum_{n=0}^{n_max}
+    (1/n!) (-i H dt)^n psi(t), summed term by term (t_n = (-i dt / n) H t_{n-1}).
+    Records at t_k = k dt the norm <psi|psi>, the energy <psi|H|psi> / <psi|psi>
+    and, with a diagonal weight w_x (e.g. the count of doubly occupied sites
+    divided by N_s), <psi|w|psi> / <psi|psi>. psi0: (dim,) or (dim, B)."""
+    psi = np.array(psi0, dtype=np.complex128)
+    if psi.ndim == 1:
+        psi = psi[:, None]
+    nrm, en, ob = [], [], []
+    for k in range(n_steps + 1):
+        hp = np.stack([hv(psi[:, j]) for j in range(psi.shape[1])], axis=1)
+        n2 = np.real(np.sum(np.conj(psi) * psi, axis=0))
+        nrm.append(n2)
+        en.append(np.real(np.sum(np.conj(psi) * hp, axis=0)) / n2)
+        if weight is not None:
+            ob.append(np.real(np.sum(weight[:, None] * np.abs(psi) ** 2, axis=0)) / n2)
+        if k == n_steps:
+            break
+        term = psi.copy()
+        new = psi.copy()
+        for n in range(1, n_max + 1):
+            term = np.stack([hv(term[:, j]) for j in range(term.shape[1])], axis=1) * (-1j * dt / n)
+            new = new + term
+        psi = new
+    out = {"norm": np.array(nrm), "energy": np.array(en), "psi": psi}
+    if weight is not None:
+        out["obs"] = np.array(ob)
+    return out
+
+
+def hubbard_double_occupancy_weight(ups: np.ndarray, dns: np.ndarray, n_sites: int) -> np.ndarray:
+    """Diagonal of (1/N_s) sum_i n_i,up n_i,dn on the up-major product basis."""
+    cnt = np.array([[bin(int(u) & int(d)).count("1") for d in dns] for u in ups], dtype=np.float64)
+    return cnt.reshape(-1) / n_sites

@@ -46,6 +46,11 @@ class CtpqOpts(C.Structure):
                 ("phi0_dev", C.c_void_p), ("stream", C.c_void_p)]
 
 
+class TevolOpts(C.Structure):
+    _fields_ = [("n_vec", C.c_int), ("n_max", C.c_int), ("dt", C.c_double), ("n_steps", C.c_int),
+                ("storage", C.c_int), ("stream", C.c_void_p)]
+
+
 class Schedule(C.Structure):
     _fields_ = [("hub_slab_cols", C.c_int), ("hub_groups", C.c_int), ("hub_item_rows", C.c_int),
                 ("hub_row_cols", C.c_int), ("spin_per_cu", C.c_int), ("spin_implicit", C.c_int),
@@ -91,6 +96,7 @@ SIGNATURES = {
     "hphi_tridiag_lowest": (I, [PD, PD, I, I, PD, PD]),
     "hphi_lanczos_batch": (I, [C.POINTER(BatchItem), I, P]),
     "hphi_ctpq": (I, [P, C.POINTER(CtpqOpts), P, PD, PD, PD]),
+    "hphi_time_evolve": (I, [P, C.POINTER(TevolOpts), P, PD, PD, PD]),
     "hphi_szq": (I, [P, PD, P, P, P]),
     "hphi_sqw": (I, [P, C.POINTER(SqwOpts), P, PD, PD, I, PD, PD, C.POINTER(SqwInfo)]),
 }

@@ -300,6 +300,33 @@ def ctpq(ham: Hamiltonian, n_vec: int, n_max: int, dtau: float, k_steps: int,
     return {"beta": dtau * np.arange(k_steps + 1), "D": D, "E": E, "E2": E2, "phi": phi}
 
 
+def time_evolve(ham: Hamiltonian, psi, n_steps: int, dt: float = 0.01, n_max: int = 10,
+                double_occupancy: bool = False, stream=None) -> Dict:
+    """Real-time evolution of psi (device tensor [dim] or [dim, n_vec],
+    complex128 or complex64, updated in place) by the truncated Taylor series;
+    returns per recorded time norms, energies and (Hubbard) double occupancy."""
+    _dev_check(psi, "psi")
+    torch = _torch()
+    if psi.dtype not in (torch.complex128, torch.complex64):
+        raise HphiError("psi must be complex128 or complex64")
+    nv = 1 if psi.dim() == 1 else int(psi.shape[1])
+    o = L.TevolOpts()
+    o.n_vec, o.n_max, o.dt, o.n_steps = nv, n_max, dt, n_steps
+    o.storage = L.C128 if psi.dtype == torch.complex128 else L.C64
+    o.stream = _stream_ptr(stream)
+    nrm = np.zeros((n_steps + 1) * nv)
+    en = np.zeros((n_steps + 1) * nv)
+    dc = np.zeros(n_steps + 1) if double_occupancy else None
+    _check(L.lib().hphi_time_evolve(ham.h, C.byref(o), psi.data_ptr(), nrm.ctypes.data_as(L.PD),
+                                    en.ctypes.data_as(L.PD),
+                                    dc.ctypes.data_as(L.PD) if dc is not None else None), "hphi_time_evolve")
+    out = {"norm": nrm.reshape(n_steps + 1, nv), "energy": en.reshape(n_steps + 1, nv),
+           "t": dt * np.arange(n_steps + 1)}
+    if dc is not None:
+        out["double_occupancy"] = dc
+    return out
+
+
 def szq(ham: Hamiltonian, q: float, psi, stream=None):
     """b = sum_l e^{i q x_l} S^z_l psi, x_l from the model's site_x."""
     torch = _torch()

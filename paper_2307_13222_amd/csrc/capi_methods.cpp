@@ -149,6 +149,105 @@ int hphi_ctpq(hphi_ham *h, const hphi_ctpq_opts *o, void *phi_dev, double *D_out
     return HPHI_OK;
 }
 
+int hphi_time_evolve(hphi_ham *h, const hphi_tevol_opts *o, void *psi_dev, double *norm_out, double *energy_out,
+                     double *docc_out)
+{
+    if (!h || !o || !psi_dev) return fail(HPHI_ERR_INVALID_ARG, "null argument");
+    if (o->n_vec < 1 || o->n_vec > 16) return fail(HPHI_ERR_INVALID_ARG, "n_vec %d outside [1, 16]", o->n_vec);
+    if (o->n_max < 1 || o->n_max > 64) return fail(HPHI_ERR_INVALID_ARG, "n_max %d outside [1, 64]", o->n_max);
+    if (o->n_steps < 0 || !std::isfinite(o->dt) || o->dt == 0.0)
+        return fail(HPHI_ERR_INVALID_ARG, "n_steps / dt");
+    if (o->storage != HPHI_C128 && o->storage != HPHI_C64)
+        return fail(HPHI_ERR_INVALID_ARG, "time evolution storage must be C128 or C64");
+    if (h->kind == 1 && o->n_vec != 1)
+        return fail(HPHI_ERR_UNSUPPORTED, "Hubbard time evolution runs one vector per call");
+    if (docc_out && h->kind != 1) return fail(HPHI_ERR_INVALID_ARG, "double occupancy needs a Hubbard model");
+    DeviceGuard g(h->basis->ctx->device);
+    hipStream_t st = (hipStream_t)o->stream;
+    const int dt = o->storage, nv = o->n_vec, nl = 2 * nv;
+    const int64_t dim = h->basis->dim;
+    const size_t bytes = (size_t)dim * nl * dtype_size(dt);
+    DevMem y1, y2, scal, res_e, res_n, res_d;
+    HPHI_TRY(y1.alloc(bytes));
+    HPHI_TRY(y2.alloc(bytes));
+    HPHI_TRY(scal.alloc(sizeof(double) * 4 * ((size_t)o->n_max + 1)));
+    HPHI_TRY(res_e.alloc(sizeof(double) * 2 * 64));
+    HPHI_TRY(res_n.alloc(sizeof(double) * 2 * 64));
+    HPHI_TRY(res_d.alloc(sizeof(double) * 8));
+    // Horner order n: y <- psi + (-i dt / n) H y, i.e. c1 = -i dt / n, c2 = 1
+    std::vector<double> cf(4 * ((size_t)o->n_max + 1), 0.0);
+    for (int n = 1; n <= o->n_max; ++n) {
+        cf[4 * n + 0] = 0.0;
+        cf[4 * n + 1] = 1.0;
+        cf[4 * n + 2] = -o->dt / n;
+        cf[4 * n + 3] = 0.0;
+    }
+    HPHI_HIP(hipMemcpy(scal.p, cf.data(), sizeof(double) * cf.size(), hipMemcpyHostToDevice));
+    const double *d_coef = scal.as<double>();
+    void *A = psi_dev;
+    void *Y[2] = {y1.p, y2.p};
+    std::vector<double> he(nl), hn(nl);
+    double hd = 0.0;
+    const int K = o->n_steps;
+    for (int k = 0; k <= K; ++k) {
+        // observables of the state at t_k = k dt
+        HPHI_TRY(launch_dots(dt, nl, dim, A, A, reduce_at(h, res_n.as<double>()), 1, st));
+        if (docc_out) HPHI_TRY(launch_docc(h, dt, A, reduce_at(h, res_d.as<double>()), st));
+        if (k == K) {
+            MultArgs a{};
+            a.dtype = dt;
+            a.nvec = nv;
+            a.v = A;
+            a.w = Y[0];
+            a.dots = 1;
+            a.dot_raw = 1;
+            a.red = reduce_at(h, res_e.as<double>());
+            a.stream = st;
+            HPHI_TRY(launch_mult(h, a));
+        } else {
+            const void *src = A;
+            int yb = 0;
+            for (int n = o->n_max; n >= 1; --n) {
+                MultArgs a{};
+                a.dtype = dt;
+                a.nvec = nv;
+                a.v = src;
+                a.w = Y[yb];
+                a.u = A;
+                a.coef = d_coef + 4 * n;
+                a.coef_cplx = 1;
+                a.stream = st;
+                if (n == o->n_max) {
+                    a.dots = 1;     // <psi, H psi> rides on the first product
+                    a.dot_raw = 1;
+                    a.red = reduce_at(h, res_e.as<double>());
+                } else {
+                    a.red = reduce_at(h, h->red_result.as<double>());
+                }
+                HPHI_TRY(launch_mult(h, a));
+                src = Y[yb];
+                yb ^= 1;
+            }
+        }
+        HPHI_HIP(hipMemcpyAsync(he.data(), res_e.p, sizeof(double) * nl, hipMemcpyDeviceToHost, st));
+        HPHI_HIP(hipMemcpyAsync(hn.data(), res_n.p, sizeof(double) * nl, hipMemcpyDeviceToHost, st));
+        if (docc_out) HPHI_HIP(hipMemcpyAsync(&hd, res_d.p, sizeof(double), hipMemcpyDeviceToHost, st));
+        if (k < K) {
+            // the order-1 product holds psi(t_{k+1}); copy it into the caller's buffer
+            const void *out = (o->n_max % 2 == 1) ? Y[0] : Y[1];
+            HPHI_HIP(hipMemcpyAsync(A, out, bytes, hipMemcpyDeviceToDevice, st));
+        }
+        HPHI_HIP(hipStreamSynchronize(st));
+        for (int j = 0; j < nv; ++j) {
+            const double nrm = hn[2 * j] + hn[2 * j + 1];
+            if (norm_out) norm_out[(size_t)k * nv + j] = nrm;
+            if (energy_out) energy_out[(size_t)k * nv + j] = (he[2 * j] + he[2 * j + 1]) / nrm;
+        }
+        if (docc_out) docc_out[k] = hd / (hn[0] + hn[1]) / h->basis->n_sites;
+    }
+    return HPHI_OK;
+}
+
 int hphi_lanczos_batch(hphi_batch_item *items, int n, void *stream)
 {
     if (!items || n < 1) return fail(HPHI_ERR_INVALID_ARG, "empty batch");

@@ -195,6 +195,7 @@ struct MultArgs {
     int dot_raw;        // x = H v (1) or x = the epilogue output w (0)
     Reduce red;
     hipStream_t stream;
+    int coef_cplx;      // coef = [c1 re, c2 re, c1 im, c2 im] applied to complex pairs
 };
 int launch_spin_mult(hphi_ham *h, const MultArgs &a);
 int launch_spin_mult_implicit(hphi_ham *h, const MultArgs &a);
@@ -219,6 +220,7 @@ int launch_axpy_lanes(int dtype, int nlanes, int64_t rows, void *y, const void *
 int launch_copy_cast(int dst_dtype, void *dst, int src_dtype, const void *src, int64_t n,
                      hipStream_t st);
 int launch_trace(hphi_ham *h, Reduce red, hipStream_t st);
+int launch_docc(hphi_ham *h, int dtype, const void *psi, Reduce red, hipStream_t st);
 int launch_szq(hphi_ham *h, const double *phase_dev, const void *psi, void *b, hipStream_t st);
 
 // Lanczos device scalars and kernels

@@ -87,6 +87,36 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t i)
 
 __device__ __forceinline__ double u53(uint64_t z) { return (double)(z >> 11) * (1.0 / 9007199254740992.0); }
 
+// Fused epilogue out = c1 * raw + c2 * u over K scalars of one state. Real
+// coefficients (cplx = 0), or complex ones applied to (re, im) pairs
+// (cplx = 1, K even): coef = [c1 re, c2 re, c1 im, c2 im]. u may be null.
+template <typename S, int K>
+__device__ __forceinline__ void epilogue(const S (&raw)[K], const S *uu, int cplx, const double *coef,
+                                         S (&out)[K])
+{
+    const S c1r = coef ? (S)coef[0] : (S)1, c2r = coef ? (S)coef[1] : (S)0;
+    if constexpr (K % 2 == 0) {
+        if (cplx) {
+            const S c1i = (S)coef[2], c2i = (S)coef[3];
+#pragma unroll
+            for (int k = 0; k < K; k += 2) {
+                out[k] = c1r * raw[k] - c1i * raw[k + 1];
+                out[k + 1] = c1r * raw[k + 1] + c1i * raw[k];
+                if (uu) {
+                    out[k] += c2r * uu[k] - c2i * uu[k + 1];
+                    out[k + 1] += c2r * uu[k + 1] + c2i * uu[k];
+                }
+            }
+            return;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        out[k] = c1r * raw[k];
+        if (uu) out[k] += c2r * uu[k];
+    }
+}
+
 template <typename T> struct VecOf;
 template <> struct VecOf<double> { using t2 = double2; };
 template <> struct VecOf<float> { using t2 = float2; };

@@ -57,6 +57,7 @@ struct HubKArgs {
     const uint32_t *fg_rows, *fg_off, *fg_cnt, *fg_ent;
     int fg_ngroups;
     double t0;
+    int coef_cplx;
 };
 
 template <typename S>
@@ -255,13 +256,20 @@ __global__ __launch_bounds__(256) void k_hub_cols(HubKArgs a)
             }
             S out[NV], raw[NV];
 #pragma unroll
-            for (int j = 0; j < NV; ++j) {
-                raw[j] = acc[j];
-                out[j] = c1s * acc[j];
-            }
-            if (u) {
+            for (int j = 0; j < NV; ++j) raw[j] = acc[j];
+            if (a.coef_cplx) {
+                S uu[NV];
+                if (u)
 #pragma unroll
-                for (int j = 0; j < NV; ++j) out[j] += c2s * __builtin_nontemporal_load(&u[me * NV + j]);
+                    for (int j = 0; j < NV; ++j) uu[j] = __builtin_nontemporal_load(&u[me * NV + j]);
+                epilogue<S, NV>(raw, u ? uu : nullptr, 1, a.ecoef, out);
+            } else {
+#pragma unroll
+                for (int j = 0; j < NV; ++j) out[j] = c1s * acc[j];
+                if (u) {
+#pragma unroll
+                    for (int j = 0; j < NV; ++j) out[j] += c2s * __builtin_nontemporal_load(&u[me * NV + j]);
+                }
             }
 #pragma unroll
             for (int j = 0; j < NV; ++j) __builtin_nontemporal_store(out[j], &w[me * NV + j]);
@@ -758,13 +766,20 @@ __global__ __launch_bounds__(256) void k_hub_cols_f(HubKArgs a)
             }
             S out[K], raw[K];
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
-                raw[j] = __builtin_nontemporal_load(&w[me * NV + j]) + nt0 * (ap[j] - am[j]);
-                out[j] = c1s * raw[j];
-            }
-            if (u) {
+            for (int j = 0; j < K; ++j) raw[j] = __builtin_nontemporal_load(&w[me * NV + j]) + nt0 * (ap[j] - am[j]);
+            if (a.coef_cplx) {
+                S uu[K];
+                if (u)
 #pragma unroll
-                for (int j = 0; j < K; ++j) out[j] += c2s * __builtin_nontemporal_load(&u[me * NV + j]);
+                    for (int j = 0; j < K; ++j) uu[j] = __builtin_nontemporal_load(&u[me * NV + j]);
+                epilogue<S, K>(raw, u ? uu : nullptr, 1, a.ecoef, out);
+            } else {
+#pragma unroll
+                for (int j = 0; j < K; ++j) out[j] = c1s * raw[j];
+                if (u) {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) out[j] += c2s * __builtin_nontemporal_load(&u[me * NV + j]);
+                }
             }
 #pragma unroll
             for (int j = 0; j < K; ++j) __builtin_nontemporal_store(out[j], &w[me * NV + j]);
@@ -1292,7 +1307,7 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
     // column kernel, geometry from the Hamiltonian's schedule
     const int cw = h->sched_cfg.hub_slab_cols;
     const int groups = h->sched_cfg.hub_groups;
-    if (fast && h->sched_cfg.hub_sweep == 2) {
+    if (fast && h->sched_cfg.hub_sweep == 2 && !a.coef_cplx) {
         // persistent sweep: hub_groups row ranges, each within the staging arrays
         int64_t rows = (a.dup + groups - 1) / groups;
         if (rows > kColsRows) rows = kColsRows;
@@ -1319,7 +1334,7 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
         HPHI_HIP(hipGetLastError());
         return HPHI_OK;
     }
-    if (fast && h->sched_cfg.hub_sweep == 4 && NV == 1 && h->hub.fg_ok && a.ddn % 2 == 0 &&
+    if (fast && h->sched_cfg.hub_sweep == 4 && NV == 1 && !a.coef_cplx && h->hub.fg_ok && a.ddn % 2 == 0 &&
         h->hub.fg_max_rows <= kGTileRows && h->hub.fg_max_ent <= (uint32_t)kGEnt) {
         // group tiles: items (64-column slab, up group)
         a.fg_rows = h->hub.fg_rows.as<uint32_t>();
@@ -1414,6 +1429,7 @@ int launch_hub_mult(hphi_ham *h, const MultArgs &m)
     a.fb_w = h->hub.fb_w.as<uint32_t>();
     a.fb_ent = h->hub.fb_ent.as<uint32_t>();
     a.t0 = h->hub.t0;
+    a.coef_cplx = m.coef_cplx;
     const int nv = m.nvec * dtype_lanes(m.dtype);
     const bool f32 = dtype_is_f32(m.dtype);
     if (nv == 1) return f32 ? launch_hub_t<float, 1>(h, a, m.stream) : launch_hub_t<double, 1>(h, a, m.stream);

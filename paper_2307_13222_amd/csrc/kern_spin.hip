@@ -31,6 +31,7 @@ struct SpinKArgs {
     int nd;
     int dot_raw;   // dots of H v itself (1) or of the epilogue output (0)
     Reduce red;
+    int coef_cplx;
 };
 
 // Load NV contiguous scalars at p (p aligned to min(16, NV * sizeof(S))).
@@ -142,15 +143,20 @@ __global__ __launch_bounds__(kBlock) void k_spin_hv(SpinKArgs a)
         load_lanes<S, NV>(v + (size_t)r * NV, me);
         S hv[NV], out[NV];
 #pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            hv[j] = acc[j] + diag * me[j];
-            out[j] = c1s * hv[j];
-        }
-        if (u) {
+        for (int j = 0; j < NV; ++j) hv[j] = acc[j] + diag * me[j];
+        if (a.coef_cplx) {
             S uu[NV];
-            load_lanes<S, NV>(u + (size_t)r * NV, uu);
+            if (u) load_lanes<S, NV>(u + (size_t)r * NV, uu);
+            epilogue<S, NV>(hv, u ? uu : nullptr, 1, a.coef, out);
+        } else {
 #pragma unroll
-            for (int j = 0; j < NV; ++j) out[j] += c2s * uu[j];
+            for (int j = 0; j < NV; ++j) out[j] = c1s * hv[j];
+            if (u) {
+                S uu[NV];
+                load_lanes<S, NV>(u + (size_t)r * NV, uu);
+#pragma unroll
+                for (int j = 0; j < NV; ++j) out[j] += c2s * uu[j];
+            }
         }
         store_lanes<S, NV>(w + (size_t)r * NV, out);
         if (accp) {
@@ -247,6 +253,7 @@ int launch_spin_mult(hphi_ham *h, const MultArgs &m)
     a.nd = m.dots;
     a.dot_raw = m.dot_raw;
     a.red = m.red;
+    a.coef_cplx = m.coef_cplx;
     const int nv = m.nvec * dtype_lanes(m.dtype);
     size_t tab = sizeof(uint32_t) * ((size_t(1) << s.n_lo) + (size_t(1) << s.n_hi));
     bool lds = tab <= 96 * 1024;

@@ -459,6 +459,47 @@ __global__ __launch_bounds__(kBlock) void k_trace_hub(const uint32_t *ups, const
     grid_finish(blk, 1, red, sh);
 }
 
+// Double occupancy weight sum_x |psi_x|^2 * #(sites with both spins) of one
+// complex vector (S = double or float, (re, im) interleaved), FP64 sum.
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_docc_hub(const uint32_t *ups, const uint32_t *dns, int64_t dup,
+                                                     int64_t ddn, const S *psi, Reduce red)
+{
+    __shared__ double sh[kBlock / kWave];
+    __shared__ double blk[1];
+    double acc = 0.0;
+    const int64_t n = dup * ddn;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int nd = __builtin_popcount(ups[t / ddn] & dns[t % ddn]);
+        const double re = (double)psi[2 * t], im = (double)psi[2 * t + 1];
+        acc += (double)nd * (re * re + im * im);
+    }
+    double v[1] = {acc};
+    block_sum<1>(v, sh);
+    if (threadIdx.x == 0) blk[0] = v[0];
+    __syncthreads();
+    grid_finish(blk, 1, red, sh);
+}
+
+int launch_docc(hphi_ham *h, int dtype, const void *psi, Reduce red, hipStream_t st)
+{
+    const hphi_basis *b = h->basis;
+    if (h->kind != 1) return fail(HPHI_ERR_UNSUPPORTED, "double occupancy is defined for Hubbard models");
+    if (dtype == HPHI_C128)
+        hipLaunchKernelGGL(k_docc_hub<double>, dim3(grid_for(b->dim, 4)), dim3(kBlock), 0, st,
+                           b->sp[0].d_states.as<uint32_t>(), b->sp[1].d_states.as<uint32_t>(), b->sp[0].dim,
+                           b->sp[1].dim, static_cast<const double *>(psi), red);
+    else if (dtype == HPHI_C64)
+        hipLaunchKernelGGL(k_docc_hub<float>, dim3(grid_for(b->dim, 4)), dim3(kBlock), 0, st,
+                           b->sp[0].d_states.as<uint32_t>(), b->sp[1].d_states.as<uint32_t>(), b->sp[0].dim,
+                           b->sp[1].dim, static_cast<const float *>(psi), red);
+    else
+        return fail(HPHI_ERR_INVALID_ARG, "double occupancy takes a complex vector");
+    HPHI_HIP(hipGetLastError());
+    return HPHI_OK;
+}
+
 int launch_trace(hphi_ham *h, Reduce red, hipStream_t st)
 {
     const hphi_basis *b = h->basis;

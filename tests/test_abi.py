@@ -22,7 +22,8 @@ def header_functions():
 def test_header_declares_expected_calls():
     names = header_functions()
     for must in ["hphi_init", "hphi_basis_spin", "hphi_basis_hubbard", "hphi_ham_spin",
-                 "hphi_ham_hubbard", "hphi_mult", "hphi_lanczos", "hphi_ctpq", "hphi_sqw"]:
+                 "hphi_ham_hubbard", "hphi_mult", "hphi_lanczos", "hphi_ctpq", "hphi_sqw",
+                 "hphi_time_evolve"]:
         assert must in names
 
 

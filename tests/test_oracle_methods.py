@@ -206,3 +206,66 @@ def test_uniform_and_gaussian_statistics():
     g = O.splitmix_complex_gaussian(9, 100000)
     assert abs(np.mean(np.abs(g) ** 2) - 2.0) < 0.03
     assert abs(np.mean(g.real)) < 0.01 and abs(np.mean(g.imag)) < 0.01
+
+
+# --------------------------------------------------------- time evolution --
+
+def _small_hubbard():
+    m = W.hubbard_chain(6, 1.0, 8.0)
+    ups, dns = O.hubbard_basis(6, 3, 3)
+    Hs = O.hubbard_sparse(m, ups, dns).toarray()
+    return m, ups, dns, Hs
+
+
+def test_taylor_evolve_matches_dense_exponential():
+    # exact propagator exp(-i H t) from the full spectrum; the truncated
+    # series differs per step by at most (|H| dt)^(n_max+1) / (n_max+1)!
+    m, ups, dns, Hd = _small_hubbard()
+    ev, U = np.linalg.eigh(Hd)
+    rng = np.random.default_rng(4)
+    psi0 = rng.normal(size=len(Hd)) + 1j * rng.normal(size=len(Hd))
+    psi0 /= np.linalg.norm(psi0)
+    dt, n_steps = 0.02, 25
+    for n_max, tol in [(10, 1e-9), (4, None)]:
+        o = O.taylor_evolve(lambda x: Hd @ x, psi0, n_max, dt, n_steps)
+        exact = U @ (np.exp(-1j * ev * dt * n_steps) * (U.conj().T @ psi0))
+        err = np.linalg.norm(o["psi"][:, 0] - exact)
+        hn = float(np.max(np.abs(ev)))
+        bound = n_steps * (hn * dt) ** (n_max + 1) / math.factorial(n_max + 1) * np.exp(hn * dt)
+        assert err <= bound + 1e-13
+        if tol is not None:
+            assert err < tol
+
+
+def test_taylor_evolve_conserves_norm_and_energy():
+    m, ups, dns, Hd = _small_hubbard()
+    rng = np.random.default_rng(5)
+    psi0 = rng.normal(size=len(Hd)) + 1j * rng.normal(size=len(Hd))
+    o = O.taylor_evolve(lambda x: Hd @ x, psi0, 10, 0.01, 40)
+    assert np.max(np.abs(o["norm"] / o["norm"][0] - 1)) < 1e-12
+    assert np.max(np.abs(o["energy"] - o["energy"][0])) < 1e-12
+    # a too short series visibly breaks unitarity
+    o2 = O.taylor_evolve(lambda x: Hd @ x, psi0, 2, 0.05, 40)
+    assert np.max(np.abs(o2["norm"] / o2["norm"][0] - 1)) > 1e-6
+
+
+def test_taylor_evolve_diagonal_hamiltonian_phases():
+    # t = 0 (no hopping): every configuration only picks up exp(-i E_x t)
+    m = W.hubbard_chain(4, 0.0, 3.0)
+    ups, dns = O.hubbard_basis(4, 2, 2)
+    rng = np.random.default_rng(6)
+    psi0 = rng.normal(size=len(ups) * len(dns)) + 0j
+    diag = O.hubbard_hv(m, ups, dns, np.ones(len(psi0)))
+    o = O.taylor_evolve(lambda x: O.hubbard_hv(m, ups, dns, x), psi0, 12, 0.01, 30)
+    assert np.max(np.abs(o["psi"][:, 0] - np.exp(-1j * diag * 0.3) * psi0)) < 1e-12
+
+
+def test_double_occupancy_weight_atomic_limits():
+    ups, dns = O.hubbard_basis(4, 2, 2)
+    w = O.hubbard_double_occupancy_weight(ups, dns, 4)
+    # the all-doubly-occupied pattern exists only when up == down
+    assert w.max() == 0.5 and w.min() == 0.0
+    # uniform superposition: mean over states of (#doubles) / N_s
+    m = W.hubbard_chain(4, 0.0, 1.0)
+    tr = np.sum(O.hubbard_hv(m, ups, dns, np.ones(len(w))))
+    assert abs(np.mean(w) - tr / len(w) / 4) < 1e-15
