@@ -460,7 +460,13 @@ def run_ctpq(a, api, ctx, W):
     print("ctpq: FP64 reference done", file=sys.stderr, flush=True)
     dE = float(np.max(np.abs(res["E"] - ref["E"])))
     dlogN = float(np.max(np.abs(np.cumsum(np.log(res["D"]), 0) - np.cumsum(np.log(ref["D"]), 0))))
+    from paper_2307_13222_amd import thermo
+    th = thermo.tpq_thermo(res["beta"], res["D"], res["E"], res["E2"], dim, 28, n_boot=200)
     out = base_line(a, gbs, 1e3 * total / a.steps, "c64", wl)
+    out.update({"thermo_final_beta": {"beta": float(th["beta"][-1]),
+                                      "E_per_site": [float(th["E"][-1]), float(th["E_err"][-1])],
+                                      "C_per_site": [float(th["C"][-1]), float(th["C_err"][-1])],
+                                      "S_per_site": [float(th["S"][-1]), float(th["S_err"][-1])]}})
     out.update({"hbm_peak_frac": round(gbs / HBM_PEAK_GBS, 4), "block_hv_ms": round(hv_ms, 4),
                 "ctpq_steps_per_s": round(a.steps * k_steps / total, 3),
                 "ctpq_run_ms_p50": round(1e3 * float(np.percentile(lat, 50)), 3),

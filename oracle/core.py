@@ -468,3 +468,21 @@ def hubbard_double_occupancy_weight(ups: np.ndarray, dns: np.ndarray, n_sites: i
     """Diagonal of (1/N_s) sum_i n_i,up n_i,dn on the up-major product basis."""
     cnt = np.array([[bin(int(u) & int(d)).count("1") for d in dns] for u in ups], dtype=np.float64)
     return cnt.reshape(-1) / n_sites
+
+
+def canonical_thermo(evals: np.ndarray, betas: np.ndarray, n_sites: int) -> Dict[str, np.ndarray]:
+    """Exact canonical energy, specific heat and entropy per site from a full
+    spectrum (the quantities the TPQ states estimate, Sec. 3.5.1):
+    Z = sum_n e^{-beta E_n}, E = <E>, C = beta^2 (<E^2> - <E>^2), S = ln Z + beta E."""
+    ev = np.asarray(evals, dtype=np.float64)
+    e0 = ev.min()
+    out = {"E": [], "C": [], "S": []}
+    for b in np.asarray(betas, dtype=np.float64):
+        wts = np.exp(-b * (ev - e0))
+        z = wts.sum()
+        e = float((wts * ev).sum() / z)
+        e2 = float((wts * ev * ev).sum() / z)
+        out["E"].append(e / n_sites)
+        out["C"].append(b * b * (e2 - e * e) / n_sites)
+        out["S"].append((np.log(z) - b * e0 + b * e) / n_sites)
+    return {k: np.array(v) for k, v in out.items()}
