@@ -328,6 +328,41 @@ typedef struct {
 int hphi_time_evolve(hphi_ham *h, const hphi_tevol_opts *opts, void *psi_dev,
                      double *norm_out, double *energy_out, double *docc_out);
 
+/* --------------------------------------------------------------- LOBPCG -- */
+
+typedef struct {
+    int n_eig;             /* M: lowest eigenpairs wanted (1..32, 3M <= dim)  */
+    int max_iter;
+    double tol;            /* stop when every |H Phi_n - E_n Phi_n| < tol     */
+    uint64_t seed;         /* start vector n: SplitMix64 uniform, seed + n    */
+    int precond;           /* 1: point-Jacobi r <- r / (H_xx - e_shift)       */
+    double e_shift;        /* shift of the preconditioner; 0: a lower bound of
+                              the spectrum from the couplings                */
+    void *stream;
+} hphi_lobpcg_opts;
+
+typedef struct {
+    int iterations;
+    int converged;
+    int64_t hv_calls;
+    double seconds;
+} hphi_lobpcg_info;
+
+/* Lowest eigenpairs by the locally optimal block preconditioned conjugate
+ * gradient method (Sec. 3.3): subspace (r, Phi, p) of 3M vectors, H_sub =
+ * V^T H V and O_sub = V^T V from device block Gram products, the
+ * generalized eigenproblem of size 3M solved on the host (near-null
+ * directions of O_sub dropped), updates Phi = V phi, p = (r, 0, p) phi as
+ * block linear combinations on the device. The point-Jacobi preconditioner
+ * needs the diagonal: stored-list spin bases and Hubbard bases.
+ * energies_out[M] ascending Ritz values, resid_out[M] (nullable) residual
+ * norms, vecs_dev (nullable, device, M * dim FP64, caller-owned) the
+ * normalized eigenvectors one after another. Synchronous.
+ * Errors: INVALID_ARG (ranges), UNSUPPORTED (preconditioner without a stored
+ * basis; subspace rank below M), OUT_OF_MEMORY, DEVICE. */
+int hphi_lobpcg(hphi_ham *h, const hphi_lobpcg_opts *opts, double *energies_out,
+                double *resid_out, void *vecs_dev, hphi_lobpcg_info *info);
+
 /* --------------------------------------------------- S^zz(q, w) / D(z) -- */
 
 /* Excitation b = sum_l e^{i q x_l} S^z_l psi for a spin basis (Sec. 3.2):

@@ -51,6 +51,16 @@ class TevolOpts(C.Structure):
                 ("storage", C.c_int), ("stream", C.c_void_p)]
 
 
+class LobpcgOpts(C.Structure):
+    _fields_ = [("n_eig", C.c_int), ("max_iter", C.c_int), ("tol", C.c_double), ("seed", C.c_uint64),
+                ("precond", C.c_int), ("e_shift", C.c_double), ("stream", C.c_void_p)]
+
+
+class LobpcgInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("hv_calls", C.c_int64),
+                ("seconds", C.c_double)]
+
+
 class Schedule(C.Structure):
     _fields_ = [("hub_slab_cols", C.c_int), ("hub_groups", C.c_int), ("hub_item_rows", C.c_int),
                 ("hub_row_cols", C.c_int), ("spin_per_cu", C.c_int), ("spin_implicit", C.c_int),
@@ -97,6 +107,7 @@ SIGNATURES = {
     "hphi_lanczos_batch": (I, [C.POINTER(BatchItem), I, P]),
     "hphi_ctpq": (I, [P, C.POINTER(CtpqOpts), P, PD, PD, PD]),
     "hphi_time_evolve": (I, [P, C.POINTER(TevolOpts), P, PD, PD, PD]),
+    "hphi_lobpcg": (I, [P, C.POINTER(LobpcgOpts), PD, PD, P, C.POINTER(LobpcgInfo)]),
     "hphi_szq": (I, [P, PD, P, P, P]),
     "hphi_sqw": (I, [P, C.POINTER(SqwOpts), P, PD, PD, I, PD, PD, C.POINTER(SqwInfo)]),
 }

@@ -327,6 +327,26 @@ def time_evolve(ham: Hamiltonian, psi, n_steps: int, dt: float = 0.01, n_max: in
     return out
 
 
+def lobpcg(ham: Hamiltonian, n_eig: int, max_iter: int = 500, tol: float = 1e-8, seed: int = 1,
+           precond: bool = True, e_shift: float = 0.0, want_vectors: bool = False, stream=None) -> Dict:
+    """Lowest n_eig eigenpairs by LOBPCG (point-Jacobi preconditioner with
+    shift e_shift, 0 = a lower bound from the couplings)."""
+    torch = _torch()
+    o = L.LobpcgOpts()
+    o.n_eig, o.max_iter, o.tol, o.seed = n_eig, max_iter, tol, seed
+    o.precond, o.e_shift, o.stream = (1 if precond else 0), e_shift, _stream_ptr(stream)
+    e = np.zeros(n_eig)
+    res = np.zeros(n_eig)
+    vecs = None
+    if want_vectors:
+        vecs = torch.empty((n_eig, ham.basis.dim), dtype=torch.float64, device=f"cuda:{ham.basis.ctx.device}")
+    info = L.LobpcgInfo()
+    _check(L.lib().hphi_lobpcg(ham.h, C.byref(o), e.ctypes.data_as(L.PD), res.ctypes.data_as(L.PD),
+                               vecs.data_ptr() if vecs is not None else None, C.byref(info)), "hphi_lobpcg")
+    return {"energies": e, "residuals": res, "vectors": vecs, "iterations": info.iterations,
+            "converged": bool(info.converged), "hv_calls": info.hv_calls, "seconds": info.seconds}
+
+
 def szq(ham: Hamiltonian, q: float, psi, stream=None):
     """b = sum_l e^{i q x_l} S^z_l psi, x_l from the model's site_x."""
     torch = _torch()

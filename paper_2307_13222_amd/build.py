@@ -20,7 +20,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Wno-unused-command-line-argument", "-I", os.path.join(HERE, "..", "include")]
 
 SOURCES = ["host.cpp", "capi.cpp", "capi_methods.cpp", "kern_spin.hip", "kern_hub.hip",
-           "kern_vec.hip", "kern_methods.hip", "kern_big.hip", "kern_batch.hip"]
+           "kern_vec.hip", "kern_methods.hip", "kern_big.hip", "kern_batch.hip", "kern_lobpcg.hip",
+           "capi_lobpcg.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -11,27 +11,7 @@ using namespace hphi;
 
 namespace {
 
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard()
-    {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
 
-Reduce reduce_at(hphi_ham *h, double *result)
-{
-    Reduce r;
-    r.partial = h->red_partial.as<double>();
-    r.counter = h->red_counter.as<unsigned>();
-    r.result = result;
-    return r;
-}
 
 } // namespace
 

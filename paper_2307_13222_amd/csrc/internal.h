@@ -45,6 +45,21 @@ struct DevMem {
 
 int upload(DevMem &m, const void *host, size_t bytes);
 
+// Makes `dev` current for the scope, restores the previous device after.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+
 // One species' sector: n_bits-bit patterns with n_pop set bits, ascending,
 // ranked by the split two-level table idx = hi_off[x >> n_lo] + lo_rank[x & mask].
 struct Species {
@@ -244,6 +259,16 @@ int launch_lz_psi_accum(int dtype, LzDev *lz, const double *svec, int64_t dim, v
 // host tridiagonal solver
 int tridiag_lowest(const double *alpha, const double *beta, int n, int k, double *eig,
                    double *vec);
+
+// The Hamiltonian's reduction scratch with the result written to `result`.
+inline Reduce reduce_at(hphi_ham *h, double *result)
+{
+    Reduce r;
+    r.partial = h->red_partial.as<double>();
+    r.counter = h->red_counter.as<unsigned>();
+    r.result = result;
+    return r;
+}
 
 int dtype_size(int dtype);     // bytes per scalar element (complex counts 2 lanes)
 int dtype_lanes(int dtype);    // 1 real, 2 complex
