@@ -21,8 +21,8 @@ int launch_gram(const double *const *X, int a, const double *const *Y, int b, in
 int launch_lincomb(const double *const *V, int nin, const double *C, double *const *out, int nout, int64_t dim,
                    hipStream_t st);
 int launch_resid(const double *const *HPhi, const double *const *Phi, double *const *R, int m, const double *E,
-                 const double *d, const double *shift, int64_t dim, Reduce red, hipStream_t st);
-int launch_scale_block(double *const *X, int m, const double *s, int64_t dim, hipStream_t st);
+                 int estride, const double *d, double shift, int64_t dim, Reduce red, hipStream_t st);
+int launch_scale_block(double *const *X, int m, const double *g, int ld, int64_t dim, hipStream_t st);
 
 // Symmetric eigenproblem A = Q diag(w) Q^T (n x n, row-major A, overwritten),
 // cyclic Jacobi; Q column j is eigenvector j; ascending order.
@@ -161,15 +161,18 @@ int hphi_lobpcg(hphi_ham *h, const hphi_lobpcg_opts *o, double *energies_out, do
     const size_t vb = sizeof(double) * (size_t)dim;
     // vectors: Phi, HPhi, R, HR, P, HP and the next Phi, HPhi, P, HP
     enum { PHI, HPHI, R, HR, P, HP, PHI2, HPHI2, P2, HP2, NSET };
-    DevMem store, diag, ptab, coef, scal, gres;
+    DevMem store, diag, ptab, coef, gres;
     HPHI_TRY(store.alloc(vb * (size_t)M * NSET));
     std::vector<std::vector<double *>> set(NSET, std::vector<double *>(M));
     for (int s = 0; s < NSET; ++s)
         for (int n = 0; n < M; ++n) set[s][n] = store.as<double>() + ((size_t)s * M + n) * (size_t)dim;
-    HPHI_TRY(ptab.alloc(sizeof(double *) * 16 * 96));
-    HPHI_TRY(coef.alloc(sizeof(double) * 96 * 32));
-    HPHI_TRY(scal.alloc(sizeof(double) * 4 * 32));
-    HPHI_TRY(gres.alloc(sizeof(double) * 32 * 32));
+    constexpr int kSlots = 64, kSlotLen = 96, kG = 32 * 32;
+    // result slots (kG doubles each): 0 = Phi^T H Phi, 1 = R^T R, 2.. = subspace
+    // blocks, kNorm = next Phi / p norms, kRes = residual norms
+    constexpr int kSub = 2, kNorm = 20, kRes = 22, kNres = 23;
+    HPHI_TRY(ptab.alloc(sizeof(double *) * kSlots * kSlotLen));
+    HPHI_TRY(coef.alloc(sizeof(double) * 2 * 96 * 32));
+    HPHI_TRY(gres.alloc(sizeof(double) * kG * kNres));
     const bool pre = o->precond != 0;
     if (pre) {
         HPHI_TRY(diag.alloc(vb));
@@ -177,19 +180,21 @@ int hphi_lobpcg(hphi_ham *h, const hphi_lobpcg_opts *o, double *energies_out, do
     }
     const double eshift = pre ? (o->e_shift != 0.0 ? o->e_shift : lower_bound(h)) : 0.0;
     double **dptr = static_cast<double **>(ptab.p);
-    auto put = [&](int slot, const std::vector<double *> &v) -> const double *const * {
-        hipMemcpyAsync(dptr + slot * 96, v.data(), sizeof(double *) * v.size(), hipMemcpyHostToDevice, st);
-        return dptr + slot * 96;
+    double *G0 = gres.as<double>();
+    // pointer tables: each launch of a phase gets its own slot; the host
+    // arrays they are copied from live until the next synchronization
+    int slot = 0;
+    auto put = [&](const std::vector<double *> &v) -> double ** {
+        double **d = dptr + (size_t)(slot++ % kSlots) * kSlotLen;
+        (void)hipMemcpyAsync(d, v.data(), sizeof(double *) * v.size(), hipMemcpyHostToDevice, st);
+        return d;
     };
-    auto dev_set = [&](int slot) { return dptr + slot * 96; };
-    std::vector<double> G(32 * 32);
-    auto gram = [&](int sx, const std::vector<double *> &X, int sy, const std::vector<double *> &Y) -> int {
-        const double *const *dx = put(sx, X);
-        const double *const *dy = put(sy, Y);
-        HPHI_TRY(launch_gram(dx, (int)X.size(), dy, (int)Y.size(), dim, reduce_at(h, gres.as<double>()), st));
-        HPHI_HIP(hipMemcpyAsync(G.data(), gres.p, sizeof(double) * X.size() * Y.size(), hipMemcpyDeviceToHost, st));
-        HPHI_HIP(hipStreamSynchronize(st));
-        return HPHI_OK;
+    auto gram = [&](const std::vector<double *> &X, const std::vector<double *> &Y, int res) -> int {
+        double **dx = put(X), **dy = put(Y);
+        return launch_gram(dx, (int)X.size(), dy, (int)Y.size(), dim, reduce_at(h, G0 + (size_t)res * kG), st);
+    };
+    auto scale = [&](const std::vector<double *> &X, int res) -> int {
+        return launch_scale_block(put(X), M, G0 + (size_t)res * kG, M, dim, st);
     };
     int64_t hv_calls = 0;
     auto hmult = [&](const std::vector<double *> &in, const std::vector<double *> &out) -> int {
@@ -206,79 +211,63 @@ int hphi_lobpcg(hphi_ham *h, const hphi_lobpcg_opts *o, double *energies_out, do
         }
         return HPHI_OK;
     };
-    auto scale = [&](int slot, const std::vector<double *> &X, const std::vector<double> &s) -> int {
-        HPHI_HIP(hipMemcpyAsync(scal.p, s.data(), sizeof(double) * s.size(), hipMemcpyHostToDevice, st));
-        put(slot, X);
-        HPHI_TRY(launch_scale_block(dev_set(slot), (int)X.size(), scal.as<double>(), dim, st));
-        HPHI_HIP(hipStreamSynchronize(st));
-        return HPHI_OK;
-    };
+    std::vector<double> Gh((size_t)kG * kNres);
     // start block: SplitMix64 uniform vectors (seed + n), normalized
     for (int n = 0; n < M; ++n) HPHI_TRY(launch_rng_uniform(HPHI_F64, set[PHI][n], dim, o->seed + (uint64_t)n, st));
-    HPHI_TRY(gram(0, set[PHI], 1, set[PHI]));
-    {
-        std::vector<double> s(M);
-        for (int n = 0; n < M; ++n) s[n] = 1.0 / std::sqrt(G[(size_t)n * M + n]);
-        HPHI_TRY(scale(2, set[PHI], s));
-    }
+    HPHI_TRY(gram(set[PHI], set[PHI], kNorm));
+    HPHI_TRY(scale(set[PHI], kNorm));
     HPHI_TRY(hmult(set[PHI], set[HPHI]));
-    std::vector<double> E(M, 0.0), res(M, 0.0);
+    std::vector<double> E(M, 0.0), res(M, 0.0), Ch(2 * 96 * 32);
+    std::vector<double *> V, HV;
+    const int blocks[3] = {R, PHI, P}, hblocks[3] = {HR, HPHI, HP};
     bool have_p = false, converged = false;
     int it = 0;
     for (; it < o->max_iter; ++it) {
-        // Rayleigh quotients (Phi normalized) and residuals
-        HPHI_TRY(gram(0, set[PHI], 1, set[HPHI]));
-        for (int n = 0; n < M; ++n) E[n] = G[(size_t)n * M + n];
-        std::vector<double> sh(2 * M);
-        for (int n = 0; n < M; ++n) {
-            sh[n] = E[n];
-            sh[M + n] = eshift;
-        }
-        HPHI_HIP(hipMemcpyAsync(scal.p, sh.data(), sizeof(double) * 2 * M, hipMemcpyHostToDevice, st));
-        put(0, set[HPHI]);
-        put(1, set[PHI]);
-        put(2, set[R]);
-        HPHI_TRY(launch_resid(dev_set(0), dev_set(1), reinterpret_cast<double *const *>(dev_set(2)), M,
-                              scal.as<double>(), pre ? diag.as<double>() : nullptr, scal.as<double>() + M, dim,
-                              reduce_at(h, gres.as<double>()), st));
-        HPHI_HIP(hipMemcpyAsync(G.data(), gres.p, sizeof(double) * M, hipMemcpyDeviceToHost, st));
+        // Rayleigh quotients (Phi normalized) on the device, residuals,
+        // normalized (preconditioned) residuals and H r
+        HPHI_TRY(gram(set[PHI], set[HPHI], 0));
+        HPHI_TRY(launch_resid(put(set[HPHI]), put(set[PHI]), put(set[R]), M, G0, M + 1,
+                              pre ? diag.as<double>() : nullptr, eshift, dim,
+                              reduce_at(h, G0 + (size_t)kRes * kG), st));
+        HPHI_TRY(gram(set[R], set[R], 1));
+        HPHI_TRY(scale(set[R], 1));
+        HPHI_TRY(hmult(set[R], set[HR]));
+        // subspace matrices over the blocks (R, Phi, P)
+        const int nb = have_p ? 3 : 2;
+        const int k = nb * M;
+        int q = kSub;
+        for (int bi = 0; bi < nb; ++bi)
+            for (int bj = 0; bj < nb; ++bj) {
+                HPHI_TRY(gram(set[blocks[bi]], set[hblocks[bj]], q++));
+                if (bj >= bi) HPHI_TRY(gram(set[blocks[bi]], set[blocks[bj]], q++));
+            }
+        // one synchronization per iteration: all small results at once
+        HPHI_HIP(hipMemcpyAsync(Gh.data(), G0, sizeof(double) * Gh.size(), hipMemcpyDeviceToHost, st));
         HPHI_HIP(hipStreamSynchronize(st));
+        slot = 0;
         double worst = 0.0;
         for (int n = 0; n < M; ++n) {
-            res[n] = std::sqrt(std::max(G[n], 0.0));
+            E[n] = Gh[(size_t)n * (M + 1)];
+            res[n] = std::sqrt(std::max(Gh[(size_t)kRes * kG + n], 0.0));
             worst = std::max(worst, res[n]);
         }
         if (worst < o->tol) {
             converged = true;
             break;
         }
-        // normalize the (preconditioned) residuals, then H r
-        HPHI_TRY(gram(0, set[R], 1, set[R]));
-        {
-            std::vector<double> s(M);
-            for (int n = 0; n < M; ++n) {
-                const double nn = G[(size_t)n * M + n];
-                s[n] = nn > 0.0 ? 1.0 / std::sqrt(nn) : 0.0;
-            }
-            HPHI_TRY(scale(2, set[R], s));
-        }
-        HPHI_TRY(hmult(set[R], set[HR]));
-        // subspace matrices over blocks (R, Phi, P)
-        const int nb = have_p ? 3 : 2;
-        const int k = nb * M;
-        const int blocks[3] = {R, PHI, P}, hblocks[3] = {HR, HPHI, HP};
         std::vector<double> Hs((size_t)k * k), Os((size_t)k * k);
+        q = kSub;
         for (int bi = 0; bi < nb; ++bi)
             for (int bj = 0; bj < nb; ++bj) {
-                HPHI_TRY(gram(0, set[blocks[bi]], 1, set[hblocks[bj]]));
+                const double *gh = Gh.data() + (size_t)(q++) * kG;
                 for (int i = 0; i < M; ++i)
-                    for (int j = 0; j < M; ++j) Hs[(size_t)(bi * M + i) * k + bj * M + j] = G[(size_t)i * M + j];
+                    for (int j = 0; j < M; ++j) Hs[(size_t)(bi * M + i) * k + bj * M + j] = gh[(size_t)i * M + j];
                 if (bj < bi) continue;
-                HPHI_TRY(gram(0, set[blocks[bi]], 1, set[blocks[bj]]));
+                const double *go = Gh.data() + (size_t)(q++) * kG;
                 for (int i = 0; i < M; ++i)
                     for (int j = 0; j < M; ++j) {
-                        Os[(size_t)(bi * M + i) * k + bj * M + j] = G[(size_t)i * M + j];
-                        Os[(size_t)(bj * M + j) * k + bi * M + i] = G[(size_t)i * M + j];
+                        Os[(size_t)(bi * M + i) * k + bj * M + j] = go[(size_t)i * M + j];
+                        Os[(size_t)(bj * M + j) * k + bi * M + i] = go[(size_t)i * M + j];
                     }
             }
         for (int i = 0; i < k; ++i)
@@ -291,45 +280,29 @@ int hphi_lobpcg(hphi_ham *h, const hphi_lobpcg_opts *o, double *energies_out, do
             continue;
         }
         // updates: Phi = V X, HPhi = HV X, p = (r, 0, p) X, Hp = (Hr, 0, Hp) X
-        std::vector<double *> V, HV;
+        V.clear();
+        HV.clear();
         for (int bi = 0; bi < nb; ++bi) {
             V.insert(V.end(), set[blocks[bi]].begin(), set[blocks[bi]].end());
             HV.insert(HV.end(), set[hblocks[bi]].begin(), set[hblocks[bi]].end());
         }
-        std::vector<double> Xp(X);
+        std::copy(X.begin(), X.end(), Ch.begin());
+        std::copy(X.begin(), X.end(), Ch.begin() + 96 * 32);
         for (int i = M; i < 2 * M; ++i)
-            for (int n = 0; n < M; ++n) Xp[(size_t)i * M + n] = 0.0;
-        auto lin = [&](const std::vector<double *> &in, const std::vector<double> &C, int out) -> int {
-            HPHI_HIP(hipMemcpyAsync(coef.p, C.data(), sizeof(double) * C.size(), hipMemcpyHostToDevice, st));
-            put(3, in);
-            put(4, set[out]);
-            HPHI_TRY(launch_lincomb(dev_set(3), (int)in.size(), coef.as<double>(),
-                                    reinterpret_cast<double *const *>(dev_set(4)), M, dim, st));
-            HPHI_HIP(hipStreamSynchronize(st));
-            return HPHI_OK;
-        };
-        HPHI_TRY(lin(V, X, PHI2));
-        HPHI_TRY(lin(HV, X, HPHI2));
-        HPHI_TRY(lin(V, Xp, P2));
-        HPHI_TRY(lin(HV, Xp, HP2));
-        // normalize Phi (and H Phi alike), p (and H p alike)
-        HPHI_TRY(gram(0, set[PHI2], 1, set[PHI2]));
-        {
-            std::vector<double> s(M);
-            for (int n = 0; n < M; ++n) s[n] = 1.0 / std::sqrt(G[(size_t)n * M + n]);
-            HPHI_TRY(scale(2, set[PHI2], s));
-            HPHI_TRY(scale(2, set[HPHI2], s));
-        }
-        HPHI_TRY(gram(0, set[P2], 1, set[P2]));
-        {
-            std::vector<double> s(M);
-            for (int n = 0; n < M; ++n) {
-                const double nn = G[(size_t)n * M + n];
-                s[n] = nn > 0.0 ? 1.0 / std::sqrt(nn) : 0.0;
-            }
-            HPHI_TRY(scale(2, set[P2], s));
-            HPHI_TRY(scale(2, set[HP2], s));
-        }
+            for (int n = 0; n < M; ++n) Ch[96 * 32 + (size_t)i * M + n] = 0.0;
+        HPHI_HIP(hipMemcpyAsync(coef.p, Ch.data(), sizeof(double) * Ch.size(), hipMemcpyHostToDevice, st));
+        const double *cx = coef.as<double>(), *cp = coef.as<double>() + 96 * 32;
+        HPHI_TRY(launch_lincomb(put(V), k, cx, put(set[PHI2]), M, dim, st));
+        HPHI_TRY(launch_lincomb(put(HV), k, cx, put(set[HPHI2]), M, dim, st));
+        HPHI_TRY(launch_lincomb(put(V), k, cp, put(set[P2]), M, dim, st));
+        HPHI_TRY(launch_lincomb(put(HV), k, cp, put(set[HP2]), M, dim, st));
+        // normalize Phi (H Phi alike) and p (H p alike) from their Gram diagonals
+        HPHI_TRY(gram(set[PHI2], set[PHI2], kNorm));
+        HPHI_TRY(scale(set[PHI2], kNorm));
+        HPHI_TRY(scale(set[HPHI2], kNorm));
+        HPHI_TRY(gram(set[P2], set[P2], kNorm + 1));
+        HPHI_TRY(scale(set[P2], kNorm + 1));
+        HPHI_TRY(scale(set[HP2], kNorm + 1));
         std::swap(set[PHI], set[PHI2]);
         std::swap(set[HPHI], set[HPHI2]);
         std::swap(set[P], set[P2]);

@@ -7,13 +7,27 @@
 //                identical)
 //   k_lincomb  : out_n = sum_m C[m][n] V_m (C in LDS)
 //   k_resid    : r_n = HPhi_n - E_n Phi_n, |r_n|^2, then optionally
-//                r_n /= (H_xx - E_shift)
-//   k_scale    : x_n *= s_n
+//                r_n /= (H_xx - E_shift); E_n read from a Gram diagonal
+//   k_scale    : x_n *= 1 / sqrt(G_nn), G a Gram matrix on the device
 #include "kern_common.h"
 
 namespace hphi {
 
 constexpr int kGramMax = 32;
+
+// Last workgroup of a launch: result[t] = sum over blocks of
+// partial[b * nres + t], one wave per result, lanes over blocks in a fixed
+// stride and a fixed shuffle tree (run-to-run identical).
+__device__ __forceinline__ void finish_waves(const double *partial, unsigned nblocks, int nres, double *result)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int t = wid; t < nres; t += nw) {
+        double s = 0.0;
+        for (unsigned b = lane; b < nblocks; b += 64) s += __builtin_nontemporal_load(&partial[(size_t)b * nres + t]);
+        s = wave_sum(s);
+        if (lane == 0) result[t] = s;
+    }
+}
 
 __global__ __launch_bounds__(kBlock) void k_diag_spin(const uint32_t *states, int64_t dim, const SpinBondDev *bonds,
                                                       int nb, const double *hz, int n_sites, double *out)
@@ -94,11 +108,64 @@ __global__ __launch_bounds__(kBlock) void k_gram(const double *const *X, int a, 
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    for (int t = threadIdx.x; t < nres; t += blockDim.x) {
-        double s = 0.0;
-        for (unsigned blk = 0; blk < gridDim.x; ++blk) s += __builtin_nontemporal_load(&partial[(size_t)blk * nres + t]);
-        result[t] = s;
+    finish_waves(partial, gridDim.x, nres, result);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *counter = 0u;
+        __threadfence();
     }
+}
+
+// Small blocks (a, b <= 8): one thread per row holds all a * b products, so
+// every load of a wave is a contiguous run of rows.
+__global__ __launch_bounds__(kBlock) void k_gram8(const double *const *X, int a, const double *const *Y, int b,
+                                                  int64_t dim, double *partial, unsigned *counter, double *result)
+{
+    __shared__ double sw[kBlock / kWave][64];
+    __shared__ unsigned s_last;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double acc[8][8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < dim;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        double x[8], y[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x[i] = i < a ? X[i][r] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) y[j] = j < b ? Y[j][r] : 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[i][j] += x[i] * y[j];
+    }
+    const int nres = a * b;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (i < a && j < b) {
+                const double v = wave_sum(acc[i][j]);
+                if (lane == 0) sw[wid][i * b + j] = v;
+            }
+        }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nres; t += blockDim.x) {
+        double sm = 0.0;
+        for (int w = 0; w < kBlock / kWave; ++w) sm += sw[w][t];
+        partial[(size_t)blockIdx.x * nres + t] = sm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        s_last = (atomicAdd(counter, 1u) == gridDim.x - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    finish_waves(partial, gridDim.x, nres, result);
     __syncthreads();
     if (threadIdx.x == 0) {
         *counter = 0u;
@@ -130,19 +197,19 @@ __global__ __launch_bounds__(kBlock) void k_lincomb(const double *const *V, int 
     }
 }
 
-// r_n = HPhi_n - E_n Phi_n; partial |r_n|^2 per block; then with a diagonal
-// r_n /= (d - shift_n).
+// r_n = HPhi_n - E_n Phi_n (E_n = E[n * estride]); partial |r_n|^2 per
+// block; then with a diagonal r_n /= (d - shift).
 __global__ __launch_bounds__(kBlock) void k_resid(const double *const *HPhi, const double *const *Phi,
-                                                  double *const *R, int m, const double *E, const double *d,
-                                                  const double *shift, int64_t dim, double *partial,
+                                                  double *const *R, int m, const double *E, int estride,
+                                                  const double *d, double shift, int64_t dim, double *partial,
                                                   unsigned *counter, double *result)
 {
     __shared__ double sh[kBlock / kWave];
     __shared__ double blk[kGramMax];
     __shared__ unsigned s_last;
     for (int n = 0; n < m; ++n) {
-        const double e = E[n];
-        const double sft = d ? shift[n] : 0.0;
+        const double e = E[n * estride];
+        const double sft = shift;
         double acc = 0.0;
         for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < dim;
              r += (int64_t)gridDim.x * blockDim.x) {
@@ -165,11 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_resid(const double *const *HPhi, con
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    if (threadIdx.x < m) {
-        double s = 0.0;
-        for (unsigned b = 0; b < gridDim.x; ++b) s += __builtin_nontemporal_load(&partial[(size_t)b * m + threadIdx.x]);
-        result[threadIdx.x] = s;
-    }
+    finish_waves(partial, gridDim.x, m, result);
     __syncthreads();
     if (threadIdx.x == 0) {
         *counter = 0u;
@@ -177,10 +240,12 @@ __global__ __launch_bounds__(kBlock) void k_resid(const double *const *HPhi, con
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scale(double *const *X, int m, const double *s, int64_t dim)
+// x_n *= 1 / sqrt(g[n * (ld + 1)]) (0 when that diagonal entry is not positive)
+__global__ __launch_bounds__(kBlock) void k_scale(double *const *X, int m, const double *g, int ld, int64_t dim)
 {
     for (int n = 0; n < m; ++n) {
-        const double f = s[n];
+        const double gn = g[(size_t)n * (ld + 1)];
+        const double f = gn > 0.0 ? 1.0 / sqrt(gn) : 0.0;
         for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < dim;
              r += (int64_t)gridDim.x * blockDim.x)
             X[n][r] *= f;
@@ -219,7 +284,8 @@ int launch_gram(const double *const *X, int a, const double *const *Y, int b, in
     if (a < 1 || a > kGramMax || b < 1 || b > kGramMax) return fail(HPHI_ERR_INVALID_ARG, "gram %d x %d", a, b);
     int g = lob_grid(dim / 4 + 1);
     if ((int64_t)g * a * b > kReduceSlots) g = (int)(kReduceSlots / (a * b));
-    if (a <= 8) hipLaunchKernelGGL(k_gram<8>, dim3(g), dim3(kBlock), 0, st, X, a, Y, b, dim, red.partial, red.counter, red.result);
+    if (a <= 8 && b <= 8) hipLaunchKernelGGL(k_gram8, dim3(g), dim3(kBlock), 0, st, X, a, Y, b, dim, red.partial, red.counter, red.result);
+    else if (a <= 8) hipLaunchKernelGGL(k_gram<8>, dim3(g), dim3(kBlock), 0, st, X, a, Y, b, dim, red.partial, red.counter, red.result);
     else if (a <= 16) hipLaunchKernelGGL(k_gram<16>, dim3(g), dim3(kBlock), 0, st, X, a, Y, b, dim, red.partial, red.counter, red.result);
     else hipLaunchKernelGGL(k_gram<32>, dim3(g), dim3(kBlock), 0, st, X, a, Y, b, dim, red.partial, red.counter, red.result);
     HPHI_HIP(hipGetLastError());
@@ -237,18 +303,18 @@ int launch_lincomb(const double *const *V, int nin, const double *C, double *con
 }
 
 int launch_resid(const double *const *HPhi, const double *const *Phi, double *const *R, int m, const double *E,
-                 const double *d, const double *shift, int64_t dim, Reduce red, hipStream_t st)
+                 int estride, const double *d, double shift, int64_t dim, Reduce red, hipStream_t st)
 {
     if (m < 1 || m > kGramMax) return fail(HPHI_ERR_INVALID_ARG, "resid block %d", m);
-    hipLaunchKernelGGL(k_resid, dim3(lob_grid(dim)), dim3(kBlock), 0, st, HPhi, Phi, R, m, E, d, shift, dim,
-                       red.partial, red.counter, red.result);
+    hipLaunchKernelGGL(k_resid, dim3(lob_grid(dim)), dim3(kBlock), 0, st, HPhi, Phi, R, m, E, estride, d, shift,
+                       dim, red.partial, red.counter, red.result);
     HPHI_HIP(hipGetLastError());
     return HPHI_OK;
 }
 
-int launch_scale_block(double *const *X, int m, const double *s, int64_t dim, hipStream_t st)
+int launch_scale_block(double *const *X, int m, const double *g, int ld, int64_t dim, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_scale, dim3(lob_grid(dim)), dim3(kBlock), 0, st, X, m, s, dim);
+    hipLaunchKernelGGL(k_scale, dim3(lob_grid(dim)), dim3(kBlock), 0, st, X, m, g, ld, dim);
     HPHI_HIP(hipGetLastError());
     return HPHI_OK;
 }
