@@ -365,9 +365,13 @@ int hphi_lobpcg(hphi_ham *h, const hphi_lobpcg_opts *opts, double *energies_out,
 
 /* --------------------------------------------------- S^zz(q, w) / D(z) -- */
 
-/* Excitation b = sum_l e^{i q x_l} S^z_l psi for a spin basis (Sec. 3.2):
+/* Excitation b = sum_l e^{i q x_l} S^z_l psi (Sec. 3.2): for a spin basis
+ * S^z_l = +-1/2 by bit l of the state (stored list, N <= 32); for a Hubbard
+ * basis S^z_l = (n_l,up - n_l,dn) / 2 at index r_up * dim_dn + r_dn.
  * phase[2*l], phase[2*l+1] = (cos, sin)(q x_l) per site, host array.
- * psi_dev: F64 vector; b_dev: C128 vector. Asynchronous on `stream`. */
+ * psi_dev: F64 vector; b_dev: C128 vector, caller-owned. Synchronous.
+ * Errors: INVALID_ARG (null, more than 64 sites), UNSUPPORTED (spin basis
+ * not stored), OUT_OF_MEMORY, DEVICE. */
 int hphi_szq(hphi_ham *h, const double *phase, const void *psi_dev, void *b_dev,
              void *stream);
 
@@ -388,9 +392,13 @@ typedef struct {
 /* Dynamical correlation D(z_j) = <b| (z_j - H)^-1 |b> for n_shift complex
  * shifts z_j = (z_re[j], z_im[j]) from one Krylov sequence (shifted COCG on
  * the complex-symmetric z - H; Sec. 3.2, method "CG"). Only the projections
- * <b|x_j> are kept (host scalar recurrences per shift). D_out receives
- * 2 * n_shift doubles (re, im); resid_out (nullable) the per-shift relative
- * residual norms. b_dev: C128 vector. Synchronous.
+ * <b|x_j> are kept (scalar recurrences per shift on the device). A complex
+ * b runs two sequences, from Re b and Im b, and D = D_Re + D_Im (exact for
+ * the real symmetric Hamiltonians here; avoids the COCG breakdown b^T b = 0
+ * of momentum excitations). D_out receives 2 * n_shift doubles (re, im);
+ * resid_out (nullable) the per-shift bound (|r_Re| + |r_Im|) / |b|;
+ * info->iterations counts H*v calls of both sequences. b = 0 gives D = 0,
+ * no iterations. b_dev: C128 vector, read only. Synchronous.
  * Errors: INVALID_ARG (n_shift < 1 or > 4096), OUT_OF_MEMORY, DEVICE. */
 int hphi_sqw(hphi_ham *h, const hphi_sqw_opts *opts, const void *b_dev,
              const double *z_re, const double *z_im, int n_shift, double *D_out,

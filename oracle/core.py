@@ -379,6 +379,21 @@ def szq_excitation(m, states: np.ndarray, q: float, psi: np.ndarray) -> np.ndarr
     return (sz @ phase) * psi
 
 
+def hubbard_szq_excitation(m, ups: np.ndarray, dns: np.ndarray, q: float,
+                           psi: np.ndarray) -> np.ndarray:
+    """Phi_ex = sum_l e^{i q x_l} S^z_l Phi_GS on the Hubbard basis (Sec. 3.2),
+    S^z_l = (n_l,up - n_l,dn) / 2, state index r_up * dim_dn + r_dn; x_l the
+    site coordinate (site number when the model gives none)."""
+    n = m.n_sites
+    sx = getattr(m, "site_x", None)
+    x = np.arange(n, dtype=np.float64) if sx is None else np.asarray(sx, dtype=np.float64)
+    l = np.arange(n, dtype=np.uint64)
+    nu = ((np.asarray(ups, dtype=np.uint64)[:, None] >> l) & np.uint64(1)).astype(np.float64)
+    nd = ((np.asarray(dns, dtype=np.uint64)[:, None] >> l) & np.uint64(1)).astype(np.float64)
+    sz = 0.5 * (nu[:, None, :] - nd[None, :, :]).reshape(-1, n)
+    return (sz @ np.exp(1j * q * x)) * psi
+
+
 def dyn_corr_direct(Hs, b: np.ndarray, zs: np.ndarray) -> np.ndarray:
     """D(z) = <b| (z I - H)^-1 |b> by one sparse direct solve per z
     (Sec. 3.2 definition; no E0 offset, no 1/pi)."""

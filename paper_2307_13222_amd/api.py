@@ -351,7 +351,8 @@ def szq(ham: Hamiltonian, q: float, psi, stream=None):
     """b = sum_l e^{i q x_l} S^z_l psi, x_l from the model's site_x."""
     torch = _torch()
     _dev_check(psi, "psi")
-    x = np.asarray(ham.model.site_x, dtype=np.float64)
+    sx = getattr(ham.model, "site_x", None)
+    x = np.arange(ham.basis.n_sites, dtype=np.float64) if sx is None else np.asarray(sx, dtype=np.float64)
     phase = np.empty(2 * len(x))
     phase[0::2] = np.cos(q * x)
     phase[1::2] = np.sin(q * x)

@@ -312,7 +312,6 @@ int hphi_lanczos_batch(hphi_batch_item *items, int n, void *stream)
 int hphi_szq(hphi_ham *h, const double *phase, const void *psi_dev, void *b_dev, void *stream)
 {
     if (!h || !phase || !psi_dev || !b_dev) return fail(HPHI_ERR_INVALID_ARG, "null argument");
-    if (h->kind != 0) return fail(HPHI_ERR_INVALID_ARG, "S^z(q) needs a spin Hamiltonian");
     if (h->basis->n_sites > 64) return fail(HPHI_ERR_INVALID_ARG, "too many sites");
     DeviceGuard g(h->basis->ctx->device);
     hipStream_t st = (hipStream_t)stream;
@@ -323,6 +322,14 @@ int hphi_szq(hphi_ham *h, const double *phase, const void *psi_dev, void *b_dev,
     return HPHI_OK;
 }
 
+// Shifted COCG needs b^T b != 0; a complex excitation such as S^z(q) psi
+// with q != 0, pi has b^T b = 0 by momentum conservation (the bilinear form
+// pairs momentum q with -q), so the seed system breaks down at once. With H
+// real symmetric, (z - H)^-1 is complex symmetric and
+//   D(z) = b^H (z - H)^-1 b = D_Re(z) + D_Im(z)
+// (the cross terms a^T (z - H)^-1 c and c^T (z - H)^-1 a cancel), where
+// D_Re, D_Im come from the real-valued right-hand sides Re b and Im b, for
+// which r^T r = |r|^2 > 0. Each nonzero part runs its own Krylov sequence.
 int hphi_sqw(hphi_ham *h, const hphi_sqw_opts *o, const void *b_dev, const double *z_re, const double *z_im,
              int n_shift, double *D_out, double *resid_out, hphi_sqw_info *info)
 {
@@ -335,7 +342,8 @@ int hphi_sqw(hphi_ham *h, const hphi_sqw_opts *o, const void *b_dev, const doubl
     hipStream_t st = (hipStream_t)o->stream;
     const int64_t dim = h->basis->dim;
     const int seed = o->seed_shift >= 0 ? o->seed_shift : n_shift / 2;
-    DevMem r, p, hp, cgm, shm;
+    DevMem bp, r, p, hp, cgm, shm;
+    HPHI_TRY(bp.alloc(sizeof(double) * 2 * (size_t)dim));
     HPHI_TRY(r.alloc(sizeof(double) * 2 * (size_t)dim));
     HPHI_TRY(p.alloc(sizeof(double) * 2 * (size_t)dim));
     HPHI_TRY(hp.alloc(sizeof(double) * 2 * (size_t)dim));
@@ -349,60 +357,76 @@ int hphi_sqw(hphi_ham *h, const hphi_sqw_opts *o, const void *b_dev, const doubl
     }
     HPHI_TRY(upload(shm, s0.data(), sizeof(ShiftDev) * n_shift));
     Reduce red = reduce_at(h, h->red_result.as<double>());
-    HPHI_TRY(launch_cocg_init(b_dev, r.p, p.p, dim, cgm.p, shm.p, n_shift, o->tol, red, st));
-    int it = 0, converged = 0;
     CgDev hc{};
-    HPHI_HIP(hipMemcpyAsync(&hc, cgm.p, sizeof(CgDev), hipMemcpyDeviceToHost, st));
-    HPHI_HIP(hipStreamSynchronize(st));
-    if (hc.bnorm2 == 0.0) {
-        // b = 0: D(z) = 0 for every shift, nothing to iterate
-        for (int j = 0; j < n_shift; ++j) {
-            D_out[2 * j] = D_out[2 * j + 1] = 0.0;
-            if (resid_out) resid_out[j] = 0.0;
-        }
-        if (info) {
-            info->iterations = 0;
-            info->converged = 1;
-            info->max_residual = 0.0;
-            info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        }
+    // starts the sequence for part `part` of b (r = p = part, shift state
+    // reset) and returns |part|^2
+    auto start = [&](int part, double *bn2) -> int {
+        HPHI_TRY(launch_cplx_part(b_dev, bp.p, dim, part, st));
+        HPHI_TRY(launch_cocg_init(bp.p, r.p, p.p, dim, cgm.p, shm.p, n_shift, o->tol, red, st));
+        HPHI_HIP(hipMemcpyAsync(&hc, cgm.p, sizeof(CgDev), hipMemcpyDeviceToHost, st));
+        HPHI_HIP(hipStreamSynchronize(st));
+        *bn2 = hc.bnorm2;
         return HPHI_OK;
-    }
-    const int check = 8;
-    while (it < o->max_iter) {
-        MultArgs a{};
-        a.dtype = HPHI_C128;
-        a.nvec = 1;
-        a.v = p.p;
-        a.w = hp.p;
-        a.red = red;
-        a.stream = st;
-        HPHI_TRY(launch_mult(h, a));
-        HPHI_TRY(launch_cocg_iter(r.p, p.p, hp.p, b_dev, dim, cgm.p, shm.p, n_shift, o->tol, red, st));
-        ++it;
-        if (it % check == 0 || it == o->max_iter) {
-            HPHI_HIP(hipMemcpyAsync(&hc, cgm.p, sizeof(CgDev), hipMemcpyDeviceToHost, st));
-            HPHI_HIP(hipStreamSynchronize(st));
-            if (hc.max_res < o->tol) {
-                converged = 1;
-                break;
-            }
-            if (hc.breakdown) break;
-        }
-    }
-    HPHI_HIP(hipMemcpyAsync(&hc, cgm.p, sizeof(CgDev), hipMemcpyDeviceToHost, st));
+    };
+    double bn2[2];
+    HPHI_TRY(start(1, &bn2[1]));
+    HPHI_TRY(start(0, &bn2[0]));           // the real part's sequence is ready
+    const double bnorm = std::sqrt(bn2[0] + bn2[1]);
+    const double bsum = std::sqrt(bn2[0]) + std::sqrt(bn2[1]);
+    // per-part relative tolerance such that |r_Re| + |r_Im| < tol |b|
+    const double tol_part = bsum > 0.0 ? o->tol * bnorm / bsum : o->tol;
+    std::vector<double> D(2 * n_shift, 0.0), res(n_shift, 0.0);
     std::vector<ShiftDev> s1(n_shift);
-    HPHI_HIP(hipMemcpyAsync(s1.data(), shm.p, sizeof(ShiftDev) * n_shift, hipMemcpyDeviceToHost, st));
-    HPHI_HIP(hipStreamSynchronize(st));
+    int it_total = 0, converged = 1;
+    const int check = 8;
+    for (int part = 0; part < 2; ++part) {
+        if (bn2[part] == 0.0) continue;     // D_part = 0, nothing to iterate
+        if (part == 1) {
+            double tmp;
+            HPHI_TRY(start(1, &tmp));
+        }
+        int it = 0, conv = 0;
+        while (it < o->max_iter) {
+            MultArgs a{};
+            a.dtype = HPHI_C128;
+            a.nvec = 1;
+            a.v = p.p;
+            a.w = hp.p;
+            a.red = red;
+            a.stream = st;
+            HPHI_TRY(launch_mult(h, a));
+            HPHI_TRY(launch_cocg_iter(r.p, p.p, hp.p, bp.p, dim, cgm.p, shm.p, n_shift, tol_part, red, st));
+            ++it;
+            if (it % check == 0 || it == o->max_iter) {
+                HPHI_HIP(hipMemcpyAsync(&hc, cgm.p, sizeof(CgDev), hipMemcpyDeviceToHost, st));
+                HPHI_HIP(hipStreamSynchronize(st));
+                if (hc.max_res < tol_part) {
+                    conv = 1;
+                    break;
+                }
+                if (hc.breakdown) break;
+            }
+        }
+        HPHI_HIP(hipMemcpyAsync(s1.data(), shm.p, sizeof(ShiftDev) * n_shift, hipMemcpyDeviceToHost, st));
+        HPHI_HIP(hipStreamSynchronize(st));
+        const double w = std::sqrt(bn2[part]) / bnorm;
+        for (int j = 0; j < n_shift; ++j) {
+            D[2 * j] += s1[j].X.re;
+            D[2 * j + 1] += s1[j].X.im;
+            res[j] += s1[j].res * w;        // |r_part| / |b|
+        }
+        it_total += it;
+        converged &= conv;
+    }
     double mx = 0.0;
     for (int j = 0; j < n_shift; ++j) {
-        D_out[2 * j] = s1[j].X.re;
-        D_out[2 * j + 1] = s1[j].X.im;
-        if (resid_out) resid_out[j] = s1[j].res;
-        mx = std::max(mx, s1[j].res);
+        D_out[2 * j] = D[2 * j];
+        D_out[2 * j + 1] = D[2 * j + 1];
+        if (resid_out) resid_out[j] = res[j];
+        mx = std::max(mx, res[j]);
     }
     if (info) {
-        info->iterations = it;
+        info->iterations = it_total;
         info->converged = converged;
         info->max_residual = mx;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

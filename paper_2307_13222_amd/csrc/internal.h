@@ -307,6 +307,7 @@ int launch_cocg_init(const void *b, void *r, void *p, int64_t dim, void *cg, voi
                      Reduce red, hipStream_t st);
 int launch_cocg_iter(void *r, void *p, const void *h, const void *b, int64_t dim, void *cg, void *sh,
                      int nsh, double tol, Reduce red, hipStream_t st);
+int launch_cplx_part(const void *b, void *out, int64_t dim, int part, hipStream_t st);
 int launch_pair_rsqrt(const double *n, double *s, int nl, hipStream_t st);
 
 // batched small-sector Lanczos (kern_batch.hip)

@@ -235,6 +235,24 @@ int launch_cocg_iter(void *r, void *p, const void *h, const void *b, int64_t dim
     return HPHI_OK;
 }
 
+// out = (Re b, 0) for part 0, (Im b, 0) for part 1 (complex vectors).
+__global__ void k_cplx_part(const double *b, double *out, int64_t dim, int part)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        out[2 * i] = b[2 * i + part];
+        out[2 * i + 1] = 0.0;
+    }
+}
+
+int launch_cplx_part(const void *b, void *out, int64_t dim, int part, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cplx_part, dim3(gridn(dim)), dim3(kBlock), 0, st, (const double *)b, (double *)out,
+                       dim, part);
+    HPHI_HIP(hipGetLastError());
+    return HPHI_OK;
+}
+
 // s[l] = 1/sqrt(n[2*(l/2)] + n[2*(l/2)+1]) for nl lanes (complex pairs).
 __global__ void k_pair_rsqrt(const double *n, double *s, int nl)
 {

@@ -541,14 +541,49 @@ __global__ void k_szq(const uint32_t *states, int64_t dim, int n_sites, const do
     }
 }
 
+// Hubbard basis: S^z_l = (n_l,up - n_l,dn) / 2; index r = r_up * dim_dn + r_dn.
+// One up row per block iteration, the threads over the down states.
+__global__ void k_szq_hub(const uint32_t *ups, const uint32_t *dns, int64_t dim_up, int64_t dim_dn,
+                          int n_sites, const double *phase, const double *psi, double *b)
+{
+    __shared__ double ph[128];
+    for (int i = threadIdx.x; i < 2 * n_sites; i += blockDim.x) ph[i] = phase[i];
+    __syncthreads();
+    for (int64_t ru = blockIdx.x; ru < dim_up; ru += gridDim.x) {
+        const uint32_t x = ups[ru];
+        for (int64_t rd = threadIdx.x; rd < dim_dn; rd += blockDim.x) {
+            const uint32_t y = dns[rd];
+            double re = 0.0, im = 0.0;
+            for (int l = 0; l < n_sites; ++l) {
+                const double sz = 0.5 * ((double)((x >> l) & 1u) - (double)((y >> l) & 1u));
+                re += sz * ph[2 * l];
+                im += sz * ph[2 * l + 1];
+            }
+            const int64_t r = ru * dim_dn + rd;
+            const double p = psi[r];
+            b[2 * r] = re * p;
+            b[2 * r + 1] = im * p;
+        }
+    }
+}
+
 int launch_szq(hphi_ham *h, const double *phase_dev, const void *psi, void *b, hipStream_t st)
 {
     const hphi_basis *bs = h->basis;
-    if (h->kind != 0 || !bs->sp[0].materialized() || bs->sp[0].state_bytes != 4)
-        return fail(HPHI_ERR_UNSUPPORTED, "S^z(q) needs a spin basis with N <= 32");
-    hipLaunchKernelGGL(k_szq, dim3(grid_for(bs->dim, 2)), dim3(kBlock), 0, st,
-                       bs->sp[0].d_states.as<uint32_t>(), bs->dim, bs->n_sites, phase_dev,
-                       (const double *)psi, (double *)b);
+    if (bs->dim == 0) return HPHI_OK;
+    if (h->kind == 0) {
+        if (!bs->sp[0].materialized() || bs->sp[0].state_bytes != 4)
+            return fail(HPHI_ERR_UNSUPPORTED, "S^z(q) needs a stored spin basis with N <= 32");
+        hipLaunchKernelGGL(k_szq, dim3(grid_for(bs->dim, 2)), dim3(kBlock), 0, st,
+                           bs->sp[0].d_states.as<uint32_t>(), bs->dim, bs->n_sites, phase_dev,
+                           (const double *)psi, (double *)b);
+    } else {
+        const int64_t du = bs->sp[0].dim, dd = bs->sp[1].dim;
+        const unsigned grid = (unsigned)std::min<int64_t>(du, 65536);
+        hipLaunchKernelGGL(k_szq_hub, dim3(grid), dim3(kBlock), 0, st,
+                           bs->sp[0].d_states.as<uint32_t>(), bs->sp[1].d_states.as<uint32_t>(), du, dd,
+                           bs->n_sites, phase_dev, (const double *)psi, (double *)b);
+    }
     HPHI_HIP(hipGetLastError());
     return HPHI_OK;
 }

@@ -45,6 +45,7 @@ class HubbardModel:
     t: np.ndarray
     u_site: np.ndarray
     name: str = ""
+    site_x: Optional[np.ndarray] = None   # coordinate used for S^z(q) phases
 
     @property
     def n_hops(self) -> int:
@@ -133,13 +134,15 @@ def hubbard_square(lx: int, ly: int, t: float = 1.0, u: float = 4.0) -> HubbardM
     p = np.asarray(square_pairs(lx, ly, False), dtype=np.int32)
     n = lx * ly
     return HubbardModel(n, p[:, 0].copy(), p[:, 1].copy(), np.full(len(p), t),
-                        np.full(n, u, dtype=np.float64), f"hubbard_square_{lx}x{ly}")
+                        np.full(n, u, dtype=np.float64), f"hubbard_square_{lx}x{ly}",
+                        np.arange(n, dtype=np.int64) % lx)
 
 
 def hubbard_chain(n: int, t: float = 1.0, u: float = 4.0) -> HubbardModel:
     p = np.asarray(chain_pairs(n), dtype=np.int32)
     return HubbardModel(n, p[:, 0].copy(), p[:, 1].copy(), np.full(len(p), t),
-                        np.full(n, u, dtype=np.float64), f"hubbard_chain_{n}")
+                        np.full(n, u, dtype=np.float64), f"hubbard_chain_{n}",
+                        np.arange(n, dtype=np.int64))
 
 
 def random_vector(dim: int, seed: int, dtype=np.float64, nvec: int = 1) -> np.ndarray:

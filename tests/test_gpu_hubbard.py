@@ -1,0 +1,156 @@
+"""GPU: the Hubbard paths of the spectral and finite-temperature rows through
+the C ABI -- S^z(q) excitation against the oracle, S^zz(q, w) by shifted
+COCG against the full-spectrum sum, canonical TPQ against the oracle's
+propagator and, with the bootstrap, against exact canonical values of the
+sector; FP32 / complex64 H*v and FP32-storage Lanczos."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg
+
+from oracle import core as O
+from paper_2307_13222_amd import thermo as T
+from paper_2307_13222_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2307_13222_amd import api as A
+    return A
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    return api.Context(0)
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def relmax(a, b):
+    return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+
+
+def ground(Hs):
+    e, u = scipy.sparse.linalg.eigsh(Hs, k=1, which="SA")
+    return float(e[0]), u[:, 0]
+
+
+@pytest.mark.parametrize("lx,ly,nu,nd,q", [(4, 2, 4, 4, math.pi / 2), (4, 2, 5, 3, math.pi),
+                                           (3, 3, 4, 5, 2 * math.pi / 3), (2, 3, 3, 0, 0.7)])
+def test_hubbard_szq_matches_oracle(api, ctx, lx, ly, nu, nd, q):
+    say("hub szq", lx, ly, nu, nd)
+    m = W.hubbard_square(lx, ly, 1.0, 4.0)
+    b = api.Basis.hubbard(ctx, m.n_sites, nu, nd)
+    h = api.Hamiltonian.hubbard(b, m)
+    ups, dns = O.hubbard_basis(m.n_sites, nu, nd)
+    psi = W.random_vector(b.dim, 31)
+    bg = host(api.szq(h, q, dev(psi)))
+    bo = O.hubbard_szq_excitation(m, ups, dns, q, psi)
+    assert relmax(bg, bo) < 1e-14
+
+
+def test_hubbard_sqw_matches_spectral_sum(api, ctx):
+    say("hub sqw")
+    m = W.hubbard_square(4, 2, 1.0, 4.0)
+    b = api.Basis.hubbard(ctx, 8, 3, 3)
+    h = api.Hamiltonian.hubbard(b, m)
+    ups, dns = O.hubbard_basis(8, 3, 3)
+    Hd = O.hubbard_sparse(m, ups, dns).toarray()
+    ev, U = np.linalg.eigh(Hd)
+    e0, psi = ev[0], U[:, 0]
+    q = math.pi / 2                      # complex phases 1, i, -1, -i along x
+    bo = O.hubbard_szq_excitation(m, ups, dns, q, psi)
+    # momentum excitation: b^T b vanishes, the device solver splits Re / Im
+    assert np.max(np.abs(bo.imag)) > 1e-3 and abs(np.sum(bo * bo)) < 1e-12
+    bg = api.szq(h, q, dev(psi))
+    assert relmax(host(bg), bo) < 1e-14
+    z = e0 + np.linspace(0.0, 12.0, 48) + 0.1j
+    g = api.sqw(h, bg, z, max_iter=3000, tol=1e-10)
+    assert g["converged"], g["max_residual"]
+    # spectral sum over the full spectrum (pinned to direct solves on the CPU)
+    d_ref = O.dyn_corr_spectral(Hd, bo, z)
+    assert relmax(g["D"], d_ref) < 1e-8
+    assert np.all(-g["D"].imag > 0)
+
+
+@pytest.mark.parametrize("dt,tol", [("c128", 1e-11), ("c64", 2e-5)])
+def test_hubbard_ctpq_matches_oracle(api, ctx, dt, tol):
+    import torch
+    say("hub ctpq", dt)
+    m = W.hubbard_square(3, 3, 1.0, 6.0)
+    b = api.Basis.hubbard(ctx, 9, 4, 5)
+    h = api.Hamiltonian.hubbard(b, m)
+    ups, dns = O.hubbard_basis(9, 4, 5)
+    phi0 = O.splitmix_complex_gaussian(77, b.dim)[:, None]
+    tdt = torch.complex128 if dt == "c128" else torch.complex64
+    g = api.ctpq(h, 1, 6, 0.02, 20, storage=dt, phi0=dev(phi0).to(tdt))
+    phi_in = host(dev(phi0).to(tdt)).astype(np.complex128)
+    o = O.ctpq(lambda x: O.hubbard_hv(m, ups, dns, x), phi_in, 6, 0.02, 20)
+    assert relmax(g["D"], o["D"]) < tol
+    assert relmax(g["E"], o["E"]) < tol
+    assert relmax(g["E2"], o["E2"]) < tol
+
+
+def test_hubbard_ctpq_thermodynamics_against_canonical(api, ctx):
+    say("hub ctpq thermo")
+    m = W.hubbard_square(2, 3, 1.0, 4.0)
+    b = api.Basis.hubbard(ctx, 6, 3, 3)
+    h = api.Hamiltonian.hubbard(b, m)
+    ups, dns = O.hubbard_basis(6, 3, 3)
+    ev = np.linalg.eigvalsh(O.hubbard_sparse(m, ups, dns).toarray())
+    runs = [api.ctpq(h, 1, 6, 0.02, 150, storage="c128", seed=11 + j) for j in range(12)]
+    D = np.concatenate([r["D"] for r in runs], axis=1)
+    E = np.concatenate([r["E"] for r in runs], axis=1)
+    E2 = np.concatenate([r["E2"] for r in runs], axis=1)
+    th = T.tpq_thermo(runs[0]["beta"], D, E, E2, b.dim, 6, n_boot=200)
+    ex = O.canonical_thermo(ev, runs[0]["beta"], 6)
+    for key in ("E", "C", "S"):
+        dev_ = np.abs(th[key] - ex[key])
+        assert np.all(dev_ < 5 * th[key + "_err"] + 5e-3), (key, float(dev_.max()))
+    assert abs(th["S"][0] - math.log(b.dim) / 6) < 1e-12
+
+
+@pytest.mark.parametrize("lx,ly,nu,nd", [(4, 2, 4, 4), (3, 4, 6, 5)])
+def test_hubbard_mult_f32_c64(api, ctx, lx, ly, nu, nd):
+    import torch
+    say("hub mult f32", lx, ly, nu, nd)
+    m = W.hubbard_square(lx, ly, 1.0, 4.0)
+    b = api.Basis.hubbard(ctx, m.n_sites, nu, nd)
+    h = api.Hamiltonian.hubbard(b, m)
+    ups, dns = O.hubbard_basis(m.n_sites, nu, nd)
+    # the oracle gets the FP32-rounded input; FP32 accumulation over at most
+    # 2 * hops + 1 terms of size <= U / 2 bounds the error well below 1e-5
+    v = dev(W.random_vector(b.dim, 41)).to(torch.float32)
+    w = host(h.mult(v)).astype(np.float64)
+    assert relmax(w, O.hubbard_hv(m, ups, dns, host(v).astype(np.float64))) < 1e-5
+    vc = dev(W.random_vector(b.dim, 42, np.complex128)).to(torch.complex64)
+    wc = host(h.mult(vc)).astype(np.complex128)
+    assert relmax(wc, O.hubbard_hv(m, ups, dns, host(vc).astype(np.complex128))) < 1e-5
+
+
+def test_hubbard_lanczos_f32_storage(api, ctx):
+    say("hub lanczos f32")
+    m = W.hubbard_square(4, 2, 1.0, 4.0)
+    b = api.Basis.hubbard(ctx, 8, 4, 4)
+    h = api.Hamiltonian.hubbard(b, m)
+    ups, dns = O.hubbard_basis(8, 4, 4)
+    e0, _ = ground(O.hubbard_sparse(m, ups, dns))
+    r = api.lanczos(h, 200, seed=3, storage="f32")
+    # FP32 vectors, FP64 scalars: the Ritz value sits within FP32 rounding of E0
+    assert abs(r["energies"][0] - e0) < 1e-4 * abs(e0)

@@ -457,9 +457,11 @@ def test_ctpq_device_rng_matches_oracle_stream(api, ctx):
 
 # ------------------------------------------------------------ S(q, w) ---
 
-@pytest.mark.parametrize("lattice,n", [("chain", 12), ("ladder", 12), ("chain", 13)])
-def test_sqw_matches_direct_solve(api, ctx, lattice, n):
-    say("sqw", lattice, n)
+@pytest.mark.parametrize("lattice,n,q", [("chain", 12, math.pi), ("ladder", 12, math.pi), ("chain", 13, math.pi),
+                                         ("chain", 12, math.pi / 3), ("ladder", 12, 2 * math.pi / 3)])
+def test_sqw_matches_direct_solve(api, ctx, lattice, n, q):
+    # q != 0, pi: complex excitation with b^T b = 0 (two real sequences)
+    say("sqw", lattice, n, q)
     m = W.random_heisenberg(n, lattice, 17)
     two_sz = n % 2
     b = api.Basis.spin(ctx, n, two_sz)
@@ -468,7 +470,6 @@ def test_sqw_matches_direct_solve(api, ctx, lattice, n):
     Hs = O.spin_sparse(m, s)
     ev, U = np.linalg.eigh(Hs.toarray())
     psi = U[:, 0]
-    q = math.pi
     bo = O.szq_excitation(m, s, q, psi)
     bg = api.szq(h, q, dev(psi))
     assert relmax(host(bg), bo) < 1e-14

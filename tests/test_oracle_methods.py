@@ -180,6 +180,65 @@ def test_szq_parseval():
     assert abs(tot - n * n / 4) < 1e-9
 
 
+def test_hubbard_szq_q0_is_total_sz():
+    # sum_l S^z_l = (N_up - N_dn) / 2 on every configuration
+    m = W.hubbard_chain(7)
+    ups, dns = O.hubbard_basis(7, 4, 2)
+    psi = W.random_vector(len(ups) * len(dns), 3)
+    b = O.hubbard_szq_excitation(m, ups, dns, 0.0, psi)
+    assert np.max(np.abs(b - 1.0 * psi)) < 1e-14
+
+
+def test_hubbard_szq_singly_occupied_equals_spin():
+    # with every site singly occupied (down = complement of up) the Hubbard
+    # S^z_l acts as the spin-1/2 one on the up bitstring
+    n, nu = 8, 3
+    hm = W.hubbard_chain(n)
+    sm = W.random_heisenberg(n, "chain", 2)
+    ups, dns = O.hubbard_basis(n, nu, n - nu)
+    mask = (1 << n) - 1
+    pos = {int(y): i for i, y in enumerate(dns)}
+    psi_s = W.random_vector(len(ups), 8)
+    psi = np.zeros(len(ups) * len(dns))
+    rows = np.array([r * len(dns) + pos[~int(x) & mask] for r, x in enumerate(ups)])
+    psi[rows] = psi_s
+    q = 2 * math.pi * 3 / n
+    bh = O.hubbard_szq_excitation(hm, ups, dns, q, psi)
+    bs = O.szq_excitation(sm, ups, q, psi_s)
+    assert np.max(np.abs(bh[rows] - bs)) < 1e-14
+    other = np.setdiff1d(np.arange(len(psi)), rows)
+    assert np.all(bh[other] == 0)
+
+
+def test_hubbard_szq_parseval_counts_single_occupancy():
+    # sum over the n momenta 2 pi k / n of |b_q|^2 = n sum_r |psi_r|^2 s_r / 4
+    # with s_r the number of singly occupied sites of configuration r
+    n = 6
+    m = W.hubbard_chain(n)
+    ups, dns = O.hubbard_basis(n, 3, 2)
+    psi = W.random_vector(len(ups) * len(dns), 5)
+    tot = sum(np.vdot(bq, bq).real for bq in
+              (O.hubbard_szq_excitation(m, ups, dns, 2 * math.pi * k / n, psi) for k in range(n)))
+    single = np.array([bin(int(x) ^ int(y)).count("1") for x in ups for y in dns], dtype=np.float64)
+    assert abs(tot - n * np.sum(psi ** 2 * single) / 4) < 1e-10
+
+
+def test_dyn_corr_splits_into_real_and_imaginary_parts():
+    # H real symmetric: D_b(z) = D_Re b(z) + D_Im b(z) for complex b, the form
+    # the device solver uses when b^T b vanishes (momentum q != 0, pi)
+    m = W.heisenberg_chain(10)
+    s = O.basis_list(10, 5)
+    Hs = O.spin_sparse(m, s)
+    ev, U = np.linalg.eigh(Hs.toarray())
+    b = O.szq_excitation(m, s, 2 * math.pi / 5, U[:, 0])
+    assert abs(np.sum(b * b)) < 1e-10 * np.vdot(b, b).real
+    zs = ev[0] + np.linspace(0, 4, 7) + 0.1j
+    d = O.dyn_corr_direct(Hs, b, zs)
+    d_split = O.dyn_corr_direct(Hs, b.real.astype(np.complex128), zs) + \
+        O.dyn_corr_direct(Hs, b.imag.astype(np.complex128), zs)
+    assert np.allclose(d, d_split, rtol=1e-12, atol=0)
+
+
 def test_continued_fraction_matches_direct():
     m, s, hv, Hs, ev, b = sqw_setup()
     zs = ev[0] + np.linspace(0, 4, 5) + 0.1j
