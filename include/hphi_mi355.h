@@ -159,7 +159,9 @@ void hphi_ham_free(hphi_ham *h);
  *   hub_row_cols    T_dn kernel variant: 1 = batched table loads, 2 = all
  *                   loads of two columns issued at once, 3 = row metadata
  *                   in LDS, 4 = as 3 with hop-ordered slots (up to 32767
- *                   down states; otherwise as 3)
+ *                   down states; otherwise as 3), 5 = as 4 with each row
+ *                   staged by one batch of loads (up to 16384 down states
+ *                   per lane group; otherwise as 4; bit-identical to 4)
  *   spin_per_cu     spin H*v workgroups per compute unit (1..16)
  *   spin_implicit   1: spin H*v rebuilds configurations from row indices
  *                   (the path sectors without a stored state list take:
@@ -174,7 +176,15 @@ void hphi_ham_free(hphi_ham *h);
  *                   (64-column slab, group of up rows sharing their high
  *                   half) with the group's tile in LDS (one real vector,
  *                   even number of down states, groups of at most 72 rows;
- *                   otherwise as 1)
+ *                   otherwise as 1); 5 = as 3, one wave per row, each
+ *                   row's neighbour lists walked in batches of 16 loads
+ *                   (128-column slabs with two columns per lane or
+ *                   64-column slabs; bit-identical to 3 at the same slab
+ *                   width); 6 = as 5 with each wave taking its own work
+ *                   items and reading the neighbour lists with scalar loads
+ *                   (no LDS staging, no block barriers; the products are
+ *                   bit-identical to 5, the fused dots sum in another
+ *                   order)
  * Errors: INVALID_ARG (value outside its range). */
 typedef struct {
     int hub_slab_cols;
@@ -233,6 +243,10 @@ typedef struct {
     double seconds;        /* wall time of the solve                         */
     double hv_seconds;     /* with time_kernels: summed H*v launch durations */
     int hv_calls;          /* number of H*v launches timed                   */
+    int fused_update;      /* 1: every product after the first also did the
+                              previous step's update (w -= alpha q, beta =
+                              |w|) in its rows kernel (Hubbard, one real
+                              vector, hub_row_cols 5); hv_seconds includes it */
 } hphi_lanczos_info;
 
 /* Lanczos ground state (Sec. 1): v_0 = r/|r|; w = H v_k - beta_k v_{k-1};

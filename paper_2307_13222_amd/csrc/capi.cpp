@@ -388,7 +388,9 @@ static int build_hub_fast(hphi_ham *h)
         for (uint32_t x : mi[r]) tgt.push_back((uint32_t)((uint64_t)x * (uint64_t)dn.dim));
     }
     off[up.dim] = (uint32_t)tgt.size();
-    if (tgt.empty()) tgt.push_back(0);
+    // padding: the wave-owned column kernel reads each row's entries in
+    // blocks of 16 that may run past the last list (row 0 targets, unused)
+    tgt.resize(tgt.size() + 16, 0u);
     HPHI_TRY(upload(h->hub.fu_off, off.data(), sizeof(uint32_t) * off.size()));
     HPHI_TRY(upload(h->hub.fu_mid, mid.data(), sizeof(uint32_t) * mid.size()));
     HPHI_TRY(upload(h->hub.fu_ent, tgt.data(), sizeof(uint32_t) * tgt.size()));
@@ -512,7 +514,7 @@ int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s)
         n.hub_item_rows = s->hub_item_rows;
     }
     if (s->hub_row_cols) {
-        if (s->hub_row_cols < 1 || s->hub_row_cols > 4)
+        if (s->hub_row_cols < 1 || s->hub_row_cols > 5)
             return fail(HPHI_ERR_INVALID_ARG, "hub_row_cols %d", s->hub_row_cols);
         n.hub_row_cols = s->hub_row_cols;
     }
@@ -526,7 +528,7 @@ int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s)
         n.spin_implicit = s->spin_implicit == 1 ? 1 : 0;
     }
     if (s->hub_sweep) {
-        if (s->hub_sweep < 1 || s->hub_sweep > 4) return fail(HPHI_ERR_INVALID_ARG, "hub_sweep %d", s->hub_sweep);
+        if (s->hub_sweep < 1 || s->hub_sweep > 6) return fail(HPHI_ERR_INVALID_ARG, "hub_sweep %d", s->hub_sweep);
         n.hub_sweep = s->hub_sweep;
     }
     h->sched_cfg = n;
@@ -590,6 +592,10 @@ struct LanczosRun {
     double *alpha = nullptr, *beta = nullptr;
     int cur = 0, prev = 2, wbuf = 1;
     bool timing = false;
+    // the update w <- w - alpha s q_k, beta = |w| runs inside the next
+    // product's rows kernel (Hubbard, one real vector); the last one after
+    // the loop
+    bool fused = false;
     std::vector<hipEvent_t> ev;   // pairs around each H*v
 
     ~LanczosRun()
@@ -621,6 +627,7 @@ struct LanczosRun {
 
     int setup(int max_iter)
     {
+        fused = h->kind == 1 && (dt == HPHI_F64 || dt == HPHI_F32) && hub_rows_fused_ok(h, 1);
         const size_t bytes = (size_t)dim * dtype_size(dt);
         for (auto &m : q) HPHI_TRY(m.alloc(bytes));
         HPHI_TRY(lz_mem.alloc(sizeof(LzDev)));
@@ -646,10 +653,14 @@ struct LanczosRun {
         return launch_lz_init(dt, lz, dim, r, st);
     }
 
-    // one Krylov step on the current buffers; first = no v_{k-1} term
+    // one Krylov step on the current buffers; first = no v_{k-1} term. In
+    // fused mode a non-first step first completes the previous step's
+    // update inside the product (q[cur] becomes q_k in place), so the
+    // Ritz-vector accumulation of q_k follows the product.
     int step(bool first, const double *svec, void *psi)
     {
-        if (psi) HPHI_TRY(launch_lz_psi_accum(dt, lz, svec, dim, psi, q[cur].p, st));
+        const bool fz = fused && !first;
+        if (psi && !fz) HPHI_TRY(launch_lz_psi_accum(dt, lz, svec, dim, psi, q[cur].p, st));
         MultArgs a{};
         a.dtype = dt;
         a.nvec = 1;
@@ -661,10 +672,19 @@ struct LanczosRun {
         a.dot_raw = 0;
         a.red = reduce_of(h, lz->dot);
         a.stream = st;
+        if (fz) {
+            a.lz = lz;
+            a.lz_alpha = alpha;
+            a.lz_beta = beta;
+            a.lz_q = q[prev].p;
+            a.lz_red = reduce_of(h, lz->nrm);
+        }
         if (timing) HPHI_TRY(mark());
         HPHI_TRY(launch_mult(h, a));
         if (timing) HPHI_TRY(mark());
-        HPHI_TRY(launch_lz_update(dt, lz, alpha, beta, dim, q[wbuf].p, q[cur].p, reduce_of(h, lz->nrm), st));
+        if (psi && fz) HPHI_TRY(launch_lz_psi_accum(dt, lz, svec, dim, psi, q[cur].p, st));
+        if (!fused)
+            HPHI_TRY(launch_lz_update(dt, lz, alpha, beta, dim, q[wbuf].p, q[cur].p, reduce_of(h, lz->nrm), st));
         const int old_prev = prev;
         prev = cur;
         cur = wbuf;
@@ -723,6 +743,10 @@ struct LanczosRun {
                 }
             }
         }
+        // fused mode: the last product's update (not needed by the
+        // Ritz-vector pass, which accumulates q_0 .. q_{n-1} only)
+        if (fused && !psi)
+            HPHI_TRY(launch_lz_update(dt, lz, alpha, beta, dim, q[cur].p, q[prev].p, reduce_of(h, lz->nrm), st));
         return HPHI_OK;
     }
 };
@@ -803,6 +827,7 @@ int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *o, double *energies, int 
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         info->hv_seconds = hv_s;
         info->hv_calls = hv_n;
+        info->fused_update = L.fused ? 1 : 0;
     }
     return HPHI_OK;
 }

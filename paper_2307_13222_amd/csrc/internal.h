@@ -173,7 +173,7 @@ struct hphi_ham {
     // defaults: 128-column slabs, 128 workgroups per XCD, 32-row items,
     // hop-ordered down slots, work-item queues with two columns per lane;
     // spin: 8 workgroups per CU
-    hphi_schedule sched_cfg{128, 128, 32, 4, 8, 0, 3};
+    hphi_schedule sched_cfg{128, 128, 16, 5, 8, 0, 5};
     // scratch for reductions and work queues
     hphi::DevMem sched;         // unsigned [16]: per-XCD item queues + counter
     hphi::DevMem red_partial;   // double [kReduceSlots]
@@ -211,7 +211,14 @@ struct MultArgs {
     Reduce red;
     hipStream_t stream;
     int coef_cplx;      // coef = [c1 re, c2 re, c1 im, c2 im] applied to complex pairs
+    // Lanczos update of the previous step fused into the product (Hubbard
+    // rows kernel; only where hub_rows_fused_ok): v <- v - f lz_q first
+    struct LzDev *lz;
+    double *lz_alpha, *lz_beta;
+    const void *lz_q;
+    Reduce lz_red;
 };
+bool hub_rows_fused_ok(hphi_ham *h, int nv);
 int launch_spin_mult(hphi_ham *h, const MultArgs &a);
 int launch_spin_mult_implicit(hphi_ham *h, const MultArgs &a);
 int launch_hub_mult(hphi_ham *h, const MultArgs &a);

@@ -117,6 +117,35 @@ __device__ __forceinline__ void epilogue(const S (&raw)[K], const S *uu, int cpl
     }
 }
 
+// The same epilogue with u held in registers (has_u false: no u term);
+// identical arithmetic, no pointer to a private array.
+template <typename S, int K>
+__device__ __forceinline__ void epilogue_r(const S (&raw)[K], const S (&uu)[K], bool has_u, int cplx,
+                                           const double *coef, S (&out)[K])
+{
+    const S c1r = coef ? (S)coef[0] : (S)1, c2r = coef ? (S)coef[1] : (S)0;
+    if constexpr (K % 2 == 0) {
+        if (cplx) {
+            const S c1i = (S)coef[2], c2i = (S)coef[3];
+#pragma unroll
+            for (int k = 0; k < K; k += 2) {
+                out[k] = c1r * raw[k] - c1i * raw[k + 1];
+                out[k + 1] = c1r * raw[k + 1] + c1i * raw[k];
+                if (has_u) {
+                    out[k] += c2r * uu[k] - c2i * uu[k + 1];
+                    out[k + 1] += c2r * uu[k + 1] + c2i * uu[k];
+                }
+            }
+            return;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        out[k] = c1r * raw[k];
+        if (has_u) out[k] += c2r * uu[k];
+    }
+}
+
 template <typename T> struct VecOf;
 template <> struct VecOf<double> { using t2 = double2; };
 template <> struct VecOf<float> { using t2 = float2; };

@@ -58,6 +58,12 @@ struct HubKArgs {
     int fg_ngroups;
     double t0;
     int coef_cplx;
+    int hb;                // column kernel: batched list walk, one wave per row
+    // Lanczos update fused into the rows kernel (null lz_q: none)
+    LzDev *lz;
+    double *lz_alpha, *lz_beta;
+    const void *lz_q;      // q_{k-1}: v <- v - f q_{k-1} before the product
+    Reduce lz_red;
 };
 
 template <typename S>
@@ -573,6 +579,229 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fb(HubKArgs a)
     }
 }
 
+// k_hub_rows_fb with the row staged by one batch of loads: each lane issues
+// all of its (up to MAXE) loads of the row before the first LDS write, so a
+// row costs one memory latency instead of one per element; the loads of row
+// ru are issued before the barrier that waits for the gathers of the
+// previous row. Needs ddn * NV <= MAXE * blockDim.x. Same slots, sums and
+// summation order as k_hub_rows_fb: bit-identical results.
+template <typename S, int NV, int MAXE>
+__global__ __launch_bounds__(1024) void k_hub_rows_fp(HubKArgs a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int64_t ddn = a.ddn;
+    const int64_t nch = (ddn + 63) >> 6;
+    S *s_row = reinterpret_cast<S *>(smem_raw);
+    uint32_t *s_base = reinterpret_cast<uint32_t *>(s_row + (ddn + 1) * NV);
+    uint32_t *s_w = s_base + nch;
+    uint16_t *s_d = reinterpret_cast<uint16_t *>(s_w + nch);
+    const S *__restrict__ v = static_cast<const S *>(a.v);
+    S *__restrict__ w = static_cast<S *>(a.w);
+    const S nt0 = (S)(-a.t0);
+    const int T = blockDim.x;
+    const int tid = threadIdx.x;
+    const uint32_t nrow = (uint32_t)(ddn * NV);
+    for (int64_t j = tid; j < nch; j += T) {
+        s_base[j] = a.fb_base[j];
+        s_w[j] = a.fb_w[j];
+    }
+    for (int64_t c = tid; c < ddn; c += T) s_d[c] = (uint16_t)a.dns[c];
+    if (tid < NV) s_row[nrow + tid] = (S)0;
+    auto load_col = [&](int64_t c, uint4 (&q)[4], uint32_t &nq) {
+        nq = 0;
+        if (c >= ddn) return;
+        const uint32_t wc = s_w[c >> 6];
+        nq = wc >> 3;
+        const uint4 *p = reinterpret_cast<const uint4 *>(a.fb_ent + s_base[c >> 6] + (uint32_t)(c & 63) * (wc >> 1));
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+            if ((uint32_t)g < nq) q[g] = p[g];
+    };
+    for (int64_t ru = blockIdx.x; ru < a.dup; ru += gridDim.x) {
+        const S *vrow = v + (size_t)ru * nrow;
+        // unconditional loads (indices past the row re-read its last
+        // element) so that all of them are in flight together
+        S tmp[MAXE];
+#pragma unroll
+        for (int e = 0; e < MAXE; ++e) {
+            const uint32_t i = (uint32_t)e * T + tid;
+            tmp[e] = vrow[i < nrow ? i : nrow - 1];
+        }
+        __syncthreads();    // every gather of the previous row has finished
+#pragma unroll
+        for (int e = 0; e < MAXE; ++e) {
+            const uint32_t i = (uint32_t)e * T + tid;
+            if (i < nrow) s_row[i] = tmp[e];
+        }
+        uint4 cur[4], nxt[4];
+        uint32_t ncur, nnxt;
+        load_col(tid, cur, ncur);
+        __syncthreads();
+        const uint32_t uu = a.ups[ru];
+        for (int64_t c = tid; c < ddn; c += T) {
+            load_col(c + T, nxt, nnxt);
+            S acc[NV];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) acc[j] = (S)0;
+            fb_gather<S, NV>(cur, ncur, s_row, acc);
+            const S dg = hub_diag<S>(a, uu, (uint32_t)s_d[c]);
+#pragma unroll
+            for (int j = 0; j < NV; ++j)
+                __builtin_nontemporal_store(dg * s_row[c * NV + j] + nt0 * acc[j],
+                                            &w[((size_t)ru * ddn + c) * NV + j]);
+#pragma unroll
+            for (int g = 0; g < 4; ++g) cur[g] = nxt[g];
+            ncur = nnxt;
+        }
+    }
+}
+
+// k_hub_rows_fp with the previous Lanczos step's update fused into the row
+// staging (one real vector). The input v holds w_k, the unnormalized
+// residual of the previous product; each element becomes
+//   x = w_k - f q_{k-1},   f = alpha_{k-1} s_{k-1},  alpha_{k-1} = s_{k-1} <q_{k-1}, w_k>
+// (the same expression, in the same precision, as the separate update
+// kernel), is written back in place (it is q_k for the column kernel and the
+// next step) and staged in LDS for this product. The last block to finish
+// sums the blocks' |x|^2 in block order and performs the update's scalar
+// step: alpha_{k-1}, beta_k = |x|, breakdown test, s_k = 1 / beta_k and the
+// epilogue coefficients [s_k, -beta_k s_{k-1}] the column kernel then reads.
+// Raw buffer loads: a wave-uniform resource (base, byte size) and a 32-bit
+// per-lane byte offset, so that many loads in flight cost one address
+// register each (the callers keep every offset inside the buffer).
+constexpr int kBufWord3 = 0x00020000;   // gfx9-family buffer resource word 3
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, kBufWord3);
+}
+template <typename S> __device__ __forceinline__ S buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <> __device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+template <> __device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+
+// MAXE: row elements per lane (ddn <= MAXE * blockDim.x).
+template <typename S, int MAXE>
+__global__ __launch_bounds__(1024) void k_hub_rows_fz(HubKArgs a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ double sh_red[16];
+    __shared__ double s_blk[1];
+    const int64_t ddn = a.ddn;
+    const int64_t nch = (ddn + 63) >> 6;
+    S *s_row = reinterpret_cast<S *>(smem_raw);
+    uint32_t *s_base = reinterpret_cast<uint32_t *>(s_row + (ddn + 1));
+    uint32_t *s_w = s_base + nch;
+    uint16_t *s_d = reinterpret_cast<uint16_t *>(s_w + nch);
+    S *__restrict__ v = const_cast<S *>(static_cast<const S *>(a.v));
+    const S *__restrict__ qp = static_cast<const S *>(a.lz_q);
+    S *__restrict__ w = static_cast<S *>(a.w);
+    const S nt0 = (S)(-a.t0);
+    const int T = blockDim.x;
+    const int tid = threadIdx.x;
+    const uint32_t nrow = (uint32_t)ddn;
+    LzDev *lz = a.lz;
+    const bool corr = !lz->done;
+    const double s_k1 = lz->s_cur;
+    const double f = corr ? (s_k1 * lz->dot[0]) * s_k1 : 0.0;
+    for (int64_t j = tid; j < nch; j += T) {
+        s_base[j] = a.fb_base[j];
+        s_w[j] = a.fb_w[j];
+    }
+    for (int64_t c = tid; c < ddn; c += T) s_d[c] = (uint16_t)a.dns[c];
+    if (tid == 0) s_row[nrow] = (S)0;
+    auto load_col = [&](int64_t c, uint4 (&q)[4], uint32_t &nq) {
+        nq = 0;
+        if (c >= ddn) return;
+        const uint32_t wc = s_w[c >> 6];
+        nq = wc >> 3;
+        const uint4 *p = reinterpret_cast<const uint4 *>(a.fb_ent + s_base[c >> 6] + (uint32_t)(c & 63) * (wc >> 1));
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+            if ((uint32_t)g < nq) q[g] = p[g];
+    };
+    double acc = 0.0;
+    const uint32_t rbytes = nrow * (uint32_t)sizeof(S);
+    for (int64_t ru = blockIdx.x; ru < a.dup; ru += gridDim.x) {
+        S *vrow = v + (size_t)ru * nrow;
+        const __amdgpu_buffer_rsrc_t rv = buf_rsrc(vrow, rbytes);
+        const __amdgpu_buffer_rsrc_t rq = buf_rsrc(qp + (size_t)ru * nrow, rbytes);
+        // two rounds of loads (registers), each with all of its loads in
+        // flight (indices past the row re-read its last element); the first
+        // round is issued before the barrier that waits for the previous
+        // row's gathers
+        constexpr int E1 = (MAXE + 1) / 2;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            const int e0 = hh ? E1 : 0, ne = hh ? MAXE - E1 : E1;
+            S tv[E1], tq[E1];
+#pragma unroll
+            for (int e = 0; e < E1; ++e) {
+                if (e >= ne) break;
+                const uint32_t i = (uint32_t)(e0 + e) * T + tid;
+                const uint32_t off = (i < nrow ? i : nrow - 1) * (uint32_t)sizeof(S);
+                tv[e] = buf_ld<S>(rv, off);
+                tq[e] = buf_ld<S>(rq, off);
+            }
+            if (hh == 0) __syncthreads();    // every gather of the previous row has finished
+#pragma unroll
+            for (int e = 0; e < E1; ++e) {
+                if (e >= ne) break;
+                const uint32_t i = (uint32_t)(e0 + e) * T + tid;
+                if (i < nrow) {
+                    const S x = corr ? (S)((double)tv[e] - f * (double)tq[e]) : tv[e];
+                    s_row[i] = x;
+                    if (corr) {
+                        vrow[i] = x;
+                        acc += (double)x * (double)x;
+                    }
+                }
+            }
+        }
+        uint4 cur[4], nxt[4];
+        uint32_t ncur, nnxt;
+        load_col(tid, cur, ncur);
+        __syncthreads();
+        const uint32_t uu = a.ups[ru];
+        for (int64_t c = tid; c < ddn; c += T) {
+            load_col(c + T, nxt, nnxt);
+            S accg[1] = {(S)0};
+            fb_gather<S, 1>(cur, ncur, s_row, accg);
+            const S dg = hub_diag<S>(a, uu, (uint32_t)s_d[c]);
+            __builtin_nontemporal_store(dg * s_row[c] + nt0 * accg[0], &w[(size_t)ru * ddn + c]);
+#pragma unroll
+            for (int g = 0; g < 4; ++g) cur[g] = nxt[g];
+            ncur = nnxt;
+        }
+    }
+    double vals[1] = {acc};
+    block_sum<1>(vals, sh_red);
+    if (tid == 0) s_blk[0] = vals[0];
+    __syncthreads();
+    if (grid_finish(s_blk, 1, a.lz_red, sh_red) && tid == 0 && corr) {
+        const double b = sqrt(a.lz_red.result[0]);
+        const double al = s_k1 * lz->dot[0];
+        const int k = lz->iter;
+        a.lz_alpha[k] = al;
+        a.lz_beta[k + 1] = b;
+        lz->iter = k + 1;
+        if (!(b > 1e-13 * fmax(1.0, fabs(al)))) {
+            lz->done = 1;
+            lz->breakdown = 1;
+        } else {
+            lz->s_prev = s_k1;
+            lz->s_cur = 1.0 / b;
+            lz->coef[0] = lz->s_cur;
+            lz->coef[1] = -b * s_k1;
+        }
+        __threadfence();
+    }
+}
+
 // Deep variant: each lane issues every table load of CPT columns (up to 32
 // entries each) before the first gather, then splits the sums at the sign
 // boundary. Used when the widest chunk has at most 32 entries.
@@ -656,7 +885,14 @@ __device__ __forceinline__ void load_k(const S *p, S (&o)[K])
     }
 }
 
-template <typename S, int NV, int CW, bool DOTS, int CPL = 1>
+// HB (one wave per row, RPW == 1): the row's neighbour count is uniform
+// over the wave, so the plus and minus lists are walked as one stream with
+// up to kColsBatch loads in flight per round, and the epilogue operands are
+// loaded before the first round. Each sum keeps its entry order, so the
+// results are bit-identical to the two-list walk.
+constexpr int kColsBatch = 12;
+
+template <typename S, int NV, int CW, bool DOTS, int CPL = 1, bool HB = false>
 __global__ __launch_bounds__(256) void k_hub_cols_f(HubKArgs a)
 {
     __shared__ double sh_red[4 * 2 * NV + 8];
@@ -727,6 +963,77 @@ __global__ __launch_bounds__(256) void k_hub_cols_f(HubKArgs a)
         for (int64_t r = r0 + wid * RPW + lane / LPR; r < r1; r += 4 * RPW) {
             if (!colok) continue;
             const size_t me = (size_t)r * ddn + col;
+            if constexpr (HB) {
+                static_assert(RPW == 1, "one wave per row");
+                const uint32_t eb = __builtin_amdgcn_readfirstlane(s_off[r - r0]);
+                const uint32_t em = __builtin_amdgcn_readfirstlane(s_mid[r - r0]);
+                const uint32_t ee = __builtin_amdgcn_readfirstlane(s_off[r - r0 + 1]);
+                // u is row-uniform (null or not): the same register lanes
+                // either way, read from w itself when there is no u
+                const S *up = u ? u : w;
+                S wv[K], uv[K], vv[K];
+#pragma unroll
+                for (int j = 0; j < K; ++j) wv[j] = __builtin_nontemporal_load(&w[me * NV + j]);
+#pragma unroll
+                for (int j = 0; j < K; ++j) uv[j] = __builtin_nontemporal_load(&up[me * NV + j]);
+#pragma unroll
+                for (int j = 0; j < K; ++j) vv[j] = DOTS ? v[me * NV + j] : (S)0;
+                S hp[K], hm[K];
+#pragma unroll
+                for (int j = 0; j < K; ++j) hp[j] = hm[j] = (S)0;
+                for (uint32_t e0 = eb; e0 < ee; e0 += kColsBatch) {
+                    // every load of the batch is issued (slots past the list
+                    // re-read its last entry) so that they form one group in
+                    // flight; the sums take each entry once, in order (adding
+                    // +0 leaves a sum that starts at +0 unchanged)
+                    uint32_t eo[kColsBatch];
+#pragma unroll
+                    for (int t = 0; t < kColsBatch; ++t) eo[t] = s_ent[e0 + t < ee ? e0 + t : ee - 1] + colb;
+                    S nv[kColsBatch][K];
+#pragma unroll
+                    for (int t = 0; t < kColsBatch; ++t)
+                        load_k<S, K>(reinterpret_cast<const S *>(vb + eo[t]), nv[t]);
+#pragma unroll
+                    for (int t = 0; t < kColsBatch; ++t) {
+                        const bool in = e0 + t < ee, plus = e0 + t < em;
+#pragma unroll
+                        for (int j = 0; j < K; ++j) {
+                            hp[j] += (in && plus) ? nv[t][j] : (S)0;
+                            hm[j] += (in && !plus) ? nv[t][j] : (S)0;
+                        }
+                    }
+                }
+                S hraw[K], hout[K];
+#pragma unroll
+                for (int j = 0; j < K; ++j) hraw[j] = wv[j] + nt0 * (hp[j] - hm[j]);
+                if (a.coef_cplx) {
+                    epilogue_r<S, K>(hraw, uv, u != nullptr, 1, a.ecoef, hout);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) hout[j] = c1s * hraw[j];
+                    if (u) {
+#pragma unroll
+                        for (int j = 0; j < K; ++j) hout[j] += c2s * uv[j];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < K; ++j) __builtin_nontemporal_store(hout[j], &w[me * NV + j]);
+                if (accp) {
+#pragma unroll
+                    for (int j = 0; j < K; ++j)
+                        __builtin_nontemporal_store(__builtin_nontemporal_load(&accp[me * NV + j]) + hout[j],
+                                                    &accp[me * NV + j]);
+                }
+                if constexpr (DOTS) {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) {
+                        const double o = a.dot_raw ? (double)hraw[j] : (double)hout[j];
+                        d0[j % NV] += (double)vv[j] * o;
+                        d1[j % NV] += o * o;
+                    }
+                }
+                continue;
+            }
             S ap[K], am[K];
 #pragma unroll
             for (int j = 0; j < K; ++j) ap[j] = am[j] = (S)0;
@@ -1243,17 +1550,212 @@ static void launch_cols_f(const HubKArgs &a, int grid, hipStream_t st)
         else hipLaunchKernelGGL((k_hub_cols_f<S, NV, CW, false, 2>), dim3(grid), dim3(256), 0, st, a);
         return;
     }
+    if constexpr (CW == 64) {
+        if (a.hb) {
+            if (a.nd) hipLaunchKernelGGL((k_hub_cols_f<S, NV, 64, true, 1, true>), dim3(grid), dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((k_hub_cols_f<S, NV, 64, false, 1, true>), dim3(grid), dim3(256), 0, st, a);
+            return;
+        }
+    }
     if (a.nd) hipLaunchKernelGGL((k_hub_cols_f<S, NV, CW, true>), dim3(grid), dim3(256), 0, st, a);
     else hipLaunchKernelGGL((k_hub_cols_f<S, NV, CW, false>), dim3(grid), dim3(256), 0, st, a);
+}
+
+// T_up slab kernel with wave-owned work: each wave takes (slab, item_rows
+// rows) items from the per-XCD queues itself and walks its rows one at a
+// time with the whole wave on one row segment (CW = 64 CPL columns), so a
+// row's neighbour list is wave-uniform and is read with scalar loads
+// straight from the CSR tables: no LDS staging and no block barriers. The
+// list walk, sums and epilogue are those of the batched walk (same order,
+// so W is bit-identical to it); the FP64 dot partials are one per item
+// (lane sums over the item's rows, then across the wave) and the last wave
+// to finish adds the item partials in item order.
+template <typename S, int NV, int CPL, bool DOTS>
+__global__ __launch_bounds__(256) void k_hub_cols_s(HubKArgs a)
+{
+    constexpr int CW = 64 * CPL;
+    constexpr int K = NV * CPL;
+    constexpr uint32_t ESZ = NV * sizeof(S);
+    const int lane = threadIdx.x & 63;
+    const int home = xcc_id();
+    const char *__restrict__ vb = static_cast<const char *>(a.v);
+    const S *__restrict__ v = static_cast<const S *>(a.v);
+    S *__restrict__ w = static_cast<S *>(a.w);
+    const S *__restrict__ u = static_cast<const S *>(a.u);
+    S *__restrict__ accp = static_cast<S *>(a.acc_out);
+    // read-only tables through the constant address space: uniform indices
+    // become scalar loads
+    typedef const __attribute__((address_space(4))) uint32_t cu32;
+    cu32 *fo = (cu32 *)a.fu_off;
+    cu32 *fm = (cu32 *)a.fu_mid;
+    cu32 *fe = (cu32 *)a.fu_ent;
+    double c1 = 1.0, c2 = 0.0;
+    if (a.ecoef) {
+        c1 = a.ecoef[0];
+        c2 = a.ecoef[1];
+    }
+    const S c1s = (S)c1, c2s = (S)c2, nt0 = (S)(-a.t0);
+    const int64_t ddn = a.ddn, dup = a.dup;
+    const int nchunk = (int)((dup + a.item_rows - 1) / a.item_rows);
+    int q = home, tries = 0;
+    for (;;) {
+        int it = -1;
+        if (lane == 0) {
+            while (tries < 8) {
+                const int nsl_q = q < a.nslab ? (a.nslab - q + 7) / 8 : 0;
+                const int cand = (int)atomicAdd(&a.sched[q], 1u);
+                if (cand < nsl_q * nchunk) {
+                    it = q + 8 * cand;
+                    break;
+                }
+                q = (q + 1) & 7;
+                ++tries;
+            }
+        }
+        const int item = __builtin_amdgcn_readfirstlane(it);
+        if (item < 0) break;
+        const int iq = item & 7, idx = item >> 3;
+        const int slab = iq + 8 * (idx / nchunk);
+        const int chunk = idx % nchunk;
+        const int64_t r0 = (int64_t)chunk * a.item_rows;
+        const int64_t r1 = r0 + a.item_rows < dup ? r0 + a.item_rows : dup;
+        const int64_t col = (int64_t)slab * CW + CPL * lane;
+        const bool colok = col < ddn;
+        const uint32_t colb = (uint32_t)col * ESZ;
+        double d0[NV], d1[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) d0[j] = d1[j] = 0.0;
+        for (int64_t r = r0; r < r1; ++r) {
+            const uint32_t eb = fo[r], em = fm[r], ee = fo[r + 1];
+            if (!colok) continue;
+            const size_t me = (size_t)r * ddn + col;
+            const S *up = u ? u : w;
+            S wv[K], uv[K], vv[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) wv[j] = __builtin_nontemporal_load(&w[me * NV + j]);
+#pragma unroll
+            for (int j = 0; j < K; ++j) uv[j] = __builtin_nontemporal_load(&up[me * NV + j]);
+#pragma unroll
+            for (int j = 0; j < K; ++j) vv[j] = DOTS ? v[me * NV + j] : (S)0;
+            S hp[K], hm[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) hp[j] = hm[j] = (S)0;
+            for (uint32_t e0 = eb; e0 < ee; e0 += kColsBatch) {
+                // one contiguous scalar block of entries (the table is padded
+                // past its last list); slots past the row's list reuse the
+                // batch's first entry (a cache hit), their sums add +0
+                const uint32_t n = ee - e0;
+                uint32_t blk[kColsBatch], eo[kColsBatch];
+#pragma unroll
+                for (int t = 0; t < kColsBatch; ++t) blk[t] = fe[e0 + t];
+#pragma unroll
+                for (int t = 0; t < kColsBatch; ++t) eo[t] = ((uint32_t)t < n ? blk[t] : blk[0]) * ESZ;
+                S nv[kColsBatch][K];
+#pragma unroll
+                for (int t = 0; t < kColsBatch; ++t)
+                    load_k<S, K>(reinterpret_cast<const S *>(vb + eo[t] + colb), nv[t]);
+#pragma unroll
+                for (int t = 0; t < kColsBatch; ++t) {
+                    const bool in = e0 + t < ee, plus = e0 + t < em;
+#pragma unroll
+                    for (int j = 0; j < K; ++j) {
+                        hp[j] += (in && plus) ? nv[t][j] : (S)0;
+                        hm[j] += (in && !plus) ? nv[t][j] : (S)0;
+                    }
+                }
+            }
+            S hraw[K], hout[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) hraw[j] = wv[j] + nt0 * (hp[j] - hm[j]);
+            if (a.coef_cplx) {
+                epilogue_r<S, K>(hraw, uv, u != nullptr, 1, a.ecoef, hout);
+            } else {
+#pragma unroll
+                for (int j = 0; j < K; ++j) hout[j] = c1s * hraw[j];
+                if (u) {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) hout[j] += c2s * uv[j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < K; ++j) __builtin_nontemporal_store(hout[j], &w[me * NV + j]);
+            if (accp) {
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+                    __builtin_nontemporal_store(__builtin_nontemporal_load(&accp[me * NV + j]) + hout[j],
+                                                &accp[me * NV + j]);
+            }
+            if constexpr (DOTS) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const double o = a.dot_raw ? (double)hraw[j] : (double)hout[j];
+                    d0[j % NV] += (double)vv[j] * o;
+                    d1[j % NV] += o * o;
+                }
+            }
+        }
+        if constexpr (DOTS) {
+            const size_t slot = (size_t)slab * nchunk + chunk;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                const double s0 = wave_sum(d0[j]), s1 = wave_sum(d1[j]);
+                if (lane == 0) {
+                    a.red.partial[slot * 2 * NV + j] = s0;
+                    a.red.partial[slot * 2 * NV + NV + j] = s1;
+                }
+            }
+        }
+    }
+    unsigned last = 0;
+    if (lane == 0) {
+        __threadfence();
+        last = (atomicAdd(&a.sched[8], 1u) == gridDim.x * (blockDim.x >> 6) - 1) ? 1u : 0u;
+    }
+    if (__builtin_amdgcn_readfirstlane(last) == 0u) return;
+    __threadfence();
+    if constexpr (DOTS) {
+        const size_t nitems = (size_t)a.nslab * nchunk;
+        for (int j = 0; j < 2 * NV; ++j) {
+            double sum = 0.0;
+            for (size_t it = lane; it < nitems; it += 64)
+                sum += __builtin_nontemporal_load(&a.red.partial[it * 2 * NV + j]);
+            sum = wave_sum(sum);
+            if (lane == 0) a.red.result[j] = sum;
+        }
+    }
+    if (lane == 0) {
+        for (int i = 0; i < 8; ++i) a.sched[i] = 0u;
+        a.sched[8] = 0u;
+        __threadfence();
+    }
 }
 
 template <typename S, int NV>
 static void launch_cols_f128(const HubKArgs &a, int grid, hipStream_t st)
 {
     if constexpr (NV == 1) {
+        if (a.hb) {
+            if (a.nd) hipLaunchKernelGGL((k_hub_cols_f<S, 1, 128, true, 2, true>), dim3(grid), dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((k_hub_cols_f<S, 1, 128, false, 2, true>), dim3(grid), dim3(256), 0, st, a);
+            return;
+        }
         if (a.nd) hipLaunchKernelGGL((k_hub_cols_f<S, 1, 128, true, 2>), dim3(grid), dim3(256), 0, st, a);
         else hipLaunchKernelGGL((k_hub_cols_f<S, 1, 128, false, 2>), dim3(grid), dim3(256), 0, st, a);
     }
+}
+
+// The rows kernel with the fused Lanczos update runs where the batched
+// hop-ordered rows kernel runs (hub_row_cols 5) on one real vector with at
+// most 13 row elements per lane.
+bool hub_rows_fused_ok(hphi_ham *h, int nv)
+{
+    if (h->kind != 1 || nv != 1 || !h->hub.uniform_t || !h->hub.fb_ok) return false;
+    if (h->sched_cfg.hub_row_cols != 5 || h->basis->n_sites > 16) return false;
+    const int64_t dup = h->basis->sp[0].dim, ddn = h->basis->sp[1].dim;
+    if (ddn > 13 * 1024) return false;    // row elements per lane of k_hub_rows_fz
+    const size_t fm_bytes = (size_t)(ddn + 1) * sizeof(double) + 8 * (size_t)((ddn + 63) / 64) + 2 * (size_t)ddn + 16;
+    if (fm_bytes > 160 * 1024) return false;
+    return (unsigned __int128)dup * ddn * sizeof(double) < ((unsigned __int128)1 << 32);
 }
 
 template <typename S, int NV>
@@ -1274,11 +1776,31 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
                       (unsigned __int128)a.dup * a.ddn * NV * sizeof(S) < ((unsigned __int128)1 << 32);
     const int rmode = h->sched_cfg.hub_row_cols;
     const size_t fm_bytes = fast_row_bytes + 8 * (size_t)((a.ddn + 63) / 64) + 2 * (size_t)a.ddn + 16;
-    if (fast && rmode == 4 && h->hub.fb_ok && fm_bytes <= 160 * 1024 && h->basis->n_sites <= 16) {
+    if (a.lz_q) {
+        // fused Lanczos update: only where hub_rows_fused_ok holds
+        if constexpr (NV == 1) {
+            if (!hub_rows_fused_ok(h, 1))
+                return fail(HPHI_ERR_UNSUPPORTED, "fused Lanczos update outside its kernel range");
+            auto go = [&](auto kern) {
+                hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fm_bytes);
+                hipLaunchKernelGGL(kern, dim3((unsigned)grid_r), dim3(threads), fm_bytes, st, a);
+            };
+            const int64_t per = (a.ddn + threads - 1) / threads;
+            if (per <= 8) go(k_hub_rows_fz<S, 8>);
+            else go(k_hub_rows_fz<S, 13>);
+        } else {
+            return fail(HPHI_ERR_UNSUPPORTED, "fused Lanczos update takes one real vector");
+        }
+    } else if (fast && rmode == 5 && h->hub.fb_ok && fm_bytes <= 160 * 1024 && h->basis->n_sites <= 16 &&
+        a.ddn * NV <= 16 * (int64_t)threads) {
+        hipFuncSetAttribute((const void *)k_hub_rows_fp<S, NV, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fm_bytes);
+        hipLaunchKernelGGL((k_hub_rows_fp<S, NV, 16>), dim3((unsigned)grid_r), dim3(threads), fm_bytes, st, a);
+    } else if (fast && rmode >= 4 && h->hub.fb_ok && fm_bytes <= 160 * 1024 && h->basis->n_sites <= 16) {
         hipFuncSetAttribute((const void *)k_hub_rows_fb<S, NV>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)fm_bytes);
         hipLaunchKernelGGL((k_hub_rows_fb<S, NV>), dim3((unsigned)grid_r), dim3(threads), fm_bytes, st, a);
-    } else if (fast && (rmode == 3 || rmode == 4) && fm_bytes <= 160 * 1024 && h->basis->n_sites <= 16) {
+    } else if (fast && rmode >= 3 && fm_bytes <= 160 * 1024 && h->basis->n_sites <= 16) {
         hipFuncSetAttribute((const void *)k_hub_rows_fm<S, NV>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)fm_bytes);
         hipLaunchKernelGGL((k_hub_rows_fm<S, NV>), dim3((unsigned)grid_r), dim3(threads), fm_bytes, st, a);
@@ -1353,6 +1875,31 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
         HPHI_HIP(hipGetLastError());
         return HPHI_OK;
     }
+    if (fast && h->sched_cfg.hub_sweep == 6) {
+        // wave-owned items, scalar list walk: 128-column slabs with two
+        // columns per lane (one real vector, even row length), else 64
+        const bool two = NV == 1 && a.ddn % 2 == 0 && cw == 128;
+        const int cws = two ? 128 : 64;
+        a.item_rows = h->sched_cfg.hub_item_rows;
+        a.nslab = (int)((a.ddn + cws - 1) / cws);
+        const int64_t nitems = (int64_t)a.nslab * ((a.dup + a.item_rows - 1) / a.item_rows);
+        if (a.nd && nitems * 2 * NV > (int64_t)kReduceSlots)
+            return fail(HPHI_ERR_UNSUPPORTED, "Hubbard column items beyond the reduction scratch");
+        a.sched = h->sched.as<unsigned>();
+        const int grid_s = 8 * groups;
+        if constexpr (NV == 1) {
+            if (two) {
+                if (a.nd) hipLaunchKernelGGL((k_hub_cols_s<S, 1, 2, true>), dim3(grid_s), dim3(256), 0, st, a);
+                else hipLaunchKernelGGL((k_hub_cols_s<S, 1, 2, false>), dim3(grid_s), dim3(256), 0, st, a);
+                HPHI_HIP(hipGetLastError());
+                return HPHI_OK;
+            }
+        }
+        if (a.nd) hipLaunchKernelGGL((k_hub_cols_s<S, NV, 1, true>), dim3(grid_s), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_hub_cols_s<S, NV, 1, false>), dim3(grid_s), dim3(256), 0, st, a);
+        HPHI_HIP(hipGetLastError());
+        return HPHI_OK;
+    }
     int item_rows = h->sched_cfg.hub_item_rows;
     // the item's neighbour lists must fit the staging array
     while (item_rows > 8 && (int64_t)item_rows * h->hub.max_deg[0] > kColsLdsEntries) item_rows /= 2;
@@ -1361,8 +1908,11 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
                     (long long)h->hub.max_deg[0]);
     a.item_rows = item_rows;
     a.groups = groups;
-    // hub_sweep 3: two adjacent columns per lane (even row length only)
-    a.row_cols = (h->sched_cfg.hub_sweep == 3 && NV == 1 && a.ddn % 2 == 0) ? 2 : 1;
+    // hub_sweep 3 and 5: two adjacent columns per lane (even row length
+    // only); 5 also walks each row's lists in batches (one wave per row)
+    const int sw = h->sched_cfg.hub_sweep;
+    a.row_cols = ((sw == 3 || sw == 5) && NV == 1 && a.ddn % 2 == 0) ? 2 : 1;
+    a.hb = sw == 5 ? 1 : 0;
     // 128-column slabs only with two columns per lane (one wave per row)
     const int cw_eff = (cw == 128 && !(fast && a.row_cols == 2)) ? 64 : cw;
     a.nslab = (int)((a.ddn + cw_eff - 1) / cw_eff);
@@ -1430,6 +1980,11 @@ int launch_hub_mult(hphi_ham *h, const MultArgs &m)
     a.fb_ent = h->hub.fb_ent.as<uint32_t>();
     a.t0 = h->hub.t0;
     a.coef_cplx = m.coef_cplx;
+    a.lz = m.lz;
+    a.lz_alpha = m.lz_alpha;
+    a.lz_beta = m.lz_beta;
+    a.lz_q = m.lz_q;
+    a.lz_red = m.lz_red;
     const int nv = m.nvec * dtype_lanes(m.dtype);
     const bool f32 = dtype_is_f32(m.dtype);
     if (nv == 1) return f32 ? launch_hub_t<float, 1>(h, a, m.stream) : launch_hub_t<double, 1>(h, a, m.stream);

@@ -154,3 +154,78 @@ def test_hubbard_lanczos_f32_storage(api, ctx):
     r = api.lanczos(h, 200, seed=3, storage="f32")
     # FP32 vectors, FP64 scalars: the Ritz value sits within FP32 rounding of E0
     assert abs(r["energies"][0] - e0) < 1e-4 * abs(e0)
+
+
+@pytest.mark.parametrize("lx,ly,nu,nd", [(3, 4, 6, 5), (4, 4, 3, 5)])
+def test_hubbard_batched_list_walk_bit_identical(api, ctx, lx, ly, nu, nd):
+    # T_up with the batched list walk (hub_sweep 5) and T_dn with the batched
+    # row staging (hub_row_cols 5) keep every sum's order: real, complex and
+    # FP32 products, the fused Lanczos epilogue and dots, and the complex
+    # Taylor epilogue equal the two-list walk bit for bit
+    import torch
+    say("hub batched walk", lx, ly, nu, nd)
+    m = W.hubbard_square(lx, ly, 1.0, 4.0)
+    b = api.Basis.hubbard(ctx, m.n_sites, nu, nd)
+    h = api.Hamiltonian.hubbard(b, m)
+    ups, dns = O.hubbard_basis(m.n_sites, nu, nd)
+    base = dict(hub_slab_cols=128, hub_groups=128, hub_item_rows=32)
+    ins = [dev(W.random_vector(b.dim, 51)), dev(W.random_vector(b.dim, 52, np.complex128)),
+           dev(W.random_vector(b.dim, 53)).to(torch.float32)]
+    out = {}
+    for key, sch in (("two_list", dict(hub_row_cols=4, hub_sweep=3)), ("batched", dict(hub_row_cols=5, hub_sweep=5)),
+                     ("wave_owned", dict(hub_row_cols=5, hub_sweep=6))):
+        h.set_schedule(**base, **sch)
+        prods = [host(h.mult(x)) for x in ins]
+        lz = api.lanczos(h, 60, seed=4) if sch["hub_row_cols"] == 4 else None
+        psi = dev(W.random_vector(b.dim, 54, np.complex128))
+        te = api.time_evolve(h, psi, 3, dt=0.05, n_max=6)
+        out[key] = (prods, lz, host(psi), te)
+    a = out["two_list"]
+    for c in (out["batched"], out["wave_owned"]):
+        for x, y in zip(a[0], c[0]):
+            assert np.array_equal(x, y)
+        assert np.array_equal(a[2], c[2])
+    assert relmax(a[0][0], O.hubbard_hv(m, ups, dns, host(ins[0]))) < 1e-12
+
+
+def test_hubbard_lanczos_fused_update(api, ctx):
+    # with hub_row_cols 5 the Lanczos update (w -= alpha q, beta = |w|) runs
+    # inside the next product's rows kernel: same recurrence as the separate
+    # update kernel up to the order of the |w|^2 sum
+    say("hub lanczos fused")
+    m = W.hubbard_square(4, 4, 1.0, 4.0)
+    b = api.Basis.hubbard(ctx, 16, 3, 5)
+    h = api.Hamiltonian.hubbard(b, m)
+    ups, dns = O.hubbard_basis(16, 3, 5)
+    h.set_schedule(hub_row_cols=4)
+    ref = api.lanczos(h, 80, seed=6)
+    h.set_schedule(hub_row_cols=5)
+    fz = api.lanczos(h, 80, seed=6)
+    # rounding differences grow along a Lanczos sequence without
+    # reorthogonalization: early coefficients agree to rounding, the ground
+    # energy to the Lanczos bar
+    assert relmax(fz["alpha"][:20], ref["alpha"][:20]) < 1e-12
+    assert relmax(fz["beta"][:20], ref["beta"][:20]) < 1e-12
+    assert abs(fz["energies"][0] - ref["energies"][0]) < 1e-10
+    assert fz["fused_update"] and not ref["fused_update"]
+    # oracle Lanczos on the same start vector (SplitMix64 stream)
+    ro = O.lanczos(lambda x: O.hubbard_hv(m, ups, dns, x), O.splitmix_uniform(6, 0, b.dim), 20)
+    assert relmax(fz["alpha"][:20], ro["alpha"][:20]) < 1e-11
+    assert relmax(fz["beta"][1:20], ro["beta"][1:20]) < 1e-11
+    # fixed-order reductions: run to run and graph replay bit-identical
+    fz2 = api.lanczos(h, 80, seed=6)
+    fg = api.lanczos(h, 80, seed=6, use_graph=True)
+    for r in (fz2, fg):
+        assert np.array_equal(r["alpha"], fz["alpha"]) and np.array_equal(r["beta"], fz["beta"])
+    # Ritz vector from the second pass through the same fused steps
+    rv = api.lanczos(h, 200, seed=6, want_vector=True)
+    psi = host(rv["psi"])
+    assert abs(np.linalg.norm(psi) - 1.0) < 1e-12
+    res = O.hubbard_hv(m, ups, dns, psi) - rv["energies"][0] * psi
+    assert np.linalg.norm(res) < 1e-6
+    # convergence checks read the lagging iteration count correctly
+    rc = api.lanczos(h, 400, seed=6, check_every=10, tol=1e-12)
+    assert rc["converged"] and abs(rc["energies"][0] - rv["energies"][0]) < 1e-10
+    # FP32 vectors take the fused kernel too
+    r4 = api.lanczos(h, 200, seed=6, storage="f32")
+    assert abs(r4["energies"][0] - rv["energies"][0]) < 1e-4 * abs(rv["energies"][0])

@@ -288,7 +288,15 @@ def test_hubbard_schedules_bit_identical(api, ctx):
                 dict(hub_slab_cols=128, hub_groups=64, hub_item_rows=32, hub_row_cols=1, hub_sweep=2),
                 dict(hub_slab_cols=128, hub_groups=64, hub_item_rows=32, hub_row_cols=2, hub_sweep=1),
                 dict(hub_slab_cols=64, hub_groups=128, hub_item_rows=32, hub_row_cols=4, hub_sweep=4),
-                dict(hub_slab_cols=64, hub_groups=3, hub_item_rows=32, hub_row_cols=1, hub_sweep=4)]:
+                dict(hub_slab_cols=64, hub_groups=3, hub_item_rows=32, hub_row_cols=1, hub_sweep=4),
+                dict(hub_slab_cols=64, hub_groups=128, hub_item_rows=64, hub_row_cols=5, hub_sweep=3),
+                dict(hub_slab_cols=16, hub_groups=64, hub_item_rows=32, hub_row_cols=5, hub_sweep=1),
+                dict(hub_slab_cols=128, hub_groups=128, hub_item_rows=32, hub_row_cols=3, hub_sweep=5),
+                dict(hub_slab_cols=64, hub_groups=64, hub_item_rows=16, hub_row_cols=1, hub_sweep=5),
+                dict(hub_slab_cols=128, hub_groups=3, hub_item_rows=8, hub_row_cols=5, hub_sweep=5),
+                dict(hub_slab_cols=128, hub_groups=128, hub_item_rows=16, hub_row_cols=3, hub_sweep=6),
+                dict(hub_slab_cols=64, hub_groups=5, hub_item_rows=8, hub_row_cols=1, hub_sweep=6),
+                dict(hub_slab_cols=128, hub_groups=1, hub_item_rows=128, hub_row_cols=5, hub_sweep=6)]:
         h.set_schedule(**sch)
         assert h.get_schedule()["hub_slab_cols"] == sch["hub_slab_cols"]
         w = host(h.mult(v))
@@ -297,7 +305,7 @@ def test_hubbard_schedules_bit_identical(api, ctx):
             ups, dns = O.hubbard_basis(12, 6, 5)
             wo = O.hubbard_hv(m, ups, dns, host(v))
             assert relmax(w, wo) < 1e-12
-        if sch["hub_row_cols"] == 4 or sch.get("hub_sweep") == 4:
+        if sch["hub_row_cols"] >= 4 or sch.get("hub_sweep") == 4:
             # hop-ordered down slots / group tiles: another summation order
             assert relmax(w, ref) < 1e-12 and relmax(w, wo) < 1e-12, sch
         else:
@@ -305,7 +313,9 @@ def test_hubbard_schedules_bit_identical(api, ctx):
     with pytest.raises(api.HphiError):
         h.set_schedule(hub_slab_cols=12)
     with pytest.raises(api.HphiError):
-        h.set_schedule(hub_sweep=5)
+        h.set_schedule(hub_sweep=7)
+    with pytest.raises(api.HphiError):
+        h.set_schedule(hub_row_cols=6)
 
 
 def test_hubbard_4x4_full_size_sampled_rows(api, ctx):
