@@ -75,10 +75,10 @@ def parse():
 # counters (fetch 2.000, write 1.000). Valid only for the kernel sources and
 # schedule it was taken with; anything else reports null.
 HUB_TRAFFIC = {
-    "sources_sha256": {"kern_hub.hip": "02bd108530ba180399d5dd045aa30f96427ce6d2bff4ecc50bf61ca039b8bd4f",
+    "sources_sha256": {"kern_hub.hip": "211890a88634750dcf08c80062e0e5d7ef550f9cb7313f07e994b6e14bace2bd",
                        "kern_common.h": "3816ffad5e8dc11caca1db2d756bcb93808bf25ce51f6b61f1942c1d41a9b348"},
-    "schedule": {"hub_slab_cols": 128, "hub_groups": 128, "hub_item_rows": 16, "hub_row_cols": 5, "hub_sweep": 5},
-    "fetch_kib": 6.34693e+06 + 1.38191e+06, "write_kib": 1.32044e+06 + 2.67795e+06,
+    "schedule": {"hub_slab_cols": 128, "hub_groups": 128, "hub_item_rows": 16, "hub_row_cols": 5, "hub_sweep": 5, "hub_row_order": 2},
+    "fetch_kib": 5.77867e+06 + 1.3804e+06, "write_kib": 1.32052e+06 + 2.67795e+06,
     "fetch_factor": 2.0, "write_factor": 1.0,
 }
 

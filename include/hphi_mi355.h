@@ -185,6 +185,12 @@ void hphi_ham_free(hphi_ham *h);
  *                   (no LDS staging, no block barriers; the products are
  *                   bit-identical to 5, the fused dots sum in another
  *                   order)
+ *   hub_row_order   order in which the T_up kernels of hub_sweep 1, 3, 5
+ *                   and 6 take the up rows: 1 = index order, 2 = reverse
+ *                   Cuthill-McKee order of the up-species hop graph (rows
+ *                   processed close together share more neighbour rows, so
+ *                   more of them are still in L2); the products do not
+ *                   depend on it (each element's sum keeps its order)
  * Errors: INVALID_ARG (value outside its range). */
 typedef struct {
     int hub_slab_cols;
@@ -194,6 +200,7 @@ typedef struct {
     int spin_per_cu;
     int spin_implicit;
     int hub_sweep;
+    int hub_row_order;
 } hphi_schedule;
 
 int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s);

@@ -296,6 +296,97 @@ static void split_lists(const Species &sp, const std::vector<hphi_hop> &hops,
     }
 }
 
+// Reverse Cuthill-McKee order of an undirected graph given by adjacency
+// lists (Cuthill and McKee 1969; reversed as George recommends): level-order
+// traversal from a pseudo-peripheral node, each node's unvisited neighbours
+// taken by increasing degree, a new start per connected component, then the
+// whole sequence reversed. The start node comes from repeated breadth-first
+// passes (George and Liu): from a node of least degree, move to a node of
+// least degree in the last level while the number of levels grows.
+static std::vector<uint32_t> rcm_order(const std::vector<std::vector<uint32_t>> &adj)
+{
+    const size_t n = adj.size();
+    std::vector<uint32_t> order;
+    order.reserve(n);
+    std::vector<char> seen(n, 0);
+    std::vector<int> level(n, -1);
+    auto deg = [&](uint32_t x) { return adj[x].size(); };
+    // levels of a breadth-first pass restricted to unseen nodes
+    auto bfs_levels = [&](uint32_t s, std::vector<uint32_t> &last) {
+        std::vector<uint32_t> cur{s}, touched{s};
+        level[s] = 0;
+        int depth = 0;
+        last = cur;
+        while (!cur.empty()) {
+            std::vector<uint32_t> nxt;
+            for (uint32_t x : cur)
+                for (uint32_t y : adj[x])
+                    if (!seen[y] && level[y] < 0) {
+                        level[y] = depth + 1;
+                        nxt.push_back(y);
+                        touched.push_back(y);
+                    }
+            if (!nxt.empty()) last = nxt;
+            cur.swap(nxt);
+            if (!cur.empty()) ++depth;
+        }
+        for (uint32_t x : touched) level[x] = -1;
+        return depth;
+    };
+    for (size_t c0 = 0; c0 < n; ++c0) {
+        if (seen[c0]) continue;
+        // least-degree unseen node of this component as the first guess
+        uint32_t s = (uint32_t)c0;
+        {
+            std::vector<uint32_t> stack{s};
+            std::vector<uint32_t> mark;
+            level[s] = 0;
+            mark.push_back(s);
+            while (!stack.empty()) {
+                const uint32_t x = stack.back();
+                stack.pop_back();
+                if (deg(x) < deg(s)) s = x;
+                for (uint32_t y : adj[x])
+                    if (!seen[y] && level[y] < 0) {
+                        level[y] = 0;
+                        mark.push_back(y);
+                        stack.push_back(y);
+                    }
+            }
+            for (uint32_t x : mark) level[x] = -1;
+        }
+        std::vector<uint32_t> last;
+        int ecc = bfs_levels(s, last);
+        for (int guard = 0; guard < 16; ++guard) {
+            uint32_t best = last[0];
+            for (uint32_t x : last)
+                if (deg(x) < deg(best)) best = x;
+            std::vector<uint32_t> last2;
+            const int e2 = bfs_levels(best, last2);
+            if (e2 <= ecc) break;
+            s = best;
+            ecc = e2;
+            last.swap(last2);
+        }
+        // Cuthill-McKee from s
+        const size_t first = order.size();
+        order.push_back(s);
+        seen[s] = 1;
+        for (size_t k = first; k < order.size(); ++k) {
+            std::vector<uint32_t> nb;
+            for (uint32_t y : adj[order[k]])
+                if (!seen[y]) {
+                    seen[y] = 1;
+                    nb.push_back(y);
+                }
+            std::stable_sort(nb.begin(), nb.end(), [&](uint32_t a, uint32_t b) { return deg(a) < deg(b); });
+            order.insert(order.end(), nb.begin(), nb.end());
+        }
+    }
+    std::reverse(order.begin(), order.end());
+    return order;
+}
+
 static int build_hub_fast(hphi_ham *h)
 {
     const hphi_basis *b = h->basis;
@@ -388,6 +479,33 @@ static int build_hub_fast(hphi_ham *h)
         for (uint32_t x : mi[r]) tgt.push_back((uint32_t)((uint64_t)x * (uint64_t)dn.dim));
     }
     off[up.dim] = (uint32_t)tgt.size();
+    // the same lists in reverse Cuthill-McKee order of the up rows (the
+    // column kernels' processing order with hub_row_order 2): row rr_row[p]
+    // is processed at position p, its lists at rr_off[p] .. rr_off[p + 1].
+    // Built for up to 2^22 up rows (beyond, index order is used).
+    if (up.dim <= (int64_t(1) << 22)) {
+        std::vector<std::vector<uint32_t>> adj((size_t)up.dim);
+        for (int64_t r = 0; r < up.dim; ++r) {
+            adj[r] = pl[r];
+            adj[r].insert(adj[r].end(), mi[r].begin(), mi[r].end());
+        }
+        const std::vector<uint32_t> ord = rcm_order(adj);
+        std::vector<uint32_t> roff(up.dim + 1, 0), rmid(up.dim, 0), rent;
+        rent.reserve(tgt.size() + 16);
+        for (int64_t p = 0; p < up.dim; ++p) {
+            const uint32_t r = ord[p];
+            roff[p] = (uint32_t)rent.size();
+            rent.insert(rent.end(), tgt.begin() + off[r], tgt.begin() + mid[r]);
+            rmid[p] = (uint32_t)rent.size();
+            rent.insert(rent.end(), tgt.begin() + mid[r], tgt.begin() + off[r + 1]);
+        }
+        roff[up.dim] = (uint32_t)rent.size();
+        rent.resize(rent.size() + 16, 0u);
+        HPHI_TRY(upload(h->hub.rr_off, roff.data(), sizeof(uint32_t) * roff.size()));
+        HPHI_TRY(upload(h->hub.rr_mid, rmid.data(), sizeof(uint32_t) * rmid.size()));
+        HPHI_TRY(upload(h->hub.rr_ent, rent.data(), sizeof(uint32_t) * rent.size()));
+        HPHI_TRY(upload(h->hub.rr_row, ord.data(), sizeof(uint32_t) * ord.size()));
+    }
     // padding: the wave-owned column kernel reads each row's entries in
     // blocks of 16 that may run past the last list (row 0 targets, unused)
     tgt.resize(tgt.size() + 16, 0u);
@@ -530,6 +648,11 @@ int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s)
     if (s->hub_sweep) {
         if (s->hub_sweep < 1 || s->hub_sweep > 6) return fail(HPHI_ERR_INVALID_ARG, "hub_sweep %d", s->hub_sweep);
         n.hub_sweep = s->hub_sweep;
+    }
+    if (s->hub_row_order) {
+        if (s->hub_row_order != 1 && s->hub_row_order != 2)
+            return fail(HPHI_ERR_INVALID_ARG, "hub_row_order %d", s->hub_row_order);
+        n.hub_row_order = s->hub_row_order;
     }
     h->sched_cfg = n;
     return HPHI_OK;

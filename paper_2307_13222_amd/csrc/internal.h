@@ -131,6 +131,7 @@ struct HubTables {
     uint32_t fs_maxw = 0;                    // widest down chunk (plus + minus)
     DevMem fs_base, fs_wp, fs_wm, fs_ent;    // down: chunk base, widths, uint16 entries
     DevMem fu_off, fu_mid, fu_ent;           // up: row offsets, split points, targets
+    DevMem rr_off, rr_mid, rr_ent, rr_row;   // the same in reverse Cuthill-McKee row order; rr_row[p] = row
     // up species by groups of rows sharing the high half (rows
     // fg_rows[g] .. fg_rows[g + 1]): per row four consecutive lists,
     // in-group plus / in-group minus (local row) and far plus / far minus
@@ -173,7 +174,7 @@ struct hphi_ham {
     // defaults: 128-column slabs, 128 workgroups per XCD, 32-row items,
     // hop-ordered down slots, work-item queues with two columns per lane;
     // spin: 8 workgroups per CU
-    hphi_schedule sched_cfg{128, 128, 16, 5, 8, 0, 5};
+    hphi_schedule sched_cfg{128, 128, 16, 5, 8, 0, 5, 2};
     // scratch for reductions and work queues
     hphi::DevMem sched;         // unsigned [16]: per-XCD item queues + counter
     hphi::DevMem red_partial;   // double [kReduceSlots]

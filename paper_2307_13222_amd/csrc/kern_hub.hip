@@ -64,6 +64,7 @@ struct HubKArgs {
     double *lz_alpha, *lz_beta;
     const void *lz_q;      // q_{k-1}: v <- v - f q_{k-1} before the product
     Reduce lz_red;
+    const uint32_t *row_of;   // column kernels: row processed at position p (null: p)
 };
 
 template <typename S>
@@ -962,7 +963,7 @@ __global__ __launch_bounds__(256) void k_hub_cols_f(HubKArgs a)
         const uint32_t colb = (uint32_t)col * ESZ;
         for (int64_t r = r0 + wid * RPW + lane / LPR; r < r1; r += 4 * RPW) {
             if (!colok) continue;
-            const size_t me = (size_t)r * ddn + col;
+            const size_t me = (size_t)(a.row_of ? (int64_t)a.row_of[r] : r) * ddn + col;
             if constexpr (HB) {
                 static_assert(RPW == 1, "one wave per row");
                 const uint32_t eb = __builtin_amdgcn_readfirstlane(s_off[r - r0]);
@@ -1589,6 +1590,7 @@ __global__ __launch_bounds__(256) void k_hub_cols_s(HubKArgs a)
     cu32 *fo = (cu32 *)a.fu_off;
     cu32 *fm = (cu32 *)a.fu_mid;
     cu32 *fe = (cu32 *)a.fu_ent;
+    cu32 *rowm = (cu32 *)a.row_of;
     double c1 = 1.0, c2 = 0.0;
     if (a.ecoef) {
         c1 = a.ecoef[0];
@@ -1628,7 +1630,7 @@ __global__ __launch_bounds__(256) void k_hub_cols_s(HubKArgs a)
         for (int64_t r = r0; r < r1; ++r) {
             const uint32_t eb = fo[r], em = fm[r], ee = fo[r + 1];
             if (!colok) continue;
-            const size_t me = (size_t)r * ddn + col;
+            const size_t me = (size_t)(rowm ? (int64_t)rowm[r] : r) * ddn + col;
             const S *up = u ? u : w;
             S wv[K], uv[K], vv[K];
 #pragma unroll
@@ -1874,6 +1876,14 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
         else hipLaunchKernelGGL((k_hub_cols_g<S, false>), dim3(grid_g), dim3(256), 0, st, a);
         HPHI_HIP(hipGetLastError());
         return HPHI_OK;
+    }
+    if (fast && h->sched_cfg.hub_row_order == 2 && h->sched_cfg.hub_sweep != 2 && h->sched_cfg.hub_sweep != 4 &&
+        h->hub.rr_row.p) {
+        // reverse Cuthill-McKee processing order: lists by position, row map
+        a.fu_off = h->hub.rr_off.as<uint32_t>();
+        a.fu_mid = h->hub.rr_mid.as<uint32_t>();
+        a.fu_ent = h->hub.rr_ent.as<uint32_t>();
+        a.row_of = h->hub.rr_row.as<uint32_t>();
     }
     if (fast && h->sched_cfg.hub_sweep == 6) {
         // wave-owned items, scalar list walk: 128-column slabs with two

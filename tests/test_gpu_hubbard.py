@@ -172,8 +172,10 @@ def test_hubbard_batched_list_walk_bit_identical(api, ctx, lx, ly, nu, nd):
     ins = [dev(W.random_vector(b.dim, 51)), dev(W.random_vector(b.dim, 52, np.complex128)),
            dev(W.random_vector(b.dim, 53)).to(torch.float32)]
     out = {}
-    for key, sch in (("two_list", dict(hub_row_cols=4, hub_sweep=3)), ("batched", dict(hub_row_cols=5, hub_sweep=5)),
-                     ("wave_owned", dict(hub_row_cols=5, hub_sweep=6))):
+    for key, sch in (("two_list", dict(hub_row_cols=4, hub_sweep=3, hub_row_order=1)),
+                     ("batched", dict(hub_row_cols=5, hub_sweep=5, hub_row_order=1)),
+                     ("wave_owned", dict(hub_row_cols=5, hub_sweep=6, hub_row_order=1)),
+                     ("rcm", dict(hub_row_cols=5, hub_sweep=5, hub_row_order=2))):
         h.set_schedule(**base, **sch)
         prods = [host(h.mult(x)) for x in ins]
         lz = api.lanczos(h, 60, seed=4) if sch["hub_row_cols"] == 4 else None
@@ -181,7 +183,7 @@ def test_hubbard_batched_list_walk_bit_identical(api, ctx, lx, ly, nu, nd):
         te = api.time_evolve(h, psi, 3, dt=0.05, n_max=6)
         out[key] = (prods, lz, host(psi), te)
     a = out["two_list"]
-    for c in (out["batched"], out["wave_owned"]):
+    for c in (out["batched"], out["wave_owned"], out["rcm"]):
         for x, y in zip(a[0], c[0]):
             assert np.array_equal(x, y)
         assert np.array_equal(a[2], c[2])

@@ -296,7 +296,12 @@ def test_hubbard_schedules_bit_identical(api, ctx):
                 dict(hub_slab_cols=128, hub_groups=3, hub_item_rows=8, hub_row_cols=5, hub_sweep=5),
                 dict(hub_slab_cols=128, hub_groups=128, hub_item_rows=16, hub_row_cols=3, hub_sweep=6),
                 dict(hub_slab_cols=64, hub_groups=5, hub_item_rows=8, hub_row_cols=1, hub_sweep=6),
-                dict(hub_slab_cols=128, hub_groups=1, hub_item_rows=128, hub_row_cols=5, hub_sweep=6)]:
+                dict(hub_slab_cols=128, hub_groups=1, hub_item_rows=128, hub_row_cols=5, hub_sweep=6),
+                # reverse Cuthill-McKee processing order of the up rows
+                dict(hub_slab_cols=128, hub_groups=128, hub_item_rows=16, hub_row_cols=5, hub_sweep=5, hub_row_order=2),
+                dict(hub_slab_cols=16, hub_groups=64, hub_item_rows=32, hub_row_cols=1, hub_sweep=1, hub_row_order=2),
+                dict(hub_slab_cols=64, hub_groups=7, hub_item_rows=8, hub_row_cols=3, hub_sweep=3, hub_row_order=2),
+                dict(hub_slab_cols=128, hub_groups=32, hub_item_rows=16, hub_row_cols=5, hub_sweep=6, hub_row_order=2)]:
         h.set_schedule(**sch)
         assert h.get_schedule()["hub_slab_cols"] == sch["hub_slab_cols"]
         w = host(h.mult(v))
@@ -314,6 +319,9 @@ def test_hubbard_schedules_bit_identical(api, ctx):
         h.set_schedule(hub_slab_cols=12)
     with pytest.raises(api.HphiError):
         h.set_schedule(hub_sweep=7)
+    with pytest.raises(api.HphiError):
+        h.set_schedule(hub_row_order=3)
+    h.set_schedule(hub_row_order=1)
     with pytest.raises(api.HphiError):
         h.set_schedule(hub_row_cols=6)
 
