@@ -69,23 +69,25 @@ def parse():
     return a
 
 
-# HBM traffic of one H*v of the 4x4 Hubbard workload, from two rocprofv3 --pmc
-# passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, summed over the two H*v
-# kernels) scaled by the factors a plain 2 GiB device copy gives for the same
+# HBM traffic of one Lanczos step of the 4x4 Hubbard workload, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch of the
+# column kernel and of the rows kernel) scaled by the factors a plain 2 GiB device copy gives for the same
 # counters (fetch 2.000, write 1.000). Valid only for the kernel sources and
 # schedule it was taken with; anything else reports null.
 HUB_TRAFFIC = {
-    "sources_sha256": {"kern_hub.hip": "211890a88634750dcf08c80062e0e5d7ef550f9cb7313f07e994b6e14bace2bd",
+    "sources_sha256": {"kern_hub.hip": "4a83e0076f18f3f036926e8e499e072d4cbba1a8cc5706899a8c6fea5909aa54",
                        "kern_common.h": "3816ffad5e8dc11caca1db2d756bcb93808bf25ce51f6b61f1942c1d41a9b348"},
     "schedule": {"hub_slab_cols": 128, "hub_groups": 128, "hub_item_rows": 16, "hub_row_cols": 5, "hub_sweep": 5, "hub_row_order": 2},
-    "fetch_kib": 5.77867e+06 + 1.3804e+06, "write_kib": 1.32052e+06 + 2.67795e+06,
+    "cols_fetch_kib": 5.78114e+06, "cols_write_kib": 1.32052e+06,
+    "rows_fetch_kib": 1.37935e+06, "rows_write_kib": 2.67797e+06,
     "fetch_factor": 2.0, "write_factor": 1.0,
 }
 
 
-def hub_traffic(schedule) -> float:
-    """Measured HBM bytes per H*v launch pair, or None when the kernel
-    sources or the schedule differ from those the counters were taken on."""
+def hub_traffic(schedule, which: str = "pair") -> float:
+    """Measured HBM bytes per launch of the column kernel ("cols") or of the
+    rows + column launch pair ("pair"), or None when the kernel sources or
+    the schedule differ from those the counters were taken on."""
     import hashlib
     src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2307_13222_amd", "csrc")
     for f, h in HUB_TRAFFIC["sources_sha256"].items():
@@ -95,7 +97,9 @@ def hub_traffic(schedule) -> float:
     if any(schedule.get(k) != v for k, v in HUB_TRAFFIC["schedule"].items()):
         return None
     t = HUB_TRAFFIC
-    return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
+    fetch = t["cols_fetch_kib"] + (t["rows_fetch_kib"] if which == "pair" else 0.0)
+    write = t["cols_write_kib"] + (t["rows_write_kib"] if which == "pair" else 0.0)
+    return 1024.0 * (fetch * t["fetch_factor"] + write * t["write_factor"])
 
 
 def omp_threads() -> int:
@@ -173,7 +177,7 @@ def run_lanczos(a, api, ham, dim, iters, storage, wl, kernel, tune_dtype):
     for _ in range(a.warmup):
         api.lanczos(ham, iters, seed=1, storage=storage, stream=stream)
     torch.cuda.synchronize()
-    lat, hv_s, hv_n, energies, fused = [], 0.0, 0, [], False
+    lat, hv_s, hv_n, k2_s, energies, fused = [], 0.0, 0, 0.0, [], False
     t0 = time.perf_counter()
     for k in range(a.steps):
         s0 = time.perf_counter()
@@ -181,6 +185,7 @@ def run_lanczos(a, api, ham, dim, iters, storage, wl, kernel, tune_dtype):
         lat.append(time.perf_counter() - s0)
         hv_s += r["hv_seconds"]
         hv_n += r["hv_calls"]
+        k2_s += r["hv_second_kernel_seconds"]
         fused = r["fused_update"]
         energies.append(float(r["energies"][0]))
     torch.cuda.synchronize()
@@ -193,6 +198,21 @@ def run_lanczos(a, api, ham, dim, iters, storage, wl, kernel, tune_dtype):
     frac_fused = (1.0 - a.steps / max(1, hv_n)) if fused else 0.0
     alg_bytes = esize * dim * (2.0 + 2.0 * frac_fused)
     gbs = alg_bytes / hv_avg / 1e9
+    hub = ham.basis.kind == "hubbard"
+    if hub and k2_s > 0.0:
+        # dominant kernel: the T_up column kernel; its pass reads the rows
+        # kernel's partial W, V (the T_up gathers, once) and u = q_{k-1}
+        # (the epilogue; none in a solve's first product) and writes W
+        k2_avg = k2_s / max(1, hv_n)
+        cols_bytes = esize * dim * (4.0 - a.steps / max(1, hv_n))
+        roof = roofline(cols_bytes / k2_avg / 1e9, cols_bytes,
+                        f"k_hub_cols_f (T_up slab kernel with the Lanczos epilogue and FP64 dots; "
+                        f"{100 * k2_avg / hv_avg:.0f} % of a step)", hub_traffic(wl["schedule"], "cols"))
+        roof["ms"] = round(1e3 * k2_avg, 5)
+        pair = roofline(gbs, alg_bytes, kernel, hub_traffic(wl["schedule"], "pair"))
+    else:
+        roof = roofline(gbs, alg_bytes, kernel, None)
+        pair = None
     out = base_line(a, gbs, 1e3 * total / a.steps, storage, wl)
     out.update({"hbm_peak_frac": round(gbs / HBM_PEAK_GBS, 4),
                 "lanczos_solves_per_s": round(a.steps / total, 4),
@@ -201,8 +221,9 @@ def run_lanczos(a, api, ham, dim, iters, storage, wl, kernel, tune_dtype):
                 "hv_ms_avg": round(1e3 * hv_avg, 5), "e0": energies[0],
                 "fused_lanczos_update": fused,
                 "hv_only_gbs": round(2 * esize * dim / hv_avg / 1e9, 2),
-                "roofline": roofline(gbs, alg_bytes, kernel,
-                                     hub_traffic(wl["schedule"]) if ham.basis.kind == "hubbard" else None)})
+                "roofline": roof})
+    if pair is not None:
+        out["launch_pair"] = pair
     return out, energies
 
 

@@ -254,6 +254,9 @@ typedef struct {
                               previous step's update (w -= alpha q, beta =
                               |w|) in its rows kernel (Hubbard, one real
                               vector, hub_row_cols 5); hv_seconds includes it */
+    double hv_second_kernel_seconds; /* with time_kernels, Hubbard: summed
+                              durations of the column (T_up) kernel alone,
+                              from an event between the two launches       */
 } hphi_lanczos_info;
 
 /* Lanczos ground state (Sec. 1): v_0 = r/|r|; w = H v_k - beta_k v_{k-1};

@@ -32,7 +32,7 @@ class LanczosOpts(C.Structure):
 class LanczosInfo(C.Structure):
     _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("breakdown", C.c_int),
                 ("seconds", C.c_double), ("hv_seconds", C.c_double), ("hv_calls", C.c_int),
-                ("fused_update", C.c_int)]
+                ("fused_update", C.c_int), ("hv_second_kernel_seconds", C.c_double)]
 
 
 class BatchItem(C.Structure):

@@ -233,7 +233,8 @@ def lanczos(ham: Hamiltonian, max_iter: int, seed: int = 1, v0=None, storage: st
     return {"energies": e, "alpha": alpha[:n], "beta": beta[:n], "iterations": n,
             "converged": bool(info.converged), "breakdown": bool(info.breakdown),
             "seconds": info.seconds, "hv_seconds": info.hv_seconds, "hv_calls": info.hv_calls,
-            "fused_update": bool(info.fused_update), "psi": psi}
+            "fused_update": bool(info.fused_update),
+            "hv_second_kernel_seconds": info.hv_second_kernel_seconds, "psi": psi}
 
 
 def lanczos_batch(hams: Sequence[Hamiltonian], max_iter, seeds, keep_coefficients: bool = False,

@@ -720,10 +720,12 @@ struct LanczosRun {
     // the loop
     bool fused = false;
     std::vector<hipEvent_t> ev;   // pairs around each H*v
+    std::vector<hipEvent_t> evm;  // Hubbard: between the rows and the column kernel of each H*v
 
     ~LanczosRun()
     {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        for (hipEvent_t e : evm) (void)hipEventDestroy(e);
     }
 
     int mark()
@@ -735,16 +737,24 @@ struct LanczosRun {
         return HPHI_OK;
     }
 
-    int timed(double *seconds, int *calls)
+    // total H*v time; with the mid events also the time of the second
+    // (column) kernel alone
+    int timed(double *seconds, int *calls, double *second_kernel)
     {
-        double tot = 0.0;
+        double tot = 0.0, k2 = 0.0;
         for (size_t i = 0; i + 1 < ev.size(); i += 2) {
             float ms = 0.f;
             HPHI_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
             tot += ms;
+            if (evm.size() == ev.size() / 2) {
+                float m2 = 0.f;
+                HPHI_HIP(hipEventElapsedTime(&m2, evm[i / 2], ev[i + 1]));
+                k2 += m2;
+            }
         }
         *seconds = tot * 1e-3;
         *calls = (int)(ev.size() / 2);
+        *second_kernel = k2 * 1e-3;
         return HPHI_OK;
     }
 
@@ -802,7 +812,15 @@ struct LanczosRun {
             a.lz_q = q[prev].p;
             a.lz_red = reduce_of(h, lz->nrm);
         }
-        if (timing) HPHI_TRY(mark());
+        if (timing) {
+            HPHI_TRY(mark());
+            if (h->kind == 1) {
+                hipEvent_t e;
+                HPHI_HIP(hipEventCreate(&e));
+                evm.push_back(e);
+                a.ev_mid = e;
+            }
+        }
         HPHI_TRY(launch_mult(h, a));
         if (timing) HPHI_TRY(mark());
         if (psi && fz) HPHI_TRY(launch_lz_psi_accum(dt, lz, svec, dim, psi, q[cur].p, st));
@@ -922,9 +940,9 @@ int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *o, double *energies, int 
     const int ne = std::min(n_energies, n);
     if (ne > 0) HPHI_TRY(tridiag_lowest(ha.data(), hb.data(), n, ne, energies, nullptr));
     for (int i = ne; i < n_energies; ++i) energies[i] = NAN;
-    double hv_s = 0.0;
+    double hv_s = 0.0, hv_k2 = 0.0;
     int hv_n = 0;
-    if (L.timing) HPHI_TRY(L.timed(&hv_s, &hv_n));
+    if (L.timing) HPHI_TRY(L.timed(&hv_s, &hv_n, &hv_k2));
     L.timing = false;
     if (o->psi_dev && n > 0) {
         // second pass: same start vector and kernels, psi = sum_k s_k v_k
@@ -951,6 +969,7 @@ int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *o, double *energies, int 
         info->hv_seconds = hv_s;
         info->hv_calls = hv_n;
         info->fused_update = L.fused ? 1 : 0;
+        info->hv_second_kernel_seconds = hv_k2;
     }
     return HPHI_OK;
 }

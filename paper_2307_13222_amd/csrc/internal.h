@@ -218,6 +218,7 @@ struct MultArgs {
     double *lz_alpha, *lz_beta;
     const void *lz_q;
     Reduce lz_red;
+    hipEvent_t ev_mid;  // optional: recorded between the two kernels of a Hubbard H*v
 };
 bool hub_rows_fused_ok(hphi_ham *h, int nv);
 int launch_spin_mult(hphi_ham *h, const MultArgs &a);

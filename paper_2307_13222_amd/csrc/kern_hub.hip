@@ -65,6 +65,7 @@ struct HubKArgs {
     const void *lz_q;      // q_{k-1}: v <- v - f q_{k-1} before the product
     Reduce lz_red;
     const uint32_t *row_of;   // column kernels: row processed at position p (null: p)
+    hipEvent_t ev_mid;        // recorded between the rows and the column kernel (null: none)
 };
 
 template <typename S>
@@ -1828,6 +1829,7 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
                            128 * sizeof(S), st, a);
     }
     HPHI_HIP(hipGetLastError());
+    if (a.ev_mid) HPHI_HIP(hipEventRecord(a.ev_mid, st));
     // column kernel, geometry from the Hamiltonian's schedule
     const int cw = h->sched_cfg.hub_slab_cols;
     const int groups = h->sched_cfg.hub_groups;
@@ -1995,6 +1997,7 @@ int launch_hub_mult(hphi_ham *h, const MultArgs &m)
     a.lz_beta = m.lz_beta;
     a.lz_q = m.lz_q;
     a.lz_red = m.lz_red;
+    a.ev_mid = m.ev_mid;
     const int nv = m.nvec * dtype_lanes(m.dtype);
     const bool f32 = dtype_is_f32(m.dtype);
     if (nv == 1) return f32 ? launch_hub_t<float, 1>(h, a, m.stream) : launch_hub_t<double, 1>(h, a, m.stream);
