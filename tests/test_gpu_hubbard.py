@@ -231,3 +231,37 @@ def test_hubbard_lanczos_fused_update(api, ctx):
     # FP32 vectors take the fused kernel too
     r4 = api.lanczos(h, 200, seed=6, storage="f32")
     assert abs(r4["energies"][0] - rv["energies"][0]) < 1e-4 * abs(rv["energies"][0])
+
+
+def test_hubbard_lanczos_fused_update_edges(api, ctx):
+    # the fused path's scalar step (and breakdown test) runs in the rows
+    # kernel's last block; the last step's update after the loop
+    say("hub lanczos fused edges")
+    m = W.hubbard_square(2, 3, 1.0, 4.0)
+    b = api.Basis.hubbard(ctx, 6, 2, 3)
+    h = api.Hamiltonian.hubbard(b, m)
+    h.set_schedule(hub_row_cols=5)
+    ups, dns = O.hubbard_basis(6, 2, 3)
+    hv = lambda x: O.hubbard_hv(m, ups, dns, x)
+    v0 = O.splitmix_uniform(9, 0, b.dim)
+    ro = O.lanczos(hv, v0, 3)
+    for n in (1, 2, 3):
+        r = api.lanczos(h, n, seed=9)
+        assert r["fused_update"] and r["iterations"] == n
+        assert relmax(r["alpha"], ro["alpha"][:n]) < 1e-12
+        if n > 1:
+            assert relmax(r["beta"][1:], np.asarray(ro["beta"])[1:n]) < 1e-12
+    # more steps than states: the recurrence breaks down (beta -> 0) inside
+    # the fused kernel; the lowest level is still found
+    m2 = W.hubbard_square(2, 2, 1.0, 4.0)
+    b2 = api.Basis.hubbard(ctx, 4, 1, 1)
+    h2 = api.Hamiltonian.hubbard(b2, m2)
+    h2.set_schedule(hub_row_cols=5)
+    u2, d2 = O.hubbard_basis(4, 1, 1)
+    e = np.linalg.eigvalsh(O.hubbard_sparse(m2, u2, d2).toarray())
+    r2 = api.lanczos(h2, 40, seed=2)
+    assert r2["fused_update"] and r2["breakdown"] and r2["iterations"] <= b2.dim
+    assert abs(r2["energies"][0] - e[0]) < 1e-10
+    r3 = api.lanczos(h2, 40, seed=2, want_vector=True)
+    psi = host(r3["psi"])
+    assert np.linalg.norm(O.hubbard_hv(m2, u2, d2, psi) - e[0] * psi) < 1e-8
