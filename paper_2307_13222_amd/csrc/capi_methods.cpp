@@ -22,8 +22,8 @@ extern "C" {
 // same polynomial as the term-by-term sum), one block H*V per order with the
 // epilogue w = c1 H y + c2 phi fused into the kernel. The first order of each
 // step applies H to the normalized state itself, so its raw FP64 dots give
-// <phi|H|phi> and |H phi|^2 at beta_{k-1}; the last order's output dots give
-// the squared norm N_k = D_k of U_c phi.
+// <phi|H|phi> and |H phi|^2 at beta_{k-1}; a streaming pass over the last
+// order's stored output gives the squared norm N_k = D_k of U_c phi.
 int hphi_ctpq(hphi_ham *h, const hphi_ctpq_opts *o, void *phi_dev, double *D_out, double *E_out,
               double *E2_out)
 {
@@ -92,27 +92,23 @@ int hphi_ctpq(hphi_ham *h, const hphi_ctpq_opts *o, void *phi_dev, double *D_out
                 a.dots = 1;
                 a.dot_raw = 1;
                 a.red = reduce_at(h, res_first.as<double>());
-            } else if (last) {
-                a.dots = 1;
-                a.dot_raw = 0;
-                a.red = reduce_at(h, res_last.as<double>());
             } else {
                 a.red = reduce_at(h, h->red_result.as<double>());
             }
+            (void)last;
             HPHI_TRY(launch_mult(h, a));
             if (k == K) break;
             src = Y[yb];
             yb ^= 1;
         }
-        if (k == K || n_top == 1) {
-            // norms of a first-order-only step need their own pass
-            if (k < K) HPHI_TRY(launch_dots(dt, nl, dim, Y[0], Y[0], reduce_at(h, res_last.as<double>()), 1, st));
-        }
         HPHI_HIP(hipMemcpyAsync(hf.data(), res_first.p, sizeof(double) * 2 * nl, hipMemcpyDeviceToHost, st));
         if (k < K) {
-            // the last order wrote Y[yb ^ 1]; its lanes' |.|^2 sit at res_last[nl + l]
+            // the last order wrote Y[yb ^ 1]; its lanes' |.|^2 from one
+            // streaming pass over the stored values (the fused dots of the
+            // wide block kernel cost more registers than this pass costs)
             void *out = Y[yb ^ 1];
-            double *nrm = res_last.as<double>() + (n_top == 1 ? 0 : nl);
+            HPHI_TRY(launch_dots(dt, nl, dim, out, out, reduce_at(h, res_last.as<double>()), 1, st));
+            double *nrm = res_last.as<double>();
             HPHI_HIP(hipMemcpyAsync(hl.data(), nrm, sizeof(double) * nl, hipMemcpyDeviceToHost, st));
             HPHI_TRY(launch_pair_rsqrt(nrm, d_lane_scale, nl, st));
             HPHI_TRY(launch_scale_lanes(dt, nl, dim, out, d_lane_scale, 0, st));

@@ -146,8 +146,10 @@ __global__ __launch_bounds__(kBlock) void k_spin_hv(SpinKArgs a)
         for (int j = 0; j < NV; ++j) hv[j] = acc[j] + diag * me[j];
         if (a.coef_cplx) {
             S uu[NV];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) uu[j] = (S)0;
             if (u) load_lanes<S, NV>(u + (size_t)r * NV, uu);
-            epilogue<S, NV>(hv, u ? uu : nullptr, 1, a.coef, out);
+            epilogue_r<S, NV>(hv, uu, u != nullptr, 1, a.coef, out);
         } else {
 #pragma unroll
             for (int j = 0; j < NV; ++j) out[j] = c1s * hv[j];
@@ -176,14 +178,23 @@ __global__ __launch_bounds__(kBlock) void k_spin_hv(SpinKArgs a)
         }
     }
     if constexpr (DOTS) {
-        // per-lane block sums, one lane at a time to bound LDS use
+        // per-lane sums: across each wave with shuffles (the accumulators
+        // stay in registers: every index is a compile-time constant), then
+        // over the block's waves in wave order
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
         for (int j = 0; j < NV; ++j) {
-            double vals[2] = {d0[j], d1[j]};
-            block_sum<2>(vals, sh_red);
-            if (threadIdx.x == 0) {
-                sh_blk[j] = vals[0];
-                sh_blk[NV + j] = vals[1];
+            const double s0 = wave_sum(d0[j]), s1 = wave_sum(d1[j]);
+            if (lane == 0) {
+                sh_red[wid * 2 * NV + j] = s0;
+                sh_red[wid * 2 * NV + NV + j] = s1;
             }
+        }
+        __syncthreads();
+        if (threadIdx.x < 2 * NV) {
+            double t = 0.0;
+            for (int w2 = 0; w2 < nw; ++w2) t += sh_red[w2 * 2 * NV + threadIdx.x];
+            sh_blk[threadIdx.x] = t;
         }
         __syncthreads();
         grid_finish(sh_blk, 2 * NV, a.red, sh_red);
