@@ -320,6 +320,9 @@ typedef struct {
  * Outputs (host, (k_steps + 1) * n_vec, row k = beta_k): D_out, E_out,
  * E2_out (any may be NULL). phi_dev (device, [dim][n_vec] complex of the
  * storage type) receives the final normalized states. Synchronous.
+ * Workspace (library-allocated for the call): two blocks of the caller's
+ * size, three for spin sectors with n_vec >= 4 on a stored basis (the first
+ * order's H Phi is kept for the <H>, <H^2> pass).
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
 int hphi_ctpq(hphi_ham *h, const hphi_ctpq_opts *opts, void *phi_dev,
               double *D_out, double *E_out, double *E2_out);

@@ -40,9 +40,15 @@ int hphi_ctpq(hphi_ham *h, const hphi_ctpq_opts *o, void *phi_dev, double *D_out
     const int dt = o->storage, nv = o->n_vec, nl = 2 * nv;
     const int64_t dim = h->basis->dim;
     const size_t bytes = (size_t)dim * nl * dtype_size(dt);
-    DevMem y1, y2, scal, res_first, res_last;
+    DevMem y1, y2, yraw, scal, res_first, res_last;
     HPHI_TRY(y1.alloc(bytes));
     HPHI_TRY(y2.alloc(bytes));
+    // wide spin blocks: the first order stores H phi itself and a streaming
+    // pass takes <phi|H phi>, |H phi|^2 from it (the same FP32/FP64 values
+    // the fused dots would use; the block kernel with 2 x nl FP64 dot
+    // accumulators per thread runs far fewer waves)
+    const bool raw_dots = h->kind == 0 && nl >= 8 && spin_stored_path(h);
+    if (raw_dots) HPHI_TRY(yraw.alloc(bytes));
     HPHI_TRY(scal.alloc(sizeof(double) * (2 * (size_t)o->n_max + 2 + 64)));
     HPHI_TRY(res_first.alloc(sizeof(double) * 2 * 64));
     HPHI_TRY(res_last.alloc(sizeof(double) * 2 * 64));
@@ -88,15 +94,18 @@ int hphi_ctpq(hphi_ham *h, const hphi_ctpq_opts *o, void *phi_dev, double *D_out
             a.u = A;
             a.coef = d_coef + 2 * n;
             a.stream = st;
-            if (first) {
+            if (first && !raw_dots) {
                 a.dots = 1;
                 a.dot_raw = 1;
                 a.red = reduce_at(h, res_first.as<double>());
             } else {
                 a.red = reduce_at(h, h->red_result.as<double>());
+                if (first) a.raw_out = yraw.p;
             }
             (void)last;
             HPHI_TRY(launch_mult(h, a));
+            if (first && raw_dots)
+                HPHI_TRY(launch_dots_xy_yy(dt, nl, dim, src, yraw.p, reduce_at(h, res_first.as<double>()), st));
             if (k == K) break;
             src = Y[yb];
             yb ^= 1;
@@ -107,7 +116,7 @@ int hphi_ctpq(hphi_ham *h, const hphi_ctpq_opts *o, void *phi_dev, double *D_out
             // streaming pass over the stored values (the fused dots of the
             // wide block kernel cost more registers than this pass costs)
             void *out = Y[yb ^ 1];
-            HPHI_TRY(launch_dots(dt, nl, dim, out, out, reduce_at(h, res_last.as<double>()), 1, st));
+            HPHI_TRY(launch_dots_xy_yy(dt, nl, dim, out, out, reduce_at(h, res_last.as<double>()), st));
             double *nrm = res_last.as<double>();
             HPHI_HIP(hipMemcpyAsync(hl.data(), nrm, sizeof(double) * nl, hipMemcpyDeviceToHost, st));
             HPHI_TRY(launch_pair_rsqrt(nrm, d_lane_scale, nl, st));

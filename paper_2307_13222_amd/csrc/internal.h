@@ -219,8 +219,10 @@ struct MultArgs {
     const void *lz_q;
     Reduce lz_red;
     hipEvent_t ev_mid;  // optional: recorded between the two kernels of a Hubbard H*v
+    void *raw_out;      // optional (spin, stored basis): H v before the epilogue
 };
 bool hub_rows_fused_ok(hphi_ham *h, int nv);
+bool spin_stored_path(const hphi_ham *h);
 int launch_spin_mult(hphi_ham *h, const MultArgs &a);
 int launch_spin_mult_implicit(hphi_ham *h, const MultArgs &a);
 int launch_hub_mult(hphi_ham *h, const MultArgs &a);
@@ -237,6 +239,10 @@ int launch_rng_uniform(int dtype, void *out, int64_t n, uint64_t seed, hipStream
 int launch_rng_cgauss(int dtype, void *out, int64_t dim, int nvec, uint64_t seed, hipStream_t st);
 int launch_dots(int dtype, int nlanes, int64_t rows, const void *x, const void *y, Reduce red,
                 int mode, hipStream_t st);   // mode 0: x.y per lane; 1: x.x per lane
+// x.y per lane into result[lane] and y.y into result[nlanes + lane]; one
+// thread per scalar of the flat [rows][nlanes] arrays (nlanes divides 256)
+int launch_dots_xy_yy(int dtype, int nlanes, int64_t rows, const void *x, const void *y, Reduce red,
+                      hipStream_t st);
 int launch_scale_lanes(int dtype, int nlanes, int64_t rows, void *x, const double *scale_dev,
                        int mode, hipStream_t st);   // mode 0: x *= s[lane]; 1: x *= 1/sqrt(s[lane])
 int launch_axpy_lanes(int dtype, int nlanes, int64_t rows, void *y, const void *x,

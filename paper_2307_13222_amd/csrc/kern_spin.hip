@@ -32,6 +32,7 @@ struct SpinKArgs {
     int dot_raw;   // dots of H v itself (1) or of the epilogue output (0)
     Reduce red;
     int coef_cplx;
+    void *raw_out;   // optional: H v itself (before the epilogue), same layout as w
 };
 
 // Load NV contiguous scalars at p (p aligned to min(16, NV * sizeof(S))).
@@ -161,6 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_spin_hv(SpinKArgs a)
             }
         }
         store_lanes<S, NV>(w + (size_t)r * NV, out);
+        if (a.raw_out) store_lanes<S, NV>(static_cast<S *>(a.raw_out) + (size_t)r * NV, hv);
         if (accp) {
             S aa[NV];
             load_lanes<S, NV>(accp + (size_t)r * NV, aa);
@@ -239,12 +241,22 @@ static int launch_spin_nv(int nv, const SpinKArgs &a, bool lds, int grid, size_t
     return fail(HPHI_ERR_UNSUPPORTED, "spin H*v: %d real lanes per state (supported 1,2,4,8,16,32)", nv);
 }
 
+// The stored-list kernel runs for a materialized basis with 32-bit states
+// unless the schedule asks for the implicit one.
+bool spin_stored_path(const hphi_ham *h)
+{
+    const Species &s = h->basis->sp[0];
+    return s.materialized() && s.state_bytes == 4 && s.d_hi_off32.p && !h->sched_cfg.spin_implicit;
+}
+
 int launch_spin_mult(hphi_ham *h, const MultArgs &m)
 {
     const hphi_basis *b = h->basis;
     const Species &s = b->sp[0];
-    if (!s.materialized() || s.state_bytes != 4 || !s.d_hi_off32.p || h->sched_cfg.spin_implicit)
+    if (!spin_stored_path(h)) {
+        if (m.raw_out) return fail(HPHI_ERR_UNSUPPORTED, "raw product output needs the stored-list spin kernel");
         return launch_spin_mult_implicit(h, m);
+    }
     SpinKArgs a{};
     a.states = s.d_states.as<uint32_t>();
     a.dim = s.dim;
@@ -265,6 +277,7 @@ int launch_spin_mult(hphi_ham *h, const MultArgs &m)
     a.dot_raw = m.dot_raw;
     a.red = m.red;
     a.coef_cplx = m.coef_cplx;
+    a.raw_out = m.raw_out;
     const int nv = m.nvec * dtype_lanes(m.dtype);
     size_t tab = sizeof(uint32_t) * ((size_t(1) << s.n_lo) + (size_t(1) << s.n_hi));
     bool lds = tab <= 96 * 1024;

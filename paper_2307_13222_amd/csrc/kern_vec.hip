@@ -113,6 +113,60 @@ int launch_dots(int dtype, int nlanes, int64_t rows, const void *x, const void *
     return dots_t<double>(nlanes, rows, x, y, red, mode, st);
 }
 
+// Per-lane x.y and y.y over flat [rows][NL] arrays: thread t always sees
+// lane t % NL (the block size is a multiple of NL), so each thread keeps two
+// FP64 sums; the block adds its threads of one lane in thread order, the
+// last block adds the blocks' partials in block order.
+template <typename S, int NL>
+__global__ __launch_bounds__(kBlock) void k_dots_xy_yy(const S *x, const S *y, int64_t rows, Reduce red)
+{
+    __shared__ double sh[2 * kBlock];
+    __shared__ double blk[2 * NL];
+    __shared__ double shr[kBlock / kWave * 2];
+    const int64_t n = rows * NL;
+    double a0 = 0.0, a1 = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const double yv = (double)y[t];
+        a0 += (double)x[t] * yv;
+        a1 += yv * yv;
+    }
+    sh[threadIdx.x] = a0;
+    sh[kBlock + threadIdx.x] = a1;
+    __syncthreads();
+    if (threadIdx.x < NL) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int k = threadIdx.x; k < kBlock; k += NL) {
+            s0 += sh[k];
+            s1 += sh[kBlock + k];
+        }
+        blk[threadIdx.x] = s0;
+        blk[NL + threadIdx.x] = s1;
+    }
+    __syncthreads();
+    grid_finish(blk, 2 * NL, red, shr);
+}
+
+int launch_dots_xy_yy(int dtype, int nl, int64_t rows, const void *x, const void *y, Reduce red, hipStream_t st)
+{
+    if (nl < 1 || nl > 64 || kBlock % nl != 0) return fail(HPHI_ERR_UNSUPPORTED, "dots: %d lanes", nl);
+    const int g = grid_for(rows * nl, 4);
+    const bool f32 = dtype_is_f32(dtype);
+#define XY_CASE(N)                                                                                             \
+    case N:                                                                                                    \
+        if (f32) hipLaunchKernelGGL((k_dots_xy_yy<float, N>), dim3(g), dim3(kBlock), 0, st, (const float *)x,  \
+                                    (const float *)y, rows, red);                                              \
+        else hipLaunchKernelGGL((k_dots_xy_yy<double, N>), dim3(g), dim3(kBlock), 0, st, (const double *)x,   \
+                                (const double *)y, rows, red);                                                 \
+        break;
+    switch (nl) {
+        XY_CASE(1) XY_CASE(2) XY_CASE(4) XY_CASE(8) XY_CASE(16) XY_CASE(32) XY_CASE(64)
+    default: return fail(HPHI_ERR_UNSUPPORTED, "dots: %d lanes", nl);
+    }
+#undef XY_CASE
+    HPHI_HIP(hipGetLastError());
+    return HPHI_OK;
+}
+
 // x[r, l] *= s[l] (mode 0) or 1/sqrt(s[l]) (mode 1); s per lane on device.
 template <typename S>
 __global__ void k_scale_lanes(S *x, int64_t rows, int nl, const double *s, int mode)
