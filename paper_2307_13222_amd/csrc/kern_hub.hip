@@ -804,6 +804,81 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fz(HubKArgs a)
     }
 }
 
+// Rows kernel for NV > 1 interleaved lanes whose full row does not fit LDS
+// (a complex FP64 row of the 4x4 sector is 206 KB): T_dn and U are real,
+// so each lane of the row is a separate real row. Per row, lane by lane:
+// stage the lane (stride NV; the row's cache lines stay in L2 between the
+// lanes) in rounds of E loads per thread, gather its hop-ordered slots, and
+// write the lane of W. Same slots, sums and order as k_hub_rows_fb per lane.
+template <typename S, int NV, int E>
+__global__ __launch_bounds__(1024) void k_hub_rows_fl(HubKArgs a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int64_t ddn = a.ddn;
+    const int64_t nch = (ddn + 63) >> 6;
+    S *s_row = reinterpret_cast<S *>(smem_raw);
+    uint32_t *s_base = reinterpret_cast<uint32_t *>(s_row + (ddn + 1));
+    uint32_t *s_w = s_base + nch;
+    uint16_t *s_d = reinterpret_cast<uint16_t *>(s_w + nch);
+    const S *__restrict__ v = static_cast<const S *>(a.v);
+    S *__restrict__ w = static_cast<S *>(a.w);
+    const S nt0 = (S)(-a.t0);
+    const int T = blockDim.x;
+    const int tid = threadIdx.x;
+    const uint32_t nrow = (uint32_t)ddn;
+    for (int64_t j = tid; j < nch; j += T) {
+        s_base[j] = a.fb_base[j];
+        s_w[j] = a.fb_w[j];
+    }
+    for (int64_t c = tid; c < ddn; c += T) s_d[c] = (uint16_t)a.dns[c];
+    if (tid == 0) s_row[nrow] = (S)0;
+    auto load_col = [&](int64_t c, uint4 (&q)[4], uint32_t &nq) {
+        nq = 0;
+        if (c >= ddn) return;
+        const uint32_t wc = s_w[c >> 6];
+        nq = wc >> 3;
+        const uint4 *p = reinterpret_cast<const uint4 *>(a.fb_ent + s_base[c >> 6] + (uint32_t)(c & 63) * (wc >> 1));
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+            if ((uint32_t)g < nq) q[g] = p[g];
+    };
+    const uint32_t rbytes = nrow * NV * (uint32_t)sizeof(S);
+    for (int64_t ru = blockIdx.x; ru < a.dup; ru += gridDim.x) {
+        const __amdgpu_buffer_rsrc_t rv = buf_rsrc(v + (size_t)ru * nrow * NV, rbytes);
+        const uint32_t uu = a.ups[ru];
+        for (int ln = 0; ln < NV; ++ln) {
+            for (uint32_t base = 0; base < nrow; base += (uint32_t)E * T) {
+                S tv[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const uint32_t i = base + (uint32_t)e * T + tid;
+                    tv[e] = buf_ld<S>(rv, ((i < nrow ? i : nrow - 1) * NV + ln) * (uint32_t)sizeof(S));
+                }
+                if (base == 0) __syncthreads();    // every gather of the previous lane has finished
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const uint32_t i = base + (uint32_t)e * T + tid;
+                    if (i < nrow) s_row[i] = tv[e];
+                }
+            }
+            uint4 cur[4], nxt[4];
+            uint32_t ncur, nnxt;
+            load_col(tid, cur, ncur);
+            __syncthreads();
+            for (int64_t c = tid; c < ddn; c += T) {
+                load_col(c + T, nxt, nnxt);
+                S acc[1] = {(S)0};
+                fb_gather<S, 1>(cur, ncur, s_row, acc);
+                const S dg = hub_diag<S>(a, uu, (uint32_t)s_d[c]);
+                w[((size_t)ru * ddn + c) * NV + ln] = dg * s_row[c] + nt0 * acc[0];
+#pragma unroll
+                for (int g = 0; g < 4; ++g) cur[g] = nxt[g];
+                ncur = nnxt;
+            }
+        }
+    }
+}
+
 // Deep variant: each lane issues every table load of CPT columns (up to 32
 // entries each) before the first gather, then splits the sums at the sign
 // boundary. Used when the widest chunk has at most 32 entries.
@@ -1775,10 +1850,17 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
     if (grid_r > a.dup) grid_r = a.dup;
     int threads = 1024;
     const size_t fast_row_bytes = (size_t)(a.ddn + 1) * NV * sizeof(S);
-    const bool fast = h->hub.uniform_t && fast_row_bytes <= 160 * 1024 &&
-                      (unsigned __int128)a.dup * a.ddn * NV * sizeof(S) < ((unsigned __int128)1 << 32);
+    // uniform |t| tables and 32-bit byte offsets: the fast column kernels;
+    // the fast rows kernels also need the whole NV-lane row in LDS
+    const bool fast_cols = h->hub.uniform_t &&
+                           (unsigned __int128)a.dup * a.ddn * NV * sizeof(S) < ((unsigned __int128)1 << 32);
+    const bool fast = fast_cols && fast_row_bytes <= 160 * 1024;
     const int rmode = h->sched_cfg.hub_row_cols;
     const size_t fm_bytes = fast_row_bytes + 8 * (size_t)((a.ddn + 63) / 64) + 2 * (size_t)a.ddn + 16;
+    // one lane of the row in LDS (rows kernel for wide rows of NV > 1 lanes)
+    const size_t fl_bytes = (size_t)(a.ddn + 1) * sizeof(S) + 8 * (size_t)((a.ddn + 63) / 64) + 2 * (size_t)a.ddn + 16;
+    const bool lane_rows = NV > 1 && !fast && fast_cols && rmode >= 4 && h->hub.fb_ok && fl_bytes <= 160 * 1024 &&
+                           h->basis->n_sites <= 16;
     if (a.lz_q) {
         // fused Lanczos update: only where hub_rows_fused_ok holds
         if constexpr (NV == 1) {
@@ -1793,6 +1875,13 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
             else go(k_hub_rows_fz<S, 13>);
         } else {
             return fail(HPHI_ERR_UNSUPPORTED, "fused Lanczos update takes one real vector");
+        }
+    } else if (lane_rows) {
+        if constexpr (NV > 1) {
+            hipFuncSetAttribute((const void *)k_hub_rows_fl<S, NV, 13>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)fl_bytes);
+            hipLaunchKernelGGL((k_hub_rows_fl<S, NV, 13>), dim3((unsigned)std::min<int64_t>(ncu, a.dup)),
+                               dim3(threads), fl_bytes, st, a);
         }
     } else if (fast && rmode == 5 && h->hub.fb_ok && fm_bytes <= 160 * 1024 && h->basis->n_sites <= 16 &&
         a.ddn * NV <= 16 * (int64_t)threads) {
@@ -1833,7 +1922,7 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
     // column kernel, geometry from the Hamiltonian's schedule
     const int cw = h->sched_cfg.hub_slab_cols;
     const int groups = h->sched_cfg.hub_groups;
-    if (fast && h->sched_cfg.hub_sweep == 2 && !a.coef_cplx) {
+    if (fast_cols && h->sched_cfg.hub_sweep == 2 && !a.coef_cplx) {
         // persistent sweep: hub_groups row ranges, each within the staging arrays
         int64_t rows = (a.dup + groups - 1) / groups;
         if (rows > kColsRows) rows = kColsRows;
@@ -1860,7 +1949,7 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
         HPHI_HIP(hipGetLastError());
         return HPHI_OK;
     }
-    if (fast && h->sched_cfg.hub_sweep == 4 && NV == 1 && !a.coef_cplx && h->hub.fg_ok && a.ddn % 2 == 0 &&
+    if (fast_cols && h->sched_cfg.hub_sweep == 4 && NV == 1 && !a.coef_cplx && h->hub.fg_ok && a.ddn % 2 == 0 &&
         h->hub.fg_max_rows <= kGTileRows && h->hub.fg_max_ent <= (uint32_t)kGEnt) {
         // group tiles: items (64-column slab, up group)
         a.fg_rows = h->hub.fg_rows.as<uint32_t>();
@@ -1879,7 +1968,7 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
         HPHI_HIP(hipGetLastError());
         return HPHI_OK;
     }
-    if (fast && h->sched_cfg.hub_row_order == 2 && h->sched_cfg.hub_sweep != 2 && h->sched_cfg.hub_sweep != 4 &&
+    if (fast_cols && h->sched_cfg.hub_row_order == 2 && h->sched_cfg.hub_sweep != 2 && h->sched_cfg.hub_sweep != 4 &&
         h->hub.rr_row.p) {
         // reverse Cuthill-McKee processing order: lists by position, row map
         a.fu_off = h->hub.rr_off.as<uint32_t>();
@@ -1887,7 +1976,7 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
         a.fu_ent = h->hub.rr_ent.as<uint32_t>();
         a.row_of = h->hub.rr_row.as<uint32_t>();
     }
-    if (fast && h->sched_cfg.hub_sweep == 6) {
+    if (fast_cols && h->sched_cfg.hub_sweep == 6) {
         // wave-owned items, scalar list walk: 128-column slabs with two
         // columns per lane (one real vector, even row length), else 64
         const bool two = NV == 1 && a.ddn % 2 == 0 && cw == 128;
@@ -1926,14 +2015,14 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
     a.row_cols = ((sw == 3 || sw == 5) && NV == 1 && a.ddn % 2 == 0) ? 2 : 1;
     a.hb = sw == 5 ? 1 : 0;
     // 128-column slabs only with two columns per lane (one wave per row)
-    const int cw_eff = (cw == 128 && !(fast && a.row_cols == 2)) ? 64 : cw;
+    const int cw_eff = (cw == 128 && !(fast_cols && a.row_cols == 2)) ? 64 : cw;
     a.nslab = (int)((a.ddn + cw_eff - 1) / cw_eff);
     const int64_t grid_c = 8 * (int64_t)groups;
     const int64_t nitems = (int64_t)a.nslab * ((a.dup + item_rows - 1) / item_rows);
     if (a.nd && nitems * 2 * NV > (int64_t)kReduceSlots)
         return fail(HPHI_ERR_UNSUPPORTED, "Hubbard column items beyond the reduction scratch");
     a.sched = h->sched.as<unsigned>();
-    if (fast) {
+    if (fast_cols) {
         switch (cw_eff) {
         case 8: launch_cols_f<S, NV, 8>(a, (int)grid_c, st); break;
         case 128: launch_cols_f128<S, NV>(a, (int)grid_c, st); break;

@@ -265,3 +265,23 @@ def test_hubbard_lanczos_fused_update_edges(api, ctx):
     r3 = api.lanczos(h2, 40, seed=2, want_vector=True)
     psi = host(r3["psi"])
     assert np.linalg.norm(O.hubbard_hv(m2, u2, d2, psi) - e[0] * psi) < 1e-8
+
+
+@pytest.mark.parametrize("nu,nd", [(1, 7), (2, 7)])
+def test_hubbard_complex_wide_rows(api, ctx, nu, nd):
+    # complex128 rows of 11440 down states (183 KB) exceed LDS: the rows
+    # kernel stages one lane (re, im) at a time; the slab kernel takes the
+    # uniform-|t| path
+    say("hub complex wide rows", nu, nd)
+    m = W.hubbard_square(4, 4, 1.0, 4.0)
+    b = api.Basis.hubbard(ctx, 16, nu, nd)
+    h = api.Hamiltonian.hubbard(b, m)
+    ups, dns = O.hubbard_basis(16, nu, nd)
+    vc = W.random_vector(b.dim, 61, np.complex128)
+    wc = host(h.mult(dev(vc)))
+    assert relmax(wc, O.hubbard_hv(m, ups, dns, vc)) < 1e-12
+    # the same product through the general rows kernel (hop lists in order)
+    h.set_schedule(hub_row_cols=1)
+    wg = host(h.mult(dev(vc)))
+    assert relmax(wg, O.hubbard_hv(m, ups, dns, vc)) < 1e-12
+    h.set_schedule(hub_row_cols=5)
