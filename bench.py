@@ -75,11 +75,11 @@ def parse():
 # counters (fetch 2.000, write 1.000). Valid only for the kernel sources and
 # schedule it was taken with; anything else reports null.
 HUB_TRAFFIC = {
-    "sources_sha256": {"kern_hub.hip": "4a83e0076f18f3f036926e8e499e072d4cbba1a8cc5706899a8c6fea5909aa54",
+    "sources_sha256": {"kern_hub.hip": "3080a3910a63c9b65bbaec756bc6a2d721e2101670b7a961501e0666dcc009a7",
                        "kern_common.h": "3816ffad5e8dc11caca1db2d756bcb93808bf25ce51f6b61f1942c1d41a9b348"},
     "schedule": {"hub_slab_cols": 128, "hub_groups": 128, "hub_item_rows": 16, "hub_row_cols": 5, "hub_sweep": 5, "hub_row_order": 2},
-    "cols_fetch_kib": 5.78114e+06, "cols_write_kib": 1.32052e+06,
-    "rows_fetch_kib": 1.37935e+06, "rows_write_kib": 2.67797e+06,
+    "cols_fetch_kib": 5.77871e+06, "cols_write_kib": 1.32054e+06,
+    "rows_fetch_kib": 1.37983e+06, "rows_write_kib": 2.67796e+06,
     "fetch_factor": 2.0, "write_factor": 1.0,
 }
 
@@ -260,9 +260,21 @@ def main():
         ham = api.Hamiltonian.hubbard(basis, m)
         wl = {"workload": "hubbard_4x4_pbc_t1_U4_half_filling", "dim": basis.dim, "lanczos_iters": iters,
               "storage": "f64", "lattice": "square 4x4", "n_up": 8, "n_dn": 8}
-        out, _ = run_lanczos(a, api, ham, basis.dim, iters, "f64", wl,
-                             "H*v launch pair = k_hub_rows_fz (previous step's Lanczos update fused into the T_dn/U "
-                             "rows kernel) + k_hub_cols_f (T_up slab kernel, epilogue and FP64 dots)", "f64")
+        out, e64 = run_lanczos(a, api, ham, basis.dim, iters, "f64", wl,
+                               "H*v launch pair = k_hub_rows_fz (previous step's Lanczos update fused into the T_dn/U "
+                               "rows kernel) + k_hub_cols_f (T_up slab kernel, epilogue and FP64 dots)", "f64")
+        # the same solves with FP32 vector storage (FP64 alpha/beta, dots
+        # and tridiagonal), outside the timed FP64 region
+        ts, hv32, e32 = [], [], []
+        for k in range(max(1, min(a.steps, 3))):
+            r = api.lanczos(ham, iters, seed=1 + k, storage="f32", time_kernels=True)
+            ts.append(r["seconds"])
+            hv32.append(r["hv_seconds"] / max(1, r["hv_calls"]))
+            e32.append(float(r["energies"][0]))
+        out["fp32_storage"] = {"solve_ms_p50": round(1e3 * float(np.median(ts)), 3),
+                               "lanczos_solves_per_s": round(1.0 / float(np.median(ts)), 4),
+                               "hv_ms_avg": round(1e3 * float(np.mean(hv32)), 5),
+                               "e0": e32[0], "abs_dE0_vs_fp64_same_seed": abs(e32[0] - e64[0])}
     elif a.workload == "heisenberg16":
         iters = a.iters or 200
         m = W.heisenberg_chain(16)
