@@ -285,3 +285,29 @@ def test_hubbard_complex_wide_rows(api, ctx, nu, nd):
     wg = host(h.mult(dev(vc)))
     assert relmax(wg, O.hubbard_hv(m, ups, dns, vc)) < 1e-12
     h.set_schedule(hub_row_cols=5)
+
+
+def test_hubbard_4x4_complex_full_size_sampled_rows(api, ctx):
+    # the complex FP64 product of the full half-filled 4x4 sector (the real-time
+    # evolution workload): lane-by-lane rows kernel + complex slab kernel
+    import torch
+    say("hub 4x4 complex full size")
+    m = W.hubbard_square(4, 4, 1.0, 4.0)
+    b = api.Basis.hubbard(ctx, 16, 8, 8)
+    h = api.Hamiltonian.hubbard(b, m)
+    ups, dns = O.hubbard_basis(16, 8, 8)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    v = torch.complex(torch.rand(b.dim, dtype=torch.float64, device="cuda", generator=g) - 0.5,
+                      torch.rand(b.dim, dtype=torch.float64, device="cuda", generator=g) - 0.5)
+    w = h.mult(v)
+    assert torch.equal(w, h.mult(v))
+    rng = np.random.default_rng(9)
+    rows = np.concatenate([[0, b.dim - 1], rng.integers(0, b.dim, 2000)])
+    wmax = float(w.abs().max())
+    errs = []
+    for r in rows:
+        cols, vals = O.hubbard_row(m, ups, dns, int(r) // 12870, int(r) % 12870)
+        vv = host(v[torch.from_numpy(cols).cuda()])
+        errs.append(abs(complex(w[int(r)]) - complex(np.dot(vals, vv))))
+    assert max(errs) / wmax < 1e-12
+    del v, w
