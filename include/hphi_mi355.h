@@ -422,7 +422,8 @@ typedef struct {
  * <b|x_j> are kept (scalar recurrences per shift on the device). A complex
  * b runs two sequences, from Re b and Im b, and D = D_Re + D_Im (exact for
  * the real symmetric Hamiltonians here; avoids the COCG breakdown b^T b = 0
- * of momentum excitations). D_out receives 2 * n_shift doubles (re, im);
+ * of momentum excitations; a part with norm <= tol |b| runs no sequence,
+ * its norm joins the residual). D_out receives 2 * n_shift doubles (re, im);
  * resid_out (nullable) the per-shift bound (|r_Re| + |r_Im|) / |b|;
  * info->iterations counts H*v calls of both sequences. b = 0 gives D = 0,
  * no iterations. b_dev: C128 vector, read only. Synchronous.

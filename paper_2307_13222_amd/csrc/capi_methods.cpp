@@ -386,6 +386,13 @@ int hphi_sqw(hphi_ham *h, const hphi_sqw_opts *o, const void *b_dev, const doubl
     const int check = 8;
     for (int part = 0; part < 2; ++part) {
         if (bn2[part] == 0.0) continue;     // D_part = 0, nothing to iterate
+        // a part below tol |b| (e.g. the rounding of sin(q x) at q = pi) is
+        // left out: x_part = 0 leaves the residual |b_part| < tol |b|,
+        // which is counted, and changes D by O(|b_part|^2)
+        if (std::sqrt(bn2[part]) <= o->tol * bnorm) {
+            for (int j = 0; j < n_shift; ++j) res[j] += std::sqrt(bn2[part]) / bnorm;
+            continue;
+        }
         if (part == 1) {
             double tmp;
             HPHI_TRY(start(1, &tmp));
