@@ -78,6 +78,9 @@ __global__ __launch_bounds__(kBlock) void k_cocg_init(const double *b, double *r
     }
 }
 
+// The streaming COCG kernels keep four independent elements (16 B each) in
+// flight per thread and trip; the tail loop takes the rest.
+
 // mu = p^T (z_s p - h) with h = H p; alpha_k = rho / mu.
 __global__ __launch_bounds__(kBlock) void k_cocg_mu(const double *p, const double *h, int64_t dim, CgDev *cg,
                                                     Reduce red)
@@ -85,16 +88,29 @@ __global__ __launch_bounds__(kBlock) void k_cocg_mu(const double *p, const doubl
     __shared__ double shr[kBlock / kWave * 4];
     __shared__ double blk[4];
     const cd zs = cg->zs;
+    const double2 *P = reinterpret_cast<const double2 *>(p);
+    const double2 *H = reinterpret_cast<const double2 *>(h);
     double a[2] = {0, 0};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const cd pv = {p[2 * i], p[2 * i + 1]};
-        const cd hv = {h[2 * i], h[2 * i + 1]};
-        const cd ap = csub(cmul(zs, pv), hv);
+    auto add = [&](double2 pp, double2 hh) {
+        const cd pv = {pp.x, pp.y};
+        const cd ap = csub(cmul(zs, pv), cd{hh.x, hh.y});
         const cd t = cmul(pv, ap);
         a[0] += t.re;
         a[1] += t.im;
+    };
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * st < dim; i += 4 * st) {
+        double2 pv[4], hv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            pv[u] = P[i + u * st];
+            hv[u] = H[i + u * st];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) add(pv[u], hv[u]);
     }
+    for (; i < dim; i += st) add(P[i], H[i]);
     block_sum<2>(a, shr);
     if (threadIdx.x == 0) { blk[0] = a[0]; blk[1] = a[1]; }
     __syncthreads();
@@ -112,54 +128,10 @@ __global__ __launch_bounds__(kBlock) void k_cocg_mu(const double *p, const doubl
     }
 }
 
-// r -= alpha (z_s p - h); rho' = r^T r, |r|^2, b^H r; beta = rho'/rho.
-__global__ __launch_bounds__(kBlock) void k_cocg_r(double *r, const double *p, const double *h, const double *b,
-                                                   int64_t dim, CgDev *cg, Reduce red)
+// Per-shift scalar recurrences (the threads of one block, one shift each at
+// a time) and the max residual over the unconverged shifts.
+__device__ void cocg_shifts_step(CgDev *cg, ShiftDev *sh, int nsh, double tol, double *smax)
 {
-    __shared__ double shr[kBlock / kWave * 8];
-    __shared__ double blk[8];
-    const cd zs = cg->zs, al = cg->alpha;
-    double a[5] = {0, 0, 0, 0, 0};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const cd pv = {p[2 * i], p[2 * i + 1]};
-        const cd hv = {h[2 * i], h[2 * i + 1]};
-        const cd ap = csub(cmul(zs, pv), hv);
-        cd rv = {r[2 * i], r[2 * i + 1]};
-        rv = csub(rv, cmul(al, ap));
-        r[2 * i] = rv.re;
-        r[2 * i + 1] = rv.im;
-        const cd bv = {b[2 * i], b[2 * i + 1]};
-        a[0] += rv.re * rv.re - rv.im * rv.im;
-        a[1] += 2 * rv.re * rv.im;
-        a[2] += rv.re * rv.re + rv.im * rv.im;
-        a[3] += bv.re * rv.re + bv.im * rv.im;      // conj(b) r
-        a[4] += bv.re * rv.im - bv.im * rv.re;
-    }
-    block_sum<5>(a, shr);
-    if (threadIdx.x == 0)
-        for (int t = 0; t < 5; ++t) blk[t] = a[t];
-    __syncthreads();
-    if (grid_finish(blk, 5, red, shr) && threadIdx.x == 0) {
-        const cd rho1 = {red.result[0], red.result[1]};
-        cg->rnorm2 = red.result[2];
-        cg->bhr = {red.result[3], red.result[4]};
-        if (cabs2(cg->rho) == 0.0) {
-            cg->breakdown = 1;
-            cg->beta = {0.0, 0.0};
-        } else {
-            cg->beta = cdiv(rho1, cg->rho);
-        }
-        cg->rho = rho1;
-        cg->iter += 1;
-        __threadfence();
-    }
-}
-
-// Per-shift scalar recurrences (one thread per shift) and the max residual.
-__global__ void k_cocg_shifts(CgDev *cg, ShiftDev *sh, int nsh, double tol)
-{
-    __shared__ double smax[256];
     const cd al = cg->alpha, be = cg->beta, alp = cg->alpha_prev, bep = cg->beta_prev;
     const cd bhr = cg->bhr;
     const double rn = sqrt(cg->rnorm2), bn = sqrt(cg->bnorm2);
@@ -190,20 +162,96 @@ __global__ void k_cocg_shifts(CgDev *cg, ShiftDev *sh, int nsh, double tol)
         double m = 0.0;
         for (int t = 0; t < (int)blockDim.x; ++t) m = fmax(m, smax[t]);
         cg->max_res = m;
+        __threadfence();
     }
 }
 
+// r -= alpha (z_s p - h); rho' = r^T r, |r|^2, b^H r; beta = rho'/rho; then
+// (last block) the per-shift recurrences.
+__global__ __launch_bounds__(kBlock) void k_cocg_r(double *r, const double *p, const double *h, const double *b,
+                                                   int64_t dim, CgDev *cg, ShiftDev *sh, int nsh, double tol,
+                                                   Reduce red)
+{
+    __shared__ double shr[kBlock / kWave * 8];
+    __shared__ double blk[8];
+    __shared__ double smax[kBlock];
+    const cd zs = cg->zs, al = cg->alpha;
+    const double2 *P = reinterpret_cast<const double2 *>(p);
+    const double2 *H = reinterpret_cast<const double2 *>(h);
+    const double2 *B = reinterpret_cast<const double2 *>(b);
+    double2 *R = reinterpret_cast<double2 *>(r);
+    double a[5] = {0, 0, 0, 0, 0};
+    auto step = [&](int64_t k, double2 pp, double2 hh, double2 rr, double2 bb) {
+        const cd ap = csub(cmul(zs, cd{pp.x, pp.y}), cd{hh.x, hh.y});
+        const cd rv = csub(cd{rr.x, rr.y}, cmul(al, ap));
+        R[k] = make_double2(rv.re, rv.im);
+        a[0] += rv.re * rv.re - rv.im * rv.im;
+        a[1] += 2 * rv.re * rv.im;
+        a[2] += rv.re * rv.re + rv.im * rv.im;
+        a[3] += bb.x * rv.re + bb.y * rv.im;      // conj(b) r
+        a[4] += bb.x * rv.im - bb.y * rv.re;
+    };
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * st < dim; i += 4 * st) {
+        double2 pv[4], hv[4], rv[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            pv[u] = P[i + u * st];
+            hv[u] = H[i + u * st];
+            rv[u] = R[i + u * st];
+            bv[u] = B[i + u * st];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) step(i + u * st, pv[u], hv[u], rv[u], bv[u]);
+    }
+    for (; i < dim; i += st) step(i, P[i], H[i], R[i], B[i]);
+    block_sum<5>(a, shr);
+    if (threadIdx.x == 0)
+        for (int t = 0; t < 5; ++t) blk[t] = a[t];
+    __syncthreads();
+    if (!grid_finish(blk, 5, red, shr)) return;
+    if (threadIdx.x == 0) {
+        const cd rho1 = {red.result[0], red.result[1]};
+        cg->rnorm2 = red.result[2];
+        cg->bhr = {red.result[3], red.result[4]};
+        if (cabs2(cg->rho) == 0.0) {
+            cg->breakdown = 1;
+            cg->beta = {0.0, 0.0};
+        } else {
+            cg->beta = cdiv(rho1, cg->rho);
+        }
+        cg->rho = rho1;
+        cg->iter += 1;
+        __threadfence();
+    }
+    __syncthreads();
+    cocg_shifts_step(cg, sh, nsh, tol, smax);
+}
+
 // p = r + beta p
-__global__ void k_cocg_p(const double *r, double *p, int64_t dim, const CgDev *cg)
+__global__ __launch_bounds__(kBlock) void k_cocg_p(const double *r, double *p, int64_t dim, const CgDev *cg)
 {
     const cd be = cg->beta;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const cd pv = {p[2 * i], p[2 * i + 1]};
-        const cd t = cmul(be, pv);
-        p[2 * i] = r[2 * i] + t.re;
-        p[2 * i + 1] = r[2 * i + 1] + t.im;
+    const double2 *R = reinterpret_cast<const double2 *>(r);
+    double2 *P = reinterpret_cast<double2 *>(p);
+    auto step = [&](int64_t k, double2 rr, double2 pp) {
+        const cd t = cmul(be, cd{pp.x, pp.y});
+        P[k] = make_double2(rr.x + t.re, rr.y + t.im);
+    };
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * st < dim; i += 4 * st) {
+        double2 rv[4], pv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            rv[u] = R[i + u * st];
+            pv[u] = P[i + u * st];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) step(i + u * st, rv[u], pv[u]);
     }
+    for (; i < dim; i += st) step(i, R[i], P[i]);
 }
 
 static int gridn(int64_t n)
@@ -224,12 +272,14 @@ int launch_cocg_init(const void *b, void *r, void *p, int64_t dim, void *cg, voi
 int launch_cocg_iter(void *r, void *p, const void *h, const void *b, int64_t dim, void *cg, void *sh,
                      int nsh, double tol, Reduce red, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cocg_mu, dim3(gridn(dim)), dim3(kBlock), 0, st, (const double *)p, (const double *)h,
+    // at least 8 elements per thread, so the four-element trips dominate
+    int64_t g8 = (dim + kBlock * 8 - 1) / (kBlock * 8);
+    const int g = (int)(g8 < 1 ? 1 : (g8 > 2048 ? 2048 : g8));
+    hipLaunchKernelGGL(k_cocg_mu, dim3(g), dim3(kBlock), 0, st, (const double *)p, (const double *)h,
                        dim, (CgDev *)cg, red);
-    hipLaunchKernelGGL(k_cocg_r, dim3(gridn(dim)), dim3(kBlock), 0, st, (double *)r, (const double *)p,
-                       (const double *)h, (const double *)b, dim, (CgDev *)cg, red);
-    hipLaunchKernelGGL(k_cocg_shifts, dim3(1), dim3(256), 0, st, (CgDev *)cg, (ShiftDev *)sh, nsh, tol);
-    hipLaunchKernelGGL(k_cocg_p, dim3(gridn(dim)), dim3(kBlock), 0, st, (const double *)r, (double *)p, dim,
+    hipLaunchKernelGGL(k_cocg_r, dim3(g), dim3(kBlock), 0, st, (double *)r, (const double *)p,
+                       (const double *)h, (const double *)b, dim, (CgDev *)cg, (ShiftDev *)sh, nsh, tol, red);
+    hipLaunchKernelGGL(k_cocg_p, dim3(g), dim3(kBlock), 0, st, (const double *)r, (double *)p, dim,
                        (const CgDev *)cg);
     HPHI_HIP(hipGetLastError());
     return HPHI_OK;
