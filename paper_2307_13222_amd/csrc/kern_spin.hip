@@ -119,21 +119,58 @@ __global__ __launch_bounds__(kBlock) void k_spin_hv(SpinKArgs a)
 #pragma unroll
         for (int j = 0; j < NV; ++j) acc[j] = (S)0;
         S diag = (S)0;
-        for (int b = 0; b < a.nb; ++b) {
-            const uint32_t m = (uint32_t)a.bonds[b].mask;
-            const uint32_t t = x & m;
-            const S jz4 = (S)a.bonds[b].jz4;
-            if (t == 0u || t == m) {
-                diag += jz4;
-            } else {
-                diag -= jz4;
-                const uint32_t y = x ^ m;
-                const uint32_t idx = hi[y >> n_lo] + lo[y & lomask];
-                const S cf = (S)a.bonds[b].jxy2;
-                S nv[NV];
-                load_lanes<S, NV>(v + (size_t)idx * NV, nv);
+        if constexpr (NV <= 4) {
+            // narrow lanes: eight bonds per batch, their targets first, then
+            // all eight gathers in flight, then the sums in bond order (an
+            // antiparallel-free slot re-reads this state and adds exactly +0)
+            constexpr int BB = 8;
+            for (int b0 = 0; b0 < a.nb; b0 += BB) {
+                uint32_t idx[BB];
+                S cf[BB];
 #pragma unroll
-                for (int j = 0; j < NV; ++j) acc[j] += cf * nv[j];
+                for (int k = 0; k < BB; ++k) {
+                    idx[k] = (uint32_t)r;
+                    cf[k] = (S)0;
+                    const int b = b0 + k;
+                    if (b < a.nb) {
+                        const uint32_t m = (uint32_t)a.bonds[b].mask;
+                        const uint32_t t = x & m;
+                        const S jz4 = (S)a.bonds[b].jz4;
+                        if (t == 0u || t == m) {
+                            diag += jz4;
+                        } else {
+                            diag -= jz4;
+                            const uint32_t y = x ^ m;
+                            idx[k] = hi[y >> n_lo] + lo[y & lomask];
+                            cf[k] = (S)a.bonds[b].jxy2;
+                        }
+                    }
+                }
+                S nv[BB][NV];
+#pragma unroll
+                for (int k = 0; k < BB; ++k) load_lanes<S, NV>(v + (size_t)idx[k] * NV, nv[k]);
+#pragma unroll
+                for (int k = 0; k < BB; ++k)
+#pragma unroll
+                    for (int j = 0; j < NV; ++j) acc[j] += cf[k] * nv[k][j];
+            }
+        } else {
+            for (int b = 0; b < a.nb; ++b) {
+                const uint32_t m = (uint32_t)a.bonds[b].mask;
+                const uint32_t t = x & m;
+                const S jz4 = (S)a.bonds[b].jz4;
+                if (t == 0u || t == m) {
+                    diag += jz4;
+                } else {
+                    diag -= jz4;
+                    const uint32_t y = x ^ m;
+                    const uint32_t idx = hi[y >> n_lo] + lo[y & lomask];
+                    const S cf = (S)a.bonds[b].jxy2;
+                    S nv[NV];
+                    load_lanes<S, NV>(v + (size_t)idx * NV, nv);
+#pragma unroll
+                    for (int j = 0; j < NV; ++j) acc[j] += cf * nv[j];
+                }
             }
         }
         if (a.hz) {
