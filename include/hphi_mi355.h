@@ -161,7 +161,11 @@ void hphi_ham_free(hphi_ham *h);
  *                   in LDS, 4 = as 3 with hop-ordered slots (up to 32767
  *                   down states; otherwise as 3), 5 = as 4 with each row
  *                   staged by one batch of loads (up to 16384 down states
- *                   per lane group; otherwise as 4; bit-identical to 4)
+ *                   per lane group; otherwise as 4; bit-identical to 4),
+ *                   6 = as 5 with slot words that carry the LDS byte
+ *                   offset of one slot of each pair (one real vector, up
+ *                   to 16383 down states; otherwise as 5; bit-identical
+ *                   to 5; the default)
  *   spin_per_cu     spin H*v workgroups per compute unit (1..16)
  *   spin_implicit   1: spin H*v rebuilds configurations from row indices
  *                   (the path sectors without a stored state list take:
@@ -177,7 +181,7 @@ void hphi_ham_free(hphi_ham *h);
  *                   half) with the group's tile in LDS (one real vector,
  *                   even number of down states, groups of at most 72 rows;
  *                   otherwise as 1); 5 = as 3, one wave per row, each
- *                   row's neighbour lists walked in batches of 16 loads
+ *                   row's neighbour lists walked in batches of 12 loads
  *                   (128-column slabs with two columns per lane or
  *                   64-column slabs; bit-identical to 3 at the same slab
  *                   width); 6 = as 5 with each wave taking its own work

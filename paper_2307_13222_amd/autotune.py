@@ -29,10 +29,10 @@ def candidates(ham) -> List[Dict[str, int]]:
     if ham.basis.kind == "hubbard":
         out = []
         for cw, g, rows, rc, sw, ro in itertools.product((16, 32, 64, 128), (64, 128, 192, 256), (16, 32, 64),
-                                                         (3, 5), (1, 3, 5, 6), (1, 2)):
+                                                         (3, 5, 6), (1, 3, 5, 6), (1, 2)):
             out.append({"hub_slab_cols": cw, "hub_groups": g, "hub_item_rows": rows, "hub_row_cols": rc,
                         "hub_sweep": sw, "hub_row_order": ro})
-        for cw, g, rc in itertools.product((16, 32, 64), (64, 128, 256, 512), (3, 5)):
+        for cw, g, rc in itertools.product((16, 32, 64), (64, 128, 256, 512), (3, 5, 6)):
             out.append({"hub_slab_cols": cw, "hub_groups": g, "hub_item_rows": 64, "hub_row_cols": rc,
                         "hub_sweep": 2})
         return out

@@ -425,8 +425,16 @@ static int build_hub_fast(hphi_ham *h)
     // their fermion signs in bits 31 and 30; unconnected slots hold dim_dn.
     if (dn.dim < 32768) {
         std::vector<uint32_t> fbase(nchunk + 1, 0), fw(nchunk, 0);
-        std::vector<uint32_t> fent;
+        std::vector<uint32_t> fent, fc4, fc8;
         std::vector<std::vector<uint32_t>> slots;   // column | negative << 16
+        // pre-scaled words (element size E = 4 or 8): bits 0..16 hold E times
+        // the low slot's column with its sign in bit 0, bits 17..30 the high
+        // slot's column and bit 31 its sign; columns (and dim_dn, the padding
+        // column) must fit 14 bits
+        const bool fc = dn.dim <= 16383;
+        auto fc_word = [](uint32_t e0, uint32_t e1, uint32_t esz) {
+            return esz * (e0 & 0x7FFFu) | ((e0 >> 16) & 1u) | ((e1 & 0x7FFFu) << 17) | ((e1 >> 16) << 31);
+        };
         uint32_t wmax = 0;
         for (int64_t j = 0; j < nchunk; ++j) {
             const int64_t c0 = j * kSellChunk, c1 = std::min(dn.dim, c0 + kSellChunk);
@@ -453,12 +461,20 @@ static int build_hub_fast(hphi_ham *h)
             wmax = std::max(wmax, w8);
             const size_t at = fent.size();
             fent.resize(at + (size_t)w8 / 2 * kSellChunk, 0);
+            if (fc) {
+                fc4.resize(fent.size(), 0);
+                fc8.resize(fent.size(), 0);
+            }
             for (int l = 0; l < kSellChunk; ++l)
                 for (uint32_t k = 0; k < w8; k += 2) {
                     const uint32_t e0 = k < slots.size() ? slots[k][l] : (uint32_t)dn.dim;
                     const uint32_t e1 = k + 1 < slots.size() ? slots[k + 1][l] : (uint32_t)dn.dim;
-                    fent[at + (size_t)l * (w8 / 2) + k / 2] = (e0 & 0x7FFFu) | ((e1 & 0x7FFFu) << 15) |
-                                                              ((e1 >> 16) << 30) | ((e0 >> 16) << 31);
+                    const size_t at_w = at + (size_t)l * (w8 / 2) + k / 2;
+                    fent[at_w] = (e0 & 0x7FFFu) | ((e1 & 0x7FFFu) << 15) | ((e1 >> 16) << 30) | ((e0 >> 16) << 31);
+                    if (fc) {
+                        fc4[at_w] = fc_word(e0, e1, 4);
+                        fc8[at_w] = fc_word(e0, e1, 8);
+                    }
                 }
             fbase[j + 1] = (uint32_t)fent.size();
         }
@@ -467,6 +483,11 @@ static int build_hub_fast(hphi_ham *h)
         HPHI_TRY(upload(h->hub.fb_w, fw.data(), sizeof(uint32_t) * fw.size()));
         HPHI_TRY(upload(h->hub.fb_ent, fent.data(), sizeof(uint32_t) * fent.size()));
         h->hub.fb_ok = wmax <= 32;   // the kernel holds up to 32 slots per state
+        if (fc && !fc4.empty()) {
+            HPHI_TRY(upload(h->hub.fc_ent[0], fc4.data(), sizeof(uint32_t) * fc4.size()));
+            HPHI_TRY(upload(h->hub.fc_ent[1], fc8.data(), sizeof(uint32_t) * fc8.size()));
+            h->hub.fc_ok = h->hub.fb_ok;
+        }
     }
     // up species: CSR, plus entries then minus entries, targets as row
     // element offsets r' * dim_dn
@@ -632,7 +653,7 @@ int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s)
         n.hub_item_rows = s->hub_item_rows;
     }
     if (s->hub_row_cols) {
-        if (s->hub_row_cols < 1 || s->hub_row_cols > 5)
+        if (s->hub_row_cols < 1 || s->hub_row_cols > 6)
             return fail(HPHI_ERR_INVALID_ARG, "hub_row_cols %d", s->hub_row_cols);
         n.hub_row_cols = s->hub_row_cols;
     }

@@ -148,6 +148,10 @@ struct HubTables {
     // point at the zero slot dim_dn
     bool fb_ok = false;
     DevMem fb_base, fb_w, fb_ent;
+    // the same slots with the low slot's LDS byte address pre-scaled
+    // (element size 4 or 8: fc_ent[0] or [1]); built when dim_dn <= 16383
+    bool fc_ok = false;
+    DevMem fc_ent[2];
     DevMem coef;     // double [128]: -t per value class
     DevMem u_site;   // double [n_sites]
     int n_coef = 0;
@@ -174,7 +178,7 @@ struct hphi_ham {
     // defaults: 128-column slabs, 128 workgroups per XCD, 32-row items,
     // hop-ordered down slots, work-item queues with two columns per lane;
     // spin: 8 workgroups per CU
-    hphi_schedule sched_cfg{128, 128, 16, 5, 8, 0, 5, 2};
+    hphi_schedule sched_cfg{128, 128, 16, 6, 8, 0, 5, 2};
     // scratch for reductions and work queues
     hphi::DevMem sched;         // unsigned [16]: per-XCD item queues + counter
     hphi::DevMem red_partial;   // double [kReduceSlots]

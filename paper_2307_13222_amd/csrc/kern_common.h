@@ -47,18 +47,19 @@ __device__ __forceinline__ void block_sum(double (&vals)[NR], double *sh)
 // Returns true in the last block (all threads) so callers can finish scalar
 // work after the reduction; red.result is then valid for thread 0 only after
 // the final __syncthreads inside.
-__device__ __forceinline__ bool grid_finish(const double *blockvals, int nres, const Reduce &red,
-                                            double *sh)
+// `last` is a block-shared flag word (static LDS in grid_finish; kernels
+// that keep all of their LDS dynamic pass one of their own).
+__device__ __forceinline__ bool grid_finish_at(const double *blockvals, int nres, const Reduce &red,
+                                               double *sh, unsigned *last)
 {
-    __shared__ unsigned s_last;
     if (threadIdx.x == 0) {
         for (int i = 0; i < nres; ++i) red.partial[(size_t)blockIdx.x * nres + i] = blockvals[i];
         __threadfence();
         unsigned prev = atomicAdd(red.counter, 1u);
-        s_last = (prev == gridDim.x - 1) ? 1u : 0u;
+        *last = (prev == gridDim.x - 1) ? 1u : 0u;
     }
     __syncthreads();
-    if (!s_last) return false;
+    if (!*last) return false;
     __threadfence();
     const int nb = gridDim.x;
     for (int i = 0; i < nres; ++i) {
@@ -73,6 +74,13 @@ __device__ __forceinline__ bool grid_finish(const double *blockvals, int nres, c
     __threadfence();
     __syncthreads();
     return true;
+}
+
+__device__ __forceinline__ bool grid_finish(const double *blockvals, int nres, const Reduce &red,
+                                            double *sh)
+{
+    __shared__ unsigned s_last;
+    return grid_finish_at(blockvals, nres, red, sh, &s_last);
 }
 
 // SplitMix64 (Steele, Lea, Flood 2014): state advances by the golden-ratio

@@ -54,6 +54,7 @@ struct HubKArgs {
     const uint32_t *fu_off, *fu_mid, *fu_ent;
     const uint32_t *fb_base, *fb_w;
     const uint32_t *fb_ent;
+    const uint32_t *fc_ent;   // pre-scaled slot words for this element size (or null)
     const uint32_t *fg_rows, *fg_off, *fg_cnt, *fg_ent;
     int fg_ngroups;
     double t0;
@@ -523,6 +524,40 @@ __device__ __forceinline__ void fb_gather(const uint4 (&q)[4], uint32_t nq, cons
     }
 }
 
+// The same slots as fb_gather (one real vector) from pre-scaled words:
+// bits 0..16 hold the low slot's LDS byte offset (element size times its
+// column) with its sign in bit 0, bits 17..30 the high slot's column and
+// bit 31 its sign. The row must sit at LDS address 0 (dynamic LDS of a
+// kernel without static LDS; the launcher checks), so the offsets are LDS
+// addresses as they are. Same sums in the same order as fb_gather:
+// bit-identical results.
+template <typename S>
+__device__ __forceinline__ void fc_gather(const uint4 (&q)[4], uint32_t nq, S &acc)
+{
+    using lds_ptr = const __attribute__((address_space(3))) S *;
+    constexpr bool F64 = sizeof(S) == 8;
+    constexpr uint32_t lo_mask = F64 ? 0x1FFF8u : 0xFFFCu;
+    constexpr uint32_t hi_shift = F64 ? 14u : 15u;
+    constexpr uint32_t hi_mask = F64 ? 0x1FFF8u : 0xFFFCu;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        if ((uint32_t)g >= nq) break;
+        const uint32_t wd[4] = {q[g].x, q[g].y, q[g].z, q[g].w};
+        // the eight reads of a group first (all in flight), then the sums
+        S x[8];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            x[2 * p] = *(lds_ptr)(wd[p] & lo_mask);
+            x[2 * p + 1] = *(lds_ptr)((wd[p] >> hi_shift) & hi_mask);
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            acc += flip_sign(x[2 * p], wd[p] << 31);
+            acc += flip_sign(x[2 * p + 1], wd[p] & 0x80000000u);
+        }
+    }
+}
+
 template <typename S, int NV>
 __global__ __launch_bounds__(1024) void k_hub_rows_fb(HubKArgs a)
 {
@@ -587,9 +622,12 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fb(HubKArgs a)
 // ru are issued before the barrier that waits for the gathers of the
 // previous row. Needs ddn * NV <= MAXE * blockDim.x. Same slots, sums and
 // summation order as k_hub_rows_fb: bit-identical results.
-template <typename S, int NV, int MAXE>
+// FC: pre-scaled slot words (one real vector), see fc_gather.
+template <typename S, int NV, int MAXE, bool FC = false>
 __global__ __launch_bounds__(1024) void k_hub_rows_fp(HubKArgs a)
 {
+    static_assert(!FC || NV == 1, "pre-scaled slots address one real lane");
+    const uint32_t *__restrict__ ent = FC ? a.fc_ent : a.fb_ent;
     extern __shared__ unsigned char smem_raw[];
     const int64_t ddn = a.ddn;
     const int64_t nch = (ddn + 63) >> 6;
@@ -609,12 +647,18 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fp(HubKArgs a)
     }
     for (int64_t c = tid; c < ddn; c += T) s_d[c] = (uint16_t)a.dns[c];
     if (tid < NV) s_row[nrow + tid] = (S)0;
+    // the 64 columns of a wave form one chunk (T is a multiple of 64), so
+    // the chunk index, width and base are wave-uniform (scalar); lanes past
+    // the row in the last chunk read its padding slots (in bounds, never
+    // stored)
     auto load_col = [&](int64_t c, uint4 (&q)[4], uint32_t &nq) {
+        const uint32_t k = __builtin_amdgcn_readfirstlane((uint32_t)(c >> 6));
         nq = 0;
-        if (c >= ddn) return;
-        const uint32_t wc = s_w[c >> 6];
+        if (k >= (uint32_t)nch) return;
+        const uint32_t wc = __builtin_amdgcn_readfirstlane(s_w[k]);
+        const uint32_t base = __builtin_amdgcn_readfirstlane(s_base[k]);
         nq = wc >> 3;
-        const uint4 *p = reinterpret_cast<const uint4 *>(a.fb_ent + s_base[c >> 6] + (uint32_t)(c & 63) * (wc >> 1));
+        const uint4 *p = reinterpret_cast<const uint4 *>(ent + base + __umul24((uint32_t)(c & 63), wc >> 1));
 #pragma unroll
         for (int g = 0; g < 4; ++g)
             if ((uint32_t)g < nq) q[g] = p[g];
@@ -645,7 +689,10 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fp(HubKArgs a)
             S acc[NV];
 #pragma unroll
             for (int j = 0; j < NV; ++j) acc[j] = (S)0;
-            fb_gather<S, NV>(cur, ncur, s_row, acc);
+            if constexpr (FC)
+                fc_gather<S>(cur, ncur, acc[0]);
+            else
+                fb_gather<S, NV>(cur, ncur, s_row, acc);
             const S dg = hub_diag<S>(a, uu, (uint32_t)s_d[c]);
 #pragma unroll
             for (int j = 0; j < NV; ++j)
@@ -686,19 +733,24 @@ template <> __device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
 }
 
-// MAXE: row elements per lane (ddn <= MAXE * blockDim.x).
-template <typename S, int MAXE>
+// MAXE: row elements per lane (ddn <= MAXE * blockDim.x). All LDS is
+// dynamic, the row first (at LDS address 0, as fc_gather needs) and the
+// reduction scratch last; FC: pre-scaled slot words.
+constexpr size_t kRowsFzTail = 160;   // reduction scratch after the row metadata
+template <typename S, int MAXE, bool FC = false>
 __global__ __launch_bounds__(1024) void k_hub_rows_fz(HubKArgs a)
 {
     extern __shared__ unsigned char smem_raw[];
-    __shared__ double sh_red[16];
-    __shared__ double s_blk[1];
     const int64_t ddn = a.ddn;
     const int64_t nch = (ddn + 63) >> 6;
     S *s_row = reinterpret_cast<S *>(smem_raw);
     uint32_t *s_base = reinterpret_cast<uint32_t *>(s_row + (ddn + 1));
     uint32_t *s_w = s_base + nch;
     uint16_t *s_d = reinterpret_cast<uint16_t *>(s_w + nch);
+    double *sh_red = reinterpret_cast<double *>(((uintptr_t)(s_d + ddn) + 7) & ~(uintptr_t)7);
+    double *s_blk = sh_red + 16;
+    unsigned *s_last = reinterpret_cast<unsigned *>(s_blk + 1);
+    const uint32_t *__restrict__ ent = FC ? a.fc_ent : a.fb_ent;
     S *__restrict__ v = const_cast<S *>(static_cast<const S *>(a.v));
     const S *__restrict__ qp = static_cast<const S *>(a.lz_q);
     S *__restrict__ w = static_cast<S *>(a.w);
@@ -716,12 +768,18 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fz(HubKArgs a)
     }
     for (int64_t c = tid; c < ddn; c += T) s_d[c] = (uint16_t)a.dns[c];
     if (tid == 0) s_row[nrow] = (S)0;
+    // the 64 columns of a wave form one chunk (T is a multiple of 64), so
+    // the chunk index, width and base are wave-uniform (scalar); lanes past
+    // the row in the last chunk read its padding slots (in bounds, never
+    // stored)
     auto load_col = [&](int64_t c, uint4 (&q)[4], uint32_t &nq) {
+        const uint32_t k = __builtin_amdgcn_readfirstlane((uint32_t)(c >> 6));
         nq = 0;
-        if (c >= ddn) return;
-        const uint32_t wc = s_w[c >> 6];
+        if (k >= (uint32_t)nch) return;
+        const uint32_t wc = __builtin_amdgcn_readfirstlane(s_w[k]);
+        const uint32_t base = __builtin_amdgcn_readfirstlane(s_base[k]);
         nq = wc >> 3;
-        const uint4 *p = reinterpret_cast<const uint4 *>(a.fb_ent + s_base[c >> 6] + (uint32_t)(c & 63) * (wc >> 1));
+        const uint4 *p = reinterpret_cast<const uint4 *>(ent + base + __umul24((uint32_t)(c & 63), wc >> 1));
 #pragma unroll
         for (int g = 0; g < 4; ++g)
             if ((uint32_t)g < nq) q[g] = p[g];
@@ -772,7 +830,10 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fz(HubKArgs a)
         for (int64_t c = tid; c < ddn; c += T) {
             load_col(c + T, nxt, nnxt);
             S accg[1] = {(S)0};
-            fb_gather<S, 1>(cur, ncur, s_row, accg);
+            if constexpr (FC)
+                fc_gather<S>(cur, ncur, accg[0]);
+            else
+                fb_gather<S, 1>(cur, ncur, s_row, accg);
             const S dg = hub_diag<S>(a, uu, (uint32_t)s_d[c]);
             __builtin_nontemporal_store(dg * s_row[c] + nt0 * accg[0], &w[(size_t)ru * ddn + c]);
 #pragma unroll
@@ -784,7 +845,7 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fz(HubKArgs a)
     block_sum<1>(vals, sh_red);
     if (tid == 0) s_blk[0] = vals[0];
     __syncthreads();
-    if (grid_finish(s_blk, 1, a.lz_red, sh_red) && tid == 0 && corr) {
+    if (grid_finish_at(s_blk, 1, a.lz_red, sh_red, s_last) && tid == 0 && corr) {
         const double b = sqrt(a.lz_red.result[0]);
         const double al = s_k1 * lz->dot[0];
         const int k = lz->iter;
@@ -966,8 +1027,31 @@ __device__ __forceinline__ void load_k(const S *p, S (&o)[K])
 // over the wave, so the plus and minus lists are walked as one stream with
 // up to kColsBatch loads in flight per round, and the epilogue operands are
 // loaded before the first round. Each sum keeps its entry order, so the
-// results are bit-identical to the two-list walk.
+// results are bit-identical to the two-list walk. The neighbour rows are
+// read with raw buffer loads over V; the slots of a round past the end of
+// the list take an offset beyond V's last byte, which the buffer range
+// check answers with zeros and no memory request (the sums then add +0,
+// which leaves a sum that starts at +0 unchanged).
 constexpr int kColsBatch = 12;
+// V may take at most this many bytes on the HB path (offset kColsOob is
+// out of range, and offset + 16 does not wrap)
+constexpr uint32_t kColsOob = 0xFFFFFF00u;
+
+template <typename S, int K>
+__device__ __forceinline__ void buf_load_k(__amdgpu_buffer_rsrc_t r, uint32_t off, S (&o)[K])
+{
+    if constexpr (K * sizeof(S) == 16) {
+        const auto x = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+        __builtin_memcpy(o, &x, 16);
+    } else if constexpr (K * sizeof(S) == 8) {
+        const auto x = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+        __builtin_memcpy(o, &x, 8);
+    } else {
+        static_assert(K * sizeof(S) == 4, "one, two or four 32-bit words per lane");
+        const auto x = __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+        __builtin_memcpy(o, &x, 4);
+    }
+}
 
 template <typename S, int NV, int CW, bool DOTS, int CPL = 1, bool HB = false>
 __global__ __launch_bounds__(256) void k_hub_cols_f(HubKArgs a)
@@ -993,6 +1077,8 @@ __global__ __launch_bounds__(256) void k_hub_cols_f(HubKArgs a)
     constexpr uint32_t ESZ = NV * sizeof(S);
 
     const int64_t ddn = a.ddn, dup = a.dup;
+    // V as one raw buffer (HB path: the launcher keeps its size below kColsOob)
+    const __amdgpu_buffer_rsrc_t rvb = buf_rsrc(a.v, (uint32_t)((uint64_t)dup * (uint64_t)ddn * ESZ));
     const int nchunk = (int)((dup + a.item_rows - 1) / a.item_rows);
     constexpr int LPR = CW / CPL;   // lanes per row
     constexpr int RPW = 64 / LPR;
@@ -1059,24 +1145,26 @@ __global__ __launch_bounds__(256) void k_hub_cols_f(HubKArgs a)
 #pragma unroll
                 for (int j = 0; j < K; ++j) hp[j] = hm[j] = (S)0;
                 for (uint32_t e0 = eb; e0 < ee; e0 += kColsBatch) {
-                    // every load of the batch is issued (slots past the list
-                    // re-read its last entry) so that they form one group in
-                    // flight; the sums take each entry once, in order (adding
-                    // +0 leaves a sum that starts at +0 unchanged)
+                    // every load of the batch is issued so that they form
+                    // one group in flight; slots past the list read zeros
+                    // (out-of-range offset, no request); the sums take each
+                    // entry once, in order
                     uint32_t eo[kColsBatch];
 #pragma unroll
-                    for (int t = 0; t < kColsBatch; ++t) eo[t] = s_ent[e0 + t < ee ? e0 + t : ee - 1] + colb;
+                    for (int t = 0; t < kColsBatch; ++t)
+                        eo[t] = e0 + t < ee ? s_ent[e0 + t < ee ? e0 + t : ee - 1] + colb : kColsOob;
                     S nv[kColsBatch][K];
 #pragma unroll
-                    for (int t = 0; t < kColsBatch; ++t)
-                        load_k<S, K>(reinterpret_cast<const S *>(vb + eo[t]), nv[t]);
+                    for (int t = 0; t < kColsBatch; ++t) buf_load_k<S, K>(rvb, eo[t], nv[t]);
+                    // keep the whole group in flight before the first sum
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int t = 0; t < kColsBatch; ++t) {
-                        const bool in = e0 + t < ee, plus = e0 + t < em;
+                        const bool plus = e0 + t < em;
 #pragma unroll
                         for (int j = 0; j < K; ++j) {
-                            hp[j] += (in && plus) ? nv[t][j] : (S)0;
-                            hm[j] += (in && !plus) ? nv[t][j] : (S)0;
+                            hp[j] += plus ? nv[t][j] : (S)0;
+                            hm[j] += plus ? (S)0 : nv[t][j];
                         }
                     }
                 }
@@ -1823,17 +1911,38 @@ static void launch_cols_f128(const HubKArgs &a, int grid, hipStream_t st)
 }
 
 // The rows kernel with the fused Lanczos update runs where the batched
-// hop-ordered rows kernel runs (hub_row_cols 5) on one real vector with at
-// most 13 row elements per lane.
+// hop-ordered rows kernel runs (hub_row_cols 5 or 6) on one real vector
+// with at most 13 row elements per lane.
+static size_t rows_fz_bytes(int64_t ddn, size_t esz)
+{
+    return (size_t)(ddn + 1) * esz + 8 * (size_t)((ddn + 63) / 64) + 2 * (size_t)ddn + kRowsFzTail;
+}
 bool hub_rows_fused_ok(hphi_ham *h, int nv)
 {
     if (h->kind != 1 || nv != 1 || !h->hub.uniform_t || !h->hub.fb_ok) return false;
-    if (h->sched_cfg.hub_row_cols != 5 || h->basis->n_sites > 16) return false;
+    const int rc = h->sched_cfg.hub_row_cols;
+    if ((rc != 5 && rc != 6) || h->basis->n_sites > 16) return false;
     const int64_t dup = h->basis->sp[0].dim, ddn = h->basis->sp[1].dim;
     if (ddn > 13 * 1024) return false;    // row elements per lane of k_hub_rows_fz
-    const size_t fm_bytes = (size_t)(ddn + 1) * sizeof(double) + 8 * (size_t)((ddn + 63) / 64) + 2 * (size_t)ddn + 16;
-    if (fm_bytes > 160 * 1024) return false;
+    if (rows_fz_bytes(ddn, sizeof(double)) > 160 * 1024) return false;
     return (unsigned __int128)dup * ddn * sizeof(double) < ((unsigned __int128)1 << 32);
+}
+
+// True when every kernel that reads pre-scaled slot words has no static
+// LDS, so that its dynamic LDS (the row) starts at LDS address 0.
+template <typename S>
+static bool fc_kernels_lds0()
+{
+    static const bool ok = [] {
+        const void *ks[] = {(const void *)k_hub_rows_fp<S, 1, 16, true>, (const void *)k_hub_rows_fz<S, 8, true>,
+                            (const void *)k_hub_rows_fz<S, 13, true>};
+        for (const void *k : ks) {
+            hipFuncAttributes fa{};
+            if (hipFuncGetAttributes(&fa, k) != hipSuccess || fa.sharedSizeBytes != 0) return false;
+        }
+        return true;
+    }();
+    return ok;
 }
 
 template <typename S, int NV>
@@ -1861,18 +1970,29 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
     const size_t fl_bytes = (size_t)(a.ddn + 1) * sizeof(S) + 8 * (size_t)((a.ddn + 63) / 64) + 2 * (size_t)a.ddn + 16;
     const bool lane_rows = NV > 1 && !fast && fast_cols && rmode >= 4 && h->hub.fb_ok && fl_bytes <= 160 * 1024 &&
                            h->basis->n_sites <= 16;
+    // hub_row_cols 6: the batched hop-ordered rows kernels read pre-scaled
+    // slot words (one real vector; otherwise as 5). Their LDS addresses
+    // assume the row at LDS address 0: no static LDS in those kernels.
+    const bool fc_rows = rmode == 6 && NV == 1 && h->hub.fc_ok && fc_kernels_lds0<S>();
+    a.fc_ent = fc_rows ? h->hub.fc_ent[sizeof(S) == 8 ? 1 : 0].as<uint32_t>() : nullptr;
     if (a.lz_q) {
         // fused Lanczos update: only where hub_rows_fused_ok holds
         if constexpr (NV == 1) {
             if (!hub_rows_fused_ok(h, 1))
                 return fail(HPHI_ERR_UNSUPPORTED, "fused Lanczos update outside its kernel range");
+            const size_t fz_bytes = rows_fz_bytes(a.ddn, sizeof(S));
             auto go = [&](auto kern) {
-                hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fm_bytes);
-                hipLaunchKernelGGL(kern, dim3((unsigned)grid_r), dim3(threads), fm_bytes, st, a);
+                hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fz_bytes);
+                hipLaunchKernelGGL(kern, dim3((unsigned)grid_r), dim3(threads), fz_bytes, st, a);
             };
             const int64_t per = (a.ddn + threads - 1) / threads;
-            if (per <= 8) go(k_hub_rows_fz<S, 8>);
-            else go(k_hub_rows_fz<S, 13>);
+            if (fc_rows) {
+                if (per <= 8) go(k_hub_rows_fz<S, 8, true>);
+                else go(k_hub_rows_fz<S, 13, true>);
+            } else {
+                if (per <= 8) go(k_hub_rows_fz<S, 8>);
+                else go(k_hub_rows_fz<S, 13>);
+            }
         } else {
             return fail(HPHI_ERR_UNSUPPORTED, "fused Lanczos update takes one real vector");
         }
@@ -1883,7 +2003,12 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
             hipLaunchKernelGGL((k_hub_rows_fl<S, NV, 13>), dim3((unsigned)std::min<int64_t>(ncu, a.dup)),
                                dim3(threads), fl_bytes, st, a);
         }
-    } else if (fast && rmode == 5 && h->hub.fb_ok && fm_bytes <= 160 * 1024 && h->basis->n_sites <= 16 &&
+    } else if (fc_rows && fast && fm_bytes <= 160 * 1024 && h->basis->n_sites <= 16 &&
+               a.ddn <= 16 * (int64_t)threads) {
+        hipFuncSetAttribute((const void *)k_hub_rows_fp<S, 1, 16, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fm_bytes);
+        hipLaunchKernelGGL((k_hub_rows_fp<S, 1, 16, true>), dim3((unsigned)grid_r), dim3(threads), fm_bytes, st, a);
+    } else if (fast && rmode >= 5 && h->hub.fb_ok && fm_bytes <= 160 * 1024 && h->basis->n_sites <= 16 &&
         a.ddn * NV <= 16 * (int64_t)threads) {
         hipFuncSetAttribute((const void *)k_hub_rows_fp<S, NV, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)fm_bytes);
@@ -2013,7 +2138,7 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
     // only); 5 also walks each row's lists in batches (one wave per row)
     const int sw = h->sched_cfg.hub_sweep;
     a.row_cols = ((sw == 3 || sw == 5) && NV == 1 && a.ddn % 2 == 0) ? 2 : 1;
-    a.hb = sw == 5 ? 1 : 0;
+    a.hb = (sw == 5 && (uint64_t)a.dup * (uint64_t)a.ddn * NV * sizeof(S) <= kColsOob) ? 1 : 0;
     // 128-column slabs only with two columns per lane (one wave per row)
     const int cw_eff = (cw == 128 && !(fast_cols && a.row_cols == 2)) ? 64 : cw;
     a.nslab = (int)((a.ddn + cw_eff - 1) / cw_eff);

@@ -159,9 +159,10 @@ def test_hubbard_lanczos_f32_storage(api, ctx):
 @pytest.mark.parametrize("lx,ly,nu,nd", [(3, 4, 6, 5), (4, 4, 3, 5)])
 def test_hubbard_batched_list_walk_bit_identical(api, ctx, lx, ly, nu, nd):
     # T_up with the batched list walk (hub_sweep 5) and T_dn with the batched
-    # row staging (hub_row_cols 5) keep every sum's order: real, complex and
-    # FP32 products, the fused Lanczos epilogue and dots, and the complex
-    # Taylor epilogue equal the two-list walk bit for bit
+    # row staging (hub_row_cols 5, and 6 with pre-scaled slot words) keep
+    # every sum's order: real, complex and FP32 products, the fused Lanczos
+    # epilogue and dots, and the complex Taylor epilogue equal the two-list
+    # walk bit for bit
     import torch
     say("hub batched walk", lx, ly, nu, nd)
     m = W.hubbard_square(lx, ly, 1.0, 4.0)
@@ -175,7 +176,8 @@ def test_hubbard_batched_list_walk_bit_identical(api, ctx, lx, ly, nu, nd):
     for key, sch in (("two_list", dict(hub_row_cols=4, hub_sweep=3, hub_row_order=1)),
                      ("batched", dict(hub_row_cols=5, hub_sweep=5, hub_row_order=1)),
                      ("wave_owned", dict(hub_row_cols=5, hub_sweep=6, hub_row_order=1)),
-                     ("rcm", dict(hub_row_cols=5, hub_sweep=5, hub_row_order=2))):
+                     ("rcm", dict(hub_row_cols=5, hub_sweep=5, hub_row_order=2)),
+                     ("prescaled", dict(hub_row_cols=6, hub_sweep=5, hub_row_order=2))):
         h.set_schedule(**base, **sch)
         prods = [host(h.mult(x)) for x in ins]
         lz = api.lanczos(h, 60, seed=4) if sch["hub_row_cols"] == 4 else None
@@ -183,7 +185,7 @@ def test_hubbard_batched_list_walk_bit_identical(api, ctx, lx, ly, nu, nd):
         te = api.time_evolve(h, psi, 3, dt=0.05, n_max=6)
         out[key] = (prods, lz, host(psi), te)
     a = out["two_list"]
-    for c in (out["batched"], out["wave_owned"], out["rcm"]):
+    for c in (out["batched"], out["wave_owned"], out["rcm"], out["prescaled"]):
         for x, y in zip(a[0], c[0]):
             assert np.array_equal(x, y)
         assert np.array_equal(a[2], c[2])
@@ -191,9 +193,9 @@ def test_hubbard_batched_list_walk_bit_identical(api, ctx, lx, ly, nu, nd):
 
 
 def test_hubbard_lanczos_fused_update(api, ctx):
-    # with hub_row_cols 5 the Lanczos update (w -= alpha q, beta = |w|) runs
-    # inside the next product's rows kernel: same recurrence as the separate
-    # update kernel up to the order of the |w|^2 sum
+    # with hub_row_cols 5 (and 6) the Lanczos update (w -= alpha q,
+    # beta = |w|) runs inside the next product's rows kernel: same recurrence
+    # as the separate update kernel up to the order of the |w|^2 sum
     say("hub lanczos fused")
     m = W.hubbard_square(4, 4, 1.0, 4.0)
     b = api.Basis.hubbard(ctx, 16, 3, 5)
@@ -203,6 +205,11 @@ def test_hubbard_lanczos_fused_update(api, ctx):
     ref = api.lanczos(h, 80, seed=6)
     h.set_schedule(hub_row_cols=5)
     fz = api.lanczos(h, 80, seed=6)
+    # pre-scaled slot words: the same sums in the same order
+    h.set_schedule(hub_row_cols=6)
+    f6 = api.lanczos(h, 80, seed=6)
+    assert np.array_equal(f6["alpha"], fz["alpha"]) and np.array_equal(f6["beta"], fz["beta"])
+    assert f6["fused_update"]
     # rounding differences grow along a Lanczos sequence without
     # reorthogonalization: early coefficients agree to rounding, the ground
     # energy to the Lanczos bar
@@ -231,16 +238,20 @@ def test_hubbard_lanczos_fused_update(api, ctx):
     # FP32 vectors take the fused kernel too
     r4 = api.lanczos(h, 200, seed=6, storage="f32")
     assert abs(r4["energies"][0] - rv["energies"][0]) < 1e-4 * abs(rv["energies"][0])
+    h.set_schedule(hub_row_cols=5)
+    r45 = api.lanczos(h, 200, seed=6, storage="f32")
+    assert np.array_equal(r4["alpha"], r45["alpha"]) and np.array_equal(r4["beta"], r45["beta"])
 
 
-def test_hubbard_lanczos_fused_update_edges(api, ctx):
+@pytest.mark.parametrize("rc", [5, 6])
+def test_hubbard_lanczos_fused_update_edges(api, ctx, rc):
     # the fused path's scalar step (and breakdown test) runs in the rows
     # kernel's last block; the last step's update after the loop
-    say("hub lanczos fused edges")
+    say("hub lanczos fused edges", rc)
     m = W.hubbard_square(2, 3, 1.0, 4.0)
     b = api.Basis.hubbard(ctx, 6, 2, 3)
     h = api.Hamiltonian.hubbard(b, m)
-    h.set_schedule(hub_row_cols=5)
+    h.set_schedule(hub_row_cols=rc)
     ups, dns = O.hubbard_basis(6, 2, 3)
     hv = lambda x: O.hubbard_hv(m, ups, dns, x)
     v0 = O.splitmix_uniform(9, 0, b.dim)
@@ -256,7 +267,7 @@ def test_hubbard_lanczos_fused_update_edges(api, ctx):
     m2 = W.hubbard_square(2, 2, 1.0, 4.0)
     b2 = api.Basis.hubbard(ctx, 4, 1, 1)
     h2 = api.Hamiltonian.hubbard(b2, m2)
-    h2.set_schedule(hub_row_cols=5)
+    h2.set_schedule(hub_row_cols=rc)
     u2, d2 = O.hubbard_basis(4, 1, 1)
     e = np.linalg.eigvalsh(O.hubbard_sparse(m2, u2, d2).toarray())
     r2 = api.lanczos(h2, 40, seed=2)

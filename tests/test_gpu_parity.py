@@ -301,7 +301,10 @@ def test_hubbard_schedules_bit_identical(api, ctx):
                 dict(hub_slab_cols=128, hub_groups=128, hub_item_rows=16, hub_row_cols=5, hub_sweep=5, hub_row_order=2),
                 dict(hub_slab_cols=16, hub_groups=64, hub_item_rows=32, hub_row_cols=1, hub_sweep=1, hub_row_order=2),
                 dict(hub_slab_cols=64, hub_groups=7, hub_item_rows=8, hub_row_cols=3, hub_sweep=3, hub_row_order=2),
-                dict(hub_slab_cols=128, hub_groups=32, hub_item_rows=16, hub_row_cols=5, hub_sweep=6, hub_row_order=2)]:
+                dict(hub_slab_cols=128, hub_groups=32, hub_item_rows=16, hub_row_cols=5, hub_sweep=6, hub_row_order=2),
+                # pre-scaled down slots
+                dict(hub_slab_cols=128, hub_groups=128, hub_item_rows=16, hub_row_cols=6, hub_sweep=5, hub_row_order=2),
+                dict(hub_slab_cols=16, hub_groups=64, hub_item_rows=32, hub_row_cols=6, hub_sweep=1)]:
         h.set_schedule(**sch)
         assert h.get_schedule()["hub_slab_cols"] == sch["hub_slab_cols"]
         w = host(h.mult(v))
@@ -323,7 +326,7 @@ def test_hubbard_schedules_bit_identical(api, ctx):
         h.set_schedule(hub_row_order=3)
     h.set_schedule(hub_row_order=1)
     with pytest.raises(api.HphiError):
-        h.set_schedule(hub_row_cols=6)
+        h.set_schedule(hub_row_cols=7)
 
 
 def test_hubbard_4x4_full_size_sampled_rows(api, ctx):
