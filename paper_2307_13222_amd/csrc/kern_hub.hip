@@ -1127,10 +1127,15 @@ __global__ __launch_bounds__(256) void k_hub_cols_f(HubKArgs a)
             if (!colok) continue;
             const size_t me = (size_t)(a.row_of ? (int64_t)a.row_of[r] : r) * ddn + col;
             if constexpr (HB) {
-                static_assert(RPW == 1, "one wave per row");
-                const uint32_t eb = __builtin_amdgcn_readfirstlane(s_off[r - r0]);
-                const uint32_t em = __builtin_amdgcn_readfirstlane(s_mid[r - r0]);
-                const uint32_t ee = __builtin_amdgcn_readfirstlane(s_off[r - r0 + 1]);
+                // one wave per row: the list bounds are wave-uniform
+                // (scalar); several rows per wave: per lane, and the wave
+                // walks until its longest list is done
+                uint32_t eb = s_off[r - r0], em = s_mid[r - r0], ee = s_off[r - r0 + 1];
+                if constexpr (RPW == 1) {
+                    eb = __builtin_amdgcn_readfirstlane(eb);
+                    em = __builtin_amdgcn_readfirstlane(em);
+                    ee = __builtin_amdgcn_readfirstlane(ee);
+                }
                 // u is row-uniform (null or not): the same register lanes
                 // either way, read from w itself when there is no u
                 const S *up = u ? u : w;
@@ -1144,22 +1149,25 @@ __global__ __launch_bounds__(256) void k_hub_cols_f(HubKArgs a)
                 S hp[K], hm[K];
 #pragma unroll
                 for (int j = 0; j < K; ++j) hp[j] = hm[j] = (S)0;
-                for (uint32_t e0 = eb; e0 < ee; e0 += kColsBatch) {
-                    // every load of the batch is issued so that they form
-                    // one group in flight; slots past the list read zeros
-                    // (out-of-range offset, no request); the sums take each
-                    // entry once, in order
-                    uint32_t eo[kColsBatch];
+                // one round: NB loads issued as one group in flight; slots
+                // past the list read zeros (out-of-range offset, no
+                // request); the sums take each entry once, in order (a lane
+                // whose list is done, or empty, reads an entry of the staged
+                // lists and discards it)
+                const uint32_t elast = ee > 0 ? ee - 1 : 0;
+                auto round = [&](auto nb_c, uint32_t e0) {
+                    constexpr int NB = decltype(nb_c)::value;
+                    uint32_t eo[NB];
 #pragma unroll
-                    for (int t = 0; t < kColsBatch; ++t)
-                        eo[t] = e0 + t < ee ? s_ent[e0 + t < ee ? e0 + t : ee - 1] + colb : kColsOob;
-                    S nv[kColsBatch][K];
+                    for (int t = 0; t < NB; ++t)
+                        eo[t] = e0 + t < ee ? s_ent[e0 + t < ee ? e0 + t : elast] + colb : kColsOob;
+                    S nv[NB][K];
 #pragma unroll
-                    for (int t = 0; t < kColsBatch; ++t) buf_load_k<S, K>(rvb, eo[t], nv[t]);
+                    for (int t = 0; t < NB; ++t) buf_load_k<S, K>(rvb, eo[t], nv[t]);
                     // keep the whole group in flight before the first sum
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                    for (int t = 0; t < kColsBatch; ++t) {
+                    for (int t = 0; t < NB; ++t) {
                         const bool plus = e0 + t < em;
 #pragma unroll
                         for (int j = 0; j < K; ++j) {
@@ -1167,6 +1175,20 @@ __global__ __launch_bounds__(256) void k_hub_cols_f(HubKArgs a)
                             hm[j] += plus ? (S)0 : nv[t][j];
                         }
                     }
+                };
+                if constexpr (RPW == 1) {
+                    // rounds of kColsBatch, the last one sized to what is
+                    // left (8 or 4): fewer issued slots, same order
+                    uint32_t e0 = eb;
+                    for (; e0 + kColsBatch <= ee; e0 += kColsBatch)
+                        round(std::integral_constant<int, kColsBatch>{}, e0);
+                    const uint32_t rem = ee - e0;
+                    if (rem > 8) round(std::integral_constant<int, kColsBatch>{}, e0);
+                    else if (rem > 4) round(std::integral_constant<int, 8>{}, e0);
+                    else if (rem > 0) round(std::integral_constant<int, 4>{}, e0);
+                } else {
+                    for (uint32_t e0 = eb; __ballot(e0 < ee) != 0; e0 += kColsBatch)
+                        round(std::integral_constant<int, kColsBatch>{}, e0);
                 }
                 S hraw[K], hout[K];
 #pragma unroll
@@ -1711,6 +1733,14 @@ template <typename S, int NV, int CW>
 static void launch_cols_f(const HubKArgs &a, int grid, hipStream_t st)
 {
     if (a.row_cols == 2 && NV == 1) {
+        if constexpr (CW >= 16 && NV == 1) {
+            if (a.hb) {
+                // batched walk, 64 / (CW / 2) rows per wave
+                if (a.nd) hipLaunchKernelGGL((k_hub_cols_f<S, NV, CW, true, 2, true>), dim3(grid), dim3(256), 0, st, a);
+                else hipLaunchKernelGGL((k_hub_cols_f<S, NV, CW, false, 2, true>), dim3(grid), dim3(256), 0, st, a);
+                return;
+            }
+        }
         if (a.nd) hipLaunchKernelGGL((k_hub_cols_f<S, NV, CW, true, 2>), dim3(grid), dim3(256), 0, st, a);
         else hipLaunchKernelGGL((k_hub_cols_f<S, NV, CW, false, 2>), dim3(grid), dim3(256), 0, st, a);
         return;

@@ -304,7 +304,10 @@ def test_hubbard_schedules_bit_identical(api, ctx):
                 dict(hub_slab_cols=128, hub_groups=32, hub_item_rows=16, hub_row_cols=5, hub_sweep=6, hub_row_order=2),
                 # pre-scaled down slots
                 dict(hub_slab_cols=128, hub_groups=128, hub_item_rows=16, hub_row_cols=6, hub_sweep=5, hub_row_order=2),
-                dict(hub_slab_cols=16, hub_groups=64, hub_item_rows=32, hub_row_cols=6, hub_sweep=1)]:
+                dict(hub_slab_cols=16, hub_groups=64, hub_item_rows=32, hub_row_cols=6, hub_sweep=1),
+                # batched walk with several rows per wave (16 and 32 columns)
+                dict(hub_slab_cols=16, hub_groups=64, hub_item_rows=32, hub_row_cols=6, hub_sweep=5),
+                dict(hub_slab_cols=32, hub_groups=7, hub_item_rows=16, hub_row_cols=5, hub_sweep=5, hub_row_order=2)]:
         h.set_schedule(**sch)
         assert h.get_schedule()["hub_slab_cols"] == sch["hub_slab_cols"]
         w = host(h.mult(v))
