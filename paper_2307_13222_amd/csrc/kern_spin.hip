@@ -77,25 +77,47 @@ __device__ __forceinline__ void store_lanes(S *__restrict__ p, const S (&o)[NV])
     }
 }
 
-template <typename S, int NV, bool LDS_TAB, bool DOTS>
-__global__ __launch_bounds__(kBlock) void k_spin_hv(SpinKArgs a)
+// TAB: where rank() reads its tables. 0: global memory; 1: both 32-bit
+// tables in LDS (kBlock threads); 2: hi_off (32-bit) and lo_rank narrowed
+// to 16 bits in LDS (ranks below 65536), kSpinBigBlock threads, so tables
+// of up to 96 KB (27 and 28 sites) sit in LDS at one workgroup per CU
+// without losing waves.
+constexpr int kSpinBigBlock = 1024;
+template <int TAB> constexpr int spin_block() { return TAB == 2 ? kSpinBigBlock : kBlock; }
+
+template <typename S, int NV, int TAB, bool DOTS>
+__global__ __launch_bounds__(spin_block<TAB>()) void k_spin_hv(SpinKArgs a)
 {
     extern __shared__ uint32_t smem_tab[];
-    __shared__ double sh_red[kBlock / kWave * 2 * 32];
+    __shared__ double sh_red[spin_block<TAB>() / kWave * 2 * 32];
     __shared__ double sh_blk[64];
 
     const uint32_t *lo = a.lo_rank;
     const uint32_t *hi = a.hi_off;
-    if constexpr (LDS_TAB) {
+    const uint16_t *lo16 = nullptr;
+    if constexpr (TAB == 1) {
         const int nl = 1 << a.n_lo, nh = 1 << a.n_hi;
         for (int i = threadIdx.x; i < nl; i += blockDim.x) smem_tab[i] = a.lo_rank[i];
         for (int i = threadIdx.x; i < nh; i += blockDim.x) smem_tab[nl + i] = a.hi_off[i];
         __syncthreads();
         lo = smem_tab;
         hi = smem_tab + nl;
+    } else if constexpr (TAB == 2) {
+        const int nl = 1 << a.n_lo, nh = 1 << a.n_hi;
+        uint16_t *l16 = reinterpret_cast<uint16_t *>(smem_tab + nh);
+        for (int i = threadIdx.x; i < nh; i += blockDim.x) smem_tab[i] = a.hi_off[i];
+        for (int i = threadIdx.x; i < nl; i += blockDim.x) l16[i] = (uint16_t)a.lo_rank[i];
+        __syncthreads();
+        hi = smem_tab;
+        lo16 = l16;
     }
     const uint32_t lomask = (1u << a.n_lo) - 1u;
     const int n_lo = a.n_lo;
+    // rank of an in-sector configuration
+    auto rank = [&](uint32_t y) -> uint32_t {
+        if constexpr (TAB == 2) return hi[y >> n_lo] + (uint32_t)lo16[y & lomask];
+        else return hi[y >> n_lo] + lo[y & lomask];
+    };
     const S *__restrict__ v = static_cast<const S *>(a.v);
     S *__restrict__ w = static_cast<S *>(a.w);
     const S *__restrict__ u = static_cast<const S *>(a.u);
@@ -141,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_spin_hv(SpinKArgs a)
                         } else {
                             diag -= jz4;
                             const uint32_t y = x ^ m;
-                            idx[k] = hi[y >> n_lo] + lo[y & lomask];
+                            idx[k] = rank(y);
                             cf[k] = (S)a.bonds[b].jxy2;
                         }
                     }
@@ -164,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_spin_hv(SpinKArgs a)
                 } else {
                     diag -= jz4;
                     const uint32_t y = x ^ m;
-                    const uint32_t idx = hi[y >> n_lo] + lo[y & lomask];
+                    const uint32_t idx = rank(y);
                     const S cf = (S)a.bonds[b].jxy2;
                     S nv[NV];
                     load_lanes<S, NV>(v + (size_t)idx * NV, nv);
@@ -240,31 +262,46 @@ __global__ __launch_bounds__(kBlock) void k_spin_hv(SpinKArgs a)
     }
 }
 
-template <typename S, int NV, bool LDS>
+template <typename S, int NV, int LDS>
 static void launch_spin_d(const SpinKArgs &a, int grid, size_t lds_bytes, hipStream_t st)
 {
-    if (a.nd) {
+    constexpr int BS = spin_block<LDS>();
+    if constexpr (LDS == 2) {
+        // the launcher picks these tables only for products without dots
+        hipFuncSetAttribute((const void *)k_spin_hv<S, NV, 2, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds_bytes);
+        hipLaunchKernelGGL((k_spin_hv<S, NV, 2, false>), dim3(grid), dim3(BS), lds_bytes, st, a);
+        return;
+    } else if (a.nd) {
         if (LDS) hipFuncSetAttribute((const void *)k_spin_hv<S, NV, LDS, true>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-        hipLaunchKernelGGL((k_spin_hv<S, NV, LDS, true>), dim3(grid), dim3(kBlock), lds_bytes, st, a);
+        hipLaunchKernelGGL((k_spin_hv<S, NV, LDS, true>), dim3(grid), dim3(BS), lds_bytes, st, a);
     } else {
         if (LDS) hipFuncSetAttribute((const void *)k_spin_hv<S, NV, LDS, false>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-        hipLaunchKernelGGL((k_spin_hv<S, NV, LDS, false>), dim3(grid), dim3(kBlock), lds_bytes, st, a);
+        hipLaunchKernelGGL((k_spin_hv<S, NV, LDS, false>), dim3(grid), dim3(BS), lds_bytes, st, a);
     }
 }
 
 template <typename S, int NV>
-static int launch_spin_t(const SpinKArgs &a, bool lds, int grid, size_t lds_bytes, hipStream_t st)
+static int launch_spin_t(const SpinKArgs &a, int tab, int grid, size_t lds_bytes, hipStream_t st)
 {
-    if (lds) launch_spin_d<S, NV, true>(a, grid, lds_bytes, st);
-    else launch_spin_d<S, NV, false>(a, grid, 0, st);
+    if constexpr (NV * sizeof(S) <= 128) {
+        if (tab == 2) {
+            launch_spin_d<S, NV, 2>(a, grid, lds_bytes, st);
+            HPHI_HIP(hipGetLastError());
+            return HPHI_OK;
+        }
+    }
+    if (tab == 2) return fail(HPHI_ERR_UNSUPPORTED, "spin H*v: narrowed tables with %d-byte states", (int)(NV * sizeof(S)));
+    if (tab == 1) launch_spin_d<S, NV, 1>(a, grid, lds_bytes, st);
+    else launch_spin_d<S, NV, 0>(a, grid, 0, st);
     HPHI_HIP(hipGetLastError());
     return HPHI_OK;
 }
 
 template <typename S>
-static int launch_spin_nv(int nv, const SpinKArgs &a, bool lds, int grid, size_t lds_bytes,
+static int launch_spin_nv(int nv, const SpinKArgs &a, int lds, int grid, size_t lds_bytes,
                           hipStream_t st)
 {
     switch (nv) {
@@ -317,11 +354,23 @@ int launch_spin_mult(hphi_ham *h, const MultArgs &m)
     a.raw_out = m.raw_out;
     const int nv = m.nvec * dtype_lanes(m.dtype);
     size_t tab = sizeof(uint32_t) * ((size_t(1) << s.n_lo) + (size_t(1) << s.n_hi));
-    bool lds = tab <= 96 * 1024;
-    int64_t need = (s.dim + kBlock - 1) / kBlock;
+    // the same tables with lo_rank in 16 bits (its values are ranks among
+    // the same-popcount low patterns: below 65536 for up to 18 low sites)
+    const size_t tab_c = sizeof(uint32_t) * (size_t(1) << s.n_hi) + sizeof(uint16_t) * (size_t(1) << s.n_lo);
+    // (not with fused dots, nor above 128 bytes per state: their
+    // accumulators do not fit the registers of a 1024-thread workgroup)
+    const size_t state_bytes = (size_t)m.nvec * dtype_lanes(m.dtype) * (dtype_is_f32(m.dtype) ? 4 : 8);
+    int lds = tab <= 96 * 1024                                                                 ? 1
+              : (tab_c <= 96 * 1024 && s.n_lo <= 18 && !m.dots && state_bytes <= 128) ? 2
+                                                                                        : 0;
+    if (lds == 2) tab = tab_c;
+    const int bs = lds == 2 ? kSpinBigBlock : kBlock;
+    int64_t need = (s.dim + bs - 1) / bs;
     // workgroups per CU from the schedule, capped by the LDS the tables use
+    // (one 1024-thread workgroup per CU with the narrowed tables)
     int per_cu = h->sched_cfg.spin_per_cu;
-    if (lds) per_cu = std::min(per_cu, std::max(1, (int)((160 * 1024) / (tab + 4096))));
+    if (lds == 1) per_cu = std::min(per_cu, std::max(1, (int)((160 * 1024) / (tab + 4096))));
+    if (lds == 2) per_cu = 1;
     int64_t cap = (int64_t)(h->basis->ctx->n_cu > 0 ? h->basis->ctx->n_cu : 256) * per_cu;
     if (cap > kMaxGrid) cap = kMaxGrid;
     int grid = (int)(need < cap ? need : cap);

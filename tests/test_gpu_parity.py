@@ -225,6 +225,45 @@ def test_spin_36_sites_sampled_rows_fp32(api, ctx):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("dt,nvec", [("c64", 16), ("f64", 1), ("c128", 1)])
+def test_spin_28_sites_sampled_rows(api, ctx, dt, nvec):
+    # the cTPQ block workload's sector (XXZ + J2 ring, 28 sites, 2S^z = 0,
+    # dim 40,116,600) at full size: its rank tables (16384 + 16384 entries)
+    # sit in LDS with lo_rank narrowed to 16 bits; sampled output rows
+    # against the oracle's row formula
+    import torch
+    say("spin 28 sites sampled rows", dt, nvec)
+    m = W.xxz_chain_j2(28)
+    b = api.Basis.spin(ctx, 28, 0)
+    h = api.Hamiltonian.spin(b, m)
+    dim = b.dim
+    assert dim == 40116600
+    g = torch.Generator(device="cuda").manual_seed(28)
+    real = torch.float32 if dt == "c64" else torch.float64
+    shape = (dim, nvec) if nvec > 1 else (dim,)
+    v = torch.rand(shape, dtype=real, device="cuda", generator=g) - 0.5
+    if dt.startswith("c"):
+        v = torch.complex(v, torch.rand(shape, dtype=real, device="cuda", generator=g) - 0.5)
+    torch.cuda.synchronize()
+    w = h.mult(v)
+    torch.cuda.synchronize()
+    say("  mult done")
+    rng = np.random.default_rng(2828)
+    rows = np.concatenate([[0, 1, dim - 1], rng.integers(0, dim, 300)])
+    worst = 0.0
+    for r in rows:
+        cols, vals = O.spin_row(m, 14, int(r))
+        vv = host(v[torch.from_numpy(cols).cuda()]).astype(np.complex128).reshape(len(cols), nvec)
+        ref = vals @ vv
+        scale = np.abs(vals) @ np.abs(vv)
+        got = host(w[int(r)]).astype(np.complex128).reshape(nvec)
+        worst = max(worst, float(np.max(np.abs(got - ref) / scale)))
+    # FP32 storage and accumulation over <= 57 terms; FP64 to rounding
+    assert worst < (2e-6 if dt == "c64" else 1e-13), worst
+    del v, w
+    torch.cuda.empty_cache()
+
+
 def test_spin_mult_deterministic(api, ctx):
     m = W.xxz_chain_j2(20)
     b = api.Basis.spin(ctx, 20, 0)
