@@ -80,8 +80,9 @@ __device__ __forceinline__ void store_lanes(S *__restrict__ p, const S (&o)[NV])
 // TAB: where rank() reads its tables. 0: global memory; 1: both 32-bit
 // tables in LDS (kBlock threads); 2: hi_off (32-bit) and lo_rank narrowed
 // to 16 bits in LDS (ranks below 65536), kSpinBigBlock threads, so tables
-// of up to 96 KB (27 and 28 sites) sit in LDS at one workgroup per CU
-// without losing waves.
+// of up to 96 KB (27 and 28 sites) sit in LDS at one workgroup per CU, and
+// the 48-64 KB tables of 25 and 26 sites leave 16 or more waves per CU
+// (with 32-bit tables and kBlock threads the LDS held 8 to 12).
 constexpr int kSpinBigBlock = 1024;
 template <int TAB> constexpr int spin_block() { return TAB == 2 ? kSpinBigBlock : kBlock; }
 
@@ -267,7 +268,17 @@ static void launch_spin_d(const SpinKArgs &a, int grid, size_t lds_bytes, hipStr
 {
     constexpr int BS = spin_block<LDS>();
     if constexpr (LDS == 2) {
-        // the launcher picks these tables only for products without dots
+        // the launcher picks these tables for fused dots only up to 32 B
+        // per state (the FP64 accumulators of wider states do not fit the
+        // registers of a 1024-thread workgroup)
+        if constexpr (NV * sizeof(S) <= 32) {
+            if (a.nd) {
+                hipFuncSetAttribute((const void *)k_spin_hv<S, NV, 2, true>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+                hipLaunchKernelGGL((k_spin_hv<S, NV, 2, true>), dim3(grid), dim3(BS), lds_bytes, st, a);
+                return;
+            }
+        }
         hipFuncSetAttribute((const void *)k_spin_hv<S, NV, 2, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds_bytes);
         hipLaunchKernelGGL((k_spin_hv<S, NV, 2, false>), dim3(grid), dim3(BS), lds_bytes, st, a);
@@ -357,20 +368,23 @@ int launch_spin_mult(hphi_ham *h, const MultArgs &m)
     // the same tables with lo_rank in 16 bits (its values are ranks among
     // the same-popcount low patterns: below 65536 for up to 18 low sites)
     const size_t tab_c = sizeof(uint32_t) * (size_t(1) << s.n_hi) + sizeof(uint16_t) * (size_t(1) << s.n_lo);
-    // (not with fused dots, nor above 128 bytes per state: their
-    // accumulators do not fit the registers of a 1024-thread workgroup)
+    // (up to 128 bytes per state, 32 with fused dots: wider accumulators
+    // do not fit the registers of a 1024-thread workgroup)
     const size_t state_bytes = (size_t)m.nvec * dtype_lanes(m.dtype) * (dtype_is_f32(m.dtype) ? 4 : 8);
-    int lds = tab <= 96 * 1024                                                                 ? 1
-              : (tab_c <= 96 * 1024 && s.n_lo <= 18 && !m.dots && state_bytes <= 128) ? 2
-                                                                                        : 0;
+    // 32-bit tables in LDS while they leave room for 1024 threads per CU;
+    // beyond that the narrowed tables with 1024-thread workgroups
+    const int per_cu_sched = h->sched_cfg.spin_per_cu;
+    const int per_cu_1 = std::min(per_cu_sched, std::max(1, (int)((160 * 1024) / (tab + 4096))));
+    const bool narrow_ok = tab_c <= 96 * 1024 && s.n_lo <= 18 && state_bytes <= (m.dots ? 32u : 128u);
+    int lds = (tab <= 96 * 1024 && (per_cu_1 * kBlock >= kSpinBigBlock || !narrow_ok)) ? 1 : narrow_ok ? 2 : 0;
     if (lds == 2) tab = tab_c;
     const int bs = lds == 2 ? kSpinBigBlock : kBlock;
     int64_t need = (s.dim + bs - 1) / bs;
     // workgroups per CU from the schedule, capped by the LDS the tables use
-    // (one 1024-thread workgroup per CU with the narrowed tables)
-    int per_cu = h->sched_cfg.spin_per_cu;
-    if (lds == 1) per_cu = std::min(per_cu, std::max(1, (int)((160 * 1024) / (tab + 4096))));
-    if (lds == 2) per_cu = 1;
+    // (and by the static reduction scratch of a 1024-thread workgroup)
+    int per_cu = per_cu_sched;
+    if (lds == 1) per_cu = per_cu_1;
+    if (lds == 2) per_cu = std::min(2, std::max(1, (int)((160 * 1024) / (tab + 9 * 1024))));
     int64_t cap = (int64_t)(h->basis->ctx->n_cu > 0 ? h->basis->ctx->n_cu : 256) * per_cu;
     if (cap > kMaxGrid) cap = kMaxGrid;
     int grid = (int)(need < cap ? need : cap);
