@@ -81,8 +81,8 @@ __device__ __forceinline__ void store_lanes(S *__restrict__ p, const S (&o)[NV])
 // tables in LDS (kBlock threads); 2: hi_off (32-bit) and lo_rank narrowed
 // to 16 bits in LDS (ranks below 65536), kSpinBigBlock threads, so tables
 // of up to 96 KB (27 and 28 sites) sit in LDS at one workgroup per CU, and
-// the 48-64 KB tables of 25 and 26 sites leave 16 or more waves per CU
-// (with 32-bit tables and kBlock threads the LDS held 8 to 12).
+// the tables of 23 to 26 sites leave 16 to 32 waves per CU (with 32-bit
+// tables and kBlock threads the LDS held 8 to 16).
 constexpr int kSpinBigBlock = 1024;
 template <int TAB> constexpr int spin_block() { return TAB == 2 ? kSpinBigBlock : kBlock; }
 
@@ -371,12 +371,13 @@ int launch_spin_mult(hphi_ham *h, const MultArgs &m)
     // (up to 128 bytes per state, 32 with fused dots: wider accumulators
     // do not fit the registers of a 1024-thread workgroup)
     const size_t state_bytes = (size_t)m.nvec * dtype_lanes(m.dtype) * (dtype_is_f32(m.dtype) ? 4 : 8);
-    // 32-bit tables in LDS while they leave room for 1024 threads per CU;
-    // beyond that the narrowed tables with 1024-thread workgroups
+    // 32-bit tables in LDS while they leave room for 2048 threads per CU;
+    // beyond that the narrowed tables with 1024-thread workgroups (two per
+    // CU where they fit: 23-24 sites)
     const int per_cu_sched = h->sched_cfg.spin_per_cu;
     const int per_cu_1 = std::min(per_cu_sched, std::max(1, (int)((160 * 1024) / (tab + 4096))));
     const bool narrow_ok = tab_c <= 96 * 1024 && s.n_lo <= 18 && state_bytes <= (m.dots ? 32u : 128u);
-    int lds = (tab <= 96 * 1024 && (per_cu_1 * kBlock >= kSpinBigBlock || !narrow_ok)) ? 1 : narrow_ok ? 2 : 0;
+    int lds = (tab <= 96 * 1024 && (per_cu_1 * kBlock >= 2 * kSpinBigBlock || !narrow_ok)) ? 1 : narrow_ok ? 2 : 0;
     if (lds == 2) tab = tab_c;
     const int bs = lds == 2 ? kSpinBigBlock : kBlock;
     int64_t need = (s.dim + bs - 1) / bs;
