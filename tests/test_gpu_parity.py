@@ -225,19 +225,24 @@ def test_spin_36_sites_sampled_rows_fp32(api, ctx):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("dt,nvec", [("c64", 16), ("f64", 1), ("c128", 1)])
-def test_spin_28_sites_sampled_rows(api, ctx, dt, nvec):
-    # the cTPQ block workload's sector (XXZ + J2 ring, 28 sites, 2S^z = 0,
-    # dim 40,116,600) at full size: its rank tables (16384 + 16384 entries)
-    # sit in LDS with lo_rank narrowed to 16 bits; sampled output rows
-    # against the oracle's row formula
+@pytest.mark.parametrize("n,two_sz,lat,dt,nvec", [
+    (28, 0, "xxz_j2", "c64", 16), (28, 0, "xxz_j2", "f64", 1), (28, 0, "xxz_j2", "c128", 1),
+    (27, 1, "chain", "c64", 16), (27, 1, "chain", "f64", 1),
+    (25, 1, "chain", "c128", 1), (24, 0, "ladder", "c128", 1), (24, 0, "ladder", "c64", 16)])
+def test_spin_large_sectors_sampled_rows(api, ctx, n, two_sz, lat, dt, nvec):
+    # 24-28 sites, among them the cTPQ block workload's sector (XXZ + J2
+    # ring, 28 sites, 2S^z = 0, dim 40,116,600) at full size: the rank
+    # tables sit in LDS with lo_rank narrowed to 16 bits (even and odd
+    # splits of the sites, one or two 1024-thread workgroups per CU);
+    # sampled output rows against the oracle's row formula
     import torch
-    say("spin 28 sites sampled rows", dt, nvec)
-    m = W.xxz_chain_j2(28)
-    b = api.Basis.spin(ctx, 28, 0)
+    say("spin large sector sampled rows", n, two_sz, lat, dt, nvec)
+    m = W.xxz_chain_j2(n) if lat == "xxz_j2" else W.random_heisenberg(n, lat, 7)
+    b = api.Basis.spin(ctx, n, two_sz)
     h = api.Hamiltonian.spin(b, m)
     dim = b.dim
-    assert dim == 40116600
+    n_pop = (n + two_sz) // 2
+    assert dim == math.comb(n, n_pop)
     g = torch.Generator(device="cuda").manual_seed(28)
     real = torch.float32 if dt == "c64" else torch.float64
     shape = (dim, nvec) if nvec > 1 else (dim,)
@@ -248,11 +253,11 @@ def test_spin_28_sites_sampled_rows(api, ctx, dt, nvec):
     w = h.mult(v)
     torch.cuda.synchronize()
     say("  mult done")
-    rng = np.random.default_rng(2828)
+    rng = np.random.default_rng(2800 + n)
     rows = np.concatenate([[0, 1, dim - 1], rng.integers(0, dim, 300)])
     worst = 0.0
     for r in rows:
-        cols, vals = O.spin_row(m, 14, int(r))
+        cols, vals = O.spin_row(m, n_pop, int(r))
         vv = host(v[torch.from_numpy(cols).cuda()]).astype(np.complex128).reshape(len(cols), nvec)
         ref = vals @ vv
         scale = np.abs(vals) @ np.abs(vv)
