@@ -257,7 +257,8 @@ typedef struct {
     int fused_update;      /* 1: every product after the first also did the
                               previous step's update (w -= alpha q, beta =
                               |w|) in its rows kernel (Hubbard, one real
-                              vector, hub_row_cols 5); hv_seconds includes it */
+                              vector, hub_row_cols 5 or 6); hv_seconds
+                              includes it */
     double hv_second_kernel_seconds; /* with time_kernels, Hubbard: summed
                               durations of the column (T_up) kernel alone,
                               from an event between the two launches       */
