@@ -115,8 +115,10 @@ def cpu_baseline(workload: str, sample_rows: int):
     if workload == "hubbard4x4":
         m = W.hubbard_square(4, 4, 1.0, 4.0)
         ups, dns = O.hubbard_basis(16, 8, 8)
-        # all down states of the first nu up states; gathers read the whole vector
-        nu = min(sample_rows if sample_rows > 0 else 3000, len(ups))
+        # all down states of the first nu up states (default: every up
+        # state, one whole H*v, about 11 s on 16 threads); gathers read the
+        # whole vector
+        nu = min(sample_rows if sample_rows > 0 else len(ups), len(ups))
         v = np.random.default_rng(0).random(len(ups) * len(dns)) - 0.5
         t0 = time.perf_counter()
         w = O.hubbard_hv_rows(m, ups, dns, v, 0, nu)
