@@ -160,9 +160,9 @@ def test_hubbard_lanczos_f32_storage(api, ctx):
 def test_hubbard_batched_list_walk_bit_identical(api, ctx, lx, ly, nu, nd):
     # T_up with the batched list walk (hub_sweep 5) and T_dn with the batched
     # row staging (hub_row_cols 5, and 6 with pre-scaled slot words) keep
-    # every sum's order: real, complex and FP32 products, the fused Lanczos
-    # epilogue and dots, and the complex Taylor epilogue equal the two-list
-    # walk bit for bit
+    # every sum's order, also with several rows per wave on 32-column slabs:
+    # real, complex and FP32 products, the fused Lanczos epilogue and dots,
+    # and the complex Taylor epilogue equal the two-list walk bit for bit
     import torch
     say("hub batched walk", lx, ly, nu, nd)
     m = W.hubbard_square(lx, ly, 1.0, 4.0)
@@ -177,15 +177,16 @@ def test_hubbard_batched_list_walk_bit_identical(api, ctx, lx, ly, nu, nd):
                      ("batched", dict(hub_row_cols=5, hub_sweep=5, hub_row_order=1)),
                      ("wave_owned", dict(hub_row_cols=5, hub_sweep=6, hub_row_order=1)),
                      ("rcm", dict(hub_row_cols=5, hub_sweep=5, hub_row_order=2)),
-                     ("prescaled", dict(hub_row_cols=6, hub_sweep=5, hub_row_order=2))):
-        h.set_schedule(**base, **sch)
+                     ("prescaled", dict(hub_row_cols=6, hub_sweep=5, hub_row_order=2)),
+                     ("narrow", dict(hub_slab_cols=32, hub_row_cols=6, hub_sweep=5, hub_row_order=2))):
+        h.set_schedule(**{**base, **sch})
         prods = [host(h.mult(x)) for x in ins]
         lz = api.lanczos(h, 60, seed=4) if sch["hub_row_cols"] == 4 else None
         psi = dev(W.random_vector(b.dim, 54, np.complex128))
         te = api.time_evolve(h, psi, 3, dt=0.05, n_max=6)
         out[key] = (prods, lz, host(psi), te)
     a = out["two_list"]
-    for c in (out["batched"], out["wave_owned"], out["rcm"], out["prescaled"]):
+    for c in (out["batched"], out["wave_owned"], out["rcm"], out["prescaled"], out["narrow"]):
         for x, y in zip(a[0], c[0]):
             assert np.array_equal(x, y)
         assert np.array_equal(a[2], c[2])
