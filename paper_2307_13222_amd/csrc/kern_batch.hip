@@ -18,6 +18,9 @@
 
 namespace hphi {
 
+typedef const __attribute__((address_space(4))) SpinBondDev CSpinBond;
+typedef const __attribute__((address_space(4))) double CDouble;
+
 struct BatchItemDev {
     const uint32_t *states;
     int64_t dim;
@@ -56,6 +59,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_lanczos_batch(const BatchItem
     __shared__ double sh[kBatchThreads / kWave];
     __shared__ uint32_t s_tab[kBatchLdsTab];
     const BatchItemDev it = items[blockIdx.x];
+    // uniform tables through the scalar cache (the item is read from memory,
+    // so without the cast every lane would load them with vector loads)
+    const CSpinBond *bc = (const CSpinBond *)(it.bonds);
+    const CDouble *hzc = (const CDouble *)(it.hz);
     const int64_t dim = it.dim;
     const uint32_t lomask = (1u << it.n_lo) - 1u;
     const uint32_t nl = 1u << it.n_lo, nh = 1u << it.n_hi;
@@ -86,17 +93,17 @@ __global__ __launch_bounds__(kBatchThreads) void k_lanczos_batch(const BatchItem
             const uint32_t x = it.states[r];
             double hv = 0.0, diag = 0.0;
             for (int b = 0; b < it.nb; ++b) {
-                const uint32_t m = (uint32_t)it.bonds[b].mask, t = x & m;
+                const uint32_t m = (uint32_t)bc[b].mask, t = x & m;
                 if (t == 0u || t == m) {
-                    diag += it.bonds[b].jz4;
+                    diag += bc[b].jz4;
                 } else {
-                    diag -= it.bonds[b].jz4;
+                    diag -= bc[b].jz4;
                     const uint32_t y = x ^ m;
-                    hv += it.bonds[b].jxy2 * qc[hi[y >> it.n_lo] + lo[y & lomask]];
+                    hv += bc[b].jxy2 * qc[hi[y >> it.n_lo] + lo[y & lomask]];
                 }
             }
             if (it.hz)
-                for (int i = 0; i < it.n_sites; ++i) diag -= it.hz[i] * (((x >> i) & 1u) ? 0.5 : -0.5);
+                for (int i = 0; i < it.n_sites; ++i) diag -= hzc[i] * (((x >> i) & 1u) ? 0.5 : -0.5);
             double o = c1 * (hv + diag * qc[r]);
             if (k > 0) o += c2 * qp[r];
             w[r] = o;
@@ -147,6 +154,10 @@ __global__ __launch_bounds__(kBatchLdsThreads) void k_lanczos_batch_lds(const Ba
     extern __shared__ unsigned char smem_raw[];
     __shared__ double sh[kBatchLdsThreads / kWave];
     const BatchItemDev it = items[blockIdx.x];
+    // uniform tables through the scalar cache (the item is read from memory,
+    // so without the cast every lane would load them with vector loads)
+    const CSpinBond *bc = (const CSpinBond *)(it.bonds);
+    const CDouble *hzc = (const CDouble *)(it.hz);
     const int64_t dim = it.dim;
     double *Q = reinterpret_cast<double *>(smem_raw);
     uint32_t *lo = reinterpret_cast<uint32_t *>(Q + dim);
@@ -172,17 +183,17 @@ __global__ __launch_bounds__(kBatchLdsThreads) void k_lanczos_batch_lds(const Ba
             const uint32_t x = it.states[r];
             double hv = 0.0, diag = 0.0;
             for (int b = 0; b < it.nb; ++b) {
-                const uint32_t m = (uint32_t)it.bonds[b].mask, t = x & m;
+                const uint32_t m = (uint32_t)bc[b].mask, t = x & m;
                 if (t == 0u || t == m) {
-                    diag += it.bonds[b].jz4;
+                    diag += bc[b].jz4;
                 } else {
-                    diag -= it.bonds[b].jz4;
+                    diag -= bc[b].jz4;
                     const uint32_t y = x ^ m;
-                    hv += it.bonds[b].jxy2 * Q[hi[y >> it.n_lo] + lo[y & lomask]];
+                    hv += bc[b].jxy2 * Q[hi[y >> it.n_lo] + lo[y & lomask]];
                 }
             }
             if (it.hz)
-                for (int i = 0; i < it.n_sites; ++i) diag -= it.hz[i] * (((x >> i) & 1u) ? 0.5 : -0.5);
+                for (int i = 0; i < it.n_sites; ++i) diag -= hzc[i] * (((x >> i) & 1u) ? 0.5 : -0.5);
             const double qr = Q[r];
             double o = c1 * (hv + diag * qr);
             if (k > 0) o += c2 * P[r];
