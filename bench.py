@@ -75,11 +75,11 @@ def parse():
 # counters (fetch 2.000, write 1.000). Valid only for the kernel sources and
 # schedule it was taken with; anything else reports null.
 HUB_TRAFFIC = {
-    "sources_sha256": {"kern_hub.hip": "d25e65348a8f0be4198037ca687cf1758dac3a6a111dc9b4bfd38a86f73a4d96",
+    "sources_sha256": {"kern_hub.hip": "050162874246d20567af0a22231414661dd1bfbc326b74c4e7a3f78321f18bc3",
                        "kern_common.h": "a2e26c530c1c272d1d655a2c1c871ef80258f6d052067e42662ba1d7b102b269"},
     "schedule": {"hub_slab_cols": 128, "hub_groups": 128, "hub_item_rows": 16, "hub_row_cols": 6, "hub_sweep": 5, "hub_row_order": 2},
-    "cols_fetch_kib": 5.77634e+06, "cols_write_kib": 1.32041e+06,
-    "rows_fetch_kib": 1.43001e+06, "rows_write_kib": 2.68634e+06,
+    "cols_fetch_kib": 5.78109e+06, "cols_write_kib": 1.32042e+06,
+    "rows_fetch_kib": 1.43681e+06, "rows_write_kib": 2.68637e+06,
     "fetch_factor": 2.0, "write_factor": 1.0,
 }
 

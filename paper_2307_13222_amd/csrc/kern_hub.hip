@@ -747,7 +747,9 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fz(HubKArgs a)
     uint32_t *s_base = reinterpret_cast<uint32_t *>(s_row + (ddn + 1));
     uint32_t *s_w = s_base + nch;
     uint16_t *s_d = reinterpret_cast<uint16_t *>(s_w + nch);
-    double *sh_red = reinterpret_cast<double *>(((uintptr_t)(s_d + ddn) + 7) & ~(uintptr_t)7);
+    // (byte offset from the LDS base, so the pointer stays an LDS pointer)
+    const size_t red_off = ((size_t)(reinterpret_cast<unsigned char *>(s_d + ddn) - smem_raw) + 7) & ~(size_t)7;
+    double *sh_red = reinterpret_cast<double *>(smem_raw + red_off);
     double *s_blk = sh_red + 16;
     unsigned *s_last = reinterpret_cast<unsigned *>(s_blk + 1);
     const uint32_t *__restrict__ ent = FC ? a.fc_ent : a.fb_ent;
