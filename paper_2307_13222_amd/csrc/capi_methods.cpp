@@ -398,6 +398,9 @@ int hphi_sqw(hphi_ham *h, const hphi_sqw_opts *o, const void *b_dev, const doubl
             HPHI_TRY(start(1, &tmp));
         }
         int it = 0, conv = 0;
+        // spin models on a stored basis: the product's fixed-order dots form
+        // mu = p^T (z_s p - H p) and alpha (one vector pass fewer)
+        const bool fold_mu = h->kind == 0 && spin_stored_path(h);
         while (it < o->max_iter) {
             MultArgs a{};
             a.dtype = HPHI_C128;
@@ -406,8 +409,12 @@ int hphi_sqw(hphi_ham *h, const hphi_sqw_opts *o, const void *b_dev, const doubl
             a.w = hp.p;
             a.red = red;
             a.stream = st;
+            if (fold_mu) {
+                a.dots = 1;
+                a.cocg = cgm.p;
+            }
             HPHI_TRY(launch_mult(h, a));
-            HPHI_TRY(launch_cocg_iter(r.p, p.p, hp.p, bp.p, dim, cgm.p, shm.p, n_shift, tol_part, red, st));
+            HPHI_TRY(launch_cocg_iter(r.p, p.p, hp.p, bp.p, dim, cgm.p, shm.p, n_shift, tol_part, red, st, fold_mu));
             ++it;
             if (it % check == 0 || it == o->max_iter) {
                 HPHI_HIP(hipMemcpyAsync(&hc, cgm.p, sizeof(CgDev), hipMemcpyDeviceToHost, st));

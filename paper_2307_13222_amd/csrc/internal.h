@@ -224,6 +224,9 @@ struct MultArgs {
     Reduce lz_red;
     hipEvent_t ev_mid;  // optional: recorded between the two kernels of a Hubbard H*v
     void *raw_out;      // optional (spin, stored basis): H v before the epilogue
+    void *cocg;         // optional (spin, stored basis, one complex vector, dots = 1):
+                        // the dots become the COCG mu = v^T (z_s v - H v) and the
+                        // last block does the alpha step on this CgDev
 };
 bool hub_rows_fused_ok(hphi_ham *h, int nv);
 bool spin_stored_path(const hphi_ham *h);
@@ -325,7 +328,7 @@ struct ShiftDev {
 int launch_cocg_init(const void *b, void *r, void *p, int64_t dim, void *cg, void *sh, int nsh, double tol,
                      Reduce red, hipStream_t st);
 int launch_cocg_iter(void *r, void *p, const void *h, const void *b, int64_t dim, void *cg, void *sh,
-                     int nsh, double tol, Reduce red, hipStream_t st);
+                     int nsh, double tol, Reduce red, hipStream_t st, bool mu_done = false);
 int launch_cplx_part(const void *b, void *out, int64_t dim, int part, hipStream_t st);
 int launch_pair_rsqrt(const double *n, double *s, int nl, hipStream_t st);
 

@@ -13,6 +13,37 @@ namespace hphi {
 constexpr int kBlock = 256;      // threads per workgroup for streaming kernels
 constexpr int kWave = 64;
 
+// complex FP64 arithmetic of the shifted COCG
+__device__ __forceinline__ cd cmul(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ cd cadd(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cd csub(cd a, cd b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cd cdiv(cd a, cd b)
+{
+    // Smith's algorithm
+    if (fabs(b.re) >= fabs(b.im)) {
+        const double r = b.im / b.re, d = b.re + b.im * r;
+        return {(a.re + a.im * r) / d, (a.im - a.re * r) / d};
+    }
+    const double r = b.re / b.im, d = b.re * r + b.im;
+    return {(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+}
+__device__ __forceinline__ double cabs2(cd a) { return a.re * a.re + a.im * a.im; }
+
+// COCG scalar step once mu = p^T (z_s p - H p) is known: alpha = rho / mu
+// (breakdown when mu = 0). One thread.
+__device__ __forceinline__ void cocg_alpha_step(CgDev *cg, cd mu)
+{
+    cg->alpha_prev = cg->alpha;
+    cg->beta_prev = cg->beta;
+    if (cabs2(mu) == 0.0) {
+        cg->breakdown = 1;
+        cg->alpha = {0.0, 0.0};
+    } else {
+        cg->alpha = cdiv(cg->rho, mu);
+    }
+    __threadfence();
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll

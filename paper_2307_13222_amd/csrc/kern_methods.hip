@@ -19,20 +19,6 @@
 
 namespace hphi {
 
-__device__ __forceinline__ cd cmul(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
-__device__ __forceinline__ cd cadd(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
-__device__ __forceinline__ cd csub(cd a, cd b) { return {a.re - b.re, a.im - b.im}; }
-__device__ __forceinline__ cd cdiv(cd a, cd b)
-{
-    // Smith's algorithm
-    if (fabs(b.re) >= fabs(b.im)) {
-        const double r = b.im / b.re, d = b.re + b.im * r;
-        return {(a.re + a.im * r) / d, (a.im - a.re * r) / d};
-    }
-    const double r = b.re / b.im, d = b.re * r + b.im;
-    return {(a.re * r + a.im) / d, (a.im * r - a.re) / d};
-}
-__device__ __forceinline__ double cabs2(cd a) { return a.re * a.re + a.im * a.im; }
 
 // init: rho = b^T b, |b|^2; r = p = b; shift state.
 __global__ __launch_bounds__(kBlock) void k_cocg_init(const double *b, double *r, double *p, int64_t dim,
@@ -114,18 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_cocg_mu(const double *p, const doubl
     block_sum<2>(a, shr);
     if (threadIdx.x == 0) { blk[0] = a[0]; blk[1] = a[1]; }
     __syncthreads();
-    if (grid_finish(blk, 2, red, shr) && threadIdx.x == 0) {
-        const cd mu = {red.result[0], red.result[1]};
-        cg->alpha_prev = cg->alpha;
-        cg->beta_prev = cg->beta;
-        if (cabs2(mu) == 0.0) {
-            cg->breakdown = 1;
-            cg->alpha = {0.0, 0.0};
-        } else {
-            cg->alpha = cdiv(cg->rho, mu);
-        }
-        __threadfence();
-    }
+    if (grid_finish(blk, 2, red, shr) && threadIdx.x == 0) cocg_alpha_step(cg, {red.result[0], red.result[1]});
 }
 
 // Per-shift scalar recurrences (the threads of one block, one shift each at
@@ -270,13 +245,15 @@ int launch_cocg_init(const void *b, void *r, void *p, int64_t dim, void *cg, voi
 }
 
 int launch_cocg_iter(void *r, void *p, const void *h, const void *b, int64_t dim, void *cg, void *sh,
-                     int nsh, double tol, Reduce red, hipStream_t st)
+                     int nsh, double tol, Reduce red, hipStream_t st, bool mu_done)
 {
     // at least 8 elements per thread, so the four-element trips dominate
     int64_t g8 = (dim + kBlock * 8 - 1) / (kBlock * 8);
     const int g = (int)(g8 < 1 ? 1 : (g8 > 2048 ? 2048 : g8));
-    hipLaunchKernelGGL(k_cocg_mu, dim3(g), dim3(kBlock), 0, st, (const double *)p, (const double *)h,
-                       dim, (CgDev *)cg, red);
+    // (mu_done: the product's epilogue already formed mu and alpha)
+    if (!mu_done)
+        hipLaunchKernelGGL(k_cocg_mu, dim3(g), dim3(kBlock), 0, st, (const double *)p, (const double *)h,
+                           dim, (CgDev *)cg, red);
     hipLaunchKernelGGL(k_cocg_r, dim3(g), dim3(kBlock), 0, st, (double *)r, (const double *)p,
                        (const double *)h, (const double *)b, dim, (CgDev *)cg, (ShiftDev *)sh, nsh, tol, red);
     hipLaunchKernelGGL(k_cocg_p, dim3(g), dim3(kBlock), 0, st, (const double *)r, (double *)p, dim,

@@ -33,6 +33,7 @@ struct SpinKArgs {
     Reduce red;
     int coef_cplx;
     void *raw_out;   // optional: H v itself (before the epilogue), same layout as w
+    CgDev *cocg;     // optional (NV = 2 with dots): COCG mu and alpha step
 };
 
 // Load NV contiguous scalars at p (p aligned to min(16, NV * sizeof(S))).
@@ -86,8 +87,16 @@ __device__ __forceinline__ void store_lanes(S *__restrict__ p, const S (&o)[NV])
 constexpr int kSpinBigBlock = 1024;
 template <int TAB> constexpr int spin_block() { return TAB == 2 ? kSpinBigBlock : kBlock; }
 
+// Narrowed-table kernels with fused dots on states of at most 16 bytes:
+// registers for two 1024-thread workgroups per CU (8 waves per SIMD), as
+// their LDS allows (the dots' FP64 accumulators would otherwise leave one).
+template <int TAB, typename S, int NV, bool DOTS> constexpr int spin_min_waves()
+{
+    return (TAB == 2 && DOTS && NV * sizeof(S) <= 16) ? 8 : 1;
+}
+
 template <typename S, int NV, int TAB, bool DOTS>
-__global__ __launch_bounds__(spin_block<TAB>()) void k_spin_hv(SpinKArgs a)
+__global__ __launch_bounds__(spin_block<TAB>(), (spin_min_waves<TAB, S, NV, DOTS>())) void k_spin_hv(SpinKArgs a)
 {
     extern __shared__ uint32_t smem_tab[];
     __shared__ double sh_red[spin_block<TAB>() / kWave * 2 * 32];
@@ -131,6 +140,8 @@ __global__ __launch_bounds__(spin_block<TAB>()) void k_spin_hv(SpinKArgs a)
     const S c1s = (S)c1, c2s = (S)c2;
 
     constexpr int ND = DOTS ? NV : 1;
+    CgDev *const cgp = (DOTS && NV == 2) ? a.cocg : nullptr;
+    const cd zs = cgp ? cgp->zs : cd{0.0, 0.0};
     double d0[ND], d1[ND];
 #pragma unroll
     for (int j = 0; j < ND; ++j) d0[j] = d1[j] = 0.0;
@@ -231,11 +242,24 @@ __global__ __launch_bounds__(spin_block<TAB>()) void k_spin_hv(SpinKArgs a)
             store_lanes<S, NV>(accp + (size_t)r * NV, aa);
         }
         if constexpr (DOTS) {
+            bool cg_done = false;
+            if constexpr (NV == 2) {
+                if (cgp) {
+                    // COCG mu term p^T (z_s p - H p) of this state
+                    const cd pv = {(double)me[0], (double)me[1]};
+                    const cd t = cmul(pv, csub(cmul(zs, pv), cd{(double)hv[0], (double)hv[1]}));
+                    d0[0] += t.re;
+                    d0[1] += t.im;
+                    cg_done = true;
+                }
+            }
+            if (!cg_done) {
 #pragma unroll
-            for (int j = 0; j < NV; ++j) {
-                const double o = a.dot_raw ? (double)hv[j] : (double)out[j];
-                d0[j] += (double)me[j] * o;
-                d1[j] += o * o;
+                for (int j = 0; j < NV; ++j) {
+                    const double o = a.dot_raw ? (double)hv[j] : (double)out[j];
+                    d0[j] += (double)me[j] * o;
+                    d1[j] += o * o;
+                }
             }
         }
     }
@@ -259,7 +283,8 @@ __global__ __launch_bounds__(spin_block<TAB>()) void k_spin_hv(SpinKArgs a)
             sh_blk[threadIdx.x] = t;
         }
         __syncthreads();
-        grid_finish(sh_blk, 2 * NV, a.red, sh_red);
+        if (grid_finish(sh_blk, 2 * NV, a.red, sh_red) && cgp && threadIdx.x == 0)
+            cocg_alpha_step(cgp, {a.red.result[0], a.red.result[1]});
     }
 }
 
@@ -363,6 +388,7 @@ int launch_spin_mult(hphi_ham *h, const MultArgs &m)
     a.red = m.red;
     a.coef_cplx = m.coef_cplx;
     a.raw_out = m.raw_out;
+    a.cocg = static_cast<CgDev *>(m.cocg);
     const int nv = m.nvec * dtype_lanes(m.dtype);
     size_t tab = sizeof(uint32_t) * ((size_t(1) << s.n_lo) + (size_t(1) << s.n_hi));
     // the same tables with lo_rank in 16 bits (its values are ranks among
