@@ -284,15 +284,22 @@ typedef struct {
     int breakdown;         /* out: 1 if beta_k fell below the threshold       */
 } hphi_batch_item;
 
-/* Many independent Lanczos ground-state solves in one launch, one
- * workgroup per request (the recurrence of hphi_lanczos, FP64 vectors,
- * fixed-order block reductions: a request's numbers do not depend on the
- * other requests in the launch). Meant for sectors small enough that a
- * single solve is bound by kernel-launch latency. The library allocates
- * 3 * dim doubles of workspace per request for the call. Synchronous on
- * `stream`. Errors: INVALID_ARG (n < 1, max_iter < 1), UNSUPPORTED (a
- * Hamiltonian that is not a spin model on a stored basis), OUT_OF_MEMORY,
- * DEVICE. */
+/* Many independent Lanczos ground-state solves in one launch (the
+ * recurrence of hphi_lanczos, FP64 vectors). Meant for sectors small enough
+ * that a single solve is bound by kernel-launch latency. A launch whose
+ * requests together need at most half of the CUs runs each request on a
+ * team of up to 32 workgroups (1024 rows each, or more for sectors above
+ * 32768 states) that meet at a barrier of their own twice per step; larger
+ * launches run each request on one workgroup. Every reduction follows an
+ * order fixed by the rows (64-row chunks, chunks in order within 1024-row
+ * slices, slices in order), so a request's numbers do not depend on the
+ * other requests in the launch nor on which of the two ways ran it. The
+ * library allocates 3 * dim doubles of workspace per request for the
+ * call (plus under 2 % of that for partial sums). Synchronous on `stream`. Errors: INVALID_ARG (n < 1,
+ * max_iter < 1), UNSUPPORTED (a Hamiltonian that is not a spin model on a
+ * stored basis), OUT_OF_MEMORY, DEVICE (also when a team barrier waited
+ * for seconds without its members arriving, which the launch scheme rules
+ * out: every wave then leaves and the call reports the item). */
 int hphi_lanczos_batch(hphi_batch_item *items, int n, void *stream);
 
 /* Lowest k eigenvalues (ascending) of the symmetric tridiagonal matrix with

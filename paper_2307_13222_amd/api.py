@@ -239,8 +239,10 @@ def lanczos(ham: Hamiltonian, max_iter: int, seed: int = 1, v0=None, storage: st
 
 def lanczos_batch(hams: Sequence[Hamiltonian], max_iter, seeds, keep_coefficients: bool = False,
                   stream=None):
-    """Independent Lanczos ground-state solves in one launch (one workgroup
-    per request). max_iter and seeds are scalars or per-request sequences."""
+    """Independent Lanczos ground-state solves in one launch (a team of
+    workgroups per request when the launch is small, one workgroup per
+    request otherwise; the same numbers either way). max_iter and seeds are
+    scalars or per-request sequences."""
     n = len(hams)
     its = [max_iter] * n if np.isscalar(max_iter) else list(max_iter)
     sds = [seeds] * n if np.isscalar(seeds) else list(seeds)

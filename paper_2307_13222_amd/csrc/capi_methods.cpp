@@ -245,60 +245,97 @@ int hphi_lanczos_batch(hphi_batch_item *items, int n, void *stream)
     }
     DeviceGuard g(items[0].ham->basis->ctx->device);
     hipStream_t st = (hipStream_t)stream;
-    // one allocation: vectors, then alpha/beta, then flags
-    size_t nq = 0, nab = 0;
+    // Team shape of each request (from its dimension alone). Requests whose
+    // vector fits in LDS run on one workgroup each (throughput) unless the
+    // whole launch is small, when teams cut the latency (teams of a large
+    // launch cost each other: every team barrier writes back and invalidates
+    // its XCD's L2). The other requests always run as teams, in launches of
+    // at most one workgroup per CU so that all members of a launch are
+    // resident together. The reductions are ordered by rows, so every way
+    // gives the same numbers.
+    const size_t kLdsCap = 150 * 1024;
+    std::vector<size_t> q_off(n), ab_off(n), part_off(n);
+    std::vector<int> tw(n), tbase(n);
+    std::vector<char> lds_ok(n);
+    size_t nq = 0, nab = 0, npart = 0;
+    int team_total = 0, team_max = 1;
     for (int i = 0; i < n; ++i) {
-        nq += 3 * (size_t)items[i].ham->basis->dim;
+        const Species &s = items[i].ham->basis->sp[0];
+        q_off[i] = nq;
+        ab_off[i] = nab;
+        part_off[i] = npart;
+        nq += 3 * (size_t)s.dim;
         nab += 2 * (size_t)items[i].max_iter + 1;
+        npart += batch_part_doubles(s.dim);
+        int rows = 0;
+        batch_team_shape(s.dim, &tw[i], &rows);
+        team_total += tw[i];
+        team_max = std::max(team_max, tw[i]);
+        lds_ok[i] = batch_lds_bytes(s.dim, s.n_lo, s.n_hi) <= kLdsCap;
     }
+    const int n_cu = items[0].ham->basis->ctx->n_cu > 0 ? items[0].ham->basis->ctx->n_cu : 256;
+    const bool small = team_max > 1 && 2 * team_total <= n_cu;
+    std::vector<int> order;   // LDS-kernel requests, then team requests by launch group
+    size_t lds_max = 0;
+    for (int i = 0; i < n; ++i)
+        if (lds_ok[i] && !small) {
+            order.push_back(i);
+            const Species &s = items[i].ham->basis->sp[0];
+            lds_max = std::max(lds_max, batch_lds_bytes(s.dim, s.n_lo, s.n_hi));
+        }
+    const int n_lds = (int)order.size();
+    std::vector<int> grp_first, grp_w;   // team launch groups: first position, workgroups
+    for (int i = 0; i < n; ++i) {
+        if (lds_ok[i] && !small) continue;
+        if (grp_first.empty() || grp_w.back() + tw[i] > n_cu) {
+            grp_first.push_back((int)order.size());
+            grp_w.push_back(0);
+        }
+        tbase[i] = grp_w.back();
+        grp_w.back() += tw[i];
+        order.push_back(i);
+    }
+    const int n_grp = (int)grp_first.size();
+    // one allocation: vectors, alpha/beta, partial sums, then (zeroed
+    // together) one arrival ticket per team launch, the team barrier
+    // counters and the flags; tickets and counters one per 256-byte line so
+    // that polling teams do not share a line
     DevMem work, desc;
-    HPHI_TRY(work.alloc(sizeof(double) * (nq + nab) + sizeof(int) * 2 * (size_t)n));
+    constexpr size_t kLine = 64;   // unsigned per 256-byte line
+    const size_t dbytes = (sizeof(double) * (nq + nab + npart) + 255) / 256 * 256;
+    const size_t ibytes = sizeof(unsigned) * kLine * ((size_t)n_grp + (size_t)n) + sizeof(int) * 2 * (size_t)n;
+    HPHI_TRY(work.alloc(dbytes + ibytes));
     double *qbase = work.as<double>();
     double *abbase = qbase + nq;
-    int *flags = reinterpret_cast<int *>(abbase + nab);
-    // descriptors: requests whose vector fits in LDS first (LDS kernel),
-    // the rest after (L2 kernel)
-    const size_t kLdsCap = 150 * 1024;
-    std::vector<int> order;
-    size_t lds_max = 0;
-    for (int i = 0; i < n; ++i) {
-        const Species &s = items[i].ham->basis->sp[0];
-        const size_t need = batch_lds_bytes(s.dim, s.n_lo, s.n_hi);
-        if (need <= kLdsCap) {
-            order.push_back(i);
-            lds_max = std::max(lds_max, need);
-        }
-    }
-    const int n_lds = (int)order.size();
-    for (int i = 0; i < n; ++i) {
-        const Species &s = items[i].ham->basis->sp[0];
-        if (batch_lds_bytes(s.dim, s.n_lo, s.n_hi) > kLdsCap) order.push_back(i);
-    }
+    double *partbase = abbase + nab;
+    unsigned *tickets = reinterpret_cast<unsigned *>(static_cast<unsigned char *>(work.p) + dbytes);
+    unsigned *bar0 = tickets + kLine * (size_t)n_grp;
+    int *flags = reinterpret_cast<int *>(bar0 + kLine * (size_t)n);
+    HPHI_HIP(hipMemsetAsync(tickets, 0, ibytes, st));
     std::vector<unsigned char> hd(batch_item_size() * (size_t)n);
-    size_t oq = 0, oab = 0;
-    std::vector<size_t> ab_off(n);
-    for (int i = 0; i < n; ++i) {
-        ab_off[i] = oab;
-        oab += 2 * (size_t)items[i].max_iter + 1;
-    }
     for (int p = 0; p < n; ++p) {
         const int i = order[p];
-        HPHI_TRY(fill_batch_item(items[i].ham, items[i].max_iter, items[i].seed, qbase + oq, abbase + ab_off[i],
-                                 abbase + ab_off[i] + items[i].max_iter, flags + 2 * i,
+        HPHI_TRY(fill_batch_item(items[i].ham, items[i].max_iter, items[i].seed, qbase + q_off[i],
+                                 abbase + ab_off[i], abbase + ab_off[i] + items[i].max_iter, flags + 2 * i,
+                                 partbase + part_off[i], bar0 + kLine * i, tbase[i],
                                  hd.data() + batch_item_size() * p));
-        oq += 3 * (size_t)items[i].ham->basis->dim;
     }
     HPHI_TRY(desc.alloc(hd.size()));
     HPHI_HIP(hipMemcpyAsync(desc.p, hd.data(), hd.size(), hipMemcpyHostToDevice, st));
-    if (n_lds > 0) HPHI_TRY(launch_lanczos_batch(desc.p, n_lds, st, lds_max));
-    if (n_lds < n)
-        HPHI_TRY(launch_lanczos_batch(static_cast<unsigned char *>(desc.p) + batch_item_size() * n_lds, n - n_lds,
-                                      st, 0));
+    unsigned char *dd = static_cast<unsigned char *>(desc.p);
+    if (n_lds > 0) HPHI_TRY(launch_lanczos_batch(dd, n_lds, st, lds_max));
+    for (int g = 0; g < n_grp; ++g) {
+        const int end = g + 1 < n_grp ? grp_first[g + 1] : n;
+        HPHI_TRY(launch_lanczos_team(dd + batch_item_size() * grp_first[g], end - grp_first[g], grp_w[g],
+                                     tickets + kLine * g, st));
+    }
     std::vector<double> hab(nab);
     std::vector<int> hf(2 * (size_t)n);
     HPHI_HIP(hipMemcpyAsync(hab.data(), abbase, sizeof(double) * nab, hipMemcpyDeviceToHost, st));
     HPHI_HIP(hipMemcpyAsync(hf.data(), flags, sizeof(int) * 2 * n, hipMemcpyDeviceToHost, st));
     HPHI_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i)
+        if (hf[2 * i + 1] == 3) return fail(HPHI_ERR_DEVICE, "item %d: team barrier timed out", i);
     for (int i = 0; i < n; ++i) {
         const double *al = hab.data() + ab_off[i];
         const double *be = al + items[i].max_iter;

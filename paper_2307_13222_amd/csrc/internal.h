@@ -335,7 +335,10 @@ int launch_pair_rsqrt(const double *n, double *s, int nl, hipStream_t st);
 // batched small-sector Lanczos (kern_batch.hip)
 size_t batch_item_size();
 int fill_batch_item(hphi_ham *h, int iters, uint64_t seed, double *q, double *alpha, double *beta, int *done,
-                    void *out);
+                    double *part, unsigned *bar, int team_base, void *out);
+int launch_lanczos_team(const void *items_dev, int n, int grid, unsigned *ticket, hipStream_t st);
+size_t batch_part_doubles(int64_t dim);
+void batch_team_shape(int64_t dim, int *w, int *rows);
 int launch_lanczos_batch(const void *items_dev, int n, hipStream_t st, size_t lds_bytes);
 size_t batch_lds_bytes(int64_t dim, int n_lo, int n_hi);
 

@@ -1,19 +1,24 @@
-// Batched small-sector Lanczos: one workgroup runs a whole solve.
+// Batched small-sector Lanczos: whole solves inside one launch.
 //
 // For sectors of up to a few hundred thousand states an H*v takes a few
 // microseconds, so a solve driven by one kernel launch per step is bound by
 // launch latency. Here a launch carries many independent requests (each its
-// own spin Hamiltonian, sector, iteration count and seed); workgroup b runs
-// the complete recurrence of request b (the plain Lanczos of the HPhi update
-// paper's introduction, without reorthogonalization):
+// own spin Hamiltonian, sector, iteration count and seed) and runs the
+// complete recurrence of each (the plain Lanczos of the HPhi update paper's
+// introduction, without reorthogonalization):
 //   q_0 = r (SplitMix64 uniform [-1/2, 1/2), the same stream as the
 //   single-solve path), s_0 = 1/|q_0|;
 //   w = s_k H q_k - beta_k s_{k-1} q_{k-1};  alpha_k = s_k <q_k, w>;
 //   w -= alpha_k s_k q_k;  beta_{k+1} = |w|;  q_{k+1} = w, s_{k+1} = 1/beta_{k+1};
-// with FP64 block reductions in a fixed order, so a request's result does
-// not depend on which other requests share the launch. The vectors live in
-// global memory (L2-resident at these sizes); the rank tables are staged in
-// LDS when they fit.
+// either on one workgroup with the vector in LDS (many small requests:
+// throughput) or on a team of workgroups that meet at a barrier of their own
+// (few requests, or vectors too large for LDS: latency).
+//
+// Every reduction follows one order defined on the rows alone: each 64-row
+// chunk is summed by one fixed cross-lane tree, the chunks of a 1024-row
+// slice in order, then the slices in order. A request's numbers are
+// therefore the same in either kernel, whatever the team width and whatever
+// else shares the launch.
 #include "kern_common.h"
 
 namespace hphi {
@@ -36,34 +41,307 @@ struct BatchItemDev {
     double *q;          // 3 * dim workspace
     double *alpha;      // iters
     double *beta;       // iters + 1
-    int *done;          // [0] steps done, [1] breakdown flag
+    int *done;          // [0] steps done, [1] breakdown flag (3: team barrier timed out)
+    double *part;       // chunk partials (dim / 64, rounded up), then two buffers of slice sums
+    unsigned *bar;      // team barrier arrivals (zero at launch)
+    int team_base;      // first arrival ticket of the request's team
+    int team_w;         // members in the team
+    int team_rows;      // rows per member, a multiple of the slice
 };
 
-constexpr int kBatchThreads = 256;
 constexpr int kBatchLdsTab = 8192;   // uint32 entries of staged tables
+constexpr int kChunk = 64;           // rows per chunk partial (one wave)
+constexpr int kSlice = 16;           // chunks per slice
+constexpr unsigned kTeamSpin = 1u << 25;   // polls before a barrier gives up (seconds)
+constexpr int kTeamMax = 32;               // workgroups per request at most
 
-__device__ __forceinline__ double batch_sum(double x, double *sh)
+__host__ __device__ __forceinline__ int64_t n_chunks(int64_t dim) { return (dim + kChunk - 1) / kChunk; }
+
+// One DPP move of a double (both halves); lanes without a source read 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v)
 {
-    double v[1] = {x};
-    block_sum<1>(v, sh);
-    __shared__ double bcast;
-    if (threadIdx.x == 0) bcast = v[0];
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// The wave's 64 row contributions -> part[c], by one fixed tree: shifts by
+// 1, 2, 4 and 8 lanes within each 16-lane row (lane 15 of a row then holds
+// the row's sum), lane 15 of rows 0 and 2 added into rows 1 and 3, then
+// lane 31 into rows 2 and 3; lane 63 holds the total and stores it. Every
+// lane of the wave must be active.
+__device__ __forceinline__ void chunk_store(double v, double *part, int64_t c)
+{
+    v += dpp_f64<0x111, 0xF>(v);   // row_shr:1
+    v += dpp_f64<0x112, 0xF>(v);   // row_shr:2
+    v += dpp_f64<0x114, 0xF>(v);   // row_shr:4
+    v += dpp_f64<0x118, 0xF>(v);   // row_shr:8
+    v += dpp_f64<0x142, 0xA>(v);   // row_bcast:15
+    v += dpp_f64<0x143, 0xC>(v);   // row_bcast:31
+    if ((threadIdx.x & (kWave - 1)) == kWave - 1) part[c] = v;
+}
+
+// Slice s of the chunk partials, summed in chunk order (all loads in flight
+// first; a chunk past the end adds exactly +0).
+__device__ __forceinline__ double slice_sum(const double *part, int64_t s, int64_t nch)
+{
+    double v[kSlice];
+#pragma unroll
+    for (int j = 0; j < kSlice; ++j) {
+        const int64_t c = s * kSlice + j;
+        v[j] = c < nch ? part[c] : 0.0;
+    }
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < kSlice; ++j) t += v[j];
+    return t;
+}
+
+// Sum of the ns slice values in order; one whole wave calls it and every
+// lane returns the same value. With FROM_CHUNKS the slice values are summed
+// from the chunk partials here, otherwise they are read from `v`.
+template <bool FROM_CHUNKS>
+__device__ __forceinline__ double ordered_total(const double *v, int64_t nch)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t ns = (nch + kSlice - 1) / kSlice;
+    double tot = 0.0;
+    for (int64_t s0 = 0; s0 < ns; s0 += kWave) {
+        const int64_t s = s0 + lane;
+        double S = 0.0;
+        if (s < ns) S = FROM_CHUNKS ? slice_sum(v, s, nch) : v[s];
+        const int cnt = (int)min((int64_t)kWave, ns - s0);
+        for (int j = 0; j < cnt; ++j) tot += __shfl(S, j, kWave);
+    }
+    return tot;
+}
+
+// Workgroup-wide ordered total of the chunk partials just stored by this
+// workgroup (the one-workgroup kernel).
+__device__ __forceinline__ double block_total(const double *part, int64_t nch, double *bcast)
+{
     __syncthreads();
-    const double r = bcast;
+    if (threadIdx.x < kWave) {
+        const double t = ordered_total<true>(part, nch);
+        if (threadIdx.x == 0) *bcast = t;
+    }
+    __syncthreads();
+    const double r = *bcast;
     __syncthreads();
     return r;
 }
 
-__global__ __launch_bounds__(kBatchThreads) void k_lanczos_batch(const BatchItemDev *items)
+// Bond sums of one state: the off-diagonal gathers and the diagonal. With
+// BATCH (vectors in global memory) eight bonds go per batch, their targets
+// first, then all eight loads in flight, then the sums in bond order, a bond
+// without a flip adding exactly +0; without (vector in LDS) only the flips
+// load. Both add the same terms in the same order.
+template <bool BATCH, typename RankFn>
+__device__ __forceinline__ void spin_row(const BatchItemDev &it, const CSpinBond *bc, const CDouble *hzc, uint32_t x,
+                                         int64_t r, const double *qc, RankFn rank, double &hv, double &diag)
 {
-    __shared__ double sh[kBatchThreads / kWave];
-    __shared__ uint32_t s_tab[kBatchLdsTab];
+    hv = 0.0;
+    diag = 0.0;
+    if (!BATCH) {
+        for (int b = 0; b < it.nb; ++b) {
+            const uint32_t m = (uint32_t)bc[b].mask, t = x & m;
+            if (t == 0u || t == m) {
+                diag += bc[b].jz4;
+            } else {
+                diag -= bc[b].jz4;
+                hv += bc[b].jxy2 * qc[rank(x ^ m)];
+            }
+        }
+    }
+    for (int b0 = 0; BATCH && b0 < it.nb; b0 += 8) {
+        uint32_t idx[8];
+        double cf[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            idx[k] = (uint32_t)r;
+            cf[k] = 0.0;
+            const int b = b0 + k;
+            if (b < it.nb) {
+                const uint32_t m = (uint32_t)bc[b].mask, t = x & m;
+                if (t == 0u || t == m) {
+                    diag += bc[b].jz4;
+                } else {
+                    diag -= bc[b].jz4;
+                    idx[k] = rank(x ^ m);
+                    cf[k] = bc[b].jxy2;
+                }
+            }
+        }
+        double nv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) nv[k] = qc[idx[k]];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) hv += cf[k] * nv[k];
+    }
+    if (it.hz)
+        for (int i = 0; i < it.n_sites; ++i) diag -= hzc[i] * (((x >> i) & 1u) ? 0.5 : -0.5);
+}
+
+// LDS-resident variant for sectors whose vector fits next to the rank
+// tables in LDS: q_k and the chunk partials live in LDS (the H*v gathers
+// read q_k there), q_{k-1} and w in global memory. The update step moves q_k to the q_{k-1} buffer
+// and writes q_{k+1} into LDS row by row (each thread touches only its own
+// rows), so a step is one gather pass from LDS plus four streaming passes.
+constexpr int kBatchLdsThreads = 1024;
+
+__global__ __launch_bounds__(kBatchLdsThreads) void k_lanczos_batch_lds(const BatchItemDev *items)
+{
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ double bcast;
     const BatchItemDev it = items[blockIdx.x];
     // uniform tables through the scalar cache (the item is read from memory,
     // so without the cast every lane would load them with vector loads)
     const CSpinBond *bc = (const CSpinBond *)(it.bonds);
     const CDouble *hzc = (const CDouble *)(it.hz);
-    const int64_t dim = it.dim;
+    const int64_t dim = it.dim, nch = n_chunks(dim);
+    double *Q = reinterpret_cast<double *>(smem_raw);
+    double *part = Q + dim;   // chunk partials, in LDS here
+    uint32_t *lo = reinterpret_cast<uint32_t *>(part + nch);
+    const uint32_t nl = 1u << it.n_lo, nh = 1u << it.n_hi;
+    uint32_t *hi = lo + nl;
+    for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) lo[i] = it.lo_rank[i];
+    for (uint32_t i = threadIdx.x; i < nh; i += blockDim.x) hi[i] = it.hi_off[i];
+    const uint32_t lomask = nl - 1u;
+    const int n_lo = it.n_lo;
+    auto rank = [&](uint32_t y) -> uint32_t { return hi[y >> n_lo] + lo[y & lomask]; };
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wrow = threadIdx.x & ~(kWave - 1);
+    double *P = it.q, *Wv = it.q + dim;
+    for (int64_t b0 = wrow; b0 < dim; b0 += blockDim.x) {
+        const int64_t r = b0 + lane;
+        double c = 0.0;
+        if (r < dim) {
+            const double x = u53(splitmix64_at(it.seed, (uint64_t)r)) - 0.5;
+            Q[r] = x;
+            c = x * x;
+        }
+        chunk_store(c, part, b0 / kChunk);
+    }
+    const double n0 = block_total(part, nch, &bcast);
+    double s_cur = 1.0 / sqrt(n0), s_prev = 0.0, b_cur = 0.0;
+    int k = 0, brk = 0;
+    for (; k < it.iters; ++k) {
+        const double c1 = s_cur, c2 = -b_cur * s_prev;
+        for (int64_t b0 = wrow; b0 < dim; b0 += blockDim.x) {
+            const int64_t r = b0 + lane;
+            double c = 0.0;
+            if (r < dim) {
+                double hv, diag;
+                spin_row<false>(it, bc, hzc, it.states[r], r, Q, rank, hv, diag);
+                const double qr = Q[r];
+                double o = c1 * (hv + diag * qr);
+                if (k > 0) o += c2 * P[r];
+                Wv[r] = o;
+                c = qr * o;
+            }
+            chunk_store(c, part, b0 / kChunk);
+        }
+        const double al = s_cur * block_total(part, nch, &bcast);
+        const double f = al * s_cur;
+        for (int64_t b0 = wrow; b0 < dim; b0 += blockDim.x) {
+            const int64_t r = b0 + lane;
+            double c = 0.0;
+            if (r < dim) {
+                const double qr = Q[r];
+                const double x = Wv[r] - f * qr;
+                P[r] = qr;
+                Q[r] = x;
+                c = x * x;
+            }
+            chunk_store(c, part, b0 / kChunk);
+        }
+        const double bn = sqrt(block_total(part, nch, &bcast));
+        if (threadIdx.x == 0) {
+            it.alpha[k] = al;
+            it.beta[k + 1] = bn;
+        }
+        if (!(bn > 1e-13 * fmax(1.0, fabs(al)))) {
+            brk = 1;
+            ++k;
+            break;
+        }
+        s_prev = s_cur;
+        s_cur = 1.0 / bn;
+        b_cur = bn;
+    }
+    if (threadIdx.x == 0) {
+        it.done[0] = k;
+        it.done[1] = brk;
+        it.beta[0] = 0.0;
+    }
+}
+
+// Team variant: request b runs on team_w workgroups, member m owning rows
+// [m * team_rows, (m + 1) * team_rows) of every vector (whole slices). Per
+// step the members meet twice, after the <q_k, w> slice sums and after the
+// |w|^2 slice sums, and every member adds the slice sums in order, so all
+// of them hold the same alpha and beta bits and take the same branch.
+// Members take their place from an arrival ticket: the arrived workgroups
+// form complete teams except at most the last one, and complete teams finish
+// on their own, so the launch progresses even while other work holds part of
+// the GPU. A barrier that still waits after kTeamSpin polls sets the
+// request's flag to 3 and its members leave, so every wave ends.
+__device__ __forceinline__ bool team_sync(unsigned *bar, unsigned target, int tw, int *s_fail)
+{
+    __syncthreads();
+    if (tw > 1 && threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned polls = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(4);
+            if (++polls >= kTeamSpin) {
+                *s_fail = 1;
+                break;
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+    return *s_fail != 0;
+}
+
+// 1024 threads: one row per thread for members of one slice, so all of a
+// member's gathers are in flight at once.
+constexpr int kTeamThreads = 1024;
+
+__global__ __launch_bounds__(kTeamThreads) void k_lanczos_team(const BatchItemDev *items, int n, unsigned *ticket)
+{
+    __shared__ double bcast;
+    __shared__ unsigned s_ticket;
+    __shared__ int s_fail;
+    __shared__ uint32_t s_tab[kBatchLdsTab];
+    if (threadIdx.x == 0) {
+        s_ticket = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_fail = 0;
+    }
+    __syncthreads();
+    const int tk = (int)s_ticket;
+    // request whose ticket range holds tk (items sorted by team_base)
+    int lo_i = 0, hi_i = n - 1;
+    while (lo_i < hi_i) {
+        const int mid = (lo_i + hi_i + 1) >> 1;
+        if (items[mid].team_base <= tk) lo_i = mid;
+        else hi_i = mid - 1;
+    }
+    const BatchItemDev it = items[lo_i];
+    const int mem = tk - it.team_base, tw = it.team_w;
+    const CSpinBond *bc = (const CSpinBond *)(it.bonds);
+    const CDouble *hzc = (const CDouble *)(it.hz);
+    const int64_t dim = it.dim, nch = n_chunks(dim);
+    const int64_t rbeg = (int64_t)mem * it.team_rows, rend = min(dim, rbeg + it.team_rows);
+    const int64_t s_beg = rbeg / (kChunk * kSlice);
+    const int64_t s_end = (rend + kChunk * kSlice - 1) / (kChunk * kSlice);
+    // slice sums, two buffers used by turns: a member may write the next
+    // barrier's sums while a slower one still reads the last barrier's
+    const int64_t ns = (nch + kSlice - 1) / kSlice;
+    int turn = 0;
     const uint32_t lomask = (1u << it.n_lo) - 1u;
     const uint32_t nl = 1u << it.n_lo, nh = 1u << it.n_hi;
     const uint32_t *lo = it.lo_rank, *hi = it.hi_off;
@@ -73,179 +351,148 @@ __global__ __launch_bounds__(kBatchThreads) void k_lanczos_batch(const BatchItem
         lo = s_tab;
         hi = s_tab + nl;
     }
+    const int n_lo = it.n_lo;
+    auto rank = [&](uint32_t y) -> uint32_t { return hi[y >> n_lo] + lo[y & lomask]; };
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wrow = rbeg + (threadIdx.x & ~(kWave - 1));
+    unsigned arrivals = 0;
+    // this member's slice sums -> ssum, barrier, then the ordered total of
+    // all slice sums (identical in every member)
+    auto team_total = [&](double &out) -> bool {
+        double *ssum = it.part + nch + (turn ? ns : 0);
+        turn ^= 1;
+        __syncthreads();
+        if (threadIdx.x < kWave)
+            for (int64_t s = s_beg + lane; s < s_end; s += kWave) ssum[s] = slice_sum(it.part, s, nch);
+        arrivals += (unsigned)tw;
+        if (team_sync(it.bar, arrivals, tw, &s_fail)) return false;
+        if (threadIdx.x < kWave) {
+            const double t = ordered_total<false>(ssum, nch);
+            if (threadIdx.x == 0) bcast = t;
+        }
+        __syncthreads();
+        out = bcast;
+        __syncthreads();
+        return true;
+    };
     double *q[3] = {it.q, it.q + dim, it.q + 2 * dim};
-    // start vector and its norm
-    double acc = 0.0;
-    for (int64_t r = threadIdx.x; r < dim; r += blockDim.x) {
-        const double x = u53(splitmix64_at(it.seed, (uint64_t)r)) - 0.5;
-        q[0][r] = x;
-        acc += x * x;
-    }
-    const double n0 = batch_sum(acc, sh);
-    double s_cur = 1.0 / sqrt(n0), s_prev = 0.0, b_cur = 0.0;
-    int cur = 0, prev = 2, wb = 1, k = 0, brk = 0;
-    for (; k < it.iters; ++k) {
-        const double c1 = s_cur, c2 = -b_cur * s_prev;
-        const double *qc = q[cur], *qp = q[prev];
-        double *w = q[wb];
-        double pa = 0.0;
-        for (int64_t r = threadIdx.x; r < dim; r += blockDim.x) {
-            const uint32_t x = it.states[r];
-            double hv = 0.0, diag = 0.0;
-            for (int b = 0; b < it.nb; ++b) {
-                const uint32_t m = (uint32_t)bc[b].mask, t = x & m;
-                if (t == 0u || t == m) {
-                    diag += bc[b].jz4;
-                } else {
-                    diag -= bc[b].jz4;
-                    const uint32_t y = x ^ m;
-                    hv += bc[b].jxy2 * qc[hi[y >> it.n_lo] + lo[y & lomask]];
-                }
-            }
-            if (it.hz)
-                for (int i = 0; i < it.n_sites; ++i) diag -= hzc[i] * (((x >> i) & 1u) ? 0.5 : -0.5);
-            double o = c1 * (hv + diag * qc[r]);
-            if (k > 0) o += c2 * qp[r];
-            w[r] = o;
-            pa += qc[r] * o;
-        }
-        const double al = s_cur * batch_sum(pa, sh);
-        const double f = al * s_cur;
-        double pb = 0.0;
-        for (int64_t r = threadIdx.x; r < dim; r += blockDim.x) {
-            const double x = w[r] - f * qc[r];
-            w[r] = x;
-            pb += x * x;
-        }
-        const double bn = sqrt(batch_sum(pb, sh));
-        if (threadIdx.x == 0) {
-            it.alpha[k] = al;
-            it.beta[k + 1] = bn;
-        }
-        if (!(bn > 1e-13 * fmax(1.0, fabs(al)))) {
-            brk = 1;
-            ++k;
-            break;
-        }
-        s_prev = s_cur;
-        s_cur = 1.0 / bn;
-        b_cur = bn;
-        const int op = prev;
-        prev = cur;
-        cur = wb;
-        wb = op;
-    }
-    if (threadIdx.x == 0) {
-        it.done[0] = k;
-        it.done[1] = brk;
-        it.beta[0] = 0.0;
-    }
-}
-
-// LDS-resident variant for sectors whose vector fits next to the rank
-// tables in LDS: q_k lives in LDS (the H*v gathers read it there), q_{k-1}
-// and w in global memory. The update step moves q_k to the q_{k-1} buffer
-// and writes q_{k+1} into LDS row by row (each thread touches only its own
-// rows), so a step is one gather pass from LDS plus four streaming passes.
-constexpr int kBatchLdsThreads = 1024;
-
-__global__ __launch_bounds__(kBatchLdsThreads) void k_lanczos_batch_lds(const BatchItemDev *items)
-{
-    extern __shared__ unsigned char smem_raw[];
-    __shared__ double sh[kBatchLdsThreads / kWave];
-    const BatchItemDev it = items[blockIdx.x];
-    // uniform tables through the scalar cache (the item is read from memory,
-    // so without the cast every lane would load them with vector loads)
-    const CSpinBond *bc = (const CSpinBond *)(it.bonds);
-    const CDouble *hzc = (const CDouble *)(it.hz);
-    const int64_t dim = it.dim;
-    double *Q = reinterpret_cast<double *>(smem_raw);
-    uint32_t *lo = reinterpret_cast<uint32_t *>(Q + dim);
-    const uint32_t nl = 1u << it.n_lo, nh = 1u << it.n_hi;
-    uint32_t *hi = lo + nl;
-    for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) lo[i] = it.lo_rank[i];
-    for (uint32_t i = threadIdx.x; i < nh; i += blockDim.x) hi[i] = it.hi_off[i];
-    const uint32_t lomask = nl - 1u;
-    double *P = it.q, *Wv = it.q + dim;
-    double acc = 0.0;
-    for (int64_t r = threadIdx.x; r < dim; r += blockDim.x) {
-        const double x = u53(splitmix64_at(it.seed, (uint64_t)r)) - 0.5;
-        Q[r] = x;
-        acc += x * x;
-    }
-    const double n0 = batch_sum(acc, sh);
-    double s_cur = 1.0 / sqrt(n0), s_prev = 0.0, b_cur = 0.0;
     int k = 0, brk = 0;
-    for (; k < it.iters; ++k) {
-        const double c1 = s_cur, c2 = -b_cur * s_prev;
-        double pa = 0.0;
-        for (int64_t r = threadIdx.x; r < dim; r += blockDim.x) {
-            const uint32_t x = it.states[r];
-            double hv = 0.0, diag = 0.0;
-            for (int b = 0; b < it.nb; ++b) {
-                const uint32_t m = (uint32_t)bc[b].mask, t = x & m;
-                if (t == 0u || t == m) {
-                    diag += bc[b].jz4;
-                } else {
-                    diag -= bc[b].jz4;
-                    const uint32_t y = x ^ m;
-                    hv += bc[b].jxy2 * Q[hi[y >> it.n_lo] + lo[y & lomask]];
-                }
-            }
-            if (it.hz)
-                for (int i = 0; i < it.n_sites; ++i) diag -= hzc[i] * (((x >> i) & 1u) ? 0.5 : -0.5);
-            const double qr = Q[r];
-            double o = c1 * (hv + diag * qr);
-            if (k > 0) o += c2 * P[r];
-            Wv[r] = o;
-            pa += qr * o;
+    double n0;
+    for (int64_t b0 = wrow; b0 < rend; b0 += blockDim.x) {
+        const int64_t r = b0 + lane;
+        double c = 0.0;
+        if (r < rend) {
+            const double x = u53(splitmix64_at(it.seed, (uint64_t)r)) - 0.5;
+            q[0][r] = x;
+            c = x * x;
         }
-        const double al = s_cur * batch_sum(pa, sh);
-        const double f = al * s_cur;
-        double pb = 0.0;
-        for (int64_t r = threadIdx.x; r < dim; r += blockDim.x) {
-            const double qr = Q[r];
-            const double x = Wv[r] - f * qr;
-            P[r] = qr;
-            Q[r] = x;
-            pb += x * x;
-        }
-        const double bn = sqrt(batch_sum(pb, sh));
-        if (threadIdx.x == 0) {
-            it.alpha[k] = al;
-            it.beta[k + 1] = bn;
-        }
-        if (!(bn > 1e-13 * fmax(1.0, fabs(al)))) {
-            brk = 1;
-            ++k;
-            break;
-        }
-        s_prev = s_cur;
-        s_cur = 1.0 / bn;
-        b_cur = bn;
+        chunk_store(c, it.part, b0 / kChunk);
     }
-    if (threadIdx.x == 0) {
+    if (!team_total(n0)) goto timed_out;
+    {
+        double s_cur = 1.0 / sqrt(n0), s_prev = 0.0, b_cur = 0.0;
+        int cur = 0, prev = 2, wb = 1;
+        for (; k < it.iters; ++k) {
+            const double c1 = s_cur, c2 = -b_cur * s_prev;
+            const double *qc = q[cur], *qp = q[prev];
+            double *w = q[wb];
+            for (int64_t b0 = wrow; b0 < rend; b0 += blockDim.x) {
+                const int64_t r = b0 + lane;
+                double c = 0.0;
+                if (r < rend) {
+                    double hv, diag;
+                    spin_row<true>(it, bc, hzc, it.states[r], r, qc, rank, hv, diag);
+                    const double qr = qc[r];
+                    double o = c1 * (hv + diag * qr);
+                    if (k > 0) o += c2 * qp[r];
+                    w[r] = o;
+                    c = qr * o;
+                }
+                chunk_store(c, it.part, b0 / kChunk);
+            }
+            double pa;
+            if (!team_total(pa)) goto timed_out;
+            const double al = s_cur * pa;
+            const double f = al * s_cur;
+            for (int64_t b0 = wrow; b0 < rend; b0 += blockDim.x) {
+                const int64_t r = b0 + lane;
+                double c = 0.0;
+                if (r < rend) {
+                    const double x = w[r] - f * qc[r];
+                    w[r] = x;
+                    c = x * x;
+                }
+                chunk_store(c, it.part, b0 / kChunk);
+            }
+            double pb;
+            if (!team_total(pb)) goto timed_out;
+            const double bn = sqrt(pb);
+            if (mem == 0 && threadIdx.x == 0) {
+                it.alpha[k] = al;
+                it.beta[k + 1] = bn;
+            }
+            if (!(bn > 1e-13 * fmax(1.0, fabs(al)))) {
+                brk = 1;
+                ++k;
+                break;
+            }
+            s_prev = s_cur;
+            s_cur = 1.0 / bn;
+            b_cur = bn;
+            const int op = prev;
+            prev = cur;
+            cur = wb;
+            wb = op;
+        }
+    }
+    if (mem == 0 && threadIdx.x == 0) {
         it.done[0] = k;
-        it.done[1] = brk;
+        atomicMax(it.done + 1, brk);
         it.beta[0] = 0.0;
+    }
+    return;
+timed_out:
+    if (threadIdx.x == 0) {
+        if (mem == 0) it.done[0] = k;
+        atomicMax(it.done + 1, 3);
     }
 }
 
 size_t batch_lds_bytes(int64_t dim, int n_lo, int n_hi)
 {
-    return sizeof(double) * (size_t)dim + sizeof(uint32_t) * ((size_t(1) << n_lo) + (size_t(1) << n_hi));
+    return sizeof(double) * (size_t)(dim + n_chunks(dim)) +
+           sizeof(uint32_t) * ((size_t(1) << n_lo) + (size_t(1) << n_hi));
+}
+
+size_t batch_part_doubles(int64_t dim)
+{
+    const int64_t nch = n_chunks(dim), ns = (nch + kSlice - 1) / kSlice;
+    return (size_t)(nch + 2 * ns);
+}
+
+void batch_team_shape(int64_t dim, int *w, int *rows)
+{
+    const int64_t sl = (int64_t)kChunk * kSlice;
+    const int64_t per = (dim + kTeamMax - 1) / kTeamMax;
+    const int64_t r = std::max<int64_t>(sl, (per + sl - 1) / sl * sl);
+    *rows = (int)r;
+    *w = (int)std::max<int64_t>(1, (dim + r - 1) / r);
+}
+
+int launch_lanczos_team(const void *items_dev, int n, int grid, unsigned *ticket, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lanczos_team, dim3(grid), dim3(kTeamThreads), 0, st, (const BatchItemDev *)items_dev, n,
+                       ticket);
+    HPHI_HIP(hipGetLastError());
+    return HPHI_OK;
 }
 
 int launch_lanczos_batch(const void *items_dev, int n, hipStream_t st, size_t lds_bytes)
 {
-    if (lds_bytes > 0) {
-        hipFuncSetAttribute((const void *)k_lanczos_batch_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds_bytes);
-        hipLaunchKernelGGL(k_lanczos_batch_lds, dim3(n), dim3(kBatchLdsThreads), lds_bytes, st,
-                           (const BatchItemDev *)items_dev);
-    } else {
-        hipLaunchKernelGGL(k_lanczos_batch, dim3(n), dim3(kBatchThreads), 0, st, (const BatchItemDev *)items_dev);
-    }
+    HPHI_HIP(hipFuncSetAttribute((const void *)k_lanczos_batch_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds_bytes));
+    hipLaunchKernelGGL(k_lanczos_batch_lds, dim3(n), dim3(kBatchLdsThreads), lds_bytes, st,
+                       (const BatchItemDev *)items_dev);
     HPHI_HIP(hipGetLastError());
     return HPHI_OK;
 }
@@ -253,7 +500,7 @@ int launch_lanczos_batch(const void *items_dev, int n, hipStream_t st, size_t ld
 size_t batch_item_size() { return sizeof(BatchItemDev); }
 
 int fill_batch_item(hphi_ham *h, int iters, uint64_t seed, double *q, double *alpha, double *beta, int *done,
-                    void *out)
+                    double *part, unsigned *bar, int team_base, void *out)
 {
     const hphi_basis *b = h->basis;
     const Species &s = b->sp[0];
@@ -276,6 +523,10 @@ int fill_batch_item(hphi_ham *h, int iters, uint64_t seed, double *q, double *al
     d.alpha = alpha;
     d.beta = beta;
     d.done = done;
+    d.part = part;
+    d.bar = bar;
+    d.team_base = team_base;
+    batch_team_shape(s.dim, &d.team_w, &d.team_rows);
     *static_cast<BatchItemDev *>(out) = d;
     return HPHI_OK;
 }

@@ -56,6 +56,27 @@ def test_lanczos_batch_matches_single_and_oracle(api, ctx):
     assert mixed[1]["iterations"] == 50
 
 
+def test_lanczos_batch_team_and_single_workgroup_agree(api, ctx):
+    """Few requests run on teams of workgroups, many small ones on one
+    workgroup each; the reductions are ordered by rows, so a request's
+    numbers agree bit for bit. 16 sites: a team of 13 (ragged last member and
+    chunk) against the LDS kernel; 20 sites: a team of 31 members of 6144
+    rows alone against nine such teams split over two launches."""
+    for n_sites, copies, iters in ((16, 24, 200), (20, 9, 60)):
+        say("lanczos batch team vs one workgroup", n_sites, copies)
+        m = W.random_heisenberg(n_sites, "chain", 11)
+        h = api.Hamiltonian.spin(api.Basis.spin(ctx, n_sites, 0), m)
+        many = api.lanczos_batch([h] * copies, iters, list(range(1, copies + 1)), keep_coefficients=True)
+        for j in (0, copies - 1):
+            alone = api.lanczos_batch([h], iters, [j + 1], keep_coefficients=True)[0]
+            assert alone["iterations"] == many[j]["iterations"] == iters
+            assert np.array_equal(alone["alpha"], many[j]["alpha"])
+            assert np.array_equal(alone["beta"], many[j]["beta"])
+        single = api.lanczos(h, iters, seed=1)
+        assert abs(many[0]["energy"] - single["energies"][0]) < 1e-10
+        assert np.allclose(many[0]["alpha"][:15], single["alpha"][:15], atol=1e-12)
+
+
 def test_lanczos_batch_breakdown(api, ctx):
     m = W._spin(8, W.chain_pairs(8), [(1.0, 0.0)] * 8, "ising")
     h = api.Hamiltonian.spin(api.Basis.spin(ctx, 8, 0), m)
