@@ -76,10 +76,10 @@ def parse():
 # schedule it was taken with; anything else reports null.
 HUB_TRAFFIC = {
     "sources_sha256": {"kern_hub.hip": "050162874246d20567af0a22231414661dd1bfbc326b74c4e7a3f78321f18bc3",
-                       "kern_common.h": "a2e26c530c1c272d1d655a2c1c871ef80258f6d052067e42662ba1d7b102b269"},
+                       "kern_common.h": "82a4da084e46d3f069fff2bbec75262cce5cf6131077ca6b4d166d41e8c25fce"},
     "schedule": {"hub_slab_cols": 128, "hub_groups": 128, "hub_item_rows": 16, "hub_row_cols": 6, "hub_sweep": 5, "hub_row_order": 2},
-    "cols_fetch_kib": 5.78109e+06, "cols_write_kib": 1.32042e+06,
-    "rows_fetch_kib": 1.43681e+06, "rows_write_kib": 2.68637e+06,
+    "cols_fetch_kib": 5.77533e+06, "cols_write_kib": 1.32042e+06,
+    "rows_fetch_kib": 1.43595e+06, "rows_write_kib": 2.68657e+06,
     "fetch_factor": 2.0, "write_factor": 1.0,
 }
 
