@@ -298,8 +298,10 @@ typedef struct {
  * call (plus under 2 % of that for partial sums). Synchronous on `stream`. Errors: INVALID_ARG (n < 1,
  * max_iter < 1), UNSUPPORTED (a Hamiltonian that is not a spin model on a
  * stored basis), OUT_OF_MEMORY, DEVICE (also when a team barrier waited
- * for seconds without its members arriving, which the launch scheme rules
- * out: every wave then leaves and the call reports the item). */
+ * for seconds without its members arriving: within one launch the members
+ * always arrive, so this needs many concurrent launches of wide teams
+ * crowding each other off the CUs; every wave then leaves and the call
+ * reports the item). */
 int hphi_lanczos_batch(hphi_batch_item *items, int n, void *stream);
 
 /* Lowest k eigenvalues (ascending) of the symmetric tridiagonal matrix with
