@@ -297,7 +297,8 @@ def main():
         wl = {"workload": "heisenberg_chain16_sz0", "dim": basis.dim, "lanczos_iters": iters, "storage": "f64"}
         out, _ = run_lanczos(a, api, ham, basis.dim, iters, "f64", wl, "H*v = k_spin_hv<double,1>", "f64",
                              hv_events=False)
-        # many independent solves per launch (one workgroup per solve)
+        # many independent solves per call (B = 1: the request on a team of
+        # workgroups; larger B: one workgroup per request)
         hams = [ham] * 256
         rates, lat_b = {}, {}
         for B in (1, 16, 64, 256):

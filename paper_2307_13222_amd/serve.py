@@ -8,8 +8,9 @@ at a time):
 
   * small ground-state requests (sector dimension <= batch_max_dim) are
     grouped: whatever is admitted while the previous group runs goes into
-    the next single launch of the batched Lanczos kernel (one workgroup per
-    request);
+    the next single call of the batched Lanczos (a team of workgroups per
+    request when the group is small, one workgroup per request otherwise;
+    the same numbers either way);
   * larger ground-state requests and S(q, w) requests each run on a worker
     thread with its own HIP stream (Lanczos with a convergence check every
     10 steps, ground vector from a second pass, S^z(q) excitation, shifted
