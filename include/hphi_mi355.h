@@ -287,10 +287,11 @@ typedef struct {
 /* Many independent Lanczos ground-state solves in one launch (the
  * recurrence of hphi_lanczos, FP64 vectors). Meant for sectors small enough
  * that a single solve is bound by kernel-launch latency. A launch whose
- * requests together need at most half of the CUs runs each request on a
+ * requests together need at most 7/8 of the CUs runs each request on a
  * team of up to 32 workgroups (1024 rows each, or more for sectors above
  * 32768 states) that meet at a barrier of their own twice per step; larger
- * launches run each request on one workgroup. Every reduction follows an
+ * launches run each request whose vector fits in LDS on one workgroup (the
+ * others still as teams, in launches of at most one workgroup per CU). Every reduction follows an
  * order fixed by the rows (64-row chunks, chunks in order within 1024-row
  * slices, slices in order), so a request's numbers do not depend on the
  * other requests in the launch nor on which of the two ways ran it. The
