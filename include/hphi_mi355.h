@@ -287,7 +287,7 @@ typedef struct {
 /* Many independent Lanczos ground-state solves in one launch (the
  * recurrence of hphi_lanczos, FP64 vectors). Meant for sectors small enough
  * that a single solve is bound by kernel-launch latency. A launch whose
- * requests together need at most 7/8 of the CUs runs each request on a
+ * requests together need at most one workgroup per CU runs each request on a
  * team of up to 32 workgroups (1024 rows each, or more for sectors above
  * 32768 states) that meet at a barrier of their own twice per step; larger
  * launches run each request whose vector fits in LDS on one workgroup (the

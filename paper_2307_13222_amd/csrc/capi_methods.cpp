@@ -247,10 +247,9 @@ int hphi_lanczos_batch(hphi_batch_item *items, int n, void *stream)
     hipStream_t st = (hipStream_t)stream;
     // Team shape of each request (from its dimension alone). Requests whose
     // vector fits in LDS run on one workgroup each (throughput) unless the
-    // whole launch needs at most 7/8 of the CUs as teams, which then cut the
-    // latency (teams of a large launch cost each other: every team barrier
-    // writes back and invalidates its XCD's L2; 16-site requests: teams win
-    // up to 16 requests, 208 workgroups, and lose at 19). The other requests always run as teams, in launches of
+    // whole launch fits on the CUs as teams (one workgroup per CU), which
+    // then cut the latency (16-site requests, 13 members each: 19 requests
+    // as teams 5.3 ms, on one workgroup each 9.7 ms). The other requests always run as teams, in launches of
     // at most one workgroup per CU so that all members of a launch are
     // resident together. The reductions are ordered by rows, so every way
     // gives the same numbers.
@@ -275,7 +274,7 @@ int hphi_lanczos_batch(hphi_batch_item *items, int n, void *stream)
         lds_ok[i] = batch_lds_bytes(s.dim, s.n_lo, s.n_hi) <= kLdsCap;
     }
     const int n_cu = items[0].ham->basis->ctx->n_cu > 0 ? items[0].ham->basis->ctx->n_cu : 256;
-    const bool small = team_max > 1 && 8 * team_total <= 7 * n_cu;
+    const bool small = team_max > 1 && team_total <= n_cu;
     std::vector<int> order;   // LDS-kernel requests, then team requests by launch group
     size_t lds_max = 0;
     for (int i = 0; i < n; ++i)

@@ -289,19 +289,22 @@ __global__ __launch_bounds__(kBatchLdsThreads) void k_lanczos_batch_lds(const Ba
 // request's flag to 3 and its members leave, so every wave ends.
 __device__ __forceinline__ bool team_sync(unsigned *bar, unsigned target, int tw, int *s_fail)
 {
+    // the workgroup barrier orders every wave's stores before thread 0's
+    // agent-scope release; thread 0's acquire fence after the polls (relaxed,
+    // so that waiting does not invalidate the XCD's L2 once per poll) orders
+    // the other members' stores before every wave's loads
     __syncthreads();
     if (tw > 1 && threadIdx.x == 0) {
-        __threadfence();
         __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         unsigned polls = 0;
-        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(4);
             if (++polls >= kTeamSpin) {
                 *s_fail = 1;
                 break;
             }
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     return *s_fail != 0;
