@@ -77,6 +77,24 @@ def test_lanczos_batch_team_and_single_workgroup_agree(api, ctx):
         assert np.allclose(many[0]["alpha"][:15], single["alpha"][:15], atol=1e-12)
 
 
+def test_lanczos_batch_team_breakdown(api, ctx):
+    """A Krylov breakdown on a team of 4 (14-site Ising chain, 3432 states:
+    the diagonal H spans few Krylov directions) stops every member at the
+    same step, with the same coefficients as on one workgroup (next to
+    twenty 16-site requests the launch no longer fits on the CUs as teams)."""
+    say("lanczos batch team breakdown")
+    ising = api.Hamiltonian.spin(api.Basis.spin(ctx, 14, 0), W._spin(14, W.chain_pairs(14), [(1.0, 0.0)] * 14, "ising"))
+    heis = api.Hamiltonian.spin(api.Basis.spin(ctx, 16, 0), W.random_heisenberg(16, "chain", 3))
+    alone = api.lanczos_batch([ising], 50, [5], keep_coefficients=True)[0]
+    crowd = api.lanczos_batch([ising] + [heis] * 20, 50, list(range(5, 26)), keep_coefficients=True)
+    assert alone["breakdown"] and crowd[0]["breakdown"]
+    assert alone["iterations"] == crowd[0]["iterations"] < 50
+    assert np.array_equal(alone["alpha"], crowd[0]["alpha"])
+    assert np.array_equal(alone["beta"], crowd[0]["beta"])
+    assert alone["energy"] == crowd[0]["energy"] and alone["energy"] >= -14 * 0.25 - 1e-12
+    assert all(c["iterations"] == 50 and not c["breakdown"] for c in crowd[1:])
+
+
 def test_lanczos_batch_breakdown(api, ctx):
     m = W._spin(8, W.chain_pairs(8), [(1.0, 0.0)] * 8, "ising")
     h = api.Hamiltonian.spin(api.Basis.spin(ctx, 8, 0), m)
