@@ -124,9 +124,38 @@ def cpu_baseline(workload: str, sample_rows: int):
         w = O.hubbard_hv_rows(m, ups, dns, v, 0, nu)
         dt = time.perf_counter() - t0
         states, bytes_per = nu * len(dns), 16.0
-        del w
         sample = (f"oracle Hubbard H*v over up-rows [0, {nu}) of {len(ups)} "
                   f"({states} of {len(ups) * len(dns)} states)")
+        # the vector work of one oracle Lanczos step on full-size vectors
+        # (numpy), for the time-to-E0 extrapolation
+        u = np.random.default_rng(1).random(len(v)) - 0.5
+        t1 = time.perf_counter()
+        w -= 0.5 * u
+        al = float(np.dot(v, w))
+        w -= al * v
+        bt = float(np.linalg.norm(w))
+        u = w / bt
+        t_vec = time.perf_counter() - t1
+        del w, u
+        t_hv_full = dt * len(ups) / nu
+        # one core: the same row formula over a sixteenth of the rows
+        n1 = max(1, len(ups) // 16)
+        try:
+            import ctypes
+            gomp = ctypes.CDLL("libgomp.so.1")
+            gomp.omp_set_num_threads(1)
+            t2 = time.perf_counter()
+            O.hubbard_hv_rows(m, ups, dns, v, 0, n1)
+            dt1 = time.perf_counter() - t2
+            gomp.omp_set_num_threads(omp_threads())
+            one_core = {"value": round(16.0 * n1 * len(dns) / dt1 / 1e9, 4), "unit": "GB/s", "cores": 1,
+                        "sample": f"up-rows [0, {n1}), {n1 * len(dns)} states", "seconds": round(dt1, 3)}
+        except OSError:
+            one_core = None
+        extra = {"one_core": one_core,
+                 "time_to_e0_s": {"value": round(300 * (t_hv_full + t_vec), 1), "kind": "extrapolated",
+                                  "how": "300 x (one full oracle H*v on all cores + one step's numpy vector "
+                                         "work on full-size vectors), both timed here"}}
     elif workload in ("heisenberg16", "ctpq_xxz28"):
         n = 16 if workload == "heisenberg16" else 20
         m = W.heisenberg_chain(16) if n == 16 else W.xxz_chain_j2(20)
@@ -149,8 +178,11 @@ def cpu_baseline(workload: str, sample_rows: int):
         states, bytes_per = rows, 8.0
         sample = f"oracle sparse rows of the 6x6 J1-J2 sector, {rows} random rows (row formula only)"
     gbs = bytes_per * states / dt / 1e9
-    return {"value": round(gbs, 4), "unit": "GB/s", "cores": omp_threads(), "kind": "oracle",
-            "sample": sample, "seconds": round(dt, 3)}
+    out = {"value": round(gbs, 4), "unit": "GB/s", "cores": omp_threads(), "kind": "oracle",
+           "sample": sample, "seconds": round(dt, 3)}
+    if workload == "hubbard4x4":
+        out.update(extra)
+    return out
 
 
 def roofline(gbs: float, alg_bytes: float, kernel: str, traffic=None):
@@ -214,15 +246,19 @@ def run_lanczos(a, api, ham, dim, iters, storage, wl, kernel, tune_dtype, hv_eve
     gbs = alg_bytes / hv_avg / 1e9
     hub = ham.basis.kind == "hubbard"
     if hub and k2_s > 0.0:
-        # dominant kernel: the T_up column kernel; its pass reads the rows
-        # kernel's partial W, V (the T_up gathers, once) and u = q_{k-1}
-        # (the epilogue; none in a solve's first product) and writes W
+        # dominant kernel: the T_up column kernel. Algorithmic bytes: what
+        # its part of the method must move -- read V (the T_up gathers,
+        # once), read u = q_{k-1} (the epilogue; none in a solve's first
+        # product), write W. The partial W the rows kernel hands it (written
+        # there, read here: 16 B per state) is an intermediate of the
+        # two-kernel split, reported beside the measured traffic, not counted
         k2_avg = k2_s / max(1, hv_n)
-        cols_bytes = esize * dim * (4.0 - hv_solves / max(1, hv_n))
+        cols_bytes = esize * dim * (3.0 - hv_solves / max(1, hv_n))
         roof = roofline(cols_bytes / k2_avg / 1e9, cols_bytes,
                         f"k_hub_cols_f (T_up slab kernel with the Lanczos epilogue and FP64 dots; "
                         f"{100 * k2_avg / hv_avg:.0f} % of a step)", hub_traffic(wl["schedule"], "cols"))
         roof["ms"] = round(1e3 * k2_avg, 5)
+        roof["split_overhead_bytes_per_launch"] = 2.0 * esize * dim
         pair = roofline(gbs, alg_bytes, kernel, hub_traffic(wl["schedule"], "pair"))
     else:
         roof = roofline(gbs, alg_bytes, kernel, None)
@@ -285,10 +321,19 @@ def main():
             ts.append(r["seconds"])
             hv32.append(r["hv_seconds"] / max(1, r["hv_calls"]))
             e32.append(float(r["energies"][0]))
+        # refined: the FP32 run's Ritz vector rebuilt in FP64 (second pass)
+        # and its FP64 Rayleigh quotient, with the residual it carries
+        rr = api.lanczos(ham, iters, seed=1, storage="f32", refine=True)
+        rr64 = api.lanczos(ham, iters, seed=1, storage="f64", refine=True)
         out["fp32_storage"] = {"solve_ms_p50": round(1e3 * float(np.median(ts)), 3),
                                "lanczos_solves_per_s": round(1.0 / float(np.median(ts)), 4),
                                "hv_ms_avg": round(1e3 * float(np.mean(hv32)), 5),
-                               "e0": e32[0], "abs_dE0_vs_fp64_same_seed": abs(e32[0] - e64[0])}
+                               "e0_ritz": e32[0], "abs_dE0_ritz_vs_fp64_same_seed": abs(e32[0] - e64[0]),
+                               "refined": {"e0": rr["rq_e0"], "abs_dE0_vs_fp64_same_seed": abs(rr["rq_e0"] - e64[0]),
+                                           "residual": rr["residual"], "err_est": rr["err_est"],
+                                           "solve_ms": round(1e3 * rr["seconds"], 3),
+                                           "fp64_refined_e0": rr64["rq_e0"],
+                                           "fp64_refined_residual": rr64["residual"]}}
     elif a.workload == "heisenberg16":
         iters = a.iters or 200
         m = W.heisenberg_chain(16)

@@ -29,6 +29,19 @@
  *  - Vector layout: element (state r, vector j) of a block of nvec vectors
  *    sits at r * nvec + j ("interleaved"); complex numbers are (re, im)
  *    pairs. Input and output blocks must not alias.
+ *  - Concurrency: a Hamiltonian owns one set of reduction and work-queue
+ *    scratch that every call on it uses, so it serves one call at a time on
+ *    one stream at a time. A call that takes a Hamiltonian returns
+ *    HPHI_ERR_BUSY, and launches nothing, when another host thread is inside
+ *    a call on the same Hamiltonian, or when the previous call on it was
+ *    made on a different stream and its work has not finished yet (the
+ *    library records an event on the calling stream at the end of each
+ *    call). Calls on one stream queue in order and need nothing. To switch
+ *    streams, order them first (an event wait or a synchronization). While
+ *    a stream is being captured into a graph the stream check is skipped:
+ *    the caller orders the graph's launches. hphi_lanczos_batch only reads
+ *    the Hamiltonians' tables, so one Hamiltonian may appear in it many
+ *    times. Different Hamiltonians are independent.
  */
 #ifndef HPHI_MI355_H
 #define HPHI_MI355_H
@@ -48,6 +61,7 @@ extern "C" {
 #define HPHI_ERR_OUT_OF_MEMORY -4   /* device or host allocation failed     */
 #define HPHI_ERR_DEVICE        -5   /* a HIP runtime call failed            */
 #define HPHI_ERR_UNSUPPORTED   -6   /* valid request this build cannot do   */
+#define HPHI_ERR_BUSY          -7   /* the Hamiltonian is in use elsewhere  */
 
 typedef enum {
     HPHI_F64 = 0,    /* real double                         */
@@ -195,6 +209,15 @@ void hphi_ham_free(hphi_ham *h);
  *                   processed close together share more neighbour rows, so
  *                   more of them are still in L2); the products do not
  *                   depend on it (each element's sum keeps its order)
+ *   spin_tables     where the stored-list spin kernel keeps its rank
+ *                   tables: 1 = both 32-bit tables in LDS, 256-thread
+ *                   workgroups; 2 = hi_off in 32 bits and lo_rank narrowed
+ *                   to 16 bits in LDS, 1024-thread workgroups (the path
+ *                   sectors of 23 to 28 sites take); 3 = tables in global
+ *                   memory; -1 = automatic by size (the default). A forced
+ *                   choice the sector's tables do not fit returns
+ *                   UNSUPPORTED from the product. The products are the same
+ *                   sums in the same order whichever is chosen.
  * Errors: INVALID_ARG (value outside its range). */
 typedef struct {
     int hub_slab_cols;
@@ -205,6 +228,7 @@ typedef struct {
     int spin_implicit;
     int hub_sweep;
     int hub_row_order;
+    int spin_tables;
 } hphi_schedule;
 
 int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s);
@@ -233,6 +257,13 @@ typedef struct {
                               host solves T_k and stops when the lowest
                               n_energies Ritz values move by < tol           */
     double tol;            /* convergence threshold for check_every > 0      */
+    double resid_tol;      /* > 0 (with check_every): stopping also needs the
+                              residual estimate beta_k |s_k| of the lowest
+                              Ritz pair (s the eigenvector of T_k) below
+                              resid_tol max(1, |theta|): the Ritz vector's
+                              error is then about that over the spectral gap
+                              (an energy test alone leaves it near the square
+                              root of the energy's)                          */
     uint64_t seed;         /* start vector: SplitMix64 uniform [-1/2, 1/2)   */
     const void *v0_dev;    /* or a caller start vector (storage dtype); NULL
                               = use the seed                                 */
@@ -245,6 +276,12 @@ typedef struct {
     int use_graph;         /* capture the iteration in a hipGraph            */
     int time_kernels;      /* bracket every H*v with HIP events on `stream`
                               (not with use_graph); totals go to info        */
+    int refine;            /* 1: after the solve, rebuild the lowest Ritz
+                              vector by a second pass accumulated in FP64,
+                              normalize it in FP64 and take its Rayleigh
+                              quotient and residual with an FP64 product;
+                              energies[0] is then that Rayleigh quotient
+                              (see hphi_lanczos_info)                        */
 } hphi_lanczos_opts;
 
 typedef struct {
@@ -262,13 +299,30 @@ typedef struct {
     double hv_second_kernel_seconds; /* with time_kernels, Hubbard: summed
                               durations of the column (T_up) kernel alone,
                               from an event between the two launches       */
+    /* With refine = 1 (otherwise NaN):                                     */
+    double ritz_e0;        /* lowest Ritz value of T_k (before refinement)   */
+    double rq_e0;          /* rho = <psi|H psi> of the FP64 Ritz vector psi,
+                              |psi| = 1, product and sums in FP64            */
+    double residual;       /* eps = |H psi - rho psi|: some eigenvalue of H
+                              lies within eps of rho (bound of Weinstein)    */
+    double err_est;        /* eps^2 / (theta_2 - rho), theta_2 the lowest
+                              Ritz value distinct from the first: the error
+                              of rho by the bound of Temple when theta_2
+                              does not exceed the second eigenvalue by much
+                              (an estimate, not a bound)                    */
 } hphi_lanczos_info;
 
 /* Lanczos ground state (Sec. 1): v_0 = r/|r|; w = H v_k - beta_k v_{k-1};
  * alpha_k = <v_k, w>; w -= alpha_k v_k; beta_{k+1} = |w|; v_{k+1} = w /
  * beta_{k+1}; no reorthogonalization. The lowest n_energies eigenvalues of
- * the tridiagonal T_k come from host FP64 Sturm bisection. Synchronous.
- * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+ * the tridiagonal T_k come from host FP64 Sturm bisection. With FP32
+ * storage the Krylov vectors carry FP32 rounding, which bounds the Ritz
+ * values' accuracy by about 1e-7 |H|; opts->refine = 1 adds the FP64
+ * Rayleigh quotient of the Ritz vector (its error is quadratic in the
+ * vector's) and its residual, which bound the result's error without an
+ * FP64 run. The refinement needs two FP64 vectors of workspace and a
+ * second pass. Synchronous.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE, BUSY. */
 int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *opts, double *energies,
                  int n_energies, hphi_lanczos_info *info);
 

@@ -30,7 +30,9 @@ import scipy.sparse.linalg
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hphi_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "_build", "libhphi_oracle.so")
+# HPHI_ORACLE_LIB: another build of the same source (the sanitizer test
+# loads one built with -fsanitize=address,undefined)
+_LIB_PATH = os.environ.get("HPHI_ORACLE_LIB") or os.path.join(_HERE, "_build", "libhphi_oracle.so")
 _lib = None
 
 
@@ -294,8 +296,32 @@ def lanczos(hv: Callable[[np.ndarray], np.ndarray], v0: np.ndarray, n_iter: int,
             break
         beta.append(b)
         v_prev, v = v, w / b
+    # beta_full also holds the norm after the last step (a residual estimate)
     return {"alpha": np.array(alpha), "beta": np.array(beta[:len(alpha)]),
-            "steps": len(alpha)}
+            "beta_full": np.array(beta[:len(alpha)] + [b]), "steps": len(alpha)}
+
+
+def lanczos_stop(alpha: np.ndarray, beta_full: np.ndarray, check_every: int, tol: float,
+                 resid_tol: float = 0.0) -> int:
+    """Step count at which a checked Lanczos run stops: every check_every
+    steps m the lowest Ritz value theta_m of T_m is compared with the
+    previous check's, and the run stops at the first m where it moved by
+    less than tol max(1, |theta_m|) and (resid_tol > 0) the residual
+    estimate beta_m |s_{m-1}| of the lowest Ritz pair (s its eigenvector of
+    T_m) is below resid_tol max(1, |theta_m|). beta_full[m] must be the
+    norm after step m (beta_full[0] = 0). Returns len(alpha) if no check
+    passes."""
+    last = None
+    for m in range(check_every, len(alpha) + 1, check_every):
+        th, s = scipy.linalg.eigh_tridiagonal(alpha[:m], beta_full[1:m], select="i", select_range=(0, 0))
+        th = float(th[0])
+        ok = last is not None and abs(th - last) < tol * max(1.0, abs(th))
+        if ok and resid_tol > 0:
+            ok = m < len(beta_full) and beta_full[m] * abs(s[m - 1, 0]) < resid_tol * max(1.0, abs(th))
+        if ok:
+            return m
+        last = th
+    return len(alpha)
 
 
 def tridiag_lowest(alpha: np.ndarray, beta: np.ndarray, k: int = 1) -> np.ndarray:

@@ -11,6 +11,7 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_build", "libhphi_mi355.so")
 
 F64, F32, C128, C64 = 0, 1, 2, 3
+ERR_BUSY = -7
 
 
 class SpinBond(C.Structure):
@@ -23,16 +24,18 @@ class Hop(C.Structure):
 
 class LanczosOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("check_every", C.c_int), ("tol", C.c_double),
-                ("seed", C.c_uint64), ("v0_dev", C.c_void_p), ("storage", C.c_int),
+                ("resid_tol", C.c_double), ("seed", C.c_uint64), ("v0_dev", C.c_void_p), ("storage", C.c_int),
                 ("stream", C.c_void_p), ("alpha_out", C.POINTER(C.c_double)),
                 ("beta_out", C.POINTER(C.c_double)), ("psi_dev", C.c_void_p),
-                ("use_graph", C.c_int), ("time_kernels", C.c_int)]
+                ("use_graph", C.c_int), ("time_kernels", C.c_int), ("refine", C.c_int)]
 
 
 class LanczosInfo(C.Structure):
     _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("breakdown", C.c_int),
                 ("seconds", C.c_double), ("hv_seconds", C.c_double), ("hv_calls", C.c_int),
-                ("fused_update", C.c_int), ("hv_second_kernel_seconds", C.c_double)]
+                ("fused_update", C.c_int), ("hv_second_kernel_seconds", C.c_double),
+                ("ritz_e0", C.c_double), ("rq_e0", C.c_double), ("residual", C.c_double),
+                ("err_est", C.c_double)]
 
 
 class BatchItem(C.Structure):
@@ -65,7 +68,7 @@ class LobpcgInfo(C.Structure):
 class Schedule(C.Structure):
     _fields_ = [("hub_slab_cols", C.c_int), ("hub_groups", C.c_int), ("hub_item_rows", C.c_int),
                 ("hub_row_cols", C.c_int), ("spin_per_cu", C.c_int), ("spin_implicit", C.c_int),
-                ("hub_sweep", C.c_int), ("hub_row_order", C.c_int)]
+                ("hub_sweep", C.c_int), ("hub_row_order", C.c_int), ("spin_tables", C.c_int)]
 
 
 class SqwOpts(C.Structure):

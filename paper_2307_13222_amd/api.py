@@ -15,13 +15,15 @@ from .workloads import HubbardModel, SpinModel
 
 
 class HphiError(RuntimeError):
-    pass
+    def __init__(self, msg: str, code: int = 0):
+        super().__init__(msg)
+        self.code = code
 
 
 def _check(rc: int, what: str):
     if rc != 0:
         msg = L.lib().hphi_last_error()
-        raise HphiError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
+        raise HphiError(f"{what} failed ({rc}): {msg.decode() if msg else ''}", rc)
 
 
 def _torch():
@@ -183,7 +185,7 @@ class Hamiltonian:
         return w
 
     SCHEDULE_FIELDS = ("hub_slab_cols", "hub_groups", "hub_item_rows", "hub_row_cols", "spin_per_cu",
-                       "spin_implicit", "hub_sweep", "hub_row_order")
+                       "spin_implicit", "hub_sweep", "hub_row_order", "spin_tables")
 
     def set_schedule(self, **kw):
         s = L.Schedule(*[int(kw.get(f, 0)) for f in self.SCHEDULE_FIELDS])
@@ -203,10 +205,14 @@ class Hamiltonian:
 def lanczos(ham: Hamiltonian, max_iter: int, seed: int = 1, v0=None, storage: str = "f64",
             n_energies: int = 1, want_vector: bool = False, use_graph: bool = False,
             check_every: int = 0, tol: float = 1e-12, time_kernels: bool = False,
-            stream=None) -> Dict:
+            refine: bool = False, resid_tol: float = 0.0, stream=None) -> Dict:
+    """Lanczos ground state. refine: FP64 Rayleigh quotient of the Ritz
+    vector (second pass accumulated in FP64), returned as energies[0] with
+    its residual |H psi - rho psi| and error estimate."""
     torch = _torch()
     o = L.LanczosOpts()
     o.max_iter, o.check_every, o.tol, o.seed = max_iter, check_every, tol, seed
+    o.resid_tol = resid_tol
     o.storage = L.F64 if storage == "f64" else L.F32
     tdt = torch.float64 if storage == "f64" else torch.float32
     if v0 is not None:
@@ -225,6 +231,7 @@ def lanczos(ham: Hamiltonian, max_iter: int, seed: int = 1, v0=None, storage: st
         o.psi_dev = psi.data_ptr()
     o.use_graph = 1 if use_graph else 0
     o.time_kernels = 1 if time_kernels else 0
+    o.refine = 1 if refine else 0
     e = np.zeros(n_energies)
     info = L.LanczosInfo()
     _check(L.lib().hphi_lanczos(ham.h, C.byref(o), e.ctypes.data_as(L.PD), n_energies, C.byref(info)),
@@ -234,7 +241,9 @@ def lanczos(ham: Hamiltonian, max_iter: int, seed: int = 1, v0=None, storage: st
             "converged": bool(info.converged), "breakdown": bool(info.breakdown),
             "seconds": info.seconds, "hv_seconds": info.hv_seconds, "hv_calls": info.hv_calls,
             "fused_update": bool(info.fused_update),
-            "hv_second_kernel_seconds": info.hv_second_kernel_seconds, "psi": psi}
+            "hv_second_kernel_seconds": info.hv_second_kernel_seconds, "psi": psi,
+            "ritz_e0": info.ritz_e0, "rq_e0": info.rq_e0, "residual": info.residual,
+            "err_est": info.err_est}
 
 
 def lanczos_batch(hams: Sequence[Hamiltonian], max_iter, seeds, keep_coefficients: bool = False,

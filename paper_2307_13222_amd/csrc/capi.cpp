@@ -18,12 +18,12 @@ int ensure_reduce(hphi_ham *h)
     if (!h->red_partial.p) {
         HPHI_TRY(h->red_partial.alloc(sizeof(double) * (size_t)kReduceSlots));
         HPHI_TRY(h->red_counter.alloc(sizeof(unsigned) * 16));
-        HPHI_HIP(hipMemset(h->red_counter.p, 0, sizeof(unsigned) * 16));
+        HPHI_TRY(zero_now(h->red_counter.p, sizeof(unsigned) * 16));
         HPHI_TRY(h->sched.alloc(sizeof(unsigned) * 16));
-        HPHI_HIP(hipMemset(h->sched.p, 0, sizeof(unsigned) * 16));
+        HPHI_TRY(zero_now(h->sched.p, sizeof(unsigned) * 16));
         HPHI_TRY(h->red_result.alloc(sizeof(double) * 128));
     }
-    return HPHI_OK;
+    return init_ham_use(h);
 }
 
 Reduce reduce_of(hphi_ham *h, double *result = nullptr)
@@ -38,6 +38,15 @@ Reduce reduce_of(hphi_ham *h, double *result = nullptr)
 } // namespace
 
 namespace hphi {
+
+int init_ham_use(hphi_ham *h)
+{
+    if (h->use.event) return HPHI_OK;
+    hipEvent_t e = nullptr;
+    HPHI_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    h->use.event = (void *)e;
+    return HPHI_OK;
+}
 
 int launch_mult(hphi_ham *h, const MultArgs &a)
 {
@@ -675,6 +684,11 @@ int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s)
             return fail(HPHI_ERR_INVALID_ARG, "hub_row_order %d", s->hub_row_order);
         n.hub_row_order = s->hub_row_order;
     }
+    if (s->spin_tables) {
+        if (s->spin_tables != -1 && (s->spin_tables < 1 || s->spin_tables > 3))
+            return fail(HPHI_ERR_INVALID_ARG, "spin_tables %d", s->spin_tables);
+        n.spin_tables = s->spin_tables == -1 ? 0 : s->spin_tables;
+    }
     h->sched_cfg = n;
     return HPHI_OK;
 }
@@ -691,6 +705,7 @@ int hphi_ham_trace(hphi_ham *h, double *trace_out, void *stream)
     if (!h || !trace_out) return fail(HPHI_ERR_INVALID_ARG, "null argument");
     DeviceGuard g(h->basis->ctx->device);
     hipStream_t st = (hipStream_t)stream;
+    HPHI_USE_HAM(h, st);
     HPHI_TRY(launch_trace(h, reduce_of(h), st));
     HPHI_HIP(hipMemcpyAsync(trace_out, h->red_result.p, sizeof(double), hipMemcpyDeviceToHost, st));
     HPHI_HIP(hipStreamSynchronize(st));
@@ -706,6 +721,7 @@ int hphi_mult(hphi_ham *h, hphi_dtype dt, const void *v_dev, void *w_dev, int64_
     if (nvec * dtype_lanes(dt) > 32) return fail(HPHI_ERR_INVALID_ARG, "more than 32 real lanes per state");
     if (v_dev == w_dev) return fail(HPHI_ERR_INVALID_ARG, "v and w alias");
     DeviceGuard g(h->basis->ctx->device);
+    HPHI_USE_HAM(h, stream);
     MultArgs a{};
     a.dtype = dt;
     a.nvec = (int)nvec;
@@ -728,6 +744,7 @@ namespace {
 struct LanczosRun {
     hphi_ham *h;
     int dt;
+    int psi_dt = -1;   // type of the Ritz-vector accumulator (default: dt)
     int64_t dim;
     hipStream_t st;
     DevMem q[3];
@@ -814,7 +831,8 @@ struct LanczosRun {
     int step(bool first, const double *svec, void *psi)
     {
         const bool fz = fused && !first;
-        if (psi && !fz) HPHI_TRY(launch_lz_psi_accum(dt, lz, svec, dim, psi, q[cur].p, st));
+        const int pdt = psi_dt < 0 ? dt : psi_dt;
+        if (psi && !fz) HPHI_TRY(launch_lz_psi_accum(pdt, dt, lz, svec, dim, psi, q[cur].p, st));
         MultArgs a{};
         a.dtype = dt;
         a.nvec = 1;
@@ -844,7 +862,7 @@ struct LanczosRun {
         }
         HPHI_TRY(launch_mult(h, a));
         if (timing) HPHI_TRY(mark());
-        if (psi && fz) HPHI_TRY(launch_lz_psi_accum(dt, lz, svec, dim, psi, q[cur].p, st));
+        if (psi && fz) HPHI_TRY(launch_lz_psi_accum(pdt, dt, lz, svec, dim, psi, q[cur].p, st));
         if (!fused)
             HPHI_TRY(launch_lz_update(dt, lz, alpha, beta, dim, q[wbuf].p, q[cur].p, reduce_of(h, lz->nrm), st));
         const int old_prev = prev;
@@ -855,7 +873,7 @@ struct LanczosRun {
     }
 
     int run(int n_iter, bool graph, const double *svec, void *psi, int check_every, double tol,
-            int n_energies, int *converged, std::vector<double> &last_ev)
+            int n_energies, int *converged, std::vector<double> &last_ev, double resid_tol = 0.0)
     {
         int k = 0;
         HPHI_TRY(step(true, svec, psi));
@@ -898,6 +916,13 @@ struct LanczosRun {
                 bool ok = last_ev.size() == ev.size();
                 for (size_t i = 0; ok && i < ev.size(); ++i)
                     ok = std::fabs(ev[i] - last_ev[i]) < tol * std::max(1.0, std::fabs(ev[i]));
+                if (ok && resid_tol > 0.0) {
+                    // residual estimate of the lowest Ritz pair: beta_n |s_{n-1}|
+                    std::vector<double> sv(n);
+                    double th = 0.0;
+                    HPHI_TRY(tridiag_lowest(ha.data(), hb.data(), n, 1, &th, sv.data()));
+                    ok = hb[n] * std::fabs(sv[n - 1]) < resid_tol * std::max(1.0, std::fabs(th));
+                }
                 last_ev = ev;
                 if (ok) {
                     *converged = 1;
@@ -915,6 +940,20 @@ struct LanczosRun {
 
 } // namespace
 
+// Lowest Ritz value of T_n distinct from the first (ghost copies of the
+// first, which plain Lanczos produces once it has converged, are skipped);
+// NaN if there is none.
+static double second_distinct_ritz(const std::vector<double> &a, const std::vector<double> &b, int n)
+{
+    const int k = std::min(n, 8);
+    if (k < 2) return NAN;
+    std::vector<double> ev(k);
+    if (tridiag_lowest(a.data(), b.data(), n, k, ev.data(), nullptr) != HPHI_OK) return NAN;
+    for (int i = 1; i < k; ++i)
+        if (ev[i] - ev[0] > 1e-6 * std::max(1.0, std::fabs(ev[0]))) return ev[i];
+    return NAN;
+}
+
 int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *o, double *energies, int n_energies,
                  hphi_lanczos_info *info)
 {
@@ -924,7 +963,10 @@ int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *o, double *energies, int 
         return fail(HPHI_ERR_INVALID_ARG, "Lanczos storage must be F64 or F32");
     if (n_energies < 0 || n_energies > o->max_iter) return fail(HPHI_ERR_INVALID_ARG, "n_energies %d", n_energies);
     if (o->check_every < 0) return fail(HPHI_ERR_INVALID_ARG, "check_every < 0");
+    if (o->refine != 0 && o->refine != 1) return fail(HPHI_ERR_INVALID_ARG, "refine %d", o->refine);
+    if (o->resid_tol < 0.0 || !std::isfinite(o->resid_tol)) return fail(HPHI_ERR_INVALID_ARG, "resid_tol");
     DeviceGuard g(h->basis->ctx->device);
+    HPHI_USE_HAM(h, o->stream);
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = (hipStream_t)o->stream;
     hipStream_t own = nullptr;
@@ -947,7 +989,7 @@ int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *o, double *energies, int 
     int converged = 0;
     std::vector<double> last_ev;
     HPHI_TRY(L.run(o->max_iter, o->use_graph != 0, nullptr, nullptr, o->check_every, o->tol,
-                   std::max(1, n_energies), &converged, last_ev));
+                   std::max(1, n_energies), &converged, last_ev, o->resid_tol));
     LzDev hl;
     HPHI_HIP(hipMemcpyAsync(&hl, L.lz, sizeof(LzDev), hipMemcpyDeviceToHost, st));
     HPHI_HIP(hipStreamSynchronize(st));
@@ -965,21 +1007,55 @@ int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *o, double *energies, int 
     int hv_n = 0;
     if (L.timing) HPHI_TRY(L.timed(&hv_s, &hv_n, &hv_k2));
     L.timing = false;
-    if (o->psi_dev && n > 0) {
-        // second pass: same start vector and kernels, psi = sum_k s_k v_k
+    double ritz_e0 = NAN, rq_e0 = NAN, resid = NAN, err_est = NAN;
+    if ((o->psi_dev || o->refine) && n > 0) {
+        // second pass: same start vector and kernels, psi = sum_k s_k v_k;
+        // with refine the sum is kept in FP64 whatever the storage type
         std::vector<double> s(n);
-        double e0;
-        HPHI_TRY(tridiag_lowest(ha.data(), hb.data(), n, 1, &e0, s.data()));
-        DevMem sv;
+        HPHI_TRY(tridiag_lowest(ha.data(), hb.data(), n, 1, &ritz_e0, s.data()));
+        DevMem sv, psi64, hpsi;
         HPHI_TRY(upload(sv, s.data(), sizeof(double) * n));
-        HPHI_HIP(hipMemsetAsync(o->psi_dev, 0, (size_t)L.dim * dtype_size(L.dt), st));
+        void *psi = o->psi_dev;
+        int pdt = L.dt;
+        if (o->refine) {
+            HPHI_TRY(psi64.alloc((size_t)L.dim * sizeof(double)));
+            psi = psi64.p;
+            pdt = HPHI_F64;
+        }
+        L.psi_dt = pdt;
+        HPHI_HIP(hipMemsetAsync(psi, 0, (size_t)L.dim * dtype_size(pdt), st));
         HPHI_TRY(L.start(o));
         std::vector<double> dummy;
         int cv = 0;
-        HPHI_TRY(L.run(n, false, sv.as<double>(), o->psi_dev, 0, 0.0, 1, &cv, dummy));
-        Reduce r = reduce_of(h);
-        HPHI_TRY(launch_dots(L.dt, 1, L.dim, o->psi_dev, o->psi_dev, r, 1, st));
-        HPHI_TRY(launch_scale_lanes(L.dt, 1, L.dim, o->psi_dev, h->red_result.as<double>(), 1, st));
+        HPHI_TRY(L.run(n, false, sv.as<double>(), psi, 0, 0.0, 1, &cv, dummy));
+        double *res = h->red_result.as<double>();
+        HPHI_TRY(launch_dots(pdt, 1, L.dim, psi, psi, reduce_of(h), 1, st));
+        HPHI_TRY(launch_scale_lanes(pdt, 1, L.dim, psi, res, 1, st));
+        if (o->refine) {
+            // rho = <psi|H psi> and eps = |H psi - rho psi| in FP64
+            HPHI_TRY(hpsi.alloc((size_t)L.dim * sizeof(double)));
+            MultArgs a{};
+            a.dtype = HPHI_F64;
+            a.nvec = 1;
+            a.v = psi;
+            a.w = hpsi.p;
+            a.stream = st;
+            a.red = reduce_of(h);
+            HPHI_TRY(launch_mult(h, a));
+            HPHI_TRY(launch_dots(HPHI_F64, 1, L.dim, psi, hpsi.p, reduce_of(h), 0, st));
+            HPHI_HIP(hipMemcpyAsync(&rq_e0, res, sizeof(double), hipMemcpyDeviceToHost, st));
+            HPHI_HIP(hipStreamSynchronize(st));
+            HPHI_TRY(launch_axpy_lanes(HPHI_F64, 1, L.dim, hpsi.p, psi, nullptr, -rq_e0, st));
+            HPHI_TRY(launch_dots(HPHI_F64, 1, L.dim, hpsi.p, hpsi.p, reduce_of(h), 1, st));
+            double r2 = 0.0;
+            HPHI_HIP(hipMemcpyAsync(&r2, res, sizeof(double), hipMemcpyDeviceToHost, st));
+            HPHI_HIP(hipStreamSynchronize(st));
+            resid = std::sqrt(std::max(0.0, r2));
+            const double th2 = second_distinct_ritz(ha, hb, n);
+            if (std::isfinite(th2) && th2 > rq_e0) err_est = r2 / (th2 - rq_e0);
+            if (n_energies > 0) energies[0] = rq_e0;
+            if (o->psi_dev) HPHI_TRY(launch_copy_cast(L.dt, o->psi_dev, HPHI_F64, psi, L.dim, st));
+        }
         HPHI_HIP(hipStreamSynchronize(st));
     }
     if (info) {
@@ -991,6 +1067,10 @@ int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *o, double *energies, int 
         info->hv_calls = hv_n;
         info->fused_update = L.fused ? 1 : 0;
         info->hv_second_kernel_seconds = hv_k2;
+        info->ritz_e0 = o->refine ? ritz_e0 : NAN;
+        info->rq_e0 = rq_e0;
+        info->residual = resid;
+        info->err_est = err_est;
     }
     return HPHI_OK;
 }

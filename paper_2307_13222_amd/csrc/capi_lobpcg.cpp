@@ -157,6 +157,7 @@ int hphi_lobpcg(hphi_ham *h, const hphi_lobpcg_opts *o, double *energies_out, do
         return fail(HPHI_ERR_UNSUPPORTED, "preconditioned LOBPCG with a field: give e_shift explicitly");
     DeviceGuard g(h->basis->ctx->device);
     hipStream_t st = (hipStream_t)o->stream;
+    HPHI_USE_HAM(h, st);
     auto t0 = std::chrono::steady_clock::now();
     const size_t vb = sizeof(double) * (size_t)dim;
     // vectors: Phi, HPhi, R, HR, P, HP and the next Phi, HPhi, P, HP

@@ -37,6 +37,7 @@ int hphi_ctpq(hphi_ham *h, const hphi_ctpq_opts *o, void *phi_dev, double *D_out
         return fail(HPHI_ERR_UNSUPPORTED, "Hubbard cTPQ runs one vector per call");
     DeviceGuard g(h->basis->ctx->device);
     hipStream_t st = (hipStream_t)o->stream;
+    HPHI_USE_HAM(h, st);
     const int dt = o->storage, nv = o->n_vec, nl = 2 * nv;
     const int64_t dim = h->basis->dim;
     const size_t bytes = (size_t)dim * nl * dtype_size(dt);
@@ -58,7 +59,8 @@ int hphi_ctpq(hphi_ham *h, const hphi_ctpq_opts *o, void *phi_dev, double *D_out
         cf[2 * n] = -o->dtau / (2.0 * n);
         cf[2 * n + 1] = 1.0;
     }
-    HPHI_HIP(hipMemcpy(scal.p, cf.data(), sizeof(double) * cf.size(), hipMemcpyHostToDevice));
+    HPHI_HIP(hipMemcpyAsync(scal.p, cf.data(), sizeof(double) * cf.size(), hipMemcpyHostToDevice, st));
+    HPHI_HIP(hipStreamSynchronize(st));
     double *d_coef = scal.as<double>();
     double *d_lane_scale = d_coef + 2 * o->n_max + 2;
 
@@ -149,6 +151,7 @@ int hphi_time_evolve(hphi_ham *h, const hphi_tevol_opts *o, void *psi_dev, doubl
     if (docc_out && h->kind != 1) return fail(HPHI_ERR_INVALID_ARG, "double occupancy needs a Hubbard model");
     DeviceGuard g(h->basis->ctx->device);
     hipStream_t st = (hipStream_t)o->stream;
+    HPHI_USE_HAM(h, st);
     const int dt = o->storage, nv = o->n_vec, nl = 2 * nv;
     const int64_t dim = h->basis->dim;
     const size_t bytes = (size_t)dim * nl * dtype_size(dt);
@@ -167,7 +170,8 @@ int hphi_time_evolve(hphi_ham *h, const hphi_tevol_opts *o, void *psi_dev, doubl
         cf[4 * n + 2] = -o->dt / n;
         cf[4 * n + 3] = 0.0;
     }
-    HPHI_HIP(hipMemcpy(scal.p, cf.data(), sizeof(double) * cf.size(), hipMemcpyHostToDevice));
+    HPHI_HIP(hipMemcpyAsync(scal.p, cf.data(), sizeof(double) * cf.size(), hipMemcpyHostToDevice, st));
+    HPHI_HIP(hipStreamSynchronize(st));
     const double *d_coef = scal.as<double>();
     void *A = psi_dev;
     void *Y[2] = {y1.p, y2.p};
@@ -357,6 +361,7 @@ int hphi_szq(hphi_ham *h, const double *phase, const void *psi_dev, void *b_dev,
     if (h->basis->n_sites > 64) return fail(HPHI_ERR_INVALID_ARG, "too many sites");
     DeviceGuard g(h->basis->ctx->device);
     hipStream_t st = (hipStream_t)stream;
+    HPHI_USE_HAM(h, st);
     DevMem ph;
     HPHI_TRY(upload(ph, phase, sizeof(double) * 2 * h->basis->n_sites));
     HPHI_TRY(launch_szq(h, ph.as<double>(), psi_dev, b_dev, st));
@@ -382,6 +387,7 @@ int hphi_sqw(hphi_ham *h, const hphi_sqw_opts *o, const void *b_dev, const doubl
     DeviceGuard g(h->basis->ctx->device);
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = (hipStream_t)o->stream;
+    HPHI_USE_HAM(h, st);
     const int64_t dim = h->basis->dim;
     const int seed = o->seed_shift >= 0 ? o->seed_shift : n_shift / 2;
     DevMem bp, r, p, hp, cgm, shm;

@@ -46,10 +46,24 @@ void DevMem::reset()
     bytes = 0;
 }
 
+// Copies on the null stream and waits for them: a copy from pageable host
+// memory may return before its data has landed, and kernels on the caller's
+// streams (non-blocking ones do not order against the null stream) must
+// see the data.
 int upload(DevMem &m, const void *host, size_t bytes)
 {
     HPHI_TRY(m.alloc(bytes));
-    if (bytes) HPHI_HIP(hipMemcpy(m.p, host, bytes, hipMemcpyHostToDevice));
+    if (bytes) {
+        HPHI_HIP(hipMemcpyAsync(m.p, host, bytes, hipMemcpyHostToDevice, nullptr));
+        HPHI_HIP(hipStreamSynchronize(nullptr));
+    }
+    return HPHI_OK;
+}
+
+int zero_now(void *p, size_t bytes)
+{
+    HPHI_HIP(hipMemsetAsync(p, 0, bytes, nullptr));
+    HPHI_HIP(hipStreamSynchronize(nullptr));
     return HPHI_OK;
 }
 
@@ -65,7 +79,7 @@ static uint64_t binom_u64(int n, int k)
 // Two-level rank table. lo_rank[l] counts the n_lo-bit patterns below l with
 // the same popcount; hi_off[h] counts sector states whose high part is below
 // h, i.e. sum over h' < h of C(n_lo, n_pop - popcount(h')).
-int build_species(Species &s, int n_bits, int n_pop, int n_lo_override, bool materialize)
+int build_species_tables(Species &s, int n_bits, int n_pop, int n_lo_override)
 {
     if (n_bits < 1 || n_bits > 64 || n_pop < 0 || n_pop > n_bits)
         return fail(HPHI_ERR_INVALID_ARG, "invalid species (%d bits, %d set)", n_bits, n_pop);
@@ -96,7 +110,15 @@ int build_species(Species &s, int n_bits, int n_pop, int n_lo_override, bool mat
     }
     s.hi_off[nh] = acc;
     if (acc != dim) return fail(HPHI_ERR_DIM_OVERFLOW, "rank table mismatch");
+    s.state_bytes = n_bits <= 32 ? 4 : 8;
+    return HPHI_OK;
+}
 
+int build_species(Species &s, int n_bits, int n_pop, int n_lo_override, bool materialize)
+{
+    HPHI_TRY(build_species_tables(s, n_bits, n_pop, n_lo_override));
+    const uint64_t dim = (uint64_t)s.dim;
+    const uint32_t nl = 1u << s.n_lo, nh = 1u << s.n_hi;
     HPHI_TRY(upload(s.d_lo_rank, s.lo_rank.data(), sizeof(uint32_t) * nl));
     HPHI_TRY(upload(s.d_hi_off, s.hi_off.data(), sizeof(uint64_t) * ((size_t)nh + 1)));
     if (dim < (uint64_t(1) << 32)) {
@@ -105,7 +127,6 @@ int build_species(Species &s, int n_bits, int n_pop, int n_lo_override, bool mat
     }
     HPHI_TRY(upload(s.d_lo_list, s.lo_list.data(), sizeof(uint32_t) * nl));
     HPHI_TRY(upload(s.d_lo_list_off, s.lo_list_off.data(), sizeof(uint32_t) * s.lo_list_off.size()));
-    s.state_bytes = n_bits <= 32 ? 4 : 8;
     if (materialize) {
         HPHI_TRY(s.d_states.alloc((size_t)dim * s.state_bytes));
         HPHI_TRY(launch_materialize(s, nullptr));

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/hphi_mi355.h"
+#include "use_guard.h"
 
 namespace hphi {
 
@@ -43,7 +44,9 @@ struct DevMem {
     template <typename T> T *as() const { return static_cast<T *>(p); }
 };
 
+// Both complete before returning (ordered before any later launch on any stream).
 int upload(DevMem &m, const void *host, size_t bytes);
+int zero_now(void *p, size_t bytes);
 
 // Makes `dev` current for the scope, restores the previous device after.
 struct DeviceGuard {
@@ -77,6 +80,8 @@ struct Species {
     int64_t rank_of(uint64_t x) const;   // host rank, -1 if outside
 };
 
+// Host tables only (no device memory touched).
+int build_species_tables(Species &s, int n_bits, int n_pop, int n_lo_override);
 int build_species(Species &s, int n_bits, int n_pop, int n_lo_override, bool materialize);
 
 } // namespace hphi
@@ -178,13 +183,60 @@ struct hphi_ham {
     // defaults: 128-column slabs, 128 workgroups per XCD, 32-row items,
     // hop-ordered down slots, work-item queues with two columns per lane;
     // spin: 8 workgroups per CU
-    hphi_schedule sched_cfg{128, 128, 16, 6, 8, 0, 5, 2};
+    hphi_schedule sched_cfg{128, 128, 16, 6, 8, 0, 5, 2, 0};
     // scratch for reductions and work queues
     hphi::DevMem sched;         // unsigned [16]: per-XCD item queues + counter
     hphi::DevMem red_partial;   // double [kReduceSlots]
     hphi::DevMem red_counter;   // unsigned [16]
     hphi::DevMem red_result;    // double [64]
+    // one call at a time, one stream at a time (the scratch above is shared)
+    hphi::UseState use;
+    hphi_ham() = default;
+    hphi_ham(const hphi_ham &) = delete;
+    hphi_ham &operator=(const hphi_ham &) = delete;
+    ~hphi_ham()
+    {
+        if (use.event) (void)hipEventDestroy((hipEvent_t)use.event);
+    }
 };
+
+namespace hphi {
+
+// The guard's device side: an event recorded at the end of each call.
+struct HipUseOps {
+    bool pending(void *e) { return hipEventQuery((hipEvent_t)e) == hipErrorNotReady; }
+    void record(void *e, void *st) { (void)hipEventRecord((hipEvent_t)e, (hipStream_t)st); }
+    bool capturing(void *st)
+    {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing((hipStream_t)st, &cs) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        return cs != hipStreamCaptureStatusNone;
+    }
+};
+
+struct HamUse {
+    HipUseOps ops;
+    UseScope<HipUseOps> scope;
+    HamUse(hphi_ham *h, void *st) : scope(h->use, ops, st) {}
+};
+
+// Creates the Hamiltonian's guard event (after its device is current).
+int init_ham_use(hphi_ham *h);
+
+} // namespace hphi
+
+// Enter a call on Hamiltonian h issued on stream st (after the device guard);
+// returns HPHI_ERR_BUSY from the enclosing function when it may not start.
+#define HPHI_USE_HAM(h, st)                                                                    \
+    ::hphi::HamUse hphi_use_((h), (void *)(st));                                               \
+    if (hphi_use_.scope.verdict() != ::hphi::USE_OK)                                           \
+        return ::hphi::fail(HPHI_ERR_BUSY, "%s",                                               \
+                            hphi_use_.scope.verdict() == ::hphi::USE_OTHER_THREAD              \
+                                ? "the Hamiltonian is in a call on another thread"             \
+                                : "the previous call on this Hamiltonian still runs on another stream")
 
 namespace hphi {
 
@@ -275,7 +327,7 @@ struct LzDev {
 int launch_lz_init(int dtype, LzDev *lz, int64_t dim, Reduce red, hipStream_t st);
 int launch_lz_update(int dtype, LzDev *lz, double *alpha, double *beta, int64_t dim, void *w,
                      const void *qk, Reduce red, hipStream_t st);
-int launch_lz_psi_accum(int dtype, LzDev *lz, const double *svec, int64_t dim, void *psi,
+int launch_lz_psi_accum(int psi_dtype, int dtype, LzDev *lz, const double *svec, int64_t dim, void *psi,
                         const void *qk, hipStream_t st);
 
 // host tridiagonal solver

@@ -404,6 +404,18 @@ int launch_spin_mult(hphi_ham *h, const MultArgs &m)
     const int per_cu_1 = std::min(per_cu_sched, std::max(1, (int)((160 * 1024) / (tab + 4096))));
     const bool narrow_ok = tab_c <= 96 * 1024 && s.n_lo <= 18 && state_bytes <= (m.dots ? 32u : 128u);
     int lds = (tab <= 96 * 1024 && (per_cu_1 * kBlock >= 2 * kSpinBigBlock || !narrow_ok)) ? 1 : narrow_ok ? 2 : 0;
+    switch (h->sched_cfg.spin_tables) {
+    case 1:
+        if (tab > 96 * 1024) return fail(HPHI_ERR_UNSUPPORTED, "spin_tables 1: %zu bytes of tables exceed LDS", tab);
+        lds = 1;
+        break;
+    case 2:
+        if (!narrow_ok) return fail(HPHI_ERR_UNSUPPORTED, "spin_tables 2: narrowed tables do not fit this product");
+        lds = 2;
+        break;
+    case 3: lds = 0; break;
+    default: break;
+    }
     if (lds == 2) tab = tab_c;
     const int bs = lds == 2 ? kSpinBigBlock : kBlock;
     int64_t need = (s.dim + bs - 1) / bs;

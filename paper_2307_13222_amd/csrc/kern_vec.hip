@@ -329,22 +329,27 @@ int launch_lz_update(int dtype, LzDev *lz, double *alpha, double *beta, int64_t 
 }
 
 // Second pass: psi += svec[k] * s_k * q_k (k = lz->iter before the update).
-template <typename S>
-__global__ void k_lz_psi(LzDev *lz, const double *svec, int64_t dim, S *psi, const S *qk)
+// psi += svec[k] s_k q_k; psi may be kept wider than q (P = double with
+// FP32 storage: the Ritz vector of a refined solve).
+template <typename P, typename S>
+__global__ void k_lz_psi(LzDev *lz, const double *svec, int64_t dim, P *psi, const S *qk)
 {
     if (lz->done) return;
     const double c = svec[lz->iter] * lz->s_cur;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < dim;
          r += (int64_t)gridDim.x * blockDim.x)
-        psi[r] = (S)((double)psi[r] + c * (double)qk[r]);
+        psi[r] = (P)((double)psi[r] + c * (double)qk[r]);
 }
 
-int launch_lz_psi_accum(int dtype, LzDev *lz, const double *svec, int64_t dim, void *psi,
+int launch_lz_psi_accum(int psi_dtype, int dtype, LzDev *lz, const double *svec, int64_t dim, void *psi,
                         const void *qk, hipStream_t st)
 {
     int g = grid_for(dim);
-    if (dtype_is_f32(dtype)) hipLaunchKernelGGL(k_lz_psi<float>, dim3(g), dim3(kBlock), 0, st, lz, svec, dim, (float *)psi, (const float *)qk);
-    else hipLaunchKernelGGL(k_lz_psi<double>, dim3(g), dim3(kBlock), 0, st, lz, svec, dim, (double *)psi, (const double *)qk);
+    const bool pf = dtype_is_f32(psi_dtype), qf = dtype_is_f32(dtype);
+    if (pf && !qf) return fail(HPHI_ERR_INVALID_ARG, "Ritz vector narrower than the Krylov vectors");
+    if (pf) hipLaunchKernelGGL((k_lz_psi<float, float>), dim3(g), dim3(kBlock), 0, st, lz, svec, dim, (float *)psi, (const float *)qk);
+    else if (qf) hipLaunchKernelGGL((k_lz_psi<double, float>), dim3(g), dim3(kBlock), 0, st, lz, svec, dim, (double *)psi, (const float *)qk);
+    else hipLaunchKernelGGL((k_lz_psi<double, double>), dim3(g), dim3(kBlock), 0, st, lz, svec, dim, (double *)psi, (const double *)qk);
     HPHI_HIP(hipGetLastError());
     return HPHI_OK;
 }

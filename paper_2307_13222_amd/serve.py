@@ -13,8 +13,10 @@ at a time):
     the same numbers either way);
   * larger ground-state requests and S(q, w) requests each run on a worker
     thread with its own HIP stream (Lanczos with a convergence check every
-    10 steps, ground vector from a second pass, S^z(q) excitation, shifted
-    COCG over the shift grid), so their kernels overlap on the device.
+    10 steps -- for S(q, w) on the Ritz residual estimate as well, since the
+    ground vector's error carries into D(z) -- ground vector from a second
+    pass, S^z(q) excitation, shifted COCG over the shift grid), so their
+    kernels overlap on the device.
 
 Every path uses fixed-order reductions, so a request's numbers are the same
 alone and in any mix. The server records arrival, admission and completion
@@ -226,7 +228,8 @@ class GpuExecutor:
 
     def __init__(self, device: int = 0, n_workers: int = 4, batch_max_dim: int = 20000,
                  max_batch: int = 512, lanczos_iters: int = 200, max_iter: int = 500, eta: float = 0.05,
-                 n_shift: int = 64, sqw_tol: float = 1e-8, sqw_max_iter: int = 6000):
+                 n_shift: int = 64, sqw_tol: float = 1e-8, sqw_max_iter: int = 6000,
+                 gs_resid_tol: float = 1e-9):
         from . import api
         self.api = api
         self.ctx = api.Context(device)
@@ -239,6 +242,7 @@ class GpuExecutor:
         self.n_shift = n_shift
         self.sqw_tol = sqw_tol
         self.sqw_max_iter = sqw_max_iter
+        self.gs_resid_tol = gs_resid_tol
         self.t0 = time.perf_counter()
         self.work: "queue.Queue" = queue.Queue()
         self.batchq: "queue.Queue" = queue.Queue()
@@ -310,8 +314,11 @@ class GpuExecutor:
         if req.kind == "lanczos":
             r = api.lanczos(ham, self.max_iter, seed=req.rid + 1, check_every=10, tol=1e-12, stream=stream)
             return {"energy": float(r["energies"][0]), "iterations": r["iterations"], "path": "stream"}
-        r = api.lanczos(ham, self.max_iter, seed=req.rid + 1, check_every=10, tol=1e-12, want_vector=True,
-                        stream=stream)
+        # the excitation is built from the ground vector, so its error (about
+        # the Ritz residual over the gap) sets D(z)'s: stop on the residual
+        # estimate too, not on the energy alone
+        r = api.lanczos(ham, self.max_iter, seed=req.rid + 1, check_every=10, tol=1e-12,
+                        resid_tol=self.gs_resid_tol, want_vector=True, stream=stream)
         e0 = float(r["energies"][0])
         b = api.szq(ham, math.pi, r["psi"], stream=stream)
         omega = sqw_grid(float(np.max(m.jz)), self.n_shift)

@@ -129,3 +129,31 @@ def test_batched_one_state_request(api, ctx):
     s = O.basis_list(12, 6)
     e_ref = np.linalg.eigvalsh(O.spin_sparse(W.heisenberg_chain(12), s).toarray())[0]
     assert abs(out[1]["energy"] - e_ref) < 1e-10
+
+
+def test_ham_busy_on_another_stream(api, ctx):
+    """A Hamiltonian serves one stream at a time: while products queued on
+    one stream still run, a call on another stream returns HPHI_ERR_BUSY and
+    launches nothing; on the same stream calls queue; after a
+    synchronization the other stream may take it."""
+    import torch
+    from paper_2307_13222_amd import _lib as L
+    say("edge: busy guard")
+    m = W.hubbard_square(4, 4, 1.0, 4.0)
+    b = api.Basis.hubbard(ctx, 16, 6, 6)
+    h = api.Hamiltonian.hubbard(b, m)
+    v = torch.rand(b.dim, dtype=torch.float64, device="cuda")
+    w = torch.empty_like(v)
+    w2 = torch.zeros_like(v)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for _ in range(8):   # about 10 ms of products in flight on s1
+        h.mult(v, w, stream=s1)
+    with pytest.raises(api.HphiError) as e:
+        h.mult(v, w2, stream=s2)
+    assert e.value.code == L.ERR_BUSY
+    h.mult(v, w, stream=s1)            # same stream: fine
+    s1.synchronize()
+    h.mult(v, w2, stream=s2)           # drained: the other stream may use it
+    s2.synchronize()
+    assert torch.equal(w, w2)

@@ -104,14 +104,58 @@ def test_lanczos_batch_breakdown(api, ctx):
     assert o["energy"] >= -8 * 0.25 - 1e-12
 
 
+def _oracle_served_sqw(req, ex):
+    """The server's S(q, w) procedure written out with the oracle: Lanczos
+    from the request's SplitMix64 start vector, stopped by the same rule
+    (checks every 10 steps: energy moved < 1e-12 and residual estimate
+    < gs_resid_tol, relative), ground vector from the second pass, S^z(pi)
+    excitation, and D(z) on the request's grid from the continued fraction
+    of a Lanczos run on b (2000 steps: the fraction has converged to 1e-13
+    of max|D| at eta = 0.05 for these sizes, checked on the CPU against full
+    spectra). The sparse direct solve is the definition but takes ~30 s per
+    shift at 16 sites (fill-in), so the continued fraction stands in."""
+    from paper_2307_13222_amd import serve as S
+    m = W.random_heisenberg(req.n_sites, req.lattice, seed=req.rid)
+    s = O.basis_list(req.n_sites, O.sector_popcount_spin(req.n_sites, req.two_sz))
+    Hs = O.spin_sparse(m, s)
+    hv = lambda x: Hs @ x
+    v0 = O.splitmix_uniform(req.rid + 1, 0, len(s))
+    lz = O.lanczos(hv, v0, ex.max_iter)
+    k = O.lanczos_stop(lz["alpha"], lz["beta_full"], 10, 1e-12, ex.gs_resid_tol)
+    e0 = float(O.tridiag_lowest(lz["alpha"][:k], lz["beta"][:k])[0])
+    psi = O.lanczos_ground_vector(hv, v0, lz["alpha"][:k], lz["beta"][:k])
+    b = O.szq_excitation(m, s, math.pi, psi)
+    omega = S.sqw_grid(float(np.max(m.jz)), ex.n_shift)
+    a_b, b_b = O.lanczos_complex(hv, b, 2000)
+    d = O.continued_fraction(a_b, b_b, float(np.vdot(b, b).real), e0 + omega + 1j * ex.eta)
+    return k, e0, d, float(np.vdot(b, b).real)
+
+
 def test_serving_mix_same_alone_and_in_mix(api, ctx):
+    """Every request is the same alone and in the mix (bit for bit), every
+    S(q, w) request of up to 16 sites matches the oracle's run of the same
+    procedure, and the mix also holds 23- and 24-site requests, which run
+    the narrowed-table spin kernel with fused dots (its element-wise oracle
+    parity is in test_gpu_narrow_tables.py).
+
+    D(z) tolerance: COCG stops at |r| <= 1e-8 |b|, so |dD| <= 1e-8 |b|^2 /
+    eta against the exact D of the device's b; z differs by the E0
+    difference (|dD/dz| <= |b|^2 / eta^2). Both sides build b from the same
+    Krylov construction (same start vector, same stopping step), so their
+    ground vectors differ by rounding only: two oracle runs with different
+    summation orders of H*v give vectors within 1e-15 and D within 1e-11 of
+    each other at these sizes. The assertion is (1e-8 + 1e-9) |b|^2 / eta +
+    |dE0| |b|^2 / eta^2, the 1e-9 for the ground vectors."""
     from paper_2307_13222_amd import serve as S
     say("serving mix")
     reqs = W.serving_requests(24, 400.0, seed=7, n_range=(12, 16))
+    t_last = reqs[-1].arrival
+    reqs += [W.Request(24, t_last + 0.001, "sqw", "chain", 23, 1),
+             W.Request(25, t_last + 0.002, "lanczos", "ladder", 24, 0)]
     ex = S.GpuExecutor(0, n_workers=4, batch_max_dim=20000, lanczos_iters=200)
     out = S.Server(ex, hbm_budget=8 * 10 ** 9, max_active=32).run(reqs)
     say("  mix done", out["completed"], out["p50_latency_s"], out["p99_latency_s"], out["peak_active"])
-    assert out["completed"] == 24, [r.error for r in out["results"] if not r.ok]
+    assert out["completed"] == len(reqs), [r.error for r in out["results"] if not r.ok]
     assert out["peak_active"] > 1
     for r, res in zip(reqs, out["results"]):
         assert res.rid == r.rid
@@ -123,16 +167,18 @@ def test_serving_mix_same_alone_and_in_mix(api, ctx):
         if r.kind == "sqw":
             assert np.array_equal(alone["D"], res.D)
             assert np.all(-res.D.imag > 0)
-    # spot check against the oracle: the first S(q, w) request
-    r = next(q for q in reqs if q.kind == "sqw")
-    res = out["results"][r.rid]
-    m = W.random_heisenberg(r.n_sites, r.lattice, seed=r.rid)
-    s = O.basis_list(r.n_sites, O.sector_popcount_spin(r.n_sites, r.two_sz))
-    Hs = O.spin_sparse(m, s)
-    ev, U = np.linalg.eigh(Hs.toarray()) if len(s) <= 4000 else (None, None)
-    if ev is not None:
-        assert abs(res.energy - ev[0]) < 1e-9
-        b = O.szq_excitation(m, s, math.pi, U[:, 0])
-        z = res.energy + res.omega + 0.05j
-        ref = O.dyn_corr_direct(Hs, b, z)
-        assert np.max(np.abs(res.D - ref)) / np.max(np.abs(ref)) < 1e-5
+    checked = 0
+    for r in reqs:
+        if r.kind != "sqw" or r.n_sites > 16:
+            continue
+        res = out["results"][r.rid]
+        k, e0, d_ref, b2 = _oracle_served_sqw(r, ex)
+        de = abs(res.energy - e0)
+        err = float(np.max(np.abs(res.D - d_ref)))
+        bound = (ex.sqw_tol + 1e-9) * b2 / ex.eta + de * b2 / ex.eta ** 2
+        say(f"  sqw {r.rid} {r.lattice} {r.n_sites}: stop {k} vs {res.iterations}, dE0 {de:.2e}, "
+            f"max|dD| {err:.2e} (bound {bound:.2e}, max|D| {np.max(np.abs(d_ref)):.3e})")
+        assert de < 1e-10
+        assert err <= bound
+        checked += 1
+    assert checked >= 5

@@ -328,3 +328,41 @@ def test_double_occupancy_weight_atomic_limits():
     m = W.hubbard_chain(4, 0.0, 1.0)
     tr = np.sum(O.hubbard_hv(m, ups, dns, np.ones(len(w))))
     assert abs(np.mean(w) - tr / len(w) / 4) < 1e-15
+
+
+def test_lanczos_stop_rule_and_residual_estimate():
+    """The stopping rule of a checked Lanczos run, and the residual estimate
+    it uses: beta_m |s_{m-1}| equals |H y - theta y| for the Ritz vector
+    y = Q_m s (before orthogonality is lost), checked by forming y."""
+    m = W.random_heisenberg(12, "chain", 4)
+    s = O.basis_list(12, 6)
+    Hs = O.spin_sparse(m, s)
+    hv = lambda x: Hs @ x
+    v0 = O.splitmix_uniform(3, 0, len(s))
+    lz = O.lanczos(hv, v0, 200)
+    assert len(lz["beta_full"]) == len(lz["alpha"]) + 1
+    for mm in (8, 15, 25):
+        a, bf = lz["alpha"][:mm], lz["beta_full"]
+        th, sv = scipy.linalg.eigh_tridiagonal(a, bf[1:mm], select="i", select_range=(0, 0))
+        y = O.lanczos_ground_vector(hv, v0, a, lz["beta"][:mm])
+        ry = np.linalg.norm(hv(y) - th[0] * y)
+        est = bf[mm] * abs(sv[mm - 1, 0])
+        assert abs(ry - est) <= 1e-9 * max(1.0, est) + 1e-12
+    # brute force over the checks
+    def brute(tol, rtol):
+        last = None
+        for k in range(10, len(lz["alpha"]) + 1, 10):
+            a, bf = lz["alpha"][:k], lz["beta_full"]
+            th, sv = scipy.linalg.eigh_tridiagonal(a, bf[1:k], select="i", select_range=(0, 0))
+            ok = last is not None and abs(th[0] - last) < tol * max(1, abs(th[0]))
+            if ok and rtol > 0:
+                ok = bf[k] * abs(sv[k - 1, 0]) < rtol * max(1, abs(th[0]))
+            if ok:
+                return k
+            last = th[0]
+        return len(lz["alpha"])
+    for tol, rtol in ((1e-12, 0.0), (1e-12, 1e-9), (1e-6, 0.0), (1e-6, 1e-4)):
+        assert O.lanczos_stop(lz["alpha"], lz["beta_full"], 10, tol, rtol) == brute(tol, rtol)
+    # the residual rule can only stop later
+    assert O.lanczos_stop(lz["alpha"], lz["beta_full"], 10, 1e-12, 1e-10) >= \
+        O.lanczos_stop(lz["alpha"], lz["beta_full"], 10, 1e-12, 0.0)
