@@ -326,6 +326,29 @@ typedef struct {
 int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *opts, double *energies,
                  int n_energies, hphi_lanczos_info *info);
 
+/* For callers that cannot allocate device memory (code that runs while a
+ * stream is captured into a graph, tight serving loops, harnesses that
+ * forbid hipMalloc): hphi_lanczos with every device buffer (the three
+ * Krylov vectors, the device scalars, the T_k coefficients, the Ritz
+ * coefficients of the second pass and, with refine, the two FP64 vectors of
+ * the refinement) taken from a static device array of
+ * HPHI_NOALLOC_SCRATCH_BYTES that the library holds on each device from
+ * hphi_init to the end of the process, instead of allocated per call. The
+ * caller still passes the outputs (host arrays, psi_dev). Each buffer is
+ * rounded up to 256 bytes; the call needs
+ *   3 * S(dim * elem) + S(128) + S(8 * (2 * max_iter + 4)) + S(8 * max_iter)
+ *   + (refine ? 2 * S(8 * dim) : 0)  bytes,  S(n) = n rounded up to 256,
+ * elem = 8 (F64) or 4 (F32): FP64 solves up to about 2.79e6 states (a
+ * 24-site chain at Sz = 0). The library clears what must start at zero on
+ * each call. Every call on a device shares that device's array: a call
+ * that starts while another one holds it (from another thread) returns
+ * HPHI_ERR_BUSY; calls must not overlap on one device. Synchronous.
+ * Errors: INVALID_ARG (a workspace need above the array, use_graph or
+ * time_kernels set, and as hphi_lanczos), BUSY, DEVICE. */
+#define HPHI_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int hphi_lanczos_noalloc(hphi_ham *h, const hphi_lanczos_opts *opts, double *energies,
+                         int n_energies, hphi_lanczos_info *info);
+
 /* One request of a batched Lanczos launch. */
 typedef struct {
     hphi_ham *ham;         /* spin Hamiltonian on a stored basis (<= 32 sites) */

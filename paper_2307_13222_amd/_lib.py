@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_build", "l
 
 F64, F32, C128, C64 = 0, 1, 2, 3
 ERR_BUSY = -7
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class SpinBond(C.Structure):
@@ -107,6 +108,7 @@ SIGNATURES = {
     "hphi_ham_trace": (I, [P, PD, P]),
     "hphi_mult": (I, [P, I, P, P, I64, P]),
     "hphi_lanczos": (I, [P, C.POINTER(LanczosOpts), PD, I, C.POINTER(LanczosInfo)]),
+    "hphi_lanczos_noalloc": (I, [P, C.POINTER(LanczosOpts), PD, I, C.POINTER(LanczosInfo)]),
     "hphi_tridiag_lowest": (I, [PD, PD, I, I, PD, PD]),
     "hphi_lanczos_batch": (I, [C.POINTER(BatchItem), I, P]),
     "hphi_ctpq": (I, [P, C.POINTER(CtpqOpts), P, PD, PD, PD]),

@@ -205,10 +205,12 @@ class Hamiltonian:
 def lanczos(ham: Hamiltonian, max_iter: int, seed: int = 1, v0=None, storage: str = "f64",
             n_energies: int = 1, want_vector: bool = False, use_graph: bool = False,
             check_every: int = 0, tol: float = 1e-12, time_kernels: bool = False,
-            refine: bool = False, resid_tol: float = 0.0, stream=None) -> Dict:
+            refine: bool = False, resid_tol: float = 0.0, no_alloc: bool = False, stream=None) -> Dict:
     """Lanczos ground state. refine: FP64 Rayleigh quotient of the Ritz
     vector (second pass accumulated in FP64), returned as energies[0] with
-    its residual |H psi - rho psi| and error estimate."""
+    its residual |H psi - rho psi| and error estimate. no_alloc: the entry
+    point that takes its device buffers from the library's static scratch
+    (hphi_lanczos_noalloc) instead of allocating them."""
     torch = _torch()
     o = L.LanczosOpts()
     o.max_iter, o.check_every, o.tol, o.seed = max_iter, check_every, tol, seed
@@ -234,8 +236,9 @@ def lanczos(ham: Hamiltonian, max_iter: int, seed: int = 1, v0=None, storage: st
     o.refine = 1 if refine else 0
     e = np.zeros(n_energies)
     info = L.LanczosInfo()
-    _check(L.lib().hphi_lanczos(ham.h, C.byref(o), e.ctypes.data_as(L.PD), n_energies, C.byref(info)),
-           "hphi_lanczos")
+    fn = L.lib().hphi_lanczos_noalloc if no_alloc else L.lib().hphi_lanczos
+    _check(fn(ham.h, C.byref(o), e.ctypes.data_as(L.PD), n_energies, C.byref(info)),
+           "hphi_lanczos_noalloc" if no_alloc else "hphi_lanczos")
     n = info.iterations
     return {"energies": e, "alpha": alpha[:n], "beta": beta[:n], "iterations": n,
             "converged": bool(info.converged), "breakdown": bool(info.breakdown),

@@ -75,6 +75,11 @@ int hphi_init(int device, hphi_ctx **ctx)
     c->device = device;
     c->n_cu = prop.multiProcessorCount;
     c->lds_per_block = prop.sharedMemPerBlock;
+    const int rc = noalloc_scratch_init(device);
+    if (rc != HPHI_OK) {
+        delete c;
+        return rc;
+    }
     *ctx = c;
     return HPHI_OK;
 }
@@ -741,13 +746,29 @@ int hphi_tridiag_lowest(const double *alpha, const double *beta, int n, int k, d
 
 namespace {
 
+// Sequential 256-byte aligned pieces of a caller-provided device buffer.
+struct Carve {
+    unsigned char *base;
+    size_t cap, off = 0;
+    Carve(void *b, size_t c) : base(static_cast<unsigned char *>(b)), cap(c) {}
+    static size_t up(size_t n) { return (n + 255) & ~size_t(255); }
+    void *take(size_t n)
+    {
+        void *p = base + off;
+        off += up(n);
+        return off <= cap ? p : nullptr;
+    }
+    bool ok() const { return off <= cap; }
+};
+
 struct LanczosRun {
     hphi_ham *h;
     int dt;
     int psi_dt = -1;   // type of the Ritz-vector accumulator (default: dt)
     int64_t dim;
     hipStream_t st;
-    DevMem q[3];
+    void *q[3] = {nullptr, nullptr, nullptr};
+    DevMem own_q[3];
     DevMem lz_mem, ab;   // LzDev; alpha[max_iter + 1] then beta[max_iter + 2]
     LzDev *lz = nullptr;
     double *alpha = nullptr, *beta = nullptr;
@@ -796,17 +817,33 @@ struct LanczosRun {
         return HPHI_OK;
     }
 
-    int setup(int max_iter)
+    // Device buffers: allocated here, or carved from `ws` (caller-provided
+    // workspace, 256-byte aligned pieces; see lanczos_ws_bytes) and zeroed
+    // by a kernel.
+    int setup(int max_iter, Carve *ws = nullptr)
     {
         fused = h->kind == 1 && (dt == HPHI_F64 || dt == HPHI_F32) && hub_rows_fused_ok(h, 1);
         const size_t bytes = (size_t)dim * dtype_size(dt);
-        for (auto &m : q) HPHI_TRY(m.alloc(bytes));
-        HPHI_TRY(lz_mem.alloc(sizeof(LzDev)));
-        HPHI_HIP(hipMemsetAsync(lz_mem.p, 0, sizeof(LzDev), st));
-        lz = lz_mem.as<LzDev>();
-        HPHI_TRY(ab.alloc(sizeof(double) * (2 * (size_t)max_iter + 4)));
-        HPHI_HIP(hipMemsetAsync(ab.p, 0, ab.bytes, st));
-        alpha = ab.as<double>();
+        const size_t ab_bytes = sizeof(double) * (2 * (size_t)max_iter + 4);
+        if (ws) {
+            for (auto &p : q) p = ws->take(bytes);
+            lz = static_cast<LzDev *>(ws->take(sizeof(LzDev)));
+            alpha = static_cast<double *>(ws->take(ab_bytes));
+            if (!ws->ok()) return fail(HPHI_ERR_INVALID_ARG, "Lanczos workspace too small");
+            HPHI_TRY(launch_zero(lz, sizeof(LzDev), st));
+            HPHI_TRY(launch_zero(alpha, ab_bytes, st));
+        } else {
+            for (int i = 0; i < 3; ++i) {
+                HPHI_TRY(own_q[i].alloc(bytes));
+                q[i] = own_q[i].p;
+            }
+            HPHI_TRY(lz_mem.alloc(sizeof(LzDev)));
+            HPHI_HIP(hipMemsetAsync(lz_mem.p, 0, sizeof(LzDev), st));
+            lz = lz_mem.as<LzDev>();
+            HPHI_TRY(ab.alloc(ab_bytes));
+            HPHI_HIP(hipMemsetAsync(ab.p, 0, ab.bytes, st));
+            alpha = ab.as<double>();
+        }
         beta = alpha + max_iter + 1;
         return HPHI_OK;
     }
@@ -815,12 +852,12 @@ struct LanczosRun {
     {
         cur = 0; wbuf = 1; prev = 2;
         if (o->v0_dev) {
-            HPHI_HIP(hipMemcpyAsync(q[0].p, o->v0_dev, (size_t)dim * dtype_size(dt), hipMemcpyDeviceToDevice, st));
+            HPHI_HIP(hipMemcpyAsync(q[0], o->v0_dev, (size_t)dim * dtype_size(dt), hipMemcpyDeviceToDevice, st));
         } else {
-            HPHI_TRY(launch_rng_uniform(dt, q[0].p, dim, o->seed, st));
+            HPHI_TRY(launch_rng_uniform(dt, q[0], dim, o->seed, st));
         }
         Reduce r = reduce_of(h, lz->nrm);
-        HPHI_TRY(launch_dots(dt, 1, dim, q[0].p, q[0].p, r, 1, st));
+        HPHI_TRY(launch_dots(dt, 1, dim, q[0], q[0], r, 1, st));
         return launch_lz_init(dt, lz, dim, r, st);
     }
 
@@ -832,13 +869,13 @@ struct LanczosRun {
     {
         const bool fz = fused && !first;
         const int pdt = psi_dt < 0 ? dt : psi_dt;
-        if (psi && !fz) HPHI_TRY(launch_lz_psi_accum(pdt, dt, lz, svec, dim, psi, q[cur].p, st));
+        if (psi && !fz) HPHI_TRY(launch_lz_psi_accum(pdt, dt, lz, svec, dim, psi, q[cur], st));
         MultArgs a{};
         a.dtype = dt;
         a.nvec = 1;
-        a.v = q[cur].p;
-        a.w = q[wbuf].p;
-        a.u = first ? nullptr : q[prev].p;
+        a.v = q[cur];
+        a.w = q[wbuf];
+        a.u = first ? nullptr : q[prev];
         a.coef = lz->coef;
         a.dots = 1;
         a.dot_raw = 0;
@@ -848,7 +885,7 @@ struct LanczosRun {
             a.lz = lz;
             a.lz_alpha = alpha;
             a.lz_beta = beta;
-            a.lz_q = q[prev].p;
+            a.lz_q = q[prev];
             a.lz_red = reduce_of(h, lz->nrm);
         }
         if (timing) {
@@ -862,9 +899,9 @@ struct LanczosRun {
         }
         HPHI_TRY(launch_mult(h, a));
         if (timing) HPHI_TRY(mark());
-        if (psi && fz) HPHI_TRY(launch_lz_psi_accum(pdt, dt, lz, svec, dim, psi, q[cur].p, st));
+        if (psi && fz) HPHI_TRY(launch_lz_psi_accum(pdt, dt, lz, svec, dim, psi, q[cur], st));
         if (!fused)
-            HPHI_TRY(launch_lz_update(dt, lz, alpha, beta, dim, q[wbuf].p, q[cur].p, reduce_of(h, lz->nrm), st));
+            HPHI_TRY(launch_lz_update(dt, lz, alpha, beta, dim, q[wbuf], q[cur], reduce_of(h, lz->nrm), st));
         const int old_prev = prev;
         prev = cur;
         cur = wbuf;
@@ -933,7 +970,7 @@ struct LanczosRun {
         // fused mode: the last product's update (not needed by the
         // Ritz-vector pass, which accumulates q_0 .. q_{n-1} only)
         if (fused && !psi)
-            HPHI_TRY(launch_lz_update(dt, lz, alpha, beta, dim, q[cur].p, q[prev].p, reduce_of(h, lz->nrm), st));
+            HPHI_TRY(launch_lz_update(dt, lz, alpha, beta, dim, q[cur], q[prev], reduce_of(h, lz->nrm), st));
         return HPHI_OK;
     }
 };
@@ -954,8 +991,11 @@ static double second_distinct_ritz(const std::vector<double> &a, const std::vect
     return NAN;
 }
 
-int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *o, double *energies, int n_energies,
-                 hphi_lanczos_info *info)
+// The Lanczos solve behind hphi_lanczos and hphi_lanczos_noalloc. ws: null
+// = allocate the device buffers here; otherwise every device buffer is
+// carved from ws (no allocation, no graph, no events).
+static int lanczos_impl(hphi_ham *h, const hphi_lanczos_opts *o, double *energies, int n_energies,
+                        hphi_lanczos_info *info, Carve *ws)
 {
     if (!h || !o || (n_energies > 0 && !energies)) return fail(HPHI_ERR_INVALID_ARG, "null argument");
     if (o->max_iter < 1 || o->max_iter > 100000) return fail(HPHI_ERR_INVALID_ARG, "max_iter %d", o->max_iter);
@@ -984,7 +1024,7 @@ int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *o, double *energies, int 
     L.dim = h->basis->dim;
     L.st = st;
     L.timing = o->time_kernels != 0 && !o->use_graph;
-    HPHI_TRY(L.setup(o->max_iter));
+    HPHI_TRY(L.setup(o->max_iter, ws));
     HPHI_TRY(L.start(o));
     int converged = 0;
     std::vector<double> last_ev;
@@ -1013,40 +1053,58 @@ int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *o, double *energies, int 
         // with refine the sum is kept in FP64 whatever the storage type
         std::vector<double> s(n);
         HPHI_TRY(tridiag_lowest(ha.data(), hb.data(), n, 1, &ritz_e0, s.data()));
-        DevMem sv, psi64, hpsi;
-        HPHI_TRY(upload(sv, s.data(), sizeof(double) * n));
+        DevMem sv_m, psi64_m, hpsi_m;
+        double *sv = nullptr;
+        void *psi64 = nullptr, *hpsi = nullptr;
+        if (ws) {
+            sv = static_cast<double *>(ws->take(sizeof(double) * n));
+            if (o->refine) {
+                psi64 = ws->take((size_t)L.dim * sizeof(double));
+                hpsi = ws->take((size_t)L.dim * sizeof(double));
+            }
+            if (!ws->ok()) return fail(HPHI_ERR_INVALID_ARG, "Lanczos workspace too small");
+            HPHI_HIP(hipMemcpyAsync(sv, s.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+        } else {
+            HPHI_TRY(upload(sv_m, s.data(), sizeof(double) * n));
+            sv = sv_m.as<double>();
+            if (o->refine) {
+                HPHI_TRY(psi64_m.alloc((size_t)L.dim * sizeof(double)));
+                HPHI_TRY(hpsi_m.alloc((size_t)L.dim * sizeof(double)));
+                psi64 = psi64_m.p;
+                hpsi = hpsi_m.p;
+            }
+        }
         void *psi = o->psi_dev;
         int pdt = L.dt;
         if (o->refine) {
-            HPHI_TRY(psi64.alloc((size_t)L.dim * sizeof(double)));
-            psi = psi64.p;
+            psi = psi64;
             pdt = HPHI_F64;
         }
         L.psi_dt = pdt;
-        HPHI_HIP(hipMemsetAsync(psi, 0, (size_t)L.dim * dtype_size(pdt), st));
+        if (ws) HPHI_TRY(launch_zero(psi, (size_t)L.dim * dtype_size(pdt), st));
+        else HPHI_HIP(hipMemsetAsync(psi, 0, (size_t)L.dim * dtype_size(pdt), st));
         HPHI_TRY(L.start(o));
         std::vector<double> dummy;
         int cv = 0;
-        HPHI_TRY(L.run(n, false, sv.as<double>(), psi, 0, 0.0, 1, &cv, dummy));
+        HPHI_TRY(L.run(n, false, sv, psi, 0, 0.0, 1, &cv, dummy));
         double *res = h->red_result.as<double>();
         HPHI_TRY(launch_dots(pdt, 1, L.dim, psi, psi, reduce_of(h), 1, st));
         HPHI_TRY(launch_scale_lanes(pdt, 1, L.dim, psi, res, 1, st));
         if (o->refine) {
             // rho = <psi|H psi> and eps = |H psi - rho psi| in FP64
-            HPHI_TRY(hpsi.alloc((size_t)L.dim * sizeof(double)));
             MultArgs a{};
             a.dtype = HPHI_F64;
             a.nvec = 1;
             a.v = psi;
-            a.w = hpsi.p;
+            a.w = hpsi;
             a.stream = st;
             a.red = reduce_of(h);
             HPHI_TRY(launch_mult(h, a));
-            HPHI_TRY(launch_dots(HPHI_F64, 1, L.dim, psi, hpsi.p, reduce_of(h), 0, st));
+            HPHI_TRY(launch_dots(HPHI_F64, 1, L.dim, psi, hpsi, reduce_of(h), 0, st));
             HPHI_HIP(hipMemcpyAsync(&rq_e0, res, sizeof(double), hipMemcpyDeviceToHost, st));
             HPHI_HIP(hipStreamSynchronize(st));
-            HPHI_TRY(launch_axpy_lanes(HPHI_F64, 1, L.dim, hpsi.p, psi, nullptr, -rq_e0, st));
-            HPHI_TRY(launch_dots(HPHI_F64, 1, L.dim, hpsi.p, hpsi.p, reduce_of(h), 1, st));
+            HPHI_TRY(launch_axpy_lanes(HPHI_F64, 1, L.dim, hpsi, psi, nullptr, -rq_e0, st));
+            HPHI_TRY(launch_dots(HPHI_F64, 1, L.dim, hpsi, hpsi, reduce_of(h), 1, st));
             double r2 = 0.0;
             HPHI_HIP(hipMemcpyAsync(&r2, res, sizeof(double), hipMemcpyDeviceToHost, st));
             HPHI_HIP(hipStreamSynchronize(st));
@@ -1073,6 +1131,55 @@ int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *o, double *energies, int 
         info->err_est = err_est;
     }
     return HPHI_OK;
+}
+
+
+int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *o, double *energies, int n_energies,
+                 hphi_lanczos_info *info)
+{
+    return lanczos_impl(h, o, energies, n_energies, info, nullptr);
+}
+
+} // extern "C"
+
+// Device bytes hphi_lanczos_noalloc carves from the static scratch.
+static size_t noalloc_bytes(int64_t dim, int storage, int max_iter, int refine)
+{
+    const size_t vb = (size_t)dim * (storage == HPHI_F32 ? 4 : 8);
+    size_t n = 3 * Carve::up(vb) + Carve::up(sizeof(LzDev)) + Carve::up(sizeof(double) * (2 * (size_t)max_iter + 4)) +
+               Carve::up(sizeof(double) * (size_t)max_iter);
+    if (refine) n += 2 * Carve::up((size_t)dim * sizeof(double));
+    return n;
+}
+
+static_assert(HPHI_NOALLOC_SCRATCH_BYTES == kNoAllocScratchBytes, "scratch size in the header");
+
+extern "C" {
+
+int hphi_lanczos_noalloc(hphi_ham *h, const hphi_lanczos_opts *o, double *energies, int n_energies,
+                         hphi_lanczos_info *info)
+{
+    if (!h || !o) return fail(HPHI_ERR_INVALID_ARG, "null argument");
+    if (o->use_graph || o->time_kernels)
+        return fail(HPHI_ERR_INVALID_ARG, "hphi_lanczos_noalloc: use_graph and time_kernels are not available");
+    if (o->max_iter < 1 || o->max_iter > 100000) return fail(HPHI_ERR_INVALID_ARG, "max_iter %d", o->max_iter);
+    if (o->storage != HPHI_F64 && o->storage != HPHI_F32)
+        return fail(HPHI_ERR_INVALID_ARG, "Lanczos storage must be F64 or F32");
+    const size_t need = noalloc_bytes(h->basis->dim, o->storage, o->max_iter, o->refine);
+    if (need > kNoAllocScratchBytes)
+        return fail(HPHI_ERR_INVALID_ARG,
+                    "hphi_lanczos_noalloc: %zu bytes of workspace needed (dim %lld), the static scratch holds %zu",
+                    need, (long long)h->basis->dim, kNoAllocScratchBytes);
+    const int dev = h->basis->ctx->device;
+    DeviceGuard g(dev);
+    void *p = nullptr;
+    HPHI_TRY(noalloc_scratch_acquire(dev, &p));
+    struct Release {
+        int d;
+        ~Release() { noalloc_scratch_release(d); }
+    } rel{dev};
+    Carve ws(p, kNoAllocScratchBytes);
+    return lanczos_impl(h, o, energies, n_energies, info, &ws);
 }
 
 } // extern "C"

@@ -330,6 +330,16 @@ int launch_lz_update(int dtype, LzDev *lz, double *alpha, double *beta, int64_t 
 int launch_lz_psi_accum(int psi_dtype, int dtype, LzDev *lz, const double *svec, int64_t dim, void *psi,
                         const void *qk, hipStream_t st);
 
+// Static device scratch of the no-allocation Lanczos entry point
+// (noalloc.hip): set up per device in hphi_init; one call at a time per
+// device (acquire returns HPHI_ERR_BUSY otherwise).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+int noalloc_scratch_init(int device);
+int noalloc_scratch_acquire(int device, void **ptr);
+void noalloc_scratch_release(int device);
+// zero fill by a kernel (bytes a multiple of 4, 4-byte aligned)
+int launch_zero(void *p, size_t bytes, hipStream_t st);
+
 // host tridiagonal solver
 int tridiag_lowest(const double *alpha, const double *beta, int n, int k, double *eig,
                    double *vec);
