@@ -64,6 +64,8 @@ def parse():
     p.add_argument("--retune", action="store_true", help="with --tune: sweep even if a schedule is recorded")
     p.add_argument("--cpu-sample-rows", type=int, default=0,
                    help="oracle sample size in up-rows (hubbard4x4)")
+    p.add_argument("--schedule", default="",
+                   help='JSON launch-schedule fields applied before timing, e.g. \'{"hub_sweep": 5}\'')
     a = p.parse_args()
     a.no_tune = a.no_tune or not a.tune
     return a
@@ -204,6 +206,8 @@ def run_lanczos(a, api, ham, dim, iters, storage, wl, kernel, tune_dtype, hv_eve
     after the timed ones."""
     import torch
     stream = torch.cuda.current_stream()
+    if a.schedule:
+        ham.set_schedule(**json.loads(a.schedule))
     if not a.no_tune:
         from paper_2307_13222_amd import autotune
         tuned = autotune.tune(ham, tune_dtype, 1, force=a.retune)
@@ -254,9 +258,11 @@ def run_lanczos(a, api, ham, dim, iters, storage, wl, kernel, tune_dtype, hv_eve
         # two-kernel split, reported beside the measured traffic, not counted
         k2_avg = k2_s / max(1, hv_n)
         cols_bytes = esize * dim * (3.0 - hv_solves / max(1, hv_n))
-        roof = roofline(cols_bytes / k2_avg / 1e9, cols_bytes,
-                        f"k_hub_cols_f (T_up slab kernel with the Lanczos epilogue and FP64 dots; "
-                        f"{100 * k2_avg / hv_avg:.0f} % of a step)", hub_traffic(wl["schedule"], "cols"))
+        kname = ("k_hub_up_tile (T_up block tiles in LDS, Lanczos epilogue and FP64 dots" if
+                 wl["schedule"].get("hub_sweep") == 7 else
+                 "k_hub_cols_f (T_up slab kernel with the Lanczos epilogue and FP64 dots")
+        roof = roofline(cols_bytes / k2_avg / 1e9, cols_bytes, f"{kname}; {100 * k2_avg / hv_avg:.0f} % of a step)",
+                        hub_traffic(wl["schedule"], "cols"))
         roof["ms"] = round(1e3 * k2_avg, 5)
         roof["split_overhead_bytes_per_launch"] = 2.0 * esize * dim
         pair = roofline(gbs, alg_bytes, kernel, hub_traffic(wl["schedule"], "pair"))
@@ -312,7 +318,7 @@ def main():
               "storage": "f64", "lattice": "square 4x4", "n_up": 8, "n_dn": 8}
         out, e64 = run_lanczos(a, api, ham, basis.dim, iters, "f64", wl,
                                "H*v launch pair = k_hub_rows_fz (previous step's Lanczos update fused into the T_dn/U "
-                               "rows kernel) + k_hub_cols_f (T_up slab kernel, epilogue and FP64 dots)", "f64")
+                               "rows kernel) + the T_up kernel (epilogue and FP64 dots)", "f64")
         # the same solves with FP32 vector storage (FP64 alpha/beta, dots
         # and tridiagonal), outside the timed FP64 region
         ts, hv32, e32 = [], [], []

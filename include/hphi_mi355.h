@@ -202,7 +202,14 @@ void hphi_ham_free(hphi_ham *h);
  *                   items and reading the neighbour lists with scalar loads
  *                   (no LDS staging, no block barriers; the products are
  *                   bit-identical to 5, the fused dots sum in another
- *                   order)
+ *                   order); 7 = block tiles: a work item is (slab of 16
+ *                   columns, block of the up rows sharing their top
+ *                   hub_tile_bits sites), the block's rows of the slab are
+ *                   staged in LDS once, hops that keep those sites read
+ *                   LDS and only the others gather from memory (one real
+ *                   vector, even number of down states; otherwise as 5;
+ *                   the products equal those of 5 up to summation order;
+ *                   the default where the tables could be built, else 5)
  *   hub_row_order   order in which the T_up kernels of hub_sweep 1, 3, 5
  *                   and 6 take the up rows: 1 = index order, 2 = reverse
  *                   Cuthill-McKee order of the up-species hop graph (rows
@@ -218,7 +225,12 @@ void hphi_ham_free(hphi_ham *h);
  *                   choice the sector's tables do not fit returns
  *                   UNSUPPORTED from the product. The products are the same
  *                   sums in the same order whichever is chosen.
- * Errors: INVALID_ARG (value outside its range). */
+ *   hub_tile_bits   top up-species sites that label the blocks of hub_sweep
+ *                   7 (the tables are rebuilt when it changes); -1 = the
+ *                   fewest sites whose largest block of 16 FP64 columns
+ *                   fits LDS (the default)
+ * Errors: INVALID_ARG (value outside its range), UNSUPPORTED (hub_sweep 7
+ * or hub_tile_bits for blocks the tile kernel cannot take). */
 typedef struct {
     int hub_slab_cols;
     int hub_groups;
@@ -229,6 +241,7 @@ typedef struct {
     int hub_sweep;
     int hub_row_order;
     int spin_tables;
+    int hub_tile_bits;
 } hphi_schedule;
 
 int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s);

@@ -401,6 +401,124 @@ static std::vector<uint32_t> rcm_order(const std::vector<std::vector<uint32_t>> 
     return order;
 }
 
+// Tile tables of the up species (see HubTables::ft_*): blocks of consecutive
+// up rows sharing the top `bits` sites; each row's hops split into local
+// (target in the block: row index in the block) and far (target row), each
+// by fermion sign; the rows of a block ordered by (far count, local count)
+// so the eight rows of a wave walk lists of similar length. bits = 0: the
+// fewest top sites whose largest block fits the kernel's LDS in FP64. Sets
+// ft_ok false when the shape does not fit the kernel.
+constexpr int kTileMaxRowsF64 = 1135;   // (160 KiB - reduction scratch) / 144-byte rows
+
+static int build_hub_tile(hphi_ham *h, int bits)
+{
+    HubTables &T = h->hub;
+    T.ft_ok = false;
+    const Species &up = h->basis->sp[0];
+    if (!T.uniform_t || up.dim >= (int64_t(1) << 24) || up.n_bits > 32) return HPHI_OK;
+    const int n = up.n_bits;
+    auto block_starts = [&](int nb_bits) {
+        std::vector<uint32_t> blk;
+        uint64_t prev = ~uint64_t(0);
+        for (int64_t r = 0; r < up.dim; ++r) {
+            const uint64_t lab = nb_bits > 0 ? up.state_at(r) >> (n - nb_bits) : 0;
+            if (lab != prev) {
+                blk.push_back((uint32_t)r);
+                prev = lab;
+            }
+        }
+        blk.push_back((uint32_t)up.dim);
+        return blk;
+    };
+    auto max_rows = [](const std::vector<uint32_t> &blk) {
+        uint32_t m = 0;
+        for (size_t b = 0; b + 1 < blk.size(); ++b) m = std::max(m, blk[b + 1] - blk[b]);
+        return m;
+    };
+    std::vector<uint32_t> blk;
+    if (bits <= 0) {
+        for (bits = 1; bits <= n; ++bits) {
+            blk = block_starts(bits);
+            if (max_rows(blk) <= (uint32_t)kTileMaxRowsF64) break;
+        }
+        if (bits > n) return HPHI_OK;
+    } else {
+        if (bits > n) return fail(HPHI_ERR_INVALID_ARG, "hub_tile_bits %d above the site count", bits);
+        blk = block_starts(bits);
+        if (max_rows(blk) > (uint32_t)kTileMaxRowsF64) {
+            T.ft_bits = bits;
+            return HPHI_OK;
+        }
+    }
+    std::vector<std::vector<uint32_t>> pl, mi;
+    split_lists(up, h->hops, pl, mi);
+    const size_t nb = blk.size() - 1;
+    std::vector<uint32_t> pos((size_t)up.dim), off((size_t)up.dim + 1, 0), cnt((size_t)up.dim), ent;
+    bool ok = true;
+    for (size_t b = 0; b < nb; ++b) {
+        const uint32_t b0 = blk[b], b1 = blk[b + 1];
+        std::vector<uint32_t> rows(b1 - b0);
+        std::vector<uint32_t> nloc(b1 - b0), nfar(b1 - b0);
+        for (uint32_t r = b0; r < b1; ++r) {
+            rows[r - b0] = r - b0;
+            uint32_t l = 0, f = 0;
+            for (const auto *lst : {&pl[r], &mi[r]})
+                for (uint32_t x : *lst) (x >= b0 && x < b1 ? l : f) += 1;
+            nloc[r - b0] = l;
+            nfar[r - b0] = f;
+        }
+        std::stable_sort(rows.begin(), rows.end(), [&](uint32_t x, uint32_t y) {
+            return nfar[x] != nfar[y] ? nfar[x] < nfar[y] : nloc[x] < nloc[y];
+        });
+        for (uint32_t p = 0; p < b1 - b0; ++p) {
+            const uint32_t lr = rows[p], r = b0 + lr;
+            pos[b0 + p] = lr;
+            off[b0 + p] = (uint32_t)ent.size();
+            uint32_t c[4] = {0, 0, 0, 0};
+            std::vector<uint32_t> loc;
+            for (int part = 0; part < 4; ++part) {
+                const std::vector<uint32_t> &lst = (part & 1) ? mi[r] : pl[r];
+                const bool local = part < 2;
+                for (uint32_t x : lst) {
+                    const bool in = x >= b0 && x < b1;
+                    if (in != local) continue;
+                    if (local) loc.push_back(x - b0);
+                    else ent.push_back(x);
+                    ++c[part];
+                }
+                // local entries: 16 bits each, two per word, in 16-byte
+                // groups; far entries: one word each, from the next group
+                // boundary; padding (never read) points at row 0 / row b0
+                if (part == 1) {
+                    while (loc.size() % 8) loc.push_back(0u);
+                    for (size_t k = 0; k < loc.size(); k += 2) ent.push_back(loc[k] | (loc[k + 1] << 16));
+                }
+                if (part == 3)
+                    while (ent.size() % 4) ent.push_back(b0);
+            }
+            for (uint32_t k : c) ok = ok && k <= 255;
+            // the kernel holds a row's entries in registers: at most 24
+            // local (16-bit row indices) and 12 far ones
+            const uint32_t nl = c[0] + c[1], nf = c[2] + c[3];
+            ok = ok && nl <= 24 && nf <= 12 && b1 - b0 <= 65536;
+            cnt[b0 + p] = c[0] | (c[1] << 8) | (c[2] << 16) | (c[3] << 24);
+        }
+    }
+    off[up.dim] = (uint32_t)ent.size();
+    T.ft_bits = bits;
+    if (!ok) return HPHI_OK;
+    ent.resize(ent.size() + 8, 0u);   // the far loop may read one group past a row's list
+    HPHI_TRY(upload(T.ft_blk, blk.data(), sizeof(uint32_t) * blk.size()));
+    HPHI_TRY(upload(T.ft_pos, pos.data(), sizeof(uint32_t) * pos.size()));
+    HPHI_TRY(upload(T.ft_off, off.data(), sizeof(uint32_t) * off.size()));
+    HPHI_TRY(upload(T.ft_cnt, cnt.data(), sizeof(uint32_t) * cnt.size()));
+    HPHI_TRY(upload(T.ft_ent, ent.data(), sizeof(uint32_t) * ent.size()));
+    T.ft_nb = (int)nb;
+    T.ft_max_rows = (int)max_rows(blk);
+    T.ft_ok = true;
+    return HPHI_OK;
+}
+
 static int build_hub_fast(hphi_ham *h)
 {
     const hphi_basis *b = h->basis;
@@ -639,6 +757,9 @@ int hphi_ham_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops, const doub
     if (h->hub.uniform_t) {
         h->hub.t0 = std::fabs(hops[0].t);
         HPHI_TRY(build_hub_fast(h.get()));
+        HPHI_TRY(build_hub_tile(h.get(), h->sched_cfg.hub_tile_bits));
+        // the block-tile T_up kernel where its tables could be built
+        if (h->hub.ft_ok) h->sched_cfg.hub_sweep = 7;
     }
     HPHI_TRY(ensure_reduce(h.get()));
     *out = h.release();
@@ -681,7 +802,7 @@ int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s)
         n.spin_implicit = s->spin_implicit == 1 ? 1 : 0;
     }
     if (s->hub_sweep) {
-        if (s->hub_sweep < 1 || s->hub_sweep > 6) return fail(HPHI_ERR_INVALID_ARG, "hub_sweep %d", s->hub_sweep);
+        if (s->hub_sweep < 1 || s->hub_sweep > 7) return fail(HPHI_ERR_INVALID_ARG, "hub_sweep %d", s->hub_sweep);
         n.hub_sweep = s->hub_sweep;
     }
     if (s->hub_row_order) {
@@ -693,6 +814,21 @@ int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s)
         if (s->spin_tables != -1 && (s->spin_tables < 1 || s->spin_tables > 3))
             return fail(HPHI_ERR_INVALID_ARG, "spin_tables %d", s->spin_tables);
         n.spin_tables = s->spin_tables == -1 ? 0 : s->spin_tables;
+    }
+    if (s->hub_sweep == 7 && h->kind == 1 && !h->hub.ft_ok && !s->hub_tile_bits)
+        return fail(HPHI_ERR_UNSUPPORTED, "hub_sweep 7: no tile tables for this Hamiltonian");
+    if (s->hub_tile_bits) {
+        if (s->hub_tile_bits != -1 && (s->hub_tile_bits < 1 || s->hub_tile_bits > 32))
+            return fail(HPHI_ERR_INVALID_ARG, "hub_tile_bits %d", s->hub_tile_bits);
+        n.hub_tile_bits = s->hub_tile_bits == -1 ? 0 : s->hub_tile_bits;
+        if (h->kind == 1 && h->hub.uniform_t) {
+            DeviceGuard g(h->basis->ctx->device);
+            HPHI_USE_HAM(h, nullptr);
+            HPHI_TRY(build_hub_tile(h, n.hub_tile_bits));
+            if (!h->hub.ft_ok && n.hub_sweep == 7)
+                return fail(HPHI_ERR_UNSUPPORTED, "hub_tile_bits %d: blocks do not fit the tile kernel",
+                            s->hub_tile_bits);
+        }
     }
     h->sched_cfg = n;
     return HPHI_OK;
@@ -766,6 +902,9 @@ struct LanczosRun {
     int dt;
     int psi_dt = -1;   // type of the Ritz-vector accumulator (default: dt)
     int64_t dim;
+    // Hubbard: the vectors may be stored with rows padded to whole cache
+    // lines (pitch ld >= cols = dim_dn, padding zero); nstore elements each
+    int64_t cols = 0, ld = 0, nstore = 0;
     hipStream_t st;
     void *q[3] = {nullptr, nullptr, nullptr};
     DevMem own_q[3];
@@ -823,7 +962,15 @@ struct LanczosRun {
     int setup(int max_iter, Carve *ws = nullptr)
     {
         fused = h->kind == 1 && (dt == HPHI_F64 || dt == HPHI_F32) && hub_rows_fused_ok(h, 1);
-        const size_t bytes = (size_t)dim * dtype_size(dt);
+        cols = ld = dim;
+        if (h->kind == 1) {
+            cols = h->basis->sp[1].dim;
+            // padded rows only with allocated buffers (the static scratch
+            // path keeps the caller's layout and its size formula)
+            ld = (fused && !ws) ? hub_lanczos_pitch(h, dt) : cols;
+        }
+        nstore = dim / cols * ld;
+        const size_t bytes = (size_t)nstore * dtype_size(dt);
         const size_t ab_bytes = sizeof(double) * (2 * (size_t)max_iter + 4);
         if (ws) {
             for (auto &p : q) p = ws->take(bytes);
@@ -836,6 +983,8 @@ struct LanczosRun {
             for (int i = 0; i < 3; ++i) {
                 HPHI_TRY(own_q[i].alloc(bytes));
                 q[i] = own_q[i].p;
+                // the padding stays zero: the kernels write whole rows only
+                if (ld != cols) HPHI_HIP(hipMemsetAsync(q[i], 0, bytes, st));
             }
             HPHI_TRY(lz_mem.alloc(sizeof(LzDev)));
             HPHI_HIP(hipMemsetAsync(lz_mem.p, 0, sizeof(LzDev), st));
@@ -851,13 +1000,21 @@ struct LanczosRun {
     int start(const hphi_lanczos_opts *o)
     {
         cur = 0; wbuf = 1; prev = 2;
+        const size_t es = dtype_size(dt);
         if (o->v0_dev) {
-            HPHI_HIP(hipMemcpyAsync(q[0], o->v0_dev, (size_t)dim * dtype_size(dt), hipMemcpyDeviceToDevice, st));
-        } else {
+            if (ld == cols)
+                HPHI_HIP(hipMemcpyAsync(q[0], o->v0_dev, (size_t)dim * es, hipMemcpyDeviceToDevice, st));
+            else
+                HPHI_HIP(hipMemcpy2DAsync(q[0], (size_t)ld * es, o->v0_dev, (size_t)cols * es, (size_t)cols * es,
+                                          (size_t)(dim / cols), hipMemcpyDeviceToDevice, st));
+        } else if (ld == cols) {
             HPHI_TRY(launch_rng_uniform(dt, q[0], dim, o->seed, st));
+        } else {
+            HPHI_TRY(launch_rng_uniform_pitched(dt, q[0], dim / cols, cols, ld, o->seed, st));
         }
         Reduce r = reduce_of(h, lz->nrm);
-        HPHI_TRY(launch_dots(dt, 1, dim, q[0], q[0], r, 1, st));
+        if (ld == cols) HPHI_TRY(launch_dots(dt, 1, dim, q[0], q[0], r, 1, st));
+        else HPHI_TRY(launch_norm2_pitched(dt, q[0], dim, cols, ld, r, st));
         return launch_lz_init(dt, lz, dim, r, st);
     }
 
@@ -869,7 +1026,7 @@ struct LanczosRun {
     {
         const bool fz = fused && !first;
         const int pdt = psi_dt < 0 ? dt : psi_dt;
-        if (psi && !fz) HPHI_TRY(launch_lz_psi_accum(pdt, dt, lz, svec, dim, psi, q[cur], st));
+        if (psi && !fz) HPHI_TRY(launch_lz_psi_accum(pdt, dt, lz, svec, dim, psi, q[cur], st, cols, ld));
         MultArgs a{};
         a.dtype = dt;
         a.nvec = 1;
@@ -881,6 +1038,7 @@ struct LanczosRun {
         a.dot_raw = 0;
         a.red = reduce_of(h, lz->dot);
         a.stream = st;
+        a.ld = h->kind == 1 ? ld : 0;
         if (fz) {
             a.lz = lz;
             a.lz_alpha = alpha;
@@ -899,9 +1057,9 @@ struct LanczosRun {
         }
         HPHI_TRY(launch_mult(h, a));
         if (timing) HPHI_TRY(mark());
-        if (psi && fz) HPHI_TRY(launch_lz_psi_accum(pdt, dt, lz, svec, dim, psi, q[cur], st));
+        if (psi && fz) HPHI_TRY(launch_lz_psi_accum(pdt, dt, lz, svec, dim, psi, q[cur], st, cols, ld));
         if (!fused)
-            HPHI_TRY(launch_lz_update(dt, lz, alpha, beta, dim, q[wbuf], q[cur], reduce_of(h, lz->nrm), st));
+            HPHI_TRY(launch_lz_update(dt, lz, alpha, beta, nstore, q[wbuf], q[cur], reduce_of(h, lz->nrm), st));
         const int old_prev = prev;
         prev = cur;
         cur = wbuf;
@@ -970,7 +1128,7 @@ struct LanczosRun {
         // fused mode: the last product's update (not needed by the
         // Ritz-vector pass, which accumulates q_0 .. q_{n-1} only)
         if (fused && !psi)
-            HPHI_TRY(launch_lz_update(dt, lz, alpha, beta, dim, q[cur], q[prev], reduce_of(h, lz->nrm), st));
+            HPHI_TRY(launch_lz_update(dt, lz, alpha, beta, nstore, q[cur], q[prev], reduce_of(h, lz->nrm), st));
         return HPHI_OK;
     }
 };

@@ -157,6 +157,15 @@ struct HubTables {
     // (element size 4 or 8: fc_ent[0] or [1]); built when dim_dn <= 16383
     bool fc_ok = false;
     DevMem fc_ent[2];
+    // up species for the T_up tile kernel: blocks of consecutive rows
+    // sharing the top ft_bits sites (rows ft_blk[b] .. ft_blk[b + 1]); by
+    // position p (block-major, rows of a block in an order grouping equal hop
+    // counts): ft_pos[p] the row's index in its block, ft_off[p] its first
+    // entry, ft_cnt[p] four 8-bit counts (local plus, local minus, far plus,
+    // far minus); entries: local = row index in the block, far = up row
+    bool ft_ok = false;
+    int ft_bits = 0, ft_nb = 0, ft_max_rows = 0;
+    DevMem ft_blk, ft_pos, ft_off, ft_cnt, ft_ent;
     DevMem coef;     // double [128]: -t per value class
     DevMem u_site;   // double [n_sites]
     int n_coef = 0;
@@ -183,7 +192,7 @@ struct hphi_ham {
     // defaults: 128-column slabs, 128 workgroups per XCD, 32-row items,
     // hop-ordered down slots, work-item queues with two columns per lane;
     // spin: 8 workgroups per CU
-    hphi_schedule sched_cfg{128, 128, 16, 6, 8, 0, 5, 2, 0};
+    hphi_schedule sched_cfg{128, 128, 16, 6, 8, 0, 5, 2, 0, 0};
     // scratch for reductions and work queues
     hphi::DevMem sched;         // unsigned [16]: per-XCD item queues + counter
     hphi::DevMem red_partial;   // double [kReduceSlots]
@@ -279,6 +288,7 @@ struct MultArgs {
     void *cocg;         // optional (spin, stored basis, one complex vector, dots = 1):
                         // the dots become the COCG mu = v^T (z_s v - H v) and the
                         // last block does the alpha step on this CgDev
+    int64_t ld;         // Hubbard: row pitch of v, w, u, lz_q in elements (0: dim_dn)
 };
 bool hub_rows_fused_ok(hphi_ham *h, int nv);
 bool spin_stored_path(const hphi_ham *h);
@@ -327,8 +337,16 @@ struct LzDev {
 int launch_lz_init(int dtype, LzDev *lz, int64_t dim, Reduce red, hipStream_t st);
 int launch_lz_update(int dtype, LzDev *lz, double *alpha, double *beta, int64_t dim, void *w,
                      const void *qk, Reduce red, hipStream_t st);
+// q stored in rows of `cols` elements at pitch ld (cols = 0: unpadded)
 int launch_lz_psi_accum(int psi_dtype, int dtype, LzDev *lz, const double *svec, int64_t dim, void *psi,
-                        const void *qk, hipStream_t st);
+                        const void *qk, hipStream_t st, int64_t cols = 0, int64_t ld = 0);
+int launch_rng_uniform_pitched(int dtype, void *out, int64_t rows, int64_t cols, int64_t ld, uint64_t seed,
+                               hipStream_t st);
+int launch_norm2_pitched(int dtype, const void *x, int64_t dim, int64_t cols, int64_t ld, Reduce red, hipStream_t st);
+// Row pitch (elements) a Hubbard Lanczos run may store its vectors with
+// (rows padded to whole 128-byte lines) for the current schedule; dim_dn
+// when the kernels it selects take only unpadded rows.
+int64_t hub_lanczos_pitch(hphi_ham *h, int dtype);
 
 // Static device scratch of the no-allocation Lanczos entry point
 // (noalloc.hip): set up per device in hphi_init; one call at a time per

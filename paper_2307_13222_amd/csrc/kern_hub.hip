@@ -67,6 +67,14 @@ struct HubKArgs {
     Reduce lz_red;
     const uint32_t *row_of;   // column kernels: row processed at position p (null: p)
     hipEvent_t ev_mid;        // recorded between the rows and the column kernel (null: none)
+    // T_up tile kernel (k_hub_up_tile): blocks of up rows, per-position lists
+    const uint32_t *ft_blk, *ft_pos, *ft_off, *ft_cnt, *ft_ent;
+    int ft_nb;
+    uint32_t ft_tile_bytes;   // LDS bytes of the staged block (most rows x row stride)
+    // row pitch (elements) of v, w, u and lz_q: ddn for caller vectors; the
+    // Lanczos run pads rows to whole cache lines for the rows kernels
+    // k_hub_rows_fp / k_hub_rows_fz and the tile kernel
+    int64_t ld;
 };
 
 template <typename S>
@@ -608,7 +616,7 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fb(HubKArgs a)
 #pragma unroll
             for (int j = 0; j < NV; ++j)
                 __builtin_nontemporal_store(dg * s_row[c * NV + j] + nt0 * acc[j],
-                                            &w[((size_t)ru * ddn + c) * NV + j]);
+                                            &w[((size_t)ru * a.ld + c) * NV + j]);
 #pragma unroll
             for (int g = 0; g < 4; ++g) cur[g] = nxt[g];
             ncur = nnxt;
@@ -664,7 +672,7 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fp(HubKArgs a)
             if ((uint32_t)g < nq) q[g] = p[g];
     };
     for (int64_t ru = blockIdx.x; ru < a.dup; ru += gridDim.x) {
-        const S *vrow = v + (size_t)ru * nrow;
+        const S *vrow = v + (size_t)ru * a.ld * NV;
         // unconditional loads (indices past the row re-read its last
         // element) so that all of them are in flight together
         S tmp[MAXE];
@@ -697,7 +705,7 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fp(HubKArgs a)
 #pragma unroll
             for (int j = 0; j < NV; ++j)
                 __builtin_nontemporal_store(dg * s_row[c * NV + j] + nt0 * acc[j],
-                                            &w[((size_t)ru * ddn + c) * NV + j]);
+                                            &w[((size_t)ru * a.ld + c) * NV + j]);
 #pragma unroll
             for (int g = 0; g < 4; ++g) cur[g] = nxt[g];
             ncur = nnxt;
@@ -789,9 +797,9 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fz(HubKArgs a)
     double acc = 0.0;
     const uint32_t rbytes = nrow * (uint32_t)sizeof(S);
     for (int64_t ru = blockIdx.x; ru < a.dup; ru += gridDim.x) {
-        S *vrow = v + (size_t)ru * nrow;
+        S *vrow = v + (size_t)ru * a.ld;
         const __amdgpu_buffer_rsrc_t rv = buf_rsrc(vrow, rbytes);
-        const __amdgpu_buffer_rsrc_t rq = buf_rsrc(qp + (size_t)ru * nrow, rbytes);
+        const __amdgpu_buffer_rsrc_t rq = buf_rsrc(qp + (size_t)ru * a.ld, rbytes);
         // two rounds of loads (registers), each with all of its loads in
         // flight (indices past the row re-read its last element); the first
         // round is issued before the barrier that waits for the previous
@@ -837,7 +845,7 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fz(HubKArgs a)
             else
                 fb_gather<S, 1>(cur, ncur, s_row, accg);
             const S dg = hub_diag<S>(a, uu, (uint32_t)s_d[c]);
-            __builtin_nontemporal_store(dg * s_row[c] + nt0 * accg[0], &w[(size_t)ru * ddn + c]);
+            __builtin_nontemporal_store(dg * s_row[c] + nt0 * accg[0], &w[(size_t)ru * a.ld + c]);
 #pragma unroll
             for (int g = 0; g < 4; ++g) cur[g] = nxt[g];
             ncur = nnxt;
@@ -1334,6 +1342,248 @@ __global__ __launch_bounds__(256) void k_hub_cols_f(HubKArgs a)
     }
 }
 
+
+// ------------------------------------------------------------ tile T_up --
+// T_up with the rows of one up block staged in LDS (uniform |t|, one real
+// vector, even row length). The up rows split by the top `tile bits` sites
+// of the up configuration into blocks of consecutive rows; a hop that
+// leaves those sites alone keeps its target in the block ("local"), the
+// others change the block ("far"). A work item is (slab of kTileCols
+// columns, block): the block's rows of the slab are staged once (eight lanes
+// per row segment, two columns each), the local hops read LDS and only the
+// far hops gather from L2/HBM. Items are taken slab-major from per-XCD
+// queues, so all blocks of a slab -- the rows the far hops read -- pass
+// through one XCD's L2 close together. Each thread reads its row's lists
+// itself (16-byte groups of four entries, L2-resident: every slab of a
+// block reuses them), so the passes over the block need no barrier; the
+// LDS holds the staged rows only, and small blocks let several workgroups
+// share a CU. Rows are processed in an order that groups equal hop counts
+// (less divergence among the eight rows of a wave); each element's sum
+// keeps the table's entry order, and the fused dots are per-item partials
+// summed in item order by the last workgroup.
+constexpr int kTileCols = 16;        // columns per slab (8 lanes x 2)
+constexpr int kTileSlots = 128;      // rows per pass (1024 threads / 8 lanes)
+constexpr int kTileLocalGroups = 3;  // 8-entry groups of local hops per row (16-bit)
+constexpr int kTileFar = 12;         // far hops per row
+// LDS behind the staged rows: block reduction scratch (16 waves x 2), item
+// and last-group words
+constexpr uint32_t kTileTailBytes = 8u * 32 + 16;
+template <typename S> constexpr int tile_row_stride() { return kTileCols + 16 / (int)sizeof(S); }
+
+template <typename S> struct Pair;
+template <> struct Pair<double> { using T = double2; };
+template <> struct Pair<float> { using T = float2; };
+
+template <typename S, bool DOTS>
+__global__ __launch_bounds__(1024) void k_hub_up_tile(HubKArgs a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    using P2 = typename Pair<S>::T;
+    constexpr int RS = tile_row_stride<S>();
+    S *tile = reinterpret_cast<S *>(smem_raw);
+    double *sh_red = reinterpret_cast<double *>(smem_raw + a.ft_tile_bytes);
+    int *s_item = reinterpret_cast<int *>(sh_red + 32);
+    unsigned *s_last = reinterpret_cast<unsigned *>(s_item + 1);
+    const int home = xcc_id();
+    const S *__restrict__ v = static_cast<const S *>(a.v);
+    S *__restrict__ w = static_cast<S *>(a.w);
+    const S *__restrict__ u = static_cast<const S *>(a.u);
+    const uint4 *__restrict__ ent4 = reinterpret_cast<const uint4 *>(a.ft_ent);
+    double c1 = 1.0, c2 = 0.0;
+    if (a.ecoef) {
+        c1 = a.ecoef[0];
+        c2 = a.ecoef[1];
+    }
+    const S c1s = (S)c1, c2s = (S)c2, nt0 = (S)(-a.t0);
+    const int64_t ddn = a.ddn, ld = a.ld;
+    const int tid = threadIdx.x, l8 = tid & 7, slot = tid >> 3;
+    const int nb = a.ft_nb;
+    int q = home, tries = 0;
+    for (;;) {
+        __syncthreads();    // the previous item's readers of the staged rows are done
+        if (tid == 0) {
+            int it = -1;
+            while (tries < 8) {
+                const int nsl_q = q < a.nslab ? (a.nslab - q + 7) / 8 : 0;
+                const int cand = (int)atomicAdd(&a.sched[q], 1u);
+                if (cand < nsl_q * nb) {
+                    it = q + 8 * cand;
+                    break;
+                }
+                q = (q + 1) & 7;
+                ++tries;
+            }
+            *s_item = it;
+        }
+        __syncthreads();
+        const int item = *s_item;
+        if (item < 0) break;
+        const int idx = item >> 3;
+        const int slab = (item & 7) + 8 * (idx / nb);
+        const int blk = idx % nb;
+        const int64_t r0 = a.ft_blk[blk], nr = (int64_t)a.ft_blk[blk + 1] - r0;
+        const int64_t col = (int64_t)slab * kTileCols + 2 * l8;
+        const bool cok = col < ddn;    // an even row length: both columns or neither
+        for (int64_t i = slot; i < nr; i += kTileSlots) {
+            P2 x;
+            x.x = (S)0;
+            x.y = (S)0;
+            if (cok) x = *reinterpret_cast<const P2 *>(v + (size_t)(r0 + i) * ld + col);
+            *reinterpret_cast<P2 *>(tile + i * RS + 2 * l8) = x;
+        }
+        __syncthreads();
+        double dv = 0.0, dd = 0.0;
+        // software pipeline over this thread's rows of the block: a row's
+        // position data are loaded one pass ahead; its epilogue operands
+        // and all of its entry groups are issued together, then the local
+        // reads (LDS) and the far gathers, so a pass waits on two rounds of
+        // memory latency
+        uint32_t lr_n = 0, cnt_n = 0, off_n = 0;
+        if (slot < nr) {
+            lr_n = a.ft_pos[r0 + slot];
+            cnt_n = a.ft_cnt[r0 + slot];
+            off_n = a.ft_off[r0 + slot];
+        }
+        for (int64_t p = slot; p < nr && cok; p += kTileSlots) {
+            const uint32_t lr = lr_n, cnt = cnt_n, g0 = off_n >> 2;
+            if (p + kTileSlots < nr) {
+                lr_n = a.ft_pos[r0 + p + kTileSlots];
+                cnt_n = a.ft_cnt[r0 + p + kTileSlots];
+                off_n = a.ft_off[r0 + p + kTileSlots];
+            }
+            const size_t me = (size_t)(r0 + lr) * ld + col;
+            const P2 wv = *reinterpret_cast<const P2 *>(w + me);
+            P2 uv;
+            uv.x = (S)0;
+            uv.y = (S)0;
+            if (u) uv = *reinterpret_cast<const P2 *>(u + me);
+            // entries in 16-byte groups: local (plus then minus), then far
+            // (plus then minus) from the next group boundary; at most
+            // kTileLocalGroups local groups and kTileFar far entries per
+            // row (checked when the tables are built)
+            const uint32_t nlp = cnt & 255u, nl = nlp + ((cnt >> 8) & 255u);
+            const uint32_t nfp = (cnt >> 16) & 255u, nf = nfp + (cnt >> 24);
+            // local entries are 16-bit (eight per group), far ones 32-bit
+            const uint32_t ngl = (nl + 7) >> 3, ngf = (nf + 3) >> 2;
+            uint4 fe[kTileFar / 4], le[kTileLocalGroups];
+#pragma unroll
+            for (int g = 0; g < kTileFar / 4; ++g) {
+                fe[g] = make_uint4(0u, 0u, 0u, 0u);
+                if ((uint32_t)g < ngf) fe[g] = ent4[g0 + ngl + g];
+            }
+#pragma unroll
+            for (int g = 0; g < kTileLocalGroups; ++g) {
+                le[g] = make_uint4(0u, 0u, 0u, 0u);
+                if ((uint32_t)g < ngl) le[g] = ent4[g0 + g];
+            }
+            S p0v = (S)0, p1v = (S)0, m0v = (S)0, m1v = (S)0;
+            // far gathers in batches of eight, the first batch in flight
+            // while the local reads run
+            auto far_batch = [&](auto b0_c, P2 (&fx)[8]) {
+                constexpr int b0 = decltype(b0_c)::value;
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    if (b0 + t >= kTileFar) break;
+                    const uint4 g4 = fe[(b0 + t) >> 2];
+                    const uint32_t e = ((b0 + t) & 3) == 0 ? g4.x : ((b0 + t) & 3) == 1 ? g4.y
+                                     : ((b0 + t) & 3) == 2 ? g4.z : g4.w;
+                    fx[t].x = (S)0;
+                    fx[t].y = (S)0;
+                    if ((uint32_t)(b0 + t) < nf) fx[t] = *reinterpret_cast<const P2 *>(v + (size_t)e * ld + col);
+                }
+            };
+            auto far_sum = [&](auto b0_c, const P2 (&fx)[8]) {
+                constexpr int b0 = decltype(b0_c)::value;
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    if (b0 + t >= kTileFar) break;
+                    if ((uint32_t)(b0 + t) < nfp) {
+                        p0v += fx[t].x;
+                        p1v += fx[t].y;
+                    } else if ((uint32_t)(b0 + t) < nf) {
+                        m0v += fx[t].x;
+                        m1v += fx[t].y;
+                    }
+                }
+            };
+            P2 fx[8];
+            far_batch(std::integral_constant<int, 0>{}, fx);
+#pragma unroll
+            for (int g = 0; g < kTileLocalGroups; ++g) {
+                const uint32_t e4[4] = {le[g].x, le[g].y, le[g].z, le[g].w};
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const uint32_t k = 8u * g + t;
+                    if (k < nl) {
+                        const S *tp = tile + ((e4[t >> 1] >> (16 * (t & 1))) & 0xFFFFu) * RS + 2 * l8;
+                        if (k < nlp) {
+                            p0v += tp[0];
+                            p1v += tp[1];
+                        } else {
+                            m0v += tp[0];
+                            m1v += tp[1];
+                        }
+                    }
+                }
+            }
+            far_sum(std::integral_constant<int, 0>{}, fx);
+            if (nf > 8) {
+                far_batch(std::integral_constant<int, 8>{}, fx);
+                far_sum(std::integral_constant<int, 8>{}, fx);
+            }
+            const S raw0 = wv.x + nt0 * (p0v - m0v), raw1 = wv.y + nt0 * (p1v - m1v);
+            S o0 = c1s * raw0 + c2s * uv.x, o1 = c1s * raw1 + c2s * uv.y;
+            if (!u) {
+                o0 = c1s * raw0;
+                o1 = c1s * raw1;
+            }
+            P2 ov;
+            ov.x = o0;
+            ov.y = o1;
+            *reinterpret_cast<P2 *>(w + me) = ov;
+            if constexpr (DOTS) {
+                const S *tp = tile + lr * RS + 2 * l8;
+                const double x0 = a.dot_raw ? (double)raw0 : (double)o0;
+                const double x1 = a.dot_raw ? (double)raw1 : (double)o1;
+                dv += (double)tp[0] * x0 + (double)tp[1] * x1;
+                dd += x0 * x0 + x1 * x1;
+            }
+        }
+        if constexpr (DOTS) {
+            double vals[2] = {dv, dd};
+            block_sum<2>(vals, sh_red);
+            if (tid == 0) {
+                const size_t sl = (size_t)slab * nb + blk;
+                a.red.partial[2 * sl] = vals[0];
+                a.red.partial[2 * sl + 1] = vals[1];
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        *s_last = (atomicAdd(&a.sched[8], 1u) == gridDim.x - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!*s_last) return;
+    __threadfence();
+    if constexpr (DOTS) {
+        const size_t nitems = (size_t)a.nslab * nb;
+        for (int j = 0; j < 2; ++j) {
+            double sum = 0.0;
+            for (size_t it = tid; it < nitems; it += blockDim.x)
+                sum += __builtin_nontemporal_load(&a.red.partial[it * 2 + j]);
+            double vv[1] = {sum};
+            block_sum<1>(vv, sh_red);
+            if (tid == 0) a.red.result[j] = vv[0];
+        }
+    }
+    if (tid == 0) {
+        for (int i = 0; i < 8; ++i) a.sched[i] = 0u;
+        a.sched[8] = 0u;
+        __threadfence();
+    }
+}
 
 // Columns kernel, group tiles (one real vector, two columns per lane). A work
 // item is (slab of 64 columns, group of up rows sharing their high half, at
@@ -2007,6 +2257,16 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
     // assume the row at LDS address 0: no static LDS in those kernels.
     const bool fc_rows = rmode == 6 && NV == 1 && h->hub.fc_ok && fc_kernels_lds0<S>();
     a.fc_ent = fc_rows ? h->hub.fc_ent[sizeof(S) == 8 ? 1 : 0].as<uint32_t>() : nullptr;
+    const bool rows_fp_fc = fc_rows && fast && fm_bytes <= 160 * 1024 && h->basis->n_sites <= 16 &&
+                            a.ddn <= 16 * (int64_t)threads;
+    const bool rows_fp = fast && rmode >= 5 && h->hub.fb_ok && fm_bytes <= 160 * 1024 && h->basis->n_sites <= 16 &&
+                         a.ddn * NV <= 16 * (int64_t)threads;
+    // the T_up tile kernel (hub_sweep 7)
+    const size_t tile_bytes = (size_t)h->hub.ft_max_rows * tile_row_stride<S>() * sizeof(S);
+    const bool tile = h->sched_cfg.hub_sweep == 7 && NV == 1 && fast_cols && !a.coef_cplx && !a.acc_out &&
+                      h->hub.ft_ok && a.ddn % 2 == 0 && a.ld % 2 == 0 && tile_bytes + kTileTailBytes <= 160 * 1024;
+    if (a.ld != a.ddn && !(NV == 1 && tile && (a.lz_q || rows_fp_fc || rows_fp)))
+        return fail(HPHI_ERR_UNSUPPORTED, "padded rows need the tile T_up kernel and the batched rows kernels");
     if (a.lz_q) {
         // fused Lanczos update: only where hub_rows_fused_ok holds
         if constexpr (NV == 1) {
@@ -2035,13 +2295,11 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
             hipLaunchKernelGGL((k_hub_rows_fl<S, NV, 13>), dim3((unsigned)std::min<int64_t>(ncu, a.dup)),
                                dim3(threads), fl_bytes, st, a);
         }
-    } else if (fc_rows && fast && fm_bytes <= 160 * 1024 && h->basis->n_sites <= 16 &&
-               a.ddn <= 16 * (int64_t)threads) {
+    } else if (rows_fp_fc) {
         hipFuncSetAttribute((const void *)k_hub_rows_fp<S, 1, 16, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)fm_bytes);
         hipLaunchKernelGGL((k_hub_rows_fp<S, 1, 16, true>), dim3((unsigned)grid_r), dim3(threads), fm_bytes, st, a);
-    } else if (fast && rmode >= 5 && h->hub.fb_ok && fm_bytes <= 160 * 1024 && h->basis->n_sites <= 16 &&
-        a.ddn * NV <= 16 * (int64_t)threads) {
+    } else if (rows_fp) {
         hipFuncSetAttribute((const void *)k_hub_rows_fp<S, NV, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)fm_bytes);
         hipLaunchKernelGGL((k_hub_rows_fp<S, NV, 16>), dim3((unsigned)grid_r), dim3(threads), fm_bytes, st, a);
@@ -2079,6 +2337,35 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
     // column kernel, geometry from the Hamiltonian's schedule
     const int cw = h->sched_cfg.hub_slab_cols;
     const int groups = h->sched_cfg.hub_groups;
+    if (tile) {
+        if constexpr (NV == 1) {
+            a.ft_blk = h->hub.ft_blk.as<uint32_t>();
+            a.ft_pos = h->hub.ft_pos.as<uint32_t>();
+            a.ft_off = h->hub.ft_off.as<uint32_t>();
+            a.ft_cnt = h->hub.ft_cnt.as<uint32_t>();
+            a.ft_ent = h->hub.ft_ent.as<uint32_t>();
+            a.ft_nb = h->hub.ft_nb;
+            a.ft_tile_bytes = (uint32_t)((tile_bytes + 15) & ~(size_t)15);
+            a.nslab = (int)((a.ddn + kTileCols - 1) / kTileCols);
+            const int64_t nitems = (int64_t)a.nslab * a.ft_nb;
+            if (a.nd && nitems * 2 > (int64_t)kReduceSlots)
+                return fail(HPHI_ERR_UNSUPPORTED, "Hubbard tile items beyond the reduction scratch");
+            a.sched = h->sched.as<unsigned>();
+            const size_t lds = a.ft_tile_bytes + kTileTailBytes;
+            // as many 1024-thread workgroups per CU as the LDS holds (at
+            // most two: registers), spread over every XCD
+            const int per_cu = std::max(1, std::min(2, (int)((160 * 1024) / lds)));
+            const int grid_t = 8 * std::max(1, std::min(groups, per_cu * ncu / 8));
+            auto go = [&](auto kern) {
+                hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                hipLaunchKernelGGL(kern, dim3(grid_t), dim3(1024), lds, st, a);
+            };
+            if (a.nd) go(k_hub_up_tile<S, true>);
+            else go(k_hub_up_tile<S, false>);
+            HPHI_HIP(hipGetLastError());
+            return HPHI_OK;
+        }
+    }
     if (fast_cols && h->sched_cfg.hub_sweep == 2 && !a.coef_cplx) {
         // persistent sweep: hub_groups row ranges, each within the staging arrays
         int64_t rows = (a.dup + groups - 1) / groups;
@@ -2168,7 +2455,8 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
     a.groups = groups;
     // hub_sweep 3 and 5: two adjacent columns per lane (even row length
     // only); 5 also walks each row's lists in batches (one wave per row)
-    const int sw = h->sched_cfg.hub_sweep;
+    // hub_sweep 7 where the tile kernel does not apply runs as 5
+    const int sw = h->sched_cfg.hub_sweep == 7 ? 5 : h->sched_cfg.hub_sweep;
     a.row_cols = ((sw == 3 || sw == 5) && NV == 1 && a.ddn % 2 == 0) ? 2 : 1;
     a.hb = (sw == 5 && (uint64_t)a.dup * (uint64_t)a.ddn * NV * sizeof(S) <= kColsOob) ? 1 : 0;
     // 128-column slabs only with two columns per lane (one wave per row)
@@ -2198,6 +2486,24 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
     }
     HPHI_HIP(hipGetLastError());
     return HPHI_OK;
+}
+
+int64_t hub_lanczos_pitch(hphi_ham *h, int dtype)
+{
+    const int64_t ddn = h->basis->sp[1].dim, dup = h->basis->sp[0].dim;
+    if (h->kind != 1 || h->sched_cfg.hub_sweep != 7 || !h->hub.ft_ok || ddn % 2) return ddn;
+    if ((dtype != HPHI_F64 && dtype != HPHI_F32) || !hub_rows_fused_ok(h, 1)) return ddn;
+    const size_t esz = dtype_is_f32(dtype) ? 4 : 8;
+    const int64_t line = (int64_t)(128 / esz);
+    const int64_t ld = (ddn + line - 1) / line * line;
+    // the rows kernels' raw buffer offsets stay 32-bit
+    if ((unsigned __int128)dup * ld * esz >= ((unsigned __int128)1 << 32)) return ddn;
+    const size_t tile_bytes = (size_t)h->hub.ft_max_rows * (esz == 8 ? tile_row_stride<double>() * 8 : tile_row_stride<float>() * 4);
+    if (tile_bytes + kTileTailBytes > 160 * 1024) return ddn;
+    // the first product's rows kernel must take the pitch too
+    const size_t fm_bytes = (size_t)(ddn + 1) * esz + 8 * (size_t)((ddn + 63) / 64) + 2 * (size_t)ddn + 16;
+    if (fm_bytes > 160 * 1024 || ddn > 16 * 1024) return ddn;
+    return ld;
 }
 
 int launch_hub_mult(hphi_ham *h, const MultArgs &m)
@@ -2244,6 +2550,8 @@ int launch_hub_mult(hphi_ham *h, const MultArgs &m)
     a.lz_q = m.lz_q;
     a.lz_red = m.lz_red;
     a.ev_mid = m.ev_mid;
+    a.ld = m.ld > 0 ? m.ld : a.ddn;
+    if (a.ld < a.ddn) return fail(HPHI_ERR_INVALID_ARG, "row pitch %lld below the row length", (long long)a.ld);
     const int nv = m.nvec * dtype_lanes(m.dtype);
     const bool f32 = dtype_is_f32(m.dtype);
     if (nv == 1) return f32 ? launch_hub_t<float, 1>(h, a, m.stream) : launch_hub_t<double, 1>(h, a, m.stream);

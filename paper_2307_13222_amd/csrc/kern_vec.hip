@@ -57,6 +57,52 @@ int launch_rng_uniform(int dtype, void *out, int64_t n, uint64_t seed, hipStream
     return HPHI_OK;
 }
 
+// The uniform stream laid out in rows of `cols` elements at pitch `ld`:
+// element (r, c) is stream element r * cols + c; the padding is zero.
+template <typename S>
+__global__ void k_rng_uniform_pitched(S *out, int64_t rows, int64_t cols, int64_t ld, uint64_t seed)
+{
+    const int64_t n = rows * ld;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = t / ld, c = t - r * ld;
+        out[t] = c < cols ? (S)(u53(splitmix64_at(seed, (uint64_t)(r * cols + c))) - 0.5) : (S)0;
+    }
+}
+
+int launch_rng_uniform_pitched(int dtype, void *out, int64_t rows, int64_t cols, int64_t ld, uint64_t seed,
+                               hipStream_t st)
+{
+    int g = grid_for(rows * ld);
+    if (dtype_is_f32(dtype))
+        hipLaunchKernelGGL(k_rng_uniform_pitched<float>, dim3(g), dim3(kBlock), 0, st, (float *)out, rows, cols, ld, seed);
+    else
+        hipLaunchKernelGGL(k_rng_uniform_pitched<double>, dim3(g), dim3(kBlock), 0, st, (double *)out, rows, cols, ld,
+                           seed);
+    HPHI_HIP(hipGetLastError());
+    return HPHI_OK;
+}
+
+// |x|^2 of a vector stored in rows of `cols` elements at pitch ld, summed in
+// the order k_dots uses for the same vector unpadded (same grid, same
+// element-to-thread assignment), so padded and unpadded runs agree bit for bit.
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_norm2_pitched(const S *x, int64_t dim, int64_t cols, int64_t ld, Reduce red)
+{
+    __shared__ double sh[kBlock / kWave * 64];
+    __shared__ double blk[64];
+    double acc[1] = {0.0};
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < dim;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const double a = (double)x[(r / cols) * ld + r % cols];
+        acc[0] += a * a;
+    }
+    block_sum<1>(acc, sh);
+    if (threadIdx.x == 0) blk[0] = acc[0];
+    __syncthreads();
+    grid_finish(blk, 1, red, sh);
+}
+
 int launch_rng_cgauss(int dtype, void *out, int64_t dim, int nvec, uint64_t seed, hipStream_t st)
 {
     int g = grid_for(dim * nvec);
@@ -111,6 +157,17 @@ int launch_dots(int dtype, int nlanes, int64_t rows, const void *x, const void *
 {
     if (dtype_is_f32(dtype)) return dots_t<float>(nlanes, rows, x, y, red, mode, st);
     return dots_t<double>(nlanes, rows, x, y, red, mode, st);
+}
+
+int launch_norm2_pitched(int dtype, const void *x, int64_t dim, int64_t cols, int64_t ld, Reduce red, hipStream_t st)
+{
+    int g = grid_for(dim, 2);
+    if (dtype_is_f32(dtype))
+        hipLaunchKernelGGL(k_norm2_pitched<float>, dim3(g), dim3(kBlock), 0, st, (const float *)x, dim, cols, ld, red);
+    else
+        hipLaunchKernelGGL(k_norm2_pitched<double>, dim3(g), dim3(kBlock), 0, st, (const double *)x, dim, cols, ld, red);
+    HPHI_HIP(hipGetLastError());
+    return HPHI_OK;
 }
 
 // Per-lane x.y and y.y over flat [rows][NL] arrays: thread t always sees
@@ -331,25 +388,30 @@ int launch_lz_update(int dtype, LzDev *lz, double *alpha, double *beta, int64_t 
 // Second pass: psi += svec[k] * s_k * q_k (k = lz->iter before the update).
 // psi += svec[k] s_k q_k; psi may be kept wider than q (P = double with
 // FP32 storage: the Ritz vector of a refined solve).
+// q may be stored in rows of `cols` elements at pitch ld (psi is not).
 template <typename P, typename S>
-__global__ void k_lz_psi(LzDev *lz, const double *svec, int64_t dim, P *psi, const S *qk)
+__global__ void k_lz_psi(LzDev *lz, const double *svec, int64_t dim, P *psi, const S *qk, int64_t cols,
+                         int64_t ld)
 {
     if (lz->done) return;
     const double c = svec[lz->iter] * lz->s_cur;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < dim;
-         r += (int64_t)gridDim.x * blockDim.x)
-        psi[r] = (P)((double)psi[r] + c * (double)qk[r]);
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t qr = ld == cols ? r : (r / cols) * ld + r % cols;
+        psi[r] = (P)((double)psi[r] + c * (double)qk[qr]);
+    }
 }
 
 int launch_lz_psi_accum(int psi_dtype, int dtype, LzDev *lz, const double *svec, int64_t dim, void *psi,
-                        const void *qk, hipStream_t st)
+                        const void *qk, hipStream_t st, int64_t cols, int64_t ld)
 {
     int g = grid_for(dim);
+    if (cols <= 0) cols = ld = dim;
     const bool pf = dtype_is_f32(psi_dtype), qf = dtype_is_f32(dtype);
     if (pf && !qf) return fail(HPHI_ERR_INVALID_ARG, "Ritz vector narrower than the Krylov vectors");
-    if (pf) hipLaunchKernelGGL((k_lz_psi<float, float>), dim3(g), dim3(kBlock), 0, st, lz, svec, dim, (float *)psi, (const float *)qk);
-    else if (qf) hipLaunchKernelGGL((k_lz_psi<double, float>), dim3(g), dim3(kBlock), 0, st, lz, svec, dim, (double *)psi, (const float *)qk);
-    else hipLaunchKernelGGL((k_lz_psi<double, double>), dim3(g), dim3(kBlock), 0, st, lz, svec, dim, (double *)psi, (const double *)qk);
+    if (pf) hipLaunchKernelGGL((k_lz_psi<float, float>), dim3(g), dim3(kBlock), 0, st, lz, svec, dim, (float *)psi, (const float *)qk, cols, ld);
+    else if (qf) hipLaunchKernelGGL((k_lz_psi<double, float>), dim3(g), dim3(kBlock), 0, st, lz, svec, dim, (double *)psi, (const float *)qk, cols, ld);
+    else hipLaunchKernelGGL((k_lz_psi<double, double>), dim3(g), dim3(kBlock), 0, st, lz, svec, dim, (double *)psi, (const double *)qk, cols, ld);
     HPHI_HIP(hipGetLastError());
     return HPHI_OK;
 }

@@ -317,7 +317,7 @@ def test_hubbard_schedules_bit_identical(api, ctx):
     h = api.Hamiltonian.hubbard(b, m)
     v = dev(W.random_vector(b.dim, 4))
     ref = None
-    for sch in [dict(hub_slab_cols=16, hub_groups=128, hub_item_rows=64, hub_row_cols=1),
+    for sch in [dict(hub_slab_cols=16, hub_groups=128, hub_item_rows=64, hub_row_cols=1, hub_sweep=5),
                 dict(hub_slab_cols=8, hub_groups=64, hub_item_rows=32, hub_row_cols=2),
                 dict(hub_slab_cols=32, hub_groups=256, hub_item_rows=128, hub_row_cols=3),
                 dict(hub_slab_cols=64, hub_groups=1, hub_item_rows=8, hub_row_cols=1),
@@ -351,7 +351,13 @@ def test_hubbard_schedules_bit_identical(api, ctx):
                 dict(hub_slab_cols=16, hub_groups=64, hub_item_rows=32, hub_row_cols=6, hub_sweep=1),
                 # batched walk with several rows per wave (16 and 32 columns)
                 dict(hub_slab_cols=16, hub_groups=64, hub_item_rows=32, hub_row_cols=6, hub_sweep=5),
-                dict(hub_slab_cols=32, hub_groups=7, hub_item_rows=16, hub_row_cols=5, hub_sweep=5, hub_row_order=2)]:
+                dict(hub_slab_cols=32, hub_groups=7, hub_item_rows=16, hub_row_cols=5, hub_sweep=5, hub_row_order=2),
+                # block tiles of the up rows (local hops from LDS): automatic
+                # split, three-site blocks, one workgroup per XCD, four-site blocks
+                dict(hub_slab_cols=128, hub_groups=128, hub_item_rows=16, hub_row_cols=6, hub_sweep=7),
+                dict(hub_slab_cols=128, hub_groups=32, hub_item_rows=16, hub_row_cols=5, hub_sweep=7, hub_tile_bits=3),
+                dict(hub_slab_cols=128, hub_groups=1, hub_item_rows=16, hub_row_cols=6, hub_sweep=7, hub_tile_bits=2),
+                dict(hub_slab_cols=128, hub_groups=32, hub_item_rows=16, hub_row_cols=6, hub_sweep=7, hub_tile_bits=4)]:
         h.set_schedule(**sch)
         assert h.get_schedule()["hub_slab_cols"] == sch["hub_slab_cols"]
         w = host(h.mult(v))
@@ -360,7 +366,7 @@ def test_hubbard_schedules_bit_identical(api, ctx):
             ups, dns = O.hubbard_basis(12, 6, 5)
             wo = O.hubbard_hv(m, ups, dns, host(v))
             assert relmax(w, wo) < 1e-12
-        if sch["hub_row_cols"] >= 4 or sch.get("hub_sweep") == 4:
+        if sch["hub_row_cols"] >= 4 or sch.get("hub_sweep") in (4, 7):
             # hop-ordered down slots / group tiles: another summation order
             assert relmax(w, ref) < 1e-12 and relmax(w, wo) < 1e-12, sch
         else:
@@ -368,7 +374,7 @@ def test_hubbard_schedules_bit_identical(api, ctx):
     with pytest.raises(api.HphiError):
         h.set_schedule(hub_slab_cols=12)
     with pytest.raises(api.HphiError):
-        h.set_schedule(hub_sweep=7)
+        h.set_schedule(hub_sweep=8)
     with pytest.raises(api.HphiError):
         h.set_schedule(hub_row_order=3)
     h.set_schedule(hub_row_order=1)
