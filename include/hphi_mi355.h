@@ -293,8 +293,12 @@ typedef struct {
                               vector by a second pass accumulated in FP64,
                               normalize it in FP64 and take its Rayleigh
                               quotient and residual with an FP64 product;
-                              energies[0] is then that Rayleigh quotient
-                              (see hphi_lanczos_info)                        */
+                              then run refine_steps FP64 Lanczos steps from
+                              that vector; energies[0] is the lowest Ritz
+                              value of that short run (the Rayleigh quotient
+                              itself with refine_steps < 0; see
+                              hphi_lanczos_info)                             */
+    int refine_steps;      /* FP64 steps of the refinement (0: 16)           */
 } hphi_lanczos_opts;
 
 typedef struct {
@@ -323,6 +327,10 @@ typedef struct {
                               of rho by the bound of Temple when theta_2
                               does not exceed the second eigenvalue by much
                               (an estimate, not a bound)                    */
+    double polish_e0;      /* lowest Ritz value of the FP64 steps from psi
+                              (below rho: the Krylov space holds psi); NaN
+                              without them                                  */
+    double polish_resid;   /* its residual estimate beta_m |s_m| (FP64)      */
 } hphi_lanczos_info;
 
 /* Lanczos ground state (Sec. 1): v_0 = r/|r|; w = H v_k - beta_k v_{k-1};
@@ -333,8 +341,10 @@ typedef struct {
  * values' accuracy by about 1e-7 |H|; opts->refine = 1 adds the FP64
  * Rayleigh quotient of the Ritz vector (its error is quadratic in the
  * vector's) and its residual, which bound the result's error without an
- * FP64 run. The refinement needs two FP64 vectors of workspace and a
- * second pass. Synchronous.
+ * FP64 run, then a few FP64 Lanczos steps from that vector (a restart in
+ * FP64: its Krylov space holds the vector, so its lowest Ritz value lies
+ * at or below the Rayleigh quotient). The refinement needs a second pass
+ * and five FP64 vectors of workspace. Synchronous.
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE, BUSY. */
 int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *opts, double *energies,
                  int n_energies, hphi_lanczos_info *info);
@@ -343,14 +353,15 @@ int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *opts, double *energies,
  * stream is captured into a graph, tight serving loops, harnesses that
  * forbid hipMalloc): hphi_lanczos with every device buffer (the three
  * Krylov vectors, the device scalars, the T_k coefficients, the Ritz
- * coefficients of the second pass and, with refine, the two FP64 vectors of
- * the refinement) taken from a static device array of
+ * coefficients of the second pass and, with refine, the five FP64 vectors
+ * of the refinement) taken from a static device array of
  * HPHI_NOALLOC_SCRATCH_BYTES that the library holds on each device from
  * hphi_init to the end of the process, instead of allocated per call. The
  * caller still passes the outputs (host arrays, psi_dev). Each buffer is
  * rounded up to 256 bytes; the call needs
  *   3 * S(dim * elem) + S(128) + S(8 * (2 * max_iter + 4)) + S(8 * max_iter)
- *   + (refine ? 2 * S(8 * dim) : 0)  bytes,  S(n) = n rounded up to 256,
+ *   + (refine ? 5 * S(8 * dim) + S(128) + S(8 * (2 * r + 4)) : 0)  bytes,
+ * S(n) = n rounded up to 256, r = refine_steps (16 when 0),
  * elem = 8 (F64) or 4 (F32): FP64 solves up to about 2.79e6 states (a
  * 24-site chain at Sz = 0). The library clears what must start at zero on
  * each call. Every call on a device shares that device's array: a call

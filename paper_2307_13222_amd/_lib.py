@@ -28,7 +28,8 @@ class LanczosOpts(C.Structure):
                 ("resid_tol", C.c_double), ("seed", C.c_uint64), ("v0_dev", C.c_void_p), ("storage", C.c_int),
                 ("stream", C.c_void_p), ("alpha_out", C.POINTER(C.c_double)),
                 ("beta_out", C.POINTER(C.c_double)), ("psi_dev", C.c_void_p),
-                ("use_graph", C.c_int), ("time_kernels", C.c_int), ("refine", C.c_int)]
+                ("use_graph", C.c_int), ("time_kernels", C.c_int), ("refine", C.c_int),
+                ("refine_steps", C.c_int)]
 
 
 class LanczosInfo(C.Structure):
@@ -36,7 +37,7 @@ class LanczosInfo(C.Structure):
                 ("seconds", C.c_double), ("hv_seconds", C.c_double), ("hv_calls", C.c_int),
                 ("fused_update", C.c_int), ("hv_second_kernel_seconds", C.c_double),
                 ("ritz_e0", C.c_double), ("rq_e0", C.c_double), ("residual", C.c_double),
-                ("err_est", C.c_double)]
+                ("err_est", C.c_double), ("polish_e0", C.c_double), ("polish_resid", C.c_double)]
 
 
 class BatchItem(C.Structure):

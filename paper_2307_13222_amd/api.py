@@ -205,10 +205,13 @@ class Hamiltonian:
 def lanczos(ham: Hamiltonian, max_iter: int, seed: int = 1, v0=None, storage: str = "f64",
             n_energies: int = 1, want_vector: bool = False, use_graph: bool = False,
             check_every: int = 0, tol: float = 1e-12, time_kernels: bool = False,
-            refine: bool = False, resid_tol: float = 0.0, no_alloc: bool = False, stream=None) -> Dict:
+            refine: bool = False, resid_tol: float = 0.0, no_alloc: bool = False, refine_steps: int = 0,
+            stream=None) -> Dict:
     """Lanczos ground state. refine: FP64 Rayleigh quotient of the Ritz
     vector (second pass accumulated in FP64), returned as energies[0] with
-    its residual |H psi - rho psi| and error estimate. no_alloc: the entry
+    its residual |H psi - rho psi| and error estimate, then refine_steps
+    (0: 16; < 0: none) FP64 Lanczos steps from that vector, whose lowest
+    Ritz value becomes energies[0] (polish_e0). no_alloc: the entry
     point that takes its device buffers from the library's static scratch
     (hphi_lanczos_noalloc) instead of allocating them."""
     torch = _torch()
@@ -234,6 +237,7 @@ def lanczos(ham: Hamiltonian, max_iter: int, seed: int = 1, v0=None, storage: st
     o.use_graph = 1 if use_graph else 0
     o.time_kernels = 1 if time_kernels else 0
     o.refine = 1 if refine else 0
+    o.refine_steps = refine_steps
     e = np.zeros(n_energies)
     info = L.LanczosInfo()
     fn = L.lib().hphi_lanczos_noalloc if no_alloc else L.lib().hphi_lanczos
@@ -246,7 +250,7 @@ def lanczos(ham: Hamiltonian, max_iter: int, seed: int = 1, v0=None, storage: st
             "fused_update": bool(info.fused_update),
             "hv_second_kernel_seconds": info.hv_second_kernel_seconds, "psi": psi,
             "ritz_e0": info.ritz_e0, "rq_e0": info.rq_e0, "residual": info.residual,
-            "err_est": info.err_est}
+            "err_est": info.err_est, "polish_e0": info.polish_e0, "polish_resid": info.polish_resid}
 
 
 def lanczos_batch(hams: Sequence[Hamiltonian], max_iter, seeds, keep_coefficients: bool = False,

@@ -1162,6 +1162,7 @@ static int lanczos_impl(hphi_ham *h, const hphi_lanczos_opts *o, double *energie
     if (n_energies < 0 || n_energies > o->max_iter) return fail(HPHI_ERR_INVALID_ARG, "n_energies %d", n_energies);
     if (o->check_every < 0) return fail(HPHI_ERR_INVALID_ARG, "check_every < 0");
     if (o->refine != 0 && o->refine != 1) return fail(HPHI_ERR_INVALID_ARG, "refine %d", o->refine);
+    if (o->refine_steps > 1000) return fail(HPHI_ERR_INVALID_ARG, "refine_steps %d", o->refine_steps);
     if (o->resid_tol < 0.0 || !std::isfinite(o->resid_tol)) return fail(HPHI_ERR_INVALID_ARG, "resid_tol");
     DeviceGuard g(h->basis->ctx->device);
     HPHI_USE_HAM(h, o->stream);
@@ -1205,7 +1206,7 @@ static int lanczos_impl(hphi_ham *h, const hphi_lanczos_opts *o, double *energie
     int hv_n = 0;
     if (L.timing) HPHI_TRY(L.timed(&hv_s, &hv_n, &hv_k2));
     L.timing = false;
-    double ritz_e0 = NAN, rq_e0 = NAN, resid = NAN, err_est = NAN;
+    double ritz_e0 = NAN, rq_e0 = NAN, resid = NAN, err_est = NAN, polish_e0 = NAN, polish_resid = NAN;
     if ((o->psi_dev || o->refine) && n > 0) {
         // second pass: same start vector and kernels, psi = sum_k s_k v_k;
         // with refine the sum is kept in FP64 whatever the storage type
@@ -1271,6 +1272,36 @@ static int lanczos_impl(hphi_ham *h, const hphi_lanczos_opts *o, double *energie
             if (std::isfinite(th2) && th2 > rq_e0) err_est = r2 / (th2 - rq_e0);
             if (n_energies > 0) energies[0] = rq_e0;
             if (o->psi_dev) HPHI_TRY(launch_copy_cast(L.dt, o->psi_dev, HPHI_F64, psi, L.dim, st));
+            // FP64 restart from psi: a few Lanczos steps whose Krylov space
+            // holds psi, so the lowest Ritz value is at most rho
+            const int rs = o->refine_steps == 0 ? 16 : o->refine_steps;
+            if (rs > 0) {
+                LanczosRun P;
+                P.h = h;
+                P.dt = HPHI_F64;
+                P.dim = L.dim;
+                P.st = st;
+                HPHI_TRY(P.setup(rs, ws));
+                hphi_lanczos_opts po = *o;
+                po.v0_dev = psi;
+                po.storage = HPHI_F64;
+                HPHI_TRY(P.start(&po));
+                std::vector<double> dum;
+                int cvp = 0;
+                HPHI_TRY(P.run(rs, false, nullptr, nullptr, 0, 0.0, 1, &cvp, dum));
+                LzDev hp;
+                HPHI_HIP(hipMemcpyAsync(&hp, P.lz, sizeof(LzDev), hipMemcpyDeviceToHost, st));
+                HPHI_HIP(hipStreamSynchronize(st));
+                const int np = hp.iter;
+                if (np > 0) {
+                    std::vector<double> pa(np), pb(np + 1), ps(np);
+                    HPHI_HIP(hipMemcpy(pa.data(), P.alpha, sizeof(double) * np, hipMemcpyDeviceToHost));
+                    HPHI_HIP(hipMemcpy(pb.data(), P.beta, sizeof(double) * (np + 1), hipMemcpyDeviceToHost));
+                    HPHI_TRY(tridiag_lowest(pa.data(), pb.data(), np, 1, &polish_e0, ps.data()));
+                    polish_resid = pb[np] * std::fabs(ps[np - 1]);
+                    if (n_energies > 0) energies[0] = polish_e0;
+                }
+            }
         }
         HPHI_HIP(hipStreamSynchronize(st));
     }
@@ -1287,6 +1318,8 @@ static int lanczos_impl(hphi_ham *h, const hphi_lanczos_opts *o, double *energie
         info->rq_e0 = rq_e0;
         info->residual = resid;
         info->err_est = err_est;
+        info->polish_e0 = polish_e0;
+        info->polish_resid = polish_resid;
     }
     return HPHI_OK;
 }
@@ -1301,12 +1334,18 @@ int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *o, double *energies, int 
 } // extern "C"
 
 // Device bytes hphi_lanczos_noalloc carves from the static scratch.
-static size_t noalloc_bytes(int64_t dim, int storage, int max_iter, int refine)
+static size_t noalloc_bytes(int64_t dim, int storage, int max_iter, int refine, int refine_steps)
 {
     const size_t vb = (size_t)dim * (storage == HPHI_F32 ? 4 : 8);
     size_t n = 3 * Carve::up(vb) + Carve::up(sizeof(LzDev)) + Carve::up(sizeof(double) * (2 * (size_t)max_iter + 4)) +
                Carve::up(sizeof(double) * (size_t)max_iter);
-    if (refine) n += 2 * Carve::up((size_t)dim * sizeof(double));
+    if (refine) {
+        const int rs = refine_steps == 0 ? 16 : refine_steps;
+        n += 2 * Carve::up((size_t)dim * sizeof(double));
+        if (rs > 0)
+            n += 3 * Carve::up((size_t)dim * sizeof(double)) + Carve::up(sizeof(LzDev)) +
+                 Carve::up(sizeof(double) * (2 * (size_t)rs + 4));
+    }
     return n;
 }
 
@@ -1323,7 +1362,7 @@ int hphi_lanczos_noalloc(hphi_ham *h, const hphi_lanczos_opts *o, double *energi
     if (o->max_iter < 1 || o->max_iter > 100000) return fail(HPHI_ERR_INVALID_ARG, "max_iter %d", o->max_iter);
     if (o->storage != HPHI_F64 && o->storage != HPHI_F32)
         return fail(HPHI_ERR_INVALID_ARG, "Lanczos storage must be F64 or F32");
-    const size_t need = noalloc_bytes(h->basis->dim, o->storage, o->max_iter, o->refine);
+    const size_t need = noalloc_bytes(h->basis->dim, o->storage, o->max_iter, o->refine, o->refine_steps);
     if (need > kNoAllocScratchBytes)
         return fail(HPHI_ERR_INVALID_ARG,
                     "hphi_lanczos_noalloc: %zu bytes of workspace needed (dim %lld), the static scratch holds %zu",

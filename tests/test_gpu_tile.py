@@ -153,7 +153,7 @@ def test_tile_lanczos_padded_vs_oracle(api, ctx):
     assert abs(rr["rq_e0"] - e_or) < 1e-10 and rr["residual"] < 1e-6
     # FP32 vectors: padded to 32 floats per line
     rf = api.lanczos(h, 250, seed=3, storage="f32", refine=True)
-    assert abs(rf["rq_e0"] - e_or) < 1e-8
+    assert abs(rf["energies"][0] - e_or) < 1e-9
     # the static-scratch entry point keeps unpadded rows; every sum runs in
     # the same order (the start norm is taken in the unpadded order), so the
     # numbers are the same bit for bit

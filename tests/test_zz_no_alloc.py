@@ -64,6 +64,7 @@ def test_noalloc_fp32_refined_and_hubbard(api, ctx):
     got = api.lanczos(h, 200, seed=1, storage="f32", refine=True, no_alloc=True)
     _same(ref, got)
     assert got["rq_e0"] == ref["rq_e0"] and got["residual"] == ref["residual"]
+    assert got["polish_e0"] == ref["polish_e0"] and got["polish_resid"] == ref["polish_resid"]
     hh = api.Hamiltonian.hubbard(api.Basis.hubbard(ctx, 10, 5, 5), W.hubbard_square(2, 5, 1.0, 4.0))
     ref = api.lanczos(hh, 150, seed=2)
     got = api.lanczos(hh, 150, seed=2, no_alloc=True)
