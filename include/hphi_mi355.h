@@ -426,6 +426,8 @@ typedef struct {
                               entries (Box-Muller on SplitMix64 outputs)     */
     const void *phi0_dev;  /* or a caller start block [dim][n_vec] complex   */
     void *stream;
+    int use_graph;         /* capture one step's launches in a hipGraph and
+                              replay it (the same numbers as without)        */
 } hphi_ctpq_opts;
 
 /* Canonical TPQ (Sec. 3.5.1): Phi_k = U_c(dtau)^k Phi_rand with
@@ -453,6 +455,8 @@ typedef struct {
     int n_steps;           /* steps: t_k = k dt, k = 0..n_steps               */
     hphi_dtype storage;    /* HPHI_C128 or HPHI_C64                          */
     void *stream;
+    int use_graph;         /* capture one step's launches in a hipGraph and
+                              replay it (the same numbers as without)        */
 } hphi_tevol_opts;
 
 /* Real-time evolution by the truncated Taylor series of Sec. 3.4:

@@ -49,12 +49,12 @@ class BatchItem(C.Structure):
 class CtpqOpts(C.Structure):
     _fields_ = [("n_vec", C.c_int), ("n_max", C.c_int), ("dtau", C.c_double),
                 ("k_steps", C.c_int), ("storage", C.c_int), ("seed", C.c_uint64),
-                ("phi0_dev", C.c_void_p), ("stream", C.c_void_p)]
+                ("phi0_dev", C.c_void_p), ("stream", C.c_void_p), ("use_graph", C.c_int)]
 
 
 class TevolOpts(C.Structure):
     _fields_ = [("n_vec", C.c_int), ("n_max", C.c_int), ("dt", C.c_double), ("n_steps", C.c_int),
-                ("storage", C.c_int), ("stream", C.c_void_p)]
+                ("storage", C.c_int), ("stream", C.c_void_p), ("use_graph", C.c_int)]
 
 
 class LobpcgOpts(C.Structure):

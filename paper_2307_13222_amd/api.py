@@ -298,10 +298,11 @@ def tridiag_lowest(alpha: np.ndarray, beta: np.ndarray, k: int = 1, want_vector:
 
 
 def ctpq(ham: Hamiltonian, n_vec: int, n_max: int, dtau: float, k_steps: int,
-         storage: str = "c128", seed: int = 1, phi0=None, stream=None) -> Dict:
+         storage: str = "c128", seed: int = 1, phi0=None, use_graph: bool = False, stream=None) -> Dict:
     torch = _torch()
     o = L.CtpqOpts()
     o.n_vec, o.n_max, o.dtau, o.k_steps, o.seed = n_vec, n_max, dtau, k_steps, seed
+    o.use_graph = 1 if use_graph else 0
     o.storage = L.C128 if storage == "c128" else L.C64
     tdt = torch.complex128 if storage == "c128" else torch.complex64
     if phi0 is not None:
@@ -320,7 +321,7 @@ def ctpq(ham: Hamiltonian, n_vec: int, n_max: int, dtau: float, k_steps: int,
 
 
 def time_evolve(ham: Hamiltonian, psi, n_steps: int, dt: float = 0.01, n_max: int = 10,
-                double_occupancy: bool = False, stream=None) -> Dict:
+                double_occupancy: bool = False, use_graph: bool = False, stream=None) -> Dict:
     """Real-time evolution of psi (device tensor [dim] or [dim, n_vec],
     complex128 or complex64, updated in place) by the truncated Taylor series;
     returns per recorded time norms, energies and (Hubbard) double occupancy."""
@@ -333,6 +334,7 @@ def time_evolve(ham: Hamiltonian, psi, n_steps: int, dt: float = 0.01, n_max: in
     o.n_vec, o.n_max, o.dt, o.n_steps = nv, n_max, dt, n_steps
     o.storage = L.C128 if psi.dtype == torch.complex128 else L.C64
     o.stream = _stream_ptr(stream)
+    o.use_graph = 1 if use_graph else 0
     nrm = np.zeros((n_steps + 1) * nv)
     en = np.zeros((n_steps + 1) * nv)
     dc = np.zeros(n_steps + 1) if double_occupancy else None

@@ -1,7 +1,8 @@
 """Autotuner for the H*v launch schedules.
 
-Sweeps the schedule knobs of a Hamiltonian (Hubbard T_up slab width,
-workgroups per XCD, rows per work item, T_dn kernel variant; spin
+Sweeps the schedule knobs of a Hamiltonian (Hubbard T_up kernel: block
+tiles with their split, or slabs with their width, workgroups per XCD and
+rows per work item; T_dn kernel variant; spin rank-table placement and
 workgroups per CU), times w = H v for each candidate with HIP events on the
 launch stream, keeps the fastest and records it in a JSON table keyed by
 (model kind, dimensions, dtype, block width). Later runs look the key up and
@@ -25,18 +26,28 @@ def schedule_key(ham, dtype: str, nvec: int) -> str:
     return f"{kind}:n{b.n_sites}:dim{b.dim}:{getattr(m, 'name', '')}:{dtype}:v{nvec}"
 
 
-def candidates(ham) -> List[Dict[str, int]]:
+def candidates(ham, quick: bool = False) -> List[Dict[str, int]]:
+    """Schedules to time. Hubbard: the block-tile T_up kernel (hub_sweep 7)
+    over tile splits (hub_tile_bits: -1 = the fewest top sites whose blocks
+    fit LDS, or a few more: smaller blocks, more far hops) and T_dn variants,
+    and the slab kernels (hub_sweep 5, 6; slab width, workgroups per XCD,
+    rows per item, row order). Spin: placement of the rank tables (LDS
+    32-bit, LDS narrowed, global) x workgroups per CU. Candidates the
+    Hamiltonian cannot take are skipped when timed."""
     if ham.basis.kind == "hubbard":
         out = []
-        for cw, g, rows, rc, sw, ro in itertools.product((16, 32, 64, 128), (64, 128, 192, 256), (16, 32, 64),
-                                                         (3, 5, 6), (1, 3, 5, 6), (1, 2)):
+        bits = (-1, 5) if quick else (-1, 3, 5, 6)
+        for tb, rc, g in itertools.product(bits, (6,) if quick else (5, 6), (32,) if quick else (16, 32, 64)):
+            out.append({"hub_sweep": 7, "hub_tile_bits": tb, "hub_row_cols": rc, "hub_groups": g})
+        slab = itertools.product((128,) if quick else (64, 128), (128,) if quick else (64, 128, 256),
+                                 (16,) if quick else (16, 32), (6,) if quick else (5, 6),
+                                 (5,) if quick else (5, 6), (2,) if quick else (1, 2))
+        for cw, g, rows, rc, sw, ro in slab:
             out.append({"hub_slab_cols": cw, "hub_groups": g, "hub_item_rows": rows, "hub_row_cols": rc,
                         "hub_sweep": sw, "hub_row_order": ro})
-        for cw, g, rc in itertools.product((16, 32, 64), (64, 128, 256, 512), (3, 5, 6)):
-            out.append({"hub_slab_cols": cw, "hub_groups": g, "hub_item_rows": 64, "hub_row_cols": rc,
-                        "hub_sweep": 2})
         return out
-    return [{"spin_per_cu": p} for p in (1, 2, 4, 8, 16)]
+    per = (2, 8) if quick else (1, 2, 4, 8, 16)
+    return [{"spin_tables": t, "spin_per_cu": p} for t in (1, 2, 3) for p in per]
 
 
 def time_mult(ham, v, w, reps: int = 5) -> float:
@@ -80,10 +91,16 @@ def tune(ham, dtype: str = "f64", nvec: int = 1, reps: int = 5, cands: Optional[
     v = torch.rand(shape, dtype=torch.float64 if not tdt.is_complex else torch.complex128,
                    device="cuda", generator=g).to(tdt) - 0.5
     w = torch.empty_like(v)
+    from .api import HphiError
     results = []
     for c in (cands or candidates(ham)):
-        ham.set_schedule(**c)
-        results.append((time_mult(ham, v, w, reps), c))
+        try:
+            ham.set_schedule(**c)
+            results.append((time_mult(ham, v, w, reps), c))
+        except HphiError:
+            continue      # a schedule this Hamiltonian or block cannot take
+    if not results:
+        raise HphiError("autotune: no candidate schedule runs")
     results.sort(key=lambda t: t[0])
     best_ms, best = results[0]
     ham.set_schedule(**best)
@@ -95,5 +112,5 @@ def tune(ham, dtype: str = "f64", nvec: int = 1, reps: int = 5, cands: Optional[
         json.dump(tab, f, indent=1, sort_keys=True)
     os.replace(tmp, table)
     del v, w
-    return {"key": key, "schedule": best, "ms": best_ms, "swept": True,
+    return {"key": key, "schedule": best, "ms": best_ms, "swept": True, "n_valid": len(results),
             "table": [(round(t, 4), c) for t, c in results[:8]], "worst_ms": results[-1][0]}

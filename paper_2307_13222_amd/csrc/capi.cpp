@@ -825,9 +825,12 @@ int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s)
             DeviceGuard g(h->basis->ctx->device);
             HPHI_USE_HAM(h, nullptr);
             HPHI_TRY(build_hub_tile(h, n.hub_tile_bits));
-            if (!h->hub.ft_ok && n.hub_sweep == 7)
+            if (!h->hub.ft_ok && n.hub_sweep == 7) {
+                // keep the tables of the schedule in force
+                (void)build_hub_tile(h, h->sched_cfg.hub_tile_bits);
                 return fail(HPHI_ERR_UNSUPPORTED, "hub_tile_bits %d: blocks do not fit the tile kernel",
                             s->hub_tile_bits);
+            }
         }
     }
     h->sched_cfg = n;

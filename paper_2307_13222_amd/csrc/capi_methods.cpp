@@ -38,6 +38,10 @@ int hphi_ctpq(hphi_ham *h, const hphi_ctpq_opts *o, void *phi_dev, double *D_out
     DeviceGuard g(h->basis->ctx->device);
     hipStream_t st = (hipStream_t)o->stream;
     HPHI_USE_HAM(h, st);
+    // the legacy default stream cannot be captured: a stream of our own,
+    // after the work queued on the default one
+    OwnStream own;
+    if (o->use_graph && !st) HPHI_TRY(own.make(&st));
     const int dt = o->storage, nv = o->n_vec, nl = 2 * nv;
     const int64_t dim = h->basis->dim;
     const size_t bytes = (size_t)dim * nl * dtype_size(dt);
@@ -68,7 +72,7 @@ int hphi_ctpq(hphi_ham *h, const hphi_ctpq_opts *o, void *phi_dev, double *D_out
     if (o->phi0_dev) HPHI_HIP(hipMemcpyAsync(A, o->phi0_dev, bytes, hipMemcpyDeviceToDevice, st));
     else HPHI_TRY(launch_rng_cgauss(dt, A, dim, nv, o->seed, st));
 
-    std::vector<double> hf(2 * nl), hl(2 * nl);
+    std::vector<double> hl(2 * nl);
     // N_0 and normalization
     HPHI_TRY(launch_dots(dt, nl, dim, A, A, reduce_at(h, res_last.as<double>()), 1, st));
     HPHI_HIP(hipMemcpyAsync(hl.data(), res_last.p, sizeof(double) * nl, hipMemcpyDeviceToHost, st));
@@ -80,14 +84,21 @@ int hphi_ctpq(hphi_ham *h, const hphi_ctpq_opts *o, void *phi_dev, double *D_out
 
     void *Y[2] = {y1.p, y2.p};
     const int K = o->k_steps;
-    for (int k = 0; k <= K; ++k) {
-        // k < K: one propagator step from beta_k to beta_{k+1};
-        // k == K: only the first-order product for <H>, <H^2> at beta_K.
-        const int n_top = o->n_max;
+    // Per-step results stay on the device (row k of `stage`: <H> and <H^2>
+    // lanes, then the new squared norms) and come back once at the end, so a
+    // step needs no host round trip and its launches can be replayed from a
+    // graph. `step` enqueues step k (k < K: the whole propagator; k == K:
+    // only the first-order product).
+    const int row = 3 * nl;
+    DevMem stage, counter;
+    HPHI_TRY(stage.alloc(sizeof(double) * (size_t)row * (K + 1)));
+    HPHI_TRY(counter.alloc(sizeof(int) * 2));
+    HPHI_TRY(launch_zero(counter.p, sizeof(int) * 2, st));
+    auto step = [&](bool last_step) -> int {
         const void *src = A;
         int yb = 0;
-        for (int n = n_top; n >= 1; --n) {
-            const bool first = (n == n_top), last = (n == 1);
+        for (int n = o->n_max; n >= 1; --n) {
+            const bool first = (n == o->n_max);
             MultArgs a{};
             a.dtype = dt;
             a.nvec = nv;
@@ -104,33 +115,64 @@ int hphi_ctpq(hphi_ham *h, const hphi_ctpq_opts *o, void *phi_dev, double *D_out
                 a.red = reduce_at(h, h->red_result.as<double>());
                 if (first) a.raw_out = yraw.p;
             }
-            (void)last;
             HPHI_TRY(launch_mult(h, a));
             if (first && raw_dots)
                 HPHI_TRY(launch_dots_xy_yy(dt, nl, dim, src, yraw.p, reduce_at(h, res_first.as<double>()), st));
-            if (k == K) break;
+            if (last_step) break;
             src = Y[yb];
             yb ^= 1;
         }
-        HPHI_HIP(hipMemcpyAsync(hf.data(), res_first.p, sizeof(double) * 2 * nl, hipMemcpyDeviceToHost, st));
-        if (k < K) {
+        HPHI_TRY(launch_record(res_first.as<double>(), 2 * nl, stage.as<double>(), row, counter.as<int>(), 0, st));
+        if (!last_step) {
             // the last order wrote Y[yb ^ 1]; its lanes' |.|^2 from one
             // streaming pass over the stored values (the fused dots of the
             // wide block kernel cost more registers than this pass costs)
             void *out = Y[yb ^ 1];
-            HPHI_TRY(launch_dots_xy_yy(dt, nl, dim, out, out, reduce_at(h, res_last.as<double>()), st));
             double *nrm = res_last.as<double>();
-            HPHI_HIP(hipMemcpyAsync(hl.data(), nrm, sizeof(double) * nl, hipMemcpyDeviceToHost, st));
+            HPHI_TRY(launch_dots_xy_yy(dt, nl, dim, out, out, reduce_at(h, nrm), st));
+            HPHI_TRY(launch_record(nrm, nl, stage.as<double>() + 2 * nl, row, counter.as<int>(), 1, st));
             HPHI_TRY(launch_pair_rsqrt(nrm, d_lane_scale, nl, st));
             HPHI_TRY(launch_scale_lanes(dt, nl, dim, out, d_lane_scale, 0, st));
             // new state: copy back into the caller's buffer
             HPHI_HIP(hipMemcpyAsync(A, out, bytes, hipMemcpyDeviceToDevice, st));
         }
-        HPHI_HIP(hipStreamSynchronize(st));
+        return HPHI_OK;
+    };
+    int k = 0;
+    if (o->use_graph && K >= 2) {
+        // one step captured and replayed: the same launches on the same
+        // buffers, so the same numbers as the eager steps
+        HPHI_TRY(step(false));
+        ++k;
+        hipGraph_t gph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        HPHI_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        const int rc = step(false);
+        const hipError_t e = hipStreamEndCapture(st, &gph);
+        if (rc != HPHI_OK) {
+            if (gph) (void)hipGraphDestroy(gph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(HPHI_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        const hipError_t ei = hipGraphInstantiate(&exec, gph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gph);
+        if (ei != hipSuccess) return fail(HPHI_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(ei));
+        hipError_t el = hipSuccess;
+        for (; k < K && el == hipSuccess; ++k) el = hipGraphLaunch(exec, st);
+        (void)hipGraphExecDestroy(exec);
+        if (el != hipSuccess) return fail(HPHI_ERR_DEVICE, "graph launch: %s", hipGetErrorString(el));
+    }
+    for (; k < K; ++k) HPHI_TRY(step(false));
+    HPHI_TRY(step(true));
+    std::vector<double> hs((size_t)row * (K + 1));
+    HPHI_HIP(hipMemcpyAsync(hs.data(), stage.p, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, st));
+    HPHI_HIP(hipStreamSynchronize(st));
+    for (int kk = 0; kk <= K; ++kk) {
+        const double *hf = hs.data() + (size_t)kk * row, *hl2 = hf + 2 * nl;
         for (int j = 0; j < nv; ++j) {
-            if (E_out) E_out[(size_t)k * nv + j] = hf[2 * j] + hf[2 * j + 1];
-            if (E2_out) E2_out[(size_t)k * nv + j] = hf[nl + 2 * j] + hf[nl + 2 * j + 1];
-            if (k < K && D_out) D_out[(size_t)(k + 1) * nv + j] = hl[2 * j] + hl[2 * j + 1];
+            if (E_out) E_out[(size_t)kk * nv + j] = hf[2 * j] + hf[2 * j + 1];
+            if (E2_out) E2_out[(size_t)kk * nv + j] = hf[nl + 2 * j] + hf[nl + 2 * j + 1];
+            if (kk < K && D_out) D_out[(size_t)(kk + 1) * nv + j] = hl2[2 * j] + hl2[2 * j + 1];
         }
     }
     return HPHI_OK;
@@ -152,6 +194,8 @@ int hphi_time_evolve(hphi_ham *h, const hphi_tevol_opts *o, void *psi_dev, doubl
     DeviceGuard g(h->basis->ctx->device);
     hipStream_t st = (hipStream_t)o->stream;
     HPHI_USE_HAM(h, st);
+    OwnStream own;
+    if (o->use_graph && !st) HPHI_TRY(own.make(&st));
     const int dt = o->storage, nv = o->n_vec, nl = 2 * nv;
     const int64_t dim = h->basis->dim;
     const size_t bytes = (size_t)dim * nl * dtype_size(dt);
@@ -175,14 +219,21 @@ int hphi_time_evolve(hphi_ham *h, const hphi_tevol_opts *o, void *psi_dev, doubl
     const double *d_coef = scal.as<double>();
     void *A = psi_dev;
     void *Y[2] = {y1.p, y2.p};
-    std::vector<double> he(nl), hn(nl);
-    double hd = 0.0;
     const int K = o->n_steps;
-    for (int k = 0; k <= K; ++k) {
-        // observables of the state at t_k = k dt
+    // Per recorded time, on the device (row k of `stage`: <psi|H|psi>
+    // lanes, <psi|psi> lanes, double occupancy), copied back once at the
+    // end; `step` enqueues time k (k < K: observables and one Taylor step;
+    // k == K: observables only), so steps replay from a graph.
+    const int row = 2 * nl + 1;
+    DevMem stage, counter;
+    HPHI_TRY(stage.alloc(sizeof(double) * (size_t)row * (K + 1)));
+    HPHI_TRY(counter.alloc(sizeof(int) * 4));
+    HPHI_TRY(launch_zero(counter.p, sizeof(int) * 4, st));
+    HPHI_TRY(launch_zero(res_d.p, sizeof(double) * 8, st));
+    auto step = [&](bool last_step) -> int {
         HPHI_TRY(launch_dots(dt, nl, dim, A, A, reduce_at(h, res_n.as<double>()), 1, st));
         if (docc_out) HPHI_TRY(launch_docc(h, dt, A, reduce_at(h, res_d.as<double>()), st));
-        if (k == K) {
+        if (last_step) {
             MultArgs a{};
             a.dtype = dt;
             a.nvec = nv;
@@ -218,21 +269,51 @@ int hphi_time_evolve(hphi_ham *h, const hphi_tevol_opts *o, void *psi_dev, doubl
                 yb ^= 1;
             }
         }
-        HPHI_HIP(hipMemcpyAsync(he.data(), res_e.p, sizeof(double) * nl, hipMemcpyDeviceToHost, st));
-        HPHI_HIP(hipMemcpyAsync(hn.data(), res_n.p, sizeof(double) * nl, hipMemcpyDeviceToHost, st));
-        if (docc_out) HPHI_HIP(hipMemcpyAsync(&hd, res_d.p, sizeof(double), hipMemcpyDeviceToHost, st));
-        if (k < K) {
+        HPHI_TRY(launch_record(res_e.as<double>(), nl, stage.as<double>(), row, counter.as<int>(), 0, st));
+        HPHI_TRY(launch_record(res_n.as<double>(), nl, stage.as<double>() + nl, row, counter.as<int>(), 1, st));
+        HPHI_TRY(launch_record(res_d.as<double>(), 1, stage.as<double>() + 2 * nl, row, counter.as<int>(), 2, st));
+        if (!last_step) {
             // the order-1 product holds psi(t_{k+1}); copy it into the caller's buffer
             const void *out = (o->n_max % 2 == 1) ? Y[0] : Y[1];
             HPHI_HIP(hipMemcpyAsync(A, out, bytes, hipMemcpyDeviceToDevice, st));
         }
-        HPHI_HIP(hipStreamSynchronize(st));
+        return HPHI_OK;
+    };
+    int k = 0;
+    if (o->use_graph && K >= 2) {
+        HPHI_TRY(step(false));
+        ++k;
+        hipGraph_t gph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        HPHI_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        const int rc = step(false);
+        const hipError_t e = hipStreamEndCapture(st, &gph);
+        if (rc != HPHI_OK) {
+            if (gph) (void)hipGraphDestroy(gph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(HPHI_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        const hipError_t ei = hipGraphInstantiate(&exec, gph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gph);
+        if (ei != hipSuccess) return fail(HPHI_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(ei));
+        hipError_t el = hipSuccess;
+        for (; k < K && el == hipSuccess; ++k) el = hipGraphLaunch(exec, st);
+        (void)hipGraphExecDestroy(exec);
+        if (el != hipSuccess) return fail(HPHI_ERR_DEVICE, "graph launch: %s", hipGetErrorString(el));
+    }
+    for (; k < K; ++k) HPHI_TRY(step(false));
+    HPHI_TRY(step(true));
+    std::vector<double> hs((size_t)row * (K + 1));
+    HPHI_HIP(hipMemcpyAsync(hs.data(), stage.p, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, st));
+    HPHI_HIP(hipStreamSynchronize(st));
+    for (int kk = 0; kk <= K; ++kk) {
+        const double *he = hs.data() + (size_t)kk * row, *hn = he + nl;
         for (int j = 0; j < nv; ++j) {
             const double nrm = hn[2 * j] + hn[2 * j + 1];
-            if (norm_out) norm_out[(size_t)k * nv + j] = nrm;
-            if (energy_out) energy_out[(size_t)k * nv + j] = (he[2 * j] + he[2 * j + 1]) / nrm;
+            if (norm_out) norm_out[(size_t)kk * nv + j] = nrm;
+            if (energy_out) energy_out[(size_t)kk * nv + j] = (he[2 * j] + he[2 * j + 1]) / nrm;
         }
-        if (docc_out) docc_out[k] = hd / (hn[0] + hn[1]) / h->basis->n_sites;
+        if (docc_out) docc_out[kk] = he[2 * nl] / (hn[0] + hn[1]) / h->basis->n_sites;
     }
     return HPHI_OK;
 }

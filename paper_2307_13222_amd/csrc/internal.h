@@ -237,6 +237,28 @@ int init_ham_use(hphi_ham *h);
 
 } // namespace hphi
 
+// A non-blocking stream for work that must be captured into a graph when
+// the caller gave the legacy default stream (which cannot be captured); the
+// default stream's queued work is waited for first. Synchronized and
+// destroyed at scope exit.
+struct OwnStream {
+    hipStream_t s = nullptr;
+    int make(hipStream_t *st)
+    {
+        HPHI_HIP(hipStreamSynchronize(nullptr));
+        HPHI_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        *st = s;
+        return HPHI_OK;
+    }
+    ~OwnStream()
+    {
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+    }
+};
+
 // Enter a call on Hamiltonian h issued on stream st (after the device guard);
 // returns HPHI_ERR_BUSY from the enclosing function when it may not start.
 #define HPHI_USE_HAM(h, st)                                                                    \
@@ -343,6 +365,8 @@ int launch_lz_psi_accum(int psi_dtype, int dtype, LzDev *lz, const double *svec,
 int launch_rng_uniform_pitched(int dtype, void *out, int64_t rows, int64_t cols, int64_t ld, uint64_t seed,
                                hipStream_t st);
 int launch_norm2_pitched(int dtype, const void *x, int64_t dim, int64_t cols, int64_t ld, Reduce red, hipStream_t st);
+// dst[counter[which] * row + i] = src[i] for i < n; counter[which]++ (one step's results per row)
+int launch_record(const double *src, int n, double *dst, int row, int *counter, int which, hipStream_t st);
 // Row pitch (elements) a Hubbard Lanczos run may store its vectors with
 // (rows padded to whole 128-byte lines) for the current schedule; dim_dn
 // when the kernels it selects take only unpadded rows.

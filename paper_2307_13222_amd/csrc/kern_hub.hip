@@ -1373,6 +1373,24 @@ template <typename S> constexpr int tile_row_stride() { return kTileCols + 16 / 
 template <typename S> struct Pair;
 template <> struct Pair<double> { using T = double2; };
 template <> struct Pair<float> { using T = float2; };
+// two adjacent elements through the nontemporal path (streams touched once)
+template <typename S> __device__ __forceinline__ typename Pair<S>::T nt_load2(const S *p)
+{
+    typedef S v2 __attribute__((ext_vector_type(2)));
+    const v2 x = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
+    typename Pair<S>::T o;
+    o.x = x.x;
+    o.y = x.y;
+    return o;
+}
+template <typename S> __device__ __forceinline__ void nt_store2(S *p, S a, S b)
+{
+    typedef S v2 __attribute__((ext_vector_type(2)));
+    v2 x;
+    x.x = a;
+    x.y = b;
+    __builtin_nontemporal_store(x, reinterpret_cast<v2 *>(p));
+}
 
 template <typename S, bool DOTS>
 __global__ __launch_bounds__(1024) void k_hub_up_tile(HubKArgs a)
@@ -1451,12 +1469,14 @@ __global__ __launch_bounds__(1024) void k_hub_up_tile(HubKArgs a)
                 cnt_n = a.ft_cnt[r0 + p + kTileSlots];
                 off_n = a.ft_off[r0 + p + kTileSlots];
             }
+            // the epilogue streams (w in and out, u) are touched once: kept
+            // out of the way of the slab's rows in L2
             const size_t me = (size_t)(r0 + lr) * ld + col;
-            const P2 wv = *reinterpret_cast<const P2 *>(w + me);
+            const P2 wv = nt_load2<S>(w + me);
             P2 uv;
             uv.x = (S)0;
             uv.y = (S)0;
-            if (u) uv = *reinterpret_cast<const P2 *>(u + me);
+            if (u) uv = nt_load2<S>(u + me);
             // entries in 16-byte groups: local (plus then minus), then far
             // (plus then minus) from the next group boundary; at most
             // kTileLocalGroups local groups and kTileFar far entries per
@@ -1537,10 +1557,7 @@ __global__ __launch_bounds__(1024) void k_hub_up_tile(HubKArgs a)
                 o0 = c1s * raw0;
                 o1 = c1s * raw1;
             }
-            P2 ov;
-            ov.x = o0;
-            ov.y = o1;
-            *reinterpret_cast<P2 *>(w + me) = ov;
+            nt_store2<S>(w + me, o0, o1);
             if constexpr (DOTS) {
                 const S *tp = tile + lr * RS + 2 * l8;
                 const double x0 = a.dot_raw ? (double)raw0 : (double)o0;

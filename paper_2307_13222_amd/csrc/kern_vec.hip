@@ -710,3 +710,25 @@ int launch_szq(hphi_ham *h, const double *phase_dev, const void *psi, void *b, h
 }
 
 } // namespace hphi
+
+namespace hphi {
+
+// dst[k * row + i] = src[i] (i < n), k = counter[which], then counter[which]
+// advances: results of successive steps land in successive rows of a device
+// staging array, with the same launch for every step (graph replay).
+__global__ void k_record(const double *src, int n, double *dst, int row, int *counter, int which)
+{
+    const int k = counter[which];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[(size_t)k * row + i] = src[i];
+    __syncthreads();
+    if (threadIdx.x == 0) counter[which] = k + 1;
+}
+
+int launch_record(const double *src, int n, double *dst, int row, int *counter, int which, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_record, dim3(1), dim3(64), 0, st, src, n, dst, row, counter, which);
+    HPHI_HIP(hipGetLastError());
+    return HPHI_OK;
+}
+
+} // namespace hphi
