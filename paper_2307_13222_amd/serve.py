@@ -1,10 +1,11 @@
 """Continuous-batching request server for ground-state and S(q, w) solves.
 
 Requests (Poisson arrivals, chains and 2-leg ladders of mixed size) are
-admitted as soon as a slot is free and their device-memory footprint fits
-the budget; admitted requests run concurrently on the device, and new
-arrivals join while others are in flight (not a queue drained one request
-at a time):
+admitted as soon as a slot is free, their device-memory footprint fits the
+budget and the device's free memory (as the device reports it, less what
+admitted requests have yet to allocate) can hold it; admitted requests run
+concurrently on the device, and new arrivals join while others are in
+flight (not a queue drained one request at a time):
 
   * small ground-state requests (sector dimension <= batch_max_dim) are
     grouped: whatever is admitted while the previous group runs goes into
@@ -166,15 +167,23 @@ class FakeExecutor:
     """Simulated device clock: service time from `service(req)`, with a
     concurrency slowdown `1 + slow * (active - 1)` frozen at start;
     `fail(req)` may return 'alloc' (start raises MemoryError once),
-    'breakdown' (the solve reports a breakdown) or None."""
+    'breakdown' (the solve reports a breakdown) or None. With `device_bytes`
+    the device has that much memory, of which `external(t)` is held by
+    others at time t; a request starts only when its footprint fits what
+    the running requests and the others leave free (as GpuExecutor asks the
+    device)."""
 
     def __init__(self, service: Callable[[Request], float], slow: float = 0.0,
-                 fail: Optional[Callable[[Request], Optional[str]]] = None):
+                 fail: Optional[Callable[[Request], Optional[str]]] = None,
+                 device_bytes: Optional[int] = None, external: Optional[Callable[[float], int]] = None):
         self.service, self.slow, self.fail = service, slow, fail
+        self.device_bytes, self.external = device_bytes, external
         self.t = 0.0
         self.heap: List[Tuple[float, int]] = []
         self.out: Dict[int, Dict] = {}
+        self.held: Dict[int, int] = {}
         self.failed_once = set()
+        self.admit_free: List[Tuple[int, int]] = []   # (free bytes seen, footprint) at each start
 
     def begin(self):
         pass
@@ -185,14 +194,25 @@ class FakeExecutor:
     def now(self) -> float:
         return self.t
 
+    def free_bytes(self) -> Optional[int]:
+        if self.device_bytes is None:
+            return None
+        ext = self.external(self.t) if self.external else 0
+        return self.device_bytes - ext - sum(self.held.values())
+
     def can_start(self, req) -> bool:
-        return True
+        free = self.free_bytes()
+        return free is None or footprint_bytes(req) <= free
 
     def start(self, req):
         mode = self.fail(req) if self.fail else None
         if mode == "alloc" and req.rid not in self.failed_once:
             self.failed_once.add(req.rid)
             raise MemoryError("injected allocation failure")
+        free = self.free_bytes()
+        if free is not None:
+            self.admit_free.append((free, footprint_bytes(req)))
+        self.held[req.rid] = footprint_bytes(req)
         dt = self.service(req) * (1.0 + self.slow * len(self.heap))
         heapq.heappush(self.heap, (self.t + dt, req.rid))
         self.out[req.rid] = {"energy": -float(req.n_sites), "iterations": 1, "path": "fake",
@@ -212,6 +232,7 @@ class FakeExecutor:
         done = []
         while self.heap and self.heap[0][0] <= self.t:
             _, rid = heapq.heappop(self.heap)
+            self.held.pop(rid, None)
             done.append((rid, self.out.pop(rid)))
         return done
 
@@ -229,7 +250,7 @@ class GpuExecutor:
     def __init__(self, device: int = 0, n_workers: int = 4, batch_max_dim: int = 20000,
                  max_batch: int = 512, lanczos_iters: int = 200, max_iter: int = 500, eta: float = 0.05,
                  n_shift: int = 64, sqw_tol: float = 1e-8, sqw_max_iter: int = 6000,
-                 gs_resid_tol: float = 1e-9):
+                 gs_resid_tol: float = 1e-9, reserve_bytes: int = 512 << 20):
         from . import api
         self.api = api
         self.ctx = api.Context(device)
@@ -243,6 +264,9 @@ class GpuExecutor:
         self.sqw_tol = sqw_tol
         self.sqw_max_iter = sqw_max_iter
         self.gs_resid_tol = gs_resid_tol
+        self.device = device
+        self.pending_bytes = 0
+        self.reserve_bytes = reserve_bytes
         self.t0 = time.perf_counter()
         self.work: "queue.Queue" = queue.Queue()
         self.batchq: "queue.Queue" = queue.Queue()
@@ -288,9 +312,23 @@ class GpuExecutor:
         return time.perf_counter() - self.t0
 
     def can_start(self, req) -> bool:
-        return True
+        """Admit only what the device can still hold: its free memory now
+        (other processes and the allocator's cache included), less the
+        footprints of requests admitted but not yet running (their buffers
+        are not allocated yet), less a reserve."""
+        import torch
+        free, _ = torch.cuda.mem_get_info(self.device)
+        with self.lock:
+            pending = self.pending_bytes
+        return footprint_bytes(req) + pending + self.reserve_bytes <= free
+
+    def _begin_request(self, req):
+        with self.lock:
+            self.pending_bytes -= footprint_bytes(req)
 
     def start(self, req):
+        with self.lock:
+            self.pending_bytes += footprint_bytes(req)
         if req.kind == "lanczos" and sector_dim(req.n_sites, req.two_sz) <= self.batch_max_dim:
             self.batchq.put(req)
         else:
@@ -338,6 +376,7 @@ class GpuExecutor:
             req = self.work.get()
             if req is None:
                 return
+            self._begin_request(req)
             try:
                 res = self.run_one(req, stream)
             except Exception as e:  # report, keep serving
@@ -360,6 +399,8 @@ class GpuExecutor:
                     stop = True
                     break
                 group.append(r)
+            for r in group:
+                self._begin_request(r)
             try:
                 outs = self.run_batch(group, stream)
             except Exception as e:

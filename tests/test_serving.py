@@ -93,3 +93,21 @@ def test_footprint_model():
     d = math.comb(26, 13)
     assert fp > 100 * d and fp < 140 * d
     assert S.footprint_bytes(W.Request(0, 0.0, "lanczos", "chain", 26, 0)) < fp
+
+
+def test_admission_follows_device_free_memory():
+    # the device (8 GB) is half held by another user for the first 0.05 s:
+    # requests that fit the budget but not the free memory wait, none is
+    # started on memory the device does not have, and all complete
+    reqs = W.serving_requests(60, 2000.0, seed=9, n_range=(22, 26))
+    dev_bytes = 8 * 10 ** 9
+    ex = S.FakeExecutor(service, device_bytes=dev_bytes,
+                        external=lambda t: 4 * 10 ** 9 if t < 0.05 else 0)
+    out = S.Server(ex, 10 ** 12, max_active=64).run(reqs)
+    assert out["completed"] == 60
+    assert ex.admit_free and all(fp <= free for free, fp in ex.admit_free)
+    early = [r for r in out["results"] if r.arrival < 0.02]
+    assert any(r.admit > r.arrival for r in early)
+    # with the device all free the same list waits less
+    out2 = S.Server(S.FakeExecutor(service, device_bytes=dev_bytes), 10 ** 12, max_active=64).run(reqs)
+    assert out2["mean_latency_s"] < out["mean_latency_s"]
