@@ -79,6 +79,12 @@ def lib():
         L.or_spin_ell.argtypes = [i32, p, i64, i32, p, p, p, p, p, p, p, p]
         L.or_hubbard_ell.restype = None
         L.or_hubbard_ell.argtypes = [i32, p, i64, p, i64, i32, p, p, p, p, p, p, p]
+        L.or_hubbard_pairs_row.restype = i32
+        L.or_hubbard_pairs_row.argtypes = [i32, p, i64, p, i64, i32, p, p, p, p, p, p, i64, i64, p, p]
+        L.or_hubbard_pairs_hv.restype = None
+        L.or_hubbard_pairs_hv.argtypes = [i32, p, i64, p, i64, i32, p, p, p, p, p, p, p, p]
+        L.or_hubbard_pairs_ell.restype = None
+        L.or_hubbard_pairs_ell.argtypes = [i32, p, i64, p, i64, i32, p, p, p, p, p, p, p, p, p]
         _lib = L
     return _lib
 
@@ -196,6 +202,26 @@ def _hub_arrays(m):
             np.ascontiguousarray(m.u_site, dtype=np.float64))
 
 
+def _pair_arrays(m):
+    f = lambda x: np.ascontiguousarray(x, dtype=np.float64)
+    return (np.ascontiguousarray(m.pi, dtype=np.int32), np.ascontiguousarray(m.pj, dtype=np.int32),
+            f(m.pv), f(m.pjh), f(m.pjx), f(m.pjp))
+
+
+def _n_pairs(m) -> int:
+    return 0 if getattr(m, "pi", None) is None else int(len(m.pi))
+
+
+def hubbard_pairs_hv(m, ups: np.ndarray, dns: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """H_2body v alone (Sec. 5, Eq. ham_general two-body terms)."""
+    pa = _pair_arrays(m)
+    vv = np.ascontiguousarray(v, dtype=np.float64)
+    w = np.empty_like(vv)
+    lib().or_hubbard_pairs_hv(m.n_sites, _p(ups), ups.shape[0], _p(dns), dns.shape[0], pa[0].shape[0],
+                              *[_p(x) for x in pa], _p(vv), _p(w))
+    return w
+
+
 def hubbard_hv(m, ups: np.ndarray, dns: np.ndarray, v: np.ndarray) -> np.ndarray:
     v = np.asarray(v)
     if np.iscomplexobj(v):
@@ -205,6 +231,8 @@ def hubbard_hv(m, ups: np.ndarray, dns: np.ndarray, v: np.ndarray) -> np.ndarray
     w = np.empty_like(vv)
     lib().or_hubbard_hv(m.n_sites, _p(ups), ups.shape[0], _p(dns), dns.shape[0], hi.shape[0],
                         _p(hi), _p(hj), _p(t), _p(us), _p(vv), _p(w))
+    if _n_pairs(m):
+        w += hubbard_pairs_hv(m, ups, dns, vv)
     return w
 
 
@@ -215,7 +243,22 @@ def hubbard_hv_rows(m, ups, dns, v: np.ndarray, ru_first: int, ru_count: int) ->
     w = np.empty(ru_count * dns.shape[0])
     lib().or_hubbard_hv_rows(m.n_sites, _p(ups), ups.shape[0], _p(dns), dns.shape[0], hi.shape[0],
                              _p(hi), _p(hj), _p(t), _p(us), _p(vv), int(ru_first), int(ru_count), _p(w))
+    if _n_pairs(m):
+        ddn = dns.shape[0]
+        for k in range(ru_count * ddn):
+            cols, vals = hubbard_pairs_row(m, ups, dns, ru_first + k // ddn, k % ddn)
+            w[k] += float(np.dot(vals, vv[cols]))
     return w
+
+
+def hubbard_pairs_row(m, ups, dns, ru: int, rd: int):
+    pa = _pair_arrays(m)
+    s = 1 + 4 * pa[0].shape[0]
+    cols = np.empty(s, dtype=np.int64)
+    vals = np.empty(s, dtype=np.float64)
+    k = lib().or_hubbard_pairs_row(m.n_sites, _p(ups), ups.shape[0], _p(dns), dns.shape[0], pa[0].shape[0],
+                                   *[_p(x) for x in pa], int(ru), int(rd), _p(cols), _p(vals))
+    return cols[:k].copy(), vals[:k].copy()
 
 
 def hubbard_row(m, ups, dns, ru: int, rd: int):
@@ -226,7 +269,11 @@ def hubbard_row(m, ups, dns, ru: int, rd: int):
     k = lib().or_hubbard_row(m.n_sites, _p(ups), ups.shape[0], _p(dns), dns.shape[0],
                              hi.shape[0], _p(hi), _p(hj), _p(t), _p(us), int(ru), int(rd),
                              _p(cols), _p(vals))
-    return cols[:k].copy(), vals[:k].copy()
+    cols, vals = cols[:k].copy(), vals[:k].copy()
+    if _n_pairs(m):
+        c2, v2 = hubbard_pairs_row(m, ups, dns, ru, rd)
+        cols, vals = np.concatenate([cols, c2]), np.concatenate([vals, v2])
+    return cols, vals
 
 
 def hubbard_sparse(m, ups, dns) -> scipy.sparse.csr_matrix:
@@ -237,6 +284,22 @@ def hubbard_sparse(m, ups, dns) -> scipy.sparse.csr_matrix:
     cnt = np.zeros(dim, dtype=np.int32)
     lib().or_hubbard_ell(m.n_sites, _p(ups), ups.shape[0], _p(dns), dns.shape[0], hi.shape[0],
                          _p(hi), _p(hj), _p(t), _p(us), _p(cols), _p(vals), _p(cnt))
+    mask = (np.arange(s)[None, :] < cnt[:, None]).ravel()
+    rows = np.repeat(np.arange(dim), s)[mask]
+    H = scipy.sparse.csr_matrix((vals[mask], (rows, cols[mask])), shape=(dim, dim))
+    if _n_pairs(m):
+        H = H + hubbard_pairs_sparse(m, ups, dns)
+    return H
+
+
+def hubbard_pairs_sparse(m, ups, dns) -> scipy.sparse.csr_matrix:
+    pa = _pair_arrays(m)
+    dim, s = ups.shape[0] * dns.shape[0], 1 + 4 * pa[0].shape[0]
+    cols = np.zeros(dim * s, dtype=np.int64)
+    vals = np.zeros(dim * s, dtype=np.float64)
+    cnt = np.zeros(dim, dtype=np.int32)
+    lib().or_hubbard_pairs_ell(m.n_sites, _p(ups), ups.shape[0], _p(dns), dns.shape[0], pa[0].shape[0],
+                               *[_p(x) for x in pa], _p(cols), _p(vals), _p(cnt))
     mask = (np.arange(s)[None, :] < cnt[:, None]).ravel()
     rows = np.repeat(np.arange(dim), s)[mask]
     return scipy.sparse.csr_matrix((vals[mask], (rows, cols[mask])), shape=(dim, dim))

@@ -15,7 +15,9 @@
  *     (Heisenberg model of Sec. 3.2, S^z = (n_up - n_dn)/2);
  *   - the Hubbard Hamiltonian -t sum c^+c + U n_up n_dn applied to a vector
  *     (Sec. 3.4, Eq. Hquench; Sec. 5 transfer integrals), with the fermion
- *     sign written out from the anticommutation relations.
+ *     sign written out from the anticommutation relations, and the two-body
+ *     terms of Sec. 5, Eq. ham_general (inter-site Coulomb, Hund, exchange,
+ *     pair hopping), applied operator by operator;
  *
  * Readings where the paper is silent (bit 1 = up spin / occupied orbital,
  * ascending integer order, all up orbitals ordered before all down orbitals)
@@ -334,6 +336,119 @@ int or_hubbard_row(int nsites, const uint64_t *ups, int64_t dup,
         }
     }
     return m;
+}
+
+/* ------------------------------------------------ Hubbard two-body terms -- */
+
+/* One creation (dag = 1) or annihilation (dag = 0) operator on orbital o of
+ * the occupation pattern occ over 2 * nsites orbitals (orbital i = site i
+ * up, nsites + i = site i down), with |occ> = prod_{o in occ, ascending}
+ * c^+_o |0>. The operator anticommutes past every occupied orbital below o
+ * before it acts, so the amplitude picks up (-1)^(that count). Returns 0
+ * when the result vanishes (c^+ on an occupied or c on an empty orbital). */
+static int apply_fermion(uint64_t *occ, int o, int dag, double *sign)
+{
+    int occupied = (int)((*occ >> o) & 1);
+    if (dag == occupied) return 0;
+    int below = 0;
+    for (int k = 0; k < o; ++k) below += (int)((*occ >> k) & 1);
+    if (below & 1) *sign = -*sign;
+    *occ ^= (uint64_t)1 << o;
+    return 1;
+}
+
+/* An operator product c^(d0)_{o0} c^(d1)_{o1} c^(d2)_{o2} c^(d3)_{o3} applied
+ * to occ, rightmost factor first. */
+static int apply_string4(uint64_t *occ, const int *orb, const int *dag, double *sign)
+{
+    for (int k = 3; k >= 0; --k)
+        if (!apply_fermion(occ, orb[k], dag[k], sign)) return 0;
+    return 1;
+}
+
+/* Two-body part of one row (Sec. 5, Eq. ham_general, one coefficient set per
+ * listed site pair p = (i, j), i != j):
+ *   V_p n_i n_j - JH_p (n_i,up n_j,up + n_i,dn n_j,dn)        (n_i = n_i,up + n_i,dn)
+ *   + JX_p (c+_i,up c_j,up c+_j,dn c_i,dn + h.c.)           (exchange)
+ *   + JP_p (c+_i,up c_j,up c+_i,dn c_j,dn + h.c.)           (pair hopping)
+ * The off-diagonal products and their conjugates are applied factor by
+ * factor to the full occupation pattern, so every fermion sign comes from
+ * the anticommutation relations alone. Entries are flat indices; the
+ * diagonal comes first. Returns the count (at most 1 + 4 * np). */
+int or_hubbard_pairs_row(int nsites, const uint64_t *ups, int64_t dup,
+                         const uint64_t *dns, int64_t ddn, int np, const int32_t *pi,
+                         const int32_t *pj, const double *pv, const double *pjh,
+                         const double *pjx, const double *pjp, int64_t ru, int64_t rd,
+                         int64_t *cols, double *vals)
+{
+    const uint64_t u = ups[ru], d = dns[rd];
+    const uint64_t occ0 = u | (d << nsites);
+    const uint64_t lowmask = (nsites >= 64) ? ~(uint64_t)0 : (((uint64_t)1 << nsites) - 1);
+    double diag = 0.0;
+    for (int p = 0; p < np; ++p) {
+        int i = pi[p], j = pj[p];
+        int niu = (int)((u >> i) & 1), nid = (int)((d >> i) & 1);
+        int nju = (int)((u >> j) & 1), njd = (int)((d >> j) & 1);
+        diag += pv[p] * (double)((niu + nid) * (nju + njd));
+        diag -= pjh[p] * (double)(niu * nju + nid * njd);
+    }
+    int m = 0;
+    cols[m] = ru * ddn + rd; vals[m] = diag; ++m;
+    for (int p = 0; p < np; ++p) {
+        const int iu = pi[p], ju = pj[p], id = nsites + pi[p], jd = nsites + pj[p];
+        /* exchange, its conjugate, pair hopping, its conjugate */
+        const int orb[4][4] = {{iu, ju, jd, id}, {id, jd, ju, iu}, {iu, ju, id, jd}, {jd, id, ju, iu}};
+        const int dag[4][4] = {{1, 0, 1, 0}, {1, 0, 1, 0}, {1, 0, 1, 0}, {1, 0, 1, 0}};
+        const double coef[4] = {pjx[p], pjx[p], pjp[p], pjp[p]};
+        for (int s = 0; s < 4; ++s) {
+            if (coef[s] == 0.0) continue;
+            uint64_t occ = occ0;
+            double sign = 1.0;
+            if (!apply_string4(&occ, orb[s], dag[s], &sign)) continue;
+            uint64_t u2 = occ & lowmask, d2 = occ >> nsites;
+            cols[m] = or_rank_search(ups, dup, u2) * ddn + or_rank_search(dns, ddn, d2);
+            vals[m] = coef[s] * sign;
+            ++m;
+        }
+    }
+    return m;
+}
+
+/* w = H_2body v (every row through or_hubbard_pairs_row). */
+void or_hubbard_pairs_hv(int nsites, const uint64_t *ups, int64_t dup,
+                         const uint64_t *dns, int64_t ddn, int np, const int32_t *pi,
+                         const int32_t *pj, const double *pv, const double *pjh,
+                         const double *pjx, const double *pjp, const double *v, double *w)
+{
+    #pragma omp parallel
+    {
+        int64_t *cols = (int64_t *)malloc(sizeof(int64_t) * (size_t)(1 + 4 * np));
+        double *vals = (double *)malloc(sizeof(double) * (size_t)(1 + 4 * np));
+        #pragma omp for schedule(static)
+        for (int64_t r = 0; r < dup * ddn; ++r) {
+            int m = or_hubbard_pairs_row(nsites, ups, dup, dns, ddn, np, pi, pj, pv, pjh, pjx, pjp,
+                                         r / ddn, r % ddn, cols, vals);
+            double acc = 0.0;
+            for (int k = 0; k < m; ++k) acc += vals[k] * v[cols[k]];
+            w[r] = acc;
+        }
+        free(cols);
+        free(vals);
+    }
+}
+
+/* Every row of H_2body in a fixed-stride layout (stride 1 + 4 * np). */
+void or_hubbard_pairs_ell(int nsites, const uint64_t *ups, int64_t dup,
+                          const uint64_t *dns, int64_t ddn, int np, const int32_t *pi,
+                          const int32_t *pj, const double *pv, const double *pjh,
+                          const double *pjx, const double *pjp, int64_t *cols, double *vals,
+                          int32_t *count)
+{
+    int64_t stride = 1 + 4 * (int64_t)np;
+    #pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < dup * ddn; ++r)
+        count[r] = or_hubbard_pairs_row(nsites, ups, dup, dns, ddn, np, pi, pj, pv, pjh, pjx, pjp,
+                                        r / ddn, r % ddn, cols + r * stride, vals + r * stride);
 }
 
 /* --------------------------------------------------------------- random -- */

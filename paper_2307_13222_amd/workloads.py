@@ -38,7 +38,11 @@ class SpinModel:
 
 @dataclass
 class HubbardModel:
-    """H = -sum_h t_h sum_sigma (c+_i c_j + h.c.) + sum_i U_i n_up n_dn."""
+    """H = -sum_h t_h sum_sigma (c+_i c_j + h.c.) + sum_i U_i n_up n_dn, plus
+    the optional two-body terms of Eq. ham_general (Sec. 5) per site pair
+    p = (pi, pj): inter-site Coulomb pv n_i n_j, Hund -pjh (n_i,up n_j,up +
+    n_i,dn n_j,dn), exchange pjx (c+_i,up c_j,up c+_j,dn c_i,dn + h.c.) and
+    pair hopping pjp (c+_i,up c_j,up c+_i,dn c_j,dn + h.c.)."""
     n_sites: int
     hi: np.ndarray
     hj: np.ndarray
@@ -46,10 +50,20 @@ class HubbardModel:
     u_site: np.ndarray
     name: str = ""
     site_x: Optional[np.ndarray] = None   # coordinate used for S^z(q) phases
+    pi: Optional[np.ndarray] = None
+    pj: Optional[np.ndarray] = None
+    pv: Optional[np.ndarray] = None
+    pjh: Optional[np.ndarray] = None
+    pjx: Optional[np.ndarray] = None
+    pjp: Optional[np.ndarray] = None
 
     @property
     def n_hops(self) -> int:
         return int(self.hi.shape[0])
+
+    @property
+    def n_pairs(self) -> int:
+        return 0 if self.pi is None else int(self.pi.shape[0])
 
 
 def _spin(n, pairs, couplings, name, site_x=None, hz=None) -> SpinModel:
@@ -143,6 +157,27 @@ def hubbard_chain(n: int, t: float = 1.0, u: float = 4.0) -> HubbardModel:
     return HubbardModel(n, p[:, 0].copy(), p[:, 1].copy(), np.full(len(p), t),
                         np.full(n, u, dtype=np.float64), f"hubbard_chain_{n}",
                         np.arange(n, dtype=np.int64))
+
+
+def with_pair_terms(m: HubbardModel, pairs, v=0.0, jh=0.0, jx=0.0, jp=0.0, name: str = "") -> HubbardModel:
+    """A copy of m with two-body terms on the given site pairs (scalars or
+    one value per pair)."""
+    p = np.asarray(pairs, dtype=np.int32).reshape(-1, 2)
+    k = len(p)
+    full = lambda x: np.broadcast_to(np.asarray(x, dtype=np.float64), (k,)).copy()
+    return HubbardModel(m.n_sites, m.hi, m.hj, m.t, m.u_site, name or m.name + "_ext", m.site_x,
+                        p[:, 0].copy(), p[:, 1].copy(), full(v), full(jh), full(jx), full(jp))
+
+
+def extended_hubbard_square(lx: int, ly: int, t: float = 1.0, u: float = 4.0, v: float = 1.0,
+                            j: float = 0.3) -> HubbardModel:
+    """Nearest-neighbour extended Hubbard model on the periodic square
+    lattice in the form the Wannier-function input of Sec. 5 produces: one
+    Coulomb V and one exchange integral J per bond, J entering the Hund,
+    exchange and pair-hopping terms alike."""
+    m = hubbard_square(lx, ly, t, u)
+    return with_pair_terms(m, np.stack([m.hi, m.hj], axis=1), v, j, j, j,
+                           f"ext_hubbard_square_{lx}x{ly}")
 
 
 def random_vector(dim: int, seed: int, dtype=np.float64, nvec: int = 1) -> np.ndarray:

@@ -1,7 +1,11 @@
 """Pins of the oracle's Hubbard H*v: an independent Jordan-Wigner matrix
 construction on the full Fock space (signs included), free-fermion and
 atomic-limit energies, the two-site closed form, the ring sign pins, the
-closed-form trace, hermiticity and the Kronecker-sum structure."""
+closed-form trace, hermiticity and the Kronecker-sum structure; for the
+two-body terms of Eq. ham_general (Sec. 5) the same Jordan-Wigner route with
+each term formed from the operator matrices it names, the dimer closed form,
+sector conservation, and spin-rotation invariance at JH = JX (with its
+negative control)."""
 import math
 
 import numpy as np
@@ -203,3 +207,122 @@ def test_row_matches_sparse():
         dense = np.zeros(Hs.shape[0])
         np.add.at(dense, cols, vals)
         assert np.allclose(dense, Hs.getrow(ru * len(dns) + rd).toarray()[0], atol=1e-15)
+
+
+# ------------------------------------------------------ two-body terms --
+
+def jw_dense_extended(m) -> sp.csr_matrix:
+    """The two-body terms of Eq. ham_general (Sec. 5) added to the
+    Jordan-Wigner one-body Hamiltonian, each term formed as the product of
+    the annihilator/creator matrices it names, h.c. as the transpose of the
+    product (real coefficients)."""
+    n = m.n_sites
+    n_orb = 2 * n
+    Z = sp.csr_matrix(np.diag([1.0, -1.0]))
+    lower = sp.csr_matrix(np.array([[0.0, 1.0], [0.0, 0.0]]))
+    I2 = sp.identity(2, format="csr")
+
+    def annihilate(o):
+        out = None
+        for k in range(n_orb - 1, -1, -1):
+            mm = Z if k < o else (lower if k == o else I2)
+            out = mm if out is None else sp.kron(out, mm, format="csr")
+        return out
+
+    c = [annihilate(o) for o in range(n_orb)]
+    cd = [x.T.tocsr() for x in c]
+    num = [cd[o] @ c[o] for o in range(n_orb)]
+    H = jw_dense_hubbard(m)
+    for p in range(m.n_pairs):
+        i, j = int(m.pi[p]), int(m.pj[p])
+        iu, ju, idn, jdn = i, j, n + i, n + j
+        ni, nj = num[iu] + num[idn], num[ju] + num[jdn]
+        H = H + m.pv[p] * (ni @ nj)
+        H = H - m.pjh[p] * (num[iu] @ num[ju] + num[idn] @ num[jdn])
+        x = cd[iu] @ c[ju] @ cd[jdn] @ c[idn]
+        H = H + m.pjx[p] * (x + x.T)
+        y = cd[iu] @ c[ju] @ cd[idn] @ c[jdn]
+        H = H + m.pjp[p] * (y + y.T)
+    return H
+
+
+def random_extended(n, seed, p=0.6, tie_hund_exchange=False):
+    rng = np.random.default_rng(seed)
+    m = random_hubbard(n, seed, p)
+    pairs = [(i, j) for i in range(n) for j in range(n) if i != j and rng.random() < 0.5]
+    k = len(pairs)
+    jh = rng.normal(size=k)
+    jx = jh.copy() if tie_hund_exchange else rng.normal(size=k)
+    return W.with_pair_terms(m, pairs, rng.normal(size=k), jh, jx, rng.normal(size=k))
+
+
+@pytest.mark.parametrize("n,seed", [(3, 10), (4, 11), (5, 12)])
+def test_two_body_matches_jordan_wigner(n, seed):
+    m = random_extended(n, seed)
+    assert m.n_pairs > 0
+    Hfull = jw_dense_extended(m)
+    for nu in range(n + 1):
+        for nd in range(n + 1):
+            ups, dns = O.hubbard_basis(n, nu, nd)
+            idx = sector_indices(n, ups, dns)
+            ref = Hfull[idx][:, idx].toarray()
+            Hs = O.hubbard_sparse(m, ups, dns).toarray()
+            assert np.allclose(Hs, ref, atol=1e-12, rtol=0), (nu, nd)
+            v = W.random_vector(len(idx), nu * 7 + nd + 100)
+            assert np.allclose(O.hubbard_hv(m, ups, dns, v), ref @ v, atol=1e-12)
+    # nothing leaks out of the (N_up, N_dn) sectors: the full matrix is
+    # block diagonal in them
+    occ = np.arange(1 << (2 * n))
+    nup = np.array([bin(x & ((1 << n) - 1)).count("1") for x in occ])
+    ndn = np.array([bin(x >> n).count("1") for x in occ])
+    r, cidx = Hfull.nonzero()
+    assert np.all(nup[r] == nup[cidx]) and np.all(ndn[r] == ndn[cidx])
+
+
+def test_two_body_two_sites_closed_form():
+    # t = 0 on a dimer: (1, 1) holds the doublon pair split by pair hopping,
+    # U +- JP, and the opposite-spin pair split by exchange, V +- JX; (2, 0)
+    # is the parallel pair at V - JH
+    u, v, jh, jx, jp = 3.0, 0.7, 0.4, 0.25, 0.15
+    m0 = W.HubbardModel(2, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0),
+                        np.array([u, u]), "dimer")
+    m = W.with_pair_terms(m0, [(0, 1)], v, jh, jx, jp)
+    ev = np.sort(np.linalg.eigvalsh(O.hubbard_sparse(m, *O.hubbard_basis(2, 1, 1)).toarray()))
+    assert np.allclose(ev, np.sort([u + jp, u - jp, v + jx, v - jx]), atol=1e-14)
+    e20 = O.hubbard_sparse(m, *O.hubbard_basis(2, 2, 0)).toarray()
+    assert e20.shape == (1, 1) and abs(e20[0, 0] - (v - jh)) < 1e-15
+
+
+def _sector_spectrum(m, nu, nd):
+    return np.linalg.eigvalsh(O.hubbard_sparse(m, *O.hubbard_basis(m.n_sites, nu, nd)).toarray())
+
+
+@pytest.mark.parametrize("n,seed", [(4, 21), (5, 22)])
+def test_two_body_spin_rotation_invariance(n, seed):
+    """With JH = JX on every pair the two-body terms are spin-rotation
+    invariant (Hund plus exchange is -2J S_i.S_j up to density terms; pair
+    hopping moves singlets), so every level of S^z = 1 reappears at S^z = 0.
+    With JH != JX the invariance is lost and the nesting fails: a wrong
+    relative sign of the exchange would show here."""
+    def nested(m):
+        hi = _sector_spectrum(m, (n + 2) // 2 + 1, (n + 2) // 2 - 1)
+        lo = _sector_spectrum(m, (n + 2) // 2, (n + 2) // 2)
+        return max(np.min(np.abs(lo - e)) for e in hi)
+    assert nested(random_extended(n, seed, tie_hund_exchange=True)) < 1e-10
+    assert nested(random_extended(n, seed, tie_hund_exchange=False)) > 1e-3
+
+
+def test_two_body_rows_and_row_range():
+    m = random_extended(6, 31)
+    ups, dns = O.hubbard_basis(6, 3, 2)
+    Hs = O.hubbard_sparse(m, ups, dns)
+    v = W.random_vector(len(ups) * len(dns), 3)
+    full = O.hubbard_hv(m, ups, dns, v)
+    assert np.allclose(full, Hs @ v, atol=1e-12)
+    part = O.hubbard_hv_rows(m, ups, dns, v, 4, 7)
+    assert np.allclose(part, full[4 * len(dns):11 * len(dns)], atol=1e-13)
+    for ru, rd in [(0, 0), (5, 9), (19, 14)]:
+        cols, vals = O.hubbard_row(m, ups, dns, ru, rd)
+        dense = np.zeros(Hs.shape[0])
+        np.add.at(dense, cols, vals)
+        assert np.allclose(dense, Hs.getrow(ru * len(dns) + rd).toarray()[0], atol=1e-14)
