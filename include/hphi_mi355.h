@@ -160,6 +160,30 @@ int hphi_ham_spin(hphi_basis *b, const hphi_spin_bond *bonds, int n_bonds,
 int hphi_ham_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops,
                      const double *u_site, hphi_ham **out);
 
+/* Two-body terms of one site pair (i, j), i != j (Sec. 5, Eq. ham_general,
+ * with one coefficient per term kind):
+ *   v      inter-site Coulomb   v n_i n_j,  n_i = n_i,up + n_i,dn
+ *   j_hund Hund               - j_hund (n_i,up n_j,up + n_i,dn n_j,dn)
+ *   j_ex   exchange             j_ex (c+_i,up c_j,up c+_j,dn c_i,dn + h.c.)
+ *   j_pair pair hopping         j_pair (c+_i,up c_j,up c+_i,dn c_j,dn + h.c.)
+ * The Wannier-function form of the paper is j_hund = j_ex = j_pair = J_ij. */
+typedef struct { int32_t i, j; double v, j_hund, j_ex, j_pair; } hphi_pair_term;
+
+/* Hubbard Hamiltonian with the two-body terms of Eq. ham_general (Sec. 5):
+ * hphi_ham_hubbard's H plus the listed pair terms (a repeated pair adds).
+ * Every term conserves N_up and N_dn, so the basis is the same (N_up, N_dn)
+ * sector. The terms' fermion signs follow the same ordering (all up
+ * orbitals before all down orbitals): an exchange or pair-hopping element
+ * carries (-1)^(occupied up sites strictly between i and j) times
+ * (-1)^(occupied down sites strictly between i and j). Every method that
+ * takes a Hubbard Hamiltonian takes this one. n_pairs = 0 gives
+ * hphi_ham_hubbard. Errors: INVALID_ARG (site >= n_sites, i == j,
+ * n_pairs < 0 or > 1024, null pairs with n_pairs > 0, and hphi_ham_hubbard's
+ * conditions), OUT_OF_MEMORY, DEVICE. */
+int hphi_ham_hubbard_ext(hphi_basis *b, const hphi_hop *hops, int n_hops,
+                         const double *u_site, const hphi_pair_term *pairs, int n_pairs,
+                         hphi_ham **out);
+
 void hphi_ham_free(hphi_ham *h);
 
 /* Launch schedule of the H*v kernels of one Hamiltonian (set by the

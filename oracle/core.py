@@ -83,6 +83,8 @@ def lib():
         L.or_hubbard_pairs_row.argtypes = [i32, p, i64, p, i64, i32, p, p, p, p, p, p, i64, i64, p, p]
         L.or_hubbard_pairs_hv.restype = None
         L.or_hubbard_pairs_hv.argtypes = [i32, p, i64, p, i64, i32, p, p, p, p, p, p, p, p]
+        L.or_hubbard_pairs_hv_rows.restype = None
+        L.or_hubbard_pairs_hv_rows.argtypes = [i32, p, i64, p, i64, i32, p, p, p, p, p, p, p, i64, i64, p]
         L.or_hubbard_pairs_ell.restype = None
         L.or_hubbard_pairs_ell.argtypes = [i32, p, i64, p, i64, i32, p, p, p, p, p, p, p, p, p]
         _lib = L
@@ -244,10 +246,11 @@ def hubbard_hv_rows(m, ups, dns, v: np.ndarray, ru_first: int, ru_count: int) ->
     lib().or_hubbard_hv_rows(m.n_sites, _p(ups), ups.shape[0], _p(dns), dns.shape[0], hi.shape[0],
                              _p(hi), _p(hj), _p(t), _p(us), _p(vv), int(ru_first), int(ru_count), _p(w))
     if _n_pairs(m):
-        ddn = dns.shape[0]
-        for k in range(ru_count * ddn):
-            cols, vals = hubbard_pairs_row(m, ups, dns, ru_first + k // ddn, k % ddn)
-            w[k] += float(np.dot(vals, vv[cols]))
+        pa = _pair_arrays(m)
+        w2 = np.empty_like(w)
+        lib().or_hubbard_pairs_hv_rows(m.n_sites, _p(ups), ups.shape[0], _p(dns), dns.shape[0], pa[0].shape[0],
+                                       *[_p(x) for x in pa], _p(vv), int(ru_first), int(ru_count), _p(w2))
+        w += w2
     return w
 
 

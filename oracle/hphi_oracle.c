@@ -437,6 +437,31 @@ void or_hubbard_pairs_hv(int nsites, const uint64_t *ups, int64_t dup,
     }
 }
 
+/* Rows [ru_first, ru_first + ru_count) x all r_dn of H_2body v (v is the
+ * whole vector); w holds ru_count * ddn entries. */
+void or_hubbard_pairs_hv_rows(int nsites, const uint64_t *ups, int64_t dup,
+                              const uint64_t *dns, int64_t ddn, int np, const int32_t *pi,
+                              const int32_t *pj, const double *pv, const double *pjh,
+                              const double *pjx, const double *pjp, const double *v,
+                              int64_t ru_first, int64_t ru_count, double *w)
+{
+    #pragma omp parallel
+    {
+        int64_t *cols = (int64_t *)malloc(sizeof(int64_t) * (size_t)(1 + 4 * np));
+        double *vals = (double *)malloc(sizeof(double) * (size_t)(1 + 4 * np));
+        #pragma omp for schedule(static)
+        for (int64_t k = 0; k < ru_count * ddn; ++k) {
+            int m = or_hubbard_pairs_row(nsites, ups, dup, dns, ddn, np, pi, pj, pv, pjh, pjx, pjp,
+                                         ru_first + k / ddn, k % ddn, cols, vals);
+            double acc = 0.0;
+            for (int q = 0; q < m; ++q) acc += vals[q] * v[cols[q]];
+            w[k] = acc;
+        }
+        free(cols);
+        free(vals);
+    }
+}
+
 /* Every row of H_2body in a fixed-stride layout (stride 1 + 4 * np). */
 void or_hubbard_pairs_ell(int nsites, const uint64_t *ups, int64_t dup,
                           const uint64_t *dns, int64_t ddn, int np, const int32_t *pi,

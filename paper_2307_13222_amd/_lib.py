@@ -23,6 +23,11 @@ class Hop(C.Structure):
     _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("t", C.c_double)]
 
 
+class PairTerm(C.Structure):
+    _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("v", C.c_double), ("j_hund", C.c_double),
+                ("j_ex", C.c_double), ("j_pair", C.c_double)]
+
+
 class LanczosOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("check_every", C.c_int), ("tol", C.c_double),
                 ("resid_tol", C.c_double), ("seed", C.c_uint64), ("v0_dev", C.c_void_p), ("storage", C.c_int),
@@ -104,6 +109,7 @@ SIGNATURES = {
                               C.POINTER(C.POINTER(C.c_uint64)), C.POINTER(I), C.POINTER(I)]),
     "hphi_ham_spin": (I, [P, C.POINTER(SpinBond), I, PD, C.POINTER(P)]),
     "hphi_ham_hubbard": (I, [P, C.POINTER(Hop), I, PD, C.POINTER(P)]),
+    "hphi_ham_hubbard_ext": (I, [P, C.POINTER(Hop), I, PD, C.POINTER(PairTerm), I, C.POINTER(P)]),
     "hphi_ham_free": (None, [P]),
     "hphi_ham_set_schedule": (I, [P, C.POINTER(Schedule)]),
     "hphi_ham_get_schedule": (I, [P, C.POINTER(Schedule)]),

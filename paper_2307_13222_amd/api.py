@@ -163,8 +163,17 @@ class Hamiltonian:
             arr[k] = L.Hop(int(m.hi[k]), int(m.hj[k]), float(m.t[k]))
         us = np.ascontiguousarray(m.u_site, dtype=np.float64)
         h = C.c_void_p()
-        _check(L.lib().hphi_ham_hubbard(basis.h, arr, m.n_hops, us.ctypes.data_as(L.PD), C.byref(h)),
-               "hphi_ham_hubbard")
+        n_pairs = getattr(m, "n_pairs", 0)
+        if n_pairs:
+            pa = (L.PairTerm * n_pairs)()
+            for k in range(n_pairs):
+                pa[k] = L.PairTerm(int(m.pi[k]), int(m.pj[k]), float(m.pv[k]), float(m.pjh[k]),
+                                   float(m.pjx[k]), float(m.pjp[k]))
+            _check(L.lib().hphi_ham_hubbard_ext(basis.h, arr, m.n_hops, us.ctypes.data_as(L.PD), pa, n_pairs,
+                                                C.byref(h)), "hphi_ham_hubbard_ext")
+        else:
+            _check(L.lib().hphi_ham_hubbard(basis.h, arr, m.n_hops, us.ctypes.data_as(L.PD), C.byref(h)),
+                   "hphi_ham_hubbard")
         return cls(basis, h, m)
 
     def trace(self, stream=None) -> float:

@@ -714,11 +714,57 @@ static int build_hub_fast(hphi_ham *h)
     return HPHI_OK;
 }
 
-int hphi_ham_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops, const double *u_site, hphi_ham **out)
+// Two-body tables: per-pair records and the same-species diagonal
+// (V - JH) n_i n_j of each up row and each down state.
+static int build_hub_pairs(hphi_ham *h, const hphi_pair_term *pairs, int n_pairs)
 {
-    if (!b || !out || (n_hops > 0 && !hops) || !u_site) return fail(HPHI_ERR_INVALID_ARG, "null argument");
+    hphi_basis *b = h->basis;
+    std::vector<HubPairDev> dev(n_pairs);
+    for (int k = 0; k < n_pairs; ++k) {
+        const int i = pairs[k].i, j = pairs[k].j;
+        if (i < 0 || j < 0 || i >= b->n_sites || j >= b->n_sites || i == j)
+            return fail(HPHI_ERR_INVALID_ARG, "pair term %d (%d, %d) invalid for %d sites", k, i, j, b->n_sites);
+        const int lo = std::min(i, j), hi = std::max(i, j);
+        HubPairDev &q = dev[k];
+        q.mask = (1u << i) | (1u << j);
+        q.between = (hi - lo > 1) ? (((1u << hi) - 1u) & ~((2u << lo) - 1u)) : 0u;
+        q.i = i;
+        q.j = j;
+        q.v = pairs[k].v;
+        q.jh = pairs[k].j_hund;
+        q.jx = pairs[k].j_ex;
+        q.jp = pairs[k].j_pair;
+        h->pair_terms.push_back(pairs[k]);
+    }
+    h->hub.n_pairs = n_pairs;
+    if (n_pairs == 0) return HPHI_OK;
+    if (b->n_sites > 32 || !b->sp[0].d_hi_off32.p || !b->sp[1].d_hi_off32.p)
+        return fail(HPHI_ERR_UNSUPPORTED, "two-body terms need at most 32 sites");
+    HPHI_TRY(upload(h->hub.pairs, dev.data(), sizeof(HubPairDev) * dev.size()));
+    for (int sgm = 0; sgm < 2; ++sgm) {
+        const Species &sp = b->sp[sgm];
+        std::vector<double> e((size_t)sp.dim, 0.0);
+        for (int64_t r = 0; r < sp.dim; ++r) {
+            const uint64_t x = sp.state_at(r);
+            double s = 0.0;
+            for (const HubPairDev &q : dev)
+                if (((x >> q.i) & 1u) && ((x >> q.j) & 1u)) s += q.v - q.jh;
+            e[(size_t)r] = s;
+        }
+        HPHI_TRY(upload(sgm == 0 ? h->hub.pair_eup : h->hub.pair_edn, e.data(), sizeof(double) * e.size()));
+    }
+    return HPHI_OK;
+}
+
+static int make_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops, const double *u_site,
+                        const hphi_pair_term *pairs, int n_pairs, hphi_ham **out)
+{
+    if (!b || !out || (n_hops > 0 && !hops) || !u_site || (n_pairs > 0 && !pairs))
+        return fail(HPHI_ERR_INVALID_ARG, "null argument");
     if (b->kind != 1) return fail(HPHI_ERR_INVALID_ARG, "Hubbard Hamiltonian needs a Hubbard basis");
     if (n_hops < 0 || n_hops > 4096) return fail(HPHI_ERR_INVALID_ARG, "n_hops %d outside [0, 4096]", n_hops);
+    if (n_pairs < 0 || n_pairs > kMaxPairTerms)
+        return fail(HPHI_ERR_INVALID_ARG, "n_pairs %d outside [0, %d]", n_pairs, kMaxPairTerms);
     DeviceGuard g(b->ctx->device);
     std::unique_ptr<hphi_ham> h(new hphi_ham);
     h->basis = b;
@@ -761,9 +807,21 @@ int hphi_ham_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops, const doub
         // the block-tile T_up kernel where its tables could be built
         if (h->hub.ft_ok) h->sched_cfg.hub_sweep = 7;
     }
+    HPHI_TRY(build_hub_pairs(h.get(), pairs, n_pairs));
     HPHI_TRY(ensure_reduce(h.get()));
     *out = h.release();
     return HPHI_OK;
+}
+
+int hphi_ham_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops, const double *u_site, hphi_ham **out)
+{
+    return make_hubbard(b, hops, n_hops, u_site, nullptr, 0, out);
+}
+
+int hphi_ham_hubbard_ext(hphi_basis *b, const hphi_hop *hops, int n_hops, const double *u_site,
+                         const hphi_pair_term *pairs, int n_pairs, hphi_ham **out)
+{
+    return make_hubbard(b, hops, n_hops, u_site, pairs, n_pairs, out);
 }
 
 void hphi_ham_free(hphi_ham *h) { delete h; }

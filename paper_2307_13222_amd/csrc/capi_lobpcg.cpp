@@ -134,6 +134,10 @@ static double lower_bound(const hphi_ham *h)
     } else {
         for (const hphi_hop &p : h->hops) lb -= 2.0 * std::fabs(p.t);
         for (double u : h->u_site) lb += std::min(0.0, u);
+        // two-body terms: n_i n_j in [0, 4], the Hund sum in [0, 2], and
+        // the exchange / pair-hopping blocks at -|J| at worst
+        for (const hphi_pair_term &q : h->pair_terms)
+            lb += std::min(0.0, 4.0 * q.v) + std::min(0.0, -2.0 * q.j_hund) - std::fabs(q.j_ex) - std::fabs(q.j_pair);
     }
     return lb - 1e-3 * (1.0 + std::fabs(lb));
 }

@@ -111,6 +111,15 @@ struct SpinBondDev {
     int32_t pad0, pad1;
 };
 
+// Two-body term of one site pair as the kernels read it.
+struct HubPairDev {
+    uint32_t mask;      // (1 << i) | (1 << j)
+    uint32_t between;   // sites strictly between i and j
+    int32_t i, j;
+    double v, jh, jx, jp;
+};
+constexpr int kMaxPairTerms = 1024;
+
 // Packed Hubbard neighbour entry: bits 0..23 target rank, 24..30 value
 // class, bit 31 fermion sign.
 constexpr uint32_t kNbrColMask = 0x00FFFFFFu;
@@ -166,6 +175,12 @@ struct HubTables {
     bool ft_ok = false;
     int ft_bits = 0, ft_nb = 0, ft_max_rows = 0;
     DevMem ft_blk, ft_pos, ft_off, ft_cnt, ft_ent;
+    // two-body terms of the general Hamiltonian (exchange, pair hopping,
+    // inter-site Coulomb, Hund): per-pair records and the same-species part
+    // of their diagonal per up row and per down state (n_pairs = 0: none)
+    int n_pairs = 0;
+    DevMem pairs;                // HubPairDev [n_pairs]
+    DevMem pair_eup, pair_edn;   // double [dim_up], [dim_dn]
     DevMem coef;     // double [128]: -t per value class
     DevMem u_site;   // double [n_sites]
     int n_coef = 0;
@@ -189,6 +204,7 @@ struct hphi_ham {
     hphi::HubTables hub;
     std::vector<hphi_hop> hops;
     std::vector<double> u_site;
+    std::vector<hphi_pair_term> pair_terms;
     // defaults: 128-column slabs, 128 workgroups per XCD, 32-row items,
     // hop-ordered down slots, work-item queues with two columns per lane;
     // spin: 8 workgroups per CU
@@ -318,6 +334,9 @@ int launch_spin_mult(hphi_ham *h, const MultArgs &a);
 int launch_spin_mult_implicit(hphi_ham *h, const MultArgs &a);
 int launch_hub_mult(hphi_ham *h, const MultArgs &a);
 int launch_mult(hphi_ham *h, const MultArgs &a);
+// w += H_2body v for the Hubbard two-body terms (NV lanes per element, rows
+// of pitch ld elements); a no-op without pair terms
+int launch_hub_pairs(hphi_ham *h, int elem_bytes, int nv, const void *v, void *w, int64_t ld, hipStream_t st);
 
 int launch_rank_device(const hphi_basis *b, const uint64_t *states, int64_t n, int64_t *idx,
                        hipStream_t st);

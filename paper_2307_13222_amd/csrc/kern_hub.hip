@@ -1,5 +1,7 @@
 // Hubbard H*v (HPhi update paper Sec. 3.4, Eq. Hquench with static U;
-// Sec. 5): H = -sum t (c+c + h.c.) + sum_i U_i n_i,up n_i,dn.
+// Sec. 5): H = -sum t (c+c + h.c.) + sum_i U_i n_i,up n_i,dn (the two-body
+// terms of Eq. ham_general, where present, are added by k_hub_pairs
+// between the two kernels below).
 //
 // The (N_up, N_dn) sector is the product of two one-species bases, and with
 // up-major indices a vector is the matrix V[r_up][r_dn]. Because a hop acts
@@ -2350,6 +2352,9 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
                            128 * sizeof(S), st, a);
     }
     HPHI_HIP(hipGetLastError());
+    // two-body terms (exchange, pair hopping, inter-site Coulomb, Hund) add
+    // into the partial product before the T_up kernel completes it
+    HPHI_TRY(launch_hub_pairs(h, (int)sizeof(S), NV, a.v, a.w, a.ld, st));
     if (a.ev_mid) HPHI_HIP(hipEventRecord(a.ev_mid, st));
     // column kernel, geometry from the Hamiltonian's schedule
     const int cw = h->sched_cfg.hub_slab_cols;

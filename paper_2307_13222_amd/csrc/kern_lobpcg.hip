@@ -10,6 +10,7 @@
 //                r_n /= (H_xx - E_shift); E_n read from a Gram diagonal
 //   k_scale    : x_n *= 1 / sqrt(G_nn), G a Gram matrix on the device
 #include "kern_common.h"
+#include "hub_pairs.h"
 
 namespace hphi {
 
@@ -47,17 +48,20 @@ __global__ __launch_bounds__(kBlock) void k_diag_spin(const uint32_t *states, in
 }
 
 __global__ __launch_bounds__(kBlock) void k_diag_hub(const uint32_t *ups, const uint32_t *dns, int64_t dup,
-                                                     int64_t ddn, const double *u_site, double *out)
+                                                     int64_t ddn, const double *u_site, const HubPairDev *pairs,
+                                                     int np, double *out)
 {
     const int64_t n = dup * ddn;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t both = ups[t / ddn] & dns[t % ddn];
+        const uint32_t u = ups[t / ddn], dn = dns[t % ddn];
+        uint32_t both = u & dn;
         double d = 0.0;
         while (both) {
             d += u_site[__builtin_ctz(both)];
             both &= both - 1u;
         }
+        if (np) d += hub_pair_diag(pairs, np, u, dn);
         out[t] = d;
     }
 }
@@ -272,7 +276,7 @@ int launch_diag(hphi_ham *h, double *out, hipStream_t st)
     } else {
         hipLaunchKernelGGL(k_diag_hub, dim3(lob_grid(b->dim)), dim3(kBlock), 0, st, b->sp[0].d_states.as<uint32_t>(),
                            b->sp[1].d_states.as<uint32_t>(), b->sp[0].dim, b->sp[1].dim,
-                           h->hub.u_site.as<double>(), out);
+                           h->hub.u_site.as<double>(), h->hub.pairs.as<HubPairDev>(), h->hub.n_pairs, out);
     }
     HPHI_HIP(hipGetLastError());
     return HPHI_OK;

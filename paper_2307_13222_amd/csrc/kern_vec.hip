@@ -3,6 +3,7 @@
 // Lanczos update, the basis rank/unrank kernels, the trace of H and the
 // S^z(q) excitation.
 #include "kern_common.h"
+#include "hub_pairs.h"
 
 namespace hphi {
 
@@ -559,7 +560,8 @@ __global__ __launch_bounds__(kBlock) void k_trace_spin(const uint32_t *states, i
 }
 
 __global__ __launch_bounds__(kBlock) void k_trace_hub(const uint32_t *ups, const uint32_t *dns, int64_t dup,
-                                                      int64_t ddn, const double *u_site, Reduce red)
+                                                      int64_t ddn, const double *u_site, const HubPairDev *pairs,
+                                                      int np, Reduce red)
 {
     __shared__ double sh[kBlock / kWave];
     __shared__ double blk[1];
@@ -567,11 +569,13 @@ __global__ __launch_bounds__(kBlock) void k_trace_hub(const uint32_t *ups, const
     const int64_t n = dup * ddn;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t both = ups[t / ddn] & dns[t % ddn];
+        const uint32_t u = ups[t / ddn], d = dns[t % ddn];
+        uint32_t both = u & d;
         while (both) {
             acc += u_site[__builtin_ctz(both)];
             both &= both - 1u;
         }
+        if (np) acc += hub_pair_diag(pairs, np, u, d);
     }
     double v[1] = {acc};
     block_sum<1>(v, sh);
@@ -633,7 +637,8 @@ int launch_trace(hphi_ham *h, Reduce red, hipStream_t st)
     } else {
         hipLaunchKernelGGL(k_trace_hub, dim3(grid_for(b->dim, 4)), dim3(kBlock), 0, st,
                            b->sp[0].d_states.as<uint32_t>(), b->sp[1].d_states.as<uint32_t>(),
-                           b->sp[0].dim, b->sp[1].dim, h->hub.u_site.as<double>(), red);
+                           b->sp[0].dim, b->sp[1].dim, h->hub.u_site.as<double>(), h->hub.pairs.as<HubPairDev>(),
+                           h->hub.n_pairs, red);
     }
     HPHI_HIP(hipGetLastError());
     return HPHI_OK;
