@@ -85,6 +85,14 @@ def lib():
         L.or_hubbard_pairs_hv.argtypes = [i32, p, i64, p, i64, i32, p, p, p, p, p, p, p, p]
         L.or_hubbard_pairs_hv_rows.restype = None
         L.or_hubbard_pairs_hv_rows.argtypes = [i32, p, i64, p, i64, i32, p, p, p, p, p, p, p, i64, i64, p]
+        L.or_spin_gc_row.restype = i32
+        L.or_spin_gc_row.argtypes = [i32, i32, p, p, p, p, p, p, p, u64, p, p]
+        L.or_spin_gc_hv.restype = None
+        L.or_spin_gc_hv.argtypes = [i32, i32, p, p, p, p, p, p, p, p, p]
+        L.or_spin_gc_hv_rows.restype = None
+        L.or_spin_gc_hv_rows.argtypes = [i32, i32, p, p, p, p, p, p, p, p, i64, i64, p]
+        L.or_spin_gc_ell.restype = None
+        L.or_spin_gc_ell.argtypes = [i32, i32, p, p, p, p, p, p, p, p, p, p]
         L.or_hubbard_pairs_ell.restype = None
         L.or_hubbard_pairs_ell.argtypes = [i32, p, i64, p, i64, i32, p, p, p, p, p, p, p, p, p]
         _lib = L
@@ -303,6 +311,57 @@ def hubbard_pairs_sparse(m, ups, dns) -> scipy.sparse.csr_matrix:
     cnt = np.zeros(dim, dtype=np.int32)
     lib().or_hubbard_pairs_ell(m.n_sites, _p(ups), ups.shape[0], _p(dns), dns.shape[0], pa[0].shape[0],
                                *[_p(x) for x in pa], _p(cols), _p(vals), _p(cnt))
+    mask = (np.arange(s)[None, :] < cnt[:, None]).ravel()
+    rows = np.repeat(np.arange(dim), s)[mask]
+    return scipy.sparse.csr_matrix((vals[mask], (rows, cols[mask])), shape=(dim, dim))
+
+
+# ---------------------------------------------------------------- SpinGC --
+
+def _gc_arrays(m):
+    f = lambda x: np.ascontiguousarray(x, dtype=np.float64)
+    return (np.ascontiguousarray(m.bi, dtype=np.int32), np.ascontiguousarray(m.bj, dtype=np.int32),
+            f(m.jx), f(m.jy), f(m.jz), f(m.hx), f(m.hz))
+
+
+def spin_gc_hv(m, v: np.ndarray) -> np.ndarray:
+    """H v on the full 2^N space (index = configuration, bit 1 = up)."""
+    v = np.asarray(v)
+    if np.iscomplexobj(v):
+        return spin_gc_hv(m, v.real) + 1j * spin_gc_hv(m, v.imag)
+    ga = _gc_arrays(m)
+    vv = np.ascontiguousarray(v, dtype=np.float64)
+    w = np.empty_like(vv)
+    lib().or_spin_gc_hv(m.n_sites, ga[0].shape[0], *[_p(x) for x in ga], _p(vv), _p(w))
+    return w
+
+
+def spin_gc_hv_rows(m, v: np.ndarray, first: int, count: int) -> np.ndarray:
+    ga = _gc_arrays(m)
+    vv = np.ascontiguousarray(v, dtype=np.float64)
+    w = np.empty(count)
+    lib().or_spin_gc_hv_rows(m.n_sites, ga[0].shape[0], *[_p(x) for x in ga], _p(vv), int(first), int(count),
+                             _p(w))
+    return w
+
+
+def spin_gc_row(m, x: int):
+    ga = _gc_arrays(m)
+    cap = 1 + 3 * ga[0].shape[0] + m.n_sites
+    cols = np.empty(cap, dtype=np.int64)
+    vals = np.empty(cap, dtype=np.float64)
+    k = lib().or_spin_gc_row(m.n_sites, ga[0].shape[0], *[_p(a) for a in ga], ctypes.c_uint64(int(x)),
+                             _p(cols), _p(vals))
+    return cols[:k].copy(), vals[:k].copy()
+
+
+def spin_gc_sparse(m) -> scipy.sparse.csr_matrix:
+    ga = _gc_arrays(m)
+    dim, s = 1 << m.n_sites, 1 + 3 * ga[0].shape[0] + m.n_sites
+    cols = np.zeros(dim * s, dtype=np.int64)
+    vals = np.zeros(dim * s, dtype=np.float64)
+    cnt = np.zeros(dim, dtype=np.int32)
+    lib().or_spin_gc_ell(m.n_sites, ga[0].shape[0], *[_p(x) for x in ga], _p(cols), _p(vals), _p(cnt))
     mask = (np.arange(s)[None, :] < cnt[:, None]).ravel()
     rows = np.repeat(np.arange(dim), s)[mask]
     return scipy.sparse.csr_matrix((vals[mask], (rows, cols[mask])), shape=(dim, dim))

@@ -13,6 +13,8 @@
  *     spin or particle positions);
  *   - the spin-1/2 XXZ Hamiltonian applied to a vector, row by row
  *     (Heisenberg model of Sec. 3.2, S^z = (n_up - n_dn)/2);
+ *   - the spin-1/2 XYZ Hamiltonian with transverse and longitudinal fields
+ *     on the full 2^N space (SpinGC of Sec. 4.1), Pauli by Pauli;
  *   - the Hubbard Hamiltonian -t sum c^+c + U n_up n_dn applied to a vector
  *     (Sec. 3.4, Eq. Hquench; Sec. 5 transfer integrals), with the fermion
  *     sign written out from the anticommutation relations, and the two-body
@@ -336,6 +338,134 @@ int or_hubbard_row(int nsites, const uint64_t *ups, int64_t dup,
         }
     }
     return m;
+}
+
+/* ----------------------------------------------------------- SpinGC -- */
+
+/* Pauli matrix sigma^a (a = 0: x, 1: y, 2: z) on site i applied to the
+ * configuration x (bit 1 = up): returns x' and the amplitude
+ * <x'| sigma^a_i |x> = re + i im. In the basis (up, down),
+ * sigma^x = [[0, 1], [1, 0]], sigma^y = [[0, -i], [i, 0]],
+ * sigma^z = [[1, 0], [0, -1]]. */
+static uint64_t pauli_apply(int a, int i, uint64_t x, double *re, double *im)
+{
+    const int up = (int)((x >> i) & 1);
+    if (a == 2) {
+        *re = up ? 1.0 : -1.0;
+        *im = 0.0;
+        return x;
+    }
+    const uint64_t y = x ^ ((uint64_t)1 << i);
+    if (a == 0) {
+        *re = 1.0;
+        *im = 0.0;
+    } else {
+        /* column up -> (0, i): the down component gets +i; column down ->
+         * (-i, 0): the up component gets -i */
+        *re = 0.0;
+        *im = up ? 1.0 : -1.0;
+    }
+    return y;
+}
+
+/* One row of the spin-1/2 Hamiltonian on the full 2^N space (SpinGC model
+ * keyword, Sec. 4.1 Table "Keywords": no S^z conservation):
+ *   H = sum_b [jx S^x_i S^x_j + jy S^y_i S^y_j + jz S^z_i S^z_j]
+ *       - sum_i (hx_i S^x_i + hz_i S^z_i),   S^a = sigma^a / 2.
+ * Every product is applied Pauli by Pauli; the index of a configuration is
+ * the configuration itself. Entries: diagonal first, then one per
+ * off-diagonal term (a target may repeat). Returns the count. */
+int or_spin_gc_row(int nsites, int nb, const int32_t *bi, const int32_t *bj, const double *jx,
+                   const double *jy, const double *jz, const double *hx, const double *hz,
+                   uint64_t x, int64_t *cols, double *vals)
+{
+    double diag = 0.0;
+    int m = 1;
+    for (int b = 0; b < nb; ++b) {
+        const double jab[3] = {jx[b], jy[b], jz[b]};
+        for (int a = 0; a < 3; ++a) {
+            if (jab[a] == 0.0) continue;
+            double r1, i1, r2, i2;
+            uint64_t y = pauli_apply(a, bj[b], x, &r1, &i1);
+            y = pauli_apply(a, bi[b], y, &r2, &i2);
+            const double re = r1 * r2 - i1 * i2;   /* the imaginary part cancels */
+            const double val = 0.25 * jab[a] * re;
+            if (y == x) diag += val;
+            else { cols[m] = (int64_t)y; vals[m] = val; ++m; }
+        }
+    }
+    for (int i = 0; i < nsites; ++i) {
+        double re, im;
+        if (hx && hx[i] != 0.0) {
+            uint64_t y = pauli_apply(0, i, x, &re, &im);
+            cols[m] = (int64_t)y; vals[m] = -0.5 * hx[i] * re; ++m;
+        }
+        if (hz && hz[i] != 0.0) {
+            pauli_apply(2, i, x, &re, &im);
+            diag += -0.5 * hz[i] * re;
+        }
+    }
+    cols[0] = (int64_t)x;
+    vals[0] = diag;
+    return m;
+}
+
+/* w = H v on the full space (every row through or_spin_gc_row). */
+void or_spin_gc_hv(int nsites, int nb, const int32_t *bi, const int32_t *bj, const double *jx,
+                   const double *jy, const double *jz, const double *hx, const double *hz,
+                   const double *v, double *w)
+{
+    const int64_t dim = (int64_t)1 << nsites;
+    const int cap = 1 + 3 * nb + nsites;
+    #pragma omp parallel
+    {
+        int64_t *cols = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+        double *vals = (double *)malloc(sizeof(double) * (size_t)cap);
+        #pragma omp for schedule(static)
+        for (int64_t x = 0; x < dim; ++x) {
+            int m = or_spin_gc_row(nsites, nb, bi, bj, jx, jy, jz, hx, hz, (uint64_t)x, cols, vals);
+            double acc = 0.0;
+            for (int k = 0; k < m; ++k) acc += vals[k] * v[cols[k]];
+            w[x] = acc;
+        }
+        free(cols);
+        free(vals);
+    }
+}
+
+/* Rows [first, first + count) of H v; w holds count entries. */
+void or_spin_gc_hv_rows(int nsites, int nb, const int32_t *bi, const int32_t *bj, const double *jx,
+                        const double *jy, const double *jz, const double *hx, const double *hz,
+                        const double *v, int64_t first, int64_t count, double *w)
+{
+    const int cap = 1 + 3 * nb + nsites;
+    #pragma omp parallel
+    {
+        int64_t *cols = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+        double *vals = (double *)malloc(sizeof(double) * (size_t)cap);
+        #pragma omp for schedule(static)
+        for (int64_t k = 0; k < count; ++k) {
+            int m = or_spin_gc_row(nsites, nb, bi, bj, jx, jy, jz, hx, hz, (uint64_t)(first + k), cols, vals);
+            double acc = 0.0;
+            for (int q = 0; q < m; ++q) acc += vals[q] * v[cols[q]];
+            w[k] = acc;
+        }
+        free(cols);
+        free(vals);
+    }
+}
+
+/* Every row in a fixed-stride layout (stride 1 + 3 nb + nsites). */
+void or_spin_gc_ell(int nsites, int nb, const int32_t *bi, const int32_t *bj, const double *jx,
+                    const double *jy, const double *jz, const double *hx, const double *hz,
+                    int64_t *cols, double *vals, int32_t *count)
+{
+    const int64_t dim = (int64_t)1 << nsites;
+    const int64_t stride = 1 + 3 * (int64_t)nb + nsites;
+    #pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < dim; ++x)
+        count[x] = or_spin_gc_row(nsites, nb, bi, bj, jx, jy, jz, hx, hz, (uint64_t)x, cols + x * stride,
+                                  vals + x * stride);
 }
 
 /* ------------------------------------------------ Hubbard two-body terms -- */

@@ -66,6 +66,50 @@ class HubbardModel:
         return 0 if self.pi is None else int(self.pi.shape[0])
 
 
+@dataclass
+class SpinGCModel:
+    """Spin-1/2 model without S^z conservation (SpinGC keyword, Sec. 4.1):
+    H = sum_b (jx S^x_i S^x_j + jy S^y_i S^y_j + jz S^z_i S^z_j)
+        - sum_i (hx_i S^x_i + hz_i S^z_i)."""
+    n_sites: int
+    bi: np.ndarray
+    bj: np.ndarray
+    jx: np.ndarray
+    jy: np.ndarray
+    jz: np.ndarray
+    hx: np.ndarray
+    hz: np.ndarray
+    name: str = ""
+
+    @property
+    def n_bonds(self) -> int:
+        return int(self.bi.shape[0])
+
+
+def spin_gc(n: int, pairs, jx, jy, jz, hx=0.0, hz=0.0, name: str = "") -> SpinGCModel:
+    p = np.asarray(pairs, dtype=np.int32).reshape(-1, 2)
+    k = len(p)
+    bonds = lambda x: np.broadcast_to(np.asarray(x, dtype=np.float64), (k,)).copy()
+    sites = lambda x: np.broadcast_to(np.asarray(x, dtype=np.float64), (n,)).copy()
+    return SpinGCModel(n, p[:, 0].copy(), p[:, 1].copy(), bonds(jx), bonds(jy), bonds(jz), sites(hx), sites(hz),
+                       name)
+
+
+def tfim_chain(n: int, j: float = 1.0, g: float = 1.0) -> SpinGCModel:
+    """Transverse-field Ising ring -J sum sigma^z sigma^z - g sum sigma^x,
+    written in spin operators (sigma = 2 S): jz = -4 J, hx = 2 g."""
+    return spin_gc(n, chain_pairs(n), 0.0, 0.0, -4.0 * j, 2.0 * g, 0.0, f"tfim_chain_{n}")
+
+
+def random_spin_gc(n: int, lattice: str, seed: int) -> SpinGCModel:
+    """XYZ couplings and both fields drawn from N(0, 1) on a chain or ladder."""
+    rng = np.random.default_rng(seed)
+    pairs = chain_pairs(n) if lattice == "chain" else ladder_pairs(n)
+    k = len(pairs)
+    return spin_gc(n, pairs, rng.normal(size=k), rng.normal(size=k), rng.normal(size=k),
+                   rng.normal(size=n), rng.normal(size=n), f"random_gc_{lattice}_{n}")
+
+
 def _spin(n, pairs, couplings, name, site_x=None, hz=None) -> SpinModel:
     pairs = np.asarray(pairs, dtype=np.int32).reshape(-1, 2)
     c = np.asarray(couplings, dtype=np.float64).reshape(-1, 2)
