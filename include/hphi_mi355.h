@@ -107,6 +107,12 @@ int hphi_basis_spin(hphi_ctx *ctx, int n_sites, int two_sz, hphi_basis **out);
  * [0, n_sites]), DIM_OVERFLOW, OUT_OF_MEMORY, DEVICE. */
 int hphi_basis_hubbard(hphi_ctx *ctx, int n_sites, int n_up, int n_dn, hphi_basis **out);
 
+/* The whole 2^N spin-1/2 space, no S^z conservation (SpinGC keyword,
+ * Sec. 4.1, Table "Keywords"): the index of a configuration is the
+ * configuration (bit i = 1: site i up). Nothing is stored. Errors:
+ * INVALID_ARG (n_sites < 1 or > 32). */
+int hphi_basis_spin_gc(hphi_ctx *ctx, int n_sites, hphi_basis **out);
+
 void hphi_basis_free(hphi_basis *b);
 
 /* Dimension of the sector (number of basis states). */
@@ -129,7 +135,8 @@ int hphi_basis_rank_device(const hphi_basis *b, const uint64_t *states_dev, int6
                            int64_t *idx_dev, void *stream);
 
 /* Read-only host view of the rank tables of one species (spin: species 0;
- * Hubbard: 0 = up, 1 = down). Pointers stay valid until hphi_basis_free.
+ * Hubbard: 0 = up, 1 = down; a SpinGC basis has none: UNSUPPORTED).
+ * Pointers stay valid until hphi_basis_free.
  * lo_rank has 2^n_lo entries, hi_off 2^n_hi + 1 (the last is the total). */
 int hphi_basis_tables(const hphi_basis *b, int species, const uint32_t **lo_rank,
                       const uint64_t **hi_off, int *n_lo, int *n_hi);
@@ -159,6 +166,22 @@ int hphi_ham_spin(hphi_basis *b, const hphi_spin_bond *bonds, int n_bonds,
  * more than 128 distinct t values), OUT_OF_MEMORY, DEVICE. */
 int hphi_ham_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops,
                      const double *u_site, hphi_ham **out);
+
+/* One anisotropic spin bond:
+ * H += jx S^x_i S^x_j + jy S^y_i S^y_j + jz S^z_i S^z_j. */
+typedef struct { int32_t i, j; double jx, jy, jz; } hphi_xyz_bond;
+
+/* Spin-1/2 Hamiltonian without S^z conservation on a SpinGC basis (SpinGC
+ * keyword, Sec. 4.1):
+ *   H = sum_b [jx S^x_i S^x_j + jy S^y_i S^y_j + jz S^z_i S^z_j]
+ *       - sum_i (hx[i] S^x_i + hz[i] S^z_i)        (hx, hz may be NULL).
+ * Every coefficient is real, so H is a real symmetric matrix; jx != jy and
+ * hx break S^z conservation. Every method takes it with one real or
+ * complex vector per call (as the Hubbard Hamiltonians); S(q, w) works on
+ * it through hphi_szq. Errors: INVALID_ARG (site >= n_sites, i == j,
+ * n_bonds < 0 or > 4096, basis not SpinGC), OUT_OF_MEMORY, DEVICE. */
+int hphi_ham_spin_gc(hphi_basis *b, const hphi_xyz_bond *bonds, int n_bonds, const double *hx,
+                     const double *hz, hphi_ham **out);
 
 /* Two-body terms of one site pair (i, j), i != j (Sec. 5, Eq. ham_general,
  * with one coefficient per term kind):

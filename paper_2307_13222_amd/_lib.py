@@ -23,6 +23,10 @@ class Hop(C.Structure):
     _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("t", C.c_double)]
 
 
+class XyzBond(C.Structure):
+    _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("jx", C.c_double), ("jy", C.c_double), ("jz", C.c_double)]
+
+
 class PairTerm(C.Structure):
     _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("v", C.c_double), ("j_hund", C.c_double),
                 ("j_ex", C.c_double), ("j_pair", C.c_double)]
@@ -99,6 +103,8 @@ SIGNATURES = {
     "hphi_fini": (None, [P]),
     "hphi_basis_spin": (I, [P, I, I, C.POINTER(P)]),
     "hphi_basis_hubbard": (I, [P, I, I, I, C.POINTER(P)]),
+    "hphi_basis_spin_gc": (I, [P, I, C.POINTER(P)]),
+    "hphi_ham_spin_gc": (I, [P, C.POINTER(XyzBond), I, PD, PD, C.POINTER(P)]),
     "hphi_basis_free": (None, [P]),
     "hphi_basis_dim": (I64, [P]),
     "hphi_basis_states": (I, [P, I64, I64, P]),

@@ -85,6 +85,15 @@ class Basis:
         return b
 
     @classmethod
+    def spin_gc(cls, ctx: Context, n_sites: int) -> "Basis":
+        """The whole 2^N spin-1/2 space (index = configuration)."""
+        h = C.c_void_p()
+        _check(L.lib().hphi_basis_spin_gc(ctx.h, n_sites, C.byref(h)), "hphi_basis_spin_gc")
+        b = cls(ctx, h, "spin_gc")
+        b.n_sites = n_sites
+        return b
+
+    @classmethod
     def hubbard(cls, ctx: Context, n_sites: int, n_up: int, n_dn: int) -> "Basis":
         h = C.c_void_p()
         _check(L.lib().hphi_basis_hubbard(ctx.h, n_sites, n_up, n_dn, C.byref(h)), "hphi_basis_hubbard")
@@ -154,6 +163,18 @@ class Hamiltonian:
             hz = hz_a.ctypes.data_as(L.PD)
         h = C.c_void_p()
         _check(L.lib().hphi_ham_spin(basis.h, arr, m.n_bonds, hz, C.byref(h)), "hphi_ham_spin")
+        return cls(basis, h, m)
+
+    @classmethod
+    def spin_gc(cls, basis: Basis, m) -> "Hamiltonian":
+        arr = (L.XyzBond * max(1, m.n_bonds))()
+        for k in range(m.n_bonds):
+            arr[k] = L.XyzBond(int(m.bi[k]), int(m.bj[k]), float(m.jx[k]), float(m.jy[k]), float(m.jz[k]))
+        hx = np.ascontiguousarray(m.hx, dtype=np.float64)
+        hz = np.ascontiguousarray(m.hz, dtype=np.float64)
+        h = C.c_void_p()
+        _check(L.lib().hphi_ham_spin_gc(basis.h, arr, m.n_bonds, hx.ctypes.data_as(L.PD), hz.ctypes.data_as(L.PD),
+                                        C.byref(h)), "hphi_ham_spin_gc")
         return cls(basis, h, m)
 
     @classmethod

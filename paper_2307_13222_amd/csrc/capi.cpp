@@ -48,9 +48,12 @@ int init_ham_use(hphi_ham *h)
     return HPHI_OK;
 }
 
+int ham_ensure_reduce(hphi_ham *h) { return ensure_reduce(h); }
+
 int launch_mult(hphi_ham *h, const MultArgs &a)
 {
     if (h->kind == 0) return launch_spin_mult(h, a);
+    if (h->kind == 2) return launch_gc_mult(h, a);
     return launch_hub_mult(h, a);
 }
 
@@ -144,7 +147,9 @@ int hphi_basis_states(const hphi_basis *b, int64_t first, int64_t count, uint64_
     if (first < 0 || count < 0 || first + count > b->dim) return fail(HPHI_ERR_INVALID_ARG, "range outside the basis");
     for (int64_t t = 0; t < count; ++t) {
         const int64_t r = first + t;
-        if (b->kind == 0) {
+        if (b->kind == 2) {
+            host_out[t] = (uint64_t)r;
+        } else if (b->kind == 0) {
             host_out[t] = b->sp[0].state_at(r);
         } else {
             const int64_t ru = r / b->sp[1].dim, rd = r % b->sp[1].dim;
@@ -158,7 +163,9 @@ int hphi_basis_rank(const hphi_basis *b, const uint64_t *states, int64_t n, int6
 {
     if (!b || ((!states || !idx_out) && n > 0)) return fail(HPHI_ERR_INVALID_ARG, "null argument");
     for (int64_t t = 0; t < n; ++t) {
-        if (b->kind == 0) {
+        if (b->kind == 2) {
+            idx_out[t] = states[t] < (uint64_t)b->dim ? (int64_t)states[t] : -1;
+        } else if (b->kind == 0) {
             idx_out[t] = b->sp[0].rank_of(states[t]);
         } else {
             const int64_t ru = b->sp[0].rank_of(states[t] >> 32);
@@ -174,6 +181,7 @@ int hphi_basis_states_device(const hphi_basis *b, int64_t first, int64_t count, 
     if (!b || (!out_dev && count > 0)) return fail(HPHI_ERR_INVALID_ARG, "null argument");
     if (first < 0 || count < 0 || first + count > b->dim) return fail(HPHI_ERR_INVALID_ARG, "range outside the basis");
     DeviceGuard g(b->ctx->device);
+    if (b->kind == 2) return launch_gc_states(b, first, count, out_dev, (hipStream_t)stream);
     return launch_states_device(b, first, count, out_dev, (hipStream_t)stream);
 }
 
@@ -181,12 +189,14 @@ int hphi_basis_rank_device(const hphi_basis *b, const uint64_t *states_dev, int6
 {
     if (!b || ((!states_dev || !idx_dev) && n > 0) || n < 0) return fail(HPHI_ERR_INVALID_ARG, "bad argument");
     DeviceGuard g(b->ctx->device);
+    if (b->kind == 2) return launch_gc_rank(b, states_dev, n, idx_dev, (hipStream_t)stream);
     return launch_rank_device(b, states_dev, n, idx_dev, (hipStream_t)stream);
 }
 
 int hphi_basis_tables(const hphi_basis *b, int species, const uint32_t **lo_rank, const uint64_t **hi_off,
                       int *n_lo, int *n_hi)
 {
+    if (b && b->kind == 2) return fail(HPHI_ERR_UNSUPPORTED, "a SpinGC basis has no rank tables");
     if (!b || species < 0 || species > b->kind) return fail(HPHI_ERR_INVALID_ARG, "bad species");
     const Species &s = b->sp[species];
     if (lo_rank) *lo_rank = s.lo_rank.data();

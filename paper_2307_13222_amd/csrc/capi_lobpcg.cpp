@@ -131,6 +131,13 @@ static double lower_bound(const hphi_ham *h)
             lb += std::min(jz / 4.0, -jz / 4.0 - std::fabs(jxy) / 2.0);
         }
         // field terms -h_i S^z_i: at least -|h_i| / 2 each (not stored on the host: bound by the bond sum)
+    } else if (h->kind == 2) {
+        // each bond's eigenvalues are at least -(|jx| + |jy| + |jz|) / 4, each field's -|h| / 2
+        for (const hphi_xyz_bond &b : h->xyz) lb -= 0.25 * (std::fabs(b.jx) + std::fabs(b.jy) + std::fabs(b.jz));
+        for (size_t i = 0; i < h->hx.size() || i < h->hz_gc.size(); ++i) {
+            const double x = i < h->hx.size() ? h->hx[i] : 0.0, z = i < h->hz_gc.size() ? h->hz_gc[i] : 0.0;
+            lb -= 0.5 * std::sqrt(x * x + z * z);
+        }
     } else {
         for (const hphi_hop &p : h->hops) lb -= 2.0 * std::fabs(p.t);
         for (double u : h->u_site) lb += std::min(0.0, u);

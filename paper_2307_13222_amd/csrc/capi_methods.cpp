@@ -33,8 +33,8 @@ int hphi_ctpq(hphi_ham *h, const hphi_ctpq_opts *o, void *phi_dev, double *D_out
     if (o->k_steps < 0 || !(o->dtau > 0.0)) return fail(HPHI_ERR_INVALID_ARG, "k_steps / dtau");
     if (o->storage != HPHI_C128 && o->storage != HPHI_C64)
         return fail(HPHI_ERR_INVALID_ARG, "cTPQ storage must be C128 or C64");
-    if (h->kind == 1 && o->n_vec != 1)
-        return fail(HPHI_ERR_UNSUPPORTED, "Hubbard cTPQ runs one vector per call");
+    if (h->kind != 0 && o->n_vec != 1)
+        return fail(HPHI_ERR_UNSUPPORTED, "Hubbard and SpinGC cTPQ run one vector per call");
     DeviceGuard g(h->basis->ctx->device);
     hipStream_t st = (hipStream_t)o->stream;
     HPHI_USE_HAM(h, st);
@@ -188,8 +188,8 @@ int hphi_time_evolve(hphi_ham *h, const hphi_tevol_opts *o, void *psi_dev, doubl
         return fail(HPHI_ERR_INVALID_ARG, "n_steps / dt");
     if (o->storage != HPHI_C128 && o->storage != HPHI_C64)
         return fail(HPHI_ERR_INVALID_ARG, "time evolution storage must be C128 or C64");
-    if (h->kind == 1 && o->n_vec != 1)
-        return fail(HPHI_ERR_UNSUPPORTED, "Hubbard time evolution runs one vector per call");
+    if (h->kind != 0 && o->n_vec != 1)
+        return fail(HPHI_ERR_UNSUPPORTED, "Hubbard and SpinGC time evolution run one vector per call");
     if (docc_out && h->kind != 1) return fail(HPHI_ERR_INVALID_ARG, "double occupancy needs a Hubbard model");
     DeviceGuard g(h->basis->ctx->device);
     hipStream_t st = (hipStream_t)o->stream;

@@ -94,7 +94,7 @@ struct hphi_ctx {
 
 struct hphi_basis {
     hphi_ctx *ctx = nullptr;
-    int kind = 0;  // 0 = spin, 1 = Hubbard
+    int kind = 0;  // 0 = spin, 1 = Hubbard, 2 = spin on the full 2^N space (SpinGC)
     int n_sites = 0;
     int64_t dim = 0;
     hphi::Species sp[2];
@@ -119,6 +119,38 @@ struct HubPairDev {
     double v, jh, jx, jp;
 };
 constexpr int kMaxPairTerms = 1024;
+
+// SpinGC (full 2^N space): one off-diagonal term of a bit window. The
+// tile index l holds the low bits and the window's bits; the term maps l to
+// l ^ mloc with coefficient cpar when bits pi and pj of l agree, else canti
+// (a field term has pi = pj).
+struct GcTermDev {
+    uint32_t mloc;
+    uint32_t pi, pj;
+    uint32_t pad;
+    double cpar, canti;
+};
+struct GcDiagDev {
+    uint32_t mask;   // (1 << i) | (1 << j)
+    uint32_t pad;
+    double jz4;      // jz / 4: +jz4 parallel, -jz4 antiparallel
+};
+// A plan of bit windows for one element size: window w takes the tile of
+// 2^(lowb + q_w) states that vary in the low bits and its q_w window bits;
+// the states of tile T have the complement bits set to the bits of T.
+struct GcWindow {
+    int q = 0;
+    uint32_t wmask = 0, compmask = 0;
+    size_t offw_first = 0;     // into GcPlan::offw (2^q entries)
+    int term_first = 0, term_count = 0;
+};
+struct GcPlan {
+    bool built = false;
+    int lowb = 0;
+    std::vector<GcWindow> wins;
+    DevMem offw;    // uint32: scatter of the window index onto the window bits
+    DevMem terms;   // GcTermDev
+};
 
 // Packed Hubbard neighbour entry: bits 0..23 target rank, 24..30 value
 // class, bit 31 fermion sign.
@@ -205,6 +237,14 @@ struct hphi_ham {
     std::vector<hphi_hop> hops;
     std::vector<double> u_site;
     std::vector<hphi_pair_term> pair_terms;
+    // SpinGC: XYZ bonds and fields, diagonal records, window plans per
+    // element size (4, 8, 16 bytes per state)
+    std::vector<hphi_xyz_bond> xyz;
+    std::vector<double> hx, hz_gc;
+    hphi::DevMem gc_diag, gc_hz;
+    int gc_ndiag = 0;
+    bool gc_has_hz = false;
+    hphi::GcPlan gc_plan[3];
     // defaults: 128-column slabs, 128 workgroups per XCD, 32-row items,
     // hop-ordered down slots, work-item queues with two columns per lane;
     // spin: 8 workgroups per CU
@@ -250,6 +290,8 @@ struct HamUse {
 
 // Creates the Hamiltonian's guard event (after its device is current).
 int init_ham_use(hphi_ham *h);
+// reduction and queue scratch of a Hamiltonian (allocated once)
+int ham_ensure_reduce(hphi_ham *h);
 
 } // namespace hphi
 
@@ -337,6 +379,14 @@ int launch_mult(hphi_ham *h, const MultArgs &a);
 // w += H_2body v for the Hubbard two-body terms (NV lanes per element, rows
 // of pitch ld elements); a no-op without pair terms
 int launch_hub_pairs(hphi_ham *h, int elem_bytes, int nv, const void *v, void *w, int64_t ld, hipStream_t st);
+// SpinGC: H*v by bit windows, the diagonal, the trace, S^z(q), states/ranks
+int launch_gc_mult(hphi_ham *h, const MultArgs &a);
+int gc_plan_build(hphi_ham *h, int esz_index);
+int launch_gc_diag(hphi_ham *h, double *out, hipStream_t st);
+int launch_gc_trace(hphi_ham *h, Reduce red, hipStream_t st);
+int launch_gc_szq(hphi_ham *h, const double *phase_dev, const void *psi, void *b, hipStream_t st);
+int launch_gc_states(const hphi_basis *b, int64_t first, int64_t count, uint64_t *out, hipStream_t st);
+int launch_gc_rank(const hphi_basis *b, const uint64_t *states, int64_t n, int64_t *idx, hipStream_t st);
 
 int launch_rank_device(const hphi_basis *b, const uint64_t *states, int64_t n, int64_t *idx,
                        hipStream_t st);
