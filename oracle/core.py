@@ -85,6 +85,13 @@ def lib():
         L.or_hubbard_pairs_hv.argtypes = [i32, p, i64, p, i64, i32, p, p, p, p, p, p, p, p]
         L.or_hubbard_pairs_hv_rows.restype = None
         L.or_hubbard_pairs_hv_rows.argtypes = [i32, p, i64, p, i64, i32, p, p, p, p, p, p, p, i64, i64, p]
+        L.or_spin_s_basis_fill.restype = i64; L.or_spin_s_basis_fill.argtypes = [i32, i32, i32, p, i64]
+        L.or_spin_s_row.restype = i32
+        L.or_spin_s_row.argtypes = [i32, i32, p, i64, i32, p, p, p, p, p, p, i64, p, p]
+        L.or_spin_s_hv.restype = None
+        L.or_spin_s_hv.argtypes = [i32, i32, p, i64, i32, p, p, p, p, p, p, p, p]
+        L.or_spin_s_ell.restype = None
+        L.or_spin_s_ell.argtypes = [i32, i32, p, i64, i32, p, p, p, p, p, p, p, p, p]
         L.or_spin_gc_row.restype = i32
         L.or_spin_gc_row.argtypes = [i32, i32, p, p, p, p, p, p, p, u64, p, p]
         L.or_spin_gc_hv.restype = None
@@ -311,6 +318,67 @@ def hubbard_pairs_sparse(m, ups, dns) -> scipy.sparse.csr_matrix:
     cnt = np.zeros(dim, dtype=np.int32)
     lib().or_hubbard_pairs_ell(m.n_sites, _p(ups), ups.shape[0], _p(dns), dns.shape[0], pa[0].shape[0],
                                *[_p(x) for x in pa], _p(cols), _p(vals), _p(cnt))
+    mask = (np.arange(s)[None, :] < cnt[:, None]).ravel()
+    rows = np.repeat(np.arange(dim), s)[mask]
+    return scipy.sparse.csr_matrix((vals[mask], (rows, cols[mask])), shape=(dim, dim))
+
+
+# ----------------------------------------------------------------- spin-S --
+
+def spin_s_basis(n_sites: int, two_s: int, two_sz: int) -> np.ndarray:
+    """Configurations of n spin-S sites (digit m_i = S^z_i + S in b-bit fields,
+    b the fewest bits holding 2S) with total 2S^z = two_sz, ascending."""
+    msum2 = two_sz + n_sites * two_s
+    if msum2 % 2:
+        raise ValueError("2Sz parity")
+    msum = msum2 // 2
+    n = lib().or_spin_s_basis_fill(n_sites, two_s, msum, None, 0)
+    out = np.empty(max(n, 1), dtype=np.uint64)
+    lib().or_spin_s_basis_fill(n_sites, two_s, msum, _p(out), n)
+    return out[:n]
+
+
+def _spin_s_arrays(m):
+    f = lambda x: np.ascontiguousarray(x, dtype=np.float64)
+    hz = f(m.hz) if m.hz is not None else None
+    d = f(m.d_ion) if m.d_ion is not None else None
+    return (np.ascontiguousarray(m.bi, dtype=np.int32), np.ascontiguousarray(m.bj, dtype=np.int32),
+            f(m.jz), f(m.jxy), hz, d)
+
+
+def _pn(a):
+    return None if a is None else _p(a)
+
+
+def spin_s_hv(m, states: np.ndarray, v: np.ndarray) -> np.ndarray:
+    v = np.asarray(v)
+    if np.iscomplexobj(v):
+        return spin_s_hv(m, states, v.real) + 1j * spin_s_hv(m, states, v.imag)
+    bi, bj, jz, jxy, hz, d = _spin_s_arrays(m)
+    vv = np.ascontiguousarray(v, dtype=np.float64)
+    w = np.empty_like(vv)
+    lib().or_spin_s_hv(m.n_sites, m.two_s, _p(states), states.shape[0], bi.shape[0], _p(bi), _p(bj), _p(jz),
+                       _p(jxy), _pn(hz), _pn(d), _p(vv), _p(w))
+    return w
+
+
+def spin_s_row(m, states: np.ndarray, r: int):
+    bi, bj, jz, jxy, hz, d = _spin_s_arrays(m)
+    cols = np.empty(1 + 2 * bi.shape[0], dtype=np.int64)
+    vals = np.empty(1 + 2 * bi.shape[0])
+    k = lib().or_spin_s_row(m.n_sites, m.two_s, _p(states), states.shape[0], bi.shape[0], _p(bi), _p(bj),
+                            _p(jz), _p(jxy), _pn(hz), _pn(d), int(r), _p(cols), _p(vals))
+    return cols[:k].copy(), vals[:k].copy()
+
+
+def spin_s_sparse(m, states: np.ndarray) -> scipy.sparse.csr_matrix:
+    bi, bj, jz, jxy, hz, d = _spin_s_arrays(m)
+    dim, s = states.shape[0], 1 + 2 * bi.shape[0]
+    cols = np.zeros(dim * s, dtype=np.int64)
+    vals = np.zeros(dim * s, dtype=np.float64)
+    cnt = np.zeros(dim, dtype=np.int32)
+    lib().or_spin_s_ell(m.n_sites, m.two_s, _p(states), dim, bi.shape[0], _p(bi), _p(bj), _p(jz), _p(jxy),
+                        _pn(hz), _pn(d), _p(cols), _p(vals), _p(cnt))
     mask = (np.arange(s)[None, :] < cnt[:, None]).ravel()
     rows = np.repeat(np.arange(dim), s)[mask]
     return scipy.sparse.csr_matrix((vals[mask], (rows, cols[mask])), shape=(dim, dim))

@@ -15,6 +15,8 @@
  *     (Heisenberg model of Sec. 3.2, S^z = (n_up - n_dn)/2);
  *   - the spin-1/2 XYZ Hamiltonian with transverse and longitudinal fields
  *     on the full 2^N space (SpinGC of Sec. 4.1), Pauli by Pauli;
+ *   - the spin-S Heisenberg Hamiltonian with total S^z conserved (keyword
+ *     2S of Sec. 4.1) from the ladder-operator matrix elements;
  *   - the Hubbard Hamiltonian -t sum c^+c + U n_up n_dn applied to a vector
  *     (Sec. 3.4, Eq. Hquench; Sec. 5 transfer integrals), with the fermion
  *     sign written out from the anticommutation relations, and the two-body
@@ -338,6 +340,132 @@ int or_hubbard_row(int nsites, const uint64_t *ups, int64_t dup,
         }
     }
     return m;
+}
+
+/* ----------------------------------------------------------- spin-S -- */
+
+/* Spin-S sites (2S+1 levels; keyword 2S of Sec. 4.1, "Remarks on the keyword
+ * model"): site i holds m_i = S^z_i + S in {0, ..., 2S}, stored in bits
+ * [i b, (i + 1) b) of the configuration, b the fewest bits that hold 2S. */
+static int spin_s_bits(int two_s) { int b = 1; while ((1 << b) <= two_s) ++b; return b; }
+
+static int cmp_u64(const void *a, const void *b)
+{
+    const uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* All configurations with digits <= 2S and digit sum msum, ascending.
+ * Brute force over the (2S+1)^N digit strings. Returns the count (at most
+ * cap written). */
+int64_t or_spin_s_basis_fill(int nsites, int two_s, int msum, uint64_t *out, int64_t cap)
+{
+    const int b = spin_s_bits(two_s);
+    int digits[64];
+    for (int i = 0; i < nsites; ++i) digits[i] = 0;
+    int64_t n = 0;
+    /* odometer over digit strings, site 0 fastest */
+    for (;;) {
+        int sum = 0;
+        for (int i = 0; i < nsites; ++i) sum += digits[i];
+        if (sum == msum) {
+            uint64_t x = 0;
+            for (int i = 0; i < nsites; ++i) x |= (uint64_t)digits[i] << (i * b);
+            if (n < cap) out[n] = x;
+            ++n;
+        }
+        int i = 0;
+        while (i < nsites && digits[i] == two_s) digits[i++] = 0;
+        if (i == nsites) break;
+        ++digits[i];
+    }
+    /* the odometer visits digit strings in an order that is not the
+     * numeric one; sort what was written */
+    int64_t m = n < cap ? n : cap;
+    qsort(out, (size_t)m, sizeof(uint64_t), cmp_u64);
+    return n;
+}
+
+/* <s +- 1| S^+- |s> for spin S (s = m - S): sqrt(S(S+1) - s(s +- 1)). */
+static double ladder_amp(int two_s, int m, int up)
+{
+    const double S = 0.5 * two_s, sz = m - S;
+    return sqrt(S * (S + 1.0) - sz * (sz + (up ? 1.0 : -1.0)));
+}
+
+/* One row of the spin-S Hamiltonian with total S^z conserved:
+ *   H = sum_b [jz S^z_i S^z_j + jxy/2 (S^+_i S^-_j + S^-_i S^+_j)]
+ *       - sum_i hz_i S^z_i + sum_i d_i (S^z_i)^2.
+ * Columns by binary search in the sorted state list. Returns the count. */
+int or_spin_s_row(int nsites, int two_s, const uint64_t *states, int64_t dim, int nb, const int32_t *bi,
+                  const int32_t *bj, const double *jz, const double *jxy, const double *hz, const double *dion,
+                  int64_t r, int64_t *cols, double *vals)
+{
+    const int b = spin_s_bits(two_s);
+    const uint64_t dmask = ((uint64_t)1 << b) - 1;
+    const uint64_t x = states[r];
+    const double S = 0.5 * two_s;
+    double diag = 0.0;
+    int m = 1;
+    for (int k = 0; k < nb; ++k) {
+        const int i = bi[k], j = bj[k];
+        const int mi = (int)((x >> (i * b)) & dmask), mj = (int)((x >> (j * b)) & dmask);
+        diag += jz[k] * (mi - S) * (mj - S);
+        if (jxy[k] == 0.0) continue;
+        /* S^+_i S^-_j */
+        if (mi < two_s && mj > 0) {
+            uint64_t y = x + ((uint64_t)1 << (i * b)) - ((uint64_t)1 << (j * b));
+            cols[m] = or_rank_search(states, dim, y);
+            vals[m] = 0.5 * jxy[k] * ladder_amp(two_s, mi, 1) * ladder_amp(two_s, mj, 0);
+            ++m;
+        }
+        /* S^-_i S^+_j */
+        if (mi > 0 && mj < two_s) {
+            uint64_t y = x - ((uint64_t)1 << (i * b)) + ((uint64_t)1 << (j * b));
+            cols[m] = or_rank_search(states, dim, y);
+            vals[m] = 0.5 * jxy[k] * ladder_amp(two_s, mi, 0) * ladder_amp(two_s, mj, 1);
+            ++m;
+        }
+    }
+    for (int i = 0; i < nsites; ++i) {
+        const double sz = (double)((x >> (i * b)) & dmask) - S;
+        if (hz) diag -= hz[i] * sz;
+        if (dion) diag += dion[i] * sz * sz;
+    }
+    cols[0] = r;
+    vals[0] = diag;
+    return m;
+}
+
+void or_spin_s_hv(int nsites, int two_s, const uint64_t *states, int64_t dim, int nb, const int32_t *bi,
+                  const int32_t *bj, const double *jz, const double *jxy, const double *hz, const double *dion,
+                  const double *v, double *w)
+{
+    #pragma omp parallel
+    {
+        int64_t *cols = (int64_t *)malloc(sizeof(int64_t) * (size_t)(1 + 2 * nb));
+        double *vals = (double *)malloc(sizeof(double) * (size_t)(1 + 2 * nb));
+        #pragma omp for schedule(static)
+        for (int64_t r = 0; r < dim; ++r) {
+            int m = or_spin_s_row(nsites, two_s, states, dim, nb, bi, bj, jz, jxy, hz, dion, r, cols, vals);
+            double acc = 0.0;
+            for (int k = 0; k < m; ++k) acc += vals[k] * v[cols[k]];
+            w[r] = acc;
+        }
+        free(cols);
+        free(vals);
+    }
+}
+
+void or_spin_s_ell(int nsites, int two_s, const uint64_t *states, int64_t dim, int nb, const int32_t *bi,
+                   const int32_t *bj, const double *jz, const double *jxy, const double *hz, const double *dion,
+                   int64_t *cols, double *vals, int32_t *count)
+{
+    const int64_t stride = 1 + 2 * (int64_t)nb;
+    #pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < dim; ++r)
+        count[r] = or_spin_s_row(nsites, two_s, states, dim, nb, bi, bj, jz, jxy, hz, dion, r, cols + r * stride,
+                                 vals + r * stride);
 }
 
 /* ----------------------------------------------------------- SpinGC -- */

@@ -67,6 +67,44 @@ class HubbardModel:
 
 
 @dataclass
+class SpinSModel:
+    """Spin-S Heisenberg model (keyword 2S, Sec. 4.1): H = sum_b [jz S^z_i S^z_j
+    + jxy (S^x_i S^x_j + S^y_i S^y_j)] - sum_i hz_i S^z_i + sum_i d_i (S^z_i)^2."""
+    n_sites: int
+    two_s: int
+    bi: np.ndarray
+    bj: np.ndarray
+    jz: np.ndarray
+    jxy: np.ndarray
+    hz: Optional[np.ndarray] = None
+    d_ion: Optional[np.ndarray] = None
+    site_x: Optional[np.ndarray] = None
+    name: str = ""
+
+    @property
+    def n_bonds(self) -> int:
+        return int(self.bi.shape[0])
+
+
+def spin_s_model(n: int, two_s: int, pairs, jz, jxy, hz=None, d_ion=None, name: str = "") -> SpinSModel:
+    p = np.asarray(pairs, dtype=np.int32).reshape(-1, 2)
+    k = len(p)
+    bonds = lambda x: np.broadcast_to(np.asarray(x, dtype=np.float64), (k,)).copy()
+    sites = lambda x: None if x is None else np.broadcast_to(np.asarray(x, dtype=np.float64), (n,)).copy()
+    return SpinSModel(n, two_s, p[:, 0].copy(), p[:, 1].copy(), bonds(jz), bonds(jxy), sites(hz), sites(d_ion),
+                      np.arange(n, dtype=np.int64), name)
+
+
+def random_spin_s(n: int, two_s: int, lattice: str, seed: int) -> SpinSModel:
+    """XXZ couplings in [0.5, 1.5), fields and single-ion terms from N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    pairs = chain_pairs(n) if lattice == "chain" else ladder_pairs(n)
+    k = len(pairs)
+    return spin_s_model(n, two_s, pairs, rng.uniform(0.5, 1.5, k), rng.uniform(0.5, 1.5, k),
+                        rng.normal(size=n), rng.normal(size=n), f"random_spin{two_s}_{lattice}_{n}")
+
+
+@dataclass
 class SpinGCModel:
     """Spin-1/2 model without S^z conservation (SpinGC keyword, Sec. 4.1):
     H = sum_b (jx S^x_i S^x_j + jy S^y_i S^y_j + jz S^z_i S^z_j)
