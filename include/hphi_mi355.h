@@ -107,6 +107,18 @@ int hphi_basis_spin(hphi_ctx *ctx, int n_sites, int two_sz, hphi_basis **out);
  * [0, n_sites]), DIM_OVERFLOW, OUT_OF_MEMORY, DEVICE. */
 int hphi_basis_hubbard(hphi_ctx *ctx, int n_sites, int n_up, int n_dn, hphi_basis **out);
 
+/* Sector basis of N spin-S sites with total 2S^z = two_sz (keyword 2S,
+ * Sec. 4.1, "Remarks on the keyword model"): site i holds m_i = S^z_i + S in
+ * {0, ..., 2S}, stored in bits [i b, (i + 1) b) of the configuration, with
+ * b = 1 for S = 1/2, 2 for S = 1 and 3/2, 3 up to S = 7/2. States ascend by
+ * that encoding and are ranked by the split table
+ *   idx(x) = hi_off[x >> L] + lo_rank[x & (2^L - 1)],  L = b floor(N/2),
+ * lo_rank counting the lower patterns of equal digit sum. Configurations
+ * (host and device calls) are the encoded values. Errors: INVALID_ARG
+ * (two_s outside [1, 7], n_sites < 1, N b > 40, |two_sz| > 2S N or of the
+ * wrong parity), DIM_OVERFLOW (dimension >= 2^32), OUT_OF_MEMORY, DEVICE. */
+int hphi_basis_spin_s(hphi_ctx *ctx, int n_sites, int two_s, int two_sz, hphi_basis **out);
+
 /* The whole 2^N spin-1/2 space, no S^z conservation (SpinGC keyword,
  * Sec. 4.1, Table "Keywords"): the index of a configuration is the
  * configuration (bit i = 1: site i up). Nothing is stored. Errors:
@@ -135,7 +147,7 @@ int hphi_basis_rank_device(const hphi_basis *b, const uint64_t *states_dev, int6
                            int64_t *idx_dev, void *stream);
 
 /* Read-only host view of the rank tables of one species (spin: species 0;
- * Hubbard: 0 = up, 1 = down; a SpinGC basis has none: UNSUPPORTED).
+ * Hubbard: 0 = up, 1 = down; SpinGC and spin-S bases: UNSUPPORTED).
  * Pointers stay valid until hphi_basis_free.
  * lo_rank has 2^n_lo entries, hi_off 2^n_hi + 1 (the last is the total). */
 int hphi_basis_tables(const hphi_basis *b, int species, const uint32_t **lo_rank,
@@ -166,6 +178,16 @@ int hphi_ham_spin(hphi_basis *b, const hphi_spin_bond *bonds, int n_bonds,
  * more than 128 distinct t values), OUT_OF_MEMORY, DEVICE. */
 int hphi_ham_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops,
                      const double *u_site, hphi_ham **out);
+
+/* Spin-S Heisenberg Hamiltonian on a spin-S basis (keyword 2S, Sec. 4.1):
+ *   H = sum_b [jz S^z_i S^z_j + jxy (S^x_i S^x_j + S^y_i S^y_j)]
+ *       - sum_i hz[i] S^z_i + sum_i d_ion[i] (S^z_i)^2   (hz, d_ion may be NULL),
+ * with the spin-S ladder elements <s+-1| S^+- |s> = sqrt(S(S+1) - s(s+-1)).
+ * Every method takes it with one real or complex vector per call. Errors:
+ * INVALID_ARG (site >= n_sites, i == j, n_bonds < 0 or > 4096, basis not
+ * spin-S), OUT_OF_MEMORY, DEVICE. */
+int hphi_ham_spin_s(hphi_basis *b, const hphi_spin_bond *bonds, int n_bonds, const double *hz,
+                    const double *d_ion, hphi_ham **out);
 
 /* One anisotropic spin bond:
  * H += jx S^x_i S^x_j + jy S^y_i S^y_j + jz S^z_i S^z_j. */

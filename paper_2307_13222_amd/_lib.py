@@ -104,6 +104,8 @@ SIGNATURES = {
     "hphi_basis_spin": (I, [P, I, I, C.POINTER(P)]),
     "hphi_basis_hubbard": (I, [P, I, I, I, C.POINTER(P)]),
     "hphi_basis_spin_gc": (I, [P, I, C.POINTER(P)]),
+    "hphi_basis_spin_s": (I, [P, I, I, I, C.POINTER(P)]),
+    "hphi_ham_spin_s": (I, [P, C.POINTER(SpinBond), I, PD, PD, C.POINTER(P)]),
     "hphi_ham_spin_gc": (I, [P, C.POINTER(XyzBond), I, PD, PD, C.POINTER(P)]),
     "hphi_basis_free": (None, [P]),
     "hphi_basis_dim": (I64, [P]),

@@ -85,6 +85,15 @@ class Basis:
         return b
 
     @classmethod
+    def spin_s(cls, ctx: Context, n_sites: int, two_s: int, two_sz: int) -> "Basis":
+        """Spin-S sector (2S = two_s) with total 2S^z = two_sz."""
+        h = C.c_void_p()
+        _check(L.lib().hphi_basis_spin_s(ctx.h, n_sites, two_s, two_sz, C.byref(h)), "hphi_basis_spin_s")
+        b = cls(ctx, h, "spin_s")
+        b.n_sites = n_sites
+        return b
+
+    @classmethod
     def spin_gc(cls, ctx: Context, n_sites: int) -> "Basis":
         """The whole 2^N spin-1/2 space (index = configuration)."""
         h = C.c_void_p()
@@ -163,6 +172,24 @@ class Hamiltonian:
             hz = hz_a.ctypes.data_as(L.PD)
         h = C.c_void_p()
         _check(L.lib().hphi_ham_spin(basis.h, arr, m.n_bonds, hz, C.byref(h)), "hphi_ham_spin")
+        return cls(basis, h, m)
+
+    @classmethod
+    def spin_s(cls, basis: Basis, m) -> "Hamiltonian":
+        arr = (L.SpinBond * max(1, m.n_bonds))()
+        for k in range(m.n_bonds):
+            arr[k] = L.SpinBond(int(m.bi[k]), int(m.bj[k]), float(m.jz[k]), float(m.jxy[k]))
+        keep = []
+
+        def opt(x):
+            if x is None:
+                return None
+            a = np.ascontiguousarray(x, dtype=np.float64)
+            keep.append(a)
+            return a.ctypes.data_as(L.PD)
+        h = C.c_void_p()
+        _check(L.lib().hphi_ham_spin_s(basis.h, arr, m.n_bonds, opt(m.hz), opt(m.d_ion), C.byref(h)),
+               "hphi_ham_spin_s")
         return cls(basis, h, m)
 
     @classmethod

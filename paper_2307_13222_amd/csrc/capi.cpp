@@ -54,6 +54,7 @@ int launch_mult(hphi_ham *h, const MultArgs &a)
 {
     if (h->kind == 0) return launch_spin_mult(h, a);
     if (h->kind == 2) return launch_gc_mult(h, a);
+    if (h->kind == 3) return launch_spin_s_mult(h, a);
     return launch_hub_mult(h, a);
 }
 
@@ -149,6 +150,8 @@ int hphi_basis_states(const hphi_basis *b, int64_t first, int64_t count, uint64_
         const int64_t r = first + t;
         if (b->kind == 2) {
             host_out[t] = (uint64_t)r;
+        } else if (b->kind == 3) {
+            host_out[t] = b->ss.states[(size_t)r];
         } else if (b->kind == 0) {
             host_out[t] = b->sp[0].state_at(r);
         } else {
@@ -165,6 +168,8 @@ int hphi_basis_rank(const hphi_basis *b, const uint64_t *states, int64_t n, int6
     for (int64_t t = 0; t < n; ++t) {
         if (b->kind == 2) {
             idx_out[t] = states[t] < (uint64_t)b->dim ? (int64_t)states[t] : -1;
+        } else if (b->kind == 3) {
+            idx_out[t] = b->ss.rank_of(states[t]);
         } else if (b->kind == 0) {
             idx_out[t] = b->sp[0].rank_of(states[t]);
         } else {
@@ -182,6 +187,7 @@ int hphi_basis_states_device(const hphi_basis *b, int64_t first, int64_t count, 
     if (first < 0 || count < 0 || first + count > b->dim) return fail(HPHI_ERR_INVALID_ARG, "range outside the basis");
     DeviceGuard g(b->ctx->device);
     if (b->kind == 2) return launch_gc_states(b, first, count, out_dev, (hipStream_t)stream);
+    if (b->kind == 3) return launch_spin_s_states(b, first, count, out_dev, (hipStream_t)stream);
     return launch_states_device(b, first, count, out_dev, (hipStream_t)stream);
 }
 
@@ -190,13 +196,14 @@ int hphi_basis_rank_device(const hphi_basis *b, const uint64_t *states_dev, int6
     if (!b || ((!states_dev || !idx_dev) && n > 0) || n < 0) return fail(HPHI_ERR_INVALID_ARG, "bad argument");
     DeviceGuard g(b->ctx->device);
     if (b->kind == 2) return launch_gc_rank(b, states_dev, n, idx_dev, (hipStream_t)stream);
+    if (b->kind == 3) return launch_spin_s_rank(b, states_dev, n, idx_dev, (hipStream_t)stream);
     return launch_rank_device(b, states_dev, n, idx_dev, (hipStream_t)stream);
 }
 
 int hphi_basis_tables(const hphi_basis *b, int species, const uint32_t **lo_rank, const uint64_t **hi_off,
                       int *n_lo, int *n_hi)
 {
-    if (b && b->kind == 2) return fail(HPHI_ERR_UNSUPPORTED, "a SpinGC basis has no rank tables");
+    if (b && b->kind >= 2) return fail(HPHI_ERR_UNSUPPORTED, "SpinGC and spin-S bases have no species tables");
     if (!b || species < 0 || species > b->kind) return fail(HPHI_ERR_INVALID_ARG, "bad species");
     const Species &s = b->sp[species];
     if (lo_rank) *lo_rank = s.lo_rank.data();

@@ -131,6 +131,15 @@ static double lower_bound(const hphi_ham *h)
             lb += std::min(jz / 4.0, -jz / 4.0 - std::fabs(jxy) / 2.0);
         }
         // field terms -h_i S^z_i: at least -|h_i| / 2 each (not stored on the host: bound by the bond sum)
+    } else if (h->kind == 3) {
+        // per bond |S^z S^z| <= S^2 and |S^x S^x + S^y S^y| = |S.S - S^z S^z|
+        // <= S(S+1) + S^2; |S^z| <= S per field; the single-ion term at
+        // min(0, d) S^2
+        const double S = 0.5 * h->basis->ss.two_s;
+        for (const hphi_spin_bond &b : h->sbonds)
+            lb -= std::fabs(b.jz) * S * S + std::fabs(b.jxy) * (S * (S + 1.0) + S * S);
+        for (double x : h->s_hz) lb -= std::fabs(x) * S;
+        for (double d : h->s_dion) lb += std::min(0.0, d) * S * S;
     } else if (h->kind == 2) {
         // each bond's eigenvalues are at least -(|jx| + |jy| + |jz|) / 4, each field's -|h| / 2
         for (const hphi_xyz_bond &b : h->xyz) lb -= 0.25 * (std::fabs(b.jx) + std::fabs(b.jy) + std::fabs(b.jz));

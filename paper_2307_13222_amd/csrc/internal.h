@@ -92,12 +92,24 @@ struct hphi_ctx {
     size_t lds_per_block = 0;
 };
 
+// Spin-S sector tables (basis kind 3): digits of b bits per site, split
+// two-level rank idx = hi_off[x >> lo_bits] + lo_rank[x & (2^lo_bits - 1)].
+struct SpinSTables {
+    int two_s = 0, bits = 0, lo_bits = 0, hi_bits = 0, msum = 0;
+    std::vector<uint32_t> lo_rank;    // 2^lo_bits (invalid patterns: ~0)
+    std::vector<uint64_t> hi_off;     // 2^hi_bits + 1
+    std::vector<uint64_t> states;     // host copy, ascending
+    hphi::DevMem d_lo_rank, d_hi_off32, d_states;
+    int64_t rank_of(uint64_t x) const;
+};
+
 struct hphi_basis {
     hphi_ctx *ctx = nullptr;
-    int kind = 0;  // 0 = spin, 1 = Hubbard, 2 = spin on the full 2^N space (SpinGC)
+    int kind = 0;  // 0 = spin, 1 = Hubbard, 2 = spin on the full 2^N space (SpinGC), 3 = spin-S
     int n_sites = 0;
     int64_t dim = 0;
     hphi::Species sp[2];
+    SpinSTables ss;
 };
 
 namespace hphi {
@@ -245,6 +257,10 @@ struct hphi_ham {
     int gc_ndiag = 0;
     bool gc_has_hz = false;
     hphi::GcPlan gc_plan[3];
+    // spin-S: bonds as given (jz, jxy), fields and single-ion terms
+    std::vector<hphi_spin_bond> sbonds;
+    std::vector<double> s_hz, s_dion;
+    hphi::DevMem s_dbonds, s_dhz, s_ddion;
     // defaults: 128-column slabs, 128 workgroups per XCD, 32-row items,
     // hop-ordered down slots, work-item queues with two columns per lane;
     // spin: 8 workgroups per CU
@@ -387,6 +403,13 @@ int launch_gc_trace(hphi_ham *h, Reduce red, hipStream_t st);
 int launch_gc_szq(hphi_ham *h, const double *phase_dev, const void *psi, void *b, hipStream_t st);
 int launch_gc_states(const hphi_basis *b, int64_t first, int64_t count, uint64_t *out, hipStream_t st);
 int launch_gc_rank(const hphi_basis *b, const uint64_t *states, int64_t n, int64_t *idx, hipStream_t st);
+// spin-S: H*v, the diagonal, the trace, S^z(q), states/ranks
+int launch_spin_s_mult(hphi_ham *h, const MultArgs &a);
+int launch_spin_s_diag(hphi_ham *h, double *out, hipStream_t st);
+int launch_spin_s_trace(hphi_ham *h, Reduce red, hipStream_t st);
+int launch_spin_s_szq(hphi_ham *h, const double *phase_dev, const void *psi, void *b, hipStream_t st);
+int launch_spin_s_states(const hphi_basis *b, int64_t first, int64_t count, uint64_t *out, hipStream_t st);
+int launch_spin_s_rank(const hphi_basis *b, const uint64_t *states, int64_t n, int64_t *idx, hipStream_t st);
 
 int launch_rank_device(const hphi_basis *b, const uint64_t *states, int64_t n, int64_t *idx,
                        hipStream_t st);

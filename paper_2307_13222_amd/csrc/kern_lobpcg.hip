@@ -268,6 +268,7 @@ int launch_diag(hphi_ham *h, double *out, hipStream_t st)
 {
     const hphi_basis *b = h->basis;
     if (h->kind == 2) return launch_gc_diag(h, out, st);
+    if (h->kind == 3) return launch_spin_s_diag(h, out, st);
     if (h->kind == 0) {
         if (!b->sp[0].materialized() || b->sp[0].state_bytes != 4)
             return fail(HPHI_ERR_UNSUPPORTED, "the diagonal needs a stored basis (N <= 32)");

@@ -18,6 +18,7 @@
 // pass adds the diagonal and writes w without reading it; the last applies
 // the caller's epilogue and the FP64 dot products).
 #include "kern_common.h"
+#include "row_finish.h"
 
 namespace hphi {
 
@@ -69,16 +70,12 @@ __global__ __launch_bounds__(1024) void k_spin_gc(GcKArgs a)
     const int tid = threadIdx.x, T = blockDim.x;
     for (int k = tid; k < (1 << a.q); k += T) s_offw[k] = a.offw[k];
     const S *__restrict__ v = static_cast<const S *>(a.v);
-    S *__restrict__ w = static_cast<S *>(a.w);
-    const S *__restrict__ u = static_cast<const S *>(a.u);
-    S *__restrict__ accp = static_cast<S *>(a.acc_out);
-    S *__restrict__ rawp = static_cast<S *>(a.raw_out);
+    S *w = static_cast<S *>(a.w);   // also written through the epilogue's pointer
     const uint32_t lowmask = (1u << a.lowb) - 1u;
-    const S c1s = a.coef ? (S)a.coef[0] : (S)1, c2s = a.coef ? (S)a.coef[1] : (S)0;
-    constexpr int ND = DOTS ? NV : 1;
-    double d0[ND], d1[ND];
-#pragma unroll
-    for (int j = 0; j < ND; ++j) d0[j] = d1[j] = 0.0;
+    const EpiArgs<S> ep{w, static_cast<const S *>(a.u), static_cast<S *>(a.acc_out), static_cast<S *>(a.raw_out),
+                        a.coef, a.coef_cplx, a.dot_raw};
+    RowFinish<S, NV, DOTS> fin;
+    fin.init(ep);
 
     for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
         const uint64_t base = scatter_bits((uint64_t)t, a.compmask);
@@ -122,57 +119,14 @@ __global__ __launch_bounds__(1024) void k_spin_gc(GcKArgs a)
 #pragma unroll
                 for (int j = 0; j < NV; ++j) w[x * NV + j] = hv[j];
             } else {
-                S out[NV];
-                if (a.coef_cplx) {
-                    S uu[NV];
+                S me[NV];
 #pragma unroll
-                    for (int j = 0; j < NV; ++j) uu[j] = u ? u[x * NV + j] : (S)0;
-                    epilogue_r<S, NV>(hv, uu, u != nullptr, 1, a.coef, out);
-                } else {
-#pragma unroll
-                    for (int j = 0; j < NV; ++j) out[j] = c1s * hv[j] + (u ? c2s * u[x * NV + j] : (S)0);
-                }
-#pragma unroll
-                for (int j = 0; j < NV; ++j) w[x * NV + j] = out[j];
-                if (rawp) {
-#pragma unroll
-                    for (int j = 0; j < NV; ++j) rawp[x * NV + j] = hv[j];
-                }
-                if (accp) {
-#pragma unroll
-                    for (int j = 0; j < NV; ++j) accp[x * NV + j] += out[j];
-                }
-                if constexpr (DOTS) {
-#pragma unroll
-                    for (int j = 0; j < NV; ++j) {
-                        const double o = a.dot_raw ? (double)hv[j] : (double)out[j];
-                        d0[j] += (double)s_v[(size_t)l * NV + j] * o;
-                        d1[j] += o * o;
-                    }
-                }
+                for (int j = 0; j < NV; ++j) me[j] = s_v[(size_t)l * NV + j];
+                fin.apply(hv, me, (size_t)x, ep);
             }
         }
     }
-    if constexpr (DOTS) {
-        // per-lane sums over the wave, then over the block's waves in order
-        const int lane = tid & 63, wid = tid >> 6, nw = T >> 6;
-#pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            const double s0 = wave_sum(d0[j]), s1 = wave_sum(d1[j]);
-            if (lane == 0) {
-                sh_red[wid * 2 * NV + j] = s0;
-                sh_red[wid * 2 * NV + NV + j] = s1;
-            }
-        }
-        __syncthreads();
-        if (tid < 2 * NV) {
-            double s = 0.0;
-            for (int w2 = 0; w2 < nw; ++w2) s += sh_red[w2 * 2 * NV + tid];
-            sh_blk[tid] = s;
-        }
-        __syncthreads();
-        grid_finish(sh_blk, 2 * NV, a.red, sh_red);
-    }
+    fin.reduce(a.red, sh_red, sh_blk);
 }
 
 template <typename S, int NV, bool FIRST, bool LAST>

@@ -629,6 +629,7 @@ int launch_trace(hphi_ham *h, Reduce red, hipStream_t st)
 {
     const hphi_basis *b = h->basis;
     if (h->kind == 2) return launch_gc_trace(h, red, st);
+    if (h->kind == 3) return launch_spin_s_trace(h, red, st);
     if (h->kind == 0) {
         if (!b->sp[0].materialized() || b->sp[0].state_bytes != 4)
             return fail(HPHI_ERR_UNSUPPORTED, "trace needs a materialized basis with N <= 32");
@@ -699,6 +700,7 @@ int launch_szq(hphi_ham *h, const double *phase_dev, const void *psi, void *b, h
     const hphi_basis *bs = h->basis;
     if (bs->dim == 0) return HPHI_OK;
     if (h->kind == 2) return launch_gc_szq(h, phase_dev, psi, b, st);
+    if (h->kind == 3) return launch_spin_s_szq(h, phase_dev, psi, b, st);
     if (h->kind == 0) {
         if (!bs->sp[0].materialized() || bs->sp[0].state_bytes != 4)
             return fail(HPHI_ERR_UNSUPPORTED, "S^z(q) needs a stored spin basis with N <= 32");
