@@ -758,6 +758,21 @@ static int build_hub_pairs(hphi_ham *h, const hphi_pair_term *pairs, int n_pairs
     if (b->n_sites > 32 || !b->sp[0].d_hi_off32.p || !b->sp[1].d_hi_off32.p)
         return fail(HPHI_ERR_UNSUPPORTED, "two-body terms need at most 32 sites");
     HPHI_TRY(upload(h->hub.pairs, dev.data(), sizeof(HubPairDev) * dev.size()));
+    // per-site lists (pair order) for the cross weights
+    std::vector<uint32_t> soff(b->n_sites + 1, 0);
+    for (const HubPairDev &q : dev) {
+        ++soff[q.i + 1];
+        ++soff[q.j + 1];
+    }
+    for (int k = 0; k < b->n_sites; ++k) soff[k + 1] += soff[k];
+    std::vector<PairNbrDev> snbr(soff[b->n_sites]);
+    std::vector<uint32_t> fill(soff.begin(), soff.end() - 1);
+    for (const HubPairDev &q : dev) {
+        snbr[fill[q.i]++] = PairNbrDev{q.j, 0, q.v};
+        snbr[fill[q.j]++] = PairNbrDev{q.i, 0, q.v};
+    }
+    HPHI_TRY(upload(h->hub.pair_site_off, soff.data(), sizeof(uint32_t) * soff.size()));
+    HPHI_TRY(upload(h->hub.pair_site_nbr, snbr.data(), sizeof(PairNbrDev) * snbr.size()));
     for (int sgm = 0; sgm < 2; ++sgm) {
         const Species &sp = b->sp[sgm];
         std::vector<double> e((size_t)sp.dim, 0.0);

@@ -131,6 +131,10 @@ struct HubPairDev {
     double v, jh, jx, jp;
 };
 constexpr int kMaxPairTerms = 1024;
+struct PairNbrDev {
+    int32_t other, pad;
+    double v;
+};
 
 // SpinGC (full 2^N space): one off-diagonal term of a bit window. The
 // tile index l holds the low bits and the window's bits; the term maps l to
@@ -225,6 +229,9 @@ struct HubTables {
     int n_pairs = 0;
     DevMem pairs;                // HubPairDev [n_pairs]
     DevMem pair_eup, pair_edn;   // double [dim_up], [dim_dn]
+    // per site k the pairs' other ends and V: the cross weights
+    // m_k(u) = sum V u_other (site_off [n_sites + 1], site_nbr PairNbrDev)
+    DevMem pair_site_off, pair_site_nbr;
     DevMem coef;     // double [128]: -t per value class
     DevMem u_site;   // double [n_sites]
     int n_coef = 0;

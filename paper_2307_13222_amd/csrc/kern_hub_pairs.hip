@@ -30,6 +30,8 @@ struct PairKArgs {
     const HubPairDev *pairs;
     int np;
     const double *eup, *edn;
+    const uint32_t *site_off;
+    const PairNbrDev *site_nbr;
     const uint32_t *hi_off_up, *lo_rank_up, *hi_off_dn, *lo_rank_dn;
     int nlo_up, nlo_dn;
     int n_sites;
@@ -37,7 +39,9 @@ struct PairKArgs {
     void *w;
 };
 
-template <typename S, int NV>
+// RANK_LDS: the down species' rank tables copied into dynamic LDS (they are
+// 2^n_hi + 1 + 2^n_lo words: 2 KB at 16 sites)
+template <typename S, int NV, bool RANK_LDS>
 __global__ __launch_bounds__(1024) void k_hub_pairs(PairKArgs a)
 {
     // active pairs of the current row, in pair order
@@ -47,11 +51,21 @@ __global__ __launch_bounds__(1024) void k_hub_pairs(PairKArgs a)
     __shared__ double s_m[32];                          // cross weights m_k(u)
     __shared__ double s_bt[4][256];                     // byte tables of m
     __shared__ uint32_t s_cnt;
+    extern __shared__ uint32_t s_rank[];
     const S *__restrict__ v = static_cast<const S *>(a.v);
     S *__restrict__ w = static_cast<S *>(a.w);
     const int tid = threadIdx.x, T = blockDim.x;
     const int nchunk = (a.n_sites + 7) >> 3;
     const uint32_t lomask_up = (1u << a.nlo_up) - 1u, lomask_dn = (1u << a.nlo_dn) - 1u;
+    const int nhi_dn = a.n_sites - a.nlo_dn;
+    const uint32_t *hi_dn = a.hi_off_dn, *lo_dn = a.lo_rank_dn;
+    if constexpr (RANK_LDS) {
+        const int nh = (1 << nhi_dn) + 1, nl = 1 << a.nlo_dn;
+        for (int k = tid; k < nh; k += T) s_rank[k] = a.hi_off_dn[k];
+        for (int k = tid; k < nl; k += T) s_rank[nh + k] = a.lo_rank_dn[k];
+        hi_dn = s_rank;
+        lo_dn = s_rank + nh;
+    }
     for (int64_t ru = blockIdx.x; ru < a.dup; ru += gridDim.x) {
         const uint32_t u = a.ups[ru];
         __syncthreads();   // the previous row's tables are no longer read
@@ -85,11 +99,8 @@ __global__ __launch_bounds__(1024) void k_hub_pairs(PairKArgs a)
         } else if (tid - 64 < a.n_sites) {
             const int k = tid - 64;
             double m = 0.0;
-            for (int p = 0; p < a.np; ++p) {
-                const HubPairDev &q = a.pairs[p];
-                if (q.i == k) m += q.v * (double)((u >> q.j) & 1u);
-                if (q.j == k) m += q.v * (double)((u >> q.i) & 1u);
-            }
+            for (uint32_t e = a.site_off[k]; e < a.site_off[k + 1]; ++e)
+                m += a.site_nbr[e].v * (double)((u >> a.site_nbr[e].other) & 1u);
             s_m[k] = m;
         }
         __syncthreads();
@@ -111,17 +122,39 @@ __global__ __launch_bounds__(1024) void k_hub_pairs(PairKArgs a)
             double acc[NV];
 #pragma unroll
             for (int l = 0; l < NV; ++l) acc[l] = dg * (double)v[me + l];
-            for (uint32_t k = 0; k < cnt; ++k) {
-                const uint32_t mk = s_mask[k];
-                const uint32_t dm = d & mk;
-                if (__builtin_popcount(dm) != 1) continue;
-                const double c = dm == s_um[k] ? s_jp[k] : s_jx[k];
-                const uint32_t d2 = d ^ mk;
-                const int64_t r2 = (int64_t)a.hi_off_dn[d2 >> a.nlo_dn] + a.lo_rank_dn[d2 & lomask_dn];
-                const double cs = (__builtin_popcount(d & s_bw[k]) & 1) ? -c : c;
-                const size_t src = (size_t)(s_off[k] + r2) * NV;
+            // active pairs in batches of eight: targets and coefficients
+            // first, then all eight gathers in flight, then the sums in
+            // pair order (an inactive slot adds 0 x v[me])
+            constexpr int B = 8;
+            for (uint32_t k0 = 0; k0 < cnt; k0 += B) {
+                size_t src[B];
+                double cf[B];
 #pragma unroll
-                for (int l = 0; l < NV; ++l) acc[l] += cs * (double)v[src + l];
+                for (int t = 0; t < B; ++t) {
+                    const uint32_t k = k0 + t;
+                    src[t] = me;
+                    cf[t] = 0.0;
+                    if (k < cnt) {
+                        const uint32_t mk = s_mask[k];
+                        const uint32_t dm = d & mk;
+                        if (__builtin_popcount(dm) == 1) {
+                            const double c = dm == s_um[k] ? s_jp[k] : s_jx[k];
+                            const uint32_t d2 = d ^ mk;
+                            const int64_t r2 = (int64_t)hi_dn[d2 >> a.nlo_dn] + lo_dn[d2 & lomask_dn];
+                            cf[t] = (__builtin_popcount(d & s_bw[k]) & 1) ? -c : c;
+                            src[t] = (size_t)(s_off[k] + r2) * NV;
+                        }
+                    }
+                }
+                S g[B][NV];
+#pragma unroll
+                for (int t = 0; t < B; ++t)
+#pragma unroll
+                    for (int l = 0; l < NV; ++l) g[t][l] = v[src[t] + l];
+#pragma unroll
+                for (int t = 0; t < B; ++t)
+#pragma unroll
+                    for (int l = 0; l < NV; ++l) acc[l] += cf[t] * (double)g[t][l];
             }
 #pragma unroll
             for (int l = 0; l < NV; ++l) w[me + l] += (S)acc[l];
@@ -146,6 +179,8 @@ int launch_hub_pairs(hphi_ham *h, int elem_bytes, int nv, const void *v, void *w
     a.np = h->hub.n_pairs;
     a.eup = h->hub.pair_eup.as<double>();
     a.edn = h->hub.pair_edn.as<double>();
+    a.site_off = h->hub.pair_site_off.as<uint32_t>();
+    a.site_nbr = h->hub.pair_site_nbr.as<PairNbrDev>();
     a.hi_off_up = up.d_hi_off32.as<uint32_t>();
     a.lo_rank_up = up.d_lo_rank.as<uint32_t>();
     a.hi_off_dn = dn.d_hi_off32.as<uint32_t>();
@@ -157,10 +192,17 @@ int launch_hub_pairs(hphi_ham *h, int elem_bytes, int nv, const void *v, void *w
     a.w = w;
     const int ncu = b->ctx->n_cu > 0 ? b->ctx->n_cu : 256;
     const unsigned grid = (unsigned)std::min<int64_t>(a.dup, 2 * (int64_t)ncu);
-    if (elem_bytes == 8 && nv == 1) hipLaunchKernelGGL((k_hub_pairs<double, 1>), dim3(grid), dim3(1024), 0, st, a);
-    else if (elem_bytes == 8 && nv == 2) hipLaunchKernelGGL((k_hub_pairs<double, 2>), dim3(grid), dim3(1024), 0, st, a);
-    else if (elem_bytes == 4 && nv == 1) hipLaunchKernelGGL((k_hub_pairs<float, 1>), dim3(grid), dim3(1024), 0, st, a);
-    else if (elem_bytes == 4 && nv == 2) hipLaunchKernelGGL((k_hub_pairs<float, 2>), dim3(grid), dim3(1024), 0, st, a);
+    const size_t rank_words = ((size_t)1 << (b->n_sites - dn.n_lo)) + 1 + ((size_t)1 << dn.n_lo);
+    const bool rank_lds = rank_words * 4 <= 32 * 1024;
+    const size_t lds = rank_lds ? rank_words * 4 : 0;
+    auto go = [&](auto kern) {
+        hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(1024), lds, st, a);
+    };
+    if (elem_bytes == 8 && nv == 1) rank_lds ? go(k_hub_pairs<double, 1, true>) : go(k_hub_pairs<double, 1, false>);
+    else if (elem_bytes == 8 && nv == 2) rank_lds ? go(k_hub_pairs<double, 2, true>) : go(k_hub_pairs<double, 2, false>);
+    else if (elem_bytes == 4 && nv == 1) rank_lds ? go(k_hub_pairs<float, 1, true>) : go(k_hub_pairs<float, 1, false>);
+    else if (elem_bytes == 4 && nv == 2) rank_lds ? go(k_hub_pairs<float, 2, true>) : go(k_hub_pairs<float, 2, false>);
     else return fail(HPHI_ERR_UNSUPPORTED, "two-body terms: %d-byte elements, %d lanes", elem_bytes, nv);
     HPHI_HIP(hipGetLastError());
     return HPHI_OK;

@@ -63,12 +63,19 @@ __global__ __launch_bounds__(1024) void k_spin_gc(GcKArgs a)
 {
     extern __shared__ unsigned char smem_raw[];
     const int L = 1 << (a.lowb + a.q);
+    // LDS: the tile, the window's term records and S^z S^z bonds (read with
+    // wave-uniform addresses: broadcasts), the window-bit scatter table
     S *s_v = reinterpret_cast<S *>(smem_raw);
-    uint32_t *s_offw = reinterpret_cast<uint32_t *>(s_v + (size_t)L * NV);
+    GcTermDev *s_terms = reinterpret_cast<GcTermDev *>(s_v + (size_t)L * NV);
+    GcDiagDev *s_diag = reinterpret_cast<GcDiagDev *>(s_terms + a.nterms);
+    uint32_t *s_offw = reinterpret_cast<uint32_t *>(s_diag + (FIRST ? a.ndiag : 0));
     __shared__ double sh_red[2 * NV * 16];
     __shared__ double sh_blk[2 * NV];
     const int tid = threadIdx.x, T = blockDim.x;
     for (int k = tid; k < (1 << a.q); k += T) s_offw[k] = a.offw[k];
+    for (int k = tid; k < a.nterms; k += T) s_terms[k] = a.terms[k];
+    if constexpr (FIRST)
+        for (int k = tid; k < a.ndiag; k += T) s_diag[k] = a.diag[k];
     const S *__restrict__ v = static_cast<const S *>(a.v);
     S *w = static_cast<S *>(a.w);   // also written through the epilogue's pointer
     const uint32_t lowmask = (1u << a.lowb) - 1u;
@@ -91,9 +98,11 @@ __global__ __launch_bounds__(1024) void k_spin_gc(GcKArgs a)
             S hv[NV];
             if constexpr (FIRST) {
                 S dg = (S)0;
+#pragma unroll 4
                 for (int b = 0; b < a.ndiag; ++b) {
-                    const uint32_t m = a.diag[b].mask, tb = (uint32_t)x & m;
-                    dg += (tb == 0u || tb == m) ? (S)a.diag[b].jz4 : (S)-a.diag[b].jz4;
+                    const GcDiagDev dd = s_diag[b];
+                    const uint32_t tb = (uint32_t)x & dd.mask;
+                    dg += (tb == 0u || tb == dd.mask) ? (S)dd.jz4 : (S)-dd.jz4;
                 }
                 if (a.hz)
                     for (int i = 0; i < a.n_sites; ++i) dg -= (S)a.hz[i] * (((x >> i) & 1ull) ? (S)0.5 : (S)-0.5);
@@ -103,8 +112,9 @@ __global__ __launch_bounds__(1024) void k_spin_gc(GcKArgs a)
 #pragma unroll
                 for (int j = 0; j < NV; ++j) hv[j] = (S)0;
             }
+#pragma unroll 4
             for (int k = 0; k < a.nterms; ++k) {
-                const GcTermDev tm = a.terms[k];
+                const GcTermDev tm = s_terms[k];
                 const int p = l ^ (int)tm.mloc;
                 const bool par = (((uint32_t)l >> tm.pi) ^ ((uint32_t)l >> tm.pj)) & 1u ? false : true;
                 const S c = par ? (S)tm.cpar : (S)tm.canti;
@@ -177,7 +187,9 @@ static int launch_gc_t(hphi_ham *h, const MultArgs &m)
         a.offw = plan.offw.as<uint32_t>() + wn.offw_first;
         a.terms = plan.terms.as<GcTermDev>() + wn.term_first;
         a.nterms = wn.term_count;
-        const size_t lds = ((size_t)1 << (plan.lowb + wn.q)) * NV * sizeof(S) + ((size_t)1 << wn.q) * 4;
+        const size_t lds = ((size_t)1 << (plan.lowb + wn.q)) * NV * sizeof(S) + sizeof(GcTermDev) * wn.term_count +
+                           (k == 0 ? sizeof(GcDiagDev) * (size_t)a.ndiag : 0) + ((size_t)1 << wn.q) * 4;
+        if (lds > 160 * 1024) return fail(HPHI_ERR_UNSUPPORTED, "SpinGC window tile and terms beyond the LDS");
         const int grid = (int)std::min<int64_t>(a.ntiles, 2 * (int64_t)ncu);
         if (a.nd && (int64_t)grid * 2 * NV > kReduceSlots)
             return fail(HPHI_ERR_UNSUPPORTED, "SpinGC grid beyond the reduction scratch");

@@ -39,18 +39,30 @@ struct SpinSKArgs {
     Reduce red;
 };
 
-template <typename S, int NV, bool DOTS>
+// BOND_LDS: the bond records staged in dynamic LDS (wave-uniform reads).
+// The ladder terms run in batches of eight slots (slot 2k: S^+_i S^-_j of
+// bond k, slot 2k + 1: S^-_i S^+_j): targets first, then their rank-table
+// loads, then the gathers, all eight in flight at each level; a slot that
+// does not apply gathers this row's own element with coefficient 0.
+template <typename S, int NV, bool DOTS, bool BOND_LDS>
 __global__ __launch_bounds__(256) void k_spin_s_hv(SpinSKArgs a)
 {
+    extern __shared__ SpinSBondDev s_bonds[];
     __shared__ double sh_red[2 * NV * 4 > 16 ? 2 * NV * 4 : 16];
     __shared__ double sh_blk[2 * NV];
+    const SpinSBondDev *bonds = a.bonds;
+    if constexpr (BOND_LDS) {
+        for (int k = threadIdx.x; k < a.nb; k += blockDim.x) s_bonds[k] = a.bonds[k];
+        __syncthreads();
+        bonds = s_bonds;
+    }
     const S *__restrict__ v = static_cast<const S *>(a.v);
     const EpiArgs<S> ep{static_cast<S *>(a.w), static_cast<const S *>(a.u), static_cast<S *>(a.acc_out),
                         static_cast<S *>(a.raw_out), a.coef, a.coef_cplx, a.dot_raw};
     RowFinish<S, NV, DOTS> fin;
     fin.init(ep);
     const uint64_t dmask = (1ull << a.bits) - 1ull, lomask = (1ull << a.lo_bits) - 1ull;
-    auto rank = [&](uint64_t y) -> int64_t { return (int64_t)a.hi_off[y >> a.lo_bits] + a.lo_rank[y & lomask]; };
+    const int nslot = 2 * a.nb;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < a.dim; r += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t x = a.states[r];
         double dg = 0.0;
@@ -61,23 +73,51 @@ __global__ __launch_bounds__(256) void k_spin_s_hv(SpinSKArgs a)
             me[j] = v[(size_t)r * NV + j];
         }
         for (int k = 0; k < a.nb; ++k) {
-            const SpinSBondDev bd = a.bonds[k];
-            const int si = bd.i * a.bits, sj = bd.j * a.bits;
-            const int mi = (int)((x >> si) & dmask), mj = (int)((x >> sj) & dmask);
+            const SpinSBondDev bd = bonds[k];
+            const int mi = (int)((x >> (bd.i * a.bits)) & dmask), mj = (int)((x >> (bd.j * a.bits)) & dmask);
             dg += bd.jz * ((double)mi - a.s) * ((double)mj - a.s);
-            if (bd.jxy2 == 0.0) continue;
-            if (mi < a.two_s && mj > 0) {
-                const int64_t c = rank(x + (1ull << si) - (1ull << sj));
-                const S cf = (S)(bd.jxy2 * a.amp_up[mi] * a.amp_dn[mj]);
+        }
+        constexpr int B = 8;
+        for (int s0 = 0; s0 < nslot; s0 += B) {
+            uint64_t y[B];
+            double cf[B];
 #pragma unroll
-                for (int j = 0; j < NV; ++j) hv[j] += cf * v[(size_t)c * NV + j];
+            for (int t = 0; t < B; ++t) {
+                const int sl = s0 + t;
+                y[t] = x;
+                cf[t] = 0.0;
+                if (sl < nslot) {
+                    const SpinSBondDev bd = bonds[sl >> 1];
+                    const int si = bd.i * a.bits, sj = bd.j * a.bits;
+                    const int mi = (int)((x >> si) & dmask), mj = (int)((x >> sj) & dmask);
+                    if (!(sl & 1)) {
+                        if (bd.jxy2 != 0.0 && mi < a.two_s && mj > 0) {
+                            y[t] = x + (1ull << si) - (1ull << sj);
+                            cf[t] = bd.jxy2 * a.amp_up[mi] * a.amp_dn[mj];
+                        }
+                    } else if (bd.jxy2 != 0.0 && mi > 0 && mj < a.two_s) {
+                        y[t] = x - (1ull << si) + (1ull << sj);
+                        cf[t] = bd.jxy2 * a.amp_dn[mi] * a.amp_up[mj];
+                    }
+                }
             }
-            if (mi > 0 && mj < a.two_s) {
-                const int64_t c = rank(x - (1ull << si) + (1ull << sj));
-                const S cf = (S)(bd.jxy2 * a.amp_dn[mi] * a.amp_up[mj]);
+            uint32_t ho[B], lr[B];
 #pragma unroll
-                for (int j = 0; j < NV; ++j) hv[j] += cf * v[(size_t)c * NV + j];
+            for (int t = 0; t < B; ++t) {
+                ho[t] = a.hi_off[y[t] >> a.lo_bits];
+                lr[t] = a.lo_rank[y[t] & lomask];
             }
+            S g[B][NV];
+#pragma unroll
+            for (int t = 0; t < B; ++t) {
+                const size_t c = (size_t)ho[t] + lr[t];
+#pragma unroll
+                for (int j = 0; j < NV; ++j) g[t][j] = v[c * NV + j];
+            }
+#pragma unroll
+            for (int t = 0; t < B; ++t)
+#pragma unroll
+                for (int j = 0; j < NV; ++j) hv[j] += (S)cf[t] * g[t][j];
         }
         for (int i = 0; i < a.n_sites && (a.hz || a.dion); ++i) {
             const double sz = (double)((x >> (i * a.bits)) & dmask) - a.s;
@@ -136,8 +176,14 @@ static int launch_spin_s_t(hphi_ham *h, const MultArgs &m)
     a.dot_raw = m.dot_raw;
     a.red = m.red;
     const unsigned grid = spin_s_grid(a.dim, 256);
-    if (a.nd) hipLaunchKernelGGL((k_spin_s_hv<S, NV, true>), dim3(grid), dim3(256), 0, m.stream, a);
-    else hipLaunchKernelGGL((k_spin_s_hv<S, NV, false>), dim3(grid), dim3(256), 0, m.stream, a);
+    const size_t lds = sizeof(SpinSBondDev) * (size_t)a.nb;
+    const bool bl = lds <= 32 * 1024;
+    auto go = [&](auto kern) {
+        if (bl) hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(256), bl ? lds : 0, m.stream, a);
+    };
+    if (a.nd) bl ? go(k_spin_s_hv<S, NV, true, true>) : go(k_spin_s_hv<S, NV, true, false>);
+    else bl ? go(k_spin_s_hv<S, NV, false, true>) : go(k_spin_s_hv<S, NV, false, false>);
     HPHI_HIP(hipGetLastError());
     return HPHI_OK;
 }
