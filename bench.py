@@ -85,12 +85,12 @@ def parse():
 # counters (fetch 2.000, write 1.000). Valid only for the kernel sources and
 # schedule it was taken with; anything else reports null.
 HUB_TRAFFIC = {
-    "sources_sha256": {"kern_hub.hip": "1c954a04ec34d47b2a52b822f1da57c6b6425dc5f5b5de015b147e97e13a7d12",
+    "sources_sha256": {"kern_hub.hip": "d27f08120da570c0fd4b2b128f4110562f3a264543540c276083061bae78cf23",
                        "kern_common.h": "82a4da084e46d3f069fff2bbec75262cce5cf6131077ca6b4d166d41e8c25fce"},
     "schedule": {"hub_slab_cols": 128, "hub_groups": 128, "hub_item_rows": 16, "hub_row_cols": 6, "hub_sweep": 7,
                  "hub_row_order": 2, "hub_tile_bits": 0},
-    "cols_fetch_kib": 3.688577e+06, "cols_write_kib": 1.299398e+06,
-    "rows_fetch_kib": 1.450167e+06, "rows_write_kib": 2.588495e+06,
+    "cols_fetch_kib": 3.015888e+06, "cols_write_kib": 1.299301e+06,
+    "rows_fetch_kib": 1.449196e+06, "rows_write_kib": 2.588495e+06,
     "fetch_factor": 2.0, "write_factor": 1.0,
 }
 
