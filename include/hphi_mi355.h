@@ -621,6 +621,27 @@ int hphi_sqw(hphi_ham *h, const hphi_sqw_opts *opts, const void *b_dev,
              const double *z_re, const double *z_im, int n_shift, double *D_out,
              double *resid_out, hphi_sqw_info *info);
 
+/* hphi_sqw for n independent requests in one launch (the spectrum workflow
+ * of Sec. 3.2 run for many small systems at once): request i is spin
+ * Hamiltonian hams[i] on a stored basis whose rank tables fit in LDS (at
+ * most 24 sites), excitation b_devs[i] (C128, read only) and the shifts
+ * z_re/z_im[i * n_shift ...]. Each (request, part of b) sequence runs whole
+ * on one workgroup: H*p with the COCG scalars of hphi_sqw, fixed-order
+ * reductions over the request's rows, convergence checked every 8
+ * iterations as there; a request's numbers do not depend on the rest of the
+ * launch and equal hphi_sqw's up to the summation order. opts->stream,
+ * tol, max_iter, seed_shift as for hphi_sqw. D_out: n * 2 * n_shift doubles,
+ * resid_out (nullable) n * n_shift, info (nullable) n entries. Device
+ * workspace: 3 complex vectors per request, allocated per call. Does not
+ * take the Hamiltonians' call guard (it uses none of their scratch).
+ * Synchronous. Errors: INVALID_ARG (n < 1, null arguments, n_shift outside
+ * [1, 1024], Hamiltonians on different contexts), UNSUPPORTED (a
+ * Hamiltonian that is not spin-1/2 on a stored basis, or whose tables
+ * exceed LDS), OUT_OF_MEMORY, DEVICE. */
+int hphi_sqw_batch(hphi_ham *const *hams, int n, const hphi_sqw_opts *opts, const void *const *b_devs,
+                   const double *z_re, const double *z_im, int n_shift, double *D_out, double *resid_out,
+                   hphi_sqw_info *info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -132,6 +132,8 @@ SIGNATURES = {
     "hphi_lobpcg": (I, [P, C.POINTER(LobpcgOpts), PD, PD, P, C.POINTER(LobpcgInfo)]),
     "hphi_szq": (I, [P, PD, P, P, P]),
     "hphi_sqw": (I, [P, C.POINTER(SqwOpts), P, PD, PD, I, PD, PD, C.POINTER(SqwInfo)]),
+    "hphi_sqw_batch": (I, [C.POINTER(P), I, C.POINTER(SqwOpts), C.POINTER(P), PD, PD, I, PD, PD,
+                           C.POINTER(SqwInfo)]),
 }
 
 _lib = None

@@ -6,7 +6,7 @@ runs in the HIP library. Names mirror include/hphi_mi355.h.
 from __future__ import annotations
 
 import ctypes as C
-from typing import Dict, Optional, Sequence
+from typing import Dict, List, Optional, Sequence
 
 import numpy as np
 
@@ -438,6 +438,40 @@ def szq(ham: Hamiltonian, q: float, psi, stream=None):
     _check(L.lib().hphi_szq(ham.h, phase.ctypes.data_as(L.PD), psi.data_ptr(), b.data_ptr(),
                             _stream_ptr(stream)), "hphi_szq")
     return b
+
+
+def sqw_batch(hams: Sequence[Hamiltonian], bs, zs, max_iter: int = 2000, tol: float = 1e-8,
+              seed_shift: int = -1, stream=None) -> List[Dict]:
+    """sqw for many spin requests in one launch (one workgroup per sequence):
+    hams[i], excitation bs[i] (complex128 device tensor), shifts zs[i] (all
+    of the same length)."""
+    n = len(hams)
+    if n == 0:
+        return []
+    zs = [np.asarray(z, dtype=np.complex128) for z in zs]
+    ns = len(zs[0])
+    if any(len(z) != ns for z in zs) or len(bs) != n or len(zs) != n:
+        raise HphiError("sqw_batch: one excitation and one shift list of equal length per request")
+    for b in bs:
+        _dev_check(b, "b")
+    zr = np.ascontiguousarray(np.concatenate([z.real for z in zs]))
+    zi = np.ascontiguousarray(np.concatenate([z.imag for z in zs]))
+    D = np.zeros(2 * ns * n)
+    res = np.zeros(ns * n)
+    o = L.SqwOpts()
+    o.max_iter, o.tol, o.seed_shift, o.stream = max_iter, tol, seed_shift, _stream_ptr(stream)
+    infos = (L.SqwInfo * n)()
+    hs = (C.c_void_p * n)(*[h.h for h in hams])
+    bp = (C.c_void_p * n)(*[b.data_ptr() for b in bs])
+    _check(L.lib().hphi_sqw_batch(hs, n, C.byref(o), bp, zr.ctypes.data_as(L.PD), zi.ctypes.data_as(L.PD), ns,
+                                  D.ctypes.data_as(L.PD), res.ctypes.data_as(L.PD), infos), "hphi_sqw_batch")
+    out = []
+    for i in range(n):
+        d = D[2 * ns * i:2 * ns * (i + 1)]
+        out.append({"D": d[0::2] + 1j * d[1::2], "residual": res[ns * i:ns * (i + 1)].copy(),
+                    "iterations": infos[i].iterations, "converged": bool(infos[i].converged),
+                    "max_residual": infos[i].max_residual, "seconds": infos[i].seconds})
+    return out
 
 
 def sqw(ham: Hamiltonian, b, z: Sequence[complex], max_iter: int = 2000, tol: float = 1e-8,

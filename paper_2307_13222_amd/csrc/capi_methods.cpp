@@ -577,4 +577,108 @@ int hphi_sqw(hphi_ham *h, const hphi_sqw_opts *o, const void *b_dev, const doubl
     return HPHI_OK;
 }
 
+int hphi_sqw_batch(hphi_ham *const *hams, int n, const hphi_sqw_opts *o, const void *const *b_devs,
+                   const double *z_re, const double *z_im, int n_shift, double *D_out, double *resid_out,
+                   hphi_sqw_info *info)
+{
+    if (!hams || n < 1 || !o || !b_devs || !z_re || !z_im || !D_out)
+        return fail(HPHI_ERR_INVALID_ARG, "null argument or empty batch");
+    if (n_shift < 1 || n_shift > 1024) return fail(HPHI_ERR_INVALID_ARG, "n_shift %d outside [1, 1024]", n_shift);
+    if (o->max_iter < 1) return fail(HPHI_ERR_INVALID_ARG, "max_iter < 1");
+    if (o->seed_shift >= n_shift) return fail(HPHI_ERR_INVALID_ARG, "seed_shift out of range");
+    for (int i = 0; i < n; ++i) {
+        if (!hams[i] || !b_devs[i]) return fail(HPHI_ERR_INVALID_ARG, "request %d: null Hamiltonian or b", i);
+        if (hams[i]->basis->ctx != hams[0]->basis->ctx)
+            return fail(HPHI_ERR_INVALID_ARG, "requests on different contexts");
+    }
+    DeviceGuard g(hams[0]->basis->ctx->device);
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = (hipStream_t)o->stream;
+    const int seed = o->seed_shift >= 0 ? o->seed_shift : n_shift / 2;
+    const int ni = 2 * n;   // item 2 i + part
+    // one device allocation: the items' complex vectors, chunk partials,
+    // outputs, then the shift records
+    std::vector<size_t> vec_off(ni), ch_off(ni);
+    size_t nd = 0;
+    for (int k = 0; k < ni; ++k) {
+        const int64_t dim = hams[k / 2]->basis->dim;
+        vec_off[k] = nd;
+        nd += 6 * (size_t)dim;
+    }
+    for (int k = 0; k < ni; ++k) {
+        ch_off[k] = nd;
+        nd += 5 * (size_t)cocg_chunks(hams[k / 2]->basis->dim);
+    }
+    const size_t out_off = nd;
+    nd += 6 * (size_t)ni;
+    nd = (nd + 1) & ~(size_t)1;
+    const size_t sh_bytes = sizeof(ShiftDev) * (size_t)n_shift * ni;
+    DevMem mem, items;
+    HPHI_TRY(mem.alloc(sizeof(double) * nd + sh_bytes));
+    double *base = mem.as<double>();
+    ShiftDev *sh_dev = reinterpret_cast<ShiftDev *>(base + nd);
+    std::vector<ShiftDev> sh((size_t)n_shift * ni);
+    std::vector<unsigned char> it((size_t)ni * cocg_item_size());
+    for (int k = 0; k < ni; ++k) {
+        const int i = k / 2;
+        const double *zr = z_re + (size_t)i * n_shift, *zi = z_im + (size_t)i * n_shift;
+        for (int j = 0; j < n_shift; ++j) {
+            ShiftDev &x = sh[(size_t)k * n_shift + j];
+            x = ShiftDev{};
+            x.sigma = {zr[j] - zr[seed], zi[j] - zi[seed]};
+        }
+        const int64_t dim = hams[i]->basis->dim;
+        double *v = base + vec_off[k];
+        HPHI_TRY(fill_cocg_item(hams[i], b_devs[i], k & 1, v, v + 2 * dim, v + 4 * dim, base + ch_off[k],
+                                sh_dev + (size_t)k * n_shift, n_shift, zr[seed], zi[seed], o->tol, o->max_iter,
+                                base + out_off + 6 * (size_t)k, it.data() + (size_t)k * cocg_item_size()));
+    }
+    HPHI_HIP(hipMemcpyAsync(sh_dev, sh.data(), sh_bytes, hipMemcpyHostToDevice, st));
+    HPHI_TRY(items.alloc(it.size()));
+    HPHI_HIP(hipMemcpyAsync(items.p, it.data(), it.size(), hipMemcpyHostToDevice, st));
+    HPHI_TRY(launch_cocg_batch(items.p, ni, st));
+    std::vector<double> outs(6 * (size_t)ni);
+    HPHI_HIP(hipMemcpyAsync(sh.data(), sh_dev, sh_bytes, hipMemcpyDeviceToHost, st));
+    HPHI_HIP(hipMemcpyAsync(outs.data(), base + out_off, sizeof(double) * outs.size(), hipMemcpyDeviceToHost, st));
+    HPHI_HIP(hipStreamSynchronize(st));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int i = 0; i < n; ++i) {
+        double *D = D_out + (size_t)i * 2 * n_shift;
+        std::vector<double> res(n_shift, 0.0);
+        for (int j = 0; j < 2 * n_shift; ++j) D[j] = 0.0;
+        int iters = 0, conv = 1;
+        for (int part = 0; part < 2; ++part) {
+            const int k = 2 * i + part;
+            const double *ok = outs.data() + 6 * (size_t)k;
+            const double bn2 = ok[3], bnorm = std::sqrt(ok[4]);
+            if (bn2 == 0.0 || bnorm == 0.0) continue;
+            const double w = std::sqrt(bn2) / bnorm;
+            if (ok[5] != 0.0) {   // part below tol |b|: no sequence, its norm joins the residual
+                for (int j = 0; j < n_shift; ++j) res[j] += w;
+                continue;
+            }
+            for (int j = 0; j < n_shift; ++j) {
+                const ShiftDev &x = sh[(size_t)k * n_shift + j];
+                D[2 * j] += x.X.re;
+                D[2 * j + 1] += x.X.im;
+                res[j] += x.res * w;
+            }
+            iters += (int)ok[0];
+            conv &= ok[1] != 0.0 ? 1 : 0;
+        }
+        double mx = 0.0;
+        for (int j = 0; j < n_shift; ++j) {
+            if (resid_out) resid_out[(size_t)i * n_shift + j] = res[j];
+            mx = std::max(mx, res[j]);
+        }
+        if (info) {
+            info[i].iterations = iters;
+            info[i].converged = conv;
+            info[i].max_residual = mx;
+            info[i].seconds = secs;
+        }
+    }
+    return HPHI_OK;
+}
+
 } // extern "C"

@@ -535,6 +535,13 @@ int launch_cocg_iter(void *r, void *p, const void *h, const void *b, int64_t dim
 int launch_cplx_part(const void *b, void *out, int64_t dim, int part, hipStream_t st);
 int launch_pair_rsqrt(const double *n, double *s, int nl, hipStream_t st);
 
+// batched S(q, w): one shifted-COCG sequence per workgroup (kern_batch.hip)
+size_t cocg_item_size();
+int64_t cocg_chunks(int64_t dim);
+int fill_cocg_item(hphi_ham *h, const void *b, int part, double *r, double *p, double *hv, double *chunks,
+                   void *sh, int nsh, double zs_re, double zs_im, double tol, int max_iter, double *out, void *dst);
+int launch_cocg_batch(const void *items_dev, int n, hipStream_t st);
+
 // batched small-sector Lanczos (kern_batch.hip)
 size_t batch_item_size();
 int fill_batch_item(hphi_ham *h, int iters, uint64_t seed, double *q, double *alpha, double *beta, int *done,

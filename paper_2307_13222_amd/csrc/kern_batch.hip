@@ -500,6 +500,305 @@ int launch_lanczos_batch(const void *items_dev, int n, hipStream_t st, size_t ld
     return HPHI_OK;
 }
 
+// ------------------------------------------------------ batched COCG --
+// One (request, part of b) shifted-COCG sequence per 1024-thread workgroup
+// (the scalar recurrences of kern_methods.hip, restated per workgroup):
+// the request's rank tables in LDS, p, r and H p in global memory, every
+// reduction in the row order of the batched Lanczos (64-row chunks by one
+// DPP tree, then chunks in order), the per-shift scalars in global memory
+// updated by one thread each. The part's norm decides, as in hphi_sqw,
+// whether the sequence runs at all.
+struct CocgItemDev {
+    const uint32_t *states;
+    int64_t dim;
+    const SpinBondDev *bonds;
+    int nb;
+    int n_lo, n_hi;
+    const uint32_t *lo_rank, *hi_off;
+    const double *hz;
+    int n_sites;
+    const double *b;       // complex b, interleaved (re, im)
+    int part;              // 0: Re b, 1: Im b
+    double *r, *p, *h;     // complex, 2 dim doubles each
+    double *chunks;        // 5 n_chunks(dim) doubles
+    ShiftDev *sh;          // nsh shifts (sigma set)
+    int nsh;
+    double zs_re, zs_im;
+    double tol;
+    int max_iter;
+    double *out;           // [0] iterations, [1] converged, [2] breakdown, [3] |part|^2, [4] |b|^2, [5] skipped
+};
+
+size_t cocg_item_size() { return sizeof(CocgItemDev); }
+
+__global__ __launch_bounds__(kBatchLdsThreads) void k_cocg_batch(const CocgItemDev *items)
+{
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ double bcast;
+    __shared__ double s_max[kBatchLdsThreads / kWave];
+    const CocgItemDev it = items[blockIdx.x];
+    const CSpinBond *bc = (const CSpinBond *)(it.bonds);
+    const CDouble *hzc = (const CDouble *)(it.hz);
+    const int64_t dim = it.dim, nch = n_chunks(dim);
+    uint32_t *lo = reinterpret_cast<uint32_t *>(smem_raw);
+    const uint32_t nl = 1u << it.n_lo, nh = 1u << it.n_hi;
+    uint32_t *hi = lo + nl;
+    for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) lo[i] = it.lo_rank[i];
+    for (uint32_t i = threadIdx.x; i < nh; i += blockDim.x) hi[i] = it.hi_off[i];
+    const uint32_t lomask = nl - 1u;
+    const int n_lo = it.n_lo;
+    auto rank = [&](uint32_t y) -> uint32_t { return hi[y >> n_lo] + lo[y & lomask]; };
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wrow = threadIdx.x & ~(kWave - 1);
+    double *C0 = it.chunks, *C1 = C0 + nch, *C2 = C1 + nch, *C3 = C2 + nch, *C4 = C3 + nch;
+    double2 *R = reinterpret_cast<double2 *>(it.r);
+    double2 *P = reinterpret_cast<double2 *>(it.p);
+    double2 *Hp = reinterpret_cast<double2 *>(it.h);
+    const double2 *B = reinterpret_cast<const double2 *>(it.b);
+    // norms of the two parts of b
+    for (int64_t b0 = wrow; b0 < dim; b0 += blockDim.x) {
+        const int64_t r = b0 + lane;
+        double a0 = 0.0, a1 = 0.0;
+        if (r < dim) {
+            const double2 bb = B[r];
+            a0 = bb.x * bb.x;
+            a1 = bb.y * bb.y;
+        }
+        chunk_store(a0, C0, b0 / kChunk);
+        chunk_store(a1, C1, b0 / kChunk);
+    }
+    const double bn2_0 = block_total(C0, nch, &bcast);
+    const double bn2_1 = block_total(C1, nch, &bcast);
+    const double bn2 = it.part ? bn2_1 : bn2_0;
+    const double bnorm = sqrt(bn2_0 + bn2_1);
+    const double bsum = sqrt(bn2_0) + sqrt(bn2_1);
+    const double tol_part = bsum > 0.0 ? it.tol * bnorm / bsum : it.tol;
+    if (bn2 == 0.0 || sqrt(bn2) <= it.tol * bnorm) {
+        // nothing to iterate (x_part = 0); the caller counts the part's norm
+        for (int j = threadIdx.x; j < it.nsh; j += blockDim.x) {
+            it.sh[j].X = {0.0, 0.0};
+            it.sh[j].res = 0.0;
+        }
+        if (threadIdx.x == 0) {
+            it.out[0] = 0.0; it.out[1] = 1.0; it.out[2] = 0.0;
+            it.out[3] = bn2; it.out[4] = bn2_0 + bn2_1; it.out[5] = 1.0;
+        }
+        return;
+    }
+    // r = p = the part, as a complex vector
+    for (int64_t r = threadIdx.x; r < dim; r += blockDim.x) {
+        const double2 bb = B[r];
+        const double v = it.part ? bb.y : bb.x;
+        R[r] = make_double2(v, 0.0);
+        P[r] = make_double2(v, 0.0);
+    }
+    for (int j = threadIdx.x; j < it.nsh; j += blockDim.x) {
+        ShiftDev s = it.sh[j];
+        s.pi = {1.0, 0.0};
+        s.pi_prev = {1.0, 0.0};
+        s.X = {0.0, 0.0};
+        s.P = {bn2, 0.0};
+        s.res = 1.0;
+        s.conv = 0;
+        it.sh[j] = s;
+    }
+    const cd zs = {it.zs_re, it.zs_im};
+    cd rho = {bn2, 0.0}, al = {1.0, 0.0}, be = {0.0, 0.0}, alp, bep;
+    const double bn = sqrt(bn2);
+    int iter = 0, conv = 0, brk = 0;
+    double max_res = 1.0;
+    __syncthreads();
+    while (iter < it.max_iter) {
+        // h = H p and the rows' terms of mu = p^T (z_s p - h)
+        for (int64_t b0 = wrow; b0 < dim; b0 += blockDim.x) {
+            const int64_t r = b0 + lane;
+            double m0 = 0.0, m1 = 0.0;
+            if (r < dim) {
+                const uint32_t x = it.states[r];
+                double hr = 0.0, hi_ = 0.0, diag = 0.0;
+                for (int b = 0; b < it.nb; b += 8) {
+                    uint32_t idx[8];
+                    double cf[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        idx[k] = (uint32_t)r;
+                        cf[k] = 0.0;
+                        if (b + k < it.nb) {
+                            const uint32_t m = (uint32_t)bc[b + k].mask, t = x & m;
+                            if (t == 0u || t == m) {
+                                diag += bc[b + k].jz4;
+                            } else {
+                                diag -= bc[b + k].jz4;
+                                idx[k] = rank(x ^ m);
+                                cf[k] = bc[b + k].jxy2;
+                            }
+                        }
+                    }
+                    double2 nv[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) nv[k] = P[idx[k]];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        hr += cf[k] * nv[k].x;
+                        hi_ += cf[k] * nv[k].y;
+                    }
+                }
+                if (it.hz)
+                    for (int i = 0; i < it.n_sites; ++i) diag -= hzc[i] * (((x >> i) & 1u) ? 0.5 : -0.5);
+                const double2 pp = P[r];
+                hr += diag * pp.x;
+                hi_ += diag * pp.y;
+                Hp[r] = make_double2(hr, hi_);
+                const cd t = cmul(cd{pp.x, pp.y}, csub(cmul(zs, cd{pp.x, pp.y}), cd{hr, hi_}));
+                m0 = t.re;
+                m1 = t.im;
+            }
+            chunk_store(m0, C0, b0 / kChunk);
+            chunk_store(m1, C1, b0 / kChunk);
+        }
+        const cd mu = {block_total(C0, nch, &bcast), block_total(C1, nch, &bcast)};
+        alp = al;
+        bep = be;
+        if (cabs2(mu) == 0.0) {
+            brk = 1;
+            break;
+        }
+        al = cdiv(rho, mu);
+        // r -= alpha (z_s p - h); rho' = r^T r, |r|^2, b^H r (b = the part)
+        for (int64_t b0 = wrow; b0 < dim; b0 += blockDim.x) {
+            const int64_t r = b0 + lane;
+            double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            if (r < dim) {
+                const double2 pp = P[r], hh = Hp[r], rr = R[r], bb = B[r];
+                const double bv = it.part ? bb.y : bb.x;
+                const cd ap = csub(cmul(zs, cd{pp.x, pp.y}), cd{hh.x, hh.y});
+                const cd rv = csub(cd{rr.x, rr.y}, cmul(al, ap));
+                R[r] = make_double2(rv.re, rv.im);
+                a[0] = rv.re * rv.re - rv.im * rv.im;
+                a[1] = 2 * rv.re * rv.im;
+                a[2] = rv.re * rv.re + rv.im * rv.im;
+                a[3] = bv * rv.re;
+                a[4] = bv * rv.im;
+            }
+            chunk_store(a[0], C0, b0 / kChunk);
+            chunk_store(a[1], C1, b0 / kChunk);
+            chunk_store(a[2], C2, b0 / kChunk);
+            chunk_store(a[3], C3, b0 / kChunk);
+            chunk_store(a[4], C4, b0 / kChunk);
+        }
+        const cd rho1 = {block_total(C0, nch, &bcast), block_total(C1, nch, &bcast)};
+        const double rn = sqrt(block_total(C2, nch, &bcast));
+        const cd bhr = {block_total(C3, nch, &bcast), block_total(C4, nch, &bcast)};
+        if (cabs2(rho) == 0.0) {
+            brk = 1;
+            be = {0.0, 0.0};
+        } else {
+            be = cdiv(rho1, rho);
+        }
+        rho = rho1;
+        ++iter;
+        // per-shift recurrences (one thread per shift), then the largest
+        // residual of the unconverged shifts
+        const cd ratio = cabs2(alp) > 0.0 ? cdiv(cmul(al, bep), alp) : cd{0.0, 0.0};
+        double mx = 0.0;
+        for (int j = threadIdx.x; j < it.nsh; j += blockDim.x) {
+            ShiftDev s = it.sh[j];
+            if (!s.conv) {
+                const cd one = {1.0, 0.0};
+                const cd f = cadd(cadd(one, ratio), cmul(al, s.sigma));
+                const cd pin = csub(cmul(f, s.pi), cmul(ratio, s.pi_prev));
+                const cd q = cdiv(s.pi, pin);
+                const cd als = cmul(q, al);
+                const cd bes = cmul(cmul(q, q), be);
+                s.X = cadd(s.X, cmul(als, s.P));
+                s.P = cadd(cdiv(bhr, pin), cmul(bes, s.P));
+                s.pi_prev = s.pi;
+                s.pi = pin;
+                s.res = rn / sqrt(cabs2(pin)) / bn;
+                if (s.res < tol_part) s.conv = 1;
+                it.sh[j] = s;
+            }
+            mx = fmax(mx, s.conv ? 0.0 : s.res);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, kWave));
+        if (lane == 0) s_max[threadIdx.x >> 6] = mx;
+        // p = r + beta p
+        for (int64_t r = threadIdx.x; r < dim; r += blockDim.x) {
+            const double2 rr = R[r], pp = P[r];
+            const cd t = cmul(be, cd{pp.x, pp.y});
+            P[r] = make_double2(rr.x + t.re, rr.y + t.im);
+        }
+        __syncthreads();
+        max_res = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) max_res = fmax(max_res, s_max[w]);
+        __syncthreads();
+        if (iter % 8 == 0 || iter == it.max_iter) {
+            if (max_res < tol_part) {
+                conv = 1;
+                break;
+            }
+            if (brk) break;
+        }
+    }
+    if (threadIdx.x == 0) {
+        it.out[0] = iter;
+        it.out[1] = conv;
+        it.out[2] = brk;
+        it.out[3] = bn2;
+        it.out[4] = bn2_0 + bn2_1;
+        it.out[5] = 0.0;
+    }
+}
+
+int fill_cocg_item(hphi_ham *h, const void *b, int part, double *r, double *p, double *hv, double *chunks,
+                   void *sh, int nsh, double zs_re, double zs_im, double tol, int max_iter, double *out, void *dst)
+{
+    const hphi_basis *bs = h->basis;
+    const Species &s = bs->sp[0];
+    if (h->kind != 0 || !s.materialized() || s.state_bytes != 4 || !s.d_hi_off32.p)
+        return fail(HPHI_ERR_UNSUPPORTED, "batched S(q, w) takes spin Hamiltonians with a stored basis");
+    if ((1u << s.n_lo) + (1u << s.n_hi) > (unsigned)kBatchLdsTab)
+        return fail(HPHI_ERR_UNSUPPORTED, "batched S(q, w): rank tables of %d sites exceed LDS", bs->n_sites);
+    CocgItemDev d{};
+    d.states = s.d_states.as<uint32_t>();
+    d.dim = s.dim;
+    d.bonds = h->d_bonds.as<SpinBondDev>();
+    d.nb = h->n_bonds;
+    d.n_lo = s.n_lo;
+    d.n_hi = s.n_hi;
+    d.lo_rank = s.d_lo_rank.as<uint32_t>();
+    d.hi_off = s.d_hi_off32.as<uint32_t>();
+    d.hz = h->has_field ? h->d_hz.as<double>() : nullptr;
+    d.n_sites = bs->n_sites;
+    d.b = static_cast<const double *>(b);
+    d.part = part;
+    d.r = r;
+    d.p = p;
+    d.h = hv;
+    d.chunks = chunks;
+    d.sh = static_cast<ShiftDev *>(sh);
+    d.nsh = nsh;
+    d.zs_re = zs_re;
+    d.zs_im = zs_im;
+    d.tol = tol;
+    d.max_iter = max_iter;
+    d.out = out;
+    *static_cast<CocgItemDev *>(dst) = d;
+    return HPHI_OK;
+}
+
+int launch_cocg_batch(const void *items_dev, int n, hipStream_t st)
+{
+    const size_t lds = sizeof(uint32_t) * kBatchLdsTab;
+    HPHI_HIP(hipFuncSetAttribute((const void *)k_cocg_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_cocg_batch, dim3(n), dim3(kBatchLdsThreads), lds, st, (const CocgItemDev *)items_dev);
+    HPHI_HIP(hipGetLastError());
+    return HPHI_OK;
+}
+
+int64_t cocg_chunks(int64_t dim) { return n_chunks(dim); }
+
 size_t batch_item_size() { return sizeof(BatchItemDev); }
 
 int fill_batch_item(hphi_ham *h, int iters, uint64_t seed, double *q, double *alpha, double *beta, int *done,

@@ -16,8 +16,13 @@ flight (not a queue drained one request at a time):
     thread with its own HIP stream (Lanczos with a convergence check every
     10 steps -- for S(q, w) on the Ritz residual estimate as well, since the
     ground vector's error carries into D(z) -- ground vector from a second
-    pass, S^z(q) excitation, shifted COCG over the shift grid), so their
-    kernels overlap on the device.
+    pass, S^z(q) excitation), so their kernels overlap on the device;
+  * the shifted COCG over the shift grid of a large S(q, w) request runs on
+    its worker's stream; small ones (sector dimension <= sqw_batch_max_dim)
+    hand their excitation to a grouping thread, which runs every excitation
+    that arrived while the previous group ran as one launch (one workgroup
+    per COCG sequence; a request alone takes the same launch, so its numbers
+    are the same alone and grouped).
 
 Every path uses fixed-order reductions, so a request's numbers are the same
 alone and in any mix. The server records arrival, admission and completion
@@ -250,7 +255,7 @@ class GpuExecutor:
     def __init__(self, device: int = 0, n_workers: int = 4, batch_max_dim: int = 20000,
                  max_batch: int = 512, lanczos_iters: int = 200, max_iter: int = 500, eta: float = 0.05,
                  n_shift: int = 64, sqw_tol: float = 1e-8, sqw_max_iter: int = 6000,
-                 gs_resid_tol: float = 1e-9, reserve_bytes: int = 512 << 20):
+                 gs_resid_tol: float = 1e-9, reserve_bytes: int = 512 << 20, sqw_batch_max_dim: int = 20000):
         from . import api
         self.api = api
         self.ctx = api.Context(device)
@@ -264,12 +269,14 @@ class GpuExecutor:
         self.sqw_tol = sqw_tol
         self.sqw_max_iter = sqw_max_iter
         self.gs_resid_tol = gs_resid_tol
+        self.sqw_batch_max_dim = sqw_batch_max_dim
         self.device = device
         self.pending_bytes = 0
         self.reserve_bytes = reserve_bytes
         self.t0 = time.perf_counter()
         self.work: "queue.Queue" = queue.Queue()
         self.batchq: "queue.Queue" = queue.Queue()
+        self.cocgq: "queue.Queue" = queue.Queue()
         self.done: "queue.Queue" = queue.Queue()
         self.bases: Dict[Tuple[int, int], object] = {}
         self.lock = threading.Lock()
@@ -299,6 +306,8 @@ class GpuExecutor:
         t = threading.Thread(target=self._batcher, args=(torch.cuda.Stream(),), daemon=True)
         t.start()
         self.threads.append(t)
+        self.cocg_thread = threading.Thread(target=self._cocg_grouper, args=(torch.cuda.Stream(),), daemon=True)
+        self.cocg_thread.start()
 
     def end(self):
         for _ in range(self.n_workers):
@@ -306,6 +315,9 @@ class GpuExecutor:
         self.batchq.put(None)
         for t in self.threads:
             t.join()
+        # the workers have handed over their last excitations
+        self.cocgq.put(None)
+        self.cocg_thread.join()
         self.threads = []
 
     def now(self) -> float:
@@ -345,13 +357,10 @@ class GpuExecutor:
         return out
 
     # -- execution --
-    def run_one(self, req, stream=None) -> Dict:
-        """One request on one stream (also used to run a request alone)."""
+    def _prepare_sqw(self, req, stream=None) -> Dict:
+        """Ground state, excitation and shift grid of an S(q, w) request."""
         api = self.api
         ham, m = self._ham(req)
-        if req.kind == "lanczos":
-            r = api.lanczos(ham, self.max_iter, seed=req.rid + 1, check_every=10, tol=1e-12, stream=stream)
-            return {"energy": float(r["energies"][0]), "iterations": r["iterations"], "path": "stream"}
         # the excitation is built from the ground vector, so its error (about
         # the Ritz residual over the gap) sets D(z)'s: stop on the residual
         # estimate too, not on the energy alone
@@ -360,10 +369,32 @@ class GpuExecutor:
         e0 = float(r["energies"][0])
         b = api.szq(ham, math.pi, r["psi"], stream=stream)
         omega = sqw_grid(float(np.max(m.jz)), self.n_shift)
-        z = e0 + omega + 1j * self.eta
-        d = api.sqw(ham, b, z, max_iter=self.sqw_max_iter, tol=self.sqw_tol, stream=stream)
-        return {"energy": e0, "iterations": r["iterations"], "omega": omega, "D": d["D"], "path": "stream",
-                "ok": bool(d["converged"]), "error": "" if d["converged"] else "COCG not converged"}
+        return {"ham": ham, "b": b, "z": e0 + omega + 1j * self.eta, "energy": e0, "iterations": r["iterations"],
+                "omega": omega}
+
+    @staticmethod
+    def _sqw_result(prep, d, path) -> Dict:
+        return {"energy": prep["energy"], "iterations": prep["iterations"], "omega": prep["omega"], "D": d["D"],
+                "path": path, "ok": bool(d["converged"]), "error": "" if d["converged"] else "COCG not converged"}
+
+    def run_sqw_group(self, preps, stream=None) -> List[Dict]:
+        """The COCG stage of small S(q, w) requests in one launch."""
+        out = self.api.sqw_batch([p["ham"] for p in preps], [p["b"] for p in preps], [p["z"] for p in preps],
+                                 max_iter=self.sqw_max_iter, tol=self.sqw_tol, stream=stream)
+        return [self._sqw_result(p, d, f"cocg_group{len(preps)}") for p, d in zip(preps, out)]
+
+    def run_one(self, req, stream=None) -> Dict:
+        """One request on one stream (also used to run a request alone)."""
+        api = self.api
+        if req.kind == "lanczos":
+            ham, _ = self._ham(req)
+            r = api.lanczos(ham, self.max_iter, seed=req.rid + 1, check_every=10, tol=1e-12, stream=stream)
+            return {"energy": float(r["energies"][0]), "iterations": r["iterations"], "path": "stream"}
+        prep = self._prepare_sqw(req, stream)
+        if sector_dim(req.n_sites, req.two_sz) <= self.sqw_batch_max_dim:
+            return self.run_sqw_group([prep], stream)[0]
+        d = api.sqw(prep["ham"], prep["b"], prep["z"], max_iter=self.sqw_max_iter, tol=self.sqw_tol, stream=stream)
+        return self._sqw_result(prep, d, "stream")
 
     def run_batch(self, reqs, stream=None) -> List[Dict]:
         hams = [self._ham(r)[0] for r in reqs]
@@ -378,10 +409,43 @@ class GpuExecutor:
                 return
             self._begin_request(req)
             try:
+                if req.kind == "sqw" and sector_dim(req.n_sites, req.two_sz) <= self.sqw_batch_max_dim:
+                    prep = self._prepare_sqw(req, stream)
+                    # the excitation must be complete before another stream reads it
+                    stream.synchronize()
+                    self.cocgq.put((req, prep))
+                    continue
                 res = self.run_one(req, stream)
             except Exception as e:  # report, keep serving
                 res = {"ok": False, "error": repr(e)}
             self.done.put((req.rid, res))
+
+    def _cocg_grouper(self, stream):
+        """Runs the excitations handed over while the previous group ran as
+        one batched COCG launch."""
+        while True:
+            item = self.cocgq.get()
+            if item is None:
+                return
+            group = [item]
+            stop = False
+            while len(group) < self.max_batch:
+                try:
+                    it = self.cocgq.get_nowait()
+                except queue.Empty:
+                    break
+                if it is None:
+                    stop = True
+                    break
+                group.append(it)
+            try:
+                outs = self.run_sqw_group([p for _, p in group], stream)
+            except Exception as e:
+                outs = [{"ok": False, "error": repr(e)}] * len(group)
+            for (r, _), o in zip(group, outs):
+                self.done.put((r.rid, o))
+            if stop:
+                return
 
     def _batcher(self, stream):
         while True:

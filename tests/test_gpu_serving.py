@@ -104,6 +104,48 @@ def test_lanczos_batch_breakdown(api, ctx):
     assert o["energy"] >= -8 * 0.25 - 1e-12
 
 
+def test_sqw_batch_matches_single_and_oracle(api, ctx):
+    """S(q, w) of many spin requests in one launch (one workgroup per COCG
+    sequence) against hphi_sqw run per request and against the oracle's
+    direct solve. q = pi gives a real excitation (one sequence), q = 2 pi / 3
+    a complex one (two sequences). A request's numbers do not depend on the
+    rest of the launch (bit for bit). Tolerance: both runs stop at
+    |r| <= tol |b| (tol 1e-10) from different summation orders, so
+    |dD| <= 2 tol |b|^2 / eta; the direct solve differs by tol |b|^2 / eta."""
+    say("sqw batch")
+    specs = [(12, "chain", math.pi, 1), (12, "ladder", 2 * math.pi / 3, 2), (13, "chain", math.pi, 3),
+             (14, "ladder", math.pi, 4), (16, "chain", 2 * math.pi / 3, 5), (10, "chain", math.pi, 6)]
+    hams, bs, zs, refs = [], [], [], []
+    eta, tol = 0.05, 1e-10
+    for n, lat, q, seed in specs:
+        m = W.random_heisenberg(n, lat, seed)
+        two_sz = n % 2
+        h = api.Hamiltonian.spin(api.Basis.spin(ctx, n, two_sz), m)
+        r = api.lanczos(h, 300, seed=seed, want_vector=True)
+        b = api.szq(h, q, r["psi"])
+        z = r["energies"][0] + np.linspace(0.0, 4.0 * float(np.max(m.jz)), 24) + 1j * eta
+        hams.append(h)
+        bs.append(b)
+        zs.append(z)
+        refs.append((m, n, two_sz, r))
+    out = api.sqw_batch(hams, bs, zs, max_iter=4000, tol=tol)
+    for (n, lat, q, seed), h, b, z, o, (m, n_, two_sz, r) in zip(specs, hams, bs, zs, out, refs):
+        single = api.sqw(h, b, z, max_iter=4000, tol=tol)
+        bh = b.cpu().numpy()
+        b2 = float(np.vdot(bh, bh).real)
+        assert o["converged"] and single["converged"], (n, lat, o["max_residual"])
+        err = float(np.max(np.abs(o["D"] - single["D"])))
+        assert err <= 2 * tol * b2 / eta + 1e-13 * float(np.max(np.abs(single["D"]))), (n, lat, err)
+        assert np.all(-o["D"].imag > 0)
+        if n <= 13:
+            s_ = O.basis_list(n, O.sector_popcount_spin(n, two_sz))
+            ref = O.dyn_corr_direct(O.spin_sparse(m, s_), bh, z)
+            assert float(np.max(np.abs(o["D"] - ref))) <= 3 * tol * b2 / eta + 1e-12, (n, lat)
+        say(f"  {n} {lat} q={q:.3f}: iters batch {o['iterations']} single {single['iterations']}, max|dD| {err:.2e}")
+    alone = api.sqw_batch([hams[4]], [bs[4]], [zs[4]], max_iter=4000, tol=tol)[0]
+    assert np.array_equal(alone["D"], out[4]["D"]) and alone["iterations"] == out[4]["iterations"]
+
+
 def _oracle_served_sqw(req, ex):
     """The server's S(q, w) procedure written out with the oracle: Lanczos
     from the request's SplitMix64 start vector, stopped by the same rule
