@@ -588,7 +588,7 @@ def run_serving(a, W):
            "config": {"workload": "serving_mix_heisenberg_chains_ladders_N12-26", "requests": n_req,
                       "kinds": {k: len(v) for k, v in kinds.items()}, "lanczos_small_batch_max_dim": 20000,
                       "sqw_shifts": 64, "eta": 0.05, "sqw_tol": ex.sqw_tol, "sqw_max_iter": ex.sqw_max_iter,
-                      "workers": 4},
+                      "sqw_group_max_dim": ex.sqw_batch_max_dim, "workers": 4},
            "capacity": {"throughput_per_s": round(cap, 3), "span_s": round(cap_run["span_s"], 3),
                         "completed": cap_run["completed"], "failed": cap_run["failed"],
                         "p50_latency_ms": round(1e3 * cap_run["p50_latency_s"], 2),
