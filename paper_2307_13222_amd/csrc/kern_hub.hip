@@ -1537,13 +1537,16 @@ __global__ __launch_bounds__(1024) void k_hub_up_tile(HubKArgs a)
                 for (int t = 0; t < 8; ++t) {
                     const uint32_t k = 8u * g + t;
                     if (k < nl) {
-                        const S *tp = tile + ((e4[t >> 1] >> (16 * (t & 1))) & 0xFFFFu) * RS + 2 * l8;
+                        // one 16-byte read: a row group's eight lanes read
+                        // one contiguous 128-byte row segment per pass
+                        const P2 tv = *reinterpret_cast<const P2 *>(
+                            tile + ((e4[t >> 1] >> (16 * (t & 1))) & 0xFFFFu) * RS + 2 * l8);
                         if (k < nlp) {
-                            p0v += tp[0];
-                            p1v += tp[1];
+                            p0v += tv.x;
+                            p1v += tv.y;
                         } else {
-                            m0v += tp[0];
-                            m1v += tp[1];
+                            m0v += tv.x;
+                            m1v += tv.y;
                         }
                     }
                 }
