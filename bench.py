@@ -662,8 +662,12 @@ def run_ctpq(a, api, ctx, W):
     dim, nv = basis.dim, 16
     wl = {"workload": "ctpq_xxz_j2_chain28_sz0_16vec", "dim": dim, "n_vec": nv, "n_max": 6, "dtau": 0.02,
           "k_steps": k_steps, "storage": "c64 (FP32 complex), f64 norms"}
+    if a.schedule:
+        ham.set_schedule(**json.loads(a.schedule))
     if not a.no_tune:
         wl["schedule"] = autotune.tune(ham, "c64", nv, force=a.retune)["schedule"]
+    else:
+        wl["schedule"] = {k: v for k, v in ham.get_schedule().items() if k.startswith("spin_")}
     # block H*V time with HIP events (the kernel the propagator runs)
     v = (torch.rand((dim, nv), dtype=torch.complex64, device="cuda") - (0.5 + 0.5j)).contiguous()
     w = torch.empty_like(v)

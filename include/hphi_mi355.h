@@ -298,6 +298,14 @@ void hphi_ham_free(hphi_ham *h);
  *                   7 (the tables are rebuilt when it changes); -1 = the
  *                   fewest sites whose largest block of 16 FP64 columns
  *                   fits LDS (the default)
+ *   spin_split      1: the stored-list spin product in two passes -- the
+ *                   bonds with an end in the low half of the sites (and the
+ *                   fields), then the bonds inside the high half in slab
+ *                   order (a state's high-bond partners sit at the same
+ *                   position of another block of its class); products
+ *                   without fused dots, at most 128 high bonds; otherwise
+ *                   one pass. -1: one pass (the default). The products equal
+ *                   the one-pass ones up to summation order.
  * Errors: INVALID_ARG (value outside its range), UNSUPPORTED (hub_sweep 7
  * or hub_tile_bits for blocks the tile kernel cannot take). */
 typedef struct {
@@ -311,6 +319,7 @@ typedef struct {
     int hub_row_order;
     int spin_tables;
     int hub_tile_bits;
+    int spin_split;
 } hphi_schedule;
 
 int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s);

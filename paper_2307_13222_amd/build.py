@@ -22,7 +22,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 SOURCES = ["host.cpp", "capi.cpp", "capi_methods.cpp", "kern_spin.hip", "kern_hub.hip",
            "kern_vec.hip", "kern_methods.hip", "kern_big.hip", "kern_batch.hip", "kern_lobpcg.hip",
            "capi_lobpcg.cpp", "noalloc.hip", "kern_hub_pairs.hip",
-           "kern_spin_gc.hip", "capi_gc.cpp", "kern_spin_s.hip", "capi_spin_s.cpp"]
+           "kern_spin_gc.hip", "capi_gc.cpp", "kern_spin_s.hip", "capi_spin_s.cpp",
+           "kern_spin_split.hip"]
 
 
 def _compile(src: str) -> str:

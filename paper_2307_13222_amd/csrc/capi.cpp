@@ -905,6 +905,10 @@ int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s)
             return fail(HPHI_ERR_INVALID_ARG, "spin_tables %d", s->spin_tables);
         n.spin_tables = s->spin_tables == -1 ? 0 : s->spin_tables;
     }
+    if (s->spin_split) {
+        if (s->spin_split != -1 && s->spin_split != 1) return fail(HPHI_ERR_INVALID_ARG, "spin_split %d", s->spin_split);
+        n.spin_split = s->spin_split == -1 ? 0 : 1;
+    }
     if (s->hub_sweep == 7 && h->kind == 1 && !h->hub.ft_ok && !s->hub_tile_bits)
         return fail(HPHI_ERR_UNSUPPORTED, "hub_sweep 7: no tile tables for this Hamiltonian");
     if (s->hub_tile_bits) {

@@ -136,6 +136,22 @@ struct PairNbrDev {
     double v;
 };
 
+// Split spin H*v: a bond with both ends in the high half of the sites, in
+// high-half coordinates.
+struct HiBondDev {
+    uint32_t mask, pad;
+    double jz4, jxy2;
+};
+constexpr int kMaxHiBonds = 128;
+struct SpinSplit {
+    bool built = false;
+    int n_hi_bonds = 0, n_rest = 0;
+    DevMem hib, rest, hi_list, cls_first, cls_len;
+    std::vector<uint32_t> cls_first_h, cls_len_h;
+    DevMem items[7];      // per positions per wave P = 2^i: per-XCD cumulative item counts
+    bool items_ok[7] = {};
+};
+
 // SpinGC (full 2^N space): one off-diagonal term of a bit window. The
 // tile index l holds the low bits and the window's bits; the term maps l to
 // l ^ mloc with coefficient cpar when bits pi and pj of l agree, else canti
@@ -264,6 +280,8 @@ struct hphi_ham {
     int gc_ndiag = 0;
     bool gc_has_hz = false;
     hphi::GcPlan gc_plan[3];
+    // spin: bonds split into high-half and other bonds (built on first use)
+    hphi::SpinSplit split;
     // spin-S: bonds as given (jz, jxy), fields and single-ion terms
     std::vector<hphi_spin_bond> sbonds;
     std::vector<double> s_hz, s_dion;
@@ -271,7 +289,7 @@ struct hphi_ham {
     // defaults: 128-column slabs, 128 workgroups per XCD, 32-row items,
     // hop-ordered down slots, work-item queues with two columns per lane;
     // spin: 8 workgroups per CU
-    hphi_schedule sched_cfg{128, 128, 16, 6, 8, 0, 5, 2, 0, 0};
+    hphi_schedule sched_cfg{128, 128, 16, 6, 8, 0, 5, 2, 0, 0, 0};
     // scratch for reductions and work queues
     hphi::DevMem sched;         // unsigned [16]: per-XCD item queues + counter
     hphi::DevMem red_partial;   // double [kReduceSlots]
@@ -397,6 +415,8 @@ bool hub_rows_fused_ok(hphi_ham *h, int nv);
 bool spin_stored_path(const hphi_ham *h);
 int launch_spin_mult(hphi_ham *h, const MultArgs &a);
 int launch_spin_mult_implicit(hphi_ham *h, const MultArgs &a);
+int spin_split_tables(hphi_ham *h);
+int launch_spin_hi_pass(hphi_ham *h, const MultArgs &a);
 int launch_hub_mult(hphi_ham *h, const MultArgs &a);
 int launch_mult(hphi_ham *h, const MultArgs &a);
 // w += H_2body v for the Hubbard two-body terms (NV lanes per element, rows

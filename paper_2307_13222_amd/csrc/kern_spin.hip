@@ -428,6 +428,28 @@ int launch_spin_mult(hphi_ham *h, const MultArgs &m)
     if (cap > kMaxGrid) cap = kMaxGrid;
     int grid = (int)(need < cap ? need : cap);
     if (grid < 1) grid = 1;
+    // split product: the bonds with an end in the low half into w, then
+    // the high-half bonds and the caller's epilogue in slab order
+    bool split = h->sched_cfg.spin_split == 1 && !m.dots && !m.cocg && m.v != m.w && (!m.u || m.u != m.w) &&
+                 (!m.acc || m.acc != m.w) && (!m.raw_out || m.raw_out != m.w);
+    if (split) {
+        HPHI_TRY(spin_split_tables(h));
+        split = h->split.n_hi_bonds > 0 && h->split.n_hi_bonds <= kMaxHiBonds;
+    }
+    if (split) {
+        a.bonds = h->split.rest.as<SpinBondDev>();
+        a.nb = h->split.n_rest;
+        a.u = nullptr;
+        a.acc_out = nullptr;
+        a.coef = nullptr;
+        a.coef_cplx = 0;
+        a.raw_out = nullptr;
+        a.nd = 0;
+        a.cocg = nullptr;
+        if (dtype_is_f32(m.dtype)) HPHI_TRY(launch_spin_nv<float>(nv, a, lds, grid, tab, m.stream));
+        else HPHI_TRY(launch_spin_nv<double>(nv, a, lds, grid, tab, m.stream));
+        return launch_spin_hi_pass(h, m);
+    }
     if (dtype_is_f32(m.dtype)) return launch_spin_nv<float>(nv, a, lds, grid, tab, m.stream);
     return launch_spin_nv<double>(nv, a, lds, grid, tab, m.stream);
 }
