@@ -237,7 +237,7 @@ def base_line(a, value, ms_per_step, dtype, config):
             "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
 
 
-def run_lanczos(a, api, ham, dim, iters, storage, wl, kernel, tune_dtype, hv_events=True):
+def run_lanczos(a, api, ham, dim, iters, storage, wl, kernel, tune_dtype, hv_events=True, check_every=0):
     """Timed solves; with hv_events the HIP events around every product are
     recorded inside them, otherwise (products of a few microseconds, where
     the events themselves would lengthen the solves) in two extra solves
@@ -261,7 +261,8 @@ def run_lanczos(a, api, ham, dim, iters, storage, wl, kernel, tune_dtype, hv_eve
     t0 = time.perf_counter()
     for k in range(a.steps):
         s0 = time.perf_counter()
-        r = api.lanczos(ham, iters, seed=1 + k, storage=storage, stream=stream, time_kernels=hv_events)
+        r = api.lanczos(ham, iters, seed=1 + k, storage=storage, stream=stream, time_kernels=hv_events,
+                        check_every=check_every, tol=0.0)
         lat.append(time.perf_counter() - s0)
         hv_s += r["hv_seconds"]
         hv_n += r["hv_calls"]
@@ -459,10 +460,13 @@ def main():
         wl = {"workload": "j1j2_square_6x6_J2_0.5_sz0", "dim": basis.dim, "lanczos_iters": iters,
               "storage": "f32 vectors, f64 alpha/beta"}
         a.no_tune = True
+        # a product takes seconds here: every tenth step reports on stderr
+        os.environ["HPHI_PROGRESS"] = "1"
         out, e32 = run_lanczos(a, api, ham, basis.dim, iters, "f32", wl,
-                               "H*v = k_spin_hv_implicit<float> (implicit basis, 64-bit indices)", "f32")
+                               "H*v = k_spin_hv_implicit<float> (implicit basis, 64-bit indices)", "f32",
+                               check_every=10)
         torch.cuda.empty_cache()
-        r64 = api.lanczos(ham, iters, seed=1, storage="f64")
+        r64 = api.lanczos(ham, iters, seed=1, storage="f64", check_every=10, tol=0.0)
         out["e0_fp64_storage"] = float(r64["energies"][0])
         out["e0_abs_diff_fp32_vs_fp64"] = abs(e32[0] - float(r64["energies"][0]))
     else:

@@ -422,7 +422,9 @@ typedef struct {
  * FP64 run, then a few FP64 Lanczos steps from that vector (a restart in
  * FP64: its Krylov space holds the vector, so its lowest Ritz value lies
  * at or below the Rayleigh quotient). The refinement needs a second pass
- * and five FP64 vectors of workspace. Synchronous.
+ * and five FP64 vectors of workspace. Synchronous. With HPHI_PROGRESS set
+ * in the environment each convergence check (every check_every steps)
+ * prints the step count and the lowest Ritz value on stderr.
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE, BUSY. */
 int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *opts, double *energies,
                  int n_energies, hphi_lanczos_info *info);

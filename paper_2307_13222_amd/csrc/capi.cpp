@@ -6,6 +6,9 @@
 #include <map>
 #include <memory>
 
+#include <cstdio>
+#include <cstdlib>
+
 #include "internal.h"
 
 using namespace hphi;
@@ -994,6 +997,14 @@ struct Carve {
     bool ok() const { return off <= cap; }
 };
 
+// HPHI_PROGRESS set in the environment: long solves report each
+// convergence check on stderr.
+static bool progress_enabled()
+{
+    static const bool on = std::getenv("HPHI_PROGRESS") != nullptr;
+    return on;
+}
+
 struct LanczosRun {
     hphi_ham *h;
     int dt;
@@ -1205,6 +1216,8 @@ struct LanczosRun {
                 HPHI_HIP(hipMemcpy(hb.data(), beta, sizeof(double) * (n + 1), hipMemcpyDeviceToHost));
                 std::vector<double> ev(n_energies);
                 HPHI_TRY(tridiag_lowest(ha.data(), hb.data(), n, n_energies, ev.data(), nullptr));
+                if (progress_enabled())
+                    std::fprintf(stderr, "hphi_lanczos: %d iterations, lowest Ritz value %.15g\n", n, ev[0]);
                 bool ok = last_ev.size() == ev.size();
                 for (size_t i = 0; ok && i < ev.size(); ++i)
                     ok = std::fabs(ev[i] - last_ev[i]) < tol * std::max(1.0, std::fabs(ev[i]));
