@@ -157,3 +157,36 @@ def test_ham_busy_on_another_stream(api, ctx):
     h.mult(v, w2, stream=s2)           # drained: the other stream may use it
     s2.synchronize()
     assert torch.equal(w, w2)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_spin_gc_tiny_spaces(api, ctx, n):
+    # fewer sites than the four low bits of a window tile: one tile holds
+    # the whole space; one site is a spin in a field, E0 = -|h|/2
+    say("spin gc tiny", n)
+    m = W.random_spin_gc(max(n, 2), "chain", 40 + n) if n > 1 else W.spin_gc(1, np.zeros((0, 2)), 0, 0, 0, 0.6, 0.8)
+    if n == 1:
+        h = api.Hamiltonian.spin_gc(api.Basis.spin_gc(ctx, 1), m)
+        w = host(h.mult(dev(np.array([1.0, 0.0]))))
+        assert np.allclose(w, O.spin_gc_hv(m, np.array([1.0, 0.0])), atol=1e-15)
+        r = api.lanczos(h, 2, seed=1)
+        assert abs(r["energies"][0] + 0.5) < 1e-14
+        return
+    m = W.random_spin_gc(n, "chain", 40 + n)
+    h = api.Hamiltonian.spin_gc(api.Basis.spin_gc(ctx, n), m)
+    v = W.random_vector(1 << n, n)
+    assert np.allclose(host(h.mult(dev(v))), O.spin_gc_hv(m, v), atol=1e-13)
+
+
+@pytest.mark.parametrize("n,two_s,two_sz", [(1, 2, 0), (1, 3, 3), (2, 2, -4), (2, 3, 2), (3, 2, 6)])
+def test_spin_s_tiny_sectors(api, ctx, n, two_s, two_sz):
+    # one-site and fully polarized sectors (one state), two sites
+    say("spin-S tiny", n, two_s, two_sz)
+    pairs = W.chain_pairs(n) if n > 2 else ([(0, 1)] if n == 2 else np.zeros((0, 2)))
+    m = W.spin_s_model(n, two_s, pairs, 0.9, 1.1, hz=0.3, d_ion=0.2)
+    b = api.Basis.spin_s(ctx, n, two_s, two_sz)
+    s = O.spin_s_basis(n, two_s, two_sz)
+    assert b.dim == len(s)
+    h = api.Hamiltonian.spin_s(b, m)
+    v = W.random_vector(len(s), n + two_s)
+    assert np.allclose(host(h.mult(dev(v))), O.spin_s_hv(m, s, v), atol=1e-13)
