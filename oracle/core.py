@@ -11,7 +11,8 @@ References are to the HPhi update paper (arXiv:2307.13222):
   Sec. 3.2    dynamical correlation D(z) = <Phi_ex|(z - H)^-1|Phi_ex>,
               S^zz(q, w) with S^z_l and phases e^{iql}, q = 2 pi m / L.
   Sec. 3.4    real-time evolution psi(t + dt) = sum_{n<=n_max} (-i H dt)^n / n!
-              psi(t); norm, energy and double occupancy as its checks.
+              psi(t); norm, energy and double occupancy as its checks; a
+              time-dependent H(t) held at H(t_k) over the step from t_k.
   Sec. 3.5.1  TPQ state, random vector uniform on the d_H sphere, cTPQ
               propagator U_c = sum_{n<=n_max} (-dtau H / 2)^n / n!,
               beta_k = k dtau, relative squared norms D_k = N_k / N_{k-1}.
@@ -673,11 +674,21 @@ def taylor_evolve(hv: Callable[[np.ndarray], np.ndarray], psi0: np.ndarray, n_ma
     Records at t_k = k dt the norm <psi|psi>, the energy <psi|H|psi> / <psi|psi>
     and, with a diagonal weight w_x (e.g. the count of doubly occupied sites
     divided by N_s), <psi|w|psi> / <psi|psi>. psi0: (dim,) or (dim, B)."""
+    return taylor_evolve_td(lambda k: hv, psi0, n_max, dt, n_steps, weight)
+
+
+def taylor_evolve_td(hv_at: Callable[[int], Callable[[np.ndarray], np.ndarray]], psi0: np.ndarray, n_max: int,
+                     dt: float, n_steps: int, weight: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
+    """The same with a time-dependent H (Sec. 3.4, H(t) in the Schroedinger
+    equation): hv_at(k) applies H(t_k). The step from t_k to t_{k+1} sums the
+    Taylor series of exp(-i H(t_k) dt), i.e. H is held at its value at the
+    start of the step, and the energy recorded at t_k is <H(t_k)>."""
     psi = np.array(psi0, dtype=np.complex128)
     if psi.ndim == 1:
         psi = psi[:, None]
     nrm, en, ob = [], [], []
     for k in range(n_steps + 1):
+        hv = hv_at(k)
         hp = np.stack([hv(psi[:, j]) for j in range(psi.shape[1])], axis=1)
         n2 = np.real(np.sum(np.conj(psi) * psi, axis=0))
         nrm.append(n2)

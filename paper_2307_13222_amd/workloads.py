@@ -262,6 +262,67 @@ def extended_hubbard_square(lx: int, ly: int, t: float = 1.0, u: float = 4.0, v:
                            f"ext_hubbard_square_{lx}x{ly}")
 
 
+@dataclass
+class HubbardFrames:
+    """Time-dependent amplitudes of a HubbardModel (Sec. 3.4: H(t) with
+    t_ij(t) and two-body terms I(t)). Frame k holds the amplitudes at time
+    t_k; None keeps the model's own values in every frame."""
+    n_frames: int
+    hop_t: Optional[np.ndarray] = None    # (n_frames, n_hops)
+    u_site: Optional[np.ndarray] = None   # (n_frames, n_sites)
+    pair_v: Optional[np.ndarray] = None   # (n_frames, n_pairs, 4): v, j_hund, j_ex, j_pair
+
+
+def model_at_frame(m: HubbardModel, fr: HubbardFrames, k: int) -> HubbardModel:
+    """The model with the amplitudes of frame min(k, n_frames - 1)."""
+    f = min(int(k), fr.n_frames - 1)
+    t = m.t if fr.hop_t is None else np.array(fr.hop_t[f], dtype=np.float64)
+    u = m.u_site if fr.u_site is None else np.array(fr.u_site[f], dtype=np.float64)
+    pv, pjh, pjx, pjp = m.pv, m.pjh, m.pjx, m.pjp
+    if fr.pair_v is not None and m.n_pairs:
+        pa = np.asarray(fr.pair_v[f], dtype=np.float64)
+        pv, pjh, pjx, pjp = (pa[:, c].copy() for c in range(4))
+    return HubbardModel(m.n_sites, m.hi, m.hj, t, u, f"{m.name}_frame{f}", m.site_x,
+                        m.pi, m.pj, pv, pjh, pjx, pjp)
+
+
+def interaction_ramp(m: HubbardModel, u_from: float, u_to: float, n_ramp: int, n_frames: int) -> HubbardFrames:
+    """U(t_k) rising linearly from u_from at k = 0 to u_to at k = n_ramp and
+    constant after: the interaction quench of Sec. 3.4 spread over n_ramp
+    steps (n_ramp = 0: the sudden quench)."""
+    k = np.arange(n_frames, dtype=np.float64)
+    u = u_to if n_ramp <= 0 else u_from + (u_to - u_from) * np.minimum(k, n_ramp) / n_ramp
+    u = np.broadcast_to(np.asarray(u, dtype=np.float64), (n_frames,))
+    return HubbardFrames(n_frames, u_site=np.repeat(u[:, None], m.n_sites, axis=1))
+
+
+def hopping_drive(m: HubbardModel, amp: float, omega: float, dt: float, n_frames: int) -> HubbardFrames:
+    """Periodically modulated transfers t_ij(t_k) = t_ij (1 + amp sin(omega k dt))
+    (every hop scaled alike; amp > 1 makes the factor change sign)."""
+    f = 1.0 + amp * np.sin(omega * dt * np.arange(n_frames))
+    return HubbardFrames(n_frames, hop_t=f[:, None] * np.asarray(m.t, dtype=np.float64)[None, :])
+
+
+def random_frames(m: HubbardModel, n_frames: int, seed: int, hops: bool = True, u: bool = True,
+                  pairs: bool = True, repeat: int = 2) -> HubbardFrames:
+    """Seeded random amplitudes around the model's, each drawn frame held
+    for `repeat` consecutive frames. Transfers: t_h (1/2 + r), r uniform in
+    [0, 1) per hop and frame (independent trajectories); U_i: U_i + r,
+    r uniform in [-1, 1); pair coefficients: c (1/2 + r)."""
+    rng = np.random.default_rng(seed)
+    nd = (n_frames + repeat - 1) // repeat
+    idx = np.arange(n_frames) // repeat
+    ht = us = pv = None
+    if hops and m.n_hops:
+        ht = (np.asarray(m.t, dtype=np.float64)[None, :] * (0.5 + rng.random((nd, m.n_hops))))[idx]
+    if u:
+        us = (np.asarray(m.u_site, dtype=np.float64)[None, :] + rng.uniform(-1.0, 1.0, (nd, m.n_sites)))[idx]
+    if pairs and m.n_pairs:
+        base = np.stack([m.pv, m.pjh, m.pjx, m.pjp], axis=1).astype(np.float64)
+        pv = (base[None, :, :] * (0.5 + rng.random((nd, m.n_pairs, 4))))[idx]
+    return HubbardFrames(n_frames, ht, us, pv)
+
+
 def random_vector(dim: int, seed: int, dtype=np.float64, nvec: int = 1) -> np.ndarray:
     """Seeded test vector (numpy PCG64), uniform in [-1/2, 1/2); complex
     dtypes get independent real and imaginary parts. Shape (dim,) or
