@@ -24,6 +24,11 @@ Other workloads (--workload), reported the same way:
                 (dim 165,636,900): U = 0 ground state (Lanczos), then real-time
                 steps with U = 8 (Taylor order 10, dt 0.01), complex FP64;
                 one step = 10 complex H*v; norm and energy drift reported
+  tevol_ramp_hubbard16  the same with a time-dependent H: U(t) rising
+                linearly from 0 to 8 over the warmup and timed steps (one
+                frame per step); the energy change checked against the
+                work (U_k+1 - U_k) N_s <D>, and the cost of the frame
+                switches against the same steps with one frame held
   lobpcg_hubbard3x4  lowest 4 (+2 guard) eigenpairs of the 3x4 periodic Hubbard
                 lattice at half filling (U = 4, dim 853,776) by LOBPCG with the
                 point-Jacobi preconditioner; energies vs a long Lanczos
@@ -63,6 +68,7 @@ def parse():
     p.add_argument("--iters", type=int, default=0, help="Krylov / TPQ steps per solve (0 = workload default)")
     p.add_argument("--workload", default="hubbard4x4",
                    choices=["hubbard4x4", "heisenberg16", "ctpq_xxz28", "j1j2_6x6", "serving_mix", "tevol_hubbard16",
+                            "tevol_ramp_hubbard16",
                             "lobpcg_hubbard3x4", "copy_probe", "ext_hubbard4x4", "tfim_ring28", "spin1_chain18"])
     p.add_argument("--requests", type=int, default=64, help="requests per serving run (serving_mix)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -85,12 +91,12 @@ def parse():
 # counters (fetch 2.000, write 1.000). Valid only for the kernel sources and
 # schedule it was taken with; anything else reports null.
 HUB_TRAFFIC = {
-    "sources_sha256": {"kern_hub.hip": "d27f08120da570c0fd4b2b128f4110562f3a264543540c276083061bae78cf23",
+    "sources_sha256": {"kern_hub.hip": "67c72863356c693c06bb782939071a0a960bcb395ded0378832f0ec5c999fd33",
                        "kern_common.h": "82a4da084e46d3f069fff2bbec75262cce5cf6131077ca6b4d166d41e8c25fce"},
     "schedule": {"hub_slab_cols": 128, "hub_groups": 128, "hub_item_rows": 16, "hub_row_cols": 6, "hub_sweep": 7,
                  "hub_row_order": 2, "hub_tile_bits": 0},
-    "cols_fetch_kib": 3.015888e+06, "cols_write_kib": 1.299301e+06,
-    "rows_fetch_kib": 1.449196e+06, "rows_write_kib": 2.588495e+06,
+    "cols_fetch_kib": 3.004494e+06, "cols_write_kib": 1.299302e+06,
+    "rows_fetch_kib": 1.456348e+06, "rows_write_kib": 2.588495e+06,
     "fetch_factor": 2.0, "write_factor": 1.0,
 }
 
@@ -188,6 +194,22 @@ def cpu_baseline(workload: str, sample_rows: int):
         dt = time.perf_counter() - t0
         states, bytes_per = nu * len(dns), 16.0
         sample = f"oracle extended-Hubbard H*v over up-rows [0, {nu}) of {len(ups)}"
+    elif workload in ("tevol_hubbard16", "tevol_ramp_hubbard16"):
+        # the complex product a Taylor order applies, on the 16-site ring
+        # at U = 8 (the ramp's frames differ only in U, a diagonal term)
+        m = W.hubbard_chain(16, 1.0, 8.0)
+        ups, dns = O.hubbard_basis(16, 8, 8)
+        nu = min(sample_rows if sample_rows > 0 else len(ups), len(ups))
+        rng = np.random.default_rng(0)
+        dim = len(ups) * len(dns)
+        vr, vi = rng.random(dim) - 0.5, rng.random(dim) - 0.5
+        t0 = time.perf_counter()
+        O.hubbard_hv_rows(m, ups, dns, vr, 0, nu)
+        O.hubbard_hv_rows(m, ups, dns, vi, 0, nu)
+        dt = time.perf_counter() - t0
+        states, bytes_per = nu * len(dns), 32.0
+        sample = (f"oracle complex Hubbard H*v (real and imaginary parts) over up-rows [0, {nu}) "
+                  f"of {len(ups)} on the 16-site ring")
     elif workload == "tfim_ring28":
         m = W.tfim_chain(28, 1.0, 1.0)
         count = sample_rows if sample_rows > 0 else 1 << 26
@@ -333,8 +355,10 @@ def main():
     if a.workload == "copy_probe":
         copy_probe(a)
         return
-    if a.workload == "tevol_hubbard16":
-        out = run_tevol(a, api, W)
+    if a.workload in ("tevol_hubbard16", "tevol_ramp_hubbard16"):
+        out = run_tevol(a, api, W, ramp=a.workload == "tevol_ramp_hubbard16")
+        if not a.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(a.workload, a.cpu_sample_rows)
         print(json.dumps(out), flush=True)
         return
     if a.workload == "lobpcg_hubbard3x4":
@@ -476,9 +500,11 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def run_tevol(a, api, W):
+def run_tevol(a, api, W, ramp=False):
     """Real-time evolution after an interaction quench (the example of the
-    paper's real-time section, on 16 sites)."""
+    paper's real-time section, on 16 sites); with ramp, U(t) rises linearly
+    from 0 to 8 over the warmup and timed steps (a time-dependent H, one
+    frame per step)."""
     import torch
     ctx = api.Context(0)
     n, n_max, dt = 16, 10, 0.01
@@ -488,29 +514,54 @@ def run_tevol(a, api, W):
     psi = r["psi"].to(torch.complex128)
     del r
     h0.close()
-    h = api.Hamiltonian.hubbard(basis, W.hubbard_chain(n, 1.0, 8.0))
+    m8 = W.hubbard_chain(n, 1.0, 8.0)
+    n_fr = a.warmup + a.steps + 1
+    fr = W.interaction_ramp(m8, 0.0, 8.0, n_fr - 1, n_fr) if ramp else None
+    h = api.Hamiltonian.hubbard(basis, m8, frames=fr)
     print("tevol: initial state ready", file=sys.stderr, flush=True)
     api.time_evolve(h, psi, a.warmup, dt=dt, n_max=n_max)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    g = api.time_evolve(h, psi, a.steps, dt=dt, n_max=n_max, double_occupancy=True)
+    g = api.time_evolve(h, psi, a.steps, dt=dt, n_max=n_max, double_occupancy=True,
+                        first_frame=a.warmup if ramp else 0)
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     dim = basis.dim
     alg = 2.0 * 16 * dim * n_max * a.steps          # complex FP64: read v + write w per H*v
     gbs = alg / total / 1e9
-    out = base_line(a, gbs, 1e3 * total / a.steps, "c128",
-                    {"workload": "tevol_hubbard_ring16_half_filling_quench_U0_to_U8", "dim": dim, "n_max": n_max,
-                     "dt": dt, "steps": a.steps, "initial": "U = 0 ground state (Lanczos)"})
+    wl = ("tevol_hubbard_ring16_half_filling_ramp_U0_to_U8" if ramp
+          else "tevol_hubbard_ring16_half_filling_quench_U0_to_U8")
+    cfg = {"workload": wl, "dim": dim, "n_max": n_max, "dt": dt, "steps": a.steps,
+           "initial": "U = 0 ground state (Lanczos)"}
+    if ramp:
+        cfg.update({"frames": n_fr, "ramp": f"U(t_k) = 8 k / {n_fr - 1}, one frame per step"})
+    out = base_line(a, gbs, 1e3 * total / a.steps, "c128", cfg)
     out.update({"hbm_peak_frac": round(gbs / HBM_PEAK_GBS, 4), "time_steps_per_s": round(a.steps / total, 4),
                 "hv_per_step": n_max,
                 "norm_drift": float(np.max(np.abs(g["norm"] / g["norm"][0] - 1))),
-                "energy_drift": float(np.max(np.abs(g["energy"] - g["energy"][0]))),
                 "energy": float(g["energy"][0, 0]),
                 "double_occupancy": [round(float(x), 8) for x in g["double_occupancy"]],
                 "roofline": roofline(gbs, 2.0 * 16 * dim,
                                      "complex H*v = Hubbard rows + cols kernels, complex epilogue "
                                      "(rate from wall time of whole steps)")})
+    if ramp:
+        # exact evolution under H(t_k) conserves <H(t_k)>: the energy steps
+        # by the work (U_k+1 - U_k) N_s <D>(t_k+1)
+        u = fr.u_site[a.warmup:a.warmup + a.steps + 1, 0]
+        de = np.diff(g["energy"][:, 0])
+        work = np.diff(u) * n * np.asarray(g["double_occupancy"][1:])
+        out["ramp_work_residual"] = float(np.max(np.abs(de - work)))
+        out["energy_last"] = float(g["energy"][-1, 0])
+        # the same steps with the last frame held (no frame switches)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        api.time_evolve(h, psi, a.steps, dt=dt, n_max=n_max, double_occupancy=True, first_frame=n_fr - 1)
+        torch.cuda.synchronize()
+        fixed = time.perf_counter() - t1
+        out["ms_per_step_fixed_frame"] = round(1e3 * fixed / a.steps, 3)
+        out["frame_switch_overhead"] = round(total / fixed - 1.0, 4)
+    else:
+        out["energy_drift"] = float(np.max(np.abs(g["energy"] - g["energy"][0])))
     return out
 
 

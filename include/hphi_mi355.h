@@ -229,19 +229,64 @@ int hphi_ham_hubbard_ext(hphi_basis *b, const hphi_hop *hops, int n_hops,
                          const double *u_site, const hphi_pair_term *pairs, int n_pairs,
                          hphi_ham **out);
 
+/* Time-dependent amplitudes of a Hubbard Hamiltonian (Sec. 3.4: H(t) with
+ * one-body t_ij(t) and two-body terms I(t), here the U, V, Hund, exchange
+ * and pair-hopping coefficients of the terms given at build). Frame k holds
+ * every amplitude at one time; the terms themselves (sites, kinds) are fixed.
+ * Host arrays, row-major, read during the build only:
+ *   hop_t   [n_frames][n_hops]  t of each hop, in the order of hops
+ *   u_site  [n_frames][n_sites] U_i
+ *   pair_v  [n_frames][n_pairs][4] v, j_hund, j_ex, j_pair of each pair term
+ * A NULL array keeps the build arguments' values in every frame. */
+typedef struct {
+    int n_frames;          /* 1 .. 65536                                     */
+    const double *hop_t;
+    const double *u_site;
+    const double *pair_v;
+} hphi_hub_frames;
+
+/* hphi_ham_hubbard_ext with time-dependent amplitudes: frame 0 is in force
+ * after the build (hops[k].t, u_site and the pairs' values are overridden
+ * where the frames give them). Equal frames share device tables (frames are
+ * deduplicated per kind); each distinct set of pair values holds
+ * (dim_up + dim_dn) doubles of same-species diagonal on the device. Hops
+ * keep the uniform-|t| kernels when t_k(frame) = s_k tau(frame) with one
+ * sign s_k per hop in every frame; U keeps the uniform kernels when every
+ * frame's U_i are equal. hphi_time_evolve steps through the frames;
+ * hphi_ham_set_frame selects one for every other call.
+ * Errors: INVALID_ARG (null frames, n_frames outside [1, 65536], no array
+ * given, hop_t without hops, pair_v without pair terms, a non-finite value,
+ * more than 127 distinct hop trajectories, and hphi_ham_hubbard_ext's
+ * conditions), OUT_OF_MEMORY, DEVICE. */
+int hphi_ham_hubbard_td(hphi_basis *b, const hphi_hop *hops, int n_hops,
+                        const double *u_site, const hphi_pair_term *pairs, int n_pairs,
+                        const hphi_hub_frames *frames, hphi_ham **out);
+
+/* Puts frame `frame` of a Hamiltonian built by hphi_ham_hubbard_td in
+ * force for the calls that follow on `stream`: device-to-device copies of
+ * the frame's tables, ordered on the stream after earlier work (the
+ * one-stream rule of hphi_ham applies). Asynchronous.
+ * Errors: INVALID_ARG (no frames, frame outside [0, n_frames)), BUSY, DEVICE. */
+int hphi_ham_set_frame(hphi_ham *h, int frame, void *stream);
+
+/* Number of frames (0: fixed amplitudes) and the frame in force. */
+int hphi_ham_frames(const hphi_ham *h, int *n_frames, int *current);
+
 void hphi_ham_free(hphi_ham *h);
 
 /* Launch schedule of the H*v kernels of one Hamiltonian (set by the
  * autotuner; zero fields keep the current value). Results do not depend on
  * the schedule beyond floating-point summation order.
  *   hub_slab_cols   columns per L2-resident slab of the Hubbard T_up kernel
- *                   (8, 16, 32, 64 or 128; 128 only with hub_sweep 3 on
- *                   one real vector, otherwise 64)
+ *                   (8, 16, 32, 64 or 128; 128 only with hub_sweep 3 or 5
+ *                   on one real vector, otherwise 64)
  *   hub_groups      workgroups per XCD of that kernel (1..1024)
  *   hub_item_rows   rows per work item of that kernel (8..128)
- *   hub_row_cols    T_dn kernel variant: 1 = batched table loads, 2 = all
- *                   loads of two columns issued at once, 3 = row metadata
- *                   in LDS, 4 = as 3 with hop-ordered slots (up to 32767
+ *   hub_row_cols    T_dn kernel variant (values below 5 select, at any
+ *                   size, the kernels that sectors beyond 16 sites or
+ *                   32767 down states fall back to): 1 or 2 = sliced-ELL
+ *                   table loads, 3 = row metadata in LDS (up to 16
+ *                   sites; otherwise as 1), 4 = as 3 with hop-ordered slots (up to 32767
  *                   down states; otherwise as 3), 5 = as 4 with each row
  *                   staged by one batch of loads (up to 16384 down states
  *                   per lane group; otherwise as 4; bit-identical to 4),
@@ -256,31 +301,24 @@ void hphi_ham_free(hphi_ham *h);
  *                   when there is one
  *   hub_sweep       Hubbard T_up kernel (uniform |t| tables): 1 = per-XCD
  *                   queues of (slab, hub_item_rows rows) work items;
- *                   2 = row-range sweep: hub_groups row ranges per XCD,
- *                   each walking that XCD's slabs in order; 3 = as 1 with
- *                   two adjacent columns per lane (one real vector with an
- *                   even number of down states; otherwise as 1); 4 = items
- *                   (64-column slab, group of up rows sharing their high
- *                   half) with the group's tile in LDS (one real vector,
- *                   even number of down states, groups of at most 72 rows;
- *                   otherwise as 1); 5 = as 3, one wave per row, each
- *                   row's neighbour lists walked in batches of 12 loads
+ *                   3 = as 1 with two adjacent columns per lane (one real
+ *                   vector with an even number of down states; otherwise
+ *                   as 1); 5 = as 3, one wave per row, each row's
+ *                   neighbour lists walked in batches of 12 loads
  *                   (128-column slabs with two columns per lane or
  *                   64-column slabs; bit-identical to 3 at the same slab
- *                   width); 6 = as 5 with each wave taking its own work
- *                   items and reading the neighbour lists with scalar loads
- *                   (no LDS staging, no block barriers; the products are
- *                   bit-identical to 5, the fused dots sum in another
- *                   order); 7 = block tiles: a work item is (slab of 16
+ *                   width); 7 = block tiles: a work item is (slab of 16
  *                   columns, block of the up rows sharing their top
  *                   hub_tile_bits sites), the block's rows of the slab are
  *                   staged in LDS once, hops that keep those sites read
  *                   LDS and only the others gather from memory (one real
  *                   vector, even number of down states; otherwise as 5;
  *                   the products equal those of 5 up to summation order;
- *                   the default where the tables could be built, else 5)
- *   hub_row_order   order in which the T_up kernels of hub_sweep 1, 3, 5
- *                   and 6 take the up rows: 1 = index order, 2 = reverse
+ *                   the default where the tables could be built, else 5).
+ *                   2, 4 and 6 (slower variants) are no longer built:
+ *                   INVALID_ARG.
+ *   hub_row_order   order in which the T_up kernels of hub_sweep 1, 3 and
+ *                   5 take the up rows: 1 = index order, 2 = reverse
  *                   Cuthill-McKee order of the up-species hop graph (rows
  *                   processed close together share more neighbour rows, so
  *                   more of them are still in L2); the products do not
@@ -537,6 +575,8 @@ typedef struct {
     void *stream;
     int use_graph;         /* capture one step's launches in a hipGraph and
                               replay it (the same numbers as without)        */
+    int first_frame;       /* time-dependent H: frame of t_0 (0 .. n_frames-1;
+                              a later call continues a run's frames)         */
 } hphi_tevol_opts;
 
 /* Real-time evolution by the truncated Taylor series of Sec. 3.4:
@@ -550,8 +590,14 @@ typedef struct {
  * Hubbard models docc_out[k] = sum_i <n_i,up n_i,dn> / (N_s <psi|psi>)
  * (the double occupancy of the paper's quench example). Output arrays are
  * host memory and nullable. Synchronous.
- * Errors: INVALID_ARG (ranges above, docc_out for a spin model),
- * UNSUPPORTED (several vectors with a Hubbard model), OUT_OF_MEMORY, DEVICE. */
+ * Time-dependent H (a Hamiltonian with frames, hphi_ham_hubbard_td): H(t_k)
+ * is frame min(first_frame + k, n_frames - 1); the step from t_k to t_k+1
+ * applies it as a constant over the step, and energy_out[k] is <H(t_k)>.
+ * On return frame min(first_frame + n_steps, n_frames - 1) is in force.
+ * first_frame must be 0 for a Hamiltonian without frames.
+ * Errors: INVALID_ARG (ranges above, docc_out for a spin model,
+ * first_frame outside the frames), UNSUPPORTED (several vectors with a
+ * Hubbard model, use_graph with frames), OUT_OF_MEMORY, DEVICE. */
 int hphi_time_evolve(hphi_ham *h, const hphi_tevol_opts *opts, void *psi_dev,
                      double *norm_out, double *energy_out, double *docc_out);
 

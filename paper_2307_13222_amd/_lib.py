@@ -32,6 +32,11 @@ class PairTerm(C.Structure):
                 ("j_ex", C.c_double), ("j_pair", C.c_double)]
 
 
+class HubFrames(C.Structure):
+    _fields_ = [("n_frames", C.c_int), ("hop_t", C.POINTER(C.c_double)), ("u_site", C.POINTER(C.c_double)),
+                ("pair_v", C.POINTER(C.c_double))]
+
+
 class LanczosOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("check_every", C.c_int), ("tol", C.c_double),
                 ("resid_tol", C.c_double), ("seed", C.c_uint64), ("v0_dev", C.c_void_p), ("storage", C.c_int),
@@ -63,7 +68,7 @@ class CtpqOpts(C.Structure):
 
 class TevolOpts(C.Structure):
     _fields_ = [("n_vec", C.c_int), ("n_max", C.c_int), ("dt", C.c_double), ("n_steps", C.c_int),
-                ("storage", C.c_int), ("stream", C.c_void_p), ("use_graph", C.c_int)]
+                ("storage", C.c_int), ("stream", C.c_void_p), ("use_graph", C.c_int), ("first_frame", C.c_int)]
 
 
 class LobpcgOpts(C.Structure):
@@ -118,6 +123,10 @@ SIGNATURES = {
     "hphi_ham_spin": (I, [P, C.POINTER(SpinBond), I, PD, C.POINTER(P)]),
     "hphi_ham_hubbard": (I, [P, C.POINTER(Hop), I, PD, C.POINTER(P)]),
     "hphi_ham_hubbard_ext": (I, [P, C.POINTER(Hop), I, PD, C.POINTER(PairTerm), I, C.POINTER(P)]),
+    "hphi_ham_hubbard_td": (I, [P, C.POINTER(Hop), I, PD, C.POINTER(PairTerm), I, C.POINTER(HubFrames),
+                                C.POINTER(P)]),
+    "hphi_ham_set_frame": (I, [P, I, P]),
+    "hphi_ham_frames": (I, [P, C.POINTER(I), C.POINTER(I)]),
     "hphi_ham_free": (None, [P]),
     "hphi_ham_set_schedule": (I, [P, C.POINTER(Schedule)]),
     "hphi_ham_get_schedule": (I, [P, C.POINTER(Schedule)]),

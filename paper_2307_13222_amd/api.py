@@ -205,24 +205,48 @@ class Hamiltonian:
         return cls(basis, h, m)
 
     @classmethod
-    def hubbard(cls, basis: Basis, m: HubbardModel) -> "Hamiltonian":
+    def hubbard(cls, basis: Basis, m: HubbardModel, frames=None) -> "Hamiltonian":
+        """frames: optional HubbardFrames (time-dependent amplitudes, frame 0
+        in force after the build)."""
         arr = (L.Hop * max(1, m.n_hops))()
         for k in range(m.n_hops):
             arr[k] = L.Hop(int(m.hi[k]), int(m.hj[k]), float(m.t[k]))
         us = np.ascontiguousarray(m.u_site, dtype=np.float64)
         h = C.c_void_p()
         n_pairs = getattr(m, "n_pairs", 0)
-        if n_pairs:
-            pa = (L.PairTerm * n_pairs)()
-            for k in range(n_pairs):
-                pa[k] = L.PairTerm(int(m.pi[k]), int(m.pj[k]), float(m.pv[k]), float(m.pjh[k]),
-                                   float(m.pjx[k]), float(m.pjp[k]))
+        pa = (L.PairTerm * max(1, n_pairs))()
+        for k in range(n_pairs):
+            pa[k] = L.PairTerm(int(m.pi[k]), int(m.pj[k]), float(m.pv[k]), float(m.pjh[k]),
+                               float(m.pjx[k]), float(m.pjp[k]))
+        if frames is not None:
+            keep = []
+
+            def arr2(x):
+                if x is None:
+                    return None
+                a = np.ascontiguousarray(x, dtype=np.float64)
+                keep.append(a)
+                return a.ctypes.data_as(L.PD)
+            fr = L.HubFrames(int(frames.n_frames), arr2(frames.hop_t), arr2(frames.u_site), arr2(frames.pair_v))
+            _check(L.lib().hphi_ham_hubbard_td(basis.h, arr, m.n_hops, us.ctypes.data_as(L.PD), pa, n_pairs,
+                                               C.byref(fr), C.byref(h)), "hphi_ham_hubbard_td")
+        elif n_pairs:
             _check(L.lib().hphi_ham_hubbard_ext(basis.h, arr, m.n_hops, us.ctypes.data_as(L.PD), pa, n_pairs,
                                                 C.byref(h)), "hphi_ham_hubbard_ext")
         else:
             _check(L.lib().hphi_ham_hubbard(basis.h, arr, m.n_hops, us.ctypes.data_as(L.PD), C.byref(h)),
                    "hphi_ham_hubbard")
         return cls(basis, h, m)
+
+    def set_frame(self, frame: int, stream=None):
+        """Puts frame `frame` of a time-dependent Hamiltonian in force."""
+        _check(L.lib().hphi_ham_set_frame(self.h, int(frame), _stream_ptr(stream)), "hphi_ham_set_frame")
+
+    def frames(self):
+        """(number of frames, frame in force); (0, 0) for fixed amplitudes."""
+        n, cur = C.c_int(), C.c_int()
+        _check(L.lib().hphi_ham_frames(self.h, C.byref(n), C.byref(cur)), "hphi_ham_frames")
+        return n.value, cur.value
 
     def trace(self, stream=None) -> float:
         out = C.c_double()
@@ -379,10 +403,13 @@ def ctpq(ham: Hamiltonian, n_vec: int, n_max: int, dtau: float, k_steps: int,
 
 
 def time_evolve(ham: Hamiltonian, psi, n_steps: int, dt: float = 0.01, n_max: int = 10,
-                double_occupancy: bool = False, use_graph: bool = False, stream=None) -> Dict:
+                double_occupancy: bool = False, use_graph: bool = False, stream=None,
+                first_frame: int = 0) -> Dict:
     """Real-time evolution of psi (device tensor [dim] or [dim, n_vec],
     complex128 or complex64, updated in place) by the truncated Taylor series;
-    returns per recorded time norms, energies and (Hubbard) double occupancy."""
+    returns per recorded time norms, energies and (Hubbard) double occupancy.
+    A Hamiltonian with frames takes frame min(first_frame + k, n_frames - 1)
+    at t_k."""
     _dev_check(psi, "psi")
     torch = _torch()
     if psi.dtype not in (torch.complex128, torch.complex64):
@@ -393,6 +420,7 @@ def time_evolve(ham: Hamiltonian, psi, n_steps: int, dt: float = 0.01, n_max: in
     o.storage = L.C128 if psi.dtype == torch.complex128 else L.C64
     o.stream = _stream_ptr(stream)
     o.use_graph = 1 if use_graph else 0
+    o.first_frame = int(first_frame)
     nrm = np.zeros((n_steps + 1) * nv)
     en = np.zeros((n_steps + 1) * nv)
     dc = np.zeros(n_steps + 1) if double_occupancy else None

@@ -30,7 +30,7 @@ def candidates(ham, quick: bool = False) -> List[Dict[str, int]]:
     """Schedules to time. Hubbard: the block-tile T_up kernel (hub_sweep 7)
     over tile splits (hub_tile_bits: -1 = the fewest top sites whose blocks
     fit LDS, or a few more: smaller blocks, more far hops) and T_dn variants,
-    and the slab kernels (hub_sweep 5, 6; slab width, workgroups per XCD,
+    and the slab kernels (hub_sweep 3, 5; slab width, workgroups per XCD,
     rows per item, row order). Spin: placement of the rank tables (LDS
     32-bit, LDS narrowed, global) x workgroups per CU. Candidates the
     Hamiltonian cannot take are skipped when timed."""
@@ -41,7 +41,7 @@ def candidates(ham, quick: bool = False) -> List[Dict[str, int]]:
             out.append({"hub_sweep": 7, "hub_tile_bits": tb, "hub_row_cols": rc, "hub_groups": g})
         slab = itertools.product((128,) if quick else (64, 128), (128,) if quick else (64, 128, 256),
                                  (16,) if quick else (16, 32), (6,) if quick else (5, 6),
-                                 (5,) if quick else (5, 6), (2,) if quick else (1, 2))
+                                 (5,) if quick else (3, 5), (2,) if quick else (1, 2))
         for cw, g, rows, rc, sw, ro in slab:
             out.append({"hub_slab_cols": cw, "hub_groups": g, "hub_item_rows": rows, "hub_row_cols": rc,
                         "hub_sweep": sw, "hub_row_order": ro})

@@ -3,6 +3,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 
@@ -254,7 +255,7 @@ int hphi_ham_spin(hphi_basis *b, const hphi_spin_bond *bonds, int n_bonds, const
 // s ^ (1<<i | 1<<j), value -t and sign (-1)^(occupied sites strictly
 // between i and j).
 static int build_hub_species(const Species &sp, const std::vector<hphi_hop> &hops,
-                             std::map<double, int> &classes, DevMem &off_d, DevMem &nbr_d, int64_t &max_deg,
+                             const std::vector<int> &hop_cls, DevMem &off_d, DevMem &nbr_d, int64_t &max_deg,
                              DevMem &sell_base_d, DevMem &sell_width_d, DevMem &sell_d)
 {
     std::vector<uint32_t> off((size_t)sp.dim + 1, 0);
@@ -264,7 +265,8 @@ static int build_hub_species(const Species &sp, const std::vector<hphi_hop> &hop
     for (int64_t r = 0; r < sp.dim; ++r) {
         const uint64_t s = sp.state_at(r);
         off[r] = (uint32_t)ent.size();
-        for (const hphi_hop &hp : hops) {
+        for (size_t hk = 0; hk < hops.size(); ++hk) {
+            const hphi_hop &hp = hops[hk];
             const int bi = (int)((s >> hp.i) & 1), bj = (int)((s >> hp.j) & 1);
             if (bi == bj) continue;
             const uint64_t t = s ^ ((uint64_t(1) << hp.i) | (uint64_t(1) << hp.j));
@@ -272,7 +274,7 @@ static int build_hub_species(const Species &sp, const std::vector<hphi_hop> &hop
             const uint64_t between = (hi - lo > 1) ? (((uint64_t(1) << hi) - 1) & ~((uint64_t(1) << (lo + 1)) - 1)) : 0;
             const uint32_t sign = (uint32_t)(__builtin_popcountll(s & between) & 1);
             const int64_t tr = sp.rank_of(t);
-            const int cls = classes.at(-hp.t);
+            const int cls = hop_cls[hk];
             ent.push_back((uint32_t)tr | ((uint32_t)cls << 24) | (sign << 31));
         }
         max_deg = std::max<int64_t>(max_deg, (int64_t)ent.size() - off[r]);
@@ -471,7 +473,7 @@ static int build_hub_tile(hphi_ham *h, int bits)
         }
     }
     std::vector<std::vector<uint32_t>> pl, mi;
-    split_lists(up, h->hops, pl, mi);
+    split_lists(up, h->hops_split, pl, mi);
     const size_t nb = blk.size() - 1;
     std::vector<uint32_t> pos((size_t)up.dim), off((size_t)up.dim + 1, 0), cnt((size_t)up.dim), ent;
     bool ok = true;
@@ -545,7 +547,7 @@ static int build_hub_fast(hphi_ham *h)
     const Species &up = b->sp[0], &dn = b->sp[1];
     std::vector<std::vector<uint32_t>> pl, mi;
     // down species: sliced ELL of uint16 columns, plus part then minus part
-    split_lists(dn, h->hops, pl, mi);
+    split_lists(dn, h->hops_split, pl, mi);
     const int64_t nchunk = (dn.dim + kSellChunk - 1) / kSellChunk;
     std::vector<uint32_t> base(nchunk + 1, 0), wp(nchunk, 0), wm(nchunk, 0);
     for (int64_t j = 0; j < nchunk; ++j) {
@@ -554,7 +556,6 @@ static int build_hub_fast(hphi_ham *h)
             wm[j] = std::max<uint32_t>(wm[j], (uint32_t)mi[c].size());
         }
         base[j + 1] = base[j] + (wp[j] + wm[j]) * kSellChunk;
-        h->hub.fs_maxw = std::max(h->hub.fs_maxw, wp[j] + wm[j]);
     }
     std::vector<uint16_t> ent(std::max<uint32_t>(1, base[nchunk]), (uint16_t)dn.dim);
     for (int64_t j = 0; j < nchunk; ++j)
@@ -591,7 +592,7 @@ static int build_hub_fast(hphi_ham *h)
         for (int64_t j = 0; j < nchunk; ++j) {
             const int64_t c0 = j * kSellChunk, c1 = std::min(dn.dim, c0 + kSellChunk);
             slots.clear();
-            for (const hphi_hop &hp : h->hops) {
+            for (const hphi_hop &hp : h->hops_split) {
                 bool any = false;
                 std::vector<uint32_t> col(kSellChunk, (uint32_t)dn.dim);
                 for (int64_t c = c0; c < c1; ++c) {
@@ -643,7 +644,7 @@ static int build_hub_fast(hphi_ham *h)
     }
     // up species: CSR, plus entries then minus entries, targets as row
     // element offsets r' * dim_dn
-    split_lists(up, h->hops, pl, mi);
+    split_lists(up, h->hops_split, pl, mi);
     std::vector<uint32_t> off(up.dim + 1, 0), mid(up.dim, 0), tgt;
     for (int64_t r = 0; r < up.dim; ++r) {
         off[r] = (uint32_t)tgt.size();
@@ -679,73 +680,33 @@ static int build_hub_fast(hphi_ham *h)
         HPHI_TRY(upload(h->hub.rr_ent, rent.data(), sizeof(uint32_t) * rent.size()));
         HPHI_TRY(upload(h->hub.rr_row, ord.data(), sizeof(uint32_t) * ord.size()));
     }
-    // padding: the wave-owned column kernel reads each row's entries in
-    // blocks of 16 that may run past the last list (row 0 targets, unused)
+    // padding: 16 entries past the last list (row 0 targets, never used)
     tgt.resize(tgt.size() + 16, 0u);
     HPHI_TRY(upload(h->hub.fu_off, off.data(), sizeof(uint32_t) * off.size()));
     HPHI_TRY(upload(h->hub.fu_mid, mid.data(), sizeof(uint32_t) * mid.size()));
     HPHI_TRY(upload(h->hub.fu_ent, tgt.data(), sizeof(uint32_t) * tgt.size()));
-    // up species by high-half groups: in-group hops (both sites in the low
-    // half) point at a row of the same group, which a group tile in LDS holds
-    {
-        std::vector<uint32_t> grows, goff(up.dim + 1, 0), gcnt(up.dim, 0), gent;
-        const uint64_t nh = uint64_t(1) << up.n_hi;
-        for (uint64_t hh = 0; hh < nh; ++hh)
-            if (up.hi_off[hh + 1] > up.hi_off[hh]) grows.push_back((uint32_t)up.hi_off[hh]);
-        grows.push_back((uint32_t)up.dim);
-        bool ok = true;
-        int max_rows = 0;
-        uint32_t max_ent = 0;
-        for (size_t g = 0; g + 1 < grows.size(); ++g) {
-            const uint32_t g0 = grows[g], g1 = grows[g + 1];
-            max_rows = std::max(max_rows, (int)(g1 - g0));
-            const uint32_t e0 = (uint32_t)gent.size();
-            for (uint32_t r = g0; r < g1; ++r) {
-                goff[r] = (uint32_t)gent.size();
-                uint32_t n[4] = {0, 0, 0, 0};
-                for (int part = 0; part < 4; ++part) {
-                    const std::vector<uint32_t> &lst = (part & 1) ? mi[r] : pl[r];
-                    const bool local = part < 2;
-                    for (uint32_t x : lst) {
-                        const bool in = x >= g0 && x < g1;
-                        if (in != local) continue;
-                        gent.push_back(local ? x - g0 : (uint32_t)((uint64_t)x * (uint64_t)dn.dim));
-                        ++n[part];
-                    }
-                }
-                if (n[0] > 255 || n[1] > 255 || n[2] > 255 || n[3] > 255) ok = false;
-                gcnt[r] = n[0] | (n[1] << 8) | (n[2] << 16) | (n[3] << 24);
-            }
-            max_ent = std::max(max_ent, (uint32_t)gent.size() - e0);
-        }
-        goff[up.dim] = (uint32_t)gent.size();
-        if (gent.empty()) gent.push_back(0);
-        if (ok) {
-            HPHI_TRY(upload(h->hub.fg_rows, grows.data(), sizeof(uint32_t) * grows.size()));
-            HPHI_TRY(upload(h->hub.fg_off, goff.data(), sizeof(uint32_t) * goff.size()));
-            HPHI_TRY(upload(h->hub.fg_cnt, gcnt.data(), sizeof(uint32_t) * gcnt.size()));
-            HPHI_TRY(upload(h->hub.fg_ent, gent.data(), sizeof(uint32_t) * gent.size()));
-            h->hub.fg_ngroups = (int)grows.size() - 1;
-            h->hub.fg_max_rows = max_rows;
-            h->hub.fg_max_ent = max_ent;
-            h->hub.fg_ok = true;
-        }
-    }
     return HPHI_OK;
 }
 
-// Two-body tables: per-pair records and the same-species diagonal
-// (V - JH) n_i n_j of each up row and each down state.
-static int build_hub_pairs(hphi_ham *h, const hphi_pair_term *pairs, int n_pairs)
+// Two-body tables of one set of values: per-pair records, per-site lists of
+// the pairs' other ends with V (the cross weights), and the same-species
+// diagonal (V - JH) n_i n_j of each up row and each down state.
+struct PairHost {
+    std::vector<HubPairDev> rec;
+    std::vector<uint32_t> soff;
+    std::vector<PairNbrDev> snbr;
+    std::vector<double> e[2];
+};
+
+static int pair_host_tables(const hphi_basis *b, const hphi_pair_term *pairs, int n_pairs, PairHost &o)
 {
-    hphi_basis *b = h->basis;
-    std::vector<HubPairDev> dev(n_pairs);
+    o.rec.assign(n_pairs, HubPairDev{});
     for (int k = 0; k < n_pairs; ++k) {
         const int i = pairs[k].i, j = pairs[k].j;
         if (i < 0 || j < 0 || i >= b->n_sites || j >= b->n_sites || i == j)
             return fail(HPHI_ERR_INVALID_ARG, "pair term %d (%d, %d) invalid for %d sites", k, i, j, b->n_sites);
         const int lo = std::min(i, j), hi = std::max(i, j);
-        HubPairDev &q = dev[k];
+        HubPairDev &q = o.rec[k];
         q.mask = (1u << i) | (1u << j);
         q.between = (hi - lo > 1) ? (((1u << hi) - 1u) & ~((2u << lo) - 1u)) : 0u;
         q.i = i;
@@ -754,45 +715,80 @@ static int build_hub_pairs(hphi_ham *h, const hphi_pair_term *pairs, int n_pairs
         q.jh = pairs[k].j_hund;
         q.jx = pairs[k].j_ex;
         q.jp = pairs[k].j_pair;
-        h->pair_terms.push_back(pairs[k]);
     }
-    h->hub.n_pairs = n_pairs;
     if (n_pairs == 0) return HPHI_OK;
     if (b->n_sites > 32 || !b->sp[0].d_hi_off32.p || !b->sp[1].d_hi_off32.p)
         return fail(HPHI_ERR_UNSUPPORTED, "two-body terms need at most 32 sites");
-    HPHI_TRY(upload(h->hub.pairs, dev.data(), sizeof(HubPairDev) * dev.size()));
-    // per-site lists (pair order) for the cross weights
-    std::vector<uint32_t> soff(b->n_sites + 1, 0);
-    for (const HubPairDev &q : dev) {
-        ++soff[q.i + 1];
-        ++soff[q.j + 1];
+    o.soff.assign(b->n_sites + 1, 0);
+    for (const HubPairDev &q : o.rec) {
+        ++o.soff[q.i + 1];
+        ++o.soff[q.j + 1];
     }
-    for (int k = 0; k < b->n_sites; ++k) soff[k + 1] += soff[k];
-    std::vector<PairNbrDev> snbr(soff[b->n_sites]);
-    std::vector<uint32_t> fill(soff.begin(), soff.end() - 1);
-    for (const HubPairDev &q : dev) {
-        snbr[fill[q.i]++] = PairNbrDev{q.j, 0, q.v};
-        snbr[fill[q.j]++] = PairNbrDev{q.i, 0, q.v};
+    for (int k = 0; k < b->n_sites; ++k) o.soff[k + 1] += o.soff[k];
+    o.snbr.assign(o.soff[b->n_sites], PairNbrDev{});
+    std::vector<uint32_t> fill(o.soff.begin(), o.soff.end() - 1);
+    for (const HubPairDev &q : o.rec) {
+        o.snbr[fill[q.i]++] = PairNbrDev{q.j, 0, q.v};
+        o.snbr[fill[q.j]++] = PairNbrDev{q.i, 0, q.v};
     }
-    HPHI_TRY(upload(h->hub.pair_site_off, soff.data(), sizeof(uint32_t) * soff.size()));
-    HPHI_TRY(upload(h->hub.pair_site_nbr, snbr.data(), sizeof(PairNbrDev) * snbr.size()));
     for (int sgm = 0; sgm < 2; ++sgm) {
         const Species &sp = b->sp[sgm];
-        std::vector<double> e((size_t)sp.dim, 0.0);
+        std::vector<double> &e = o.e[sgm];
+        e.assign((size_t)sp.dim, 0.0);
         for (int64_t r = 0; r < sp.dim; ++r) {
             const uint64_t x = sp.state_at(r);
             double s = 0.0;
-            for (const HubPairDev &q : dev)
+            for (const HubPairDev &q : o.rec)
                 if (((x >> q.i) & 1u) && ((x >> q.j) & 1u)) s += q.v - q.jh;
             e[(size_t)r] = s;
         }
-        HPHI_TRY(upload(sgm == 0 ? h->hub.pair_eup : h->hub.pair_edn, e.data(), sizeof(double) * e.size()));
     }
     return HPHI_OK;
 }
 
+static int build_hub_pairs(hphi_ham *h, const hphi_pair_term *pairs, int n_pairs)
+{
+    PairHost o;
+    HPHI_TRY(pair_host_tables(h->basis, pairs, n_pairs, o));
+    h->pair_terms.assign(pairs, pairs + n_pairs);
+    h->hub.n_pairs = n_pairs;
+    if (n_pairs == 0) return HPHI_OK;
+    HPHI_TRY(upload(h->hub.pairs, o.rec.data(), sizeof(HubPairDev) * o.rec.size()));
+    HPHI_TRY(upload(h->hub.pair_site_off, o.soff.data(), sizeof(uint32_t) * o.soff.size()));
+    HPHI_TRY(upload(h->hub.pair_site_nbr, o.snbr.data(), sizeof(PairNbrDev) * o.snbr.size()));
+    HPHI_TRY(upload(h->hub.pair_eup, o.e[0].data(), sizeof(double) * o.e[0].size()));
+    HPHI_TRY(upload(h->hub.pair_edn, o.e[1].data(), sizeof(double) * o.e[1].size()));
+    return HPHI_OK;
+}
+
+// Groups the frames of one kind into slots of equal values: slot_of[f],
+// and the values of each slot (first frame with them) appended to vals.
+static int frame_slots(int F, size_t width, const std::function<double(int, size_t)> &at, std::vector<int> &slot_of,
+                       std::vector<double> &vals)
+{
+    std::map<std::vector<double>, int> seen;
+    slot_of.assign(F, 0);
+    vals.clear();
+    std::vector<double> row(width);
+    for (int f = 0; f < F; ++f) {
+        for (size_t c = 0; c < width; ++c) {
+            row[c] = at(f, c);
+            if (!std::isfinite(row[c])) return fail(HPHI_ERR_INVALID_ARG, "frame %d: value %zu is not finite", f, c);
+        }
+        auto it = seen.find(row);
+        if (it == seen.end()) {
+            it = seen.emplace(row, (int)seen.size()).first;
+            vals.insert(vals.end(), row.begin(), row.end());
+        }
+        slot_of[f] = it->second;
+    }
+    return HPHI_OK;
+}
+
+// Builds a Hubbard Hamiltonian; with frames, the amplitudes of frame 0 are
+// in force and the other frames' tables are kept on the device.
 static int make_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops, const double *u_site,
-                        const hphi_pair_term *pairs, int n_pairs, hphi_ham **out)
+                        const hphi_pair_term *pairs, int n_pairs, const hphi_hub_frames *fr, hphi_ham **out)
 {
     if (!b || !out || (n_hops > 0 && !hops) || !u_site || (n_pairs > 0 && !pairs))
         return fail(HPHI_ERR_INVALID_ARG, "null argument");
@@ -800,49 +796,166 @@ static int make_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops, const d
     if (n_hops < 0 || n_hops > 4096) return fail(HPHI_ERR_INVALID_ARG, "n_hops %d outside [0, 4096]", n_hops);
     if (n_pairs < 0 || n_pairs > kMaxPairTerms)
         return fail(HPHI_ERR_INVALID_ARG, "n_pairs %d outside [0, %d]", n_pairs, kMaxPairTerms);
+    if (fr) {
+        if (fr->n_frames < 1 || fr->n_frames > kMaxFrames)
+            return fail(HPHI_ERR_INVALID_ARG, "n_frames %d outside [1, %d]", fr->n_frames, kMaxFrames);
+        if (!fr->hop_t && !fr->u_site && !fr->pair_v)
+            return fail(HPHI_ERR_INVALID_ARG, "frames without hop_t, u_site or pair_v");
+        if (fr->hop_t && n_hops == 0) return fail(HPHI_ERR_INVALID_ARG, "hop_t frames without hops");
+        if (fr->pair_v && n_pairs == 0) return fail(HPHI_ERR_INVALID_ARG, "pair_v frames without pair terms");
+    }
+    const int F = fr ? fr->n_frames : 1;
+    const int ns = b->n_sites;
     DeviceGuard g(b->ctx->device);
     std::unique_ptr<hphi_ham> h(new hphi_ham);
     h->basis = b;
     h->kind = 1;
-    std::map<double, int> classes;
     for (int k = 0; k < n_hops; ++k) {
         const int i = hops[k].i, j = hops[k].j;
-        if (i < 0 || j < 0 || i >= b->n_sites || j >= b->n_sites || i == j)
-            return fail(HPHI_ERR_INVALID_ARG, "hop %d (%d, %d) invalid for %d sites", k, i, j, b->n_sites);
-        h->hops.push_back(hops[k]);
-        if (!classes.count(-hops[k].t)) {
+        if (i < 0 || j < 0 || i >= ns || j >= ns || i == j)
+            return fail(HPHI_ERR_INVALID_ARG, "hop %d (%d, %d) invalid for %d sites", k, i, j, ns);
+    }
+    // amplitudes by frame, grouped into slots per kind
+    std::vector<int> hop_slot, u_slot, pair_slot;
+    std::vector<double> hop_v, u_v, pair_v;
+    HPHI_TRY(frame_slots(F, (size_t)n_hops,
+                         [&](int f, size_t k) { return fr && fr->hop_t ? fr->hop_t[(size_t)f * n_hops + k] : hops[k].t; },
+                         hop_slot, hop_v));
+    HPHI_TRY(frame_slots(F, (size_t)ns,
+                         [&](int f, size_t i) { return fr && fr->u_site ? fr->u_site[(size_t)f * ns + i] : u_site[i]; },
+                         u_slot, u_v));
+    HPHI_TRY(frame_slots(F, (size_t)n_pairs * 4,
+                         [&](int f, size_t c) {
+                             if (fr && fr->pair_v) return fr->pair_v[(size_t)f * n_pairs * 4 + c];
+                             const hphi_pair_term &q = pairs[c / 4];
+                             const double x[4] = {q.v, q.j_hund, q.j_ex, q.j_pair};
+                             return x[c % 4];
+                         },
+                         pair_slot, pair_v));
+    const int nhs = n_hops > 0 ? (int)(hop_v.size() / n_hops) : 1;
+    const int nus = (int)(u_v.size() / ns);
+    const int nps = n_pairs > 0 ? (int)(pair_v.size() / (4 * (size_t)n_pairs)) : 1;
+    auto hop_at = [&](int slot, int k) { return hop_v[(size_t)slot * n_hops + k]; };
+    // value classes: hops with equal amplitudes in every slot share one
+    std::map<std::vector<double>, int> classes;
+    std::vector<int> hop_cls(n_hops), cls_rep;
+    for (int k = 0; k < n_hops; ++k) {
+        std::vector<double> key(nhs);
+        for (int s = 0; s < nhs; ++s) key[s] = -hop_at(s, k);
+        auto it = classes.find(key);
+        if (it == classes.end()) {
             const int c = (int)classes.size();
             if (c >= (int)kZeroClass) return fail(HPHI_ERR_INVALID_ARG, "more than 127 distinct transfer values");
-            classes[-hops[k].t] = c;
+            it = classes.emplace(key, c).first;
+            cls_rep.push_back(k);
         }
+        hop_cls[k] = it->second;
     }
-    std::vector<double> coef(128, 0.0);
-    for (auto &kv : classes) coef[kv.second] = kv.first;
+    std::vector<double> coef((size_t)nhs * 128, 0.0);
+    for (int s = 0; s < nhs; ++s)
+        for (size_t c = 0; c < cls_rep.size(); ++c) coef[(size_t)s * 128 + c] = -hop_at(s, cls_rep[c]);
     h->hub.n_coef = (int)classes.size();
-    HPHI_TRY(upload(h->hub.coef, coef.data(), sizeof(double) * 128));
-    h->u_site.assign(u_site, u_site + b->n_sites);
-    HPHI_TRY(upload(h->hub.u_site, u_site, sizeof(double) * b->n_sites));
+    // uniform magnitude: t_k = sg_k tau(slot) in every slot, one sign per hop
+    bool uni = n_hops > 0 && b->sp[1].dim < 65535 &&
+               (unsigned __int128)b->sp[0].dim * (unsigned __int128)b->sp[1].dim * 2 < ((unsigned __int128)1 << 32);
+    std::vector<double> tau(nhs, 0.0);
+    std::vector<double> sg(n_hops, 1.0);
+    int ref = -1;
+    for (int s = 0; uni && s < nhs && ref < 0; ++s)
+        if (hop_at(s, 0) != 0.0) ref = s;
+    if (ref < 0) uni = false;
+    if (uni) {
+        const double s0 = hop_at(ref, 0) < 0.0 ? -1.0 : 1.0;
+        for (int s = 0; s < nhs; ++s) tau[s] = s0 * hop_at(s, 0);
+        for (int k = 0; k < n_hops && uni; ++k) {
+            const double r = hop_at(ref, k);
+            if (r == tau[ref]) sg[k] = 1.0;
+            else if (r == -tau[ref]) sg[k] = -1.0;
+            else uni = false;
+        }
+        for (int s = 0; s < nhs && uni; ++s)
+            for (int k = 0; k < n_hops && uni; ++k)
+                if (hop_at(s, k) != sg[k] * tau[s]) uni = false;
+    }
+    h->hops.assign(hops, hops + n_hops);
+    h->hops_split = h->hops;
+    for (int k = 0; k < n_hops; ++k) {
+        h->hops[k].t = hop_at(hop_slot[0], k);
+        if (uni) h->hops_split[k].t = sg[k] * std::fabs(tau[ref]);
+    }
+    HPHI_TRY(upload(h->hub.coef, coef.data() + (size_t)hop_slot[0] * 128, sizeof(double) * 128));
+    const double *u0v = u_v.data() + (size_t)u_slot[0] * ns;
+    h->u_site.assign(u0v, u0v + ns);
+    HPHI_TRY(upload(h->hub.u_site, u0v, sizeof(double) * ns));
     h->hub.uniform_u = true;
-    h->hub.u0 = u_site[0];
-    for (int i = 1; i < b->n_sites; ++i)
-        if (u_site[i] != u_site[0]) h->hub.uniform_u = false;
+    for (int s = 0; s < nus; ++s)
+        for (int i = 1; i < ns; ++i)
+            if (u_v[(size_t)s * ns + i] != u_v[(size_t)s * ns]) h->hub.uniform_u = false;
+    h->hub.u0 = u0v[0];
     for (int sgm = 0; sgm < 2; ++sgm)
-        HPHI_TRY(build_hub_species(b->sp[sgm], h->hops, classes, h->hub.off[sgm], h->hub.nbr[sgm],
+        HPHI_TRY(build_hub_species(b->sp[sgm], h->hops, hop_cls, h->hub.off[sgm], h->hub.nbr[sgm],
                                    h->hub.max_deg[sgm], h->hub.sell_base[sgm], h->hub.sell_width[sgm],
                                    h->hub.sell[sgm]));
     // uniform-magnitude transfers: the sign-split fast path
-    h->hub.uniform_t = n_hops > 0 && b->sp[1].dim < 65535 &&
-                       (unsigned __int128)b->sp[0].dim * (unsigned __int128)b->sp[1].dim * 2 < ((unsigned __int128)1 << 32);
-    for (int k = 0; k < n_hops && h->hub.uniform_t; ++k)
-        if (std::fabs(hops[k].t) != std::fabs(hops[0].t) || hops[k].t == 0.0) h->hub.uniform_t = false;
-    if (h->hub.uniform_t) {
-        h->hub.t0 = std::fabs(hops[0].t);
+    h->hub.uniform_t = uni;
+    if (uni) {
+        h->hub.t0 = tau[hop_slot[0]];
         HPHI_TRY(build_hub_fast(h.get()));
         HPHI_TRY(build_hub_tile(h.get(), h->sched_cfg.hub_tile_bits));
         // the block-tile T_up kernel where its tables could be built
         if (h->hub.ft_ok) h->sched_cfg.hub_sweep = 7;
     }
-    HPHI_TRY(build_hub_pairs(h.get(), pairs, n_pairs));
+    auto pair_terms_of = [&](int slot) {
+        std::vector<hphi_pair_term> q(pairs, pairs + n_pairs);
+        for (int p = 0; p < n_pairs; ++p) {
+            const double *x = pair_v.data() + ((size_t)slot * n_pairs + p) * 4;
+            q[p].v = x[0];
+            q[p].j_hund = x[1];
+            q[p].j_ex = x[2];
+            q[p].j_pair = x[3];
+        }
+        return q;
+    };
+    {
+        const std::vector<hphi_pair_term> q0 = pair_terms_of(pair_slot[0]);
+        HPHI_TRY(build_hub_pairs(h.get(), q0.data(), n_pairs));
+    }
+    if (fr) {
+        std::unique_ptr<HubFrames> T(new HubFrames);
+        T->n = F;
+        T->hop_slot = hop_slot;
+        T->u_slot = u_slot;
+        T->pair_slot = pair_slot;
+        T->cur_hop = hop_slot[0];
+        T->cur_u = u_slot[0];
+        T->cur_pair = pair_slot[0];
+        T->hop_t = hop_v;
+        T->tau = tau;
+        T->u_site = u_v;
+        T->pair_v = pair_v;
+        HPHI_TRY(upload(T->coef, coef.data(), sizeof(double) * coef.size()));
+        HPHI_TRY(upload(T->u, u_v.data(), sizeof(double) * u_v.size()));
+        if (n_pairs > 0) {
+            std::vector<HubPairDev> rec;
+            std::vector<PairNbrDev> nbr;
+            std::vector<double> eup, edn;
+            for (int s = 0; s < nps; ++s) {
+                const std::vector<hphi_pair_term> q = pair_terms_of(s);
+                PairHost o;
+                HPHI_TRY(pair_host_tables(b, q.data(), n_pairs, o));
+                rec.insert(rec.end(), o.rec.begin(), o.rec.end());
+                nbr.insert(nbr.end(), o.snbr.begin(), o.snbr.end());
+                eup.insert(eup.end(), o.e[0].begin(), o.e[0].end());
+                edn.insert(edn.end(), o.e[1].begin(), o.e[1].end());
+                T->nbr_n = o.snbr.size();
+            }
+            HPHI_TRY(upload(T->pairs, rec.data(), sizeof(HubPairDev) * rec.size()));
+            HPHI_TRY(upload(T->nbr, nbr.data(), sizeof(PairNbrDev) * nbr.size()));
+            HPHI_TRY(upload(T->eup, eup.data(), sizeof(double) * eup.size()));
+            HPHI_TRY(upload(T->edn, edn.data(), sizeof(double) * edn.size()));
+        }
+        h->td = std::move(T);
+    }
     HPHI_TRY(ensure_reduce(h.get()));
     *out = h.release();
     return HPHI_OK;
@@ -850,13 +963,91 @@ static int make_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops, const d
 
 int hphi_ham_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops, const double *u_site, hphi_ham **out)
 {
-    return make_hubbard(b, hops, n_hops, u_site, nullptr, 0, out);
+    return make_hubbard(b, hops, n_hops, u_site, nullptr, 0, nullptr, out);
 }
 
 int hphi_ham_hubbard_ext(hphi_basis *b, const hphi_hop *hops, int n_hops, const double *u_site,
                          const hphi_pair_term *pairs, int n_pairs, hphi_ham **out)
 {
-    return make_hubbard(b, hops, n_hops, u_site, pairs, n_pairs, out);
+    return make_hubbard(b, hops, n_hops, u_site, pairs, n_pairs, nullptr, out);
+}
+
+int hphi_ham_hubbard_td(hphi_basis *b, const hphi_hop *hops, int n_hops, const double *u_site,
+                        const hphi_pair_term *pairs, int n_pairs, const hphi_hub_frames *frames, hphi_ham **out)
+{
+    if (!frames) return fail(HPHI_ERR_INVALID_ARG, "null frames");
+    return make_hubbard(b, hops, n_hops, u_site, pairs, n_pairs, frames, out);
+}
+
+extern "C++" {
+namespace hphi {
+
+// Puts frame k's slots in force: copies over the live tables on stream st
+// (ordered after earlier work on st) and sets the launch-time scalars.
+int ham_apply_frame(hphi_ham *h, int k, hipStream_t st)
+{
+    HubFrames &T = *h->td;
+    const hphi_basis *b = h->basis;
+    const int ns = b->n_sites, nh = (int)h->hops.size(), np = h->hub.n_pairs;
+    const int hs = T.hop_slot[k], us = T.u_slot[k], ps = T.pair_slot[k];
+    if (hs != T.cur_hop) {
+        HPHI_HIP(hipMemcpyAsync(h->hub.coef.p, T.coef.as<double>() + (size_t)hs * 128, sizeof(double) * 128,
+                                hipMemcpyDeviceToDevice, st));
+        if (h->hub.uniform_t) h->hub.t0 = T.tau[hs];
+        for (int q = 0; q < nh; ++q) h->hops[q].t = T.hop_t[(size_t)hs * nh + q];
+        T.cur_hop = hs;
+    }
+    if (us != T.cur_u) {
+        HPHI_HIP(hipMemcpyAsync(h->hub.u_site.p, T.u.as<double>() + (size_t)us * ns, sizeof(double) * ns,
+                                hipMemcpyDeviceToDevice, st));
+        h->u_site.assign(T.u_site.begin() + (size_t)us * ns, T.u_site.begin() + (size_t)(us + 1) * ns);
+        h->hub.u0 = h->u_site[0];
+        T.cur_u = us;
+    }
+    if (np > 0 && ps != T.cur_pair) {
+        const int64_t dup = b->sp[0].dim, ddn = b->sp[1].dim;
+        HPHI_HIP(hipMemcpyAsync(h->hub.pairs.p, T.pairs.as<HubPairDev>() + (size_t)ps * np, sizeof(HubPairDev) * np,
+                                hipMemcpyDeviceToDevice, st));
+        HPHI_HIP(hipMemcpyAsync(h->hub.pair_site_nbr.p, T.nbr.as<PairNbrDev>() + (size_t)ps * T.nbr_n,
+                                sizeof(PairNbrDev) * T.nbr_n, hipMemcpyDeviceToDevice, st));
+        HPHI_HIP(hipMemcpyAsync(h->hub.pair_eup.p, T.eup.as<double>() + (size_t)ps * dup, sizeof(double) * dup,
+                                hipMemcpyDeviceToDevice, st));
+        HPHI_HIP(hipMemcpyAsync(h->hub.pair_edn.p, T.edn.as<double>() + (size_t)ps * ddn, sizeof(double) * ddn,
+                                hipMemcpyDeviceToDevice, st));
+        for (int p = 0; p < np; ++p) {
+            const double *x = T.pair_v.data() + ((size_t)ps * np + p) * 4;
+            h->pair_terms[p].v = x[0];
+            h->pair_terms[p].j_hund = x[1];
+            h->pair_terms[p].j_ex = x[2];
+            h->pair_terms[p].j_pair = x[3];
+        }
+        T.cur_pair = ps;
+    }
+    T.cur = k;
+    return HPHI_OK;
+}
+
+} // namespace hphi
+} // extern "C++"
+
+int hphi_ham_set_frame(hphi_ham *h, int frame, void *stream)
+{
+    if (!h) return fail(HPHI_ERR_INVALID_ARG, "null argument");
+    if (!h->td) return fail(HPHI_ERR_INVALID_ARG, "the Hamiltonian has no frames");
+    if (frame < 0 || frame >= h->td->n)
+        return fail(HPHI_ERR_INVALID_ARG, "frame %d outside [0, %d)", frame, h->td->n);
+    DeviceGuard g(h->basis->ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    HPHI_USE_HAM(h, st);
+    return ham_apply_frame(h, frame, st);
+}
+
+int hphi_ham_frames(const hphi_ham *h, int *n_frames, int *current)
+{
+    if (!h || !n_frames || !current) return fail(HPHI_ERR_INVALID_ARG, "null argument");
+    *n_frames = h->td ? h->td->n : 0;
+    *current = h->td ? h->td->cur : 0;
+    return HPHI_OK;
 }
 
 void hphi_ham_free(hphi_ham *h) { delete h; }
@@ -895,7 +1086,8 @@ int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s)
         n.spin_implicit = s->spin_implicit == 1 ? 1 : 0;
     }
     if (s->hub_sweep) {
-        if (s->hub_sweep < 1 || s->hub_sweep > 7) return fail(HPHI_ERR_INVALID_ARG, "hub_sweep %d", s->hub_sweep);
+        if (s->hub_sweep != 1 && s->hub_sweep != 3 && s->hub_sweep != 5 && s->hub_sweep != 7)
+            return fail(HPHI_ERR_INVALID_ARG, "hub_sweep %d (1, 3, 5 or 7)", s->hub_sweep);
         n.hub_sweep = s->hub_sweep;
     }
     if (s->hub_row_order) {

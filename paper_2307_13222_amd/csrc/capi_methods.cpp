@@ -191,6 +191,10 @@ int hphi_time_evolve(hphi_ham *h, const hphi_tevol_opts *o, void *psi_dev, doubl
     if (h->kind != 0 && o->n_vec != 1)
         return fail(HPHI_ERR_UNSUPPORTED, "Hubbard and SpinGC time evolution run one vector per call");
     if (docc_out && h->kind != 1) return fail(HPHI_ERR_INVALID_ARG, "double occupancy needs a Hubbard model");
+    if (o->first_frame < 0 || o->first_frame >= (h->td ? h->td->n : 1))
+        return fail(HPHI_ERR_INVALID_ARG, "first_frame %d outside the Hamiltonian's frames", o->first_frame);
+    if (h->td && o->use_graph)
+        return fail(HPHI_ERR_UNSUPPORTED, "frames change the products' launch arguments between steps: no graph replay");
     DeviceGuard g(h->basis->ctx->device);
     hipStream_t st = (hipStream_t)o->stream;
     HPHI_USE_HAM(h, st);
@@ -230,7 +234,10 @@ int hphi_time_evolve(hphi_ham *h, const hphi_tevol_opts *o, void *psi_dev, doubl
     HPHI_TRY(counter.alloc(sizeof(int) * 4));
     HPHI_TRY(launch_zero(counter.p, sizeof(int) * 4, st));
     HPHI_TRY(launch_zero(res_d.p, sizeof(double) * 8, st));
-    auto step = [&](bool last_step) -> int {
+    // time t_kk: with frames, H(t_kk) is frame min(first_frame + kk,
+    // n_frames - 1), held over the step to t_kk+1
+    auto step = [&](int kk, bool last_step) -> int {
+        if (h->td) HPHI_TRY(ham_apply_frame(h, (int)std::min<int64_t>((int64_t)o->first_frame + kk, h->td->n - 1), st));
         HPHI_TRY(launch_dots(dt, nl, dim, A, A, reduce_at(h, res_n.as<double>()), 1, st));
         if (docc_out) HPHI_TRY(launch_docc(h, dt, A, reduce_at(h, res_d.as<double>()), st));
         if (last_step) {
@@ -281,12 +288,12 @@ int hphi_time_evolve(hphi_ham *h, const hphi_tevol_opts *o, void *psi_dev, doubl
     };
     int k = 0;
     if (o->use_graph && K >= 2) {
-        HPHI_TRY(step(false));
+        HPHI_TRY(step(k, false));
         ++k;
         hipGraph_t gph = nullptr;
         hipGraphExec_t exec = nullptr;
         HPHI_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        const int rc = step(false);
+        const int rc = step(k, false);
         const hipError_t e = hipStreamEndCapture(st, &gph);
         if (rc != HPHI_OK) {
             if (gph) (void)hipGraphDestroy(gph);
@@ -301,8 +308,8 @@ int hphi_time_evolve(hphi_ham *h, const hphi_tevol_opts *o, void *psi_dev, doubl
         (void)hipGraphExecDestroy(exec);
         if (el != hipSuccess) return fail(HPHI_ERR_DEVICE, "graph launch: %s", hipGetErrorString(el));
     }
-    for (; k < K; ++k) HPHI_TRY(step(false));
-    HPHI_TRY(step(true));
+    for (; k < K; ++k) HPHI_TRY(step(k, false));
+    HPHI_TRY(step(K, true));
     std::vector<double> hs((size_t)row * (K + 1));
     HPHI_HIP(hipMemcpyAsync(hs.data(), stage.p, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, st));
     HPHI_HIP(hipStreamSynchronize(st));

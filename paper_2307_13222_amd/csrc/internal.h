@@ -5,6 +5,7 @@
 
 #include <cstdarg>
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -206,20 +207,9 @@ struct HubTables {
     // index dim_dn (a zero slot). Up species: CSR with the sign split point.
     bool uniform_t = false;
     double t0 = 0.0;
-    uint32_t fs_maxw = 0;                    // widest down chunk (plus + minus)
     DevMem fs_base, fs_wp, fs_wm, fs_ent;    // down: chunk base, widths, uint16 entries
     DevMem fu_off, fu_mid, fu_ent;           // up: row offsets, split points, targets
     DevMem rr_off, rr_mid, rr_ent, rr_row;   // the same in reverse Cuthill-McKee row order; rr_row[p] = row
-    // up species by groups of rows sharing the high half (rows
-    // fg_rows[g] .. fg_rows[g + 1]): per row four consecutive lists,
-    // in-group plus / in-group minus (local row) and far plus / far minus
-    // (target row * dim_dn); fg_off[r] is the row's first entry, fg_cnt[r]
-    // packs the four lengths (8 bits each)
-    bool fg_ok = false;
-    int fg_ngroups = 0;
-    int fg_max_rows = 0;
-    uint32_t fg_max_ent = 0;                 // most entries of one group
-    DevMem fg_rows, fg_off, fg_cnt, fg_ent;
     // down species, hop-ordered slots (dim_dn < 32768): per chunk of 64
     // states one slot per hop active in any of them, in hop order, two slots
     // per uint32 (15-bit columns, signs in bits 31 and 30); inactive lanes
@@ -256,6 +246,25 @@ struct HubTables {
     int64_t max_deg[2] = {0, 0};
 };
 
+// Time-dependent amplitudes of one Hubbard Hamiltonian: frames k = 0..n-1
+// of the same terms, deduplicated per kind into slots (frames with equal
+// values share one). The live tables of HubTables hold the slots in force;
+// a frame switch copies a slot's tables over them on the caller's stream.
+constexpr int kMaxFrames = 65536;
+struct HubFrames {
+    int n = 0, cur = 0;
+    std::vector<int> hop_slot, u_slot, pair_slot;   // [n]
+    int cur_hop = 0, cur_u = 0, cur_pair = 0;
+    std::vector<double> hop_t;     // [hop slots][n_hops]
+    std::vector<double> tau;       // [hop slots] t0 of the uniform-|t| path
+    std::vector<double> u_site;    // [u slots][n_sites]
+    std::vector<double> pair_v;    // [pair slots][n_pairs][4]: v, j_hund, j_ex, j_pair
+    DevMem coef;                   // double [hop slots][128]
+    DevMem u;                      // double [u slots][n_sites]
+    DevMem pairs, nbr, eup, edn;   // per pair slot: records, site lists, same-species diagonals
+    size_t nbr_n = 0;              // site-list entries per slot
+};
+
 } // namespace hphi
 
 struct hphi_ham {
@@ -269,7 +278,9 @@ struct hphi_ham {
     bool has_field = false;
     // Hubbard
     hphi::HubTables hub;
-    std::vector<hphi_hop> hops;
+    std::vector<hphi_hop> hops;          // the terms, amplitudes of the frame in force
+    std::vector<hphi_hop> hops_split;    // sign representatives of the uniform-|t| tables
+    std::unique_ptr<hphi::HubFrames> td; // time-dependent amplitudes (null: fixed)
     std::vector<double> u_site;
     std::vector<hphi_pair_term> pair_terms;
     // SpinGC: XYZ bonds and fields, diagonal records, window plans per
@@ -333,6 +344,8 @@ struct HamUse {
 int init_ham_use(hphi_ham *h);
 // reduction and queue scratch of a Hamiltonian (allocated once)
 int ham_ensure_reduce(hphi_ham *h);
+// time-dependent amplitudes: puts frame k in force on stream st
+int ham_apply_frame(hphi_ham *h, int k, hipStream_t st);
 
 } // namespace hphi
 

@@ -57,8 +57,6 @@ struct HubKArgs {
     const uint32_t *fb_base, *fb_w;
     const uint32_t *fb_ent;
     const uint32_t *fc_ent;   // pre-scaled slot words for this element size (or null)
-    const uint32_t *fg_rows, *fg_off, *fg_cnt, *fg_ent;
-    int fg_ngroups;
     double t0;
     int coef_cplx;
     int hb;                // column kernel: batched list walk, one wave per row
@@ -952,69 +950,6 @@ __global__ __launch_bounds__(1024) void k_hub_rows_fl(HubKArgs a)
     }
 }
 
-// Deep variant: each lane issues every table load of CPT columns (up to 32
-// entries each) before the first gather, then splits the sums at the sign
-// boundary. Used when the widest chunk has at most 32 entries.
-template <typename S, int NV, int CPT>
-__global__ __launch_bounds__(1024) void k_hub_rows_fd(HubKArgs a)
-{
-    extern __shared__ unsigned char smem_raw[];
-    S *s_row = reinterpret_cast<S *>(smem_raw);
-    const S *__restrict__ v = static_cast<const S *>(a.v);
-    S *__restrict__ w = static_cast<S *>(a.w);
-    const int64_t ddn = a.ddn;
-    const S nt0 = (S)(-a.t0);
-    const uint16_t pad = (uint16_t)ddn;
-    for (int64_t ru = blockIdx.x; ru < a.dup; ru += gridDim.x) {
-        const S *vrow = v + (size_t)ru * ddn * NV;
-        __syncthreads();
-        for (int64_t i = threadIdx.x; i < ddn * NV; i += blockDim.x) s_row[i] = vrow[i];
-        if (threadIdx.x < NV) s_row[ddn * NV + threadIdx.x] = (S)0;
-        __syncthreads();
-        const uint32_t uu = a.ups[ru];
-        for (int64_t c0 = threadIdx.x; c0 < ddn; c0 += (int64_t)CPT * blockDim.x) {
-            uint32_t e[CPT][32];
-            uint32_t wp[CPT];
-            int64_t cc[CPT];
-#pragma unroll
-            for (int q = 0; q < CPT; ++q) {
-                cc[q] = c0 + (int64_t)q * blockDim.x;
-                const bool ok = cc[q] < ddn;
-                const int64_t c = ok ? cc[q] : c0;
-                const int64_t ch = c >> 6;
-                const uint16_t *ent = a.fs_ent + a.fs_base[ch] + (c & 63);
-                wp[q] = ok ? a.fs_wp[ch] : 0u;
-                const uint32_t wt = ok ? wp[q] + a.fs_wm[ch] : 0u;
-#pragma unroll
-                for (int t = 0; t < 32; ++t) e[q][t] = (uint32_t)t < wt ? ent[t * 64] : pad;
-            }
-#pragma unroll
-            for (int q = 0; q < CPT; ++q) {
-                if (cc[q] >= ddn) continue;
-                S ap[NV], am[NV];
-#pragma unroll
-                for (int j = 0; j < NV; ++j) ap[j] = am[j] = (S)0;
-#pragma unroll
-                for (int t = 0; t < 32; ++t) {
-                    const bool plus = (uint32_t)t < wp[q];
-#pragma unroll
-                    for (int j = 0; j < NV; ++j) {
-                        const S x = s_row[e[q][t] * NV + j];
-                        ap[j] += plus ? x : (S)0;
-                        am[j] += plus ? (S)0 : x;
-                    }
-                }
-                const int64_t c = cc[q];
-                const S dg = hub_diag<S>(a, uu, a.dns[c]);
-#pragma unroll
-                for (int j = 0; j < NV; ++j)
-                    __builtin_nontemporal_store(dg * s_row[c * NV + j] + nt0 * (ap[j] - am[j]),
-                                                &w[((size_t)ru * ddn + c) * NV + j]);
-            }
-        }
-    }
-}
-
 // Columns kernel of the fast path: the same XCD-queued slab sweep as
 // k_hub_cols; staged entries are byte offsets of the neighbour rows. Each
 // lane owns CPL adjacent columns (CPL = 2 with one real FP64 vector: one
@@ -1607,395 +1542,6 @@ __global__ __launch_bounds__(1024) void k_hub_up_tile(HubKArgs a)
     }
 }
 
-// Columns kernel, group tiles (one real vector, two columns per lane). A work
-// item is (slab of 64 columns, group of up rows sharing their high half, at
-// most kGTileRows rows). The group's tile V[group rows][slab] is staged in
-// LDS: hops with both sites in the low half stay inside the group and read
-// the tile, the others gather neighbour rows from global memory as in
-// k_hub_cols_f. Items come from the per-XCD queues in slab order; the
-// epilogue and the per-item FP64 dot partials are those of k_hub_cols_f.
-// Sum order per state: in-group hops, then the others (plus, then minus).
-constexpr int kGTileRows = 72;
-constexpr int kGEnt = 2560;
-
-template <typename S, bool DOTS>
-__global__ __launch_bounds__(256) void k_hub_cols_g(HubKArgs a)
-{
-    constexpr int CW = 64;
-    __shared__ S s_tile[kGTileRows * CW];
-    __shared__ uint32_t s_ent[kGEnt];
-    __shared__ uint32_t s_off[kGTileRows + 1];
-    __shared__ uint32_t s_cnt[kGTileRows];
-    __shared__ double sh_red[4 * 2 + 8];
-    __shared__ int s_item;
-    __shared__ unsigned s_last;
-    const int home = xcc_id();
-    const char *__restrict__ vb = static_cast<const char *>(a.v);
-    const S *__restrict__ v = static_cast<const S *>(a.v);
-    S *__restrict__ w = static_cast<S *>(a.w);
-    const S *__restrict__ u = static_cast<const S *>(a.u);
-    S *__restrict__ accp = static_cast<S *>(a.acc_out);
-    double c1 = 1.0, c2 = 0.0;
-    if (a.ecoef) {
-        c1 = a.ecoef[0];
-        c2 = a.ecoef[1];
-    }
-    const S c1s = (S)c1, c2s = (S)c2, nt0 = (S)(-a.t0);
-    const int64_t ddn = a.ddn;
-    const int ng = a.fg_ngroups;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int lc = 2 * (lane & 31);   // this lane's first column within the slab
-    int q = home, tries = 0;
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int it = -1;
-            while (tries < 8) {
-                const int nsl_q = q < a.nslab ? (a.nslab - q + 7) / 8 : 0;
-                const int cand = (int)atomicAdd(&a.sched[q], 1u);
-                if (cand < nsl_q * ng) {
-                    it = q + 8 * cand;
-                    break;
-                }
-                q = (q + 1) & 7;
-                ++tries;
-            }
-            s_item = it;
-        }
-        __syncthreads();
-        const int item = s_item;
-        if (item < 0) break;
-        const int iq = item & 7, idx = item >> 3;
-        const int slab = iq + 8 * (idx / ng);
-        const int grp = idx % ng;
-        const uint32_t g0 = a.fg_rows[grp], g1 = a.fg_rows[grp + 1];
-        const int n = (int)(g1 - g0);
-        const int64_t col0 = (int64_t)slab * CW;
-        for (int i = threadIdx.x; i < n * (CW / 2); i += blockDim.x) {
-            const int row = i >> 5, c = 2 * (i & 31);
-            S x0 = (S)0, x1 = (S)0;
-            if (col0 + c < ddn) {
-                const S *p = v + (size_t)(g0 + row) * ddn + col0 + c;
-                x0 = p[0];
-                x1 = p[1];
-            }
-            s_tile[row * CW + c] = x0;
-            s_tile[row * CW + c + 1] = x1;
-        }
-        {
-            const uint32_t base = a.fg_off[g0];
-            for (int i = threadIdx.x; i <= n; i += blockDim.x) s_off[i] = a.fg_off[g0 + i] - base;
-            for (int i = threadIdx.x; i < n; i += blockDim.x) s_cnt[i] = a.fg_cnt[g0 + i];
-            const uint32_t ne = a.fg_off[g1] - base;
-            for (uint32_t i = threadIdx.x; i < ne; i += blockDim.x) s_ent[i] = a.fg_ent[base + i];
-        }
-        __syncthreads();
-        double d0 = 0.0, d1 = 0.0;
-        const int64_t col = col0 + lc;
-        const uint32_t colb = (uint32_t)col * (uint32_t)sizeof(S);
-        for (int r = wid * 2 + (lane >> 5); r < n; r += 8) {
-            if (col >= ddn) continue;
-            const uint32_t cnt = s_cnt[r];
-            const uint32_t n0 = cnt & 255u, n1 = (cnt >> 8) & 255u, n2 = (cnt >> 16) & 255u, n3 = cnt >> 24;
-            uint32_t e = s_off[r];
-            S ap0 = (S)0, ap1 = (S)0, am0 = (S)0, am1 = (S)0;
-            for (uint32_t k = 0; k < n0; ++k) {
-                const S *t = s_tile + s_ent[e + k] * CW + lc;
-                ap0 += t[0];
-                ap1 += t[1];
-            }
-            e += n0;
-            for (uint32_t k = 0; k < n1; ++k) {
-                const S *t = s_tile + s_ent[e + k] * CW + lc;
-                am0 += t[0];
-                am1 += t[1];
-            }
-            e += n1;
-            uint32_t k = 0;
-            for (; k + 8 <= n2; k += 8) {
-                S x[8][2];
-#pragma unroll
-                for (int t = 0; t < 8; ++t)
-                    load_k<S, 2>(reinterpret_cast<const S *>(vb + ((size_t)s_ent[e + k + t] * sizeof(S) + colb)), x[t]);
-#pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    ap0 += x[t][0];
-                    ap1 += x[t][1];
-                }
-            }
-            for (; k < n2; ++k) {
-                S x[2];
-                load_k<S, 2>(reinterpret_cast<const S *>(vb + ((size_t)s_ent[e + k] * sizeof(S) + colb)), x);
-                ap0 += x[0];
-                ap1 += x[1];
-            }
-            e += n2;
-            k = 0;
-            for (; k + 8 <= n3; k += 8) {
-                S x[8][2];
-#pragma unroll
-                for (int t = 0; t < 8; ++t)
-                    load_k<S, 2>(reinterpret_cast<const S *>(vb + ((size_t)s_ent[e + k + t] * sizeof(S) + colb)), x[t]);
-#pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    am0 += x[t][0];
-                    am1 += x[t][1];
-                }
-            }
-            for (; k < n3; ++k) {
-                S x[2];
-                load_k<S, 2>(reinterpret_cast<const S *>(vb + ((size_t)s_ent[e + k] * sizeof(S) + colb)), x);
-                am0 += x[0];
-                am1 += x[1];
-            }
-            const size_t me = (size_t)(g0 + r) * ddn + col;
-            const S raw[2] = {__builtin_nontemporal_load(&w[me]) + nt0 * (ap0 - am0),
-                              __builtin_nontemporal_load(&w[me + 1]) + nt0 * (ap1 - am1)};
-            S out[2] = {c1s * raw[0], c1s * raw[1]};
-            if (u) {
-                out[0] += c2s * __builtin_nontemporal_load(&u[me]);
-                out[1] += c2s * __builtin_nontemporal_load(&u[me + 1]);
-            }
-            __builtin_nontemporal_store(out[0], &w[me]);
-            __builtin_nontemporal_store(out[1], &w[me + 1]);
-            if (accp) {
-                __builtin_nontemporal_store(__builtin_nontemporal_load(&accp[me]) + out[0], &accp[me]);
-                __builtin_nontemporal_store(__builtin_nontemporal_load(&accp[me + 1]) + out[1], &accp[me + 1]);
-            }
-            if constexpr (DOTS) {
-                const S *mv = s_tile + r * CW + lc;
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const double o = a.dot_raw ? (double)raw[j] : (double)out[j];
-                    d0 += (double)mv[j] * o;
-                    d1 += o * o;
-                }
-            }
-        }
-        if constexpr (DOTS) {
-            double vals[2] = {d0, d1};
-            block_sum<2>(vals, sh_red);
-            if (threadIdx.x == 0) {
-                const size_t slot = (size_t)slab * ng + grp;
-                a.red.partial[slot * 2] = vals[0];
-                a.red.partial[slot * 2 + 1] = vals[1];
-            }
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        s_last = (atomicAdd(&a.sched[8], 1u) == gridDim.x - 1) ? 1u : 0u;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    if constexpr (DOTS) {
-        const size_t nitems = (size_t)a.nslab * ng;
-        for (int j = 0; j < 2; ++j) {
-            double sm = 0.0;
-            for (size_t it = threadIdx.x; it < nitems; it += blockDim.x)
-                sm += __builtin_nontemporal_load(&a.red.partial[it * 2 + j]);
-            double vv[1] = {sm};
-            block_sum<1>(vv, sh_red);
-            if (threadIdx.x == 0) a.red.result[j] = vv[0];
-        }
-    }
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < 8; ++i) a.sched[i] = 0u;
-        a.sched[8] = 0u;
-        __threadfence();
-    }
-}
-
-// Columns kernel of the fast path, row-range variant. A work item is
-// (x, g): up rows [g * item_rows, (g + 1) * item_rows) over all slabs
-// x, x + 8, x + 16, ..., swept in order. Items of class x sit in the queue of
-// XCD x (the XCD a workgroup runs on is read from the hardware register);
-// a workgroup stages its item's neighbour lists in LDS once and walks the
-// slab sequence, so all workgroups of an XCD move through the same slabs at
-// about the same pace and its L2 holds about one slab at a time. Queues
-// drained, workgroups steal from the other XCDs. Per-element summation order
-// is that of k_hub_cols_f; the FP64 dot partials are one per item, reduced in
-// item order by the last workgroup to finish.
-template <typename S, int NV, int CW, bool DOTS>
-__global__ __launch_bounds__(256) void k_hub_cols_p(HubKArgs a)
-{
-    __shared__ double sh_red[4 * 2 * NV + 8];
-    __shared__ uint32_t s_ent[kColsLdsEntries];
-    __shared__ uint32_t s_off[kColsRows + 1];
-    __shared__ uint32_t s_mid[kColsRows];
-    __shared__ int s_item;
-    __shared__ unsigned s_last;
-    const char *__restrict__ vb = static_cast<const char *>(a.v);
-    const S *__restrict__ v = static_cast<const S *>(a.v);
-    S *__restrict__ w = static_cast<S *>(a.w);
-    const S *__restrict__ u = static_cast<const S *>(a.u);
-    S *__restrict__ accp = static_cast<S *>(a.acc_out);
-    double c1 = 1.0, c2 = 0.0;
-    if (a.ecoef) {
-        c1 = a.ecoef[0];
-        c2 = a.ecoef[1];
-    }
-    const S c1s = (S)c1, c2s = (S)c2, nt0 = (S)(-a.t0);
-    constexpr uint32_t ESZ = NV * sizeof(S);
-    constexpr int RPW = 64 / CW;
-    const int64_t ddn = a.ddn, dup = a.dup;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int nrange = a.groups;   // row ranges per slab class
-    int q = xcc_id(), tries = 0;
-    for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int it = -1;
-        while (tries < 8) {
-            const int cand = (int)atomicAdd(&a.sched[q], 1u);
-            if (cand < nrange) {
-                it = q * nrange + cand;
-                break;
-            }
-            q = (q + 1) & 7;
-            ++tries;
-        }
-        s_item = it;
-    }
-    __syncthreads();
-    const int item = s_item;
-    if (item < 0) break;
-    const int x = item / nrange;
-    const int64_t r0 = (int64_t)(item % nrange) * a.item_rows;
-    const int64_t r1 = r0 + a.item_rows < dup ? r0 + a.item_rows : dup;
-    if (r0 < r1) {
-        const uint32_t base = a.fu_off[r0];
-        for (int64_t i = threadIdx.x; i <= r1 - r0; i += blockDim.x) s_off[i] = a.fu_off[r0 + i] - base;
-        for (int64_t i = threadIdx.x; i < r1 - r0; i += blockDim.x) s_mid[i] = a.fu_mid[r0 + i] - base;
-        const uint32_t n = a.fu_off[r1] - base;
-        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) s_ent[i] = a.fu_ent[base + i] * ESZ;
-    }
-    __syncthreads();
-    double d0[NV], d1[NV];
-#pragma unroll
-    for (int j = 0; j < NV; ++j) d0[j] = d1[j] = 0.0;
-    for (int slab = x; slab < a.nslab; slab += 8) {
-        const int64_t col = (int64_t)slab * CW + (lane % CW);
-        if (col >= ddn) continue;
-        const uint32_t colb = (uint32_t)col * ESZ;
-        for (int64_t r = r0 + wid * RPW + lane / CW; r < r1; r += 4 * RPW) {
-            const size_t me = (size_t)r * ddn + col;
-            S ap[NV], am[NV];
-#pragma unroll
-            for (int j = 0; j < NV; ++j) ap[j] = am[j] = (S)0;
-            const uint32_t eb = s_off[r - r0], em = s_mid[r - r0], ee = s_off[r - r0 + 1];
-            uint32_t e = eb;
-            for (; e + 8 <= em; e += 8) {
-                S nv[8][NV];
-#pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    const S *p = reinterpret_cast<const S *>(vb + (s_ent[e + t] + colb));
-#pragma unroll
-                    for (int j = 0; j < NV; ++j) nv[t][j] = p[j];
-                }
-#pragma unroll
-                for (int t = 0; t < 8; ++t)
-#pragma unroll
-                    for (int j = 0; j < NV; ++j) ap[j] += nv[t][j];
-            }
-            for (; e < em; ++e) {
-                const S *p = reinterpret_cast<const S *>(vb + (s_ent[e] + colb));
-#pragma unroll
-                for (int j = 0; j < NV; ++j) ap[j] += p[j];
-            }
-            for (; e + 8 <= ee; e += 8) {
-                S nv[8][NV];
-#pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    const S *p = reinterpret_cast<const S *>(vb + (s_ent[e + t] + colb));
-#pragma unroll
-                    for (int j = 0; j < NV; ++j) nv[t][j] = p[j];
-                }
-#pragma unroll
-                for (int t = 0; t < 8; ++t)
-#pragma unroll
-                    for (int j = 0; j < NV; ++j) am[j] += nv[t][j];
-            }
-            for (; e < ee; ++e) {
-                const S *p = reinterpret_cast<const S *>(vb + (s_ent[e] + colb));
-#pragma unroll
-                for (int j = 0; j < NV; ++j) am[j] += p[j];
-            }
-            S out[NV], raw[NV];
-#pragma unroll
-            for (int j = 0; j < NV; ++j) {
-                raw[j] = __builtin_nontemporal_load(&w[me * NV + j]) + nt0 * (ap[j] - am[j]);
-                out[j] = c1s * raw[j];
-            }
-            if (u) {
-#pragma unroll
-                for (int j = 0; j < NV; ++j) out[j] += c2s * __builtin_nontemporal_load(&u[me * NV + j]);
-            }
-#pragma unroll
-            for (int j = 0; j < NV; ++j) __builtin_nontemporal_store(out[j], &w[me * NV + j]);
-            if (accp) {
-#pragma unroll
-                for (int j = 0; j < NV; ++j)
-                    __builtin_nontemporal_store(__builtin_nontemporal_load(&accp[me * NV + j]) + out[j],
-                                                &accp[me * NV + j]);
-            }
-            if constexpr (DOTS) {
-#pragma unroll
-                for (int j = 0; j < NV; ++j) {
-                    const double o = a.dot_raw ? (double)raw[j] : (double)out[j];
-                    d0[j] += (double)v[me * NV + j] * o;
-                    d1[j] += o * o;
-                }
-            }
-        }
-    }
-    if constexpr (DOTS) {
-        double vals[2 * NV];
-#pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            vals[j] = d0[j];
-            vals[NV + j] = d1[j];
-        }
-        block_sum<2 * NV>(vals, sh_red);
-        if (threadIdx.x == 0)
-            for (int j = 0; j < 2 * NV; ++j) a.red.partial[(size_t)item * 2 * NV + j] = vals[j];
-    }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        s_last = (atomicAdd(&a.sched[8], 1u) == gridDim.x - 1) ? 1u : 0u;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    if constexpr (DOTS) {
-        const size_t nitems = 8 * (size_t)nrange;
-        for (int j = 0; j < 2 * NV; ++j) {
-            double s = 0.0;
-            for (size_t it = threadIdx.x; it < nitems; it += blockDim.x)
-                s += __builtin_nontemporal_load(&a.red.partial[it * 2 * NV + j]);
-            double vv[1] = {s};
-            block_sum<1>(vv, sh_red);
-            if (threadIdx.x == 0) a.red.result[j] = vv[0];
-        }
-    }
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < 8; ++i) a.sched[i] = 0u;
-        a.sched[8] = 0u;
-        __threadfence();
-    }
-}
-
-template <typename S, int NV, int CW>
-static void launch_cols_p(const HubKArgs &a, int grid, hipStream_t st)
-{
-    if (a.nd) hipLaunchKernelGGL((k_hub_cols_p<S, NV, CW, true>), dim3(grid), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((k_hub_cols_p<S, NV, CW, false>), dim3(grid), dim3(256), 0, st, a);
-}
-
 template <typename S, int NV, int CW>
 static void launch_cols_t(const HubKArgs &a, int grid, hipStream_t st)
 {
@@ -2028,176 +1574,6 @@ static void launch_cols_f(const HubKArgs &a, int grid, hipStream_t st)
     }
     if (a.nd) hipLaunchKernelGGL((k_hub_cols_f<S, NV, CW, true>), dim3(grid), dim3(256), 0, st, a);
     else hipLaunchKernelGGL((k_hub_cols_f<S, NV, CW, false>), dim3(grid), dim3(256), 0, st, a);
-}
-
-// T_up slab kernel with wave-owned work: each wave takes (slab, item_rows
-// rows) items from the per-XCD queues itself and walks its rows one at a
-// time with the whole wave on one row segment (CW = 64 CPL columns), so a
-// row's neighbour list is wave-uniform and is read with scalar loads
-// straight from the CSR tables: no LDS staging and no block barriers. The
-// list walk, sums and epilogue are those of the batched walk (same order,
-// so W is bit-identical to it); the FP64 dot partials are one per item
-// (lane sums over the item's rows, then across the wave) and the last wave
-// to finish adds the item partials in item order.
-template <typename S, int NV, int CPL, bool DOTS>
-__global__ __launch_bounds__(256) void k_hub_cols_s(HubKArgs a)
-{
-    constexpr int CW = 64 * CPL;
-    constexpr int K = NV * CPL;
-    constexpr uint32_t ESZ = NV * sizeof(S);
-    const int lane = threadIdx.x & 63;
-    const int home = xcc_id();
-    const char *__restrict__ vb = static_cast<const char *>(a.v);
-    const S *__restrict__ v = static_cast<const S *>(a.v);
-    S *__restrict__ w = static_cast<S *>(a.w);
-    const S *__restrict__ u = static_cast<const S *>(a.u);
-    S *__restrict__ accp = static_cast<S *>(a.acc_out);
-    // read-only tables through the constant address space: uniform indices
-    // become scalar loads
-    typedef const __attribute__((address_space(4))) uint32_t cu32;
-    cu32 *fo = (cu32 *)a.fu_off;
-    cu32 *fm = (cu32 *)a.fu_mid;
-    cu32 *fe = (cu32 *)a.fu_ent;
-    cu32 *rowm = (cu32 *)a.row_of;
-    double c1 = 1.0, c2 = 0.0;
-    if (a.ecoef) {
-        c1 = a.ecoef[0];
-        c2 = a.ecoef[1];
-    }
-    const S c1s = (S)c1, c2s = (S)c2, nt0 = (S)(-a.t0);
-    const int64_t ddn = a.ddn, dup = a.dup;
-    const int nchunk = (int)((dup + a.item_rows - 1) / a.item_rows);
-    int q = home, tries = 0;
-    for (;;) {
-        int it = -1;
-        if (lane == 0) {
-            while (tries < 8) {
-                const int nsl_q = q < a.nslab ? (a.nslab - q + 7) / 8 : 0;
-                const int cand = (int)atomicAdd(&a.sched[q], 1u);
-                if (cand < nsl_q * nchunk) {
-                    it = q + 8 * cand;
-                    break;
-                }
-                q = (q + 1) & 7;
-                ++tries;
-            }
-        }
-        const int item = __builtin_amdgcn_readfirstlane(it);
-        if (item < 0) break;
-        const int iq = item & 7, idx = item >> 3;
-        const int slab = iq + 8 * (idx / nchunk);
-        const int chunk = idx % nchunk;
-        const int64_t r0 = (int64_t)chunk * a.item_rows;
-        const int64_t r1 = r0 + a.item_rows < dup ? r0 + a.item_rows : dup;
-        const int64_t col = (int64_t)slab * CW + CPL * lane;
-        const bool colok = col < ddn;
-        const uint32_t colb = (uint32_t)col * ESZ;
-        double d0[NV], d1[NV];
-#pragma unroll
-        for (int j = 0; j < NV; ++j) d0[j] = d1[j] = 0.0;
-        for (int64_t r = r0; r < r1; ++r) {
-            const uint32_t eb = fo[r], em = fm[r], ee = fo[r + 1];
-            if (!colok) continue;
-            const size_t me = (size_t)(rowm ? (int64_t)rowm[r] : r) * ddn + col;
-            const S *up = u ? u : w;
-            S wv[K], uv[K], vv[K];
-#pragma unroll
-            for (int j = 0; j < K; ++j) wv[j] = __builtin_nontemporal_load(&w[me * NV + j]);
-#pragma unroll
-            for (int j = 0; j < K; ++j) uv[j] = __builtin_nontemporal_load(&up[me * NV + j]);
-#pragma unroll
-            for (int j = 0; j < K; ++j) vv[j] = DOTS ? v[me * NV + j] : (S)0;
-            S hp[K], hm[K];
-#pragma unroll
-            for (int j = 0; j < K; ++j) hp[j] = hm[j] = (S)0;
-            for (uint32_t e0 = eb; e0 < ee; e0 += kColsBatch) {
-                // one contiguous scalar block of entries (the table is padded
-                // past its last list); slots past the row's list reuse the
-                // batch's first entry (a cache hit), their sums add +0
-                const uint32_t n = ee - e0;
-                uint32_t blk[kColsBatch], eo[kColsBatch];
-#pragma unroll
-                for (int t = 0; t < kColsBatch; ++t) blk[t] = fe[e0 + t];
-#pragma unroll
-                for (int t = 0; t < kColsBatch; ++t) eo[t] = ((uint32_t)t < n ? blk[t] : blk[0]) * ESZ;
-                S nv[kColsBatch][K];
-#pragma unroll
-                for (int t = 0; t < kColsBatch; ++t)
-                    load_k<S, K>(reinterpret_cast<const S *>(vb + eo[t] + colb), nv[t]);
-#pragma unroll
-                for (int t = 0; t < kColsBatch; ++t) {
-                    const bool in = e0 + t < ee, plus = e0 + t < em;
-#pragma unroll
-                    for (int j = 0; j < K; ++j) {
-                        hp[j] += (in && plus) ? nv[t][j] : (S)0;
-                        hm[j] += (in && !plus) ? nv[t][j] : (S)0;
-                    }
-                }
-            }
-            S hraw[K], hout[K];
-#pragma unroll
-            for (int j = 0; j < K; ++j) hraw[j] = wv[j] + nt0 * (hp[j] - hm[j]);
-            if (a.coef_cplx) {
-                epilogue_r<S, K>(hraw, uv, u != nullptr, 1, a.ecoef, hout);
-            } else {
-#pragma unroll
-                for (int j = 0; j < K; ++j) hout[j] = c1s * hraw[j];
-                if (u) {
-#pragma unroll
-                    for (int j = 0; j < K; ++j) hout[j] += c2s * uv[j];
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < K; ++j) __builtin_nontemporal_store(hout[j], &w[me * NV + j]);
-            if (accp) {
-#pragma unroll
-                for (int j = 0; j < K; ++j)
-                    __builtin_nontemporal_store(__builtin_nontemporal_load(&accp[me * NV + j]) + hout[j],
-                                                &accp[me * NV + j]);
-            }
-            if constexpr (DOTS) {
-#pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    const double o = a.dot_raw ? (double)hraw[j] : (double)hout[j];
-                    d0[j % NV] += (double)vv[j] * o;
-                    d1[j % NV] += o * o;
-                }
-            }
-        }
-        if constexpr (DOTS) {
-            const size_t slot = (size_t)slab * nchunk + chunk;
-#pragma unroll
-            for (int j = 0; j < NV; ++j) {
-                const double s0 = wave_sum(d0[j]), s1 = wave_sum(d1[j]);
-                if (lane == 0) {
-                    a.red.partial[slot * 2 * NV + j] = s0;
-                    a.red.partial[slot * 2 * NV + NV + j] = s1;
-                }
-            }
-        }
-    }
-    unsigned last = 0;
-    if (lane == 0) {
-        __threadfence();
-        last = (atomicAdd(&a.sched[8], 1u) == gridDim.x * (blockDim.x >> 6) - 1) ? 1u : 0u;
-    }
-    if (__builtin_amdgcn_readfirstlane(last) == 0u) return;
-    __threadfence();
-    if constexpr (DOTS) {
-        const size_t nitems = (size_t)a.nslab * nchunk;
-        for (int j = 0; j < 2 * NV; ++j) {
-            double sum = 0.0;
-            for (size_t it = lane; it < nitems; it += 64)
-                sum += __builtin_nontemporal_load(&a.red.partial[it * 2 * NV + j]);
-            sum = wave_sum(sum);
-            if (lane == 0) a.red.result[j] = sum;
-        }
-    }
-    if (lane == 0) {
-        for (int i = 0; i < 8; ++i) a.sched[i] = 0u;
-        a.sched[8] = 0u;
-        __threadfence();
-    }
 }
 
 template <typename S, int NV>
@@ -2333,14 +1709,6 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
         hipFuncSetAttribute((const void *)k_hub_rows_fm<S, NV>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)fm_bytes);
         hipLaunchKernelGGL((k_hub_rows_fm<S, NV>), dim3((unsigned)grid_r), dim3(threads), fm_bytes, st, a);
-    } else if (fast && h->hub.fs_maxw <= 32 && rmode == 2) {
-        hipFuncSetAttribute((const void *)k_hub_rows_fd<S, NV, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)fast_row_bytes);
-        hipLaunchKernelGGL((k_hub_rows_fd<S, NV, 2>), dim3((unsigned)grid_r), dim3(threads), fast_row_bytes, st, a);
-    } else if (fast && h->hub.fs_maxw <= 32 && rmode == 3) {
-        hipFuncSetAttribute((const void *)k_hub_rows_fd<S, NV, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)fast_row_bytes);
-        hipLaunchKernelGGL((k_hub_rows_fd<S, NV, 1>), dim3((unsigned)grid_r), dim3(threads), fast_row_bytes, st, a);
     } else if (fast) {
         hipFuncSetAttribute((const void *)k_hub_rows_f<S, NV>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)fast_row_bytes);
@@ -2391,84 +1759,12 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
             return HPHI_OK;
         }
     }
-    if (fast_cols && h->sched_cfg.hub_sweep == 2 && !a.coef_cplx) {
-        // persistent sweep: hub_groups row ranges, each within the staging arrays
-        int64_t rows = (a.dup + groups - 1) / groups;
-        if (rows > kColsRows) rows = kColsRows;
-        const int64_t deg = h->hub.max_deg[0] > 0 ? h->hub.max_deg[0] : 1;
-        if (rows * deg > kColsLdsEntries) rows = kColsLdsEntries / deg;
-        if (rows < 1)
-            return fail(HPHI_ERR_UNSUPPORTED, "Hubbard up-species degree %lld too large for staging",
-                        (long long)h->hub.max_deg[0]);
-        const int64_t g_eff = (a.dup + rows - 1) / rows;
-        a.item_rows = (int)rows;
-        a.groups = (int)g_eff;
-        const int cwp = cw > 64 ? 64 : cw;   // this kernel takes up to 64 columns per slab
-        a.nslab = (int)((a.ddn + cwp - 1) / cwp);
-        const int64_t grid_p = 8 * g_eff;
-        if (grid_p > (int64_t)INT32_MAX || (a.nd && grid_p * 2 * NV > (int64_t)kReduceSlots))
-            return fail(HPHI_ERR_UNSUPPORTED, "Hubbard column sweep grid too large");
-        a.sched = h->sched.as<unsigned>();
-        switch (cwp) {
-        case 8: launch_cols_p<S, NV, 8>(a, (int)grid_p, st); break;
-        case 16: launch_cols_p<S, NV, 16>(a, (int)grid_p, st); break;
-        case 32: launch_cols_p<S, NV, 32>(a, (int)grid_p, st); break;
-        default: launch_cols_p<S, NV, 64>(a, (int)grid_p, st); break;
-        }
-        HPHI_HIP(hipGetLastError());
-        return HPHI_OK;
-    }
-    if (fast_cols && h->sched_cfg.hub_sweep == 4 && NV == 1 && !a.coef_cplx && h->hub.fg_ok && a.ddn % 2 == 0 &&
-        h->hub.fg_max_rows <= kGTileRows && h->hub.fg_max_ent <= (uint32_t)kGEnt) {
-        // group tiles: items (64-column slab, up group)
-        a.fg_rows = h->hub.fg_rows.as<uint32_t>();
-        a.fg_off = h->hub.fg_off.as<uint32_t>();
-        a.fg_cnt = h->hub.fg_cnt.as<uint32_t>();
-        a.fg_ent = h->hub.fg_ent.as<uint32_t>();
-        a.fg_ngroups = h->hub.fg_ngroups;
-        a.nslab = (int)((a.ddn + 63) / 64);
-        const int64_t nitems = (int64_t)a.nslab * a.fg_ngroups;
-        if (a.nd && nitems * 2 > (int64_t)kReduceSlots)
-            return fail(HPHI_ERR_UNSUPPORTED, "Hubbard group items beyond the reduction scratch");
-        a.sched = h->sched.as<unsigned>();
-        const int grid_g = 8 * groups;
-        if (a.nd) hipLaunchKernelGGL((k_hub_cols_g<S, true>), dim3(grid_g), dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((k_hub_cols_g<S, false>), dim3(grid_g), dim3(256), 0, st, a);
-        HPHI_HIP(hipGetLastError());
-        return HPHI_OK;
-    }
-    if (fast_cols && h->sched_cfg.hub_row_order == 2 && h->sched_cfg.hub_sweep != 2 && h->sched_cfg.hub_sweep != 4 &&
-        h->hub.rr_row.p) {
+    if (fast_cols && h->sched_cfg.hub_row_order == 2 && h->hub.rr_row.p) {
         // reverse Cuthill-McKee processing order: lists by position, row map
         a.fu_off = h->hub.rr_off.as<uint32_t>();
         a.fu_mid = h->hub.rr_mid.as<uint32_t>();
         a.fu_ent = h->hub.rr_ent.as<uint32_t>();
         a.row_of = h->hub.rr_row.as<uint32_t>();
-    }
-    if (fast_cols && h->sched_cfg.hub_sweep == 6) {
-        // wave-owned items, scalar list walk: 128-column slabs with two
-        // columns per lane (one real vector, even row length), else 64
-        const bool two = NV == 1 && a.ddn % 2 == 0 && cw == 128;
-        const int cws = two ? 128 : 64;
-        a.item_rows = h->sched_cfg.hub_item_rows;
-        a.nslab = (int)((a.ddn + cws - 1) / cws);
-        const int64_t nitems = (int64_t)a.nslab * ((a.dup + a.item_rows - 1) / a.item_rows);
-        if (a.nd && nitems * 2 * NV > (int64_t)kReduceSlots)
-            return fail(HPHI_ERR_UNSUPPORTED, "Hubbard column items beyond the reduction scratch");
-        a.sched = h->sched.as<unsigned>();
-        const int grid_s = 8 * groups;
-        if constexpr (NV == 1) {
-            if (two) {
-                if (a.nd) hipLaunchKernelGGL((k_hub_cols_s<S, 1, 2, true>), dim3(grid_s), dim3(256), 0, st, a);
-                else hipLaunchKernelGGL((k_hub_cols_s<S, 1, 2, false>), dim3(grid_s), dim3(256), 0, st, a);
-                HPHI_HIP(hipGetLastError());
-                return HPHI_OK;
-            }
-        }
-        if (a.nd) hipLaunchKernelGGL((k_hub_cols_s<S, NV, 1, true>), dim3(grid_s), dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((k_hub_cols_s<S, NV, 1, false>), dim3(grid_s), dim3(256), 0, st, a);
-        HPHI_HIP(hipGetLastError());
-        return HPHI_OK;
     }
     int item_rows = h->sched_cfg.hub_item_rows;
     // the item's neighbour lists must fit the staging array

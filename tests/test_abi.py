@@ -83,3 +83,42 @@ def test_invalid_arguments_fail_cleanly():
     from paper_2307_13222_amd import api
     with pytest.raises(api.HphiError):
         api.tridiag_lowest(np.zeros(3), np.zeros(3), 5)
+
+
+STRUCTS = {
+    "SpinBond": "hphi_spin_bond", "Hop": "hphi_hop", "XyzBond": "hphi_xyz_bond", "PairTerm": "hphi_pair_term",
+    "HubFrames": "hphi_hub_frames", "LanczosOpts": "hphi_lanczos_opts", "LanczosInfo": "hphi_lanczos_info",
+    "BatchItem": "hphi_batch_item", "CtpqOpts": "hphi_ctpq_opts", "TevolOpts": "hphi_tevol_opts",
+    "LobpcgOpts": "hphi_lobpcg_opts", "LobpcgInfo": "hphi_lobpcg_info", "Schedule": "hphi_schedule",
+    "SqwOpts": "hphi_sqw_opts", "SqwInfo": "hphi_sqw_info",
+}
+
+
+def test_binding_structs_match_header_layout(tmp_path):
+    # sizeof and every field's offset, from the header compiled by gcc
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for py, c in STRUCTS.items():
+        lines.append(f'printf("{py} size %zu\\n", sizeof({c}));')
+        for f, _ in getattr(_lib, py)._fields_:
+            lines.append(f'printf("{py} {f} %zu\\n", offsetof({c}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c11", "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in out:
+        if not line:
+            continue
+        py, f, val = line.split()
+        cls = getattr(_lib, py)
+        got = ctypes.sizeof(cls) if f == "size" else getattr(cls, f).offset
+        assert got == int(val), (py, f, got, val)
+    # every header field is in the binding (same count)
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    for py, c in STRUCTS.items():
+        body = re.search(r"typedef struct\s*\{([^}]*)\}\s*" + c + r"\s*;", text).group(1)
+        decl = [d.strip() for d in body.replace("\n", " ").split(";") if d.strip()]
+        n = sum(len(d.split(",")) for d in decl)
+        assert n == len(getattr(_lib, py)._fields_), (c, n)

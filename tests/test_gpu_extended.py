@@ -100,8 +100,8 @@ def test_extended_mult_vs_oracle(api, ctx, name, make, n, nu, nd):
     assert relmax(w - w0, O.hubbard_pairs_hv(m, ups, dns, v)) < 1e-11
 
 
-SCHEDULES = [dict(hub_sweep=5), dict(hub_sweep=6), dict(hub_sweep=3, hub_row_cols=1),
-             dict(hub_sweep=5, hub_row_cols=4), dict(hub_sweep=2, hub_slab_cols=32)]
+SCHEDULES = [dict(hub_sweep=5), dict(hub_sweep=1, hub_row_cols=2), dict(hub_sweep=3, hub_row_cols=1),
+             dict(hub_sweep=5, hub_row_cols=4), dict(hub_sweep=5, hub_slab_cols=32, hub_row_cols=3)]
 
 
 @pytest.mark.parametrize("sched", SCHEDULES, ids=[str(s) for s in SCHEDULES])

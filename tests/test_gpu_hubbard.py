@@ -175,7 +175,6 @@ def test_hubbard_batched_list_walk_bit_identical(api, ctx, lx, ly, nu, nd):
     out = {}
     for key, sch in (("two_list", dict(hub_row_cols=4, hub_sweep=3, hub_row_order=1)),
                      ("batched", dict(hub_row_cols=5, hub_sweep=5, hub_row_order=1)),
-                     ("wave_owned", dict(hub_row_cols=5, hub_sweep=6, hub_row_order=1)),
                      ("rcm", dict(hub_row_cols=5, hub_sweep=5, hub_row_order=2)),
                      ("prescaled", dict(hub_row_cols=6, hub_sweep=5, hub_row_order=2)),
                      ("narrow", dict(hub_slab_cols=32, hub_row_cols=6, hub_sweep=5, hub_row_order=2))):
@@ -186,7 +185,7 @@ def test_hubbard_batched_list_walk_bit_identical(api, ctx, lx, ly, nu, nd):
         te = api.time_evolve(h, psi, 3, dt=0.05, n_max=6)
         out[key] = (prods, lz, host(psi), te)
     a = out["two_list"]
-    for c in (out["batched"], out["wave_owned"], out["rcm"], out["prescaled"], out["narrow"]):
+    for c in (out["batched"], out["rcm"], out["prescaled"], out["narrow"]):
         for x, y in zip(a[0], c[0]):
             assert np.array_equal(x, y)
         assert np.array_equal(a[2], c[2])
