@@ -240,8 +240,113 @@ def hubbard_pairs_hv(m, ups: np.ndarray, dns: np.ndarray, v: np.ndarray) -> np.n
     return w
 
 
+def _complex_t(m):
+    """The transfers as complex numbers t + i t_im, or None when the model
+    has no imaginary parts."""
+    t_im = getattr(m, "t_im", None)
+    if t_im is None or not np.any(np.asarray(t_im) != 0.0):
+        return None
+    return np.asarray(m.t, dtype=np.float64) + 1j * np.asarray(t_im, dtype=np.float64)
+
+
+def species_hopping_complex(n_sites: int, states: np.ndarray, hi, hj, tc) -> scipy.sparse.csr_matrix:
+    """One species' transfer matrix for complex amplitudes: each hop
+    (i, j, t) contributes -(t c+_i c_j + t* c+_j c_i) (the one-body term of
+    the general Hamiltonian, Sec. 5, with the Hermitian partner written
+    out). For a state s with exactly one of i, j occupied and s' = s with
+    the electron moved, the element <s|.|s'> is -t when s holds i and -t*
+    when s holds j, times (-1)^(occupied sites strictly between i and j)."""
+    st = np.asarray(states, dtype=np.uint64)
+    rows, cols, vals = [], [], []
+    for h in range(len(hi)):
+        i, j, t = int(hi[h]), int(hj[h]), complex(tc[h])
+        bi = (st >> np.uint64(i)) & np.uint64(1)
+        bj = (st >> np.uint64(j)) & np.uint64(1)
+        act = np.nonzero(bi != bj)[0]
+        if act.size == 0:
+            continue
+        s = st[act]
+        s2 = s ^ (np.uint64(1 << i) | np.uint64(1 << j))
+        r2 = np.searchsorted(st, s2)
+        lo, hi_ = min(i, j), max(i, j)
+        between = np.zeros(act.size, dtype=np.int64)
+        for k in range(lo + 1, hi_):
+            between += ((s >> np.uint64(k)) & np.uint64(1)).astype(np.int64)
+        sign = np.where(between % 2 == 1, -1.0, 1.0)
+        holds_i = bi[act] == np.uint64(1)
+        coef = np.where(holds_i, -t, -np.conj(t)) * sign
+        rows.append(act)
+        cols.append(r2)
+        vals.append(coef)
+    d = st.shape[0]
+    if not rows:
+        return scipy.sparse.csr_matrix((d, d), dtype=np.complex128)
+    return scipy.sparse.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                                   shape=(d, d), dtype=np.complex128)
+
+
+def _hubbard_u_diag(m, ups, dns) -> np.ndarray:
+    """sum_i U_i n_i,up n_i,dn on the up-major product basis."""
+    u = np.asarray(ups, dtype=np.uint64)
+    d = np.asarray(dns, dtype=np.uint64)
+    diag = np.zeros((u.shape[0], d.shape[0]))
+    for i in range(m.n_sites):
+        ui = ((u >> np.uint64(i)) & np.uint64(1)).astype(np.float64)
+        di = ((d >> np.uint64(i)) & np.uint64(1)).astype(np.float64)
+        diag += float(m.u_site[i]) * ui[:, None] * di[None, :]
+    return diag.reshape(-1)
+
+
+def hubbard_sparse_complex(m, ups, dns) -> scipy.sparse.csr_matrix:
+    """H with complex transfers: T_up (x) 1 + 1 (x) T_dn + U diagonal (+ the
+    two-body terms). With all up orbitals before all down ones, a down hop
+    passes every up electron twice, so its sign is that of the down species
+    alone."""
+    tc = _complex_t(m)
+    if tc is None:
+        tc = np.asarray(m.t, dtype=np.complex128)
+    tu = species_hopping_complex(m.n_sites, ups, m.hi, m.hj, tc)
+    td = species_hopping_complex(m.n_sites, dns, m.hi, m.hj, tc)
+    H = (scipy.sparse.kron(tu, scipy.sparse.identity(len(dns)), format="csr")
+         + scipy.sparse.kron(scipy.sparse.identity(len(ups)), td, format="csr")
+         + scipy.sparse.diags(_hubbard_u_diag(m, ups, dns)))
+    if _n_pairs(m):
+        H = H + hubbard_pairs_sparse(m, ups, dns)
+    return H.tocsr()
+
+
+def hubbard_row_complex(m, ups, dns, ru: int, rd: int):
+    """Row (ru, rd) of the complex-transfer H: columns and values."""
+    tc = _complex_t(m)
+    nd = len(dns)
+    u, d = int(ups[ru]), int(dns[rd])
+    cols = [ru * nd + rd]
+    vals = [complex(sum(float(m.u_site[i]) for i in range(m.n_sites) if (u >> i) & (d >> i) & 1))]
+    for h in range(m.n_hops):
+        i, j, t = int(m.hi[h]), int(m.hj[h]), complex(tc[h])
+        lo, hi_ = min(i, j), max(i, j)
+        for sp, x in ((0, u), (1, d)):
+            if ((x >> i) & 1) == ((x >> j) & 1):
+                continue
+            x2 = x ^ ((1 << i) | (1 << j))
+            sign = -1.0 if bin(x & (((1 << hi_) - 1) & ~((2 << lo) - 1))).count("1") % 2 else 1.0
+            c = (-t if (x >> i) & 1 else -np.conj(t)) * sign
+            if sp == 0:
+                cols.append(int(np.searchsorted(ups, x2)) * nd + rd)
+            else:
+                cols.append(ru * nd + int(np.searchsorted(dns, x2)))
+            vals.append(c)
+    cols, vals = np.array(cols, dtype=np.int64), np.array(vals, dtype=np.complex128)
+    if _n_pairs(m):
+        c2, v2 = hubbard_pairs_row(m, ups, dns, ru, rd)
+        cols, vals = np.concatenate([cols, c2]), np.concatenate([vals, v2.astype(np.complex128)])
+    return cols, vals
+
+
 def hubbard_hv(m, ups: np.ndarray, dns: np.ndarray, v: np.ndarray) -> np.ndarray:
     v = np.asarray(v)
+    if _complex_t(m) is not None:
+        return hubbard_sparse_complex(m, ups, dns) @ v.astype(np.complex128)
     if np.iscomplexobj(v):
         return hubbard_hv(m, ups, dns, v.real) + 1j * hubbard_hv(m, ups, dns, v.imag)
     hi, hj, t, us = _hub_arrays(m)
@@ -281,6 +386,8 @@ def hubbard_pairs_row(m, ups, dns, ru: int, rd: int):
 
 
 def hubbard_row(m, ups, dns, ru: int, rd: int):
+    if _complex_t(m) is not None:
+        return hubbard_row_complex(m, ups, dns, ru, rd)
     hi, hj, t, us = _hub_arrays(m)
     s = 2 * hi.shape[0] + 1
     cols = np.empty(s, dtype=np.int64)
@@ -296,6 +403,8 @@ def hubbard_row(m, ups, dns, ru: int, rd: int):
 
 
 def hubbard_sparse(m, ups, dns) -> scipy.sparse.csr_matrix:
+    if _complex_t(m) is not None:
+        return hubbard_sparse_complex(m, ups, dns)
     hi, hj, t, us = _hub_arrays(m)
     dim, s = ups.shape[0] * dns.shape[0], 2 * hi.shape[0] + 1
     cols = np.zeros(dim * s, dtype=np.int64)

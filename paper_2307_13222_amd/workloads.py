@@ -38,7 +38,8 @@ class SpinModel:
 
 @dataclass
 class HubbardModel:
-    """H = -sum_h t_h sum_sigma (c+_i c_j + h.c.) + sum_i U_i n_up n_dn, plus
+    """H = -sum_h sum_sigma (t_h c+_i c_j + t_h* c+_j c_i) + sum_i U_i n_up n_dn
+    (t_h = t + i t_im; real unless t_im is given), plus
     the optional two-body terms of Eq. ham_general (Sec. 5) per site pair
     p = (pi, pj): inter-site Coulomb pv n_i n_j, Hund -pjh (n_i,up n_j,up +
     n_i,dn n_j,dn), exchange pjx (c+_i,up c_j,up c+_j,dn c_i,dn + h.c.) and
@@ -56,6 +57,7 @@ class HubbardModel:
     pjh: Optional[np.ndarray] = None
     pjx: Optional[np.ndarray] = None
     pjp: Optional[np.ndarray] = None
+    t_im: Optional[np.ndarray] = None       # imaginary parts of the transfers (None: real)
 
     @property
     def n_hops(self) -> int:
@@ -248,7 +250,7 @@ def with_pair_terms(m: HubbardModel, pairs, v=0.0, jh=0.0, jx=0.0, jp=0.0, name:
     k = len(p)
     full = lambda x: np.broadcast_to(np.asarray(x, dtype=np.float64), (k,)).copy()
     return HubbardModel(m.n_sites, m.hi, m.hj, m.t, m.u_site, name or m.name + "_ext", m.site_x,
-                        p[:, 0].copy(), p[:, 1].copy(), full(v), full(jh), full(jx), full(jp))
+                        p[:, 0].copy(), p[:, 1].copy(), full(v), full(jh), full(jx), full(jp), m.t_im)
 
 
 def extended_hubbard_square(lx: int, ly: int, t: float = 1.0, u: float = 4.0, v: float = 1.0,
@@ -271,19 +273,21 @@ class HubbardFrames:
     hop_t: Optional[np.ndarray] = None    # (n_frames, n_hops)
     u_site: Optional[np.ndarray] = None   # (n_frames, n_sites)
     pair_v: Optional[np.ndarray] = None   # (n_frames, n_pairs, 4): v, j_hund, j_ex, j_pair
+    hop_t_im: Optional[np.ndarray] = None  # (n_frames, n_hops): imaginary parts of the transfers
 
 
 def model_at_frame(m: HubbardModel, fr: HubbardFrames, k: int) -> HubbardModel:
     """The model with the amplitudes of frame min(k, n_frames - 1)."""
     f = min(int(k), fr.n_frames - 1)
     t = m.t if fr.hop_t is None else np.array(fr.hop_t[f], dtype=np.float64)
+    t_im = m.t_im if fr.hop_t_im is None else np.array(fr.hop_t_im[f], dtype=np.float64)
     u = m.u_site if fr.u_site is None else np.array(fr.u_site[f], dtype=np.float64)
     pv, pjh, pjx, pjp = m.pv, m.pjh, m.pjx, m.pjp
     if fr.pair_v is not None and m.n_pairs:
         pa = np.asarray(fr.pair_v[f], dtype=np.float64)
         pv, pjh, pjx, pjp = (pa[:, c].copy() for c in range(4))
     return HubbardModel(m.n_sites, m.hi, m.hj, t, u, f"{m.name}_frame{f}", m.site_x,
-                        m.pi, m.pj, pv, pjh, pjx, pjp)
+                        m.pi, m.pj, pv, pjh, pjx, pjp, t_im)
 
 
 def interaction_ramp(m: HubbardModel, u_from: float, u_to: float, n_ramp: int, n_frames: int) -> HubbardFrames:
@@ -301,6 +305,37 @@ def hopping_drive(m: HubbardModel, amp: float, omega: float, dt: float, n_frames
     (every hop scaled alike; amp > 1 makes the factor change sign)."""
     f = 1.0 + amp * np.sin(omega * dt * np.arange(n_frames))
     return HubbardFrames(n_frames, hop_t=f[:, None] * np.asarray(m.t, dtype=np.float64)[None, :])
+
+
+def hop_displacements(m: HubbardModel) -> np.ndarray:
+    """x_i - x_j of each hop (i, j) along the site coordinate site_x, taken
+    as the nearest periodic image on a ring of max(site_x) + 1 positions."""
+    x = np.asarray(m.site_x, dtype=np.int64)
+    L = int(x.max()) + 1
+    d = x[np.asarray(m.hi)] - x[np.asarray(m.hj)]
+    return ((d + L // 2) % L) - L // 2
+
+
+def with_flux(m: HubbardModel, phi: float, name: str = "") -> HubbardModel:
+    """A copy of m with a uniform vector potential: t_ij -> t_ij e^{i A (x_i - x_j)},
+    A = phi / L (total flux phi through the ring of L positions)."""
+    x = np.asarray(m.site_x, dtype=np.int64)
+    a = phi / (int(x.max()) + 1)
+    tc = np.asarray(m.t, dtype=np.float64) * np.exp(1j * a * hop_displacements(m))
+    return HubbardModel(m.n_sites, m.hi, m.hj, tc.real.copy(), m.u_site, name or m.name + "_flux", m.site_x,
+                        m.pi, m.pj, m.pv, m.pjh, m.pjx, m.pjp, tc.imag.copy())
+
+
+def peierls_pulse(m: HubbardModel, a0: float, omega: float, t_center: float, sigma: float, dt: float,
+                  n_frames: int) -> HubbardFrames:
+    """Transfers in a light pulse through the Peierls phase,
+    t_ij(t_k) = t_ij e^{i A(t_k) (x_i - x_j)} with
+    A(t) = a0 exp(-(t - t_center)^2 / (2 sigma^2)) cos(omega (t - t_center)),
+    t_k = k dt."""
+    tk = dt * np.arange(n_frames)
+    a = a0 * np.exp(-((tk - t_center) ** 2) / (2.0 * sigma * sigma)) * np.cos(omega * (tk - t_center))
+    tc = np.asarray(m.t, dtype=np.float64)[None, :] * np.exp(1j * a[:, None] * hop_displacements(m)[None, :])
+    return HubbardFrames(n_frames, hop_t=tc.real.copy(), hop_t_im=tc.imag.copy())
 
 
 def random_frames(m: HubbardModel, n_frames: int, seed: int, hops: bool = True, u: bool = True,

@@ -1,7 +1,10 @@
 """Pins of the oracle's Hubbard H*v: an independent Jordan-Wigner matrix
 construction on the full Fock space (signs included), free-fermion and
 atomic-limit energies, the two-site closed form, the ring sign pins, the
-closed-form trace, hermiticity and the Kronecker-sum structure; for the
+closed-form trace, hermiticity and the Kronecker-sum structure; complex
+transfers (t c+_i c_j + t* c+_j c_i) by the same Jordan-Wigner route, by
+plane waves of one electron on a ring threaded by a flux, and by the gauge
+transformation that removes bond phases on an open chain; for the
 two-body terms of Eq. ham_general (Sec. 5) the same Jordan-Wigner route with
 each term formed from the operator matrices it names, the dimer closed form,
 sector conservation, and spin-rotation invariance at JH = JX (with its
@@ -39,11 +42,14 @@ def jw_dense_hubbard(m) -> np.ndarray:
     c = [annihilate(o) for o in range(n_orb)]
     cd = [x.T.tocsr() for x in c]
     dim = 1 << n_orb
-    H = sp.csr_matrix((dim, dim))
+    t_im = getattr(m, "t_im", None)
+    H = sp.csr_matrix((dim, dim), dtype=np.complex128 if t_im is not None else np.float64)
     for h in range(m.n_hops):
-        i, j, t = int(m.hi[h]), int(m.hj[h]), float(m.t[h])
+        i, j = int(m.hi[h]), int(m.hj[h])
+        t = float(m.t[h]) + (1j * float(t_im[h]) if t_im is not None else 0.0)
         for s in (0, n):
-            H = H - t * (cd[i + s] @ c[j + s] + cd[j + s] @ c[i + s])
+            # t c+_i c_j + t* c+_j c_i (the Hermitian pair of the transfer)
+            H = H - (t * (cd[i + s] @ c[j + s]) + np.conj(t) * (cd[j + s] @ c[i + s]))
     for i in range(n):
         H = H + m.u_site[i] * (cd[i] @ c[i]) @ (cd[i + n] @ c[i + n])
     return H
@@ -326,3 +332,83 @@ def test_two_body_rows_and_row_range():
         dense = np.zeros(Hs.shape[0])
         np.add.at(dense, cols, vals)
         assert np.allclose(dense, Hs.getrow(ru * len(dns) + rd).toarray()[0], atol=1e-14)
+
+
+# ---------------------------------------------------------- complex transfers --
+
+def random_complex_hubbard(n, seed, p=0.7):
+    m = random_hubbard(n, seed, p)
+    rng = np.random.default_rng(seed + 100)
+    return W.HubbardModel(m.n_sites, m.hi, m.hj, m.t, m.u_site, "rand_c", t_im=rng.normal(size=m.n_hops))
+
+
+@pytest.mark.parametrize("n,seed", [(3, 3), (4, 4), (5, 5)])
+def test_complex_transfers_match_jordan_wigner(n, seed):
+    m = random_complex_hubbard(n, seed)
+    Hfull = jw_dense_hubbard(m)
+    for nu in range(n + 1):
+        for nd in range(n + 1):
+            ups, dns = O.hubbard_basis(n, nu, nd)
+            idx = sector_indices(n, ups, dns)
+            ref = Hfull[idx][:, idx].toarray()
+            Hs = O.hubbard_sparse(m, ups, dns).toarray()
+            assert np.allclose(Hs, ref, atol=1e-13, rtol=0), (nu, nd)
+            assert np.allclose(Hs, Hs.conj().T, atol=1e-14)
+            v = W.random_vector(len(idx), nu * 5 + nd, np.complex128)
+            assert np.allclose(O.hubbard_hv(m, ups, dns, v), ref @ v, atol=1e-12)
+            if len(idx):
+                for r in (0, len(idx) - 1, len(idx) // 2):
+                    cols, vals = O.hubbard_row(m, ups, dns, r // len(dns), r % len(dns))
+                    row = np.zeros(len(idx), dtype=np.complex128)
+                    np.add.at(row, cols, vals)
+                    assert np.allclose(row, ref[r], atol=1e-13)
+
+
+@pytest.mark.parametrize("phi", [0.3, 1.1, -2.0])
+def test_flux_ring_plane_waves(phi):
+    # one electron on a ring of L sites with flux phi: the transfer (x, x+1)
+    # carries t e^{-i phi / L}, so H e^{ikx} = -2t cos(k - phi / L) e^{ikx}
+    L, t = 7, 0.8
+    m = W.with_flux(W.hubbard_chain(L, t, 3.0), phi)
+    ups, dns = O.hubbard_basis(L, 1, 0)
+    H = O.hubbard_sparse(m, ups, dns).toarray()
+    x = np.array([int(u).bit_length() - 1 for u in ups])
+    for mk in range(L):
+        k = 2 * np.pi * mk / L
+        psi = np.exp(1j * k * x)
+        assert np.allclose(H @ psi, -2 * t * np.cos(k - phi / L) * psi, atol=1e-13)
+
+
+def test_open_chain_bond_phases_gauge_away():
+    # bond phases phi_x on an open chain: H_phi = D H_0 D^+ with
+    # D = diag(exp(i sum over electrons of theta(x))), theta(x + 1) = theta(x) - phi_x
+    n = 6
+    rng = np.random.default_rng(7)
+    hi = np.arange(n - 1, dtype=np.int32)
+    hj = hi + 1
+    t = rng.uniform(0.5, 1.5, size=n - 1)
+    phi = rng.uniform(-np.pi, np.pi, size=n - 1)
+    u = rng.normal(size=n) * 2
+    m0 = W.HubbardModel(n, hi, hj, t, u, "open")
+    mp = W.HubbardModel(n, hi, hj, t * np.cos(phi), u, "open_phase", t_im=t * np.sin(phi))
+    theta = np.concatenate([[0.0], -np.cumsum(phi)])
+    for nu, nd in [(3, 2), (2, 2), (1, 3)]:
+        ups, dns = O.hubbard_basis(n, nu, nd)
+        th_u = np.array([sum(theta[i] for i in range(n) if (int(x) >> i) & 1) for x in ups])
+        th_d = np.array([sum(theta[i] for i in range(n) if (int(x) >> i) & 1) for x in dns])
+        D = np.exp(1j * (th_u[:, None] + th_d[None, :]).ravel())
+        H0 = O.hubbard_sparse(m0, ups, dns).toarray()
+        Hp = O.hubbard_sparse(mp, ups, dns).toarray()
+        assert np.allclose(Hp, D[:, None] * H0 * D.conj()[None, :], atol=1e-13)
+        # and the phases are not trivial: the matrices differ
+        assert np.max(np.abs(Hp - H0)) > 0.1
+
+
+def test_zero_imaginary_parts_equal_real_path():
+    m = random_hubbard(6, 9)
+    ups, dns = O.hubbard_basis(6, 3, 2)
+    mc = W.HubbardModel(m.n_sites, m.hi, m.hj, m.t, m.u_site, "c", t_im=np.zeros(m.n_hops))
+    mc2 = W.HubbardModel(m.n_sites, m.hi, m.hj, m.t, m.u_site, "c2", t_im=np.full(m.n_hops, 1e-300))
+    H = O.hubbard_sparse(m, ups, dns).toarray()
+    assert np.array_equal(O.hubbard_sparse(mc, ups, dns).toarray(), H)
+    assert np.allclose(O.hubbard_sparse(mc2, ups, dns).toarray(), H, atol=1e-15)
