@@ -29,6 +29,9 @@ Other workloads (--workload), reported the same way:
                 frame per step); the energy change checked against the
                 work (U_k+1 - U_k) N_s <D>, and the cost of the frame
                 switches against the same steps with one frame held
+  tevol_pulse_hubbard16  the U = 4 ring's ground state driven by a light
+                pulse: Peierls phases e^{i A(t)(x_i - x_j)} on the transfers
+                (complex amplitudes, one frame per step)
   lobpcg_hubbard3x4  lowest 4 (+2 guard) eigenpairs of the 3x4 periodic Hubbard
                 lattice at half filling (U = 4, dim 853,776) by LOBPCG with the
                 point-Jacobi preconditioner; energies vs a long Lanczos
@@ -68,7 +71,7 @@ def parse():
     p.add_argument("--iters", type=int, default=0, help="Krylov / TPQ steps per solve (0 = workload default)")
     p.add_argument("--workload", default="hubbard4x4",
                    choices=["hubbard4x4", "heisenberg16", "ctpq_xxz28", "j1j2_6x6", "serving_mix", "tevol_hubbard16",
-                            "tevol_ramp_hubbard16",
+                            "tevol_ramp_hubbard16", "tevol_pulse_hubbard16",
                             "lobpcg_hubbard3x4", "copy_probe", "ext_hubbard4x4", "tfim_ring28", "spin1_chain18"])
     p.add_argument("--requests", type=int, default=64, help="requests per serving run (serving_mix)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -194,6 +197,23 @@ def cpu_baseline(workload: str, sample_rows: int):
         dt = time.perf_counter() - t0
         states, bytes_per = nu * len(dns), 16.0
         sample = f"oracle extended-Hubbard H*v over up-rows [0, {nu}) of {len(ups)}"
+    elif workload == "tevol_pulse_hubbard16":
+        # complex transfers: the oracle's complex row formula (Python),
+        # row by row on a bounded sample of rows
+        m = W.with_flux(W.hubbard_chain(16, 1.0, 4.0), 0.7)
+        ups, dns = O.hubbard_basis(16, 8, 8)
+        rows = sample_rows if sample_rows > 0 else 100000
+        rng = np.random.default_rng(0)
+        dim = len(ups) * len(dns)
+        v = (rng.random(dim) - 0.5) + 1j * (rng.random(dim) - 0.5)
+        t0 = time.perf_counter()
+        for r in range(rows):
+            cols, vals = O.hubbard_row(m, ups, dns, r // len(dns), r % len(dns))
+            complex(np.dot(vals, v[cols]))
+        dt = time.perf_counter() - t0
+        del v
+        states, bytes_per = rows, 32.0
+        sample = f"oracle complex-transfer Hubbard rows [0, {rows}) of the 16-site ring (row formula, one thread)"
     elif workload in ("tevol_hubbard16", "tevol_ramp_hubbard16"):
         # the complex product a Taylor order applies, on the 16-site ring
         # at U = 8 (the ramp's frames differ only in U, a diagonal term)
@@ -240,7 +260,8 @@ def cpu_baseline(workload: str, sample_rows: int):
         states, bytes_per = rows, 8.0
         sample = f"oracle sparse rows of the 6x6 J1-J2 sector, {rows} random rows (row formula only)"
     gbs = bytes_per * states / dt / 1e9
-    out = {"value": round(gbs, 4), "unit": "GB/s", "cores": omp_threads(), "kind": "oracle",
+    cores = 1 if workload == "tevol_pulse_hubbard16" else omp_threads()
+    out = {"value": round(gbs, 4), "unit": "GB/s", "cores": cores, "kind": "oracle",
            "sample": sample, "seconds": round(dt, 3)}
     if workload == "hubbard4x4":
         out.update(extra)
@@ -355,8 +376,10 @@ def main():
     if a.workload == "copy_probe":
         copy_probe(a)
         return
-    if a.workload in ("tevol_hubbard16", "tevol_ramp_hubbard16"):
-        out = run_tevol(a, api, W, ramp=a.workload == "tevol_ramp_hubbard16")
+    if a.workload in ("tevol_hubbard16", "tevol_ramp_hubbard16", "tevol_pulse_hubbard16"):
+        mode = {"tevol_hubbard16": "quench", "tevol_ramp_hubbard16": "ramp",
+                "tevol_pulse_hubbard16": "pulse"}[a.workload]
+        out = run_tevol(a, api, W, mode)
         if not a.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline(a.workload, a.cpu_sample_rows)
         print(json.dumps(out), flush=True)
@@ -500,23 +523,32 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def run_tevol(a, api, W, ramp=False):
+def run_tevol(a, api, W, mode="quench"):
     """Real-time evolution after an interaction quench (the example of the
-    paper's real-time section, on 16 sites); with ramp, U(t) rises linearly
-    from 0 to 8 over the warmup and timed steps (a time-dependent H, one
-    frame per step)."""
+    paper's real-time section, on 16 sites). ramp: U(t) rises linearly from
+    0 to 8 over the warmup and timed steps (a time-dependent H, one frame
+    per step). pulse: the U = 4 ground state driven by a light pulse through
+    Peierls phases on the transfers (complex amplitudes, one frame per
+    step, the pulse centred in the timed steps)."""
     import torch
+    ramp = mode != "quench"
     ctx = api.Context(0)
     n, n_max, dt = 16, 10, 0.01
     basis = api.Basis.hubbard(ctx, n, 8, 8)
-    h0 = api.Hamiltonian.hubbard(basis, W.hubbard_chain(n, 1.0, 0.0))
+    u_init = 4.0 if mode == "pulse" else 0.0
+    h0 = api.Hamiltonian.hubbard(basis, W.hubbard_chain(n, 1.0, u_init))
     r = api.lanczos(h0, a.iters or 150, seed=1, want_vector=True)
     psi = r["psi"].to(torch.complex128)
     del r
     h0.close()
-    m8 = W.hubbard_chain(n, 1.0, 8.0)
     n_fr = a.warmup + a.steps + 1
-    fr = W.interaction_ramp(m8, 0.0, 8.0, n_fr - 1, n_fr) if ramp else None
+    if mode == "pulse":
+        m8 = W.hubbard_chain(n, 1.0, 4.0)
+        t_c = dt * (a.warmup + a.steps / 2.0)
+        fr = W.peierls_pulse(m8, 1.0, 6.0, t_c, max(dt, dt * a.steps / 4.0), dt, n_fr)
+    else:
+        m8 = W.hubbard_chain(n, 1.0, 8.0)
+        fr = W.interaction_ramp(m8, 0.0, 8.0, n_fr - 1, n_fr) if ramp else None
     h = api.Hamiltonian.hubbard(basis, m8, frames=fr)
     print("tevol: initial state ready", file=sys.stderr, flush=True)
     api.time_evolve(h, psi, a.warmup, dt=dt, n_max=n_max)
@@ -529,12 +561,16 @@ def run_tevol(a, api, W, ramp=False):
     dim = basis.dim
     alg = 2.0 * 16 * dim * n_max * a.steps          # complex FP64: read v + write w per H*v
     gbs = alg / total / 1e9
-    wl = ("tevol_hubbard_ring16_half_filling_ramp_U0_to_U8" if ramp
-          else "tevol_hubbard_ring16_half_filling_quench_U0_to_U8")
+    wl = {"quench": "tevol_hubbard_ring16_half_filling_quench_U0_to_U8",
+          "ramp": "tevol_hubbard_ring16_half_filling_ramp_U0_to_U8",
+          "pulse": "tevol_hubbard_ring16_half_filling_U4_peierls_pulse"}[mode]
     cfg = {"workload": wl, "dim": dim, "n_max": n_max, "dt": dt, "steps": a.steps,
-           "initial": "U = 0 ground state (Lanczos)"}
-    if ramp:
+           "initial": f"U = {u_init:g} ground state (Lanczos)"}
+    if mode == "ramp":
         cfg.update({"frames": n_fr, "ramp": f"U(t_k) = 8 k / {n_fr - 1}, one frame per step"})
+    if mode == "pulse":
+        cfg.update({"frames": n_fr, "pulse": "t_ij e^{i A(t)(x_i - x_j)}, A(t) = exp(-(t - t_c)^2 / 2 s^2) "
+                                             "cos(6 (t - t_c)), t_c at the middle of the timed steps"})
     out = base_line(a, gbs, 1e3 * total / a.steps, "c128", cfg)
     out.update({"hbm_peak_frac": round(gbs / HBM_PEAK_GBS, 4), "time_steps_per_s": round(a.steps / total, 4),
                 "hv_per_step": n_max,
@@ -544,13 +580,14 @@ def run_tevol(a, api, W, ramp=False):
                 "roofline": roofline(gbs, 2.0 * 16 * dim,
                                      "complex H*v = Hubbard rows + cols kernels, complex epilogue "
                                      "(rate from wall time of whole steps)")})
-    if ramp:
+    if mode == "ramp":
         # exact evolution under H(t_k) conserves <H(t_k)>: the energy steps
         # by the work (U_k+1 - U_k) N_s <D>(t_k+1)
         u = fr.u_site[a.warmup:a.warmup + a.steps + 1, 0]
         de = np.diff(g["energy"][:, 0])
         work = np.diff(u) * n * np.asarray(g["double_occupancy"][1:])
         out["ramp_work_residual"] = float(np.max(np.abs(de - work)))
+    if ramp:
         out["energy_last"] = float(g["energy"][-1, 0])
         # the same steps with the last frame held (no frame switches)
         torch.cuda.synchronize()

@@ -234,13 +234,21 @@ int hphi_ham_hubbard_ext(hphi_basis *b, const hphi_hop *hops, int n_hops,
  * and pair-hopping coefficients of the terms given at build). Frame k holds
  * every amplitude at one time; the terms themselves (sites, kinds) are fixed.
  * Host arrays, row-major, read during the build only:
- *   hop_t   [n_frames][n_hops]  t of each hop, in the order of hops
- *   u_site  [n_frames][n_sites] U_i
- *   pair_v  [n_frames][n_pairs][4] v, j_hund, j_ex, j_pair of each pair term
- * A NULL array keeps the build arguments' values in every frame. */
+ *   hop_t     [n_frames][n_hops]  t of each hop, in the order of hops
+ *   hop_t_im  [n_frames][n_hops]  imaginary parts: the hop term becomes
+ *             -(t c+_i c_j + t* c+_j c_i), t = hop_t + i hop_t_im (Peierls
+ *             phases of a vector potential, fluxes)
+ *   u_site    [n_frames][n_sites] U_i
+ *   pair_v    [n_frames][n_pairs][4] v, j_hund, j_ex, j_pair of each pair term
+ * A NULL array keeps the build arguments' values in every frame (hop_t_im:
+ * zero). A Hamiltonian with a nonzero imaginary part in any frame acts on
+ * complex vectors only: hphi_mult with C128/C64, hphi_time_evolve and
+ * hphi_ctpq; the real-vector methods return UNSUPPORTED, and so does
+ * hphi_sqw (its COCG needs a complex-symmetric z - H). */
 typedef struct {
     int n_frames;          /* 1 .. 65536                                     */
     const double *hop_t;
+    const double *hop_t_im;
     const double *u_site;
     const double *pair_v;
 } hphi_hub_frames;
@@ -251,12 +259,15 @@ typedef struct {
  * deduplicated per kind); each distinct set of pair values holds
  * (dim_up + dim_dn) doubles of same-species diagonal on the device. Hops
  * keep the uniform-|t| kernels when t_k(frame) = s_k tau(frame) with one
- * sign s_k per hop in every frame; U keeps the uniform kernels when every
- * frame's U_i are equal. hphi_time_evolve steps through the frames;
+ * sign s_k per hop in every frame and no imaginary part; U keeps the
+ * uniform kernels when every frame's U_i are equal. n_frames = 1 builds a
+ * fixed Hamiltonian (e.g. with complex transfers). hphi_time_evolve steps
+ * through the frames;
  * hphi_ham_set_frame selects one for every other call.
  * Errors: INVALID_ARG (null frames, n_frames outside [1, 65536], no array
  * given, hop_t without hops, pair_v without pair terms, a non-finite value,
- * more than 127 distinct hop trajectories, and hphi_ham_hubbard_ext's
+ * more than 126 distinct matrix-element trajectories (a complex transfer
+ * counts twice), and hphi_ham_hubbard_ext's
  * conditions), OUT_OF_MEMORY, DEVICE. */
 int hphi_ham_hubbard_td(hphi_basis *b, const hphi_hop *hops, int n_hops,
                         const double *u_site, const hphi_pair_term *pairs, int n_pairs,

@@ -33,8 +33,8 @@ class PairTerm(C.Structure):
 
 
 class HubFrames(C.Structure):
-    _fields_ = [("n_frames", C.c_int), ("hop_t", C.POINTER(C.c_double)), ("u_site", C.POINTER(C.c_double)),
-                ("pair_v", C.POINTER(C.c_double))]
+    _fields_ = [("n_frames", C.c_int), ("hop_t", C.POINTER(C.c_double)), ("hop_t_im", C.POINTER(C.c_double)),
+                ("u_site", C.POINTER(C.c_double)), ("pair_v", C.POINTER(C.c_double))]
 
 
 class LanczosOpts(C.Structure):

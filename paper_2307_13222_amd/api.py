@@ -218,6 +218,12 @@ class Hamiltonian:
         for k in range(n_pairs):
             pa[k] = L.PairTerm(int(m.pi[k]), int(m.pj[k]), float(m.pv[k]), float(m.pjh[k]),
                                float(m.pjx[k]), float(m.pjp[k]))
+        t_im = getattr(m, "t_im", None)
+        if frames is None and t_im is not None and np.any(np.asarray(t_im) != 0.0):
+            # complex transfers: one frame holding them
+            from .workloads import HubbardFrames
+            frames = HubbardFrames(1, hop_t=np.asarray(m.t, dtype=np.float64)[None, :],
+                                   hop_t_im=np.asarray(t_im, dtype=np.float64)[None, :])
         if frames is not None:
             keep = []
 
@@ -227,7 +233,11 @@ class Hamiltonian:
                 a = np.ascontiguousarray(x, dtype=np.float64)
                 keep.append(a)
                 return a.ctypes.data_as(L.PD)
-            fr = L.HubFrames(int(frames.n_frames), arr2(frames.hop_t), arr2(frames.u_site), arr2(frames.pair_v))
+            hop_t_im = getattr(frames, "hop_t_im", None)
+            if hop_t_im is None and t_im is not None:
+                hop_t_im = np.tile(np.asarray(t_im, dtype=np.float64)[None, :], (int(frames.n_frames), 1))
+            fr = L.HubFrames(int(frames.n_frames), arr2(frames.hop_t), arr2(hop_t_im), arr2(frames.u_site),
+                             arr2(frames.pair_v))
             _check(L.lib().hphi_ham_hubbard_td(basis.h, arr, m.n_hops, us.ctypes.data_as(L.PD), pa, n_pairs,
                                                C.byref(fr), C.byref(h)), "hphi_ham_hubbard_td")
         elif n_pairs:

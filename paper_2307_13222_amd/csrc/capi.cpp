@@ -254,8 +254,11 @@ int hphi_ham_spin(hphi_basis *b, const hphi_spin_bond *bonds, int n_bonds, const
 // and transfer (i, j) with exactly one of i, j occupied, the target
 // s ^ (1<<i | 1<<j), value -t and sign (-1)^(occupied sites strictly
 // between i and j).
+// hop_cls_i / hop_cls_j: value class of hop k in a row whose state holds
+// site i / site j of the hop (the same class for real transfers)
 static int build_hub_species(const Species &sp, const std::vector<hphi_hop> &hops,
-                             const std::vector<int> &hop_cls, DevMem &off_d, DevMem &nbr_d, int64_t &max_deg,
+                             const std::vector<int> &hop_cls_i, const std::vector<int> &hop_cls_j, DevMem &off_d,
+                             DevMem &nbr_d, int64_t &max_deg,
                              DevMem &sell_base_d, DevMem &sell_width_d, DevMem &sell_d)
 {
     std::vector<uint32_t> off((size_t)sp.dim + 1, 0);
@@ -274,7 +277,7 @@ static int build_hub_species(const Species &sp, const std::vector<hphi_hop> &hop
             const uint64_t between = (hi - lo > 1) ? (((uint64_t(1) << hi) - 1) & ~((uint64_t(1) << (lo + 1)) - 1)) : 0;
             const uint32_t sign = (uint32_t)(__builtin_popcountll(s & between) & 1);
             const int64_t tr = sp.rank_of(t);
-            const int cls = hop_cls[hk];
+            const int cls = bi ? hop_cls_i[hk] : hop_cls_j[hk];
             ent.push_back((uint32_t)tr | ((uint32_t)cls << 24) | (sign << 31));
         }
         max_deg = std::max<int64_t>(max_deg, (int64_t)ent.size() - off[r]);
@@ -799,9 +802,10 @@ static int make_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops, const d
     if (fr) {
         if (fr->n_frames < 1 || fr->n_frames > kMaxFrames)
             return fail(HPHI_ERR_INVALID_ARG, "n_frames %d outside [1, %d]", fr->n_frames, kMaxFrames);
-        if (!fr->hop_t && !fr->u_site && !fr->pair_v)
-            return fail(HPHI_ERR_INVALID_ARG, "frames without hop_t, u_site or pair_v");
-        if (fr->hop_t && n_hops == 0) return fail(HPHI_ERR_INVALID_ARG, "hop_t frames without hops");
+        if (!fr->hop_t && !fr->hop_t_im && !fr->u_site && !fr->pair_v)
+            return fail(HPHI_ERR_INVALID_ARG, "frames without hop_t, hop_t_im, u_site or pair_v");
+        if ((fr->hop_t || fr->hop_t_im) && n_hops == 0)
+            return fail(HPHI_ERR_INVALID_ARG, "hop_t / hop_t_im frames without hops");
         if (fr->pair_v && n_pairs == 0) return fail(HPHI_ERR_INVALID_ARG, "pair_v frames without pair terms");
     }
     const int F = fr ? fr->n_frames : 1;
@@ -818,8 +822,13 @@ static int make_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops, const d
     // amplitudes by frame, grouped into slots per kind
     std::vector<int> hop_slot, u_slot, pair_slot;
     std::vector<double> hop_v, u_v, pair_v;
-    HPHI_TRY(frame_slots(F, (size_t)n_hops,
-                         [&](int f, size_t k) { return fr && fr->hop_t ? fr->hop_t[(size_t)f * n_hops + k] : hops[k].t; },
+    // hop values of a slot: n_hops real parts, then n_hops imaginary parts
+    HPHI_TRY(frame_slots(F, 2 * (size_t)n_hops,
+                         [&](int f, size_t c) {
+                             if (c < (size_t)n_hops)
+                                 return fr && fr->hop_t ? fr->hop_t[(size_t)f * n_hops + c] : hops[c].t;
+                             return fr && fr->hop_t_im ? fr->hop_t_im[(size_t)f * n_hops + (c - n_hops)] : 0.0;
+                         },
                          hop_slot, hop_v));
     HPHI_TRY(frame_slots(F, (size_t)ns,
                          [&](int f, size_t i) { return fr && fr->u_site ? fr->u_site[(size_t)f * ns + i] : u_site[i]; },
@@ -832,31 +841,54 @@ static int make_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops, const d
                              return x[c % 4];
                          },
                          pair_slot, pair_v));
-    const int nhs = n_hops > 0 ? (int)(hop_v.size() / n_hops) : 1;
+    const int nhs = n_hops > 0 ? (int)(hop_v.size() / (2 * (size_t)n_hops)) : 1;
     const int nus = (int)(u_v.size() / ns);
     const int nps = n_pairs > 0 ? (int)(pair_v.size() / (4 * (size_t)n_pairs)) : 1;
-    auto hop_at = [&](int slot, int k) { return hop_v[(size_t)slot * n_hops + k]; };
-    // value classes: hops with equal amplitudes in every slot share one
+    auto hop_at = [&](int slot, int k) { return hop_v[(size_t)slot * 2 * n_hops + k]; };
+    auto hop_im = [&](int slot, int k) { return hop_v[(size_t)slot * 2 * n_hops + n_hops + k]; };
+    bool cplx = false;
+    for (int s = 0; s < nhs; ++s)
+        for (int k = 0; k < n_hops; ++k)
+            if (hop_im(s, k) != 0.0) cplx = true;
+    // value classes: matrix elements equal in every slot share one. A row
+    // whose state holds site i of hop k takes -t_k, one that holds site j
+    // takes -conj(t_k): one class for real transfers, two otherwise.
     std::map<std::vector<double>, int> classes;
-    std::vector<int> hop_cls(n_hops), cls_rep;
-    for (int k = 0; k < n_hops; ++k) {
-        std::vector<double> key(nhs);
-        for (int s = 0; s < nhs; ++s) key[s] = -hop_at(s, k);
+    std::vector<int> cls_i(n_hops), cls_j(n_hops);
+    std::vector<std::vector<double>> cls_val;   // per class: (re, im) per slot
+    auto class_of = [&](const std::vector<double> &key, int &out) -> int {
         auto it = classes.find(key);
         if (it == classes.end()) {
             const int c = (int)classes.size();
-            if (c >= (int)kZeroClass) return fail(HPHI_ERR_INVALID_ARG, "more than 127 distinct transfer values");
+            if (c >= (int)kZeroClass) return fail(HPHI_ERR_INVALID_ARG, "more than 126 distinct transfer values");
             it = classes.emplace(key, c).first;
-            cls_rep.push_back(k);
+            cls_val.push_back(key);
         }
-        hop_cls[k] = it->second;
+        out = it->second;
+        return HPHI_OK;
+    };
+    for (int k = 0; k < n_hops; ++k) {
+        std::vector<double> ki(2 * (size_t)nhs), kj(2 * (size_t)nhs);
+        for (int s = 0; s < nhs; ++s) {
+            ki[2 * s] = kj[2 * s] = -hop_at(s, k);
+            ki[2 * s + 1] = -hop_im(s, k);
+            kj[2 * s + 1] = hop_im(s, k);
+        }
+        HPHI_TRY(class_of(ki, cls_i[k]));
+        if (cplx) HPHI_TRY(class_of(kj, cls_j[k]));
+        else cls_j[k] = cls_i[k];
     }
-    std::vector<double> coef((size_t)nhs * 128, 0.0);
+    // per slot: 128 real parts, then 128 imaginary parts
+    std::vector<double> coef((size_t)nhs * 256, 0.0);
     for (int s = 0; s < nhs; ++s)
-        for (size_t c = 0; c < cls_rep.size(); ++c) coef[(size_t)s * 128 + c] = -hop_at(s, cls_rep[c]);
+        for (size_t c = 0; c < cls_val.size(); ++c) {
+            coef[(size_t)s * 256 + c] = cls_val[c][2 * s];
+            coef[(size_t)s * 256 + 128 + c] = cls_val[c][2 * s + 1];
+        }
     h->hub.n_coef = (int)classes.size();
+    h->hub.cplx = cplx;
     // uniform magnitude: t_k = sg_k tau(slot) in every slot, one sign per hop
-    bool uni = n_hops > 0 && b->sp[1].dim < 65535 &&
+    bool uni = n_hops > 0 && !cplx && b->sp[1].dim < 65535 &&
                (unsigned __int128)b->sp[0].dim * (unsigned __int128)b->sp[1].dim * 2 < ((unsigned __int128)1 << 32);
     std::vector<double> tau(nhs, 0.0);
     std::vector<double> sg(n_hops, 1.0);
@@ -883,7 +915,8 @@ static int make_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops, const d
         h->hops[k].t = hop_at(hop_slot[0], k);
         if (uni) h->hops_split[k].t = sg[k] * std::fabs(tau[ref]);
     }
-    HPHI_TRY(upload(h->hub.coef, coef.data() + (size_t)hop_slot[0] * 128, sizeof(double) * 128));
+    HPHI_TRY(upload(h->hub.coef, coef.data() + (size_t)hop_slot[0] * 256, sizeof(double) * 128));
+    if (cplx) HPHI_TRY(upload(h->hub.coef_im, coef.data() + (size_t)hop_slot[0] * 256 + 128, sizeof(double) * 128));
     const double *u0v = u_v.data() + (size_t)u_slot[0] * ns;
     h->u_site.assign(u0v, u0v + ns);
     HPHI_TRY(upload(h->hub.u_site, u0v, sizeof(double) * ns));
@@ -893,7 +926,7 @@ static int make_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops, const d
             if (u_v[(size_t)s * ns + i] != u_v[(size_t)s * ns]) h->hub.uniform_u = false;
     h->hub.u0 = u0v[0];
     for (int sgm = 0; sgm < 2; ++sgm)
-        HPHI_TRY(build_hub_species(b->sp[sgm], h->hops, hop_cls, h->hub.off[sgm], h->hub.nbr[sgm],
+        HPHI_TRY(build_hub_species(b->sp[sgm], h->hops, cls_i, cls_j, h->hub.off[sgm], h->hub.nbr[sgm],
                                    h->hub.max_deg[sgm], h->hub.sell_base[sgm], h->hub.sell_width[sgm],
                                    h->hub.sell[sgm]));
     // uniform-magnitude transfers: the sign-split fast path
@@ -991,10 +1024,13 @@ int ham_apply_frame(hphi_ham *h, int k, hipStream_t st)
     const int ns = b->n_sites, nh = (int)h->hops.size(), np = h->hub.n_pairs;
     const int hs = T.hop_slot[k], us = T.u_slot[k], ps = T.pair_slot[k];
     if (hs != T.cur_hop) {
-        HPHI_HIP(hipMemcpyAsync(h->hub.coef.p, T.coef.as<double>() + (size_t)hs * 128, sizeof(double) * 128,
+        HPHI_HIP(hipMemcpyAsync(h->hub.coef.p, T.coef.as<double>() + (size_t)hs * 256, sizeof(double) * 128,
                                 hipMemcpyDeviceToDevice, st));
+        if (h->hub.cplx)
+            HPHI_HIP(hipMemcpyAsync(h->hub.coef_im.p, T.coef.as<double>() + (size_t)hs * 256 + 128,
+                                    sizeof(double) * 128, hipMemcpyDeviceToDevice, st));
         if (h->hub.uniform_t) h->hub.t0 = T.tau[hs];
-        for (int q = 0; q < nh; ++q) h->hops[q].t = T.hop_t[(size_t)hs * nh + q];
+        for (int q = 0; q < nh; ++q) h->hops[q].t = T.hop_t[(size_t)hs * 2 * nh + q];
         T.cur_hop = hs;
     }
     if (us != T.cur_u) {

@@ -472,6 +472,8 @@ int hphi_sqw(hphi_ham *h, const hphi_sqw_opts *o, const void *b_dev, const doubl
     if (n_shift < 1 || n_shift > 4096) return fail(HPHI_ERR_INVALID_ARG, "n_shift %d outside [1, 4096]", n_shift);
     if (o->max_iter < 1) return fail(HPHI_ERR_INVALID_ARG, "max_iter < 1");
     if (o->seed_shift >= n_shift) return fail(HPHI_ERR_INVALID_ARG, "seed_shift out of range");
+    if (h->kind == 1 && h->hub.cplx)
+        return fail(HPHI_ERR_UNSUPPORTED, "complex transfers: z - H is not complex symmetric (COCG)");
     DeviceGuard g(h->basis->ctx->device);
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = (hipStream_t)o->stream;
@@ -597,6 +599,8 @@ int hphi_sqw_batch(hphi_ham *const *hams, int n, const hphi_sqw_opts *o, const v
         if (!hams[i] || !b_devs[i]) return fail(HPHI_ERR_INVALID_ARG, "request %d: null Hamiltonian or b", i);
         if (hams[i]->basis->ctx != hams[0]->basis->ctx)
             return fail(HPHI_ERR_INVALID_ARG, "requests on different contexts");
+        if (hams[i]->kind == 1 && hams[i]->hub.cplx)
+            return fail(HPHI_ERR_UNSUPPORTED, "request %d: complex transfers (COCG needs a complex-symmetric z - H)", i);
     }
     DeviceGuard g(hams[0]->basis->ctx->device);
     auto t0 = std::chrono::steady_clock::now();

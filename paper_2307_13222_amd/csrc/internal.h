@@ -238,7 +238,9 @@ struct HubTables {
     // per site k the pairs' other ends and V: the cross weights
     // m_k(u) = sum V u_other (site_off [n_sites + 1], site_nbr PairNbrDev)
     DevMem pair_site_off, pair_site_nbr;
-    DevMem coef;     // double [128]: -t per value class
+    DevMem coef;     // double [128]: -t per value class (real parts)
+    DevMem coef_im;  // double [128]: imaginary parts (complex transfers only)
+    bool cplx = false;   // some transfer has an imaginary part: complex vectors only
     DevMem u_site;   // double [n_sites]
     int n_coef = 0;
     bool uniform_u = true;
@@ -255,11 +257,11 @@ struct HubFrames {
     int n = 0, cur = 0;
     std::vector<int> hop_slot, u_slot, pair_slot;   // [n]
     int cur_hop = 0, cur_u = 0, cur_pair = 0;
-    std::vector<double> hop_t;     // [hop slots][n_hops]
+    std::vector<double> hop_t;     // [hop slots][2][n_hops]: real parts, then imaginary parts
     std::vector<double> tau;       // [hop slots] t0 of the uniform-|t| path
     std::vector<double> u_site;    // [u slots][n_sites]
     std::vector<double> pair_v;    // [pair slots][n_pairs][4]: v, j_hund, j_ex, j_pair
-    DevMem coef;                   // double [hop slots][128]
+    DevMem coef;                   // double [hop slots][256]: class values, real then imaginary
     DevMem u;                      // double [u slots][n_sites]
     DevMem pairs, nbr, eup, edn;   // per pair slot: records, site lists, same-species diagonals
     size_t nbr_n = 0;              // site-list entries per slot

@@ -58,6 +58,7 @@ struct HubKArgs {
     const uint32_t *fb_ent;
     const uint32_t *fc_ent;   // pre-scaled slot words for this element size (or null)
     double t0;
+    const double *coef_im;   // imaginary parts of the class values (complex transfers; null: real)
     int coef_cplx;
     int hb;                // column kernel: batched list walk, one wave per row
     // Lanczos update fused into the rows kernel (null lz_q: none)
@@ -101,14 +102,20 @@ __device__ __forceinline__ S entry_val(uint32_t e, const S *coef)
 // ---------------------------------------------------------------- rows --
 // One workgroup per r_up (grid-stride). NV = 1 (real) or 2 (complex).
 // Thread t handles columns t, t + blockDim, ...: a wave covers one aligned
-// 64-column chunk of the sliced-ELL table.
-template <typename S, int NV, bool LDS_ROW>
+// 64-column chunk of the sliced-ELL table. CPLX (NV = 2): complex class
+// values (c_re + i c_im) times the complex vector.
+template <typename S, int NV, bool LDS_ROW, bool CPLX = false>
 __global__ __launch_bounds__(1024) void k_hub_rows(HubKArgs a)
 {
+    static_assert(!CPLX || NV == 2, "complex coefficients need complex vectors");
     extern __shared__ unsigned char smem_raw[];
     S *s_coef = reinterpret_cast<S *>(smem_raw);
-    S *s_row = s_coef + 128;
-    for (int i = threadIdx.x; i < 128; i += blockDim.x) s_coef[i] = (S)a.coef[i];
+    S *s_coef_im = s_coef + 128;
+    S *s_row = s_coef + (CPLX ? 256 : 128);
+    for (int i = threadIdx.x; i < 128; i += blockDim.x) {
+        s_coef[i] = (S)a.coef[i];
+        if constexpr (CPLX) s_coef_im[i] = (S)a.coef_im[i];
+    }
     const S *__restrict__ v = static_cast<const S *>(a.v);
     S *__restrict__ w = static_cast<S *>(a.w);
     const int64_t ddn = a.ddn;
@@ -140,16 +147,30 @@ __global__ __launch_bounds__(1024) void k_hub_rows(HubKArgs a)
                 for (int t = 0; t < 16; ++t) {
                     const S val = entry_val<S>(e[t], s_coef);
                     const uint32_t col = e[t] & kNbrColMask;
+                    if constexpr (CPLX) {
+                        const S vi = entry_val<S>(e[t], s_coef_im);
+                        const S x0 = row[(size_t)col * 2], x1 = row[(size_t)col * 2 + 1];
+                        acc[0] += val * x0 - vi * x1;
+                        acc[1] += val * x1 + vi * x0;
+                    } else {
 #pragma unroll
-                    for (int j = 0; j < NV; ++j) acc[j] += val * row[(size_t)col * NV + j];
+                        for (int j = 0; j < NV; ++j) acc[j] += val * row[(size_t)col * NV + j];
+                    }
                 }
             }
             for (; k < width; ++k) {
                 const uint32_t e = ent[(size_t)k * 64];
                 const S val = entry_val<S>(e, s_coef);
                 const uint32_t col = e & kNbrColMask;
+                if constexpr (CPLX) {
+                    const S vi = entry_val<S>(e, s_coef_im);
+                    const S x0 = row[(size_t)col * 2], x1 = row[(size_t)col * 2 + 1];
+                    acc[0] += val * x0 - vi * x1;
+                    acc[1] += val * x1 + vi * x0;
+                } else {
 #pragma unroll
-                for (int j = 0; j < NV; ++j) acc[j] += val * row[(size_t)col * NV + j];
+                    for (int j = 0; j < NV; ++j) acc[j] += val * row[(size_t)col * NV + j];
+                }
             }
 #pragma unroll
             for (int j = 0; j < NV; ++j) __builtin_nontemporal_store(acc[j], &w[((size_t)ru * ddn + c) * NV + j]);
@@ -172,16 +193,21 @@ __global__ __launch_bounds__(1024) void k_hub_rows(HubKArgs a)
 // identical. That workgroup also re-arms the queues.
 __device__ __forceinline__ int xcc_id() { return (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7u); }
 
-template <typename S, int NV, int CW, bool DOTS>
+template <typename S, int NV, int CW, bool DOTS, bool CPLX = false>
 __global__ __launch_bounds__(256) void k_hub_cols(HubKArgs a)
 {
+    static_assert(!CPLX || NV == 2, "complex coefficients need complex vectors");
     __shared__ S s_coef[128];
+    __shared__ S s_coef_im[CPLX ? 128 : 1];
     __shared__ double sh_red[4 * 2 * NV + 8];
     __shared__ uint32_t s_ent[kColsLdsEntries];
     __shared__ uint32_t s_off[kColsRows + 1];
     __shared__ int s_item;
     __shared__ unsigned s_last;
-    for (int i = threadIdx.x; i < 128; i += blockDim.x) s_coef[i] = (S)a.coef[i];
+    for (int i = threadIdx.x; i < 128; i += blockDim.x) {
+        s_coef[i] = (S)a.coef[i];
+        if constexpr (CPLX) s_coef_im[i] = (S)a.coef_im[i];
+    }
     const int home = xcc_id();
     const S *__restrict__ v = static_cast<const S *>(a.v);
     S *__restrict__ w = static_cast<S *>(a.w);
@@ -249,27 +275,41 @@ __global__ __launch_bounds__(256) void k_hub_cols(HubKArgs a)
             constexpr int GB = NV == 1 ? 32 : 16;
             for (; e < e1; e += GB) {
                 S nv[GB][NV];
-                S val[GB];
+                S val[GB], vim[CPLX ? GB : 1];
 #pragma unroll
                 for (int t = 0; t < GB; ++t) {
                     const bool ok = e + t < e1;
                     const uint32_t ent = s_ent[ok ? e + t : e];
                     val[t] = ok ? entry_val<S>(ent, s_coef) : (S)0;
+                    if constexpr (CPLX) vim[t] = ok ? entry_val<S>(ent, s_coef_im) : (S)0;
                     const size_t src = (size_t)(ent & kNbrColMask) * ddn + col;
 #pragma unroll
                     for (int j = 0; j < NV; ++j) nv[t][j] = ok ? v[src * NV + j] : (S)0;
                 }
 #pragma unroll
-                for (int t = 0; t < GB; ++t)
+                for (int t = 0; t < GB; ++t) {
+                    if constexpr (CPLX) {
+                        acc[0] += val[t] * nv[t][0] - vim[t] * nv[t][1];
+                        acc[1] += val[t] * nv[t][1] + vim[t] * nv[t][0];
+                    } else {
 #pragma unroll
-                    for (int j = 0; j < NV; ++j) acc[j] += val[t] * nv[t][j];
+                        for (int j = 0; j < NV; ++j) acc[j] += val[t] * nv[t][j];
+                    }
+                }
             }
             for (; e < e1; ++e) {
                 const uint32_t ent = s_ent[e];
                 const S val = entry_val<S>(ent, s_coef);
                 const size_t src = (size_t)(ent & kNbrColMask) * ddn + col;
+                if constexpr (CPLX) {
+                    const S vi = entry_val<S>(ent, s_coef_im);
+                    const S x0 = v[src * 2], x1 = v[src * 2 + 1];
+                    acc[0] += val * x0 - vi * x1;
+                    acc[1] += val * x1 + vi * x0;
+                } else {
 #pragma unroll
-                for (int j = 0; j < NV; ++j) acc[j] += val * v[src * NV + j];
+                    for (int j = 0; j < NV; ++j) acc[j] += val * v[src * NV + j];
+                }
             }
             S out[NV], raw[NV];
 #pragma unroll
@@ -1545,6 +1585,13 @@ __global__ __launch_bounds__(1024) void k_hub_up_tile(HubKArgs a)
 template <typename S, int NV, int CW>
 static void launch_cols_t(const HubKArgs &a, int grid, hipStream_t st)
 {
+    if constexpr (NV == 2) {
+        if (a.coef_im) {
+            if (a.nd) hipLaunchKernelGGL((k_hub_cols<S, 2, CW, true, true>), dim3(grid), dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((k_hub_cols<S, 2, CW, false, true>), dim3(grid), dim3(256), 0, st, a);
+            return;
+        }
+    }
     if (a.nd) hipLaunchKernelGGL((k_hub_cols<S, NV, CW, true>), dim3(grid), dim3(256), 0, st, a);
     else hipLaunchKernelGGL((k_hub_cols<S, NV, CW, false>), dim3(grid), dim3(256), 0, st, a);
 }
@@ -1630,7 +1677,8 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
 {
     const int ncu = h->basis->ctx->n_cu > 0 ? h->basis->ctx->n_cu : 256;
     // rows kernel
-    size_t row_bytes = (size_t)a.ddn * NV * sizeof(S) + 128 * sizeof(S);
+    const bool cx = NV == 2 && a.coef_im;   // complex class values
+    size_t row_bytes = (size_t)a.ddn * NV * sizeof(S) + (cx ? 256 : 128) * sizeof(S);
     bool lds_row = row_bytes <= 160 * 1024;
     int per_cu = lds_row ? (int)((160 * 1024) / row_bytes) : 4;
     if (per_cu < 1) per_cu = 1;
@@ -1713,6 +1761,18 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
         hipFuncSetAttribute((const void *)k_hub_rows_f<S, NV>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)fast_row_bytes);
         hipLaunchKernelGGL((k_hub_rows_f<S, NV>), dim3((unsigned)grid_r), dim3(threads), fast_row_bytes, st, a);
+    } else if (cx) {
+        if constexpr (NV == 2) {
+            if (lds_row) {
+                hipFuncSetAttribute((const void *)k_hub_rows<S, 2, true, true>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)row_bytes);
+                hipLaunchKernelGGL((k_hub_rows<S, 2, true, true>), dim3((unsigned)grid_r), dim3(threads),
+                                   row_bytes, st, a);
+            } else {
+                hipLaunchKernelGGL((k_hub_rows<S, 2, false, true>), dim3((unsigned)grid_r), dim3(threads),
+                                   256 * sizeof(S), st, a);
+            }
+        }
     } else if (lds_row) {
         hipFuncSetAttribute((const void *)k_hub_rows<S, NV, true>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)row_bytes);
@@ -1864,6 +1924,7 @@ int launch_hub_mult(hphi_ham *h, const MultArgs &m)
     a.fb_w = h->hub.fb_w.as<uint32_t>();
     a.fb_ent = h->hub.fb_ent.as<uint32_t>();
     a.t0 = h->hub.t0;
+    a.coef_im = h->hub.cplx ? h->hub.coef_im.as<double>() : nullptr;
     a.coef_cplx = m.coef_cplx;
     a.lz = m.lz;
     a.lz_alpha = m.lz_alpha;
@@ -1875,6 +1936,8 @@ int launch_hub_mult(hphi_ham *h, const MultArgs &m)
     if (a.ld < a.ddn) return fail(HPHI_ERR_INVALID_ARG, "row pitch %lld below the row length", (long long)a.ld);
     const int nv = m.nvec * dtype_lanes(m.dtype);
     const bool f32 = dtype_is_f32(m.dtype);
+    if (h->hub.cplx && dtype_lanes(m.dtype) != 2)
+        return fail(HPHI_ERR_UNSUPPORTED, "complex transfer amplitudes act on complex vectors only");
     if (nv == 1) return f32 ? launch_hub_t<float, 1>(h, a, m.stream) : launch_hub_t<double, 1>(h, a, m.stream);
     if (nv == 2) return f32 ? launch_hub_t<float, 2>(h, a, m.stream) : launch_hub_t<double, 2>(h, a, m.stream);
     return fail(HPHI_ERR_UNSUPPORTED, "Hubbard H*v supports one real or one complex vector per call");
