@@ -178,6 +178,73 @@ __global__ __launch_bounds__(1024) void k_hub_rows(HubKArgs a)
     }
 }
 
+// Complex class values (complex transfers) on complex vectors whose whole
+// row exceeds LDS: the row is staged one lane at a time. With class values
+// A + iB, the re lane gives A x_re to the real part and B x_re to the
+// imaginary part of W, the im lane A x_im to the imaginary and -B x_im to
+// the real part: the re lane writes the row of W, the im lane adds to it
+// (the row, 2 x ddn values, stays in L2 between the lanes).
+template <typename S>
+__global__ __launch_bounds__(1024) void k_hub_rows_cl(HubKArgs a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    S *s_coef = reinterpret_cast<S *>(smem_raw);
+    S *s_coef_im = s_coef + 128;
+    S *s_row = s_coef + 256;
+    for (int i = threadIdx.x; i < 128; i += blockDim.x) {
+        s_coef[i] = (S)a.coef[i];
+        s_coef_im[i] = (S)a.coef_im[i];
+    }
+    const S *__restrict__ v = static_cast<const S *>(a.v);
+    S *__restrict__ w = static_cast<S *>(a.w);
+    const int64_t ddn = a.ddn;
+    const int T = blockDim.x, tid = threadIdx.x;
+    for (int64_t ru = blockIdx.x; ru < a.dup; ru += gridDim.x) {
+        const S *vrow = v + (size_t)ru * ddn * 2;
+        S *wrow = w + (size_t)ru * ddn * 2;
+        const uint32_t uu = a.ups[ru];
+        for (int ln = 0; ln < 2; ++ln) {
+            __syncthreads();   // the previous lane's (or row's) gathers have finished
+            for (int64_t i = tid; i < ddn; i += T) s_row[i] = vrow[2 * i + ln];
+            __syncthreads();
+            for (int64_t c = tid; c < ddn; c += T) {
+                const int64_t ch = c >> 6;
+                const uint32_t *ent = a.sell_dn + a.sell_base_dn[ch] + (c & 63);
+                const uint32_t width = a.sell_width_dn[ch];
+                S sa = (S)0, sb = (S)0;
+                uint32_t k = 0;
+                // eight table loads in flight, then the LDS gathers
+                for (; k + 8 <= width; k += 8) {
+                    uint32_t en[8];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) en[t] = ent[(size_t)(k + t) * 64];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        const S x = s_row[en[t] & kNbrColMask];
+                        sa += entry_val<S>(en[t], s_coef) * x;
+                        sb += entry_val<S>(en[t], s_coef_im) * x;
+                    }
+                }
+                for (; k < width; ++k) {
+                    const uint32_t en = ent[(size_t)k * 64];
+                    const S x = s_row[en & kNbrColMask];
+                    sa += entry_val<S>(en, s_coef) * x;
+                    sb += entry_val<S>(en, s_coef_im) * x;
+                }
+                const S dx = hub_diag<S>(a, uu, a.dns[c]) * s_row[c];
+                if (ln == 0) {
+                    wrow[2 * c] = dx + sa;
+                    wrow[2 * c + 1] = sb;
+                } else {
+                    // the same thread wrote this element in the re lane
+                    wrow[2 * c] = wrow[2 * c] - sb;
+                    wrow[2 * c + 1] = wrow[2 * c + 1] + (dx + sa);
+                }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- cols --
 // Persistent grid. A work item is (slab, chunk of kColsRows rows); XCD x
 // owns the slabs x, x + 8, x + 16, ... and hands out its items in slab
@@ -1429,22 +1496,47 @@ __global__ __launch_bounds__(1024) void k_hub_up_tile(HubKArgs a)
         __syncthreads();
         double dv = 0.0, dd = 0.0;
         // software pipeline over this thread's rows of the block: a row's
-        // position data are loaded one pass ahead; its epilogue operands
-        // and all of its entry groups are issued together, then the local
-        // reads (LDS) and the far gathers, so a pass waits on two rounds of
-        // memory latency
+        // position data are loaded two passes ahead and its far entries one
+        // pass ahead; a pass issues its far gathers, epilogue operands and
+        // local entry groups together, then reads the local hops from LDS
         uint32_t lr_n = 0, cnt_n = 0, off_n = 0;
         if (slot < nr) {
             lr_n = a.ft_pos[r0 + slot];
             cnt_n = a.ft_cnt[r0 + slot];
             off_n = a.ft_off[r0 + slot];
         }
+        // a row's far entries are loaded one pass ahead (its position data
+        // two passes ahead), so a pass issues its far gathers at once
+        uint32_t lr_nn = 0, cnt_nn = 0, off_nn = 0;
+        uint4 fe_n[kTileFar / 4];
+        auto load_far = [&](uint32_t c, uint32_t o, uint4 *dst) {
+            const uint32_t nlc = (c & 255u) + ((c >> 8) & 255u), nfc = ((c >> 16) & 255u) + (c >> 24);
+            const uint32_t glc = (nlc + 7) >> 3, gfc = (nfc + 3) >> 2;
+#pragma unroll
+            for (int g = 0; g < kTileFar / 4; ++g) {
+                dst[g] = make_uint4(0u, 0u, 0u, 0u);
+                if ((uint32_t)g < gfc) dst[g] = ent4[(o >> 2) + glc + g];
+            }
+        };
+        if (slot < nr && cok) load_far(cnt_n, off_n, fe_n);
+        if (slot + kTileSlots < nr) {
+            lr_nn = a.ft_pos[r0 + slot + kTileSlots];
+            cnt_nn = a.ft_cnt[r0 + slot + kTileSlots];
+            off_nn = a.ft_off[r0 + slot + kTileSlots];
+        }
         for (int64_t p = slot; p < nr && cok; p += kTileSlots) {
             const uint32_t lr = lr_n, cnt = cnt_n, g0 = off_n >> 2;
-            if (p + kTileSlots < nr) {
-                lr_n = a.ft_pos[r0 + p + kTileSlots];
-                cnt_n = a.ft_cnt[r0 + p + kTileSlots];
-                off_n = a.ft_off[r0 + p + kTileSlots];
+            uint4 fe[kTileFar / 4];
+#pragma unroll
+            for (int g = 0; g < kTileFar / 4; ++g) fe[g] = fe_n[g];
+            lr_n = lr_nn;
+            cnt_n = cnt_nn;
+            off_n = off_nn;
+            if (p + kTileSlots < nr) load_far(cnt_n, off_n, fe_n);
+            if (p + 2 * kTileSlots < nr) {
+                lr_nn = a.ft_pos[r0 + p + 2 * kTileSlots];
+                cnt_nn = a.ft_cnt[r0 + p + 2 * kTileSlots];
+                off_nn = a.ft_off[r0 + p + 2 * kTileSlots];
             }
             // the epilogue streams (w in and out, u) are touched once: kept
             // out of the way of the slab's rows in L2
@@ -1461,13 +1553,8 @@ __global__ __launch_bounds__(1024) void k_hub_up_tile(HubKArgs a)
             const uint32_t nlp = cnt & 255u, nl = nlp + ((cnt >> 8) & 255u);
             const uint32_t nfp = (cnt >> 16) & 255u, nf = nfp + (cnt >> 24);
             // local entries are 16-bit (eight per group), far ones 32-bit
-            const uint32_t ngl = (nl + 7) >> 3, ngf = (nf + 3) >> 2;
-            uint4 fe[kTileFar / 4], le[kTileLocalGroups];
-#pragma unroll
-            for (int g = 0; g < kTileFar / 4; ++g) {
-                fe[g] = make_uint4(0u, 0u, 0u, 0u);
-                if ((uint32_t)g < ngf) fe[g] = ent4[g0 + ngl + g];
-            }
+            const uint32_t ngl = (nl + 7) >> 3;
+            uint4 le[kTileLocalGroups];
 #pragma unroll
             for (int g = 0; g < kTileLocalGroups; ++g) {
                 le[g] = make_uint4(0u, 0u, 0u, 0u);
@@ -1763,7 +1850,13 @@ static int launch_hub_t(hphi_ham *h, HubKArgs a, hipStream_t st)
         hipLaunchKernelGGL((k_hub_rows_f<S, NV>), dim3((unsigned)grid_r), dim3(threads), fast_row_bytes, st, a);
     } else if (cx) {
         if constexpr (NV == 2) {
-            if (lds_row) {
+            const size_t cl_bytes = (size_t)(a.ddn + 256) * sizeof(S);
+            if (!lds_row && cl_bytes <= 160 * 1024) {
+                hipFuncSetAttribute((const void *)k_hub_rows_cl<S>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)cl_bytes);
+                hipLaunchKernelGGL((k_hub_rows_cl<S>), dim3((unsigned)std::min<int64_t>(ncu, a.dup)),
+                                   dim3(threads), cl_bytes, st, a);
+            } else if (lds_row) {
                 hipFuncSetAttribute((const void *)k_hub_rows<S, 2, true, true>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)row_bytes);
                 hipLaunchKernelGGL((k_hub_rows<S, 2, true, true>), dim3((unsigned)grid_r), dim3(threads),
