@@ -407,7 +407,13 @@ typedef struct {
     uint64_t seed;         /* start vector: SplitMix64 uniform [-1/2, 1/2)   */
     const void *v0_dev;    /* or a caller start vector (storage dtype); NULL
                               = use the seed                                 */
-    hphi_dtype storage;    /* HPHI_F64 or HPHI_F32 (FP64 dots and scalars)   */
+    hphi_dtype storage;    /* HPHI_F64 or HPHI_F32 (FP64 dots and scalars);
+                              HPHI_C128 or HPHI_C64: complex vectors, for a
+                              Hermitian H that is not real (complex
+                              transfers): alpha and beta stay real, the
+                              start vector has uniform real and imaginary
+                              parts, v0_dev and psi_dev are complex; no
+                              refinement, not in hphi_lanczos_noalloc     */
     void *stream;          /* hipStream_t                                    */
     double *alpha_out;     /* optional host arrays of max_iter entries:      */
     double *beta_out;      /*   T_k diagonal and beta[k] (beta[0] = 0)       */

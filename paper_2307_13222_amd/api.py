@@ -305,13 +305,17 @@ def lanczos(ham: Hamiltonian, max_iter: int, seed: int = 1, v0=None, storage: st
     (0: 16; < 0: none) FP64 Lanczos steps from that vector, whose lowest
     Ritz value becomes energies[0] (polish_e0). no_alloc: the entry
     point that takes its device buffers from the library's static scratch
-    (hphi_lanczos_noalloc) instead of allocating them."""
+    (hphi_lanczos_noalloc) instead of allocating them. storage "c128" or
+    "c64": complex vectors (Hermitian H with complex transfers)."""
     torch = _torch()
     o = L.LanczosOpts()
     o.max_iter, o.check_every, o.tol, o.seed = max_iter, check_every, tol, seed
     o.resid_tol = resid_tol
-    o.storage = L.F64 if storage == "f64" else L.F32
-    tdt = torch.float64 if storage == "f64" else torch.float32
+    codes = {"f64": (L.F64, torch.float64), "f32": (L.F32, torch.float32),
+             "c128": (L.C128, torch.complex128), "c64": (L.C64, torch.complex64)}
+    if storage not in codes:
+        raise HphiError(f"storage {storage!r}: f64, f32, c128 or c64")
+    o.storage, tdt = codes[storage]
     if v0 is not None:
         _dev_check(v0, "v0")
         if v0.dtype != tdt:

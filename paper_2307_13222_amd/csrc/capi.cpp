@@ -1238,6 +1238,11 @@ struct LanczosRun {
     int dt;
     int psi_dt = -1;   // type of the Ritz-vector accumulator (default: dt)
     int64_t dim;
+    // complex vectors of a Hermitian H: every vector operation runs on the
+    // flat array of 2 x dim reals (dim above counts those; alpha and beta
+    // stay real), the product on complex vectors of type mult_dt
+    bool cview = false;
+    int mult_dt = -1;
     // Hubbard: the vectors may be stored with rows padded to whole cache
     // lines (pitch ld >= cols = dim_dn, padding zero); nstore elements each
     int64_t cols = 0, ld = 0, nstore = 0;
@@ -1297,9 +1302,9 @@ struct LanczosRun {
     // by a kernel.
     int setup(int max_iter, Carve *ws = nullptr)
     {
-        fused = h->kind == 1 && (dt == HPHI_F64 || dt == HPHI_F32) && hub_rows_fused_ok(h, 1);
+        fused = !cview && h->kind == 1 && (dt == HPHI_F64 || dt == HPHI_F32) && hub_rows_fused_ok(h, 1);
         cols = ld = dim;
-        if (h->kind == 1) {
+        if (h->kind == 1 && !cview) {
             cols = h->basis->sp[1].dim;
             // padded rows only with allocated buffers (the static scratch
             // path keeps the caller's layout and its size formula)
@@ -1364,17 +1369,17 @@ struct LanczosRun {
         const int pdt = psi_dt < 0 ? dt : psi_dt;
         if (psi && !fz) HPHI_TRY(launch_lz_psi_accum(pdt, dt, lz, svec, dim, psi, q[cur], st, cols, ld));
         MultArgs a{};
-        a.dtype = dt;
+        a.dtype = cview ? mult_dt : dt;
         a.nvec = 1;
         a.v = q[cur];
         a.w = q[wbuf];
         a.u = first ? nullptr : q[prev];
         a.coef = lz->coef;
-        a.dots = 1;
+        a.dots = cview ? 0 : 1;
         a.dot_raw = 0;
         a.red = reduce_of(h, lz->dot);
         a.stream = st;
-        a.ld = h->kind == 1 ? ld : 0;
+        a.ld = (h->kind == 1 && !cview) ? ld : 0;
         if (fz) {
             a.lz = lz;
             a.lz_alpha = alpha;
@@ -1392,6 +1397,9 @@ struct LanczosRun {
             }
         }
         HPHI_TRY(launch_mult(h, a));
+        // complex vectors: <q_k, w> and <w, w> over the flat reals (Re of the
+        // complex products; for Hermitian H <q_k|H q_k> is real)
+        if (cview) HPHI_TRY(launch_dots_xy_yy(dt, 1, dim, q[cur], q[wbuf], reduce_of(h, lz->dot), st));
         if (timing) HPHI_TRY(mark());
         if (psi && fz) HPHI_TRY(launch_lz_psi_accum(pdt, dt, lz, svec, dim, psi, q[cur], st, cols, ld));
         if (!fused)
@@ -1495,8 +1503,11 @@ static int lanczos_impl(hphi_ham *h, const hphi_lanczos_opts *o, double *energie
 {
     if (!h || !o || (n_energies > 0 && !energies)) return fail(HPHI_ERR_INVALID_ARG, "null argument");
     if (o->max_iter < 1 || o->max_iter > 100000) return fail(HPHI_ERR_INVALID_ARG, "max_iter %d", o->max_iter);
-    if (o->storage != HPHI_F64 && o->storage != HPHI_F32)
-        return fail(HPHI_ERR_INVALID_ARG, "Lanczos storage must be F64 or F32");
+    const bool cst = o->storage == HPHI_C128 || o->storage == HPHI_C64;
+    if (o->storage != HPHI_F64 && o->storage != HPHI_F32 && !cst)
+        return fail(HPHI_ERR_INVALID_ARG, "Lanczos storage must be F64, F32, C128 or C64");
+    if (cst && (o->refine || ws))
+        return fail(HPHI_ERR_INVALID_ARG, "complex Lanczos storage: no refinement and no static scratch");
     if (n_energies < 0 || n_energies > o->max_iter) return fail(HPHI_ERR_INVALID_ARG, "n_energies %d", n_energies);
     if (o->check_every < 0) return fail(HPHI_ERR_INVALID_ARG, "check_every < 0");
     if (o->refine != 0 && o->refine != 1) return fail(HPHI_ERR_INVALID_ARG, "refine %d", o->refine);
@@ -1517,8 +1528,10 @@ static int lanczos_impl(hphi_ham *h, const hphi_lanczos_opts *o, double *energie
     } drop{own};
     LanczosRun L;
     L.h = h;
-    L.dt = o->storage;
-    L.dim = h->basis->dim;
+    L.dt = cst ? (o->storage == HPHI_C128 ? HPHI_F64 : HPHI_F32) : o->storage;
+    L.dim = h->basis->dim * (cst ? 2 : 1);
+    L.cview = cst;
+    L.mult_dt = o->storage;
     L.st = st;
     L.timing = o->time_kernels != 0 && !o->use_graph;
     HPHI_TRY(L.setup(o->max_iter, ws));

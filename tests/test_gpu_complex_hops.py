@@ -165,3 +165,45 @@ def test_complex_refusals(api, ctx):
                                  frames=W.HubbardFrames(1, hop_t_im=np.zeros((1, 6))))
     r = api.lanczos(h2, 30, seed=1)
     assert np.isfinite(r["energies"][0])
+
+
+def embed_real(H):
+    """The complex Hermitian H as the real symmetric matrix acting on
+    interleaved (re, im) coordinates: [[Re H, -Im H], [Im H, Re H]]."""
+    import scipy.sparse as sp
+    Hc = sp.coo_matrix(H)
+    r, c, v = Hc.row, Hc.col, Hc.data
+    rows = np.concatenate([2 * r, 2 * r, 2 * r + 1, 2 * r + 1])
+    cols = np.concatenate([2 * c, 2 * c + 1, 2 * c, 2 * c + 1])
+    vals = np.concatenate([v.real, -v.imag, v.imag, v.real])
+    n = 2 * H.shape[0]
+    return sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+
+
+@pytest.mark.parametrize("storage", ["c128", "c64"])
+def test_complex_lanczos_flux_ring(api, ctx, storage):
+    # complex-vector Lanczos on a Hermitian H with complex transfers: the
+    # same recurrence as a real Lanczos of the real embedding on the
+    # interleaved start vector (SplitMix64 uniform over 2 dim reals)
+    say("complex lanczos", storage)
+    n, nu, nd = 10, 5, 4
+    m = W.with_flux(W.hubbard_chain(n, 1.0, 4.0), 1.3)
+    b = api.Basis.hubbard(ctx, n, nu, nd)
+    h = api.Hamiltonian.hubbard(b, m)
+    ups, dns = O.hubbard_basis(n, nu, nd)
+    H = O.hubbard_sparse(m, ups, dns)
+    e_ref = scipy.sparse.linalg.eigsh(H, k=1, which="SA")[0][0]
+    r = api.lanczos(h, 250, seed=3, storage=storage, want_vector=True)
+    tol = 1e-10 if storage == "c128" else 1e-5
+    assert abs(r["energies"][0] - e_ref) < tol * max(1.0, abs(e_ref))
+    psi = host(r["psi"]).astype(np.complex128)
+    assert abs(np.linalg.norm(psi) - 1.0) < (1e-12 if storage == "c128" else 1e-5)
+    res = np.linalg.norm(H @ psi - r["energies"][0] * psi)
+    assert res < (1e-5 if storage == "c128" else 1e-2)
+    if storage == "c128":
+        Hr = embed_real(H)
+        o = O.lanczos(lambda x: Hr @ x, O.splitmix_uniform(3, 0, 2 * b.dim), 20)
+        assert np.max(np.abs(r["alpha"][:20] - o["alpha"][:20])) < 1e-10
+        assert np.max(np.abs(r["beta"][1:20] - o["beta"][1:20])) < 1e-10
+    with pytest.raises(api.HphiError):
+        api.lanczos(h, 10, seed=3, storage="c128", refine=True)
