@@ -266,7 +266,7 @@ typedef struct {
  * hphi_ham_set_frame selects one for every other call.
  * Errors: INVALID_ARG (null frames, n_frames outside [1, 65536], no array
  * given, hop_t without hops, pair_v without pair terms, a non-finite value,
- * more than 126 distinct matrix-element trajectories (a complex transfer
+ * more than 127 distinct matrix-element trajectories (a complex transfer
  * counts twice), and hphi_ham_hubbard_ext's
  * conditions), OUT_OF_MEMORY, DEVICE. */
 int hphi_ham_hubbard_td(hphi_basis *b, const hphi_hop *hops, int n_hops,

@@ -860,7 +860,7 @@ static int make_hubbard(hphi_basis *b, const hphi_hop *hops, int n_hops, const d
         auto it = classes.find(key);
         if (it == classes.end()) {
             const int c = (int)classes.size();
-            if (c >= (int)kZeroClass) return fail(HPHI_ERR_INVALID_ARG, "more than 126 distinct transfer values");
+            if (c >= (int)kZeroClass) return fail(HPHI_ERR_INVALID_ARG, "more than 127 distinct transfer values");
             it = classes.emplace(key, c).first;
             cls_val.push_back(key);
         }
