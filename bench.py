@@ -94,12 +94,12 @@ def parse():
 # counters (fetch 2.000, write 1.000). Valid only for the kernel sources and
 # schedule it was taken with; anything else reports null.
 HUB_TRAFFIC = {
-    "sources_sha256": {"kern_hub.hip": "e377904f0d36dc5584913a2cec5277ca8c3b54465aa0c5357d045436d517fc32",
+    "sources_sha256": {"kern_hub.hip": "42fc06a1a42b002c35186ffd15f1f1b753f7627bbc42aa52d0d887972d392111",
                        "kern_common.h": "82a4da084e46d3f069fff2bbec75262cce5cf6131077ca6b4d166d41e8c25fce"},
     "schedule": {"hub_slab_cols": 128, "hub_groups": 128, "hub_item_rows": 16, "hub_row_cols": 6, "hub_sweep": 7,
                  "hub_row_order": 2, "hub_tile_bits": 0},
-    "cols_fetch_kib": 3.313920e+06, "cols_write_kib": 1.360059e+06,
-    "rows_fetch_kib": 1.456666e+06, "rows_write_kib": 2.588495e+06,
+    "cols_fetch_kib": 3.359620e+06, "cols_write_kib": 1.361091e+06,
+    "rows_fetch_kib": 1.456485e+06, "rows_write_kib": 2.588495e+06,
     "fetch_factor": 2.0, "write_factor": 1.0,
 }
 

@@ -1486,12 +1486,23 @@ __global__ __launch_bounds__(1024) void k_hub_up_tile(HubKArgs a)
         const int64_t r0 = a.ft_blk[blk], nr = (int64_t)a.ft_blk[blk + 1] - r0;
         const int64_t col = (int64_t)slab * kTileCols + 2 * l8;
         const bool cok = col < ddn;    // an even row length: both columns or neither
-        for (int64_t i = slot; i < nr; i += kTileSlots) {
-            P2 x;
-            x.x = (S)0;
-            x.y = (S)0;
-            if (cok) x = *reinterpret_cast<const P2 *>(v + (size_t)(r0 + i) * ld + col);
-            *reinterpret_cast<P2 *>(tile + i * RS + 2 * l8) = x;
+        // stage the block's rows of the slab: four row loads per thread in
+        // flight, then their LDS stores (a load-store pair per row waits out
+        // one memory round trip per row; eight in flight spill registers)
+        for (int64_t i0 = slot; i0 < nr; i0 += 4 * kTileSlots) {
+            P2 x[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int64_t i = i0 + (int64_t)t * kTileSlots;
+                x[t].x = (S)0;
+                x[t].y = (S)0;
+                if (cok && i < nr) x[t] = *reinterpret_cast<const P2 *>(v + (size_t)(r0 + i) * ld + col);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int64_t i = i0 + (int64_t)t * kTileSlots;
+                if (i < nr) *reinterpret_cast<P2 *>(tile + i * RS + 2 * l8) = x[t];
+            }
         }
         __syncthreads();
         double dv = 0.0, dd = 0.0;

@@ -207,3 +207,22 @@ def test_complex_lanczos_flux_ring(api, ctx, storage):
         assert np.max(np.abs(r["beta"][1:20] - o["beta"][1:20])) < 1e-10
     with pytest.raises(api.HphiError):
         api.lanczos(h, 10, seed=3, storage="c128", refine=True)
+
+
+@pytest.mark.parametrize("dt,tol", [("c128", 1e-11), ("c64", 2e-5)])
+def test_complex_transfers_ctpq_matches_oracle(api, ctx, dt, tol):
+    import torch
+    say("complex hops ctpq", dt)
+    m = W.with_flux(W.hubbard_square(3, 3, 1.0, 6.0), 0.8)
+    b = api.Basis.hubbard(ctx, 9, 4, 5)
+    h = api.Hamiltonian.hubbard(b, m)
+    ups, dns = O.hubbard_basis(9, 4, 5)
+    phi0 = O.splitmix_complex_gaussian(78, b.dim)[:, None]
+    tdt = torch.complex128 if dt == "c128" else torch.complex64
+    g = api.ctpq(h, 1, 6, 0.02, 20, storage=dt, phi0=dev(phi0).to(tdt))
+    phi_in = host(dev(phi0).to(tdt)).astype(np.complex128)
+    H = O.hubbard_sparse(m, ups, dns)
+    o = O.ctpq(lambda x: H @ x, phi_in, 6, 0.02, 20)
+    assert relmax(g["D"], o["D"]) < tol
+    assert relmax(g["E"], o["E"]) < tol
+    assert relmax(g["E2"], o["E2"]) < tol
