@@ -559,7 +559,10 @@ typedef struct {
     hphi_dtype storage;    /* HPHI_C128 or HPHI_C64                          */
     uint64_t seed;         /* vector j uses seed + j: complex Gaussian
                               entries (Box-Muller on SplitMix64 outputs)     */
-    const void *phi0_dev;  /* or a caller start block [dim][n_vec] complex   */
+    const void *phi0_dev;  /* or a caller start block [dim][n_vec] complex
+                              (a previous run's phi_dev output resumes that
+                              run: D_k, <H>, <H^2> continue to rounding;
+                              beta_k is counted by the caller)              */
     void *stream;
     int use_graph;         /* capture one step's launches in a hipGraph and
                               replay it (the same numbers as without)        */
