@@ -1243,6 +1243,9 @@ struct LanczosRun {
     // stay real), the product on complex vectors of type mult_dt
     bool cview = false;
     int mult_dt = -1;
+    // the product does not take the fused dots (complex view, or the split
+    // spin product): <q_k, w> and <w, w> in a pass of their own
+    bool sep_dots = false;
     // Hubbard: the vectors may be stored with rows padded to whole cache
     // lines (pitch ld >= cols = dim_dn, padding zero); nstore elements each
     int64_t cols = 0, ld = 0, nstore = 0;
@@ -1303,6 +1306,7 @@ struct LanczosRun {
     int setup(int max_iter, Carve *ws = nullptr)
     {
         fused = !cview && h->kind == 1 && (dt == HPHI_F64 || dt == HPHI_F32) && hub_rows_fused_ok(h, 1);
+        sep_dots = cview || (h->kind == 0 && h->sched_cfg.spin_split == 1);
         cols = ld = dim;
         if (h->kind == 1 && !cview) {
             cols = h->basis->sp[1].dim;
@@ -1375,7 +1379,7 @@ struct LanczosRun {
         a.w = q[wbuf];
         a.u = first ? nullptr : q[prev];
         a.coef = lz->coef;
-        a.dots = cview ? 0 : 1;
+        a.dots = sep_dots ? 0 : 1;
         a.dot_raw = 0;
         a.red = reduce_of(h, lz->dot);
         a.stream = st;
@@ -1397,9 +1401,9 @@ struct LanczosRun {
             }
         }
         HPHI_TRY(launch_mult(h, a));
-        // complex vectors: <q_k, w> and <w, w> over the flat reals (Re of the
+        // <q_k, w> and <w, w> over the flat reals (complex vectors: Re of the
         // complex products; for Hermitian H <q_k|H q_k> is real)
-        if (cview) HPHI_TRY(launch_dots_xy_yy(dt, 1, dim, q[cur], q[wbuf], reduce_of(h, lz->dot), st));
+        if (sep_dots) HPHI_TRY(launch_dots_xy_yy(dt, 1, dim, q[cur], q[wbuf], reduce_of(h, lz->dot), st));
         if (timing) HPHI_TRY(mark());
         if (psi && fz) HPHI_TRY(launch_lz_psi_accum(pdt, dt, lz, svec, dim, psi, q[cur], st, cols, ld));
         if (!fused)

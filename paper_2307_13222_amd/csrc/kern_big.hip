@@ -147,6 +147,28 @@ int launch_spin_mult_implicit(hphi_ham *h, const MultArgs &m)
     if (cap > kMaxGrid) cap = kMaxGrid;
     const int grid = (int)(need < cap ? need : cap);
     const bool f32 = dtype_is_f32(m.dtype);
+    // split product (schedule spin_split): the bonds with an end in the low
+    // half and the fields here into w, then the high-half bonds and the
+    // caller's epilogue in slab order (their gathers are contiguous runs
+    // of one block of the same class)
+    bool split = h->sched_cfg.spin_split == 1 && !m.dots && !m.cocg && m.v != m.w && (!m.u || m.u != m.w) &&
+                 (!m.acc || m.acc != m.w);
+    if (split) {
+        HPHI_TRY(spin_split_tables(h));
+        split = h->split.n_hi_bonds > 0 && h->split.n_hi_bonds <= kMaxHiBonds;
+    }
+    if (split) {
+        a.bonds = h->split.rest.as<SpinBondDev>();
+        a.nb = h->split.n_rest;
+        a.u = nullptr;
+        a.acc_out = nullptr;
+        a.coef = nullptr;
+        a.nd = 0;
+        if (f32) hipLaunchKernelGGL((k_spin_hv_implicit<float, false>), dim3(grid), dim3(kBlock), 0, m.stream, a);
+        else hipLaunchKernelGGL((k_spin_hv_implicit<double, false>), dim3(grid), dim3(kBlock), 0, m.stream, a);
+        HPHI_HIP(hipGetLastError());
+        return launch_spin_hi_pass(h, m);
+    }
     if (a.nd) {
         if (f32) hipLaunchKernelGGL((k_spin_hv_implicit<float, true>), dim3(grid), dim3(kBlock), 0, m.stream, a);
         else hipLaunchKernelGGL((k_spin_hv_implicit<double, true>), dim3(grid), dim3(kBlock), 0, m.stream, a);

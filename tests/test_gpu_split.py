@@ -99,9 +99,42 @@ def test_split_ctpq_and_lanczos(api, ctx):
     g = api.ctpq(h, 2, 6, 0.02, 12, phi0=dev(phi))
     o = O.ctpq(lambda x: O.spin_hv(m, s, x), phi, 6, 0.02, 12)
     assert relmax(g["D"], o["D"]) < 1e-11 and relmax(g["E"], o["E"]) < 1e-11 and relmax(g["E2"], o["E2"]) < 1e-11
-    # Lanczos takes the one-pass product with fused dots whatever the
-    # schedule; with dots off (the first order of cTPQ above) the split runs
+    # Lanczos with the split product takes its dots in a pass of their own:
+    # the recurrence of the one-pass product up to summation order, and the
+    # oracle's
     r = api.lanczos(h, 150, seed=1)
     h.set_schedule(spin_split=-1)
     r1 = api.lanczos(h, 150, seed=1)
-    assert np.array_equal(r["alpha"], r1["alpha"])
+    assert np.max(np.abs(r["alpha"][:30] - r1["alpha"][:30])) < 1e-11
+    assert abs(r["energies"][0] - r1["energies"][0]) < 1e-10
+    o = O.lanczos(lambda x: O.spin_hv(m, s, x), O.splitmix_uniform(1, 0, len(s)), 20)
+    assert np.max(np.abs(r["alpha"][:20] - o["alpha"][:20])) < 1e-11
+
+
+@pytest.mark.parametrize("n,dt", [(18, "f64"), (20, "f32")])
+def test_split_implicit_basis(api, ctx, n, dt):
+    # the implicit-basis kernel (the path of sectors without a stored state
+    # list) with the split: product against the oracle and the one-pass
+    # product, Lanczos coefficients against the oracle's recurrence
+    import torch
+    say("split implicit", n, dt)
+    m = W.j1j2_square(n // 2, 2, 1.0, 0.5) if n == 20 else W.xxz_chain_j2(n)
+    b = api.Basis.spin(ctx, n, 0)
+    h = api.Hamiltonian.spin(b, m)
+    h.set_schedule(spin_implicit=1, spin_split=1)
+    s = O.basis_list(n, n // 2)
+    v = W.random_vector(len(s), 9)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    w = host(h.mult(dev(v).to(tdt))).astype(np.float64)
+    ref = O.spin_hv(m, s, host(dev(v).to(tdt)).astype(np.float64))
+    tol = 1e-12 if dt == "f64" else 3e-6
+    assert relmax(w, ref) < tol
+    h.set_schedule(spin_split=-1)
+    w1 = host(h.mult(dev(v).to(tdt))).astype(np.float64)
+    assert relmax(w, w1) < (1e-13 if dt == "f64" else 2e-6)
+    if dt == "f64":
+        h.set_schedule(spin_split=1)
+        r = api.lanczos(h, 40, seed=2)
+        o = O.lanczos(lambda x: O.spin_hv(m, s, x), O.splitmix_uniform(2, 0, len(s)), 20)
+        assert np.max(np.abs(r["alpha"][:20] - o["alpha"][:20])) < 1e-11
+        assert np.max(np.abs(r["beta"][1:20] - o["beta"][1:20])) < 1e-11
