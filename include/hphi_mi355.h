@@ -347,14 +347,28 @@ void hphi_ham_free(hphi_ham *h);
  *                   7 (the tables are rebuilt when it changes); -1 = the
  *                   fewest sites whose largest block of 16 FP64 columns
  *                   fits LDS (the default)
- *   spin_split      1: the stored-list spin product in two passes -- the
- *                   bonds with an end in the low half of the sites (and the
- *                   fields), then the bonds inside the high half in slab
- *                   order (a state's high-bond partners sit at the same
- *                   position of another block of its class); products
- *                   without fused dots, at most 128 high bonds; otherwise
- *                   one pass. -1: one pass (the default). The products equal
- *                   the one-pass ones up to summation order.
+ *   spin_split      1: the spin product in two passes -- the bonds with
+ *                   an end in the low half of the sites (and the fields),
+ *                   then the bonds inside the high half in slab order (a
+ *                   state's high-bond partners sit at the same position of
+ *                   another block of its class); products without fused
+ *                   dots, at most 128 high bonds; otherwise one pass.
+ *                   2: on the implicit basis (one real vector, no fused
+ *                   dots), one pass over blocks of states: a workgroup
+ *                   stages the block of one high pattern in LDS, bonds
+ *                   inside the low part read their partners there (partner
+ *                   positions from per-bond tables over the low patterns),
+ *                   bonds inside the high part read the same positions of
+ *                   the partner block, bonds across read one position of
+ *                   the partner block from a per-site table; where no split
+ *                   point gives blocks that fit LDS, as 1; on the stored
+ *                   list, as 1. -1: one pass (the default). The products
+ *                   equal the one-pass ones up to summation order.
+ *   spin_blk_lo     split point (sites in the low part) of spin_split 2;
+ *                   -1 = the most low sites whose largest block fits LDS
+ *                   (the default, at most the basis's own split); a
+ *                   choice whose blocks do not fit returns UNSUPPORTED
+ *                   from the product.
  * Errors: INVALID_ARG (value outside its range), UNSUPPORTED (hub_sweep 7
  * or hub_tile_bits for blocks the tile kernel cannot take). */
 typedef struct {
@@ -369,6 +383,7 @@ typedef struct {
     int spin_tables;
     int hub_tile_bits;
     int spin_split;
+    int spin_blk_lo;
 } hphi_schedule;
 
 int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s);

@@ -85,7 +85,7 @@ class Schedule(C.Structure):
     _fields_ = [("hub_slab_cols", C.c_int), ("hub_groups", C.c_int), ("hub_item_rows", C.c_int),
                 ("hub_row_cols", C.c_int), ("spin_per_cu", C.c_int), ("spin_implicit", C.c_int),
                 ("hub_sweep", C.c_int), ("hub_row_order", C.c_int), ("spin_tables", C.c_int),
-                ("hub_tile_bits", C.c_int), ("spin_split", C.c_int)]
+                ("hub_tile_bits", C.c_int), ("spin_split", C.c_int), ("spin_blk_lo", C.c_int)]
 
 
 class SqwOpts(C.Structure):

@@ -277,7 +277,7 @@ class Hamiltonian:
 
     SCHEDULE_FIELDS = ("hub_slab_cols", "hub_groups", "hub_item_rows", "hub_row_cols", "spin_per_cu",
                        "spin_implicit", "hub_sweep", "hub_row_order", "spin_tables", "hub_tile_bits",
-                       "spin_split")
+                       "spin_split", "spin_blk_lo")
 
     def set_schedule(self, **kw):
         s = L.Schedule(*[int(kw.get(f, 0)) for f in self.SCHEDULE_FIELDS])

@@ -23,7 +23,7 @@ SOURCES = ["host.cpp", "capi.cpp", "capi_methods.cpp", "kern_spin.hip", "kern_hu
            "kern_vec.hip", "kern_methods.hip", "kern_big.hip", "kern_batch.hip", "kern_lobpcg.hip",
            "capi_lobpcg.cpp", "noalloc.hip", "kern_hub_pairs.hip",
            "kern_spin_gc.hip", "capi_gc.cpp", "kern_spin_s.hip", "capi_spin_s.cpp",
-           "kern_spin_split.hip"]
+           "kern_spin_split.hip", "kern_spin_blk.hip"]
 
 
 def _compile(src: str) -> str:

@@ -1137,8 +1137,14 @@ int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s)
         n.spin_tables = s->spin_tables == -1 ? 0 : s->spin_tables;
     }
     if (s->spin_split) {
-        if (s->spin_split != -1 && s->spin_split != 1) return fail(HPHI_ERR_INVALID_ARG, "spin_split %d", s->spin_split);
-        n.spin_split = s->spin_split == -1 ? 0 : 1;
+        if (s->spin_split != -1 && s->spin_split != 1 && s->spin_split != 2)
+            return fail(HPHI_ERR_INVALID_ARG, "spin_split %d", s->spin_split);
+        n.spin_split = s->spin_split == -1 ? 0 : s->spin_split;
+    }
+    if (s->spin_blk_lo) {
+        if (s->spin_blk_lo != -1 && (s->spin_blk_lo < 1 || s->spin_blk_lo > 24))
+            return fail(HPHI_ERR_INVALID_ARG, "spin_blk_lo %d", s->spin_blk_lo);
+        n.spin_blk_lo = s->spin_blk_lo == -1 ? 0 : s->spin_blk_lo;
     }
     if (s->hub_sweep == 7 && h->kind == 1 && !h->hub.ft_ok && !s->hub_tile_bits)
         return fail(HPHI_ERR_UNSUPPORTED, "hub_sweep 7: no tile tables for this Hamiltonian");
@@ -1306,7 +1312,7 @@ struct LanczosRun {
     int setup(int max_iter, Carve *ws = nullptr)
     {
         fused = !cview && h->kind == 1 && (dt == HPHI_F64 || dt == HPHI_F32) && hub_rows_fused_ok(h, 1);
-        sep_dots = cview || (h->kind == 0 && h->sched_cfg.spin_split == 1);
+        sep_dots = cview || (h->kind == 0 && h->sched_cfg.spin_split != 0);
         cols = ld = dim;
         if (h->kind == 1 && !cview) {
             cols = h->basis->sp[1].dim;

@@ -144,6 +144,27 @@ struct HiBondDev {
     double jz4, jxy2;
 };
 constexpr int kMaxHiBonds = 128;
+// Block-staged spin H*v (implicit basis): bonds by where their ends fall
+// against a split point n_lo of the sites. Low bond: both ends below it;
+// row = its row of the partner-position table. Crossing bond: low end lbit,
+// high end hbit (in high coordinates); row = the table row of site lbit.
+struct LoBondDev {
+    uint32_t mask, row;
+    double jz4, jxy2;
+};
+struct XBondDev {
+    uint32_t hbit, row, lbit, pad;
+    double jz4, jxy2;
+};
+struct SpinBlk {
+    bool built = false, ok = false;
+    int n_lo = 0, esize = 0, want = 0;
+    int n_lob = 0, n_xb = 0, n_hib = 0;
+    uint32_t n_blocks = 0, max_len = 0;
+    std::unique_ptr<Species> sp;   // rank tables for this split point
+    DevMem lob, xb, hib, tab, hi_list, cls_len, lo_off;
+};
+
 struct SpinSplit {
     bool built = false;
     int n_hi_bonds = 0, n_rest = 0;
@@ -295,6 +316,7 @@ struct hphi_ham {
     hphi::GcPlan gc_plan[3];
     // spin: bonds split into high-half and other bonds (built on first use)
     hphi::SpinSplit split;
+    hphi::SpinBlk blk;
     // spin-S: bonds as given (jz, jxy), fields and single-ion terms
     std::vector<hphi_spin_bond> sbonds;
     std::vector<double> s_hz, s_dion;
@@ -302,7 +324,7 @@ struct hphi_ham {
     // defaults: 128-column slabs, 128 workgroups per XCD, 32-row items,
     // hop-ordered down slots, work-item queues with two columns per lane;
     // spin: 8 workgroups per CU
-    hphi_schedule sched_cfg{128, 128, 16, 6, 8, 0, 5, 2, 0, 0, 0};
+    hphi_schedule sched_cfg{128, 128, 16, 6, 8, 0, 5, 2, 0, 0, 0, 0};
     // scratch for reductions and work queues
     hphi::DevMem sched;         // unsigned [16]: per-XCD item queues + counter
     hphi::DevMem red_partial;   // double [kReduceSlots]
@@ -432,6 +454,10 @@ int launch_spin_mult(hphi_ham *h, const MultArgs &a);
 int launch_spin_mult_implicit(hphi_ham *h, const MultArgs &a);
 int spin_split_tables(hphi_ham *h);
 int launch_spin_hi_pass(hphi_ham *h, const MultArgs &a);
+// Block-staged product on the implicit basis: builds its tables on first use
+// for an element size; sets *done when it ran (0: the blocks do not fit LDS
+// at any split point, the caller takes another path)
+int launch_spin_blk(hphi_ham *h, const MultArgs &a, int *done);
 int launch_hub_mult(hphi_ham *h, const MultArgs &a);
 int launch_mult(hphi_ham *h, const MultArgs &a);
 // w += H_2body v for the Hubbard two-body terms (NV lanes per element, rows

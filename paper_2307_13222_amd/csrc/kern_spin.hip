@@ -430,7 +430,7 @@ int launch_spin_mult(hphi_ham *h, const MultArgs &m)
     if (grid < 1) grid = 1;
     // split product: the bonds with an end in the low half into w, then
     // the high-half bonds and the caller's epilogue in slab order
-    bool split = h->sched_cfg.spin_split == 1 && !m.dots && !m.cocg && m.v != m.w && (!m.u || m.u != m.w) &&
+    bool split = h->sched_cfg.spin_split != 0 && !m.dots && !m.cocg && m.v != m.w && (!m.u || m.u != m.w) &&
                  (!m.acc || m.acc != m.w) && (!m.raw_out || m.raw_out != m.w);
     if (split) {
         HPHI_TRY(spin_split_tables(h));

@@ -1,0 +1,420 @@
+// Spin-1/2 XXZ H*v on an implicit sector basis, one block of states at a
+// time (HPhi update paper Sec. 3.2 Heisenberg model; the Lanczos runs on
+// sectors of about 10^10 states that motivate Sec. 1).
+//
+// A split point n_lo of the sites (chosen so that a block fits LDS; it need
+// not be the basis's own) cuts a state x into (h, l). The basis order is
+// ascending x whatever the split, so the states of one high pattern h form
+// a block in ascending l, the state (h, l) at hi_off[h] + lo_rank[l] with
+// the tables of this split point. A workgroup takes one block at a time:
+//   * it stages the block's values in LDS (one contiguous read);
+//   * a bond inside the low part maps position p to a position q of the
+//     same block; q comes from a per-bond table over the low patterns, read
+//     contiguously along p, and the partner value from LDS;
+//   * a bond inside the high part maps (h, p) to (h ^ m, p): the partner
+//     block's start is the same for the whole workgroup and the lanes read
+//     consecutive positions of it;
+//   * a bond with one end in each part flips one low site and one high
+//     site: the partner block is again common to the workgroup, the partner
+//     position comes from a per-site table over the low patterns, and the
+//     lanes' partner positions ascend with p.
+// No configuration is unranked and no rank table is searched per flip. The
+// caller's epilogue (w = c1 H v + c2 u, accumulation) is applied at the end.
+#include "kern_common.h"
+
+#include <algorithm>
+
+namespace hphi {
+
+namespace {
+
+struct BlkKArgs {
+    const uint32_t *hi_list;   // the high patterns with a nonempty block, by popcount
+    uint32_t n_blocks;
+    const uint64_t *hi_off;    // 2^n_hi + 1
+    const uint32_t *lo_list;   // low patterns grouped by popcount
+    const uint32_t *cls_len;   // by popcount of h: block length
+    const uint32_t *lo_off;    // by popcount of h: first lo_list index of its low patterns
+    const LoBondDev *lob;
+    const XBondDev *xb;
+    const HiBondDev *hib;
+    int nlob, nxb, nhib;
+    const uint16_t *tab;       // rows of 2^n_lo partner positions
+    uint64_t pitch;            // 2^n_lo
+    const double *hz;          // per site or null
+    int n_lo, n_sites;
+    unsigned *sched;           // [0] block counter, [1] finished workgroups
+    const void *v;
+    void *w;
+    const void *u;
+    void *acc_out;
+    const double *coef;
+};
+
+constexpr int kBlkThreads = 1024;
+constexpr int kBatch = 8;
+
+template <typename S>
+__global__ __launch_bounds__(kBlkThreads) void k_spin_blk(BlkKArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    S *blk = reinterpret_cast<S *>(smem_raw);
+    __shared__ unsigned s_i;
+    __shared__ unsigned s_last;
+    // read-only tables at workgroup-uniform indices: scalar loads
+    typedef const __attribute__((address_space(4))) uint64_t CU64;
+    typedef const __attribute__((address_space(4))) uint32_t CU32;
+    typedef const __attribute__((address_space(4))) LoBondDev CLB;
+    typedef const __attribute__((address_space(4))) XBondDev CXB;
+    typedef const __attribute__((address_space(4))) HiBondDev CHB;
+    const CU64 *hoff = (const CU64 *)a.hi_off;
+    const CU32 *hlist = (const CU32 *)a.hi_list;
+    const CU32 *clen = (const CU32 *)a.cls_len;
+    const CU32 *loff = (const CU32 *)a.lo_off;
+    const CLB *lob = (const CLB *)a.lob;
+    const CXB *xb = (const CXB *)a.xb;
+    const CHB *hib = (const CHB *)a.hib;
+    const S *__restrict__ v = static_cast<const S *>(a.v);
+    S *__restrict__ w = static_cast<S *>(a.w);
+    const S *__restrict__ u = static_cast<const S *>(a.u);
+    S *__restrict__ accp = static_cast<S *>(a.acc_out);
+    const uint16_t *__restrict__ tab = a.tab;
+    const uint32_t *__restrict__ lol = a.lo_list;
+    const S c1s = a.coef ? (S)a.coef[0] : (S)1, c2s = a.coef ? (S)a.coef[1] : (S)0;
+    const int tid = threadIdx.x;
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_i = atomicAdd(&a.sched[0], 1u);
+        __syncthreads();
+        const unsigned bi = __builtin_amdgcn_readfirstlane(s_i);
+        if (bi >= a.n_blocks) break;
+        const uint32_t hh = hlist[bi];
+        const int k = __builtin_popcount(hh);
+        const uint32_t L = clen[k];
+        const uint32_t g0 = loff[k];
+        const uint64_t base = hoff[hh];
+        // stage the block: four loads in flight per thread
+        for (uint32_t p0 = tid; p0 < L; p0 += 4 * kBlkThreads) {
+            S t[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t p = p0 + (uint32_t)r * kBlkThreads;
+                t[r] = p < L ? v[base + p] : (S)0;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t p = p0 + (uint32_t)r * kBlkThreads;
+                if (p < L) blk[p] = t[r];
+            }
+        }
+        __syncthreads();
+        // the high bonds' diagonal and the high sites' fields: the same for
+        // every state of the block
+        S dgh = (S)0;
+        for (int b = 0; b < a.nhib; ++b) {
+            const uint32_t mk = hib[b].mask;
+            const uint32_t t = hh & mk;
+            dgh += (t == 0u || t == mk) ? (S)hib[b].jz4 : -(S)hib[b].jz4;
+        }
+        if (a.hz)
+            for (int i = a.n_lo; i < a.n_sites; ++i)
+                dgh -= (S)a.hz[i] * (((hh >> (i - a.n_lo)) & 1u) ? (S)0.5 : (S)-0.5);
+        for (uint32_t p = tid; p < L; p += kBlkThreads) {
+            const uint32_t g = g0 + p;
+            const uint32_t l = lol[g];
+            S acc = (S)0, dg = dgh;
+            if (a.hz)
+                for (int i = 0; i < a.n_lo; ++i) dg -= (S)a.hz[i] * (((l >> i) & 1u) ? (S)0.5 : (S)-0.5);
+            // bonds inside the low part: partners in LDS
+            for (int b0 = 0; b0 < a.nlob; b0 += kBatch) {
+                uint32_t q[kBatch];
+                S cf[kBatch];
+                unsigned anti = 0u;
+#pragma unroll
+                for (int t = 0; t < kBatch; ++t) {
+                    q[t] = 0u;
+                    cf[t] = (S)0;
+                    const int b = b0 + t;
+                    if (b < a.nlob) {
+                        const uint32_t mk = lob[b].mask;
+                        const uint32_t tt = l & mk;
+                        const S jz = (S)lob[b].jz4;
+                        if (tt == 0u || tt == mk) {
+                            dg += jz;
+                        } else {
+                            dg -= jz;
+                            anti |= 1u << t;
+                            cf[t] = (S)lob[b].jxy2;
+                        }
+                        q[t] = tab[(uint64_t)lob[b].row * a.pitch + g];
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < kBatch; ++t)
+                    if (anti & (1u << t)) acc += cf[t] * blk[q[t]];
+            }
+            // bonds across the split: one position of a partner block
+            for (int b0 = 0; b0 < a.nxb; b0 += kBatch) {
+                uint64_t src[kBatch];
+                S cf[kBatch], val[kBatch];
+                unsigned anti = 0u;
+#pragma unroll
+                for (int t = 0; t < kBatch; ++t) {
+                    src[t] = 0;
+                    cf[t] = (S)0;
+                    const int b = b0 + t;
+                    if (b < a.nxb) {
+                        const uint32_t hbit = xb[b].hbit;
+                        const uint64_t pb = hoff[hh ^ (1u << hbit)];
+                        const uint32_t q = tab[(uint64_t)xb[b].row * a.pitch + g];
+                        const uint32_t hb = (hh >> hbit) & 1u;
+                        const uint32_t lb = (l >> xb[b].lbit) & 1u;
+                        const S jz = (S)xb[b].jz4;
+                        if (hb == lb) {
+                            dg += jz;
+                        } else {
+                            dg -= jz;
+                            anti |= 1u << t;
+                            cf[t] = (S)xb[b].jxy2;
+                            src[t] = pb + q;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < kBatch; ++t) val[t] = (anti & (1u << t)) ? v[src[t]] : (S)0;
+#pragma unroll
+                for (int t = 0; t < kBatch; ++t)
+                    if (anti & (1u << t)) acc += cf[t] * val[t];
+            }
+            // bonds inside the high part: the same position of a partner block
+            for (int b0 = 0; b0 < a.nhib; b0 += kBatch) {
+                uint64_t src[kBatch];
+                S cf[kBatch], val[kBatch];
+                unsigned anti = 0u;
+#pragma unroll
+                for (int t = 0; t < kBatch; ++t) {
+                    src[t] = 0;
+                    cf[t] = (S)0;
+                    const int b = b0 + t;
+                    if (b < a.nhib) {
+                        const uint32_t mk = hib[b].mask;
+                        const uint32_t tt = hh & mk;
+                        if (tt != 0u && tt != mk) {
+                            anti |= 1u << t;
+                            cf[t] = (S)hib[b].jxy2;
+                            src[t] = hoff[hh ^ mk] + p;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < kBatch; ++t) val[t] = (anti & (1u << t)) ? v[src[t]] : (S)0;
+#pragma unroll
+                for (int t = 0; t < kBatch; ++t)
+                    if (anti & (1u << t)) acc += cf[t] * val[t];
+            }
+            const S hv = acc + dg * blk[p];
+            S out = c1s * hv;
+            if (u) out += c2s * u[base + p];
+            w[base + p] = out;
+            if (accp) accp[base + p] += out;
+        }
+    }
+    // the last workgroup re-arms the counters for the next launch
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        s_last = (atomicAdd(&a.sched[1], 1u) == gridDim.x - 1) ? 1u : 0u;
+        if (s_last) {
+            a.sched[0] = 0u;
+            a.sched[1] = 0u;
+            __threadfence();
+        }
+    }
+}
+
+uint64_t binom_small(int n, int k)
+{
+    if (k < 0 || n < 0 || k > n) return 0;
+    if (k > n - k) k = n - k;
+    uint64_t r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (uint64_t)(n - k + i) / (uint64_t)i;
+    return r;
+}
+
+// Largest block at split point nl: max over high popcounts k of
+// C(nl, n_pop - k), k = 0..n_bits - nl.
+uint64_t blk_max_len(int n_bits, int n_pop, int nl)
+{
+    uint64_t m = 0;
+    for (int k = 0; k <= n_bits - nl; ++k) m = std::max(m, binom_small(nl, n_pop - k));
+    return m;
+}
+
+// 160 KB of LDS per workgroup on gfx950, less the kernel's own shared words
+constexpr size_t kBlkLdsBudget = 160 * 1024 - 256;
+
+// Split point, tables and bond lists for element size esize (4 or 8 bytes).
+int blk_tables(hphi_ham *h, int esize)
+{
+    SpinBlk &B = h->blk;
+    const Species &s = h->basis->sp[0];
+    const int N = s.n_bits, np = s.n_pop, want = h->sched_cfg.spin_blk_lo;
+    if (B.built && B.esize == esize && B.want == want) return HPHI_OK;
+    const size_t budget = kBlkLdsBudget;
+    int nl = 0;
+    if (want > 0) {
+        if (want > N || want > 24 || N - want > 24 || blk_max_len(N, np, want) * (uint64_t)esize > budget)
+            return fail(HPHI_ERR_UNSUPPORTED, "spin_blk_lo %d: blocks of %d-byte elements do not fit LDS", want, esize);
+        nl = want;
+    } else {
+        for (int n = std::min(s.n_lo, 24); n >= 1 && N - n <= 24; --n)
+            if (blk_max_len(N, np, n) * (uint64_t)esize <= budget) {
+                nl = n;
+                break;
+            }
+    }
+    B.built = true;
+    B.esize = esize;
+    B.want = want;
+    B.ok = nl > 0;
+    if (!B.ok) return HPHI_OK;
+    if (B.sp && B.n_lo == nl) return HPHI_OK;   // same split point: tables kept
+    auto sp = std::make_unique<Species>();
+    HPHI_TRY(build_species(*sp, N, np, nl, false));
+    const uint32_t nlo = 1u << nl;
+    // bonds by where their ends fall
+    std::vector<LoBondDev> lob;
+    std::vector<XBondDev> xb;
+    std::vector<HiBondDev> hib;
+    std::vector<int> site_row(nl, -1);
+    std::vector<uint32_t> low_masks, x_sites;
+    for (const SpinBondDev &b : h->bonds) {
+        const bool li = b.i < nl, lj = b.j < nl;
+        if (li && lj) {
+            LoBondDev d{};
+            d.mask = (uint32_t)b.mask;
+            d.row = (uint32_t)lob.size();
+            d.jz4 = b.jz4;
+            d.jxy2 = b.jxy2;
+            lob.push_back(d);
+            low_masks.push_back(d.mask);
+        } else if (!li && !lj) {
+            HiBondDev d{};
+            d.mask = (uint32_t)(b.mask >> nl);
+            d.jz4 = b.jz4;
+            d.jxy2 = b.jxy2;
+            hib.push_back(d);
+        } else {
+            XBondDev d{};
+            d.lbit = (uint32_t)(li ? b.i : b.j);
+            d.hbit = (uint32_t)((li ? b.j : b.i) - nl);
+            if (site_row[d.lbit] < 0) {
+                site_row[d.lbit] = (int)x_sites.size();
+                x_sites.push_back(d.lbit);
+            }
+            d.jz4 = b.jz4;
+            d.jxy2 = b.jxy2;
+            xb.push_back(d);
+        }
+    }
+    const uint32_t n_lob = (uint32_t)lob.size();
+    for (XBondDev &d : xb) d.row = n_lob + (uint32_t)site_row[d.lbit];
+    // partner positions: low bond b at row b (rank of l ^ mask where the
+    // bond is antiparallel, else 0); crossing site i at row n_lob + its
+    // index (rank of l ^ bit i), over all low patterns by popcount group
+    const size_t rows = low_masks.size() + x_sites.size();
+    std::vector<uint16_t> tab(std::max<size_t>(rows, 1) * nlo, 0);
+    for (uint32_t g = 0; g < nlo; ++g) {
+        const uint32_t l = sp->lo_list[g];
+        for (size_t r = 0; r < low_masks.size(); ++r) {
+            const uint32_t mk = low_masks[r], t = l & mk;
+            if (t != 0u && t != mk) tab[r * nlo + g] = (uint16_t)sp->lo_rank[l ^ mk];
+        }
+        for (size_t r = 0; r < x_sites.size(); ++r)
+            tab[(low_masks.size() + r) * nlo + g] = (uint16_t)sp->lo_rank[l ^ (1u << x_sites[r])];
+    }
+    // blocks by popcount of h, ascending h within
+    const int nh = N - nl;
+    std::vector<uint32_t> list, len(nh + 1, 0), off(nh + 1, 0);
+    for (int k = 0; k <= nh; ++k) {
+        const int c = np - k;
+        if (c < 0 || c > nl) continue;
+        len[k] = (uint32_t)binom_small(nl, c);
+        off[k] = sp->lo_list_off[c];
+        for (uint32_t x = 0; x < (1u << nh); ++x)
+            if (__builtin_popcount(x) == k) list.push_back(x);
+    }
+    B.n_lob = (int)n_lob;
+    B.n_xb = (int)xb.size();
+    B.n_hib = (int)hib.size();
+    if (lob.empty()) lob.push_back(LoBondDev{});
+    if (xb.empty()) xb.push_back(XBondDev{});
+    if (hib.empty()) hib.push_back(HiBondDev{});
+    B.n_blocks = (uint32_t)list.size();
+    B.max_len = (uint32_t)blk_max_len(N, np, nl);
+    HPHI_TRY(upload(B.lob, lob.data(), sizeof(LoBondDev) * lob.size()));
+    HPHI_TRY(upload(B.xb, xb.data(), sizeof(XBondDev) * xb.size()));
+    HPHI_TRY(upload(B.hib, hib.data(), sizeof(HiBondDev) * hib.size()));
+    HPHI_TRY(upload(B.tab, tab.data(), sizeof(uint16_t) * tab.size()));
+    HPHI_TRY(upload(B.hi_list, list.data(), sizeof(uint32_t) * list.size()));
+    HPHI_TRY(upload(B.cls_len, len.data(), sizeof(uint32_t) * len.size()));
+    HPHI_TRY(upload(B.lo_off, off.data(), sizeof(uint32_t) * off.size()));
+    B.sp = std::move(sp);
+    B.n_lo = nl;
+    return HPHI_OK;
+}
+
+template <typename S>
+int launch_blk_t(hphi_ham *h, const MultArgs &m)
+{
+    const SpinBlk &B = h->blk;
+    BlkKArgs a{};
+    a.hi_list = B.hi_list.as<uint32_t>();
+    a.n_blocks = B.n_blocks;
+    a.hi_off = B.sp->d_hi_off.as<uint64_t>();
+    a.lo_list = B.sp->d_lo_list.as<uint32_t>();
+    a.cls_len = B.cls_len.as<uint32_t>();
+    a.lo_off = B.lo_off.as<uint32_t>();
+    a.lob = B.lob.as<LoBondDev>();
+    a.xb = B.xb.as<XBondDev>();
+    a.hib = B.hib.as<HiBondDev>();
+    a.nlob = B.n_lob;
+    a.nxb = B.n_xb;
+    a.nhib = B.n_hib;
+    a.tab = B.tab.as<uint16_t>();
+    a.pitch = uint64_t(1) << B.n_lo;
+    a.hz = h->has_field ? h->d_hz.as<double>() : nullptr;
+    a.n_lo = B.n_lo;
+    a.n_sites = h->basis->n_sites;
+    a.sched = h->sched.as<unsigned>();
+    a.v = m.v;
+    a.w = m.w;
+    a.u = m.u;
+    a.acc_out = m.acc;
+    a.coef = m.coef;
+    const size_t lds = (size_t)B.max_len * sizeof(S);
+    HPHI_HIP(hipFuncSetAttribute((const void *)k_spin_blk<S>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int ncu = h->basis->ctx->n_cu > 0 ? h->basis->ctx->n_cu : 256;
+    const uint32_t per_cu = lds <= 40 * 1024 ? 2u : 1u;
+    uint32_t grid = (uint32_t)ncu * per_cu;
+    if (grid > B.n_blocks) grid = B.n_blocks;
+    hipLaunchKernelGGL((k_spin_blk<S>), dim3(grid), dim3(kBlkThreads), lds, m.stream, a);
+    HPHI_HIP(hipGetLastError());
+    return HPHI_OK;
+}
+
+} // namespace
+
+int launch_spin_blk(hphi_ham *h, const MultArgs &m, int *done)
+{
+    *done = 0;
+    if (m.nvec * dtype_lanes(m.dtype) != 1 || m.raw_out || m.dots || m.cocg) return HPHI_OK;
+    const bool f32 = dtype_is_f32(m.dtype);
+    HPHI_TRY(blk_tables(h, f32 ? 4 : 8));
+    if (!h->blk.ok || h->blk.n_blocks == 0) return HPHI_OK;
+    HPHI_TRY(f32 ? launch_blk_t<float>(h, m) : launch_blk_t<double>(h, m));
+    *done = 1;
+    return HPHI_OK;
+}
+
+} // namespace hphi
