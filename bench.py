@@ -507,11 +507,15 @@ def main():
         wl = {"workload": "j1j2_square_6x6_J2_0.5_sz0", "dim": basis.dim, "lanczos_iters": iters,
               "storage": "f32 vectors, f64 alpha/beta"}
         a.no_tune = True
-        # a product takes seconds here: every tenth step reports on stderr
+        if not a.schedule:
+            # block-staged product: a block of states in LDS per workgroup
+            ham.set_schedule(spin_split=2)
+        # a product takes about a second here: every tenth step reports on stderr
         os.environ["HPHI_PROGRESS"] = "1"
-        out, e32 = run_lanczos(a, api, ham, basis.dim, iters, "f32", wl,
-                               "H*v = k_spin_hv_implicit<float> (implicit basis, 64-bit indices)", "f32",
-                               check_every=10)
+        kname = ("H*v = k_spin_blk<float> (implicit basis, blocks of one high pattern staged in LDS, "
+                 "partner positions from tables) + k_dots_xy_yy<float>" if ham.get_schedule()["spin_split"] == 2
+                 else "H*v = k_spin_hv_implicit<float> (implicit basis, 64-bit indices)")
+        out, e32 = run_lanczos(a, api, ham, basis.dim, iters, "f32", wl, kname, "f32", check_every=10)
         torch.cuda.empty_cache()
         r64 = api.lanczos(ham, iters, seed=1, storage="f64", check_every=10, tol=0.0)
         out["e0_fp64_storage"] = float(r64["energies"][0])

@@ -365,10 +365,12 @@ void hphi_ham_free(hphi_ham *h);
  *                   list, as 1. -1: one pass (the default). The products
  *                   equal the one-pass ones up to summation order.
  *   spin_blk_lo     split point (sites in the low part) of spin_split 2;
- *                   -1 = the most low sites whose largest block fits LDS
- *                   (the default, at most the basis's own split); a
- *                   choice whose blocks do not fit returns UNSUPPORTED
- *                   from the product.
+ *                   -1 = the most low sites (at most the basis's own split)
+ *                   whose largest block leaves room in a CU's LDS for three
+ *                   workgroups with 4-byte values, five with 8-byte ones
+ *                   (the default); a forced choice whose largest block
+ *                   does not fit LDS at all returns UNSUPPORTED from the
+ *                   product.
  * Errors: INVALID_ARG (value outside its range), UNSUPPORTED (hub_sweep 7
  * or hub_tile_bits for blocks the tile kernel cannot take). */
 typedef struct {

@@ -51,11 +51,22 @@ struct BlkKArgs {
     const double *coef;
 };
 
-constexpr int kBlkThreads = 1024;
-constexpr int kBatch = 8;
+// Occupancy, not the block size, sets the pace (each position waits on
+// chains of table loads, LDS reads and gathers): 512-thread workgroups,
+// three per CU for 4-byte values, 256-thread workgroups, five per CU, for
+// 8-byte values (more registers per lane); the split point is chosen so
+// that a block leaves room for that many (36-site J1-J2 sector: FP32 H*v
+// 1.17 s with one 1024-thread workgroup per CU and blocks of 17 low sites,
+// 0.89 s with three of 512 and 16 low sites; FP64 1.35 s against 1.20 s
+// with five of 256 and 14 low sites).
+constexpr int kBlkMaxThreads = 512;
+constexpr int kBatch = 16;
+constexpr size_t kCuLds = 160 * 1024;
+int blk_threads(int esize) { return esize == 4 ? 512 : 256; }
+int blk_per_cu(int esize) { return esize == 4 ? 3 : 5; }
 
 template <typename S>
-__global__ __launch_bounds__(kBlkThreads) void k_spin_blk(BlkKArgs a)
+__global__ __launch_bounds__(kBlkMaxThreads) void k_spin_blk(BlkKArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     S *blk = reinterpret_cast<S *>(smem_raw);
@@ -94,16 +105,17 @@ __global__ __launch_bounds__(kBlkThreads) void k_spin_blk(BlkKArgs a)
         const uint32_t g0 = loff[k];
         const uint64_t base = hoff[hh];
         // stage the block: four loads in flight per thread
-        for (uint32_t p0 = tid; p0 < L; p0 += 4 * kBlkThreads) {
+        const uint32_t nt = blockDim.x;
+        for (uint32_t p0 = tid; p0 < L; p0 += 4 * nt) {
             S t[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const uint32_t p = p0 + (uint32_t)r * kBlkThreads;
+                const uint32_t p = p0 + (uint32_t)r * nt;
                 t[r] = p < L ? v[base + p] : (S)0;
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const uint32_t p = p0 + (uint32_t)r * kBlkThreads;
+                const uint32_t p = p0 + (uint32_t)r * nt;
                 if (p < L) blk[p] = t[r];
             }
         }
@@ -119,7 +131,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_spin_blk(BlkKArgs a)
         if (a.hz)
             for (int i = a.n_lo; i < a.n_sites; ++i)
                 dgh -= (S)a.hz[i] * (((hh >> (i - a.n_lo)) & 1u) ? (S)0.5 : (S)-0.5);
-        for (uint32_t p = tid; p < L; p += kBlkThreads) {
+        for (uint32_t p = tid; p < L; p += nt) {
             const uint32_t g = g0 + p;
             const uint32_t l = lol[g];
             S acc = (S)0, dg = dgh;
@@ -250,8 +262,11 @@ uint64_t blk_max_len(int n_bits, int n_pop, int nl)
     return m;
 }
 
-// 160 KB of LDS per workgroup on gfx950, less the kernel's own shared words
-constexpr size_t kBlkLdsBudget = 160 * 1024 - 256;
+// LDS of a block: at most all of a CU's 160 KB less the kernel's own shared
+// words for a forced split point, a share that leaves room for
+// blk_per_cu workgroups for the automatic one
+constexpr size_t kBlkLdsMax = kCuLds - 256;
+size_t blk_lds_share(int esize) { return kCuLds / (size_t)blk_per_cu(esize) - 256; }
 
 // Split point, tables and bond lists for element size esize (4 or 8 bytes).
 int blk_tables(hphi_ham *h, int esize)
@@ -260,7 +275,7 @@ int blk_tables(hphi_ham *h, int esize)
     const Species &s = h->basis->sp[0];
     const int N = s.n_bits, np = s.n_pop, want = h->sched_cfg.spin_blk_lo;
     if (B.built && B.esize == esize && B.want == want) return HPHI_OK;
-    const size_t budget = kBlkLdsBudget;
+    const size_t budget = want > 0 ? kBlkLdsMax : blk_lds_share(esize);
     int nl = 0;
     if (want > 0) {
         if (want > N || want > 24 || N - want > 24 || blk_max_len(N, np, want) * (uint64_t)esize > budget)
@@ -395,10 +410,11 @@ int launch_blk_t(hphi_ham *h, const MultArgs &m)
     const size_t lds = (size_t)B.max_len * sizeof(S);
     HPHI_HIP(hipFuncSetAttribute((const void *)k_spin_blk<S>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int ncu = h->basis->ctx->n_cu > 0 ? h->basis->ctx->n_cu : 256;
-    const uint32_t per_cu = lds <= 40 * 1024 ? 2u : 1u;
+    const uint32_t fit = (uint32_t)(kCuLds / (lds + 256));
+    const uint32_t per_cu = std::max(1u, std::min((uint32_t)blk_per_cu((int)sizeof(S)), fit));
     uint32_t grid = (uint32_t)ncu * per_cu;
     if (grid > B.n_blocks) grid = B.n_blocks;
-    hipLaunchKernelGGL((k_spin_blk<S>), dim3(grid), dim3(kBlkThreads), lds, m.stream, a);
+    hipLaunchKernelGGL((k_spin_blk<S>), dim3(grid), dim3(blk_threads((int)sizeof(S))), lds, m.stream, a);
     HPHI_HIP(hipGetLastError());
     return HPHI_OK;
 }
