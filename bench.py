@@ -513,7 +513,7 @@ def main():
         # a product takes about a second here: every tenth step reports on stderr
         os.environ["HPHI_PROGRESS"] = "1"
         kname = ("H*v = k_spin_blk<float> (implicit basis, blocks of one high pattern staged in LDS, "
-                 "partner positions from tables) + k_dots_xy_yy<float>" if ham.get_schedule()["spin_split"] == 2
+                 "partner positions from tables) + k_dots_xy_yy<float>" if ham.get_schedule()["spin_split"] in (2, 3)
                  else "H*v = k_spin_hv_implicit<float> (implicit basis, 64-bit indices)")
         out, e32 = run_lanczos(a, api, ham, basis.dim, iters, "f32", wl, kname, "f32", check_every=10)
         torch.cuda.empty_cache()

@@ -362,8 +362,11 @@ void hphi_ham_free(hphi_ham *h);
  *                   the partner block, bonds across read one position of
  *                   the partner block from a per-site table; where no split
  *                   point gives blocks that fit LDS, as 1; on the stored
- *                   list, as 1. -1: one pass (the default). The products
+ *                   list, as 1. 3 (the default): 2 on the implicit basis,
+ *                   one pass on the stored list. -1: one pass. The products
  *                   equal the one-pass ones up to summation order.
+ *                   hphi_lanczos_noalloc always takes one pass (the other
+ *                   layouts build device tables on first use).
  *   spin_blk_lo     split point (sites in the low part) of spin_split 2;
  *                   -1 = the most low sites (at most the basis's own split)
  *                   whose largest block leaves room in a CU's LDS for three
@@ -516,7 +519,9 @@ int hphi_lanczos(hphi_ham *h, const hphi_lanczos_opts *opts, double *energies,
  * S(n) = n rounded up to 256, r = refine_steps (16 when 0),
  * elem = 8 (F64) or 4 (F32): FP64 solves up to about 2.79e6 states (a
  * 24-site chain at Sz = 0). The library clears what must start at zero on
- * each call. Every call on a device shares that device's array: a call
+ * each call. Spin products run in one pass whatever spin_split says (the
+ * other layouts build device tables on first use). Every call on a
+ * device shares that device's array: a call
  * that starts while another one holds it (from another thread) returns
  * HPHI_ERR_BUSY; calls must not overlap on one device. Synchronous.
  * Errors: INVALID_ARG (a workspace need above the array, use_graph or

@@ -1137,9 +1137,9 @@ int hphi_ham_set_schedule(hphi_ham *h, const hphi_schedule *s)
         n.spin_tables = s->spin_tables == -1 ? 0 : s->spin_tables;
     }
     if (s->spin_split) {
-        if (s->spin_split != -1 && s->spin_split != 1 && s->spin_split != 2)
+        if (s->spin_split != -1 && (s->spin_split < 1 || s->spin_split > 3))
             return fail(HPHI_ERR_INVALID_ARG, "spin_split %d", s->spin_split);
-        n.spin_split = s->spin_split == -1 ? 0 : s->spin_split;
+        n.spin_split = s->spin_split;
     }
     if (s->spin_blk_lo) {
         if (s->spin_blk_lo != -1 && (s->spin_blk_lo < 1 || s->spin_blk_lo > 24))
@@ -1312,7 +1312,7 @@ struct LanczosRun {
     int setup(int max_iter, Carve *ws = nullptr)
     {
         fused = !cview && h->kind == 1 && (dt == HPHI_F64 || dt == HPHI_F32) && hub_rows_fused_ok(h, 1);
-        sep_dots = cview || (h->kind == 0 && h->sched_cfg.spin_split != 0);
+        sep_dots = cview || (h->kind == 0 && spin_split_mode(h, !spin_stored_path(h)) != 0);
         cols = ld = dim;
         if (h->kind == 1 && !cview) {
             cols = h->basis->sp[1].dim;
@@ -1736,6 +1736,11 @@ int hphi_lanczos_noalloc(hphi_ham *h, const hphi_lanczos_opts *o, double *energi
         int d;
         ~Release() { noalloc_scratch_release(d); }
     } rel{dev};
+    struct NoAllocMark {
+        hphi_ham *h;
+        ~NoAllocMark() { h->noalloc_call = false; }
+    } mark{h};
+    h->noalloc_call = true;
     Carve ws(p, kNoAllocScratchBytes);
     return lanczos_impl(h, o, energies, n_energies, info, &ws);
 }

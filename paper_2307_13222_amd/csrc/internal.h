@@ -317,6 +317,7 @@ struct hphi_ham {
     // spin: bonds split into high-half and other bonds (built on first use)
     hphi::SpinSplit split;
     hphi::SpinBlk blk;
+    bool noalloc_call = false;   // inside hphi_lanczos_noalloc
     // spin-S: bonds as given (jz, jxy), fields and single-ion terms
     std::vector<hphi_spin_bond> sbonds;
     std::vector<double> s_hz, s_dion;
@@ -324,7 +325,7 @@ struct hphi_ham {
     // defaults: 128-column slabs, 128 workgroups per XCD, 32-row items,
     // hop-ordered down slots, work-item queues with two columns per lane;
     // spin: 8 workgroups per CU
-    hphi_schedule sched_cfg{128, 128, 16, 6, 8, 0, 5, 2, 0, 0, 0, 0};
+    hphi_schedule sched_cfg{128, 128, 16, 6, 8, 0, 5, 2, 0, 0, 3, 0};
     // scratch for reductions and work queues
     hphi::DevMem sched;         // unsigned [16]: per-XCD item queues + counter
     hphi::DevMem red_partial;   // double [kReduceSlots]
@@ -450,6 +451,12 @@ struct MultArgs {
 };
 bool hub_rows_fused_ok(hphi_ham *h, int nv);
 bool spin_stored_path(const hphi_ham *h);
+// Spin product layout for the schedule in force: 0 one pass, 1 two passes
+// by bond locality, 2 block-staged (implicit basis). spin_split 3 (the
+// default) means 2 on the implicit basis and one pass on the stored list;
+// calls that must not allocate take one pass (the other layouts build
+// device tables on first use).
+int spin_split_mode(const hphi_ham *h, bool implicit);
 int launch_spin_mult(hphi_ham *h, const MultArgs &a);
 int launch_spin_mult_implicit(hphi_ham *h, const MultArgs &a);
 int spin_split_tables(hphi_ham *h);

@@ -151,9 +151,10 @@ int launch_spin_mult_implicit(hphi_ham *h, const MultArgs &m)
     // half and the fields here into w, then the high-half bonds and the
     // caller's epilogue in slab order (their gathers are contiguous runs
     // of one block of the same class)
-    bool split = h->sched_cfg.spin_split != 0 && !m.dots && !m.cocg && m.v != m.w && (!m.u || m.u != m.w) &&
+    const int mode = spin_split_mode(h, true);
+    bool split = mode != 0 && !m.dots && !m.cocg && m.v != m.w && (!m.u || m.u != m.w) &&
                  (!m.acc || m.acc != m.w);
-    if (split && h->sched_cfg.spin_split == 2) {
+    if (split && mode == 2) {
         int done = 0;
         HPHI_TRY(launch_spin_blk(h, m, &done));
         if (done) return HPHI_OK;

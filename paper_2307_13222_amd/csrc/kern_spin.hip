@@ -359,6 +359,14 @@ bool spin_stored_path(const hphi_ham *h)
     return s.materialized() && s.state_bytes == 4 && s.d_hi_off32.p && !h->sched_cfg.spin_implicit;
 }
 
+int spin_split_mode(const hphi_ham *h, bool implicit)
+{
+    const int c = h->sched_cfg.spin_split;
+    if (h->noalloc_call || c < 0) return 0;
+    if (c == 1 || c == 2) return c;
+    return implicit ? 2 : 0;
+}
+
 int launch_spin_mult(hphi_ham *h, const MultArgs &m)
 {
     const hphi_basis *b = h->basis;
@@ -430,7 +438,7 @@ int launch_spin_mult(hphi_ham *h, const MultArgs &m)
     if (grid < 1) grid = 1;
     // split product: the bonds with an end in the low half into w, then
     // the high-half bonds and the caller's epilogue in slab order
-    bool split = h->sched_cfg.spin_split != 0 && !m.dots && !m.cocg && m.v != m.w && (!m.u || m.u != m.w) &&
+    bool split = spin_split_mode(h, false) != 0 && !m.dots && !m.cocg && m.v != m.w && (!m.u || m.u != m.w) &&
                  (!m.acc || m.acc != m.w) && (!m.raw_out || m.raw_out != m.w);
     if (split) {
         HPHI_TRY(spin_split_tables(h));

@@ -1,5 +1,5 @@
 """GPU: the block-staged spin product on the implicit basis (schedule
-spin_split = 2: a workgroup stages the block of one high pattern in LDS;
+spin_split = 2, and the default 3 there: a workgroup stages the block of one high pattern in LDS;
 low bonds read partners there, high bonds read the same positions of the
 partner block, bonds across the split read one position of it) against the
 oracle and the one-pass product. Split points below, at and above the
@@ -115,6 +115,27 @@ def test_blk_lanczos(api, ctx, n, lo):
     assert abs(r32["energies"][0] - r1["energies"][0]) < 1e-4 * abs(r1["energies"][0])
 
 
+def test_blk_is_the_implicit_default(api, ctx):
+    # schedule spin_split 3 (the default): block-staged on the implicit
+    # basis, one pass on the stored list
+    import torch
+    say("block-staged default")
+    m = W.xxz_chain_j2(18)
+    h = api.Hamiltonian.spin(api.Basis.spin(ctx, 18, 0), m)
+    assert h.get_schedule()["spin_split"] == 3
+    v = dev(W.random_vector(math.comb(18, 9), 5))
+    w_list = host(h.mult(v))
+    h.set_schedule(spin_split=-1)
+    assert np.array_equal(host(h.mult(v)), w_list)
+    h.set_schedule(spin_implicit=1, spin_split=3)
+    w_auto = host(h.mult(v))
+    h.set_schedule(spin_split=2)
+    assert np.array_equal(host(h.mult(v)), w_auto)
+    h.set_schedule(spin_split=-1)
+    assert relmax(host(h.mult(v)), w_auto) < 1e-13
+    torch.cuda.synchronize()
+
+
 def test_blk_split_point_errors(api, ctx):
     import torch
     say("block-staged split point errors")
@@ -122,7 +143,7 @@ def test_blk_split_point_errors(api, ctx):
     with pytest.raises(Exception):
         h.set_schedule(spin_blk_lo=25)
     with pytest.raises(Exception):
-        h.set_schedule(spin_split=3)
+        h.set_schedule(spin_split=4)
     # all 20 sites in one block of C(20, 10) FP64 values: beyond LDS
     h.set_schedule(spin_implicit=1, spin_split=2, spin_blk_lo=20)
     v = torch.ones(math.comb(20, 10), dtype=torch.float64, device="cuda")

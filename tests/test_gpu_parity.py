@@ -190,6 +190,11 @@ def test_spin_implicit_basis_matches_oracle(api, ctx, case):
     w_imp = host(h.mult(dev(v)))
     assert relmax(w_imp, O.spin_hv(m, s, v)) < 1e-12
     assert relmax(w_imp, w_list) < 1e-14
+    # the default layout there is block-staged; the one-pass kernel too
+    h.set_schedule(spin_split=-1)
+    w_one = host(h.mult(dev(v)))
+    assert relmax(w_one, O.spin_hv(m, s, v)) < 1e-12
+    h.set_schedule(spin_split=3)
     r1 = api.lanczos(h, 60, seed=3)
     h.set_schedule(spin_implicit=-1)
     r2 = api.lanczos(h, 60, seed=3)
@@ -202,6 +207,9 @@ def test_spin_36_sites_sampled_rows_fp32(api, ctx):
     m = W.j1j2_square(6, 6, 1.0, 0.5)
     b = api.Basis.spin(ctx, 36, 0)
     h = api.Hamiltonian.spin(b, m)
+    # the one-pass implicit kernel (the block-staged default has its own
+    # full-size test)
+    h.set_schedule(spin_split=-1)
     dim = b.dim
     g = torch.Generator(device="cuda").manual_seed(5)
     v = torch.rand(dim, dtype=torch.float32, device="cuda", generator=g) - 0.5

@@ -73,6 +73,21 @@ def test_noalloc_fp32_refined_and_hubbard(api, ctx):
     _same(api.lanczos(h, 50, seed=3), api.lanczos(h, 50, seed=3, no_alloc=True))
 
 
+def test_noalloc_implicit_basis_takes_one_pass(api, ctx):
+    # on the implicit basis the default spin layout builds device tables on
+    # first use; the entry point that allocates nothing takes the one-pass
+    # product instead, so it matches hphi_lanczos with spin_split = -1
+    say("no-alloc lanczos: implicit basis")
+    h = api.Hamiltonian.spin(api.Basis.spin(ctx, 16, 0), W.xxz_chain_j2(16))
+    h.set_schedule(spin_implicit=1)
+    got = api.lanczos(h, 60, seed=4, no_alloc=True)
+    h.set_schedule(spin_split=-1)
+    _same(api.lanczos(h, 60, seed=4), got)
+    h.set_schedule(spin_split=3)
+    auto = api.lanczos(h, 60, seed=4)
+    assert abs(auto["energies"][0] - got["energies"][0]) < 1e-10
+
+
 def test_noalloc_rejects_oversized_and_unsupported(api, ctx):
     from paper_2307_13222_amd import _lib as L
     say("no-alloc lanczos: limits")
