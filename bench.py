@@ -760,6 +760,10 @@ def run_ctpq(a, api, ctx, W):
           "k_steps": k_steps, "storage": "c64 (FP32 complex), f64 norms"}
     if a.schedule:
         ham.set_schedule(**json.loads(a.schedule))
+    else:
+        # block-staged product: the block of one high pattern in LDS per
+        # workgroup (the stored list's default is the one-pass kernel)
+        ham.set_schedule(spin_split=2)
     if not a.no_tune:
         wl["schedule"] = autotune.tune(ham, "c64", nv, force=a.retune)["schedule"]
     else:
@@ -803,7 +807,9 @@ def run_ctpq(a, api, ctx, W):
                 "ctpq_run_ms_p50": round(1e3 * float(np.percentile(lat, 50)), 3),
                 "max_abs_dE_fp32_vs_fp64": dE, "max_abs_dlogN_fp32_vs_fp64": dlogN,
                 "E_beta_final_mean": float(np.mean(res["E"][-1])),
-                "roofline": roofline(gbs, alg_bytes, "block H*V = k_spin_hv<float,32> (16 complex vectors)")})
+                "roofline": roofline(gbs, alg_bytes, ("block H*V = k_spin_blk_v<float,32> (16 complex vectors; blocks of one "
+                                                      "high pattern staged in LDS)") if wl["schedule"].get("spin_split") == 2
+                                     else "block H*V = k_spin_hv<float,32> (16 complex vectors)")})
     return out
 
 

@@ -353,16 +353,18 @@ void hphi_ham_free(hphi_ham *h);
  *                   state's high-bond partners sit at the same position of
  *                   another block of its class); products without fused
  *                   dots, at most 128 high bonds; otherwise one pass.
- *                   2: on the implicit basis (one real vector, no fused
- *                   dots), one pass over blocks of states: a workgroup
+ *                   2: one pass over blocks of states (products without
+ *                   fused dots; on the implicit basis the only product for
+ *                   vector blocks and complex vectors): a workgroup
  *                   stages the block of one high pattern in LDS, bonds
  *                   inside the low part read their partners there (partner
  *                   positions from per-bond tables over the low patterns),
  *                   bonds inside the high part read the same positions of
  *                   the partner block, bonds across read one position of
  *                   the partner block from a per-site table; where no split
- *                   point gives blocks that fit LDS, as 1; on the stored
- *                   list, as 1. 3 (the default): 2 on the implicit basis,
+ *                   point gives blocks that fit LDS, as 1 on the stored
+ *                   list and UNSUPPORTED on the implicit basis for several
+ *                   lanes. 3 (the default): 2 on the implicit basis,
  *                   one pass on the stored list. -1: one pass. The products
  *                   equal the one-pass ones up to summation order.
  *                   hphi_lanczos_noalloc always takes one pass (the other

@@ -118,8 +118,20 @@ int launch_spin_mult_implicit(hphi_ham *h, const MultArgs &m)
 {
     const hphi_basis *b = h->basis;
     const Species &s = b->sp[0];
-    if (m.nvec * dtype_lanes(m.dtype) != 1)
-        return fail(HPHI_ERR_UNSUPPORTED, "implicit-basis H*v runs one real vector per call");
+    const int mode = spin_split_mode(h, true);
+    const bool apart = m.v != m.w && (!m.u || m.u != m.w) && (!m.acc || m.acc != m.w);
+    if (m.nvec * dtype_lanes(m.dtype) != 1) {
+        // several lanes per state (vector blocks, complex vectors): the
+        // block-staged product only
+        if (mode == 2 && !m.dots && !m.cocg && apart) {
+            int done = 0;
+            HPHI_TRY(launch_spin_blk(h, m, &done));
+            if (done) return HPHI_OK;
+        }
+        return fail(HPHI_ERR_UNSUPPORTED,
+                    "implicit-basis H*v: several lanes per state need the block-staged product (schedule spin_split 2 "
+                    "or 3, no fused dots)");
+    }
     BigKArgs a{};
     a.dim = s.dim;
     a.hi_off = s.d_hi_off.as<uint64_t>();
@@ -151,9 +163,7 @@ int launch_spin_mult_implicit(hphi_ham *h, const MultArgs &m)
     // half and the fields here into w, then the high-half bonds and the
     // caller's epilogue in slab order (their gathers are contiguous runs
     // of one block of the same class)
-    const int mode = spin_split_mode(h, true);
-    bool split = mode != 0 && !m.dots && !m.cocg && m.v != m.w && (!m.u || m.u != m.w) &&
-                 (!m.acc || m.acc != m.w);
+    bool split = mode != 0 && !m.dots && !m.cocg && apart;
     if (split && mode == 2) {
         int done = 0;
         HPHI_TRY(launch_spin_blk(h, m, &done));

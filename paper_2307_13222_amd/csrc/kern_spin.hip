@@ -438,8 +438,14 @@ int launch_spin_mult(hphi_ham *h, const MultArgs &m)
     if (grid < 1) grid = 1;
     // split product: the bonds with an end in the low half into w, then
     // the high-half bonds and the caller's epilogue in slab order
-    bool split = spin_split_mode(h, false) != 0 && !m.dots && !m.cocg && m.v != m.w && (!m.u || m.u != m.w) &&
+    const int mode = spin_split_mode(h, false);
+    bool split = mode != 0 && !m.dots && !m.cocg && m.v != m.w && (!m.u || m.u != m.w) &&
                  (!m.acc || m.acc != m.w) && (!m.raw_out || m.raw_out != m.w);
+    if (split && mode == 2) {
+        int done = 0;
+        HPHI_TRY(launch_spin_blk(h, m, &done));
+        if (done) return HPHI_OK;
+    }
     if (split) {
         HPHI_TRY(spin_split_tables(h));
         split = h->split.n_hi_bonds > 0 && h->split.n_hi_bonds <= kMaxHiBonds;

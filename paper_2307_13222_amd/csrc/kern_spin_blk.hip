@@ -49,6 +49,8 @@ struct BlkKArgs {
     const void *u;
     void *acc_out;
     const double *coef;
+    void *raw_out;       // several lanes per state: H v before the epilogue (optional)
+    int coef_cplx;       // several lanes per state: complex (c1, c2) on lane pairs
 };
 
 // Occupancy, not the block size, sets the pace (each position waits on
@@ -58,12 +60,16 @@ struct BlkKArgs {
 // that a block leaves room for that many (36-site J1-J2 sector: FP32 H*v
 // 1.17 s with one 1024-thread workgroup per CU and blocks of 17 low sites,
 // 0.89 s with three of 512 and 16 low sites; FP64 1.35 s against 1.20 s
-// with five of 256 and 14 low sites).
+// with five of 256 and 14 low sites). States of 16 bytes or more (blocks
+// of vectors) take two 512-thread workgroups per CU (28-site block of 16
+// complex64 vectors: 19.6 ms with blocks of 11 low sites, two per CU;
+// 22.2 ms with 10 low sites, 26.6 ms with 9, 31.1 ms with 12 and one per
+// CU).
 constexpr int kBlkMaxThreads = 512;
 constexpr int kBatch = 16;
 constexpr size_t kCuLds = 160 * 1024;
-int blk_threads(int esize) { return esize == 4 ? 512 : 256; }
-int blk_per_cu(int esize) { return esize == 4 ? 3 : 5; }
+int blk_threads(int esize) { return esize == 8 ? 256 : 512; }
+int blk_per_cu(int esize) { return esize == 4 ? 3 : esize == 8 ? 5 : 2; }
 
 template <typename S>
 __global__ __launch_bounds__(kBlkMaxThreads) void k_spin_blk(BlkKArgs a)
@@ -244,6 +250,255 @@ __global__ __launch_bounds__(kBlkMaxThreads) void k_spin_blk(BlkKArgs a)
     }
 }
 
+// Several real lanes per state (a block of vectors, complex vectors): the
+// same walk with LPS lanes per state, each holding VPT consecutive values
+// (16 bytes where the state has that many); the LDS block holds whole
+// states, so every partner read is one 16-byte piece per lane.
+constexpr int kBatchV = 8;
+
+template <typename S, int VPT>
+__device__ __forceinline__ void ld_piece(const S *p, S (&o)[VPT])
+{
+    if constexpr (VPT * sizeof(S) == 16) {
+        const float4 t = *reinterpret_cast<const float4 *>(p);
+        __builtin_memcpy(o, &t, 16);
+    } else if constexpr (VPT * sizeof(S) == 8) {
+        const float2 t = *reinterpret_cast<const float2 *>(p);
+        __builtin_memcpy(o, &t, 8);
+    } else {
+#pragma unroll
+        for (int j = 0; j < VPT; ++j) o[j] = p[j];
+    }
+}
+template <typename S, int VPT>
+__device__ __forceinline__ void st_piece(S *p, const S (&o)[VPT])
+{
+    if constexpr (VPT * sizeof(S) == 16) {
+        float4 t;
+        __builtin_memcpy(&t, o, 16);
+        *reinterpret_cast<float4 *>(p) = t;
+    } else if constexpr (VPT * sizeof(S) == 8) {
+        float2 t;
+        __builtin_memcpy(&t, o, 8);
+        *reinterpret_cast<float2 *>(p) = t;
+    } else {
+#pragma unroll
+        for (int j = 0; j < VPT; ++j) p[j] = o[j];
+    }
+}
+
+template <typename S, int NV>
+__global__ __launch_bounds__(kBlkMaxThreads) void k_spin_blk_v(BlkKArgs a)
+{
+    constexpr int VPT = (NV * (int)sizeof(S) >= 16) ? 16 / (int)sizeof(S) : NV;
+    constexpr int LPS = NV / VPT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    S *blk = reinterpret_cast<S *>(smem_raw);
+    __shared__ unsigned s_i;
+    __shared__ unsigned s_last;
+    typedef const __attribute__((address_space(4))) uint64_t CU64;
+    typedef const __attribute__((address_space(4))) uint32_t CU32;
+    typedef const __attribute__((address_space(4))) LoBondDev CLB;
+    typedef const __attribute__((address_space(4))) XBondDev CXB;
+    typedef const __attribute__((address_space(4))) HiBondDev CHB;
+    const CU64 *hoff = (const CU64 *)a.hi_off;
+    const CU32 *hlist = (const CU32 *)a.hi_list;
+    const CU32 *clen = (const CU32 *)a.cls_len;
+    const CU32 *loff = (const CU32 *)a.lo_off;
+    const CLB *lob = (const CLB *)a.lob;
+    const CXB *xb = (const CXB *)a.xb;
+    const CHB *hib = (const CHB *)a.hib;
+    const S *__restrict__ v = static_cast<const S *>(a.v);
+    S *__restrict__ w = static_cast<S *>(a.w);
+    const S *__restrict__ u = static_cast<const S *>(a.u);
+    S *__restrict__ accp = static_cast<S *>(a.acc_out);
+    S *__restrict__ rawp = static_cast<S *>(a.raw_out);
+    const uint16_t *__restrict__ tab = a.tab;
+    const uint32_t *__restrict__ lol = a.lo_list;
+    const int tid = threadIdx.x, sub = tid % LPS;
+    const uint32_t nt = blockDim.x, sp = nt / LPS, ps = (uint32_t)tid / LPS;
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_i = atomicAdd(&a.sched[0], 1u);
+        __syncthreads();
+        const unsigned bi = __builtin_amdgcn_readfirstlane(s_i);
+        if (bi >= a.n_blocks) break;
+        const uint32_t hh = hlist[bi];
+        const int k = __builtin_popcount(hh);
+        const uint32_t L = clen[k];
+        const uint32_t g0 = loff[k];
+        const uint64_t base = hoff[hh];
+        // stage the block's states, VPT values per piece, four in flight
+        const uint32_t npc = L * LPS;
+        const S *vb = v + base * NV;
+        for (uint32_t c0 = tid; c0 < npc; c0 += 4 * nt) {
+            S t[4][VPT];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t c = c0 + (uint32_t)r * nt;
+                if (c < npc) ld_piece<S, VPT>(vb + (size_t)c * VPT, t[r]);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t c = c0 + (uint32_t)r * nt;
+                if (c < npc) st_piece<S, VPT>(blk + (size_t)c * VPT, t[r]);
+            }
+        }
+        __syncthreads();
+        S dgh = (S)0;
+        for (int b = 0; b < a.nhib; ++b) {
+            const uint32_t mk = hib[b].mask;
+            const uint32_t t = hh & mk;
+            dgh += (t == 0u || t == mk) ? (S)hib[b].jz4 : -(S)hib[b].jz4;
+        }
+        if (a.hz)
+            for (int i = a.n_lo; i < a.n_sites; ++i)
+                dgh -= (S)a.hz[i] * (((hh >> (i - a.n_lo)) & 1u) ? (S)0.5 : (S)-0.5);
+        for (uint32_t p = ps; p < L; p += sp) {
+            const uint32_t g = g0 + p;
+            const uint32_t l = lol[g];
+            S acc[VPT];
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) acc[j] = (S)0;
+            S dg = dgh;
+            if (a.hz)
+                for (int i = 0; i < a.n_lo; ++i) dg -= (S)a.hz[i] * (((l >> i) & 1u) ? (S)0.5 : (S)-0.5);
+            // bonds inside the low part: partners in LDS
+            for (int b0 = 0; b0 < a.nlob; b0 += kBatchV) {
+                uint32_t q[kBatchV];
+                S cf[kBatchV];
+                unsigned anti = 0u;
+#pragma unroll
+                for (int t = 0; t < kBatchV; ++t) {
+                    q[t] = 0u;
+                    cf[t] = (S)0;
+                    const int b = b0 + t;
+                    if (b < a.nlob) {
+                        const uint32_t mk = lob[b].mask;
+                        const uint32_t tt = l & mk;
+                        const S jz = (S)lob[b].jz4;
+                        if (tt == 0u || tt == mk) {
+                            dg += jz;
+                        } else {
+                            dg -= jz;
+                            anti |= 1u << t;
+                            cf[t] = (S)lob[b].jxy2;
+                        }
+                        q[t] = tab[(uint64_t)lob[b].row * a.pitch + g];
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < kBatchV; ++t)
+                    if (anti & (1u << t)) {
+                        S x[VPT];
+                        ld_piece<S, VPT>(blk + (size_t)q[t] * NV + sub * VPT, x);
+#pragma unroll
+                        for (int j = 0; j < VPT; ++j) acc[j] += cf[t] * x[j];
+                    }
+            }
+            // bonds across the split: one state of a partner block
+            for (int b0 = 0; b0 < a.nxb; b0 += kBatchV) {
+                uint64_t src[kBatchV];
+                S cf[kBatchV], val[kBatchV][VPT];
+                unsigned anti = 0u;
+#pragma unroll
+                for (int t = 0; t < kBatchV; ++t) {
+                    src[t] = 0;
+                    cf[t] = (S)0;
+                    const int b = b0 + t;
+                    if (b < a.nxb) {
+                        const uint32_t hbit = xb[b].hbit;
+                        const uint64_t pb = hoff[hh ^ (1u << hbit)];
+                        const uint32_t q = tab[(uint64_t)xb[b].row * a.pitch + g];
+                        const uint32_t hb = (hh >> hbit) & 1u;
+                        const uint32_t lb = (l >> xb[b].lbit) & 1u;
+                        const S jz = (S)xb[b].jz4;
+                        if (hb == lb) {
+                            dg += jz;
+                        } else {
+                            dg -= jz;
+                            anti |= 1u << t;
+                            cf[t] = (S)xb[b].jxy2;
+                            src[t] = pb + q;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < kBatchV; ++t) {
+                    if (anti & (1u << t)) ld_piece<S, VPT>(v + src[t] * NV + sub * VPT, val[t]);
+                    else
+#pragma unroll
+                        for (int j = 0; j < VPT; ++j) val[t][j] = (S)0;
+                }
+#pragma unroll
+                for (int t = 0; t < kBatchV; ++t)
+                    if (anti & (1u << t))
+#pragma unroll
+                        for (int j = 0; j < VPT; ++j) acc[j] += cf[t] * val[t][j];
+            }
+            // bonds inside the high part: the same state of a partner block
+            for (int b0 = 0; b0 < a.nhib; b0 += kBatchV) {
+                uint64_t src[kBatchV];
+                S cf[kBatchV], val[kBatchV][VPT];
+                unsigned anti = 0u;
+#pragma unroll
+                for (int t = 0; t < kBatchV; ++t) {
+                    src[t] = 0;
+                    cf[t] = (S)0;
+                    const int b = b0 + t;
+                    if (b < a.nhib) {
+                        const uint32_t mk = hib[b].mask;
+                        const uint32_t tt = hh & mk;
+                        if (tt != 0u && tt != mk) {
+                            anti |= 1u << t;
+                            cf[t] = (S)hib[b].jxy2;
+                            src[t] = hoff[hh ^ mk] + p;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < kBatchV; ++t) {
+                    if (anti & (1u << t)) ld_piece<S, VPT>(v + src[t] * NV + sub * VPT, val[t]);
+                    else
+#pragma unroll
+                        for (int j = 0; j < VPT; ++j) val[t][j] = (S)0;
+                }
+#pragma unroll
+                for (int t = 0; t < kBatchV; ++t)
+                    if (anti & (1u << t))
+#pragma unroll
+                        for (int j = 0; j < VPT; ++j) acc[j] += cf[t] * val[t][j];
+            }
+            S me_v[VPT], hv[VPT], uu[VPT], out[VPT];
+            ld_piece<S, VPT>(blk + (size_t)p * NV + sub * VPT, me_v);
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                hv[j] = acc[j] + dg * me_v[j];
+                uu[j] = (S)0;
+            }
+            const size_t me = (size_t)(base + p) * NV + (size_t)sub * VPT;
+            if (u) ld_piece<S, VPT>(u + me, uu);
+            epilogue_r<S, VPT>(hv, uu, u != nullptr, a.coef_cplx, a.coef, out);
+            st_piece<S, VPT>(w + me, out);
+            if (rawp) st_piece<S, VPT>(rawp + me, hv);
+            if (accp) {
+#pragma unroll
+                for (int j = 0; j < VPT; ++j) accp[me + j] += out[j];
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        s_last = (atomicAdd(&a.sched[1], 1u) == gridDim.x - 1) ? 1u : 0u;
+        if (s_last) {
+            a.sched[0] = 0u;
+            a.sched[1] = 0u;
+            __threadfence();
+        }
+    }
+}
+
 uint64_t binom_small(int n, int k)
 {
     if (k < 0 || n < 0 || k > n) return 0;
@@ -268,7 +523,7 @@ uint64_t blk_max_len(int n_bits, int n_pop, int nl)
 constexpr size_t kBlkLdsMax = kCuLds - 256;
 size_t blk_lds_share(int esize) { return kCuLds / (size_t)blk_per_cu(esize) - 256; }
 
-// Split point, tables and bond lists for element size esize (4 or 8 bytes).
+// Split point, tables and bond lists for esize bytes per state.
 int blk_tables(hphi_ham *h, int esize)
 {
     SpinBlk &B = h->blk;
@@ -279,7 +534,7 @@ int blk_tables(hphi_ham *h, int esize)
     int nl = 0;
     if (want > 0) {
         if (want > N || want > 24 || N - want > 24 || blk_max_len(N, np, want) * (uint64_t)esize > budget)
-            return fail(HPHI_ERR_UNSUPPORTED, "spin_blk_lo %d: blocks of %d-byte elements do not fit LDS", want, esize);
+            return fail(HPHI_ERR_UNSUPPORTED, "spin_blk_lo %d: blocks of %d-byte states do not fit LDS", want, esize);
         nl = want;
     } else {
         for (int n = std::min(s.n_lo, 24); n >= 1 && N - n <= 24; --n)
@@ -379,7 +634,7 @@ int blk_tables(hphi_ham *h, int esize)
     return HPHI_OK;
 }
 
-template <typename S>
+template <typename S, int NV>
 int launch_blk_t(hphi_ham *h, const MultArgs &m)
 {
     const SpinBlk &B = h->blk;
@@ -407,14 +662,23 @@ int launch_blk_t(hphi_ham *h, const MultArgs &m)
     a.u = m.u;
     a.acc_out = m.acc;
     a.coef = m.coef;
-    const size_t lds = (size_t)B.max_len * sizeof(S);
-    HPHI_HIP(hipFuncSetAttribute((const void *)k_spin_blk<S>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    a.raw_out = m.raw_out;
+    a.coef_cplx = m.coef_cplx;
+    constexpr int esize = NV * (int)sizeof(S);
+    const size_t lds = (size_t)B.max_len * esize;
+    const void *kern;
+    if constexpr (NV == 1) kern = (const void *)k_spin_blk<S>;
+    else kern = (const void *)k_spin_blk_v<S, NV>;
+    HPHI_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int ncu = h->basis->ctx->n_cu > 0 ? h->basis->ctx->n_cu : 256;
     const uint32_t fit = (uint32_t)(kCuLds / (lds + 256));
-    const uint32_t per_cu = std::max(1u, std::min((uint32_t)blk_per_cu((int)sizeof(S)), fit));
+    const uint32_t per_cu = std::max(1u, std::min((uint32_t)blk_per_cu(esize), fit));
     uint32_t grid = (uint32_t)ncu * per_cu;
     if (grid > B.n_blocks) grid = B.n_blocks;
-    hipLaunchKernelGGL((k_spin_blk<S>), dim3(grid), dim3(blk_threads((int)sizeof(S))), lds, m.stream, a);
+    if constexpr (NV == 1)
+        hipLaunchKernelGGL((k_spin_blk<S>), dim3(grid), dim3(blk_threads(esize)), lds, m.stream, a);
+    else
+        hipLaunchKernelGGL((k_spin_blk_v<S, NV>), dim3(grid), dim3(blk_threads(esize)), lds, m.stream, a);
     HPHI_HIP(hipGetLastError());
     return HPHI_OK;
 }
@@ -424,11 +688,22 @@ int launch_blk_t(hphi_ham *h, const MultArgs &m)
 int launch_spin_blk(hphi_ham *h, const MultArgs &m, int *done)
 {
     *done = 0;
-    if (m.nvec * dtype_lanes(m.dtype) != 1 || m.raw_out || m.dots || m.cocg) return HPHI_OK;
+    const int nv = m.nvec * dtype_lanes(m.dtype);
+    if (m.dots || m.cocg || (nv == 1 && m.raw_out)) return HPHI_OK;
+    if (nv != 1 && nv != 2 && nv != 4 && nv != 8 && nv != 16 && nv != 32) return HPHI_OK;
     const bool f32 = dtype_is_f32(m.dtype);
-    HPHI_TRY(blk_tables(h, f32 ? 4 : 8));
+    HPHI_TRY(blk_tables(h, nv * (f32 ? 4 : 8)));
     if (!h->blk.ok || h->blk.n_blocks == 0) return HPHI_OK;
-    HPHI_TRY(f32 ? launch_blk_t<float>(h, m) : launch_blk_t<double>(h, m));
+    int rc = HPHI_OK;
+    switch (nv) {
+    case 1: rc = f32 ? launch_blk_t<float, 1>(h, m) : launch_blk_t<double, 1>(h, m); break;
+    case 2: rc = f32 ? launch_blk_t<float, 2>(h, m) : launch_blk_t<double, 2>(h, m); break;
+    case 4: rc = f32 ? launch_blk_t<float, 4>(h, m) : launch_blk_t<double, 4>(h, m); break;
+    case 8: rc = f32 ? launch_blk_t<float, 8>(h, m) : launch_blk_t<double, 8>(h, m); break;
+    case 16: rc = f32 ? launch_blk_t<float, 16>(h, m) : launch_blk_t<double, 16>(h, m); break;
+    default: rc = f32 ? launch_blk_t<float, 32>(h, m) : launch_blk_t<double, 32>(h, m); break;
+    }
+    HPHI_TRY(rc);
     *done = 1;
     return HPHI_OK;
 }

@@ -188,3 +188,65 @@ def test_blk_36_sites_sampled_rows(api, ctx, dt):
     assert worst < (2e-6 if dt == "f32" else 1e-13), worst
     del v, w
     torch.cuda.empty_cache()
+
+
+# blocks of vectors and complex vectors, stored list and implicit basis
+VCASES = [("xxz_j2_16", 16, 0, 4, "c128", False), ("ladder_14_field", 14, 0, 16, "c64", False),
+          ("chain_15", 15, 1, 1, "c128", True), ("j1j2_16", 16, 0, 8, "f32", True),
+          ("xxz_j2_18", 18, 0, 16, "c64", False), ("chain_13", 13, 3, 2, "f64", False)]
+
+
+@pytest.mark.parametrize("name,n,two_sz,nvec,dt,implicit", VCASES,
+                         ids=[f"{c[0]}-{c[3]}x{c[4]}-{'imp' if c[5] else 'list'}" for c in VCASES])
+def test_blk_vector_blocks_vs_oracle(api, ctx, name, n, two_sz, nvec, dt, implicit):
+    import torch
+    say("block-staged vector blocks", name, nvec, dt, implicit)
+    m = model(name, n)
+    h = api.Hamiltonian.spin(api.Basis.spin(ctx, n, two_sz), m)
+    h.set_schedule(spin_split=2, spin_implicit=1 if implicit else -1)
+    s = O.basis_list(n, O.sector_popcount_spin(n, two_sz))
+    cplx = dt.startswith("c")
+    v = W.random_vector(len(s), 13, np.complex128 if cplx else np.float64, nvec=nvec)
+    if v.ndim == 1:
+        v = v[:, None]
+    tdt = {"c128": torch.complex128, "c64": torch.complex64, "f64": torch.float64, "f32": torch.float32}[dt]
+    vt = dev(v).to(tdt)
+    if nvec == 1:
+        vt = vt[:, 0].contiguous()
+    w = host(h.mult(vt)).reshape(len(s), nvec)
+    ref = O.spin_hv(m, s, host(vt).reshape(len(s), nvec).astype(np.complex128 if cplx else np.float64))
+    assert relmax(w, ref) < (1e-12 if dt in ("c128", "f64") else 3e-6)
+    h.set_schedule(spin_split=-1)
+    if implicit and (cplx or nvec > 1):
+        # the one-pass implicit kernel takes one real vector only
+        with pytest.raises(api.HphiError, match="block-staged"):
+            h.mult(vt)
+        return
+    w1 = host(h.mult(vt)).reshape(len(s), nvec)
+    assert relmax(w, w1) < (1e-13 if dt in ("c128", "f64") else 2e-6)
+
+
+def test_blk_ctpq_and_time_evolution(api, ctx):
+    # the caller's epilogues through the block-staged product on a stored
+    # list: cTPQ (real coefficients, the first order's raw product) and
+    # real-time steps (complex coefficients) against the oracle
+    say("block-staged ctpq / time evolution")
+    m = W.xxz_chain_j2(16)
+    h = api.Hamiltonian.spin(api.Basis.spin(ctx, 16, 0), m)
+    h.set_schedule(spin_split=2)
+    s = O.basis_list(16, 8)
+    phi = np.stack([O.splitmix_complex_gaussian(30 + j, len(s)) for j in range(4)], axis=1)
+    g = api.ctpq(h, 4, 6, 0.02, 10, phi0=dev(phi))
+    o = O.ctpq(lambda x: O.spin_hv(m, s, x), phi, 6, 0.02, 10)
+    assert relmax(g["D"], o["D"]) < 1e-11 and relmax(g["E"], o["E"]) < 1e-11 and relmax(g["E2"], o["E2"]) < 1e-11
+    m2 = W.random_heisenberg(12, "ladder", 8)
+    h2 = api.Hamiltonian.spin(api.Basis.spin(ctx, 12, 0), m2)
+    h2.set_schedule(spin_split=2)
+    s2 = O.basis_list(12, 6)
+    phi0 = np.stack([O.splitmix_complex_gaussian(300 + j, len(s2)) for j in range(2)], axis=1)
+    psi = dev(phi0)
+    t = api.time_evolve(h2, psi, 20, dt=0.02, n_max=8)
+    ot = O.taylor_evolve(lambda x: O.spin_hv(m2, s2, x), phi0, 8, 0.02, 20)
+    assert np.max(np.abs(t["norm"] - ot["norm"]) / ot["norm"]) < 1e-12
+    assert np.max(np.abs(t["energy"] - ot["energy"])) < 1e-10
+    assert relmax(host(psi), ot["psi"]) < 1e-11
