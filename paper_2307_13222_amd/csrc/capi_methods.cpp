@@ -52,7 +52,10 @@ int hphi_ctpq(hphi_ham *h, const hphi_ctpq_opts *o, void *phi_dev, double *D_out
     // pass takes <phi|H phi>, |H phi|^2 from it (the same FP32/FP64 values
     // the fused dots would use; the block kernel with 2 x nl FP64 dot
     // accumulators per thread runs far fewer waves)
-    const bool raw_dots = h->kind == 0 && nl >= 8 && spin_stored_path(h);
+    // (on the implicit basis the block-staged product, the one there for
+    // several lanes, has no fused dots: the same streaming pass)
+    const bool raw_dots = h->kind == 0 && ((nl >= 8 && spin_stored_path(h)) ||
+                                           (!spin_stored_path(h) && spin_split_mode(h, true) == 2));
     if (raw_dots) HPHI_TRY(yraw.alloc(bytes));
     HPHI_TRY(scal.alloc(sizeof(double) * (2 * (size_t)o->n_max + 2 + 64)));
     HPHI_TRY(res_first.alloc(sizeof(double) * 2 * 64));
@@ -203,9 +206,13 @@ int hphi_time_evolve(hphi_ham *h, const hphi_tevol_opts *o, void *psi_dev, doubl
     const int dt = o->storage, nv = o->n_vec, nl = 2 * nv;
     const int64_t dim = h->basis->dim;
     const size_t bytes = (size_t)dim * nl * dtype_size(dt);
-    DevMem y1, y2, scal, res_e, res_n, res_d;
+    DevMem y1, y2, yraw, scal, res_e, res_n, res_d;
     HPHI_TRY(y1.alloc(bytes));
     HPHI_TRY(y2.alloc(bytes));
+    // spin sectors on the implicit basis run the block-staged product, which
+    // has no fused dots: <psi|H psi> from its raw output by a streaming pass
+    const bool raw_e = h->kind == 0 && !spin_stored_path(h) && spin_split_mode(h, true) == 2;
+    if (raw_e) HPHI_TRY(yraw.alloc(bytes));
     HPHI_TRY(scal.alloc(sizeof(double) * 4 * ((size_t)o->n_max + 1)));
     HPHI_TRY(res_e.alloc(sizeof(double) * 2 * 64));
     HPHI_TRY(res_n.alloc(sizeof(double) * 2 * 64));
@@ -246,11 +253,12 @@ int hphi_time_evolve(hphi_ham *h, const hphi_tevol_opts *o, void *psi_dev, doubl
             a.nvec = nv;
             a.v = A;
             a.w = Y[0];
-            a.dots = 1;
+            a.dots = raw_e ? 0 : 1;
             a.dot_raw = 1;
             a.red = reduce_at(h, res_e.as<double>());
             a.stream = st;
             HPHI_TRY(launch_mult(h, a));
+            if (raw_e) HPHI_TRY(launch_dots_xy_yy(dt, nl, dim, A, Y[0], reduce_at(h, res_e.as<double>()), st));
         } else {
             const void *src = A;
             int yb = 0;
@@ -264,14 +272,17 @@ int hphi_time_evolve(hphi_ham *h, const hphi_tevol_opts *o, void *psi_dev, doubl
                 a.coef = d_coef + 4 * n;
                 a.coef_cplx = 1;
                 a.stream = st;
-                if (n == o->n_max) {
+                if (n == o->n_max && !raw_e) {
                     a.dots = 1;     // <psi, H psi> rides on the first product
                     a.dot_raw = 1;
                     a.red = reduce_at(h, res_e.as<double>());
                 } else {
                     a.red = reduce_at(h, h->red_result.as<double>());
+                    if (n == o->n_max) a.raw_out = yraw.p;
                 }
                 HPHI_TRY(launch_mult(h, a));
+                if (n == o->n_max && raw_e)
+                    HPHI_TRY(launch_dots_xy_yy(dt, nl, dim, A, yraw.p, reduce_at(h, res_e.as<double>()), st));
                 src = Y[yb];
                 yb ^= 1;
             }

@@ -372,7 +372,8 @@ int launch_spin_mult(hphi_ham *h, const MultArgs &m)
     const hphi_basis *b = h->basis;
     const Species &s = b->sp[0];
     if (!spin_stored_path(h)) {
-        if (m.raw_out) return fail(HPHI_ERR_UNSUPPORTED, "raw product output needs the stored-list spin kernel");
+        if (m.raw_out && m.nvec * dtype_lanes(m.dtype) == 1)
+            return fail(HPHI_ERR_UNSUPPORTED, "raw product output of one real vector needs the stored-list spin kernel");
         return launch_spin_mult_implicit(h, m);
     }
     SpinKArgs a{};
