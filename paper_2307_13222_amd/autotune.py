@@ -31,9 +31,12 @@ def candidates(ham, quick: bool = False) -> List[Dict[str, int]]:
     over tile splits (hub_tile_bits: -1 = the fewest top sites whose blocks
     fit LDS, or a few more: smaller blocks, more far hops) and T_dn variants,
     and the slab kernels (hub_sweep 3, 5; slab width, workgroups per XCD,
-    rows per item, row order). Spin: placement of the rank tables (LDS
-    32-bit, LDS narrowed, global) x workgroups per CU. Candidates the
-    Hamiltonian cannot take are skipped when timed."""
+    rows per item, row order). Spin: the one-pass kernel over placements of
+    the rank tables (LDS 32-bit, LDS narrowed, global) x workgroups per CU,
+    and the block-staged product over split points (-1 = its own choice).
+    Every candidate sets the layout (spin_split), since a schedule keeps
+    the fields a candidate leaves out. Candidates the Hamiltonian cannot
+    take are skipped when timed."""
     if ham.basis.kind == "hubbard":
         out = []
         bits = (-1, 5) if quick else (-1, 3, 5, 6)
@@ -47,7 +50,10 @@ def candidates(ham, quick: bool = False) -> List[Dict[str, int]]:
                         "hub_sweep": sw, "hub_row_order": ro})
         return out
     per = (2, 8) if quick else (1, 2, 4, 8, 16)
-    return [{"spin_tables": t, "spin_per_cu": p} for t in (1, 2, 3) for p in per]
+    out = [{"spin_split": -1, "spin_tables": t, "spin_per_cu": p} for t in (1, 2, 3) for p in per]
+    los = (-1,) if quick else (-1, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17)
+    out += [{"spin_split": 2, "spin_blk_lo": lo} for lo in los if lo < ham.basis.n_sites]
+    return out
 
 
 def time_mult(ham, v, w, reps: int = 5) -> float:

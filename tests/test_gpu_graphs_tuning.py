@@ -112,12 +112,15 @@ def test_autotune_sweep_and_record(api, ctx, tmp_path):
     assert relmax(host(h.mult(dev(v))), O.hubbard_hv(m, ups, dns, v)) < 1e-12
     r2 = autotune.tune(h, "f64", 1, table=table)
     assert not r2["swept"] and r2["schedule"] == r["schedule"]
-    # spin: rank-table placement x workgroups per CU, and the block width of
-    # a batched product
+    # spin: the one-pass kernel (rank-table placement x workgroups per CU)
+    # against the block-staged product, for a batched product; every
+    # candidate names its layout
     ms = W.xxz_chain_j2(18)
     hs = api.Hamiltonian.spin(api.Basis.spin(ctx, 18, 0), ms)
-    rs = autotune.tune(hs, "c64", 8, reps=3, table=table, cands=autotune.candidates(hs, quick=True))
-    assert rs["swept"] and "spin_tables" in rs["schedule"]
+    cs = autotune.candidates(hs, quick=True)
+    assert all("spin_split" in c for c in cs) and any(c["spin_split"] == 2 for c in cs)
+    rs = autotune.tune(hs, "c64", 8, reps=3, table=table, cands=cs)
+    assert rs["swept"] and hs.get_schedule()["spin_split"] == rs["schedule"]["spin_split"]
     s = O.basis_list(18, 9)
     vb = W.random_vector(len(s), 92, np.complex128, nvec=8)
     vt = dev(vb).to(torch.complex64)
