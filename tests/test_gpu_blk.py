@@ -273,3 +273,26 @@ def test_blk_implicit_basis_complex_methods(api, ctx):
     assert np.max(np.abs(t["norm"] - ot["norm"]) / ot["norm"]) < 1e-12
     assert np.max(np.abs(t["energy"] - ot["energy"])) < 1e-10
     assert relmax(host(psi), ot["psi"]) < 1e-11
+
+
+def test_blk_graph_replay(api, ctx):
+    # the block-staged product inside captured steps (its tables are built
+    # by the eager first step; its queue counters re-arm themselves):
+    # replays equal the eager runs bit for bit
+    import torch
+    say("block-staged graph replay")
+    m = W.xxz_chain_j2(16)
+    h = api.Hamiltonian.spin(api.Basis.spin(ctx, 16, 0), m)
+    h.set_schedule(spin_implicit=1)
+    r0 = api.lanczos(h, 40, seed=3)
+    r1 = api.lanczos(h, 40, seed=3, use_graph=True)
+    assert np.array_equal(r0["alpha"], r1["alpha"]) and np.array_equal(r0["beta"], r1["beta"])
+    phi = np.stack([O.splitmix_complex_gaussian(50 + j, math.comb(16, 8)) for j in range(2)], axis=1)
+    a, b = dev(phi), dev(phi)
+    t0 = api.time_evolve(h, a, 6, dt=0.02, n_max=6)
+    t1 = api.time_evolve(h, b, 6, dt=0.02, n_max=6, use_graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and np.array_equal(t0["energy"], t1["energy"])
+    c0 = api.ctpq(h, 2, 4, 0.02, 6, phi0=dev(phi))
+    c1 = api.ctpq(h, 2, 4, 0.02, 6, phi0=dev(phi), use_graph=True)
+    assert np.array_equal(c0["E"], c1["E"]) and np.array_equal(c0["D"], c1["D"])
