@@ -296,3 +296,36 @@ def test_blk_graph_replay(api, ctx):
     c0 = api.ctpq(h, 2, 4, 0.02, 6, phi0=dev(phi))
     c1 = api.ctpq(h, 2, 4, 0.02, 6, phi0=dev(phi), use_graph=True)
     assert np.array_equal(c0["E"], c1["E"]) and np.array_equal(c0["D"], c1["D"])
+
+
+@pytest.mark.parametrize("case", ["all_up_16", "one_down_17", "ising_ladder_14", "long_range_15"])
+def test_blk_edge_sectors_and_bonds(api, ctx, case):
+    # degenerate sectors (one state, one flipped spin), Ising bonds (no
+    # flips) and bonds across the whole chain (every split point cuts
+    # them) through the block-staged default on the implicit basis
+    import dataclasses
+    say("block-staged edge", case)
+    if case == "all_up_16":
+        m, two_sz = W.xxz_chain_j2(16), 16
+        m.hz = np.linspace(-1.0, 1.0, 16)
+    elif case == "one_down_17":
+        m, two_sz = W.random_heisenberg(17, "chain", 2), 15
+    elif case == "ising_ladder_14":
+        m0 = W.random_heisenberg(14, "ladder", 3)
+        m, two_sz = dataclasses.replace(m0, jxy=np.zeros_like(m0.jxy)), 0
+    else:
+        rng = np.random.default_rng(15)
+        bi = np.arange(15)
+        bj = (bi + 7) % 15
+        m = W.SpinModel(15, np.concatenate([bi, bi]), np.concatenate([bj, (bi + 1) % 15]),
+                        rng.uniform(0.5, 1.5, 30), rng.uniform(0.5, 1.5, 30))
+        two_sz = 1
+    n = m.n_sites
+    h = api.Hamiltonian.spin(api.Basis.spin(ctx, n, two_sz), m)
+    h.set_schedule(spin_implicit=1)
+    s = O.basis_list(n, O.sector_popcount_spin(n, two_sz))
+    v = W.random_vector(len(s), 17)
+    w = host(h.mult(dev(v)))
+    assert relmax(w, O.spin_hv(m, s, v)) < 1e-12
+    h.set_schedule(spin_split=-1)
+    assert relmax(host(h.mult(dev(v))), w) < 1e-13
