@@ -1,6 +1,8 @@
-// Spin-1/2 XXZ H*v on an implicit sector basis, one block of states at a
-// time (HPhi update paper Sec. 3.2 Heisenberg model; the Lanczos runs on
-// sectors of about 10^10 states that motivate Sec. 1).
+// Spin-1/2 XXZ H*v one block of states at a time (HPhi update paper Sec.
+// 3.2 Heisenberg model; the Lanczos runs on sectors of about 10^10 states
+// that motivate Sec. 1, and the cTPQ blocks of Sec. 3.5.1). It needs no
+// stored state list: the default on the implicit basis, and a schedule
+// choice on the stored one.
 //
 // A split point n_lo of the sites (chosen so that a block fits LDS; it need
 // not be the basis's own) cuts a state x into (h, l). The basis order is
@@ -19,7 +21,10 @@
 //     position comes from a per-site table over the low patterns, and the
 //     lanes' partner positions ascend with p.
 // No configuration is unranked and no rank table is searched per flip. The
-// caller's epilogue (w = c1 H v + c2 u, accumulation) is applied at the end.
+// caller's epilogue (w = c1 H v + c2 u with real or complex coefficients,
+// accumulation, the raw product) is applied at the end. Sums are in bond
+// order within each kind (low, crossing, high), so they equal the one-pass
+// products up to summation order.
 #include "kern_common.h"
 
 #include <algorithm>
