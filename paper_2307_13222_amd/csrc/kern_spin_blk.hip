@@ -60,12 +60,13 @@ struct BlkKArgs {
 
 // Occupancy, not the block size, sets the pace (each position waits on
 // chains of table loads, LDS reads and gathers): 512-thread workgroups,
-// three per CU for 4-byte values, 256-thread workgroups, five per CU, for
-// 8-byte values (more registers per lane); the split point is chosen so
-// that a block leaves room for that many (36-site J1-J2 sector: FP32 H*v
-// 1.17 s with one 1024-thread workgroup per CU and blocks of 17 low sites,
-// 0.89 s with three of 512 and 16 low sites; FP64 1.35 s against 1.20 s
-// with five of 256 and 14 low sites). States of 16 bytes or more (blocks
+// four per CU for 4-byte values (eight waves per SIMD), 256-thread
+// workgroups, five per CU, for 8-byte values (more registers per lane);
+// the split point is chosen so that a block leaves room for that many
+// (36-site J1-J2 sector: FP32 H*v 1.17 s with one 1024-thread workgroup
+// per CU and blocks of 17 low sites, 0.89 s with three of 512 and 16 low
+// sites, 0.81 s with four of 512 and 15 low sites; FP64 1.35 s against
+// 1.20 s with five of 256 and 14 low sites). States of 16 bytes or more (blocks
 // of vectors) take two 512-thread workgroups per CU (28-site block of 16
 // complex64 vectors: 19.6 ms with blocks of 11 low sites, two per CU;
 // 22.2 ms with 10 low sites, 26.6 ms with 9, 31.1 ms with 12 and one per
@@ -74,10 +75,13 @@ constexpr int kBlkMaxThreads = 512;
 constexpr int kBatch = 16;
 constexpr size_t kCuLds = 160 * 1024;
 int blk_threads(int esize) { return esize == 8 ? 256 : 512; }
-int blk_per_cu(int esize) { return esize == 4 ? 3 : esize == 8 ? 5 : 2; }
+int blk_per_cu(int esize) { return esize == 4 ? 4 : esize == 8 ? 5 : 2; }
 
+// 4-byte values: registers held to 64 VGPRs and the scalar registers of
+// eight waves per SIMD (no spills), so four 512-thread workgroups share a CU
 template <typename S>
-__global__ __launch_bounds__(kBlkMaxThreads) void k_spin_blk(BlkKArgs a)
+__global__ __launch_bounds__(kBlkMaxThreads) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 4 ? 8 : 1, 8)))
+void k_spin_blk(BlkKArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     S *blk = reinterpret_cast<S *>(smem_raw);
