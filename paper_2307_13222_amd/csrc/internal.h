@@ -157,7 +157,7 @@ struct XBondDev {
     double jz4, jxy2;
 };
 struct SpinBlk {
-    bool built = false, ok = false;
+    bool built = false, ok = false, f32 = false;
     int n_lo = 0, esize = 0, want = 0;
     int n_lob = 0, n_xb = 0, n_hib = 0;
     uint32_t n_blocks = 0, max_len = 0;

@@ -60,22 +60,23 @@ struct BlkKArgs {
 
 // Occupancy, not the block size, sets the pace (each position waits on
 // chains of table loads, LDS reads and gathers): 512-thread workgroups,
-// four per CU for 4-byte values (eight waves per SIMD), 256-thread
-// workgroups, five per CU, for 8-byte values (more registers per lane);
+// four per CU for FP32 values (eight waves per SIMD), 256-thread
+// workgroups, five per CU, for FP64 values (more registers per lane);
 // the split point is chosen so that a block leaves room for that many
 // (36-site J1-J2 sector: FP32 H*v 1.17 s with one 1024-thread workgroup
 // per CU and blocks of 17 low sites, 0.89 s with three of 512 and 16 low
 // sites, 0.81 s with four of 512 and 15 low sites; FP64 1.35 s against
-// 1.20 s with five of 256 and 14 low sites). States of 16 bytes or more (blocks
-// of vectors) take two 512-thread workgroups per CU (28-site block of 16
-// complex64 vectors: 19.6 ms with blocks of 11 low sites, two per CU;
-// 22.2 ms with 10 low sites, 26.6 ms with 9, 31.1 ms with 12 and one per
-// CU).
+// 1.20 s with five of 256 and 14 low sites). FP32 states of several lanes
+// (blocks of vectors) also take four 512-thread workgroups at eight waves
+// per SIMD, with a few registers spilled (28-site block of 16 complex64
+// vectors: 17.6 ms with blocks of 10 low sites; 19.6 ms with 11 low sites
+// and two per CU at five waves per SIMD, 22.2 ms with 10 low sites there,
+// 31.1 ms with 12 and one per CU); FP64 ones two per CU.
 constexpr int kBlkMaxThreads = 512;
 constexpr int kBatch = 16;
 constexpr size_t kCuLds = 160 * 1024;
-int blk_threads(int esize) { return esize == 8 ? 256 : 512; }
-int blk_per_cu(int esize) { return esize == 4 ? 4 : esize == 8 ? 5 : 2; }
+int blk_threads(int esize, bool f32) { return !f32 && esize == 8 ? 256 : 512; }
+int blk_per_cu(int esize, bool f32) { return f32 ? 4 : esize == 8 ? 5 : 2; }
 
 // 4-byte values: registers held to 64 VGPRs and the scalar registers of
 // eight waves per SIMD (no spills), so four 512-thread workgroups share a CU
@@ -297,7 +298,8 @@ __device__ __forceinline__ void st_piece(S *p, const S (&o)[VPT])
 }
 
 template <typename S, int NV>
-__global__ __launch_bounds__(kBlkMaxThreads) void k_spin_blk_v(BlkKArgs a)
+__global__ __launch_bounds__(kBlkMaxThreads) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 4 ? 8 : 1, 8)))
+void k_spin_blk_v(BlkKArgs a)
 {
     constexpr int VPT = (NV * (int)sizeof(S) >= 16) ? 16 / (int)sizeof(S) : NV;
     constexpr int LPS = NV / VPT;
@@ -530,16 +532,16 @@ uint64_t blk_max_len(int n_bits, int n_pop, int nl)
 // words for a forced split point, a share that leaves room for
 // blk_per_cu workgroups for the automatic one
 constexpr size_t kBlkLdsMax = kCuLds - 256;
-size_t blk_lds_share(int esize) { return kCuLds / (size_t)blk_per_cu(esize) - 256; }
+size_t blk_lds_share(int esize, bool f32) { return kCuLds / (size_t)blk_per_cu(esize, f32) - 256; }
 
 // Split point, tables and bond lists for esize bytes per state.
-int blk_tables(hphi_ham *h, int esize)
+int blk_tables(hphi_ham *h, int esize, bool f32)
 {
     SpinBlk &B = h->blk;
     const Species &s = h->basis->sp[0];
     const int N = s.n_bits, np = s.n_pop, want = h->sched_cfg.spin_blk_lo;
-    if (B.built && B.esize == esize && B.want == want) return HPHI_OK;
-    const size_t budget = want > 0 ? kBlkLdsMax : blk_lds_share(esize);
+    if (B.built && B.esize == esize && B.f32 == f32 && B.want == want) return HPHI_OK;
+    const size_t budget = want > 0 ? kBlkLdsMax : blk_lds_share(esize, f32);
     int nl = 0;
     if (want > 0) {
         if (want > N || want > 24 || N - want > 24 || blk_max_len(N, np, want) * (uint64_t)esize > budget)
@@ -554,6 +556,7 @@ int blk_tables(hphi_ham *h, int esize)
     }
     B.built = true;
     B.esize = esize;
+    B.f32 = f32;
     B.want = want;
     B.ok = nl > 0;
     if (!B.ok) return HPHI_OK;
@@ -681,13 +684,14 @@ int launch_blk_t(hphi_ham *h, const MultArgs &m)
     HPHI_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int ncu = h->basis->ctx->n_cu > 0 ? h->basis->ctx->n_cu : 256;
     const uint32_t fit = (uint32_t)(kCuLds / (lds + 256));
-    const uint32_t per_cu = std::max(1u, std::min((uint32_t)blk_per_cu(esize), fit));
+    constexpr bool f32 = sizeof(S) == 4;
+    const uint32_t per_cu = std::max(1u, std::min((uint32_t)blk_per_cu(esize, f32), fit));
     uint32_t grid = (uint32_t)ncu * per_cu;
     if (grid > B.n_blocks) grid = B.n_blocks;
     if constexpr (NV == 1)
-        hipLaunchKernelGGL((k_spin_blk<S>), dim3(grid), dim3(blk_threads(esize)), lds, m.stream, a);
+        hipLaunchKernelGGL((k_spin_blk<S>), dim3(grid), dim3(blk_threads(esize, f32)), lds, m.stream, a);
     else
-        hipLaunchKernelGGL((k_spin_blk_v<S, NV>), dim3(grid), dim3(blk_threads(esize)), lds, m.stream, a);
+        hipLaunchKernelGGL((k_spin_blk_v<S, NV>), dim3(grid), dim3(blk_threads(esize, f32)), lds, m.stream, a);
     HPHI_HIP(hipGetLastError());
     return HPHI_OK;
 }
@@ -701,7 +705,7 @@ int launch_spin_blk(hphi_ham *h, const MultArgs &m, int *done)
     if (m.dots || m.cocg || (nv == 1 && m.raw_out)) return HPHI_OK;
     if (nv != 1 && nv != 2 && nv != 4 && nv != 8 && nv != 16 && nv != 32) return HPHI_OK;
     const bool f32 = dtype_is_f32(m.dtype);
-    HPHI_TRY(blk_tables(h, nv * (f32 ? 4 : 8)));
+    HPHI_TRY(blk_tables(h, nv * (f32 ? 4 : 8), f32));
     if (!h->blk.ok || h->blk.n_blocks == 0) return HPHI_OK;
     int rc = HPHI_OK;
     switch (nv) {
