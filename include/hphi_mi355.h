@@ -405,6 +405,10 @@ int hphi_ham_trace(hphi_ham *h, double *trace_out, void *stream);
  * the product at the core of every Krylov and power method (Sec. 1).
  * Real types hold nvec real vectors, complex types nvec complex vectors.
  * F32 / C64 store in float and accumulate each row in float.
+ * Spin sectors without a stored state list (more than 32 sites or 2^32
+ * states) take several lanes per state (vector blocks, complex vectors)
+ * only through the block-staged layout (schedule spin_split 2 or the
+ * default 3), whose largest block must fit LDS; otherwise UNSUPPORTED.
  * Asynchronous on `stream`. v_dev and w_dev must not alias.
  * Errors: INVALID_ARG (nvec < 1 or > 32, null pointers), UNSUPPORTED,
  * DEVICE. */
