@@ -186,6 +186,7 @@ void k_spin_blk(BlkKArgs a)
                 uint64_t src[kBatch];
                 S cf[kBatch], val[kBatch];
                 unsigned anti = 0u;
+                uint32_t qlast = 0u, rlast = 0xffffffffu;
 #pragma unroll
                 for (int t = 0; t < kBatch; ++t) {
                     src[t] = 0;
@@ -194,7 +195,12 @@ void k_spin_blk(BlkKArgs a)
                     if (b < a.nxb) {
                         const uint32_t hbit = xb[b].hbit;
                         const uint64_t pb = hoff[hh ^ (1u << hbit)];
-                        const uint32_t q = tab[(uint64_t)xb[b].row * a.pitch + g];
+                        const uint32_t row = xb[b].row;
+                        if (row != rlast) {
+                            qlast = tab[(uint64_t)row * a.pitch + g];
+                            rlast = row;
+                        }
+                        const uint32_t q = qlast;
                         const uint32_t hb = (hh >> hbit) & 1u;
                         const uint32_t lb = (l >> xb[b].lbit) & 1u;
                         const S jz = (S)xb[b].jz4;
@@ -601,6 +607,9 @@ int blk_tables(hphi_ham *h, int esize, bool f32)
     }
     const uint32_t n_lob = (uint32_t)lob.size();
     for (XBondDev &d : xb) d.row = n_lob + (uint32_t)site_row[d.lbit];
+    // bonds of one low site next to each other: a batch loads that site's
+    // partner positions once
+    std::stable_sort(xb.begin(), xb.end(), [](const XBondDev &x, const XBondDev &y) { return x.row < y.row; });
     // partner positions: low bond b at row b (rank of l ^ mask where the
     // bond is antiparallel, else 0); crossing site i at row n_lob + its
     // index (rank of l ^ bit i), over all low patterns by popcount group
