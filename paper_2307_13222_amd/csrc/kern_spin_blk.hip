@@ -88,6 +88,11 @@ void k_spin_blk(BlkKArgs a)
     S *blk = reinterpret_cast<S *>(smem_raw);
     __shared__ unsigned s_i;
     __shared__ unsigned s_last;
+    // the block's flipping high bonds, in bond order: partner block start
+    // and coefficient (the flips depend on h only)
+    __shared__ uint64_t s_hsrc[kMaxHiBonds];
+    __shared__ S s_hcf[kMaxHiBonds];
+    __shared__ unsigned s_wn[kMaxHiBonds / 64];
     // read-only tables at workgroup-uniform indices: scalar loads
     typedef const __attribute__((address_space(4))) uint64_t CU64;
     typedef const __attribute__((address_space(4))) uint32_t CU32;
@@ -138,6 +143,29 @@ void k_spin_blk(BlkKArgs a)
         __syncthreads();
         // the high bonds' diagonal and the high sites' fields: the same for
         // every state of the block
+        {
+            const int i = tid;
+            bool f = false;
+            uint32_t mk = 0u;
+            if (i < a.nhib) {
+                mk = a.hib[i].mask;
+                const uint32_t tt = hh & mk;
+                f = tt != 0u && tt != mk;
+            }
+            const uint64_t bal = __ballot(f);
+            const int lane = tid & 63;
+            if (i < kMaxHiBonds && lane == 0) s_wn[i >> 6] = (unsigned)__popcll(bal);
+            __syncthreads();
+            if (f) {
+                unsigned at = (unsigned)__popcll(bal & ((uint64_t(1) << lane) - 1));
+                for (int w = 0; w < (i >> 6); ++w) at += s_wn[w];
+                s_hsrc[at] = a.hi_off[hh ^ mk];
+                s_hcf[at] = (S)a.hib[i].jxy2;
+            }
+            __syncthreads();
+        }
+        int nha = 0;
+        for (int w = 0; w < (a.nhib + 63) / 64; ++w) nha += (int)s_wn[w];
         S dgh = (S)0;
         for (int b = 0; b < a.nhib; ++b) {
             const uint32_t mk = hib[b].mask;
@@ -220,31 +248,15 @@ void k_spin_blk(BlkKArgs a)
                 for (int t = 0; t < kBatch; ++t)
                     if (anti & (1u << t)) acc += cf[t] * val[t];
             }
-            // bonds inside the high part: the same position of a partner block
-            for (int b0 = 0; b0 < a.nhib; b0 += kBatch) {
-                uint64_t src[kBatch];
-                S cf[kBatch], val[kBatch];
-                unsigned anti = 0u;
+            // bonds inside the high part: the same position of a partner
+            // block, the block's flipping ones only
+            for (int b0 = 0; b0 < nha; b0 += kBatch) {
+                S val[kBatch];
 #pragma unroll
-                for (int t = 0; t < kBatch; ++t) {
-                    src[t] = 0;
-                    cf[t] = (S)0;
-                    const int b = b0 + t;
-                    if (b < a.nhib) {
-                        const uint32_t mk = hib[b].mask;
-                        const uint32_t tt = hh & mk;
-                        if (tt != 0u && tt != mk) {
-                            anti |= 1u << t;
-                            cf[t] = (S)hib[b].jxy2;
-                            src[t] = hoff[hh ^ mk] + p;
-                        }
-                    }
-                }
-#pragma unroll
-                for (int t = 0; t < kBatch; ++t) val[t] = (anti & (1u << t)) ? v[src[t]] : (S)0;
+                for (int t = 0; t < kBatch; ++t) val[t] = b0 + t < nha ? v[s_hsrc[b0 + t] + p] : (S)0;
 #pragma unroll
                 for (int t = 0; t < kBatch; ++t)
-                    if (anti & (1u << t)) acc += cf[t] * val[t];
+                    if (b0 + t < nha) acc += s_hcf[b0 + t] * val[t];
             }
             const S hv = acc + dg * blk[p];
             S out = c1s * hv;
@@ -634,6 +646,10 @@ int blk_tables(hphi_ham *h, int esize, bool f32)
         off[k] = sp->lo_list_off[c];
         for (uint32_t x = 0; x < (1u << nh); ++x)
             if (__builtin_popcount(x) == k) list.push_back(x);
+    }
+    if (hib.size() > (size_t)kMaxHiBonds) {   // the kernel lists a block's flipping high bonds in LDS
+        B.ok = false;
+        return HPHI_OK;
     }
     B.n_lob = (int)n_lob;
     B.n_xb = (int)xb.size();
