@@ -325,6 +325,9 @@ void k_spin_blk_v(BlkKArgs a)
     S *blk = reinterpret_cast<S *>(smem_raw);
     __shared__ unsigned s_i;
     __shared__ unsigned s_last;
+    __shared__ uint64_t s_hsrc[kMaxHiBonds];
+    __shared__ S s_hcf[kMaxHiBonds];
+    __shared__ unsigned s_wn[kMaxHiBonds / 64];
     typedef const __attribute__((address_space(4))) uint64_t CU64;
     typedef const __attribute__((address_space(4))) uint32_t CU32;
     typedef const __attribute__((address_space(4))) LoBondDev CLB;
@@ -374,6 +377,30 @@ void k_spin_blk_v(BlkKArgs a)
             }
         }
         __syncthreads();
+        // the block's flipping high bonds, in bond order (as k_spin_blk)
+        {
+            const int i = tid;
+            bool f = false;
+            uint32_t mk = 0u;
+            if (i < a.nhib) {
+                mk = a.hib[i].mask;
+                const uint32_t tt = hh & mk;
+                f = tt != 0u && tt != mk;
+            }
+            const uint64_t bal = __ballot(f);
+            const int lane = tid & 63;
+            if (i < kMaxHiBonds && lane == 0) s_wn[i >> 6] = (unsigned)__popcll(bal);
+            __syncthreads();
+            if (f) {
+                unsigned at = (unsigned)__popcll(bal & ((uint64_t(1) << lane) - 1));
+                for (int w = 0; w < (i >> 6); ++w) at += s_wn[w];
+                s_hsrc[at] = a.hi_off[hh ^ mk];
+                s_hcf[at] = (S)a.hib[i].jxy2;
+            }
+            __syncthreads();
+        }
+        int nha = 0;
+        for (int w = 0; w < (a.nhib + 63) / 64; ++w) nha += (int)s_wn[w];
         S dgh = (S)0;
         for (int b = 0; b < a.nhib; ++b) {
             const uint32_t mk = hib[b].mask;
@@ -465,38 +492,22 @@ void k_spin_blk_v(BlkKArgs a)
 #pragma unroll
                         for (int j = 0; j < VPT; ++j) acc[j] += cf[t] * val[t][j];
             }
-            // bonds inside the high part: the same state of a partner block
-            for (int b0 = 0; b0 < a.nhib; b0 += kBatchV) {
-                uint64_t src[kBatchV];
-                S cf[kBatchV], val[kBatchV][VPT];
-                unsigned anti = 0u;
+            // bonds inside the high part: the same state of a partner
+            // block, the block's flipping ones only
+            for (int b0 = 0; b0 < nha; b0 += kBatchV) {
+                S val[kBatchV][VPT];
 #pragma unroll
                 for (int t = 0; t < kBatchV; ++t) {
-                    src[t] = 0;
-                    cf[t] = (S)0;
-                    const int b = b0 + t;
-                    if (b < a.nhib) {
-                        const uint32_t mk = hib[b].mask;
-                        const uint32_t tt = hh & mk;
-                        if (tt != 0u && tt != mk) {
-                            anti |= 1u << t;
-                            cf[t] = (S)hib[b].jxy2;
-                            src[t] = hoff[hh ^ mk] + p;
-                        }
-                    }
-                }
-#pragma unroll
-                for (int t = 0; t < kBatchV; ++t) {
-                    if (anti & (1u << t)) ld_piece<S, VPT>(v + src[t] * NV + sub * VPT, val[t]);
+                    if (b0 + t < nha) ld_piece<S, VPT>(v + (s_hsrc[b0 + t] + p) * NV + sub * VPT, val[t]);
                     else
 #pragma unroll
                         for (int j = 0; j < VPT; ++j) val[t][j] = (S)0;
                 }
 #pragma unroll
                 for (int t = 0; t < kBatchV; ++t)
-                    if (anti & (1u << t))
+                    if (b0 + t < nha)
 #pragma unroll
-                        for (int j = 0; j < VPT; ++j) acc[j] += cf[t] * val[t][j];
+                        for (int j = 0; j < VPT; ++j) acc[j] += s_hcf[b0 + t] * val[t][j];
             }
             S me_v[VPT], hv[VPT], uu[VPT], out[VPT];
             ld_piece<S, VPT>(blk + (size_t)p * NV + sub * VPT, me_v);
