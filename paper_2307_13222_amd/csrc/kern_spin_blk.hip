@@ -93,6 +93,7 @@ void k_spin_blk(BlkKArgs a)
     __shared__ uint64_t s_hsrc[kMaxHiBonds];
     __shared__ S s_hcf[kMaxHiBonds];
     __shared__ unsigned s_wn[kMaxHiBonds / 64];
+    __shared__ uint64_t s_xpb[kMaxHiBonds];   // crossing bond b: its partner block's start
     // read-only tables at workgroup-uniform indices: scalar loads
     typedef const __attribute__((address_space(4))) uint64_t CU64;
     typedef const __attribute__((address_space(4))) uint32_t CU32;
@@ -162,6 +163,7 @@ void k_spin_blk(BlkKArgs a)
                 s_hsrc[at] = a.hi_off[hh ^ mk];
                 s_hcf[at] = (S)a.hib[i].jxy2;
             }
+            if (i < a.nxb) s_xpb[i] = a.hi_off[hh ^ (1u << a.xb[i].hbit)];
             __syncthreads();
         }
         int nha = 0;
@@ -222,7 +224,7 @@ void k_spin_blk(BlkKArgs a)
                     const int b = b0 + t;
                     if (b < a.nxb) {
                         const uint32_t hbit = xb[b].hbit;
-                        const uint64_t pb = hoff[hh ^ (1u << hbit)];
+                        const uint64_t pb = s_xpb[b];
                         const uint32_t row = xb[b].row;
                         if (row != rlast) {
                             qlast = tab[(uint64_t)row * a.pitch + g];
@@ -658,7 +660,9 @@ int blk_tables(hphi_ham *h, int esize, bool f32)
         for (uint32_t x = 0; x < (1u << nh); ++x)
             if (__builtin_popcount(x) == k) list.push_back(x);
     }
-    if (hib.size() > (size_t)kMaxHiBonds) {   // the kernel lists a block's flipping high bonds in LDS
+    if (hib.size() > (size_t)kMaxHiBonds || xb.size() > (size_t)kMaxHiBonds) {
+        // the kernels list a block's flipping high bonds and its crossing
+        // bonds' partner blocks in LDS
         B.ok = false;
         return HPHI_OK;
     }
