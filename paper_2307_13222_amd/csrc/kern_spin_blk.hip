@@ -163,7 +163,9 @@ void k_spin_blk(BlkKArgs a)
                 s_hsrc[at] = a.hi_off[hh ^ mk];
                 s_hcf[at] = (S)a.hib[i].jxy2;
             }
-            if (i < a.nxb) s_xpb[i] = a.hi_off[hh ^ (1u << a.xb[i].hbit)];
+            // (FP32 only: with FP64 values the extra registers cost a wave)
+            if constexpr (sizeof(S) == 4)
+                if (i < a.nxb) s_xpb[i] = a.hi_off[hh ^ (1u << a.xb[i].hbit)];
             __syncthreads();
         }
         int nha = 0;
@@ -224,7 +226,9 @@ void k_spin_blk(BlkKArgs a)
                     const int b = b0 + t;
                     if (b < a.nxb) {
                         const uint32_t hbit = xb[b].hbit;
-                        const uint64_t pb = s_xpb[b];
+                        uint64_t pb;
+                        if constexpr (sizeof(S) == 4) pb = s_xpb[b];
+                        else pb = hoff[hh ^ (1u << hbit)];
                         const uint32_t row = xb[b].row;
                         if (row != rlast) {
                             qlast = tab[(uint64_t)row * a.pitch + g];
